@@ -1,0 +1,269 @@
+"""FP64 CPU oracle for the GFDM hot path (test infrastructure only).
+
+Only the test-suite, the smoke check and the CPU-baseline leg of the benchmark
+may import this package.  The product path never calls it, and it shares no
+code with the GPU library: the C source in this directory is compiled with gcc
+on its own, and this wrapper only marshals numpy arrays through ctypes.
+
+Every function states the part of the paper it follows; the C file holds the
+arithmetic.  The pressure solve uses a sparse direct solver (scipy's SuperLU):
+the oracle of a linear solve is the solution of the linear system itself.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gfdm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+# Parameters the paper fixes (Sec. 4.1.2, 4.1.3, 7.2) and the readings used
+# where it is silent (support weight sharpness).
+EPS_LAMBDA_MAX = 0.15
+THETA_STAR = np.pi / 6.0
+ZETA = 0.3
+ALPHA_W = 8.0
+
+OP_DX, OP_DY, OP_DZ, OP_LAP = 1, 2, 4, 8
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no FMA contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math",
+               "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        _lib = ctypes.CDLL(_LIB)
+        _declare(_lib)
+    return _lib
+
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+
+
+def _declare(L):
+    L.orc_nbr_brute.restype = _I64
+    L.orc_nbr_brute.argtypes = [_I64, _P, _P, _P, _P, _P, ctypes.c_int, _P, _P]
+    L.orc_nbr_grid.restype = _I64
+    L.orc_nbr_grid.argtypes = [_I64, _P, _P, _P, _P, _P, ctypes.c_int, _P, _P]
+    L.orc_pca.restype = None
+    L.orc_pca.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P]
+    L.orc_classify.restype = None
+    L.orc_classify.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                               _P, ctypes.c_double, ctypes.c_double, ctypes.c_int, _P]
+    L.orc_gfdm_weights.restype = None
+    L.orc_gfdm_weights.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                   ctypes.c_double, _P, _I64, _P, _P, _P]
+    L.orc_gfdm_weights_normal_ld.restype = None
+    L.orc_gfdm_weights_normal_ld.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                             ctypes.c_double, _P]
+    L.orc_apply.restype = None
+    L.orc_apply.argtypes = [_I64, _P, _P, _P, ctypes.c_uint, _P, _P]
+    L.orc_apply_adjoint.restype = None
+    L.orc_apply_adjoint.argtypes = [_I64, _P, _P, _P, ctypes.c_uint, _P, _P]
+    L.orc_poisson_assemble.restype = None
+    L.orc_poisson_assemble.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_double, _P]
+    L.orc_transition_3d_to_2d.restype = None
+    L.orc_transition_3d_to_2d.argtypes = [_I64] + [_P] * 21
+    L.orc_weights_adjoint_x.restype = None
+    L.orc_weights_adjoint_x.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                        ctypes.c_double, ctypes.c_uint, _P, _P, _P]
+
+
+def _p(a):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i8(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.int8)
+
+
+def _u8(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.uint8)
+
+
+def _pos(p):
+    return (_f64(p["x"]), _f64(p["y"]), _f64(p["z"]), _f64(p["h"]), _i8(p["model"]))
+
+
+def neighbours(p, cross: bool = False, method: str = "grid"):
+    """S_i of Eq. (Nbd) (same-model sets unless cross=True), as CSR with rows
+    sorted ascending.  method 'brute' is the O(N^2) definition."""
+    x, y, z, h, model = _pos(p)
+    n = x.shape[0]
+    row_ptr = np.zeros(n + 1, np.int64)
+    fn = lib().orc_nbr_brute if method == "brute" else lib().orc_nbr_grid
+    nnz = fn(n, _p(x), _p(y), _p(z), _p(h), _p(model), int(cross), _p(row_ptr), None)
+    col = np.zeros(max(nnz, 1), np.int32)[:nnz]
+    col = np.ascontiguousarray(col)
+    fn(n, _p(x), _p(y), _p(z), _p(h), _p(model), int(cross), _p(row_ptr), _p(col))
+    return row_ptr, col
+
+
+def pca(p, row_ptr, col):
+    """Eigenvalues (descending), smallest-eigenvalue direction w3 and
+    eps_lambda = 2 l3 / (l1 + l2) of the local covariance (Sec. 4.1.2)."""
+    x, y, z, _, _ = _pos(p)
+    n = x.shape[0]
+    lam = np.zeros((n, 3)); w3 = np.zeros((n, 3)); eps = np.zeros(n)
+    lib().orc_pca(n, _p(x), _p(y), _p(z), _p(row_ptr), _p(col), _p(lam), _p(w3), _p(eps))
+    return lam, w3, eps
+
+
+def classify(p, row_ptr, col, eps, w3, cross=None, film_height=None, h3d=None, prev=None,
+             user=None, eps_max=EPS_LAMBDA_MAX, theta_star=THETA_STAR, literal_rule=False):
+    """Transition flags (0 none, 1 bulk->film, 2 film->bulk): Alg. 2,
+    Eq. (2Dto3Dcond) and the smoothing rules of Sec. 4.3."""
+    n = p["x"].shape[0]
+    flag = np.zeros(n, np.uint8)
+    xr, xc = (None, None) if cross is None else cross
+    L = lib()
+    L.orc_classify(n, _p(_i8(p["model"])), _p(_i8(p["kind"])), _p(_f64(p["nx"])),
+                   _p(_f64(p["ny"])), _p(_f64(p["nz"])), _p(row_ptr), _p(col), _p(xr), _p(xc),
+                   _p(_f64(eps)), _p(_f64(w3.reshape(-1))), _p(_f64(film_height)), _p(_f64(h3d)),
+                   _p(_u8(prev)), _p(_u8(user)), eps_max, theta_star, int(literal_rule),
+                   _p(flag))
+    return flag
+
+
+def gfdm_weights(p, row_ptr, col, alpha_w=ALPHA_W, rows=None):
+    """Second-order GFDM stencils (Eq. GFDM_Definition) by Householder QR.
+    Returns w [nnz, 4] (d/dx, d/dy, d/dz, Laplacian), status [n], kappa [n].
+    If rows is given, only those rows are computed (others stay zero)."""
+    x, y, z, h, model = _pos(p)
+    n = x.shape[0]
+    nnz = int(row_ptr[-1])
+    w = np.zeros((nnz, 4))
+    status = np.zeros(n, np.int8)
+    kappa = np.zeros(n)
+    r = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    lib().orc_gfdm_weights(n, _p(x), _p(y), _p(z), _p(h), _p(model), _p(_f64(p["nx"])),
+                           _p(_f64(p["ny"])), _p(_f64(p["nz"])), _p(row_ptr), _p(col), alpha_w,
+                           _p(r), 0 if r is None else r.shape[0], _p(w), _p(status), _p(kappa))
+    return w, status, kappa
+
+
+def gfdm_weights_normal_ld(p, row_ptr, col, alpha_w=ALPHA_W):
+    """Same stencils from the normal equations in long double (cross-check)."""
+    x, y, z, h, model = _pos(p)
+    n = x.shape[0]
+    w = np.zeros((int(row_ptr[-1]), 4))
+    lib().orc_gfdm_weights_normal_ld(n, _p(x), _p(y), _p(z), _p(h), _p(model),
+                                     _p(_f64(p["nx"])), _p(_f64(p["ny"])), _p(_f64(p["nz"])),
+                                     _p(row_ptr), _p(col), alpha_w, _p(w))
+    return w
+
+
+def mask_ops(op_mask):
+    return [s for s in range(4) if op_mask & (1 << s)]
+
+
+def apply(row_ptr, col, w, u, op_mask=0xF):
+    """y_i^s = sum_{j != i} c_ij^s (u_j - u_i), stacked [K, n]."""
+    n = row_ptr.shape[0] - 1
+    K = len(mask_ops(op_mask))
+    out = np.zeros((K, n))
+    lib().orc_apply(n, _p(row_ptr), _p(col), _p(_f64(w)), op_mask, _p(_f64(u)), _p(out))
+    return out
+
+
+def apply_adjoint(row_ptr, col, w, ybar, op_mask=0xF):
+    n = row_ptr.shape[0] - 1
+    ub = np.zeros(n)
+    lib().orc_apply_adjoint(n, _p(row_ptr), _p(col), _p(_f64(w)), op_mask,
+                            _p(_f64(np.ascontiguousarray(ybar))), _p(ub))
+    return ub
+
+
+def weights_adjoint_x(p, row_ptr, col, u, ybar, op_mask=0xF, alpha_w=ALPHA_W):
+    """Gradient of L with respect to particle positions through the stencil
+    weights, for ybar = dL/dy of the differenced application.  [n, 3]."""
+    x, y, z, h, model = _pos(p)
+    n = x.shape[0]
+    xb = np.zeros((n, 3))
+    lib().orc_weights_adjoint_x(n, _p(x), _p(y), _p(z), _p(h), _p(model), _p(_f64(p["nx"])),
+                                _p(_f64(p["ny"])), _p(_f64(p["nz"])), _p(row_ptr), _p(col),
+                                alpha_w, op_mask, _p(_f64(u)),
+                                _p(_f64(np.ascontiguousarray(ybar))), _p(xb))
+    return xb
+
+
+def poisson_matrix(p, row_ptr, col, w, row_type, zeta=ZETA):
+    """CSR values of the pressure system (interior Laplacian rows, Dirichlet
+    identity rows, PDE + zeta*BC Neumann rows)."""
+    n = row_ptr.shape[0] - 1
+    val = np.zeros(int(row_ptr[-1]))
+    lib().orc_poisson_assemble(n, _p(_f64(p["h"])), _p(_f64(p["nx"])), _p(_f64(p["ny"])),
+                               _p(_f64(p["nz"])), _p(_i8(row_type)), _p(row_ptr), _p(col),
+                               _p(_f64(w)), zeta, _p(val))
+    return val
+
+
+def poisson_solve(row_ptr, col, val, rhs):
+    """Exact solution of A p = rhs by sparse LU (the definition of the solve)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    n = row_ptr.shape[0] - 1
+    A = sp.csr_matrix((val, col, row_ptr), shape=(n, n))
+    return spla.spsolve(A.tocsc(), rhs)
+
+
+def csr_matvec(row_ptr, col, val, v):
+    import scipy.sparse as sp
+    n = row_ptr.shape[0] - 1
+    return sp.csr_matrix((val, col, row_ptr), shape=(n, n)) @ v
+
+
+def transition_3d_to_2d(p, row_ptr, col, flag, mass, rho, phi):
+    """Sec. 5.1 / Alg. 3: deletion sets, averaging, mass lumping, film height
+    and droplet diameter.  Returns a dict of arrays."""
+    x, y, z, h, model = _pos(p)
+    n = x.shape[0]
+    out = {k: np.zeros(n) for k in ("mass", "rho", "phi", "height", "diam")}
+    keep = np.zeros(n, np.uint8)
+    owner = np.zeros(n, np.int32)
+    lib().orc_transition_3d_to_2d(n, _p(x), _p(y), _p(z), _p(model), _p(_i8(p["kind"])),
+                                  _p(_f64(p["nx"])), _p(_f64(p["ny"])), _p(_f64(p["nz"])),
+                                  _p(row_ptr), _p(col), _p(_u8(flag)), _p(_f64(mass)),
+                                  _p(_f64(rho)), _p(_f64(phi)), _p(out["mass"]), _p(out["rho"]),
+                                  _p(out["phi"]), _p(out["height"]), _p(out["diam"]), _p(keep),
+                                  _p(owner))
+    out["keep"] = keep
+    out["owner"] = owner
+    return out
+
+
+def operator_error(w, w_ref, row_ptr):
+    """Per row and stencil: |c - c_ref|_2 / |c_ref|_2 over the row's entries.
+    Rows/stencils whose reference is identically zero are reported as the
+    absolute norm of c instead.  Returns an [n, 4] array."""
+    n = row_ptr.shape[0] - 1
+    rid = np.repeat(np.arange(n), np.diff(row_ptr))
+    d2 = np.stack([np.bincount(rid, (w[:, s] - w_ref[:, s]) ** 2, minlength=n) for s in range(4)], 1)
+    r2 = np.stack([np.bincount(rid, w_ref[:, s] ** 2, minlength=n) for s in range(4)], 1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        e = np.where(r2 > 0, np.sqrt(d2 / np.where(r2 > 0, r2, 1)), np.sqrt(d2))
+    return e
