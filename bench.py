@@ -1,0 +1,315 @@
+#!/usr/bin/env python3
+"""Throughput of the GFDM hot path on one MI355X.
+
+Metric: particles/s for GFDM stencil weights + application (all four
+stencils d/dx, d/dy, d/dz, Laplacian applied to one scalar field), on the
+mixed bulk/film cloud of 503,944 particles (258,944 jittered-lattice bulk
+particles beside 245,000 film particles on z = 0, h = 3 x local spacing).
+value = N / (t_weights + t_apply) for the batched path with FP32 stencil
+storage (FP64 Gram solves, QR fallback); the plain FP64 path, the fused
+weights+apply call and the other steps of the hot path are timed beside it.
+
+A step is one weights + apply pass over the resident cloud; K steps are timed
+with HIP events on the library's stream after W warm-up steps.  The FP64 CPU
+oracle is timed on the same workload (weights + apply, every particle) and
+its stencils are the reference for the stated operator error.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0        # MI355X HBM3E, GB/s
+PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector
+BANDS = (24, 48, 128)        # neighbour-count bands of the batched kernels
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--factor", type=int, default=1, help="coarsen the workload (parity/debug only)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-rows", action="store_true", help="skip timing the other hot-path steps")
+    ap.add_argument("--poisson", type=int, default=0,
+                    help="also solve the pressure system on a jet cylinder of this many particles")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="run warm-up plus a few steps of the metric path and exit (for rocprofv3)")
+    return ap.parse_args()
+
+
+def band_of(n):
+    for b, hi in enumerate(BANDS):
+        if n <= hi:
+            return b
+    return len(BANDS)
+
+
+def algorithmic_costs(rp, model):
+    """Per (model, band) launch of the stencil kernels: rows, nnz, FP64 flops
+    and unique bytes of the FP32-output path.
+    flops/row: Gram n m(m+1) + weighted monomials n m + targets 8 n m
+               + factorisation and inverse ~ m^3/3 + 2 m^3
+    bytes/row: 4 n (indices) + 16 n (FP32 stencils) + 32 (own x, y, z, h)."""
+    import numpy as np
+    n_i = np.diff(rp)
+    out = {}
+    bands = np.searchsorted(np.array(BANDS), n_i, side="left")
+    for m in (0, 1):
+        M = 10 if m == 0 else 6
+        for b in range(len(BANDS) + 1):
+            nn = n_i[(model == m) & (bands == b)]
+            if nn.size == 0:
+                continue
+            flops = float((nn * (M * (M + 1) + M + 8 * M)).sum() + nn.size * (M ** 3 / 3 + 2 * M ** 3))
+            byts = float((20 * nn + 32).sum())
+            out[(m, b)] = dict(rows=int(nn.size), nnz=int(nn.sum()), flops=flops, bytes=byts)
+    return out
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the stencil path runs on a single MI355X "
+              "(multi-GPU sharding is described in DESIGN.md but not built); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2405_13165_amd import gfdm as g
+    from paper_2405_13165_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    t0 = time.time()
+    d = W.mixed_block_film(factor=args.factor)
+    N = d["x"].shape[0]
+    print(f"[bench] workload generated: {N} particles ({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
+
+    ctx = g.Context(0)
+    p = g.Particles.from_dict(ctx, d)
+    f, *_ = W.test_field(d["x"], d["y"], d["z"])
+    u = torch.as_tensor(f, device=ctx.device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nb = g.build_neighbours(ctx, p)
+    torch.cuda.synchronize()
+    t_nbr_first = time.perf_counter() - t0
+    nnz = nb.nnz
+    rp_d, col_d = nb.export()
+    rp = rp_d.cpu().numpy()
+    print(f"[bench] neighbours: nnz={nnz} max_row={nb.max_row}", file=sys.stderr, flush=True)
+
+    w32 = torch.empty((nnz, 4), dtype=torch.float32, device=ctx.device)
+    w64 = torch.empty((nnz, 4), dtype=torch.float64, device=ctx.device)
+    y32 = torch.empty((4, N), dtype=torch.float64, device=ctx.device)
+    y64 = torch.empty((4, N), dtype=torch.float64, device=ctx.device)
+    yf = torch.empty((4, N), dtype=torch.float64, device=ctx.device)
+    status = torch.empty(N, dtype=torch.int8, device=ctx.device)
+
+    def step_batched():
+        g.gfdm_weights(ctx, p, nb, g.GF_BATCHED, g.GF_F32, out=w32, status=status)
+        g.apply_stencil(ctx, nb, w32, u, 0xF, out=y32)
+
+    def step_plain():
+        g.gfdm_weights(ctx, p, nb, g.GF_PLAIN_F64, g.GF_F64, out=w64)
+        g.apply_stencil(ctx, nb, w64, u, 0xF, out=y64)
+
+    def step_fused():
+        g.gfdm_weights_apply(ctx, p, nb, u, 0xF, g.GF_F32, w_out=w32, out=yf, status=status)
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        s = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(steps):
+            fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    if args.profile_only:
+        timed(step_batched, max(args.steps, 1), args.warmup)
+        timed(step_plain, 2, 1)
+        print("[bench] profile run done", file=sys.stderr, flush=True)
+        return
+
+    ms_batched = timed(step_batched, args.steps, args.warmup)
+    ms_plain = timed(step_plain, args.steps, args.warmup)
+    ms_fused = timed(step_fused, args.steps, args.warmup)
+    print(f"[bench] batched {ms_batched:.3f} ms  plain {ms_plain:.3f} ms  fused {ms_fused:.3f} ms",
+          file=sys.stderr, flush=True)
+
+    # per-kernel times of the metric step (HIP events around each launch)
+    ctx.profile(True)
+    reps = max(3, min(args.steps, 10))
+    for _ in range(reps):
+        step_batched()
+    prof = ctx.profile_read()
+    for _ in range(reps):
+        step_plain()
+    prof_plain = ctx.profile_read()
+    ctx.profile(False)
+    costs = algorithmic_costs(rp, d["model"])
+    kernels = {}
+    for name, (cnt, tot) in prof.items():
+        kernels[name] = {"launches": cnt, "avg_us": 1000.0 * tot / cnt}
+    weights_kernels = {k: v for k, v in kernels.items() if k.startswith("weights_") and "qr" not in k}
+    dom = max(weights_kernels, key=lambda k: weights_kernels[k]["avg_us"] * weights_kernels[k]["launches"])
+    m_dom = 0 if "_3d_" in dom else 1
+    # team size per (model, band) as launched by the library; all bands of
+    # one model with the same team size launch the same kernel
+    T_of = {(0, 0): 4, (0, 1): 8, (0, 2): 8, (0, 3): 16, (1, 0): 4, (1, 1): 4, (1, 2): 8, (1, 3): 16}
+    t_dom = int(dom.rsplit("_t", 1)[1])
+    sel = [v for (m, b), v in costs.items() if m == m_dom and T_of[(m, b)] == t_dom]
+    flops = sum(v["flops"] for v in sel)
+    byts = sum(v["bytes"] for v in sel)
+    # per-launch figures: the profile groups all launches of one name
+    per_launch_s = kernels[dom]["avg_us"] * 1e-6
+    n_launch_per_step = kernels[dom]["launches"] / reps
+    flops_l = flops / n_launch_per_step
+    bytes_l = byts / n_launch_per_step
+    tflops = flops_l / per_launch_s / 1e12
+    gbs = bytes_l / per_launch_s / 1e9
+    frac_alu = tflops / PEAK_FP64_TFLOPS
+    frac_hbm = gbs / PEAK_HBM_GBS
+    if frac_alu >= frac_hbm:
+        roof = {"kernel": dom, "bound": "alu", "achieved": round(tflops, 3), "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(frac_alu, 4), "traffic": None}
+    else:
+        roof = {"kernel": dom, "bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(frac_hbm, 4), "traffic": None}
+    roof["other_roof"] = {"hbm_GBs": round(gbs, 1), "hbm_frac": round(frac_hbm, 4),
+                          "fp64_TFLOPs": round(tflops, 3), "fp64_frac": round(frac_alu, 4)}
+    roof["algorithmic_per_launch"] = {"flops": flops_l, "bytes": bytes_l, "avg_launch_us": round(per_launch_s * 1e6, 2)}
+
+    # whole-step HBM view: unique bytes of weights + apply (FP32 stencils)
+    step_bytes = float(nnz) * (4 + 16) + N * 32 + float(nnz) * (4 + 16) + N * (8 + 32)
+    step_hbm_frac = step_bytes / (ms_batched * 1e-3) / 1e9 / PEAK_HBM_GBS
+
+    # ---- accuracy of the FP32 path against the FP64 plain path on the device
+    step_batched(); step_plain()
+    torch.cuda.synchronize()
+    w32n = w32.double().cpu().numpy()
+    w64n = w64.cpu().numpy()
+
+    result = {
+        "metric": "particles/s for GFDM weights+apply; batched-FP32 vs plain-FP64 @1e-6 rel err",
+        "value": N / (ms_batched * 1e-3),
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_batched,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "weights_storage": "f32",
+        "data": "synthetic",
+        "config": {"workload": "mixed bulk/film cloud: 258,944 jittered-lattice bulk particles beside "
+                               "245,000 film particles on z=0, h = 3 x spacing (10 / 6 monomials)",
+                   "n_particles": N, "nnz": nnz, "factor": args.factor},
+        "plain_f64": {"value": N / (ms_plain * 1e-3), "ms_per_step": ms_plain},
+        "fused_weights_apply_f32": {"value": N / (ms_fused * 1e-3), "ms_per_step": ms_fused},
+        "speedup_batched_vs_plain": ms_plain / ms_batched,
+        "step_hbm_frac": round(step_hbm_frac, 4),
+        "kernels_batched": kernels,
+        "kernels_plain": {k: {"launches": c, "avg_us": 1000.0 * t / c} for k, (c, t) in prof_plain.items()},
+        "roofline": roof,
+    }
+
+    # ---- other hot-path steps (timed once each after a warm-up call)
+    if not args.no_rows:
+        rows = {"build_neighbours_first_ms": t_nbr_first * 1e3}
+
+        def once(fn):
+            fn()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t) * 1e3, r
+
+        rows["build_neighbours_ms"], nb2 = once(lambda: g.build_neighbours(ctx, p))
+        del nb2
+        xnb = g.build_neighbours(ctx, p, cross_model=True)
+        rows["classify_pca_ms"], cl = once(lambda: g.classify_pca(ctx, p, nb, xnb, film_height=d["film_height"],
+                                                                 h3d=d["h3d"]))
+        flag = cl[3]
+        mass = torch.ones(N, dtype=torch.float64, device=ctx.device)
+        rho = torch.full((N,), 1000.0, dtype=torch.float64, device=ctx.device)
+        rows["transition_ms"], _ = once(lambda: g.transition_3d_to_2d(ctx, p, nb, flag, mass, rho, u))
+        ybar = torch.ones((1, N), dtype=torch.float64, device=ctx.device)
+        rows["apply_adjoint_ms"], _ = once(lambda: g.apply_stencil_adjoint(ctx, nb, w32, ybar, g.OP_LAP))
+        rows["weights_adjoint_ms"], _ = once(lambda: g.gfdm_weights_adjoint(ctx, p, nb, u, ybar, g.OP_LAP))
+        result["rows"] = rows
+        result["flags"] = {"bulk_to_film": int((flag == 1).sum().item()), "film_to_bulk": int((flag == 2).sum().item())}
+
+    if args.poisson:
+        dp = W.projection_cylinder(args.poisson)
+        pp = g.Particles.from_dict(ctx, dp)
+        nbp = g.build_neighbours(ctx, pp)
+        wp = g.gfdm_weights(ctx, pp, nbp, g.GF_BATCHED, g.GF_F64)
+        val = g.poisson_assemble(ctx, pp, nbp, wp, dp["row_type"])
+        rpp, colp = nbp.export()
+        A = torch.sparse_csr_tensor(rpp, colp.long(), val, size=(pp.n, pp.n))
+        b = (A @ torch.as_tensor(dp["pstar"], device=ctx.device).unsqueeze(1)).squeeze(1)
+        ps = {}
+        for mixed in (0, 1):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            x, st = g.poisson_solve(ctx, pp, nbp, wp, dp["row_type"], b, params=g.solve_params(mixed=mixed),
+                                    raise_on_fail=False)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t
+            err = ((x - torch.as_tensor(dp["pstar"], device=ctx.device)).norm() /
+                   torch.as_tensor(dp["pstar"], device=ctx.device).norm()).item()
+            ps["mixed" if mixed else "plain_f64"] = dict(seconds=el, err_vs_pstar=err, **st)
+        result["poisson"] = {"n": pp.n, "nnz": nbp.nnz, **ps}
+
+    # ---- CPU oracle baseline and operator error (oracle inputs never come from the device)
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        rp_o, col_o = oracle.neighbours(d)
+        t_nbr_o = time.perf_counter() - t0
+        assert np.array_equal(rp_o, rp) and np.array_equal(col_o, col_d.cpu().numpy()), "neighbour lists differ"
+        t0 = time.perf_counter()
+        w_o, st_o, _ = oracle.gfdm_weights(d, rp_o, col_o)
+        y_o = oracle.apply(rp_o, col_o, w_o, f)
+        t_o = time.perf_counter() - t0
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        e32 = oracle.operator_error(w32n, w_o, rp_o)
+        e64 = oracle.operator_error(w64n, w_o, rp_o)
+        result["cpu_baseline"] = {"value": N / t_o, "unit": "particles/s", "cores": cores, "kind": "oracle",
+                                  "sample": f"all {N} particles of the workload, weights + apply, one pass "
+                                            f"({t_o:.1f} s; neighbour search {t_nbr_o:.1f} s not included)"}
+        y32n = y32.cpu().numpy()
+        result["operator_error"] = {
+            "batched_f32_max": float(e32.max()), "batched_f32_p9999": float(np.quantile(e32, 0.9999)),
+            "plain_f64_max": float(e64.max()),
+            "apply_f32_max_abs_rel": float(np.max(np.abs(y32n - y_o)) / np.max(np.abs(y_o))),
+        }
+        print(f"[bench] oracle {t_o:.1f}s; f32 err max {e32.max():.2e}, f64 err max {e64.max():.2e}",
+              file=sys.stderr, flush=True)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,283 @@
+/*
+ * gfdm.h -- C ABI of the MI355X (gfx950) library for the meshfree GFDM hot
+ * path of "Adaptive coupling of 3D and 2D fluid flow models" (Suchde):
+ * neighbourhoods, local PCA transition detection, second-order GFDM stencils,
+ * stencil application, the implicit pressure-Poisson solve, the 3D->2D
+ * transition, and adjoints of the stencils.
+ *
+ * Conventions shared by every entry point
+ *  - Pointers named as device memory must point to memory on the context's
+ *    device (hipMalloc or torch CUDA tensors).  Host pointers are named so.
+ *  - The caller owns every buffer it passes.  Opaque handles (gf_ctx,
+ *    gf_nbr) own the device memory they allocate and release it in their
+ *    *_destroy / *_free call.
+ *  - All work is enqueued on the context's stream in order; calls return
+ *    without waiting unless stated ("synchronises").
+ *  - Particle arrays are in the caller's order (structure of arrays, length
+ *    n).  Outputs are in the caller's order too; the Morton/cell order used
+ *    internally never leaks out.
+ *  - Every call returns a gf_status and never aborts.  On failure
+ *    gf_last_error(ctx) describes the cause.  Bad arguments are rejected
+ *    before any kernel is launched.  Per-particle numerical problems are not
+ *    call failures: they are reported per particle (status arrays).
+ *  - Calls that share a context must not run concurrently from several host
+ *    threads.
+ */
+#ifndef GFDM_H
+#define GFDM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GF_OK = 0,
+  GF_EINVAL = -1,      /* invalid argument or input data (NaN/Inf, h <= 0, bad enum) */
+  GF_ENOMEM = -2,      /* device allocation failed */
+  GF_EHIP = -3,        /* a HIP runtime call failed */
+  GF_ECAPACITY = -4,   /* a documented size limit was exceeded */
+  GF_ENOTCONV = -5,    /* iterative solve hit its iteration limit */
+  GF_EBREAKDOWN = -6   /* iterative solve broke down and could not restart */
+} gf_status;
+
+typedef enum { GF_F64 = 0, GF_F32 = 1 } gf_dtype;
+
+/* How stencils are computed (gf_gfdm_weights).
+ *  GF_PLAIN_F64: one work-item per particle in the caller's order, FP64
+ *                throughout, FP64 weights out.
+ *  GF_BATCHED:   particles grouped by model and neighbour count, processed
+ *                in Morton order by teams of lanes; the per-particle Gram
+ *                system is solved in FP64; particles whose condition number
+ *                exceeds kappa_max are re-solved by an FP64 Householder QR.
+ *                Weights out in FP64 or FP32.  With FP32 output the support
+ *                weights w(q) are evaluated in FP32 as well. */
+typedef enum { GF_PLAIN_F64 = 0, GF_BATCHED = 1 } gf_prec;
+
+enum { GF_OP_DX = 1, GF_OP_DY = 2, GF_OP_DZ = 4, GF_OP_LAP = 8 };
+
+/* particle kinds (Sec. 2.3) and models */
+enum { GF_KIND_INTERIOR = 0, GF_KIND_FREE_SURFACE = 1, GF_KIND_WALL = 2 };
+enum { GF_MODEL_BULK = 0, GF_MODEL_FILM = 1 };
+
+typedef struct gf_ctx gf_ctx;
+typedef struct gf_nbr gf_nbr;
+
+/* Particle cloud, structure of arrays in device memory, length n.
+ *  x, y, z, h : positions and support radius h_i (> 0, finite), FP64.
+ *  model      : 0 = 3D bulk, 1 = 2D film (Sec. 2.2).
+ *  kind       : 0 interior, 1 free surface, 2 wall (Sec. 2.3).  May be NULL
+ *               for calls that do not use kinds.
+ *  nx, ny, nz : unit wall / film normal; read for wall and film particles
+ *               only (may be NULL when there are none). */
+typedef struct {
+  int64_t n;
+  const double *x, *y, *z, *h;
+  const int8_t *model;
+  const int8_t *kind;
+  const double *nx, *ny, *nz;
+} gf_particles;
+
+/* ---------------------------------------------------------------- context */
+/* Create a context on HIP device `device`.  stream: a hipStream_t to enqueue
+ * on, or NULL for the default (null) stream. */
+gf_status gf_create(int device, void *stream, gf_ctx **out);
+gf_status gf_set_stream(gf_ctx *ctx, void *stream);
+void gf_destroy(gf_ctx *ctx);
+/* Message of the last failed call on ctx ("" if none).  Owned by ctx. */
+const char *gf_last_error(const gf_ctx *ctx);
+const char *gf_version(void);
+
+/* Per-kernel timing (tracing aid).  While enabled, every kernel the library
+ * launches on ctx is bracketed by HIP events on the context stream.
+ * gf_profile_read synchronises on those events and writes one line per kernel
+ * name, "name launches total_ms", into buf (host, len bytes), then clears the
+ * record.  GF_ECAPACITY if buf is too small. */
+gf_status gf_profile_enable(gf_ctx *ctx, int on);
+gf_status gf_profile_read(gf_ctx *ctx, char *buf, size_t len);
+
+/* ---------------------------------------------------------- neighbourhoods */
+/* Build S_i = { j : |x_j - x_i| <= (h_i + h_j)/2 } for every particle
+ * (Sec. 2.2, Eq. Nbd), i in S_i.  cross_model = 0: only particles of the same
+ * model (Sec. 6.2: S_i holds neighbours of i's own model); cross_model = 1:
+ * all models (used by the smoothing rule of Sec. 4.3).  The predicate is
+ * evaluated in FP64 as d2 = (dx*dx + dy*dy) + dz*dz <= r*r, r = 0.5*(h_i+h_j),
+ * without fused multiply-adds, so the sets are reproducible bit for bit.
+ * Result rows are sorted ascending.  Limit: at most 2048 neighbours per
+ * particle (GF_ECAPACITY).  Synchronises (the size of the result is read back).
+ * The handle holds the CSR lists, the Morton processing order and the
+ * grouping of particles used by the batched kernels. */
+gf_status gf_build_neighbours(gf_ctx *ctx, const gf_particles *p, int cross_model, gf_nbr **out);
+/* n, nnz and the longest row of a neighbour handle (host outputs, any NULL). */
+gf_status gf_nbr_info(const gf_nbr *nbr, int64_t *n, int64_t *nnz, int32_t *max_row);
+/* Copy the CSR lists into caller buffers (device): row_ptr [n+1] int64,
+ * col [nnz] int32 (user indices, rows ascending).  Either may be NULL. */
+gf_status gf_nbr_export(gf_ctx *ctx, const gf_nbr *nbr, int64_t *row_ptr, int32_t *col);
+void gf_nbr_free(gf_nbr *nbr);
+
+/* ---------------------------------------------------------- PCA / flags */
+typedef struct {
+  double eps_lambda_max;  /* 0.15, Sec. 4.1.2 Eq. (EigenvalueLimit)          */
+  double theta_star;      /* pi/6, Sec. 4.1.3 Eq. (EigenvectorLimit)         */
+  int literal_rule;       /* 0: pass iff |n.w3| >= cos(theta*) (w3 along the
+                             depth direction, as the prose and Sec. 7.1
+                             require); 1: the inequality exactly as printed,
+                             |n.w3| < cos(theta*)                            */
+} gf_pca_params;
+void gf_pca_params_default(gf_pca_params *p);
+
+/* Local PCA and transition flags (Sec. 4).
+ * For every particle: covariance of S_i about its centroid (Sec. 4.1.2),
+ * eigenvalues lambda_1 >= lambda_2 >= lambda_3 -> lam_3n [n][3], unit
+ * eigenvector of lambda_3 -> w3_3n [n][3] (largest-magnitude component made
+ * positive), eps_n = 2 lambda_3 / (lambda_1 + lambda_2) (+inf if the
+ * denominator is 0).  Flags flag_n (uint8): 0 none, 1 bulk->film, 2 film->bulk:
+ *  3D wall particles follow Alg. 2 (resolution criterion on neighbour kinds,
+ *  eigenvalue and eigenvector tests, user criterion); film particles are
+ *  flagged when film_height >= h3d (Eq. 2Dto3Dcond) or by the user criterion.
+ *  Smoothing (Sec. 4.3): particles with prev_transitioned set are not
+ *  flagged; then, if `cross` is given, a flag survives only if another
+ *  particle of the cross-model neighbourhood is of the target model or
+ *  carries the same flag.
+ * same: same-model neighbourhoods (required).  cross, film_height, h3d,
+ * prev_transitioned (uint8), user_flag (uint8): optional (NULL).  Outputs
+ * lam_3n, w3_3n, eps_n may be NULL; flag_n may be NULL (then only PCA). */
+gf_status gf_classify_pca(gf_ctx *ctx, const gf_particles *p, const gf_nbr *same,
+                          const gf_nbr *cross, const double *film_height, const double *h3d,
+                          const uint8_t *prev_transitioned, const uint8_t *user_flag,
+                          const gf_pca_params *params, double *lam_3n, double *w3_3n,
+                          double *eps_n, uint8_t *flag_n);
+
+/* ---------------------------------------------------------- GFDM stencils */
+typedef struct {
+  double alpha_w;    /* support weight w(q) = (e^{-a q^2} - e^{-a}) / (1 - e^{-a}),
+                        q = |x_j - x_i| / ((h_i + h_j)/2); default a = 8      */
+  double kappa_max;  /* GF_BATCHED: 1-norm condition number of the Gram matrix
+                        above which a particle is re-solved by Householder QR
+                        (default 1e5)                                         */
+} gf_ls_params;
+void gf_ls_params_default(gf_ls_params *p);
+
+typedef struct {
+  int64_t n_ok, n_fallback, n_rank_deficient, n_too_few;
+  double kappa_max_seen;  /* largest Gram-matrix condition estimate */
+} gf_ls_stats;
+
+/* Second-order GFDM stencils (Eq. GFDM_Definition, order 2 as in Sec. 2.3).
+ * For particle i, with X = (x_j - x_i)/h_i (film: tangent coordinates of a
+ * frame built from the normal), monomials [1, X, Y, Z, X^2, Y^2, Z^2, XY, XZ,
+ * YZ] (film: [1, U, V, U^2, V^2, UV]) and weights w_j, the stencil is the
+ * minimum-norm solution (sum c_j^2 / w_j) of the exactness conditions, i.e.
+ * c = W M (M^T W M)^{-1} d.  Output w_out [nnz][4] in `wtype` (FP64 or FP32;
+ * GF_PLAIN_F64 requires FP64): physical weights for d/dx, d/dy, d/dz and the
+ * Laplacian, aligned with the neighbour CSR.  Film rows hold the surface
+ * gradient as global x, y, z components and the surface Laplacian.
+ * status_n (int8, device, may be NULL): 0 ok, 1 solved by the FP64 QR
+ * fallback, 2 rank deficient (zero weights), 3 fewer neighbours than
+ * monomials (zero weights).  kappa_n (float, device, may be NULL): condition
+ * estimate.  stats (host, may be NULL): synchronises and fills counts. */
+gf_status gf_gfdm_weights(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr, gf_prec prec,
+                          const gf_ls_params *params, gf_dtype wtype, void *w_out,
+                          int8_t *status_n, float *kappa_n, gf_ls_stats *stats);
+
+/* Apply stencils (Eq. GFDM_Definition) in differenced form:
+ *   out[s][i] = sum_{j in S_i, j != i} c_ij^s (u_j - u_i)
+ * for each operator s selected in op_mask (bit order dx, dy, dz, lap),
+ * stacked [K][n].  Weights of type wtype; u and out of type io; sums are
+ * accumulated in FP64. */
+gf_status gf_apply_stencil(gf_ctx *ctx, const gf_nbr *nbr, gf_dtype wtype, const void *w,
+                           unsigned op_mask, gf_dtype io, const void *u, void *out);
+
+/* Weights and application in one pass: computes the stencils exactly as
+ * gf_gfdm_weights (GF_BATCHED) and, while they are in registers, applies them
+ * to u (FP64) -> out [K][n] FP64 as gf_apply_stencil does.  w_out may be NULL
+ * (stencils used once and discarded). */
+gf_status gf_gfdm_weights_apply(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr,
+                                const gf_ls_params *params, gf_dtype wtype, void *w_out,
+                                unsigned op_mask, const double *u, double *out,
+                                int8_t *status_n);
+
+/* ---------------------------------------------------------- pressure solve */
+enum { GF_ROW_INTERIOR = 0, GF_ROW_DIRICHLET = 1, GF_ROW_NEUMANN_COMBINED = 2,
+       GF_ROW_NEUMANN = 3 };
+
+/* Pressure-system matrix values on the neighbour pattern (implicit pressure
+ * Poisson step of the projection scheme, Sec. 2.3; PDE + zeta*BC rows of
+ * Sec. 7.2):  row type 0: A_ij = c_ij^lap; 1: A_ij = delta_ij; 2: A_ij =
+ * c_ij^lap + (zeta/h_i) n_i . c_ij^grad; 3: A_ij = n_i . c_ij^grad.
+ * w64 [nnz][4] FP64 stencils; row_type int8 [n]; val_out FP64 [nnz]. */
+gf_status gf_poisson_assemble(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr,
+                              const double *w64, const int8_t *row_type, double zeta,
+                              double *val_out);
+
+typedef struct {
+  double rtol;        /* stop when ||b - A x||_2 <= rtol ||b||_2 (FP64 residual), 1e-8 */
+  int maxit;          /* iteration limit (inner iterations in mixed mode), 20000 */
+  int mixed;          /* 0: FP64 Jacobi-BiCGStab; 1: FP32-matrix inner Jacobi-
+                         BiCGStab with FP64 residual and iterative refinement */
+  double inner_rtol;  /* mixed: relative reduction per inner solve, 1e-4 */
+  int inner_maxit;    /* mixed: inner iteration limit per refinement, 2000 */
+  double zeta;        /* combined Neumann rows, 0.3 (Sec. 7.2) */
+  int check_every;    /* iterations between host convergence checks, 4 */
+} gf_solve_params;
+void gf_solve_params_default(gf_solve_params *p);
+
+typedef struct {
+  int outer_its;        /* refinement steps (1 in plain mode) */
+  int inner_its_total;  /* BiCGStab iterations in total */
+  int restarts;         /* breakdown restarts */
+  int converged;
+  double final_rel_res; /* ||b - A x|| / ||b|| in FP64 at exit */
+} gf_solve_stats;
+
+/* Solve A p = rhs with A assembled as in gf_poisson_assemble from FP64
+ * stencils w64.  Right-preconditioned BiCGStab with the Jacobi (diagonal)
+ * preconditioner.  p_inout: initial guess in, solution out (FP64, device).
+ * Synchronises (convergence checks).  Returns GF_ENOTCONV if the tolerance is
+ * not reached within maxit; p_inout then holds the last iterate. */
+gf_status gf_poisson_solve(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr,
+                           const double *w64, const int8_t *row_type, const double *rhs,
+                           double *p_inout, const gf_solve_params *params,
+                           gf_solve_stats *stats);
+
+/* ---------------------------------------------------------- 3D -> 2D */
+/* Transition of flagged 3D wall particles to the film (Sec. 5.1, Alg. 3).
+ * flag (uint8 [n], 1 = bulk->film) as from gf_classify_pca.  Candidates are
+ * interior / free-surface 3D neighbours of flagged particles; each candidate
+ * b is mapped to the nearest wall particle of S_b (smaller index on ties)
+ * and deleted iff that wall particle is flagged.  For flagged i with mapped
+ * set T_i: rho and phi are averaged over {i} + T_i, m_out = m_i + sum_T m_b,
+ * height_out = max_T |(x_b - x_i) . n_i| (0 if T_i is empty), diam_out =
+ * (6 m_out / (pi rho_out))^(1/3).  Other kept particles copy m, rho, phi and
+ * get height = diam = 0; deleted ones get m_out = 0.  keep_out (uint8) and
+ * owner_out (int32, -1 if kept) describe the deletion.  nbr: same-model
+ * neighbourhoods.  All arrays device, length n. */
+gf_status gf_transition_3d_to_2d(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr,
+                                 const uint8_t *flag, const double *mass, const double *rho,
+                                 const double *phi, double *mass_out, double *rho_out,
+                                 double *phi_out, double *height_out, double *diam_out,
+                                 uint8_t *keep_out, int32_t *owner_out);
+
+/* ---------------------------------------------------------- adjoints */
+/* Transpose of gf_apply_stencil with respect to u: ubar = C^T ybar, where
+ * ybar [K][n] FP64 holds dL/dout; ubar [n] FP64 is overwritten.
+ * Deterministic (gathers through the reverse-edge map, no atomics). */
+gf_status gf_apply_stencil_adjoint(gf_ctx *ctx, const gf_nbr *nbr, gf_dtype wtype,
+                                   const void *w, unsigned op_mask, const double *ybar,
+                                   double *ubar);
+
+/* Gradient with respect to particle positions of L(out), out =
+ * gf_apply_stencil(gf_gfdm_weights(p), u), given ybar = dL/dout [K][n] FP64
+ * and u [n] FP64.  The stencils are recomputed, not stored.  xbar_3n
+ * ([n][3] FP64) is accumulated (+=).  Rows with status 2 or 3 contribute
+ * nothing (their stencils are constant zero). */
+gf_status gf_gfdm_weights_adjoint(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr,
+                                  const gf_ls_params *params, unsigned op_mask,
+                                  const double *u, const double *ybar, double *xbar_3n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GFDM_H */

@@ -1,0 +1,161 @@
+// Stencil application (Eq. GFDM_Definition, differenced form) and its
+// transpose.  Rows are taken in the grouped Morton order of the neighbour
+// handle; a team of T lanes strides over a row's entries so one wave
+// instruction reads T consecutive 16-byte (FP32) or 32-byte (FP64) weight
+// records; partial sums are combined by a butterfly over the team and
+// accumulated in FP64.
+#include "stencil_common.h"
+
+using namespace gfdm_dev;
+
+namespace {
+constexpr int kBlock = 256;
+
+template <typename WT>
+struct W4;
+template <>
+struct W4<float> {
+  static __device__ inline void load(const void *w, int64_t k, double c[4]) {
+    const float4 v = reinterpret_cast<const float4 *>(w)[k];
+    c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
+  }
+};
+template <>
+struct W4<double> {
+  static __device__ inline void load(const void *w, int64_t k, double c[4]) {
+    const double2 *p = reinterpret_cast<const double2 *>(w) + 2 * k;
+    const double2 a = p[0], b = p[1];
+    c[0] = a.x; c[1] = a.y; c[2] = b.x; c[3] = b.y;
+  }
+};
+
+template <int T, typename WT, typename IOT>
+__global__ void __launch_bounds__(kBlock) k_apply(const int32_t *__restrict__ sched, int64_t nrows,
+                                                  const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                                                  const void *__restrict__ w, unsigned mask,
+                                                  const IOT *__restrict__ u, IOT *__restrict__ out, int64_t n) {
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t team = gt / T;
+  const int lane = (int)(gt % T);
+  if (team >= nrows) return;
+  const int32_t i = sched[team];
+  const int64_t b = row_ptr[i], e = row_ptr[i + 1];
+  const double ui = (double)u[i];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t k = b + lane; k < e; k += T) {
+    const int32_t j = col[k];
+    double c[4];
+    W4<WT>::load(w, k, c);
+    const double du = (j != i) ? (double)u[j] - ui : 0.0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc[s] += c[s] * du;
+  }
+  if constexpr (T > 1) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc[s] = team_sum(acc[s], T);
+  }
+  if (lane == 0) {
+    int q = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      if (mask & (1u << s)) out[(int64_t)(q++) * n + i] = (IOT)acc[s];
+  }
+}
+
+// ubar_j = sum_{i : j in S_i, i != j} c_ij ybar_i - ybar_j sum_{k in S_j, k != j} c_jk,
+// the first sum gathered through the reverse-edge map (entry (i,j) sits at
+// rev[k] for the entry k = (j,i) of row j).
+template <typename WT>
+__global__ void __launch_bounds__(kBlock) k_apply_adjoint(const int64_t *__restrict__ row_ptr,
+                                                          const int32_t *__restrict__ col,
+                                                          const int32_t *__restrict__ rev, const void *__restrict__ w,
+                                                          unsigned mask, const double *__restrict__ ybar, int64_t n,
+                                                          double *__restrict__ ubar) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  int sel[4], K = 0;
+  for (int s = 0; s < 4; ++s)
+    if (mask & (1u << s)) sel[K++] = s;
+  double yj[4];
+  for (int q = 0; q < K; ++q) yj[q] = ybar[(int64_t)q * n + j];
+  double acc = 0.0;
+  for (int64_t k = row_ptr[j]; k < row_ptr[j + 1]; ++k) {
+    const int32_t i = col[k];
+    const int32_t kr = rev[k];
+    if (i == j || kr < 0) continue;
+    double cin[4], cout_[4];
+    W4<WT>::load(w, kr, cin);  // c_ij (row i, column j)
+    W4<WT>::load(w, k, cout_);     // c_ji (row j, column i)
+    for (int q = 0; q < K; ++q) acc += cin[sel[q]] * ybar[(int64_t)q * n + i] - cout_[sel[q]] * yj[q];
+  }
+  ubar[j] = acc;
+}
+
+int apply_team(int band) {
+  static const int t[GF_NBAND] = {4, 8, 8, 16};
+  return t[band];
+}
+
+template <typename WT, typename IOT>
+gf_status launch_apply(gf_ctx *ctx, const gf_nbr *nbr, const void *w, unsigned mask, const void *u, void *out) {
+  for (int gsel = 0; gsel < 2 * GF_NBAND; ++gsel) {
+    const int64_t s0 = nbr->group_start[gsel], s1 = nbr->group_start[gsel + 1];
+    if (s1 <= s0) continue;
+    const int T = apply_team(gsel % GF_NBAND);
+    const dim3 grid(grid_for((s1 - s0) * T, kBlock)), block(kBlock);
+    const int32_t *sched = nbr->grouped + s0;
+    const IOT *uu = (const IOT *)u;
+    IOT *oo = (IOT *)out;
+    ProfScope prof(ctx, gsel < GF_NBAND ? "apply_3d" : "apply_film");
+    switch (T) {
+      case 4: hipLaunchKernelGGL((k_apply<4, WT, IOT>), grid, block, 0, ctx->stream, sched, s1 - s0, nbr->row_ptr, nbr->col, w, mask, uu, oo, nbr->n); break;
+      case 8: hipLaunchKernelGGL((k_apply<8, WT, IOT>), grid, block, 0, ctx->stream, sched, s1 - s0, nbr->row_ptr, nbr->col, w, mask, uu, oo, nbr->n); break;
+      default: hipLaunchKernelGGL((k_apply<16, WT, IOT>), grid, block, 0, ctx->stream, sched, s1 - s0, nbr->row_ptr, nbr->col, w, mask, uu, oo, nbr->n); break;
+    }
+    GF_LAUNCH_CHECK(ctx);
+  }
+  return GF_OK;
+}
+}  // namespace
+
+extern "C" gf_status gf_apply_stencil(gf_ctx *ctx, const gf_nbr *nbr, gf_dtype wtype, const void *w, unsigned op_mask,
+                                      gf_dtype io, const void *u, void *out) {
+  if (!ctx) return GF_EINVAL;
+  if (!nbr) return set_error(ctx, GF_EINVAL, "neighbour handle is NULL");
+  gf_status st = check_nbr(ctx, nbr, nbr->n);
+  if (st) return st;
+  if (nbr->cross) return set_error(ctx, GF_EINVAL, "stencils live on same-model neighbourhoods");
+  if (!w || !u || !out) return set_error(ctx, GF_EINVAL, "w, u and out are required");
+  if ((op_mask & 0xF) == 0 || (op_mask & ~0xFu)) return set_error(ctx, GF_EINVAL, "op_mask must select 1..4 operators");
+  if ((wtype != GF_F32 && wtype != GF_F64) || (io != GF_F32 && io != GF_F64))
+    return set_error(ctx, GF_EINVAL, "unknown dtype");
+  GF_HIP(ctx, hipSetDevice(ctx->device));
+  if (wtype == GF_F32) {
+    return io == GF_F64 ? launch_apply<float, double>(ctx, nbr, w, op_mask, u, out)
+                        : launch_apply<float, float>(ctx, nbr, w, op_mask, u, out);
+  }
+  return io == GF_F64 ? launch_apply<double, double>(ctx, nbr, w, op_mask, u, out)
+                      : launch_apply<double, float>(ctx, nbr, w, op_mask, u, out);
+}
+
+extern "C" gf_status gf_apply_stencil_adjoint(gf_ctx *ctx, const gf_nbr *nbr, gf_dtype wtype, const void *w,
+                                              unsigned op_mask, const double *ybar, double *ubar) {
+  if (!ctx) return GF_EINVAL;
+  if (!nbr) return set_error(ctx, GF_EINVAL, "neighbour handle is NULL");
+  gf_status st = check_nbr(ctx, nbr, nbr->n);
+  if (st) return st;
+  if (nbr->cross) return set_error(ctx, GF_EINVAL, "stencils live on same-model neighbourhoods");
+  if (!w || !ybar || !ubar) return set_error(ctx, GF_EINVAL, "w, ybar and ubar are required");
+  if ((op_mask & 0xF) == 0 || (op_mask & ~0xFu)) return set_error(ctx, GF_EINVAL, "op_mask must select 1..4 operators");
+  if (wtype != GF_F32 && wtype != GF_F64) return set_error(ctx, GF_EINVAL, "unknown dtype");
+  GF_HIP(ctx, hipSetDevice(ctx->device));
+  if ((st = ensure_rev(ctx, const_cast<gf_nbr *>(nbr)))) return st;
+  const dim3 grid(grid_for(nbr->n, kBlock)), block(kBlock);
+  ProfScope prof(ctx, "apply_adjoint");
+  if (wtype == GF_F32)
+    hipLaunchKernelGGL(k_apply_adjoint<float>, grid, block, 0, ctx->stream, nbr->row_ptr, nbr->col, nbr->rev, w, op_mask, ybar, nbr->n, ubar);
+  else
+    hipLaunchKernelGGL(k_apply_adjoint<double>, grid, block, 0, ctx->stream, nbr->row_ptr, nbr->col, nbr->rev, w, op_mask, ybar, nbr->n, ubar);
+  GF_LAUNCH_CHECK(ctx);
+  return GF_OK;
+}

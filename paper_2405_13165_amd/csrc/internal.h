@@ -1,0 +1,121 @@
+// Internal declarations of the gfdm library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/gfdm.h"
+
+struct gf_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cu = 256;
+  std::string err;
+  // grow-only scratch arena (device); carved per call, valid until the next
+  // call on this context
+  void *scratch = nullptr;
+  size_t scratch_bytes = 0;
+  // small pinned host buffer for read-backs
+  void *host_pinned = nullptr;
+  size_t host_pinned_bytes = 0;
+  // optional per-kernel timing with HIP events (gf_profile_enable)
+  int profile = 0;
+  struct ProfRec {
+    const char *name;
+    hipEvent_t start, stop;
+  };
+  std::vector<ProfRec> prof_pending;
+  std::vector<hipEvent_t> prof_pool;
+};
+
+// Brackets a kernel launch with events on the context stream when profiling
+// is enabled (names must be string literals).
+struct ProfScope {
+  gf_ctx *ctx;
+  int idx = -1;
+  ProfScope(gf_ctx *c, const char *name);
+  ~ProfScope();
+};
+
+// Row groups of the batched kernels: particles of one model whose neighbour
+// count falls in one band, in Morton (cell) order.
+enum { GF_NBAND = 4 };
+static const int kBandHi[GF_NBAND] = {24, 48, 128, 1 << 30};
+
+struct gf_nbr {
+  int device = 0;
+  int64_t n = 0;
+  int64_t nnz = 0;
+  int32_t max_row = 0;
+  int cross = 0;
+  int64_t *row_ptr = nullptr;  // [n+1]
+  int32_t *col = nullptr;      // [nnz]
+  int32_t *order = nullptr;    // [n] particles in cell (Morton) order
+  int32_t *grouped = nullptr;  // [n] particles grouped by (model, band), Morton order inside
+  int64_t group_start[2 * GF_NBAND + 1] = {0};  // host copy of the group offsets
+  int32_t *rev = nullptr;      // [nnz] position of (j,i) for entry (i,j); built lazily
+};
+
+// ------------------------------------------------------------------ errors
+gf_status set_error(gf_ctx *ctx, gf_status st, const char *fmt, ...);
+
+#define GF_HIP(ctx, call)                                                          \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return set_error((ctx), GF_EHIP, "%s failed: %s (%s:%d)", #call,            \
+                       hipGetErrorString(e_), __FILE__, __LINE__);                 \
+  } while (0)
+
+#define GF_LAUNCH_CHECK(ctx) GF_HIP(ctx, hipGetLastError())
+
+// ------------------------------------------------------------------ scratch
+struct Arena {
+  char *base = nullptr;
+  size_t off = 0;
+  template <class T>
+  T *take(size_t count) {
+    size_t a = (off + 255) & ~size_t(255);
+    T *p = reinterpret_cast<T *>(base + a);
+    off = a + count * sizeof(T);
+    return p;
+  }
+};
+size_t arena_bytes(const std::vector<size_t> &sizes);
+gf_status ensure_scratch(gf_ctx *ctx, size_t bytes, Arena *arena);
+gf_status ensure_host(gf_ctx *ctx, size_t bytes);
+
+// validation of a particle struct against a neighbour handle
+gf_status check_particles(gf_ctx *ctx, const gf_particles *p, bool need_kind, bool need_normals);
+gf_status check_nbr(gf_ctx *ctx, const gf_nbr *nbr, int64_t n);
+gf_status ensure_rev(gf_ctx *ctx, gf_nbr *nbr);
+
+// device-wide exclusive scans (in place allowed): out[k] = sum_{t<k} in[t],
+// out[n] = total.  tmp must hold scan_tmp_elems(n) elements of the output type.
+size_t scan_tmp_elems(int64_t n);
+gf_status scan_i32_to_i64(gf_ctx *ctx, const int32_t *in, int64_t *out, int64_t n, int64_t *tmp);
+gf_status scan_i32_to_i32(gf_ctx *ctx, const int32_t *in, int32_t *out, int64_t n, int32_t *tmp);
+
+static inline unsigned grid_for(int64_t work_items, int block) {
+  int64_t g = (work_items + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > 0x7fffffff) g = 0x7fffffff;
+  return (unsigned)g;
+}
+
+// support weight parameters shared by the stencil kernels
+struct WeightFn {
+  double alpha, ea, inv_den;  // e^{-a}, 1/(1 - e^{-a})
+};
+static inline WeightFn make_weight_fn(double alpha) {
+  WeightFn f;
+  f.alpha = alpha;
+  f.ea = std::exp(-alpha);
+  f.inv_den = 1.0 / (1.0 - f.ea);
+  return f;
+}

@@ -1,0 +1,521 @@
+// Implicit pressure-Poisson solve (projection scheme, Sec. 2.3) on the GFDM
+// stencils: assembly of the matrix on the neighbour pattern, then
+// right-preconditioned BiCGStab with the Jacobi preconditioner.
+//
+// The iteration runs as five fused kernels (direction update, SpMV + dot,
+// intermediate update, SpMV + two dots, solution/residual update + two dots).
+// Scalars (rho, alpha, omega, ...) stay on the device; every dot product is
+// a deterministic two-level reduction finished by the last block to arrive
+// (fixed summation order, counter reset by that block).  The host reads the
+// residual norm every few iterations.
+//
+// Mixed mode: the outer loop forms r = b - A x with FP64 matrix values and
+// vectors; the inner BiCGStab runs on FP32 matrix values and FP32 vectors
+// (dots accumulated in FP64) to a relative reduction inner_rtol; x += d.
+#include <algorithm>
+#include <cstring>
+
+#include "stencil_common.h"
+
+using namespace gfdm_dev;
+
+namespace {
+constexpr int kBlock = 256;
+constexpr int kTeam = 8;
+
+struct Scal {
+  double rho, rho_old, alpha, omega, rv, ts, tt, rr, bb;
+  int breakdown;
+  int pad;
+};
+
+// ---------------------------------------------------------------- reductions
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline double block_sum(double v) {
+  __shared__ double sh[kBlock / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) r += sh[w];
+  return r;
+}
+
+// Reduce NV values over the grid; returns true in the last block with the
+// totals in res (identical on every thread of that block).
+template <int NV>
+__device__ bool grid_reduce(const double v[NV], double *part, unsigned *counter, double res[NV]) {
+  __shared__ int last;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const double s = block_sum(v[k]);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * NV + k] = s;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = (atomicAdd(counter, 1u) == gridDim.x - 1) ? 1 : 0;
+  __syncthreads();
+  if (!last) return false;
+  __threadfence();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double acc = 0.0;
+    for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x) acc += part[(int64_t)b * NV + k];
+    res[k] = block_sum(acc);
+  }
+  if (threadIdx.x == 0) *counter = 0u;
+  return true;
+}
+
+// ---------------------------------------------------------------- assembly
+__global__ void __launch_bounds__(kBlock) k_assemble(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                                                     const double *__restrict__ w, const int8_t *__restrict__ row_type,
+                                                     const double *__restrict__ h, const double *__restrict__ nx,
+                                                     const double *__restrict__ ny, const double *__restrict__ nz,
+                                                     double zeta, int64_t n, double *__restrict__ val64,
+                                                     float *__restrict__ val32, double *__restrict__ dinv64,
+                                                     float *__restrict__ dinv32, int *__restrict__ bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int rt = row_type[i];
+  double nrm[3] = {0.0, 0.0, 0.0};
+  if (rt == GF_ROW_NEUMANN_COMBINED || rt == GF_ROW_NEUMANN) { nrm[0] = nx[i]; nrm[1] = ny[i]; nrm[2] = nz[i]; }
+  const double zf = zeta / h[i];
+  double diag = 0.0;
+  for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+    const double2 *p = reinterpret_cast<const double2 *>(w) + 2 * k;
+    const double2 g01 = p[0], g23 = p[1];
+    const double ngrad = nrm[0] * g01.x + nrm[1] * g01.y + nrm[2] * g23.x;
+    double v;
+    switch (rt) {
+      case GF_ROW_INTERIOR: v = g23.y; break;
+      case GF_ROW_DIRICHLET: v = (col[k] == i) ? 1.0 : 0.0; break;
+      case GF_ROW_NEUMANN_COMBINED: v = g23.y + zf * ngrad; break;
+      default: v = ngrad; break;
+    }
+    if (val64) val64[k] = v;
+    if (val32) val32[k] = (float)v;
+    if (col[k] == i) diag = v;
+  }
+  if (rt < 0 || rt > 3 || diag == 0.0 || !isfinite(diag)) atomicAdd(bad, 1);
+  if (dinv64) dinv64[i] = (diag != 0.0) ? 1.0 / diag : 0.0;
+  if (dinv32) dinv32[i] = (diag != 0.0) ? (float)(1.0 / diag) : 0.0f;
+}
+
+// ---------------------------------------------------------------- kernels
+// r = b - A x (FP64), optionally rhat = r and scalars reset; reduces (r,r)
+// and, if bb_too, (b,b).
+__global__ void __launch_bounds__(kBlock) k_residual(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                                                     const double *__restrict__ val, const double *__restrict__ b,
+                                                     const double *__restrict__ x, int64_t n, double *__restrict__ r,
+                                                     double *__restrict__ rhat, double *part, unsigned *counter, Scal *S,
+                                                     int reset) {
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t row = gt / kTeam;
+  const int lane = (int)(gt % kTeam);
+  double v[2] = {0.0, 0.0};
+  if (row < n) {
+    double acc = 0.0;
+    for (int64_t k = row_ptr[row] + lane; k < row_ptr[row + 1]; k += kTeam) acc += val[k] * x[col[k]];
+    acc = team_sum(acc, kTeam);
+    if (lane == 0) {
+      const double ri = b[row] - acc;
+      r[row] = ri;
+      if (rhat) rhat[row] = ri;
+      v[0] = ri * ri;
+      v[1] = b[row] * b[row];
+    }
+  }
+  double res[2];
+  if (grid_reduce<2>(v, part, counter, res) && threadIdx.x == 0) {
+    S->rr = res[0];
+    S->bb = res[1];
+    if (reset) {
+      S->rho = res[0];  // rhat = r
+      S->rho_old = 1.0;
+      S->alpha = 1.0;
+      S->omega = 1.0;
+      S->breakdown = 0;
+    }
+  }
+}
+
+// x32 = (float) r64; rhat32 = x32; p = v = 0; scalars reset with rho = (r,r)
+template <typename XT>
+__global__ void __launch_bounds__(kBlock) k_inner_init(const double *__restrict__ r64, int64_t n, XT *__restrict__ r,
+                                                       XT *__restrict__ rhat, XT *__restrict__ p, XT *__restrict__ vv,
+                                                       XT *__restrict__ x, double *part, unsigned *counter, Scal *S) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double v[1] = {0.0};
+  if (i < n) {
+    const XT ri = (XT)r64[i];
+    r[i] = ri;
+    rhat[i] = ri;
+    p[i] = (XT)0;
+    vv[i] = (XT)0;
+    x[i] = (XT)0;
+    v[0] = (double)ri * (double)ri;
+  }
+  double res[1];
+  if (grid_reduce<1>(v, part, counter, res) && threadIdx.x == 0) {
+    S->rr = res[0];
+    S->rho = res[0];
+    S->rho_old = 1.0;
+    S->alpha = 1.0;
+    S->omega = 1.0;
+    S->breakdown = 0;
+  }
+}
+
+template <typename XT>
+__global__ void __launch_bounds__(kBlock) k_zero_vecs(int64_t n, XT *a, XT *b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) { a[i] = (XT)0; b[i] = (XT)0; }
+}
+
+// p = r + beta (p - omega v); phat = p * dinv
+template <typename XT>
+__global__ void __launch_bounds__(kBlock) k_update_p(const XT *__restrict__ r, const XT *__restrict__ vv,
+                                                     const XT *__restrict__ dinv, int64_t n, XT *__restrict__ p,
+                                                     XT *__restrict__ phat, const Scal *__restrict__ S) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || S->breakdown) return;
+  const double beta = (S->rho / S->rho_old) * (S->alpha / S->omega);
+  const double pi = (double)r[i] + beta * ((double)p[i] - S->omega * (double)vv[i]);
+  p[i] = (XT)pi;
+  phat[i] = (XT)(pi * (double)dinv[i]);
+}
+
+// y = A xin; reduces (rhat, y) -> alpha = rho / (rhat, y)       [STAGE 0]
+// y = A xin; reduces (y, s), (y, y) -> omega = (t,s)/(t,t)       [STAGE 1]
+template <typename VT, typename XT, int STAGE>
+__global__ void __launch_bounds__(kBlock) k_spmv_dot(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                                                     const VT *__restrict__ val, const XT *__restrict__ xin, int64_t n,
+                                                     XT *__restrict__ y, const XT *__restrict__ other, double *part,
+                                                     unsigned *counter, Scal *S) {
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t row = gt / kTeam;
+  const int lane = (int)(gt % kTeam);
+  const bool live = !S->breakdown;
+  double v[2] = {0.0, 0.0};
+  if (row < n && live) {
+    double acc = 0.0;
+    for (int64_t k = row_ptr[row] + lane; k < row_ptr[row + 1]; k += kTeam) acc += (double)val[k] * (double)xin[col[k]];
+    acc = team_sum(acc, kTeam);
+    if (lane == 0) {
+      const XT yi = (XT)acc;
+      y[row] = yi;
+      const double o = (double)other[row];
+      v[0] = o * (double)yi;
+      v[1] = (double)yi * (double)yi;
+    }
+  }
+  double res[2];
+  if (grid_reduce<2>(v, part, counter, res) && threadIdx.x == 0 && live) {
+    if (STAGE == 0) {
+      const double rv = res[0];
+      S->rv = rv;
+      if (rv == 0.0 || !isfinite(rv)) S->breakdown = 1;
+      else S->alpha = S->rho / rv;
+    } else {
+      S->ts = res[0];
+      S->tt = res[1];
+      if (res[1] == 0.0 || !isfinite(res[1])) S->breakdown = 2;
+      else S->omega = res[0] / res[1];
+      if (S->omega == 0.0) S->breakdown = 3;
+    }
+  }
+}
+
+// s = r - alpha v; shat = s * dinv
+template <typename XT>
+__global__ void __launch_bounds__(kBlock) k_update_s(const XT *__restrict__ r, const XT *__restrict__ vv,
+                                                     const XT *__restrict__ dinv, int64_t n, XT *__restrict__ s,
+                                                     XT *__restrict__ shat, const Scal *__restrict__ S) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || S->breakdown) return;
+  const double si = (double)r[i] - S->alpha * (double)vv[i];
+  s[i] = (XT)si;
+  shat[i] = (XT)(si * (double)dinv[i]);
+}
+
+// x += alpha phat + omega shat; r = s - omega t; reduces (rhat, r), (r, r)
+template <typename XT>
+__global__ void __launch_bounds__(kBlock) k_update_xr(const XT *__restrict__ phat, const XT *__restrict__ shat,
+                                                      const XT *__restrict__ s, const XT *__restrict__ t,
+                                                      const XT *__restrict__ rhat, int64_t n, XT *__restrict__ x,
+                                                      XT *__restrict__ r, double *part, unsigned *counter, Scal *S) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = !S->breakdown;
+  double v[2] = {0.0, 0.0};
+  if (i < n && live) {
+    const double al = S->alpha, om = S->omega;
+    x[i] = (XT)((double)x[i] + al * (double)phat[i] + om * (double)shat[i]);
+    const double ri = (double)s[i] - om * (double)t[i];
+    r[i] = (XT)ri;
+    v[0] = (double)rhat[i] * (double)(XT)ri;
+    v[1] = (double)(XT)ri * (double)(XT)ri;
+  }
+  double res[2];
+  if (grid_reduce<2>(v, part, counter, res) && threadIdx.x == 0 && live) {
+    S->rho_old = S->rho;
+    S->rho = res[0];
+    S->rr = res[1];
+    if (res[0] == 0.0 || !isfinite(res[0])) S->breakdown = 4;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_add_f32(double *__restrict__ x, const float *__restrict__ d, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] += (double)d[i];
+}
+
+__global__ void k_reset_counter(unsigned *c) {
+  if (threadIdx.x == 0) *c = 0u;
+}
+
+struct Solver {
+  gf_ctx *ctx;
+  const gf_nbr *nbr;
+  int64_t n;
+  double *part;
+  unsigned *counter;
+  Scal *S;
+  Scal *hS;
+  unsigned grid_row, grid_team;
+};
+
+gf_status read_scal(Solver &sv) {
+  GF_HIP(sv.ctx, hipMemcpyAsync(sv.hS, sv.S, sizeof(Scal), hipMemcpyDeviceToHost, sv.ctx->stream));
+  GF_HIP(sv.ctx, hipStreamSynchronize(sv.ctx->stream));
+  return GF_OK;
+}
+
+template <typename VT, typename XT>
+struct Vecs {
+  const VT *val;
+  const XT *dinv;
+  XT *x, *r, *rhat, *p, *v, *phat, *s, *shat, *t;
+};
+
+// one BiCGStab iteration (5 launches)
+template <typename VT, typename XT>
+gf_status bicgstab_iter(Solver &sv, const Vecs<VT, XT> &V) {
+  hipStream_t sm = sv.ctx->stream;
+  const int64_t n = sv.n;
+  ProfScope prof(sv.ctx, sizeof(VT) == 8 ? "bicgstab_iter_f64" : "bicgstab_iter_f32");
+  hipLaunchKernelGGL((k_update_p<XT>), dim3(sv.grid_row), dim3(kBlock), 0, sm, V.r, V.v, V.dinv, n, V.p, V.phat, sv.S);
+  hipLaunchKernelGGL((k_spmv_dot<VT, XT, 0>), dim3(sv.grid_team), dim3(kBlock), 0, sm, sv.nbr->row_ptr, sv.nbr->col,
+                     V.val, V.phat, n, V.v, V.rhat, sv.part, sv.counter, sv.S);
+  hipLaunchKernelGGL((k_update_s<XT>), dim3(sv.grid_row), dim3(kBlock), 0, sm, V.r, V.v, V.dinv, n, V.s, V.shat, sv.S);
+  hipLaunchKernelGGL((k_spmv_dot<VT, XT, 1>), dim3(sv.grid_team), dim3(kBlock), 0, sm, sv.nbr->row_ptr, sv.nbr->col,
+                     V.val, V.shat, n, V.t, V.s, sv.part, sv.counter, sv.S);
+  hipLaunchKernelGGL((k_update_xr<XT>), dim3(sv.grid_row), dim3(kBlock), 0, sm, V.phat, V.shat, V.s, V.t, V.rhat, n,
+                     V.x, V.r, sv.part, sv.counter, sv.S);
+  GF_LAUNCH_CHECK(sv.ctx);
+  return GF_OK;
+}
+}  // namespace
+
+extern "C" void gf_solve_params_default(gf_solve_params *p) {
+  if (!p) return;
+  p->rtol = 1e-8;
+  p->maxit = 20000;
+  p->mixed = 0;
+  p->inner_rtol = 1e-4;
+  p->inner_maxit = 2000;
+  p->zeta = 0.3;
+  p->check_every = 4;
+}
+
+static gf_status assemble_common(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr, const double *w64,
+                                 const int8_t *row_type, double zeta, double *val64, float *val32, double *dinv64,
+                                 float *dinv32, int *bad) {
+  hipLaunchKernelGGL(k_assemble, dim3(grid_for(p->n, kBlock)), dim3(kBlock), 0, ctx->stream, nbr->row_ptr, nbr->col,
+                     w64, row_type, p->h, p->nx, p->ny, p->nz, zeta, p->n, val64, val32, dinv64, dinv32, bad);
+  GF_LAUNCH_CHECK(ctx);
+  return GF_OK;
+}
+
+static gf_status check_solve_args(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr, const double *w64,
+                                  const int8_t *row_type) {
+  gf_status st = check_particles(ctx, p, false, false);
+  if (st) return st;
+  if ((st = check_nbr(ctx, nbr, p->n))) return st;
+  if (nbr->cross) return set_error(ctx, GF_EINVAL, "the pressure system lives on same-model neighbourhoods");
+  if (!w64 || !row_type) return set_error(ctx, GF_EINVAL, "w64 and row_type are required");
+  return GF_OK;
+}
+
+extern "C" gf_status gf_poisson_assemble(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr, const double *w64,
+                                         const int8_t *row_type, double zeta, double *val_out) {
+  if (!ctx) return GF_EINVAL;
+  gf_status st = check_solve_args(ctx, p, nbr, w64, row_type);
+  if (st) return st;
+  if (!val_out) return set_error(ctx, GF_EINVAL, "val_out is NULL");
+  if (!p->nx || !p->ny || !p->nz) return set_error(ctx, GF_EINVAL, "normals are required for Neumann rows");
+  Arena ar;
+  if ((st = ensure_scratch(ctx, arena_bytes({64}), &ar))) return st;
+  int *bad = ar.take<int>(16);
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, ctx->stream, (unsigned *)bad);
+  return assemble_common(ctx, p, nbr, w64, row_type, zeta, val_out, nullptr, nullptr, nullptr, bad);
+}
+
+extern "C" gf_status gf_poisson_solve(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr, const double *w64,
+                                      const int8_t *row_type, const double *rhs, double *p_inout,
+                                      const gf_solve_params *params, gf_solve_stats *stats) {
+  if (!ctx) return GF_EINVAL;
+  gf_status st = check_solve_args(ctx, p, nbr, w64, row_type);
+  if (st) return st;
+  if (!rhs || !p_inout) return set_error(ctx, GF_EINVAL, "rhs and p_inout are required");
+  if (!p->nx || !p->ny || !p->nz) return set_error(ctx, GF_EINVAL, "normals are required for Neumann rows");
+  gf_solve_params prm;
+  gf_solve_params_default(&prm);
+  if (params) prm = *params;
+  if (!(prm.rtol > 0.0) || prm.maxit <= 0 || prm.check_every <= 0 || (prm.mixed && (!(prm.inner_rtol > 0.0) || prm.inner_maxit <= 0)))
+    return set_error(ctx, GF_EINVAL, "invalid solver parameters");
+  gf_solve_stats sts;
+  memset(&sts, 0, sizeof(sts));
+  const int64_t n = p->n, nnz = nbr->nnz;
+  const bool mixed = prm.mixed != 0;
+  Arena ar;
+  const int nblk_team = (int)grid_for(n * kTeam, kBlock), nblk_row = (int)grid_for(n, kBlock);
+  const int nblk = std::max(nblk_team, nblk_row);
+  std::vector<size_t> sz = {sizeof(double) * nnz, sizeof(double) * n, sizeof(double) * 2 * nblk + 64, 64,
+                            sizeof(Scal), 64};
+  for (int k = 0; k < 9; ++k) sz.push_back(sizeof(double) * n);
+  if (mixed) {
+    sz.push_back(sizeof(float) * nnz);
+    sz.push_back(sizeof(float) * n);
+    for (int k = 0; k < 9; ++k) sz.push_back(sizeof(float) * n);
+  }
+  if ((st = ensure_scratch(ctx, arena_bytes(sz), &ar))) return st;
+  double *val64 = ar.take<double>(nnz);
+  double *dinv64 = ar.take<double>(n);
+  double *part = ar.take<double>(2 * nblk + 8);
+  unsigned *counter = ar.take<unsigned>(16);
+  Scal *S = ar.take<Scal>(1);
+  int *bad = ar.take<int>(16);
+  double *vec64[9];
+  for (int k = 0; k < 9; ++k) vec64[k] = ar.take<double>(n);
+  float *val32 = nullptr, *dinv32 = nullptr, *vec32[9] = {nullptr};
+  if (mixed) {
+    val32 = ar.take<float>(nnz);
+    dinv32 = ar.take<float>(n);
+    for (int k = 0; k < 9; ++k) vec32[k] = ar.take<float>(n);
+  }
+  if ((st = ensure_host(ctx, 4096))) return st;
+  hipStream_t sm = ctx->stream;
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, sm, counter);
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, sm, (unsigned *)bad);
+  if ((st = assemble_common(ctx, p, nbr, w64, row_type, prm.zeta, val64, val32, dinv64, dinv32, bad))) return st;
+  Solver sv;
+  sv.ctx = ctx; sv.nbr = nbr; sv.n = n; sv.part = part; sv.counter = counter; sv.S = S;
+  sv.hS = (Scal *)ctx->host_pinned;
+  sv.grid_row = (unsigned)nblk_row;
+  sv.grid_team = (unsigned)nblk_team;
+  int *hbad = (int *)((char *)ctx->host_pinned + 1024);
+  GF_HIP(ctx, hipMemcpyAsync(hbad, bad, sizeof(int), hipMemcpyDeviceToHost, sm));
+  // FP64 work vectors: x is the caller's array
+  Vecs<double, double> V64;
+  V64.val = val64; V64.dinv = dinv64; V64.x = p_inout;
+  V64.r = vec64[0]; V64.rhat = vec64[1]; V64.p = vec64[2]; V64.v = vec64[3]; V64.phat = vec64[4];
+  V64.s = vec64[5]; V64.shat = vec64[6]; V64.t = vec64[7];
+  // initial residual
+  hipLaunchKernelGGL(k_residual, dim3(sv.grid_team), dim3(kBlock), 0, sm, nbr->row_ptr, nbr->col, val64, rhs, p_inout,
+                     n, V64.r, V64.rhat, part, counter, S, 1);
+  hipLaunchKernelGGL(k_zero_vecs<double>, dim3(sv.grid_row), dim3(kBlock), 0, sm, n, V64.p, V64.v);
+  GF_LAUNCH_CHECK(ctx);
+  if ((st = read_scal(sv))) return st;
+  if (*hbad > 0) return set_error(ctx, GF_EINVAL, "%d rows have an unknown row type or a zero/non-finite diagonal", *hbad);
+  const double bnorm = std::sqrt(sv.hS->bb);
+  double rnorm = std::sqrt(sv.hS->rr);
+  if (bnorm == 0.0) {
+    // the solution of A p = 0 is p = 0
+    hipLaunchKernelGGL(k_zero_vecs<double>, dim3(sv.grid_row), dim3(kBlock), 0, sm, n, p_inout, V64.r);
+    GF_LAUNCH_CHECK(ctx);
+    sts.converged = 1;
+    if (stats) *stats = sts;
+    return GF_OK;
+  }
+  const double target = prm.rtol * bnorm;
+  int total = 0;
+  if (!mixed) {
+    sts.outer_its = 1;
+    while (rnorm > target && total < prm.maxit) {
+      if ((st = bicgstab_iter<double, double>(sv, V64))) return st;
+      ++total;
+      if (total % prm.check_every != 0 && total < prm.maxit) continue;
+      if ((st = read_scal(sv))) return st;
+      if (sv.hS->breakdown) {
+        if (++sts.restarts > 50) {
+          sts.inner_its_total = total;
+          if (stats) *stats = sts;
+          return set_error(ctx, GF_EBREAKDOWN, "BiCGStab broke down repeatedly (code %d)", sv.hS->breakdown);
+        }
+        hipLaunchKernelGGL(k_residual, dim3(sv.grid_team), dim3(kBlock), 0, sm, nbr->row_ptr, nbr->col, val64, rhs,
+                           p_inout, n, V64.r, V64.rhat, part, counter, S, 1);
+        hipLaunchKernelGGL(k_zero_vecs<double>, dim3(sv.grid_row), dim3(kBlock), 0, sm, n, V64.p, V64.v);
+        if ((st = read_scal(sv))) return st;
+        rnorm = std::sqrt(sv.hS->rr);
+        continue;
+      }
+      rnorm = std::sqrt(sv.hS->rr);
+      if (rnorm <= target) {
+        // replace the recursive residual by the true one
+        hipLaunchKernelGGL(k_residual, dim3(sv.grid_team), dim3(kBlock), 0, sm, nbr->row_ptr, nbr->col, val64, rhs,
+                           p_inout, n, V64.r, (double *)nullptr, part, counter, S, 0);
+        if ((st = read_scal(sv))) return st;
+        rnorm = std::sqrt(sv.hS->rr);
+      }
+    }
+  } else {
+    Vecs<float, float> V32;
+    V32.val = val32; V32.dinv = dinv32; V32.x = vec32[8];
+    V32.r = vec32[0]; V32.rhat = vec32[1]; V32.p = vec32[2]; V32.v = vec32[3]; V32.phat = vec32[4];
+    V32.s = vec32[5]; V32.shat = vec32[6]; V32.t = vec32[7];
+    while (rnorm > target && total < prm.maxit) {
+      ++sts.outer_its;
+      // inner solve of A32 d = r64 from d = 0
+      hipLaunchKernelGGL(k_inner_init<float>, dim3(sv.grid_row), dim3(kBlock), 0, sm, V64.r, n, V32.r, V32.rhat,
+                         V32.p, V32.v, V32.x, part, counter, S);
+      GF_LAUNCH_CHECK(ctx);
+      const double inner_target = prm.inner_rtol * rnorm;
+      int it = 0;
+      double irn = rnorm;
+      while (it < prm.inner_maxit && total < prm.maxit) {
+        if ((st = bicgstab_iter<float, float>(sv, V32))) return st;
+        ++it;
+        ++total;
+        if (it % prm.check_every != 0) continue;
+        if ((st = read_scal(sv))) return st;
+        if (sv.hS->breakdown) { ++sts.restarts; break; }
+        irn = std::sqrt(sv.hS->rr);
+        if (irn <= inner_target) break;
+      }
+      hipLaunchKernelGGL(k_add_f32, dim3(sv.grid_row), dim3(kBlock), 0, sm, p_inout, V32.x, n);
+      hipLaunchKernelGGL(k_residual, dim3(sv.grid_team), dim3(kBlock), 0, sm, nbr->row_ptr, nbr->col, val64, rhs,
+                         p_inout, n, V64.r, (double *)nullptr, part, counter, S, 0);
+      GF_LAUNCH_CHECK(ctx);
+      if ((st = read_scal(sv))) return st;
+      const double prev = rnorm;
+      rnorm = std::sqrt(sv.hS->rr);
+      if (sts.restarts > 50) break;
+      if (!(rnorm < prev) && sts.outer_its > 3) break;  // refinement stagnated
+    }
+  }
+  sts.inner_its_total = total;
+  sts.final_rel_res = rnorm / bnorm;
+  sts.converged = rnorm <= target;
+  if (stats) *stats = sts;
+  if (!sts.converged)
+    return set_error(ctx, GF_ENOTCONV, "not converged: relative residual %.3e after %d iterations", sts.final_rel_res, total);
+  return GF_OK;
+}

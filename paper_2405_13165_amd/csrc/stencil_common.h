@@ -1,0 +1,270 @@
+// Device helpers shared by the stencil kernels (weights, fused application,
+// position adjoint): local monomial bases, the support weight, packed
+// symmetric Gram matrices and their LDL^T factorisation.
+#pragma once
+
+#include "internal.h"
+
+namespace gfdm_dev {
+
+// number of monomials of the second-order basis: 10 in 3D, 6 on a film
+__host__ __device__ constexpr int npack(int M) { return M * (M + 1) / 2; }
+// packed upper-triangular index of (a, c), a <= c
+__host__ __device__ constexpr int pidx(int a, int c, int M) { return a * M - (a * (a - 1)) / 2 + (c - a); }
+
+struct RowGeom {
+  double xi, yi, zi, hi, inv_h;
+  double t1[3], t2[3];  // film tangent frame
+};
+
+// Tangent frame of a film particle from its unit normal: t1 is the axis least
+// aligned with n projected onto the tangent plane, t2 = n x t1.
+__device__ inline void tangent_frame(double nx, double ny, double nz, double t1[3], double t2[3]) {
+  const double an[3] = {fabs(nx), fabs(ny), fabs(nz)};
+  int a = 0;
+  if (an[1] < an[a]) a = 1;
+  if (an[2] < an[a]) a = 2;
+  const double n[3] = {nx, ny, nz};
+  double e[3] = {0.0, 0.0, 0.0};
+  e[a] = 1.0;
+  const double en = n[a];
+  double t[3] = {e[0] - en * n[0], e[1] - en * n[1], e[2] - en * n[2]};
+  const double l = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+  t1[0] = t[0] / l; t1[1] = t[1] / l; t1[2] = t[2] / l;
+  t2[0] = n[1] * t1[2] - n[2] * t1[1];
+  t2[1] = n[2] * t1[0] - n[0] * t1[2];
+  t2[2] = n[0] * t1[1] - n[1] * t1[0];
+}
+
+// monomials of the scaled local coordinates
+template <int M>
+__device__ inline void monomials(const RowGeom &g, double dx, double dy, double dz, double phi[M]) {
+  if constexpr (M == 10) {
+    const double X = dx * g.inv_h, Y = dy * g.inv_h, Z = dz * g.inv_h;
+    phi[0] = 1.0; phi[1] = X; phi[2] = Y; phi[3] = Z;
+    phi[4] = X * X; phi[5] = Y * Y; phi[6] = Z * Z;
+    phi[7] = X * Y; phi[8] = X * Z; phi[9] = Y * Z;
+  } else {
+    const double U = (dx * g.t1[0] + dy * g.t1[1] + dz * g.t1[2]) * g.inv_h;
+    const double V = (dx * g.t2[0] + dy * g.t2[1] + dz * g.t2[2]) * g.inv_h;
+    phi[0] = 1.0; phi[1] = U; phi[2] = V;
+    phi[3] = U * U; phi[4] = V * V; phi[5] = U * V;
+  }
+}
+
+// derivative of the monomials with respect to the offset d = x_j - x_i,
+// contracted with a coefficient vector: returns sum_a pb[a] d(phi_a)/dd
+template <int M>
+__device__ inline void monomials_grad_dot(const RowGeom &g, double dx, double dy, double dz, const double pb[M],
+                                          double out[3]) {
+  if constexpr (M == 10) {
+    const double X = dx * g.inv_h, Y = dy * g.inv_h, Z = dz * g.inv_h;
+    const double gX = pb[1] + 2.0 * X * pb[4] + Y * pb[7] + Z * pb[8];
+    const double gY = pb[2] + 2.0 * Y * pb[5] + X * pb[7] + Z * pb[9];
+    const double gZ = pb[3] + 2.0 * Z * pb[6] + X * pb[8] + Y * pb[9];
+    out[0] = gX * g.inv_h; out[1] = gY * g.inv_h; out[2] = gZ * g.inv_h;
+  } else {
+    const double U = (dx * g.t1[0] + dy * g.t1[1] + dz * g.t1[2]) * g.inv_h;
+    const double V = (dx * g.t2[0] + dy * g.t2[1] + dz * g.t2[2]) * g.inv_h;
+    const double gU = pb[1] + 2.0 * U * pb[3] + V * pb[5];
+    const double gV = pb[2] + 2.0 * V * pb[4] + U * pb[5];
+    for (int c = 0; c < 3; ++c) out[c] = (gU * g.t1[c] + gV * g.t2[c]) * g.inv_h;
+  }
+}
+
+// support weight w(q) = (e^{-a q^2} - e^{-a}) / (1 - e^{-a}), q^2 = d2 / r^2.
+// FASTW evaluates the exponential in FP32 (same formula in every pass).
+template <bool FASTW>
+__device__ inline double support_weight(double d2, double r, const WeightFn &wf) {
+  const double q2 = d2 / (r * r);
+  if constexpr (FASTW) {
+    // e^x = 2^k 2^f with t = x log2(e) split in FP64 (k integer, |f| <= 1/2),
+    // so only 2^f is evaluated in FP32 (hardware exp2, ~1 ulp): relative
+    // error ~1e-7 independent of the size of x.
+    const double t = -wf.alpha * q2 * 1.4426950408889634;
+    const double k = rint(t);
+    const float e = __builtin_amdgcn_exp2f((float)(t - k));
+    return (ldexp((double)e, (int)k) - wf.ea) * wf.inv_den;
+  } else {
+    return (exp(-wf.alpha * q2) - wf.ea) * wf.inv_den;
+  }
+}
+// dw/dd = -2 a e^{-a q^2} / (1 - e^{-a}) * d / r^2 ; returns the scalar factor
+__device__ inline double support_weight_dfac(double d2, double r, const WeightFn &wf) {
+  const double q2 = d2 / (r * r);
+  return -2.0 * wf.alpha * exp(-wf.alpha * q2) * wf.inv_den / (r * r);
+}
+
+template <int M>
+__device__ inline void gram_add(double G[npack(M)], const double phi[M], double w) {
+  double wp[M];
+#pragma unroll
+  for (int a = 0; a < M; ++a) wp[a] = w * phi[a];
+#pragma unroll
+  for (int a = 0; a < M; ++a)
+#pragma unroll
+    for (int c = a; c < M; ++c) G[pidx(a, c, M)] += wp[a] * phi[c];
+}
+
+template <int M>
+__device__ inline double gram_norm1(const double G[npack(M)]) {
+  double best = 0.0;
+#pragma unroll
+  for (int c = 0; c < M; ++c) {
+    double s = 0.0;
+#pragma unroll
+    for (int r = 0; r < M; ++r) s += fabs(G[r <= c ? pidx(r, c, M) : pidx(c, r, M)]);
+    best = fmax(best, s);
+  }
+  return best;
+}
+
+// In-place LDL^T of a packed SPD matrix: afterwards G[pidx(t, r)] (t < r)
+// holds L[r][t] and dinv[k] = 1 / D[k].  Returns false if a pivot is not
+// positive (or not finite).
+template <int M>
+__device__ inline bool ldlt(double G[npack(M)], double dinv[M]) {
+  double d[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    double s = G[pidx(k, k, M)];
+#pragma unroll
+    for (int t = 0; t < k; ++t) s -= G[pidx(t, k, M)] * G[pidx(t, k, M)] * d[t];
+    d[k] = s;
+    if (!(s > 0.0) || !isfinite(s)) return false;
+    const double inv = 1.0 / s;
+    dinv[k] = inv;
+#pragma unroll
+    for (int r = k + 1; r < M; ++r) {
+      double v = G[pidx(k, r, M)];
+#pragma unroll
+      for (int t = 0; t < k; ++t) v -= G[pidx(t, r, M)] * G[pidx(t, k, M)] * d[t];
+      G[pidx(k, r, M)] = v * inv;
+    }
+  }
+  return true;
+}
+
+template <int M>
+__device__ inline void ldlt_solve(const double G[npack(M)], const double dinv[M], double x[M]) {
+#pragma unroll
+  for (int r = 1; r < M; ++r)
+#pragma unroll
+    for (int t = 0; t < r; ++t) x[r] -= G[pidx(t, r, M)] * x[t];
+#pragma unroll
+  for (int r = 0; r < M; ++r) x[r] *= dinv[r];
+#pragma unroll
+  for (int r = M - 2; r >= 0; --r)
+#pragma unroll
+    for (int t = r + 1; t < M; ++t) x[r] -= G[pidx(r, t, M)] * x[t];
+}
+
+// targets of the stencils as combinations of columns of G^{-1}:
+// 3D: d/dX -> col 1, d/dY -> col 2, d/dZ -> col 3, Laplacian -> 2 (col 4 + 5 + 6)
+// film: d/dU -> col 1, d/dV -> col 2, surface Laplacian -> 2 (col 3 + 4)
+template <int M>
+__device__ inline double target_coef(int s, int c) {
+  if constexpr (M == 10) {
+    if (s < 3) return (c == s + 1) ? 1.0 : 0.0;
+    return (c >= 4 && c <= 6) ? 2.0 : 0.0;
+  } else {
+    if (s < 2) return (c == s + 1) ? 1.0 : 0.0;
+    if (s == 2) return 0.0;
+    return (c == 3 || c == 4) ? 2.0 : 0.0;
+  }
+}
+
+template <typename T>
+__device__ inline T team_sum(T v, int width) {
+  for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, width);
+  return v;
+}
+__device__ inline double team_max(double v, int width) {
+  for (int o = width >> 1; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, width));
+  return v;
+}
+
+// Solve the team's Gram system: factor, estimate the 1-norm condition number
+// exactly from the columns of G^{-1} (spread over the T lanes of the team),
+// and return lam[s][:] = G^{-1} d_s for the four targets on every lane.
+// All lanes of a team hold identical G on entry (butterfly sums are
+// symmetric), so every decision below is uniform across the team.
+template <int M, int T>
+__device__ inline bool team_solve(double G[npack(M)], int lane, double lam[4][M], double *kappa) {
+  const double gn = gram_norm1<M>(G);
+  double dinv[M];
+  if (!ldlt<M>(G, dinv)) {
+    *kappa = INFINITY;
+    return false;
+  }
+  if constexpr (T == 1) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int r = 0; r < M; ++r) lam[s][r] = 0.0;
+    // one lane: columns one at a time, folded into kappa and the targets
+    double colmax = 0.0;
+    for (int c = 0; c < M; ++c) {
+      double x[M];
+#pragma unroll
+      for (int r = 0; r < M; ++r) x[r] = (r == c) ? 1.0 : 0.0;
+      ldlt_solve<M>(G, dinv, x);
+      double sacc = 0.0;
+#pragma unroll
+      for (int r = 0; r < M; ++r) sacc += fabs(x[r]);
+      colmax = fmax(colmax, sacc);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const double cf = target_coef<M>(s, c);
+        if (cf != 0.0) {
+#pragma unroll
+          for (int r = 0; r < M; ++r) lam[s][r] += cf * x[r];
+        }
+      }
+    }
+    *kappa = gn * colmax;
+  } else {
+    constexpr int NC = (M + T - 1) / T;
+    double cols[NC][M];
+    double colmax = 0.0;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const int c = lane + q * T;
+#pragma unroll
+      for (int r = 0; r < M; ++r) cols[q][r] = (r == c) ? 1.0 : 0.0;
+      if (c < M) {
+        ldlt_solve<M>(G, dinv, cols[q]);
+        double sacc = 0.0;
+#pragma unroll
+        for (int r = 0; r < M; ++r) sacc += fabs(cols[q][r]);
+        colmax = fmax(colmax, sacc);
+      }
+    }
+    colmax = team_max(colmax, T);
+    *kappa = gn * colmax;
+    // G and its factors are dead here; assemble the targets from the columns
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int r = 0; r < M; ++r) lam[s][r] = 0.0;
+#pragma unroll
+    for (int c = 1; c < M; ++c) {
+      bool used = false;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) used |= target_coef<M>(s, c) != 0.0;
+      if (!used) continue;
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        const double v = __shfl(cols[c / T][r], c % T, T);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const double cf = target_coef<M>(s, c);
+          if (cf != 0.0) lam[s][r] += cf * v;
+        }
+      }
+    }
+  }
+  return isfinite(*kappa);
+}
+
+}  // namespace gfdm_dev

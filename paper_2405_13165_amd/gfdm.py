@@ -1,0 +1,449 @@
+"""Python binding of libgfdm (ctypes).  Argument marshalling only: every
+step runs in the HIP kernels of the library.  Tensors must live on the
+context's device; calls enqueue on torch's current stream.
+
+The names follow the C ABI in include/gfdm.h (gf_build_neighbours ->
+build_neighbours, ...).  If the library is missing this module raises on
+import of the library: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgfdm.so")
+
+GF_OK, GF_EINVAL, GF_ENOMEM, GF_EHIP, GF_ECAPACITY, GF_ENOTCONV, GF_EBREAKDOWN = 0, -1, -2, -3, -4, -5, -6
+GF_F64, GF_F32 = 0, 1
+GF_PLAIN_F64, GF_BATCHED = 0, 1
+OP_DX, OP_DY, OP_DZ, OP_LAP = 1, 2, 4, 8
+ROW_INTERIOR, ROW_DIRICHLET, ROW_NEUMANN_COMBINED, ROW_NEUMANN = 0, 1, 2, 3
+
+_STATUS_NAMES = {0: "GF_OK", -1: "GF_EINVAL", -2: "GF_ENOMEM", -3: "GF_EHIP", -4: "GF_ECAPACITY",
+                 -5: "GF_ENOTCONV", -6: "GF_EBREAKDOWN"}
+
+
+class GfdmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Particles(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("z", ctypes.c_void_p), ("h", ctypes.c_void_p), ("model", ctypes.c_void_p),
+                ("kind", ctypes.c_void_p), ("nx", ctypes.c_void_p), ("ny", ctypes.c_void_p),
+                ("nz", ctypes.c_void_p)]
+
+
+class PcaParams(ctypes.Structure):
+    _fields_ = [("eps_lambda_max", ctypes.c_double), ("theta_star", ctypes.c_double),
+                ("literal_rule", ctypes.c_int)]
+
+
+class LsParams(ctypes.Structure):
+    _fields_ = [("alpha_w", ctypes.c_double), ("kappa_max", ctypes.c_double)]
+
+
+class LsStats(ctypes.Structure):
+    _fields_ = [("n_ok", ctypes.c_int64), ("n_fallback", ctypes.c_int64),
+                ("n_rank_deficient", ctypes.c_int64), ("n_too_few", ctypes.c_int64),
+                ("kappa_max_seen", ctypes.c_double)]
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("maxit", ctypes.c_int), ("mixed", ctypes.c_int),
+                ("inner_rtol", ctypes.c_double), ("inner_maxit", ctypes.c_int),
+                ("zeta", ctypes.c_double), ("check_every", ctypes.c_int)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("outer_its", ctypes.c_int), ("inner_its_total", ctypes.c_int),
+                ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
+                ("final_rel_res", ctypes.c_double)]
+
+
+EXPORTED = [
+    "gf_version", "gf_create", "gf_set_stream", "gf_destroy", "gf_last_error",
+    "gf_build_neighbours", "gf_nbr_info", "gf_nbr_export", "gf_nbr_free",
+    "gf_pca_params_default", "gf_classify_pca", "gf_ls_params_default", "gf_gfdm_weights",
+    "gf_apply_stencil", "gf_gfdm_weights_apply", "gf_poisson_assemble", "gf_solve_params_default",
+    "gf_poisson_solve", "gf_transition_3d_to_2d", "gf_apply_stencil_adjoint",
+    "gf_gfdm_weights_adjoint", "gf_profile_enable", "gf_profile_read",
+]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libgfdm.so and declare its signatures.  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run paper_2405_13165_amd/build.py "
+                           "(or __graft_entry__.build())")
+    L = ctypes.CDLL(path)
+    P, I64, I32, U, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_uint, ctypes.c_double
+    PP = ctypes.POINTER(_Particles)
+    L.gf_version.restype = ctypes.c_char_p
+    L.gf_create.argtypes = [I32, P, ctypes.POINTER(P)]
+    L.gf_set_stream.argtypes = [P, P]
+    L.gf_destroy.argtypes = [P]
+    L.gf_destroy.restype = None
+    L.gf_last_error.argtypes = [P]
+    L.gf_last_error.restype = ctypes.c_char_p
+    L.gf_build_neighbours.argtypes = [P, PP, I32, ctypes.POINTER(P)]
+    L.gf_nbr_info.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_int32)]
+    L.gf_nbr_export.argtypes = [P, P, P, P]
+    L.gf_nbr_free.argtypes = [P]
+    L.gf_nbr_free.restype = None
+    L.gf_pca_params_default.argtypes = [ctypes.POINTER(PcaParams)]
+    L.gf_pca_params_default.restype = None
+    L.gf_classify_pca.argtypes = [P, PP, P, P, P, P, P, P, ctypes.POINTER(PcaParams), P, P, P, P]
+    L.gf_ls_params_default.argtypes = [ctypes.POINTER(LsParams)]
+    L.gf_ls_params_default.restype = None
+    L.gf_gfdm_weights.argtypes = [P, PP, P, I32, ctypes.POINTER(LsParams), I32, P, P, P,
+                                  ctypes.POINTER(LsStats)]
+    L.gf_apply_stencil.argtypes = [P, P, I32, P, U, I32, P, P]
+    L.gf_gfdm_weights_apply.argtypes = [P, PP, P, ctypes.POINTER(LsParams), I32, P, U, P, P, P]
+    L.gf_poisson_assemble.argtypes = [P, PP, P, P, P, D, P]
+    L.gf_solve_params_default.argtypes = [ctypes.POINTER(SolveParams)]
+    L.gf_solve_params_default.restype = None
+    L.gf_poisson_solve.argtypes = [P, PP, P, P, P, P, P, ctypes.POINTER(SolveParams),
+                                   ctypes.POINTER(SolveStats)]
+    L.gf_transition_3d_to_2d.argtypes = [P, PP, P] + [P] * 11
+    L.gf_apply_stencil_adjoint.argtypes = [P, P, I32, P, U, P, P]
+    L.gf_gfdm_weights_adjoint.argtypes = [P, PP, P, ctypes.POINTER(LsParams), U, P, P, P]
+    L.gf_profile_enable.argtypes = [P, I32]
+    L.gf_profile_read.argtypes = [P, ctypes.c_char_p, ctypes.c_size_t]
+    for name in EXPORTED:
+        getattr(L, name)  # every declared entry point must resolve
+    _lib = L
+    return L
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_tensor(t, dtype, device):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(t)
+    return t.to(device=device, dtype=dtype).contiguous()
+
+
+class Context:
+    """A library context on one device, enqueuing on torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load_library()
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        st = self.lib.gf_create(device, None, ctypes.byref(h))
+        if st != GF_OK:
+            raise GfdmError(st, "gf_create failed")
+        self.handle = h
+
+    def _sync_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        self.lib.gf_set_stream(self.handle, ctypes.c_void_p(s))
+
+    def check(self, st):
+        if st != GF_OK:
+            raise GfdmError(st, self.lib.gf_last_error(self.handle).decode())
+
+    def profile(self, on: bool = True):
+        """Bracket every library kernel with HIP events (gf_profile_enable)."""
+        self.check(self.lib.gf_profile_enable(self.handle, int(on)))
+
+    def profile_read(self):
+        """{kernel name: (launches, total ms)} since the last read; synchronises."""
+        buf = ctypes.create_string_buffer(1 << 16)
+        self.check(self.lib.gf_profile_read(self.handle, buf, len(buf)))
+        out = {}
+        for line in buf.value.decode().splitlines():
+            name, cnt, ms = line.split()
+            out[name] = (int(cnt), float(ms))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.gf_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Particles:
+    """Device copies of a particle cloud (structure of arrays)."""
+
+    def __init__(self, ctx: Context, x, y, z, h, model, kind=None, nx=None, ny=None, nz=None):
+        dev = ctx.device
+        self.x = _dev_tensor(x, torch.float64, dev)
+        self.y = _dev_tensor(y, torch.float64, dev)
+        self.z = _dev_tensor(z, torch.float64, dev)
+        self.h = _dev_tensor(h, torch.float64, dev)
+        self.model = _dev_tensor(model, torch.int8, dev)
+        self.kind = _dev_tensor(kind, torch.int8, dev)
+        self.nx = _dev_tensor(nx, torch.float64, dev)
+        self.ny = _dev_tensor(ny, torch.float64, dev)
+        self.nz = _dev_tensor(nz, torch.float64, dev)
+        self.n = int(self.x.shape[0])
+        self.refresh()
+
+    @classmethod
+    def from_dict(cls, ctx, d):
+        return cls(ctx, d["x"], d["y"], d["z"], d["h"], d["model"], d.get("kind"), d.get("nx"),
+                   d.get("ny"), d.get("nz"))
+
+    def refresh(self):
+        self.s = _Particles(self.n, _ptr(self.x), _ptr(self.y), _ptr(self.z), _ptr(self.h),
+                            _ptr(self.model), _ptr(self.kind), _ptr(self.nx), _ptr(self.ny),
+                            _ptr(self.nz))
+        return self
+
+    def with_positions(self, x, y, z):
+        q = object.__new__(Particles)
+        q.__dict__.update(self.__dict__)
+        q.x, q.y, q.z = x.contiguous(), y.contiguous(), z.contiguous()
+        return q.refresh()
+
+
+class Neighbours:
+    def __init__(self, ctx: Context, handle):
+        self.ctx = ctx
+        self.handle = handle
+        n, nnz, mr = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        ctx.check(ctx.lib.gf_nbr_info(handle, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(mr)))
+        self.n, self.nnz, self.max_row = n.value, nnz.value, mr.value
+
+    def export(self):
+        """(row_ptr int64 [n+1], col int32 [nnz]) device tensors."""
+        row_ptr = torch.empty(self.n + 1, dtype=torch.int64, device=self.ctx.device)
+        col = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=self.ctx.device)[: self.nnz]
+        self.ctx._sync_stream()
+        self.ctx.check(self.ctx.lib.gf_nbr_export(self.ctx.handle, self.handle, _ptr(row_ptr),
+                                                  _ptr(col) if self.nnz else None))
+        return row_ptr, col
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.ctx.lib.gf_nbr_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_neighbours(ctx: Context, p: Particles, cross_model: bool = False) -> Neighbours:
+    h = ctypes.c_void_p()
+    ctx._sync_stream()
+    ctx.check(ctx.lib.gf_build_neighbours(ctx.handle, ctypes.byref(p.s), int(cross_model), ctypes.byref(h)))
+    return Neighbours(ctx, h)
+
+
+def pca_params(eps_lambda_max=0.15, theta_star=None, literal_rule=False):
+    prm = PcaParams()
+    load_library().gf_pca_params_default(ctypes.byref(prm))
+    prm.eps_lambda_max = eps_lambda_max
+    if theta_star is not None:
+        prm.theta_star = theta_star
+    prm.literal_rule = int(literal_rule)
+    return prm
+
+
+def classify_pca(ctx, p, same, cross=None, film_height=None, h3d=None, prev=None, user=None,
+                 params=None, want_flags=True):
+    """Returns (lam [n,3], w3 [n,3], eps [n], flag [n] uint8 or None)."""
+    dev = ctx.device
+    lam = torch.empty((p.n, 3), dtype=torch.float64, device=dev)
+    w3 = torch.empty((p.n, 3), dtype=torch.float64, device=dev)
+    eps = torch.empty(p.n, dtype=torch.float64, device=dev)
+    flag = torch.empty(p.n, dtype=torch.uint8, device=dev) if want_flags else None
+    fh = _dev_tensor(film_height, torch.float64, dev)
+    h3 = _dev_tensor(h3d, torch.float64, dev)
+    pv = _dev_tensor(prev, torch.uint8, dev)
+    us = _dev_tensor(user, torch.uint8, dev)
+    prm = params if params is not None else pca_params()
+    ctx._sync_stream()
+    ctx.check(ctx.lib.gf_classify_pca(ctx.handle, ctypes.byref(p.s), same.handle,
+                                      cross.handle if cross is not None else None, _ptr(fh), _ptr(h3),
+                                      _ptr(pv), _ptr(us), ctypes.byref(prm), _ptr(lam), _ptr(w3),
+                                      _ptr(eps), _ptr(flag)))
+    return lam, w3, eps, flag
+
+
+def ls_params(alpha_w=8.0, kappa_max=None):
+    prm = LsParams()
+    load_library().gf_ls_params_default(ctypes.byref(prm))
+    prm.alpha_w = alpha_w
+    if kappa_max is not None:
+        prm.kappa_max = kappa_max
+    return prm
+
+
+def gfdm_weights(ctx, p, nbr, prec=GF_BATCHED, wtype=GF_F32, params=None, out=None,
+                 status=None, kappa=None, stats=False):
+    """Stencil weights [nnz, 4] (dx, dy, dz, Laplacian) of dtype wtype."""
+    dt = torch.float32 if wtype == GF_F32 else torch.float64
+    w = out if out is not None else torch.empty((max(nbr.nnz, 1), 4), dtype=dt, device=ctx.device)[: nbr.nnz]
+    prm = params if params is not None else ls_params()
+    st = LsStats() if stats else None
+    ctx._sync_stream()
+    ctx.check(ctx.lib.gf_gfdm_weights(ctx.handle, ctypes.byref(p.s), nbr.handle, prec, ctypes.byref(prm),
+                                      wtype, _ptr(w), _ptr(status), _ptr(kappa),
+                                      ctypes.byref(st) if st is not None else None))
+    if stats:
+        return w, {k: getattr(st, k) for k, _ in LsStats._fields_}
+    return w
+
+
+def _nops(mask):
+    return bin(mask & 0xF).count("1")
+
+
+def apply_stencil(ctx, nbr, w, u, op_mask=0xF, out=None):
+    wtype = GF_F32 if w.dtype == torch.float32 else GF_F64
+    io = GF_F32 if u.dtype == torch.float32 else GF_F64
+    o = out if out is not None else torch.empty((_nops(op_mask), nbr.n), dtype=u.dtype, device=ctx.device)
+    ctx._sync_stream()
+    ctx.check(ctx.lib.gf_apply_stencil(ctx.handle, nbr.handle, wtype, _ptr(w), op_mask, io, _ptr(u), _ptr(o)))
+    return o
+
+
+def gfdm_weights_apply(ctx, p, nbr, u, op_mask=0xF, wtype=GF_F32, params=None, store_weights=True,
+                       status=None, w_out=None, out=None):
+    dt = torch.float32 if wtype == GF_F32 else torch.float64
+    w = None
+    if store_weights:
+        w = w_out if w_out is not None else torch.empty((max(nbr.nnz, 1), 4), dtype=dt, device=ctx.device)[: nbr.nnz]
+    o = out if out is not None else torch.empty((_nops(op_mask), p.n), dtype=torch.float64, device=ctx.device)
+    prm = params if params is not None else ls_params()
+    ctx._sync_stream()
+    ctx.check(ctx.lib.gf_gfdm_weights_apply(ctx.handle, ctypes.byref(p.s), nbr.handle, ctypes.byref(prm), wtype,
+                                            _ptr(w), op_mask, _ptr(u), _ptr(o), _ptr(status)))
+    return w, o
+
+
+def poisson_assemble(ctx, p, nbr, w64, row_type, zeta=0.3):
+    val = torch.empty(max(nbr.nnz, 1), dtype=torch.float64, device=ctx.device)[: nbr.nnz]
+    rt = _dev_tensor(row_type, torch.int8, ctx.device)
+    ctx._sync_stream()
+    ctx.check(ctx.lib.gf_poisson_assemble(ctx.handle, ctypes.byref(p.s), nbr.handle, _ptr(w64), _ptr(rt), zeta,
+                                          _ptr(val)))
+    return val
+
+
+def solve_params(**kw):
+    prm = SolveParams()
+    load_library().gf_solve_params_default(ctypes.byref(prm))
+    for k, v in kw.items():
+        setattr(prm, k, v)
+    return prm
+
+
+def poisson_solve(ctx, p, nbr, w64, row_type, rhs, x0=None, params=None, raise_on_fail=True):
+    """Returns (solution, stats dict)."""
+    rt = _dev_tensor(row_type, torch.int8, ctx.device)
+    x = torch.zeros(p.n, dtype=torch.float64, device=ctx.device) if x0 is None else x0.clone()
+    prm = params if params is not None else solve_params()
+    st = SolveStats()
+    ctx._sync_stream()
+    status = ctx.lib.gf_poisson_solve(ctx.handle, ctypes.byref(p.s), nbr.handle, _ptr(w64), _ptr(rt), _ptr(rhs),
+                                      _ptr(x), ctypes.byref(prm), ctypes.byref(st))
+    stats = {k: getattr(st, k) for k, _ in SolveStats._fields_}
+    stats["status"] = status
+    if raise_on_fail:
+        ctx.check(status)
+    return x, stats
+
+
+def transition_3d_to_2d(ctx, p, nbr, flag, mass, rho, phi):
+    dev = ctx.device
+    f64 = lambda: torch.empty(p.n, dtype=torch.float64, device=dev)
+    out = {k: f64() for k in ("mass", "rho", "phi", "height", "diam")}
+    out["keep"] = torch.empty(p.n, dtype=torch.uint8, device=dev)
+    out["owner"] = torch.empty(p.n, dtype=torch.int32, device=dev)
+    fl = _dev_tensor(flag, torch.uint8, dev)
+    m = _dev_tensor(mass, torch.float64, dev)
+    r = _dev_tensor(rho, torch.float64, dev)
+    ph = _dev_tensor(phi, torch.float64, dev)
+    ctx._sync_stream()
+    ctx.check(ctx.lib.gf_transition_3d_to_2d(ctx.handle, ctypes.byref(p.s), nbr.handle, _ptr(fl), _ptr(m), _ptr(r),
+                                             _ptr(ph), _ptr(out["mass"]), _ptr(out["rho"]), _ptr(out["phi"]),
+                                             _ptr(out["height"]), _ptr(out["diam"]), _ptr(out["keep"]),
+                                             _ptr(out["owner"])))
+    return out
+
+
+def apply_stencil_adjoint(ctx, nbr, w, ybar, op_mask=0xF):
+    wtype = GF_F32 if w.dtype == torch.float32 else GF_F64
+    ub = torch.empty(nbr.n, dtype=torch.float64, device=ctx.device)
+    yb = ybar.to(torch.float64).contiguous()
+    ctx._sync_stream()
+    ctx.check(ctx.lib.gf_apply_stencil_adjoint(ctx.handle, nbr.handle, wtype, _ptr(w), op_mask, _ptr(yb), _ptr(ub)))
+    return ub
+
+
+def gfdm_weights_adjoint(ctx, p, nbr, u, ybar, op_mask=0xF, params=None, xbar=None):
+    """Accumulates dL/dx into xbar [n, 3] (created as zeros if None) and returns it."""
+    xb = torch.zeros((p.n, 3), dtype=torch.float64, device=ctx.device) if xbar is None else xbar
+    prm = params if params is not None else ls_params()
+    uu = u.to(torch.float64).contiguous()
+    yb = ybar.to(torch.float64).contiguous()
+    ctx._sync_stream()
+    ctx.check(ctx.lib.gf_gfdm_weights_adjoint(ctx.handle, ctypes.byref(p.s), nbr.handle, ctypes.byref(prm), op_mask,
+                                              _ptr(uu), _ptr(yb), _ptr(xb)))
+    return xb
+
+
+class StencilOp(torch.autograd.Function):
+    """out = apply(weights(x, y, z), u) with the hand-written adjoints.
+
+    forward(u, x, y, z, ctx_, p, nbr, op_mask, wtype) -> out [K, n] FP64.
+    Gradients flow to u (transpose application) and to the positions
+    (adjoint through the local least-squares problems, weights recomputed).
+    The neighbour sets are held fixed (they change only on a set of measure
+    zero, where the support weight vanishes continuously)."""
+
+    @staticmethod
+    def forward(fctx, u, x, y, z, lib_ctx, p, nbr, op_mask, wtype):
+        q = p.with_positions(x.detach().to(torch.float64), y.detach().to(torch.float64),
+                             z.detach().to(torch.float64))
+        w = gfdm_weights(lib_ctx, q, nbr, GF_BATCHED, wtype)
+        uu = u.detach().to(torch.float64).contiguous()
+        out = apply_stencil(lib_ctx, nbr, w, uu, op_mask)
+        fctx.save_for_backward(uu, x, y, z)
+        fctx.extra = (lib_ctx, p, nbr, op_mask, w)
+        return out
+
+    @staticmethod
+    def backward(fctx, gout):
+        uu, x, y, z = fctx.saved_tensors
+        lib_ctx, p, nbr, op_mask, w = fctx.extra
+        gout = gout.contiguous().to(torch.float64)
+        gu = apply_stencil_adjoint(lib_ctx, nbr, w, gout, op_mask) if fctx.needs_input_grad[0] else None
+        gx = gy = gz = None
+        if any(fctx.needs_input_grad[1:4]):
+            q = p.with_positions(x.detach().to(torch.float64), y.detach().to(torch.float64),
+                                 z.detach().to(torch.float64))
+            xb = gfdm_weights_adjoint(lib_ctx, q, nbr, uu, gout, op_mask)
+            gx, gy, gz = xb[:, 0].contiguous(), xb[:, 1].contiguous(), xb[:, 2].contiguous()
+        return gu, gx, gy, gz, None, None, None, None, None
+
+
+def stencil_op(lib_ctx, p, nbr, u, x, y, z, op_mask=OP_LAP, wtype=GF_F32):
+    return StencilOp.apply(u, x, y, z, lib_ctx, p, nbr, op_mask, wtype)
