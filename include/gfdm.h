@@ -190,6 +190,15 @@ gf_status gf_gfdm_weights(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr,
 gf_status gf_apply_stencil(gf_ctx *ctx, const gf_nbr *nbr, gf_dtype wtype, const void *w,
                            unsigned op_mask, gf_dtype io, const void *u, void *out);
 
+/* Autotuner for the batched kernels.  For every (model, neighbour-count band)
+ * group of nbr, times the stencil kernel (weights of type wtype) and the
+ * application kernel with teams of 4, 8 and 16 lanes per particle (median of
+ * three runs each) and keeps the fastest team size in ctx; later calls on ctx
+ * use it.  Allocates temporary buffers and synchronises.  team_out (host,
+ * may be NULL) receives 16 ints: the chosen stencil team sizes of the groups
+ * (bulk bands 0-3, film bands 0-3), then those of the application kernel. */
+gf_status gf_autotune(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr, gf_dtype wtype, int *team_out);
+
 /* Weights and application in one pass: computes the stencils exactly as
  * gf_gfdm_weights (GF_BATCHED) and, while they are in registers, applies them
  * to u (FP64) -> out [K][n] FP64 as gf_apply_stencil does.  w_out may be NULL

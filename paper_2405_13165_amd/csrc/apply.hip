@@ -4,6 +4,8 @@
 // instruction reads T consecutive 16-byte (FP32) or 32-byte (FP64) weight
 // records; partial sums are combined by a butterfly over the team and
 // accumulated in FP64.
+#include <algorithm>
+
 #include "stencil_common.h"
 
 using namespace gfdm_dev;
@@ -34,7 +36,7 @@ __global__ void __launch_bounds__(kBlock) k_apply(const int32_t *__restrict__ sc
                                                   const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
                                                   const void *__restrict__ w, unsigned mask,
                                                   const IOT *__restrict__ u, IOT *__restrict__ out, int64_t n) {
-  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gt = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int64_t team = gt / T;
   const int lane = (int)(gt % T);
   if (team >= nrows) return;
@@ -91,17 +93,14 @@ __global__ void __launch_bounds__(kBlock) k_apply_adjoint(const int64_t *__restr
   ubar[j] = acc;
 }
 
-int apply_team(int band) {
-  static const int t[GF_NBAND] = {4, 8, 8, 16};
-  return t[band];
-}
-
 template <typename WT, typename IOT>
-gf_status launch_apply(gf_ctx *ctx, const gf_nbr *nbr, const void *w, unsigned mask, const void *u, void *out) {
+gf_status launch_apply(gf_ctx *ctx, const gf_nbr *nbr, const void *w, unsigned mask, const void *u, void *out,
+                       int only_group = -1, int team_override = 0) {
   for (int gsel = 0; gsel < 2 * GF_NBAND; ++gsel) {
+    if (only_group >= 0 && gsel != only_group) continue;
     const int64_t s0 = nbr->group_start[gsel], s1 = nbr->group_start[gsel + 1];
     if (s1 <= s0) continue;
-    const int T = apply_team(gsel % GF_NBAND);
+    const int T = team_override > 0 ? team_override : ctx->ateam[gsel / GF_NBAND][gsel % GF_NBAND];
     const dim3 grid(grid_for((s1 - s0) * T, kBlock)), block(kBlock);
     const int32_t *sched = nbr->grouped + s0;
     const IOT *uu = (const IOT *)u;
@@ -110,13 +109,59 @@ gf_status launch_apply(gf_ctx *ctx, const gf_nbr *nbr, const void *w, unsigned m
     switch (T) {
       case 4: hipLaunchKernelGGL((k_apply<4, WT, IOT>), grid, block, 0, ctx->stream, sched, s1 - s0, nbr->row_ptr, nbr->col, w, mask, uu, oo, nbr->n); break;
       case 8: hipLaunchKernelGGL((k_apply<8, WT, IOT>), grid, block, 0, ctx->stream, sched, s1 - s0, nbr->row_ptr, nbr->col, w, mask, uu, oo, nbr->n); break;
-      default: hipLaunchKernelGGL((k_apply<16, WT, IOT>), grid, block, 0, ctx->stream, sched, s1 - s0, nbr->row_ptr, nbr->col, w, mask, uu, oo, nbr->n); break;
+      case 16: hipLaunchKernelGGL((k_apply<16, WT, IOT>), grid, block, 0, ctx->stream, sched, s1 - s0, nbr->row_ptr, nbr->col, w, mask, uu, oo, nbr->n); break;
+      case 32: hipLaunchKernelGGL((k_apply<32, WT, IOT>), grid, block, 0, ctx->stream, sched, s1 - s0, nbr->row_ptr, nbr->col, w, mask, uu, oo, nbr->n); break;
+      default: hipLaunchKernelGGL((k_apply<64, WT, IOT>), grid, block, 0, ctx->stream, sched, s1 - s0, nbr->row_ptr, nbr->col, w, mask, uu, oo, nbr->n); break;
     }
     GF_LAUNCH_CHECK(ctx);
   }
   return GF_OK;
 }
 }  // namespace
+
+// Team-size search for the application kernel (FP64 field), per group.
+gf_status tune_apply(gf_ctx *ctx, const gf_nbr *nbr, const void *w, gf_dtype wtype) {
+  double *u = nullptr, *out = nullptr;
+  if (hipMalloc(&u, sizeof(double) * nbr->n) != hipSuccess) return set_error(ctx, GF_ENOMEM, "tuning buffer");
+  if (hipMalloc(&out, sizeof(double) * 4 * nbr->n) != hipSuccess) {
+    (void)hipFree(u);
+    return set_error(ctx, GF_ENOMEM, "tuning buffer");
+  }
+  (void)hipMemsetAsync(u, 0, sizeof(double) * nbr->n, ctx->stream);
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  const int sizes[5] = {4, 8, 16, 32, 64};
+  gf_status st = GF_OK;
+  for (int gsel = 0; gsel < 2 * GF_NBAND && !st; ++gsel) {
+    if (nbr->group_start[gsel + 1] <= nbr->group_start[gsel]) continue;
+    float best = INFINITY;
+    int bestT = ctx->ateam[gsel / GF_NBAND][gsel % GF_NBAND];
+    for (int t = 0; t < 5 && !st; ++t) {
+      float times[3];
+      for (int rep = -1; rep < 3 && !st; ++rep) {
+        if (rep >= 0) (void)hipEventRecord(e0, ctx->stream);
+        st = (wtype == GF_F32) ? launch_apply<float, double>(ctx, nbr, w, 0xF, u, out, gsel, sizes[t])
+                               : launch_apply<double, double>(ctx, nbr, w, 0xF, u, out, gsel, sizes[t]);
+        if (rep >= 0) {
+          (void)hipEventRecord(e1, ctx->stream);
+          (void)hipEventSynchronize(e1);
+          (void)hipEventElapsedTime(&times[rep], e0, e1);
+        }
+      }
+      if (st) break;
+      std::sort(times, times + 3);
+      if (times[1] < best) { best = times[1]; bestT = sizes[t]; }
+    }
+    ctx->ateam[gsel / GF_NBAND][gsel % GF_NBAND] = bestT;
+  }
+  (void)hipStreamSynchronize(ctx->stream);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(u);
+  (void)hipFree(out);
+  return st;
+}
 
 extern "C" gf_status gf_apply_stencil(gf_ctx *ctx, const gf_nbr *nbr, gf_dtype wtype, const void *w, unsigned op_mask,
                                       gf_dtype io, const void *u, void *out) {

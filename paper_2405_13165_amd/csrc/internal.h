@@ -23,6 +23,10 @@ struct gf_ctx {
   // small pinned host buffer for read-backs
   void *host_pinned = nullptr;
   size_t host_pinned_bytes = 0;
+  // team sizes (lanes per particle) of the batched stencil and application
+  // kernels per (model, neighbour-count band); set by gf_autotune
+  int wteam[2][4] = {{8, 8, 8, 16}, {8, 8, 8, 16}};
+  int ateam[2][4] = {{4, 8, 8, 16}, {4, 8, 8, 16}};
   // optional per-kernel timing with HIP events (gf_profile_enable)
   int profile = 0;
   struct ProfRec {
@@ -94,6 +98,7 @@ gf_status ensure_host(gf_ctx *ctx, size_t bytes);
 gf_status check_particles(gf_ctx *ctx, const gf_particles *p, bool need_kind, bool need_normals);
 gf_status check_nbr(gf_ctx *ctx, const gf_nbr *nbr, int64_t n);
 gf_status ensure_rev(gf_ctx *ctx, gf_nbr *nbr);
+gf_status tune_apply(gf_ctx *ctx, const gf_nbr *nbr, const void *w, gf_dtype wtype);
 
 // device-wide exclusive scans (in place allowed): out[k] = sum_{t<k} in[t],
 // out[n] = total.  tmp must hold scan_tmp_elems(n) elements of the output type.

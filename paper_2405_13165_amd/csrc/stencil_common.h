@@ -72,15 +72,14 @@ __device__ inline void monomials_grad_dot(const RowGeom &g, double dx, double dy
   }
 }
 
-// support weight w(q) = (e^{-a q^2} - e^{-a}) / (1 - e^{-a}), q^2 = d2 / r^2.
-// FASTW evaluates the exponential in FP32 (same formula in every pass).
+// support weight w(q) = (e^{-a q^2} - e^{-a}) / (1 - e^{-a}) of q^2.
+// FASTW: e^x = 2^k 2^f with t = x log2(e) split in FP64 (k integer,
+// |f| <= 1/2), so only 2^f is evaluated in FP32 (hardware exp2, ~1 ulp):
+// relative error ~1e-7 independent of the size of x.  Every pass of a kernel
+// evaluates the same expression.
 template <bool FASTW>
-__device__ inline double support_weight(double d2, double r, const WeightFn &wf) {
-  const double q2 = d2 / (r * r);
+__device__ inline double support_weight_q2(double q2, const WeightFn &wf) {
   if constexpr (FASTW) {
-    // e^x = 2^k 2^f with t = x log2(e) split in FP64 (k integer, |f| <= 1/2),
-    // so only 2^f is evaluated in FP32 (hardware exp2, ~1 ulp): relative
-    // error ~1e-7 independent of the size of x.
     const double t = -wf.alpha * q2 * 1.4426950408889634;
     const double k = rint(t);
     const float e = __builtin_amdgcn_exp2f((float)(t - k));
@@ -88,6 +87,11 @@ __device__ inline double support_weight(double d2, double r, const WeightFn &wf)
   } else {
     return (exp(-wf.alpha * q2) - wf.ea) * wf.inv_den;
   }
+}
+// the same with q^2 = d2 / r^2
+template <bool FASTW>
+__device__ inline double support_weight(double d2, double r, const WeightFn &wf) {
+  return support_weight_q2<FASTW>(d2 / (r * r), wf);
 }
 // dw/dd = -2 a e^{-a q^2} / (1 - e^{-a}) * d / r^2 ; returns the scalar factor
 __device__ inline double support_weight_dfac(double d2, double r, const WeightFn &wf) {
@@ -172,6 +176,111 @@ __device__ inline double target_coef(int s, int c) {
     if (s == 2) return 0.0;
     return (c == 3 || c == 4) ? 2.0 : 0.0;
   }
+}
+
+// ---------------------------------------------------------------- moments
+// G_rc = sum_j w_j phi_r phi_c depends only on the moments
+// sum_j w_j X^a Y^b Z^c with a+b+c <= 4 (35 in 3D, 15 on the film), so the
+// batched kernels accumulate those instead of the 55 (21) Gram entries.
+struct MomTable3 {
+  int idx[5][5][5];
+  constexpr MomTable3() : idx{} {
+    int k = 0;
+    for (int a = 0; a <= 4; ++a)
+      for (int b = 0; a + b <= 4; ++b)
+        for (int c = 0; a + b + c <= 4; ++c) idx[a][b][c] = k++;
+  }
+};
+struct MomTable2 {
+  int idx[5][5];
+  constexpr MomTable2() : idx{} {
+    int k = 0;
+    for (int a = 0; a <= 4; ++a)
+      for (int b = 0; a + b <= 4; ++b) idx[a][b] = k++;
+  }
+};
+constexpr MomTable3 kMom3{};
+constexpr MomTable2 kMom2{};
+template <int M>
+__host__ __device__ constexpr int nmom() { return M == 10 ? 35 : 15; }
+// exponents of the monomials [1 X Y Z X^2 Y^2 Z^2 XY XZ YZ] and [1 U V U^2 V^2 UV]
+constexpr int kExp3[10][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {2, 0, 0},
+                              {0, 2, 0}, {0, 0, 2}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}};
+constexpr int kExp2[6][2] = {{0, 0}, {1, 0}, {0, 1}, {2, 0}, {0, 2}, {1, 1}};
+// moment index of G_rc
+template <int M>
+__host__ __device__ constexpr int gram_moment(int r, int c) {
+  if constexpr (M == 10)
+    return kMom3.idx[kExp3[r][0] + kExp3[c][0]][kExp3[r][1] + kExp3[c][1]][kExp3[r][2] + kExp3[c][2]];
+  else
+    return kMom2.idx[kExp2[r][0] + kExp2[c][0]][kExp2[r][1] + kExp2[c][1]];
+}
+
+// scaled local coordinates (X, Y, Z) or (U, V, 0)
+template <int M>
+__device__ inline void local_xyz(const RowGeom &g, double dx, double dy, double dz, double &X, double &Y,
+                                 double &Z) {
+  if constexpr (M == 10) {
+    X = dx * g.inv_h; Y = dy * g.inv_h; Z = dz * g.inv_h;
+  } else {
+    X = (dx * g.t1[0] + dy * g.t1[1] + dz * g.t1[2]) * g.inv_h;
+    Y = (dx * g.t2[0] + dy * g.t2[1] + dz * g.t2[2]) * g.inv_h;
+    Z = 0.0;
+  }
+}
+
+template <int M>
+__device__ inline void moments_add(double mom[nmom<M>()], double w, double X, double Y, double Z) {
+  double wx[5], py[5];
+  wx[0] = w;
+#pragma unroll
+  for (int a = 1; a < 5; ++a) wx[a] = wx[a - 1] * X;
+  py[0] = 1.0;
+#pragma unroll
+  for (int b = 1; b < 5; ++b) py[b] = py[b - 1] * Y;
+  if constexpr (M == 10) {
+    double pz[5];
+    pz[0] = 1.0;
+#pragma unroll
+    for (int c = 1; c < 5; ++c) pz[c] = pz[c - 1] * Z;
+#pragma unroll
+    for (int a = 0; a <= 4; ++a)
+#pragma unroll
+      for (int b = 0; a + b <= 4; ++b) {
+        const double t = (b == 0) ? wx[a] : wx[a] * py[b];
+#pragma unroll
+        for (int c = 0; a + b + c <= 4; ++c) mom[kMom3.idx[a][b][c]] += (c == 0) ? t : t * pz[c];
+      }
+  } else {
+#pragma unroll
+    for (int a = 0; a <= 4; ++a)
+#pragma unroll
+      for (int b = 0; a + b <= 4; ++b) mom[kMom2.idx[a][b]] += (b == 0) ? wx[a] : wx[a] * py[b];
+  }
+}
+
+// monomials phi(X, Y, Z) of the basis
+template <int M>
+__device__ inline void basis(double X, double Y, double Z, double phi[M]) {
+  if constexpr (M == 10) {
+    phi[0] = 1.0; phi[1] = X; phi[2] = Y; phi[3] = Z;
+    phi[4] = X * X; phi[5] = Y * Y; phi[6] = Z * Z;
+    phi[7] = X * Y; phi[8] = X * Z; phi[9] = Y * Z;
+  } else {
+    phi[0] = 1.0; phi[1] = X; phi[2] = Y;
+    phi[3] = X * X; phi[4] = Y * Y; phi[5] = X * Y;
+  }
+}
+
+// Consecutive workgroups are dispatched round-robin over the 8 XCDs of the
+// chip, each with its own L2.  Remap so that XCD k processes the k-th
+// contiguous slice of the (Morton-ordered) work: neighbouring particles then
+// share an L2.  Bijective for any grid size.
+__device__ inline unsigned xcd_block(unsigned bid, unsigned nblocks) {
+  constexpr unsigned kXcd = 8;
+  const unsigned q = nblocks / kXcd, r = nblocks % kXcd;
+  const unsigned xcd = bid % kXcd, idx = bid / kXcd;
+  return (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
 template <typename T>

@@ -16,6 +16,8 @@
 //
 // Plain path: one work-item per particle in the caller's order, the same
 // FP64 arithmetic, FP64 output.
+#include <algorithm>
+
 #include "stencil_common.h"
 
 using namespace gfdm_dev;
@@ -27,6 +29,7 @@ constexpr int kQrStride = 15;  // per neighbour: 10 columns, 4 targets, sqrt(w)
 
 struct WArgs {
   const double *x, *y, *z, *h, *nx, *ny, *nz;
+  const double4 *pos;  // (x, y, z, h) packed per particle for the batched kernels
   const int8_t *model;
   const int64_t *row_ptr;
   const int32_t *col;
@@ -174,13 +177,241 @@ __device__ void weights_row(const WArgs &a, int32_t i, int lane) {
   if (lane == 0 && a.status) a.status[i] = 0;
 }
 
+// ------------------------------------------------------------------ batched
+// Moment-based team path.  Per particle, a team of T >= M lanes:
+//  pass 1  each lane accumulates the weighted moments sum w X^a Y^b Z^c
+//          (a+b+c <= 4) of its neighbours and caches its first KC weights;
+//  reduce  butterfly over the team; the moments are staged in LDS;
+//  invert  lane r < M assembles row r of G from the moments and the team
+//          runs an in-place Gauss-Jordan inversion, one row per lane, the
+//          pivot row broadcast through LDS (G is SPD: no pivoting);
+//          ||G||_1 ||G^-1||_1 is the condition number; the target
+//          solutions lambda_s are read off the rows of G^-1 and shared
+//          through LDS;
+//  pass 2  each lane writes c_j = w_j phi_j . lambda_s for its neighbours.
+constexpr int kCacheW = 8;
+
+template <int M>
+struct GramTable {
+  unsigned char v[M][M];
+  constexpr GramTable() : v{} {
+    for (int r = 0; r < M; ++r)
+      for (int c = 0; c < M; ++c) v[r][c] = (unsigned char)gram_moment<M>(r, c);
+  }
+};
+__constant__ GramTable<10> kGram3 = GramTable<10>();
+__constant__ GramTable<6> kGram2 = GramTable<6>();
+
+template <int M>
+constexpr int team_lds_doubles(int T) { return nmom<M>() + M + 1 + 4 * M + kCacheW * T; }
+
+// orders the LDS traffic of the lanes of one wave around a hand-off
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool FASTW>
+__device__ inline double nbr_weight_h(const WArgs &a, const RowGeom &g, double hj, double dx, double dy, double dz) {
+  const double d2 = dx * dx + dy * dy + dz * dz;
+  // equal supports (the common case) need no division: r_ij = h_i
+  const double q2 = (hj == g.hi) ? d2 * (g.inv_h * g.inv_h) : d2 / (0.25 * (g.hi + hj) * (g.hi + hj));
+  return support_weight_q2<FASTW>(q2, a.wf);
+}
+
+template <int M, int T, int OUT, bool FUSED, bool FASTW>
+__device__ void weights_row_team(const WArgs &a, int32_t i, int lane, double *sm) {
+  constexpr int NM = nmom<M>();
+  double *s_mom = sm;
+  double *s_prow = sm + NM;
+  double *s_lam = sm + NM + M + 1;
+  double *s_w = sm + NM + M + 1 + 4 * M;
+  const int64_t b = a.row_ptr[i];
+  const int n = (int)(a.row_ptr[i + 1] - b);
+  if (n < M) {
+    if (a.w_out)
+      for (int k = lane; k < n; k += T) store_w<OUT>(a.w_out, b + k, 0.0, 0.0, 0.0, 0.0);
+    if (lane == 0) {
+      if (a.status) a.status[i] = 3;
+      if (a.kappa_out) a.kappa_out[i] = 0.0f;
+      if constexpr (FUSED) {
+        const double z[4] = {0.0, 0.0, 0.0, 0.0};
+        store_fused(a, i, z);
+      }
+    }
+    return;
+  }
+  RowGeom g;
+  row_geom<M>(a, i, g);
+  // ---- pass 1: moments (the first kCacheW weights of each lane are kept in LDS)
+  double mom[NM];
+#pragma unroll
+  for (int p = 0; p < NM; ++p) mom[p] = 0.0;
+#pragma unroll 2
+  for (int k = lane; k < n; k += T) {
+    const int32_t j = a.col[b + k];
+    const double4 pj = a.pos[j];
+    const double dx = pj.x - g.xi, dy = pj.y - g.yi, dz = pj.z - g.zi;
+    const double w = nbr_weight_h<FASTW>(a, g, pj.w, dx, dy, dz);
+    if (k < kCacheW * T) s_w[k] = w;
+    double X, Y, Z;
+    local_xyz<M>(g, dx, dy, dz, X, Y, Z);
+    moments_add<M>(mom, w, X, Y, Z);
+  }
+#pragma unroll
+  for (int p = 0; p < NM; ++p) mom[p] = team_sum(mom[p], T);
+#pragma unroll
+  for (int p = 0; p < NM; ++p)
+    if (p % T == lane) s_mom[p] = mom[p];
+  wave_sync();
+  // ---- Gauss-Jordan inversion of G; lane owns rows lane + q T (q < NR)
+  constexpr int NR = (M + T - 1) / T;
+  double row[NR][M];
+  double gsum = 0.0;
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    const int r = lane + q * T;
+    const bool own = r < M;
+    double sacc = 0.0;
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      const int mi = own ? (M == 10 ? kGram3.v[r][c] : kGram2.v[r][c]) : 0;
+      row[q][c] = own ? s_mom[mi] : 0.0;
+      sacc += fabs(row[q][c]);
+    }
+    gsum = fmax(gsum, sacc);
+  }
+  bool okp = true;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const int kq = k / T;
+    if (lane == k % T) {
+      const double piv = row[kq][k];
+      const double ip = 1.0 / piv;
+      row[kq][k] = 1.0;
+#pragma unroll
+      for (int c = 0; c < M; ++c) row[kq][c] *= ip;
+#pragma unroll
+      for (int c = 0; c < M; ++c) s_prow[c] = row[kq][c];
+      s_prow[M] = piv;
+    }
+    wave_sync();
+    double pr[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) pr[c] = s_prow[c];
+    const double piv = s_prow[M];
+    okp = okp && (piv > 0.0) && isfinite(piv);
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const int r = lane + q * T;
+      if (r < M && r != k) {
+        const double f = row[q][k];
+        row[q][k] = 0.0;
+#pragma unroll
+        for (int c = 0; c < M; ++c) row[q][c] -= f * pr[c];
+      }
+    }
+    wave_sync();
+  }
+  double isum = 0.0;
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    double sacc = 0.0;
+#pragma unroll
+    for (int c = 0; c < M; ++c) sacc += fabs(row[q][c]);
+    isum = fmax(isum, (lane + q * T < M) ? sacc : 0.0);
+  }
+  const double gnorm = team_max(gsum, T);
+  const double inorm = team_max(isum, T);
+  const double kappa = gnorm * inorm;
+  // lambda_s[r] from row r of G^{-1} (= column r)
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    const int r = lane + q * T;
+    if (r < M) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        double v = 0.0;
+#pragma unroll
+        for (int c = 1; c < M; ++c) {
+          const double cf = target_coef<M>(s, c);
+          if (cf != 0.0) v += cf * row[q][c];
+        }
+        // physical scaling: first derivatives / h, Laplacian / h^2
+        s_lam[s * M + r] = v * (s == 3 ? g.inv_h * g.inv_h : g.inv_h);
+      }
+    }
+  }
+  wave_sync();
+  if (lane == 0 && a.kappa_out) a.kappa_out[i] = (float)kappa;
+  if (!okp || !(kappa <= a.kappa_max)) {
+    if (lane == 0) {
+      if (a.status) a.status[i] = 1;
+      const int32_t q = atomicAdd(a.qcount, 1);
+      a.queue[q] = i;
+    }
+    return;
+  }
+  // ---- pass 2: stencils (and their application)
+  double lam[4 * M];
+#pragma unroll
+  for (int q = 0; q < 4 * M; ++q) lam[q] = s_lam[q];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double ui = 0.0;
+  if constexpr (FUSED) ui = a.u[i];
+  auto emit = [&](int k, int32_t j, double w, double dx, double dy, double dz) {
+    double X, Y, Z, phi[M];
+    local_xyz<M>(g, dx, dy, dz, X, Y, Z);
+    basis<M>(X, Y, Z, phi);
+    double c[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < M; ++q) t += phi[q] * lam[s * M + q];
+      c[s] = w * t;
+    }
+    if constexpr (M == 6) {
+      const double cu = c[0], cv = c[1];
+      c[0] = g.t1[0] * cu + g.t2[0] * cv;
+      c[1] = g.t1[1] * cu + g.t2[1] * cv;
+      c[2] = g.t1[2] * cu + g.t2[2] * cv;
+    }
+    if (a.w_out) store_w<OUT>(a.w_out, b + k, c[0], c[1], c[2], c[3]);
+    if constexpr (FUSED) {
+      if (j != i) {
+        const double du = a.u[j] - ui;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc[s] += ((OUT == GF_F32) ? (double)(float)c[s] : c[s]) * du;
+      }
+    }
+  };
+#pragma unroll 2
+  for (int k = lane; k < n; k += T) {
+    const int32_t j = a.col[b + k];
+    const double4 pj = a.pos[j];
+    const double dx = pj.x - g.xi, dy = pj.y - g.yi, dz = pj.z - g.zi;
+    const double w = (k < kCacheW * T) ? s_w[k] : nbr_weight_h<FASTW>(a, g, pj.w, dx, dy, dz);
+    emit(k, j, w, dx, dy, dz);
+  }
+  if constexpr (FUSED) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc[s] = team_sum(acc[s], T);
+    if (lane == 0) store_fused(a, i, acc);
+  }
+  if (lane == 0 && a.status) a.status[i] = 0;
+}
+
 template <int M, int T, int OUT, bool FUSED, bool FASTW>
 __global__ void __launch_bounds__(kBlock) k_weights_team(WArgs a) {
-  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double smem[(kBlock / T) * team_lds_doubles<M>(T)];
+  const int64_t gt = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int64_t team = gt / T;
   const int lane = (int)(gt % T);
   if (team >= a.nrows) return;
-  weights_row<M, T, OUT, FUSED, FASTW>(a, a.sched[team], lane);
+  double *sm = smem + (threadIdx.x / T) * team_lds_doubles<M>(T);
+  weights_row_team<M, T, OUT, FUSED, FASTW>(a, a.sched[team], lane, sm);
 }
 
 __global__ void __launch_bounds__(kBlock) k_weights_plain(WArgs a) {
@@ -352,6 +583,13 @@ __global__ void __launch_bounds__(kQrBlock) k_weights_qr(WArgs a, double *scratc
   }
 }
 
+__global__ void __launch_bounds__(kBlock) k_pack_pos(const double *__restrict__ x, const double *__restrict__ y,
+                                                     const double *__restrict__ z, const double *__restrict__ h,
+                                                     int64_t n, double4 *__restrict__ pos) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) pos[i] = make_double4(x[i], y[i], z[i], h[i]);
+}
+
 __global__ void k_zero_i32(int32_t *p, int n) {
   if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
@@ -384,25 +622,19 @@ __global__ void __launch_bounds__(1024) k_ls_stats(const int8_t *__restrict__ st
   if (threadIdx.x == 0) *out_kmax = km[0];
 }
 
-// team size per (model, neighbour-count band)
-int team_for(int model, int band) {
-  static const int bulk[GF_NBAND] = {4, 8, 8, 16};
-  static const int film[GF_NBAND] = {4, 4, 8, 16};
-  return model ? film[band] : bulk[band];
-}
-
-const char *team_kernel_name(int M, int T, bool fused) {
-  if (M == 10) {
-    if (fused) return T == 4 ? "weights_apply_3d_t4" : T == 8 ? "weights_apply_3d_t8" : "weights_apply_3d_t16";
-    return T == 4 ? "weights_3d_t4" : T == 8 ? "weights_3d_t8" : "weights_3d_t16";
-  }
-  if (fused) return T == 4 ? "weights_apply_film_t4" : T == 8 ? "weights_apply_film_t8" : "weights_apply_film_t16";
-  return T == 4 ? "weights_film_t4" : T == 8 ? "weights_film_t8" : "weights_film_t16";
+// profiling names: one per (model, band) group
+const char *team_kernel_name(int model, int band, bool fused) {
+  static const char *names[2][2][GF_NBAND] = {
+      {{"weights_3d_b0", "weights_3d_b1", "weights_3d_b2", "weights_3d_b3"},
+       {"weights_film_b0", "weights_film_b1", "weights_film_b2", "weights_film_b3"}},
+      {{"weights_apply_3d_b0", "weights_apply_3d_b1", "weights_apply_3d_b2", "weights_apply_3d_b3"},
+       {"weights_apply_film_b0", "weights_apply_film_b1", "weights_apply_film_b2", "weights_apply_film_b3"}}};
+  return names[fused ? 1 : 0][model][band];
 }
 
 template <int M, int OUT, bool FUSED, bool FASTW>
-gf_status launch_team(gf_ctx *ctx, const WArgs &a, int T) {
-  ProfScope prof(ctx, team_kernel_name(M, T, FUSED));
+gf_status launch_team(gf_ctx *ctx, const WArgs &a, int T, const char *name) {
+  ProfScope prof(ctx, name);
   const int64_t threads = a.nrows * (int64_t)T;
   const dim3 grid(grid_for(threads, kBlock)), block(kBlock);
   switch (T) {
@@ -415,17 +647,23 @@ gf_status launch_team(gf_ctx *ctx, const WArgs &a, int T) {
   return GF_OK;
 }
 
+// one launch per non-empty (model, band) group; only_group >= 0 restricts
+// the launches to that group and team_override > 0 replaces its team size
+// (used by the autotuner)
 template <int OUT, bool FUSED, bool FASTW>
-gf_status launch_batched(gf_ctx *ctx, const gf_nbr *nbr, WArgs a) {
+gf_status launch_batched(gf_ctx *ctx, const gf_nbr *nbr, WArgs a, int only_group = -1, int team_override = 0) {
   for (int m = 0; m < 2; ++m) {
     for (int band = 0; band < GF_NBAND; ++band) {
       const int gsel = m * GF_NBAND + band;
+      if (only_group >= 0 && gsel != only_group) continue;
       const int64_t s0 = nbr->group_start[gsel], s1 = nbr->group_start[gsel + 1];
       if (s1 <= s0) continue;
       a.sched = nbr->grouped + s0;
       a.nrows = s1 - s0;
-      const int T = team_for(m, band);
-      gf_status st = (m == 0) ? launch_team<10, OUT, FUSED, FASTW>(ctx, a, T) : launch_team<6, OUT, FUSED, FASTW>(ctx, a, T);
+      const int T = team_override > 0 ? team_override : ctx->wteam[m][band];
+      const char *name = team_kernel_name(m, band, FUSED);
+      gf_status st = (m == 0) ? launch_team<10, OUT, FUSED, FASTW>(ctx, a, T, name)
+                              : launch_team<6, OUT, FUSED, FASTW>(ctx, a, T, name);
       if (st) return st;
     }
   }
@@ -467,7 +705,7 @@ gf_status weights_common(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr, 
   const int64_t slice = (int64_t)kQrStride * std::max(nbr->max_row, 1);
   Arena ar;
   if ((st = ensure_scratch(ctx, arena_bytes({sizeof(int32_t) * n, 64, sizeof(double) * slice * qr_blocks, (size_t)n,
-                                             sizeof(float) * n, 64, 64}),
+                                             sizeof(float) * n, 64, 64, sizeof(double4) * n}),
                            &ar)))
     return st;
   WeightsScratch ws;
@@ -478,8 +716,15 @@ gf_status weights_common(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr, 
   ws.kappa = ar.take<float>(n);
   ws.counts = ar.take<long long>(4);
   ws.kmax = ar.take<double>(1);
+  double4 *pos = ar.take<double4>(n);
   WArgs a;
   a.x = p->x; a.y = p->y; a.z = p->z; a.h = p->h; a.nx = p->nx; a.ny = p->ny; a.nz = p->nz; a.model = p->model;
+  a.pos = pos;
+  if (prec == GF_BATCHED) {
+    ProfScope prof(ctx, "pack_positions");
+    hipLaunchKernelGGL(k_pack_pos, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, ctx->stream, p->x, p->y, p->z, p->h, n, pos);
+    GF_LAUNCH_CHECK(ctx);
+  }
   a.row_ptr = nbr->row_ptr; a.col = nbr->col; a.sched = nullptr; a.nrows = n; a.n = n;
   a.wf = make_weight_fn(prm.alpha_w);
   a.kappa_max = prm.kappa_max;
@@ -550,4 +795,93 @@ extern "C" gf_status gf_gfdm_weights_apply(gf_ctx *ctx, const gf_particles *p, c
   if (!ctx) return GF_EINVAL;
   return weights_common(ctx, p, nbr, GF_BATCHED, params, wtype, w_out, status_n, nullptr, nullptr, true, op_mask, u,
                         out);
+}
+
+// ------------------------------------------------------------------ autotuner
+// Times every (model, band) group of the batched stencil kernel with teams of
+// 4, 8 and 16 lanes (median of three launches after a warm-up) and keeps the
+// fastest; then does the same for the application kernel.
+extern "C" gf_status gf_autotune(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr, gf_dtype wtype,
+                                 int *team_out) {
+  if (!ctx) return GF_EINVAL;
+  gf_status st = check_particles(ctx, p, false, false);
+  if (st) return st;
+  if ((st = check_nbr(ctx, nbr, p->n))) return st;
+  if (nbr->cross) return set_error(ctx, GF_EINVAL, "stencils need same-model neighbourhoods");
+  if (wtype != GF_F64 && wtype != GF_F32) return set_error(ctx, GF_EINVAL, "unknown weight type %d", (int)wtype);
+  const bool has_film = nbr->group_start[2 * GF_NBAND] > nbr->group_start[GF_NBAND];
+  if (has_film && (!p->nx || !p->ny || !p->nz)) return set_error(ctx, GF_EINVAL, "film particles need normals");
+  const int64_t n = p->n;
+  const size_t wbytes = (size_t)std::max<int64_t>(nbr->nnz, 1) * 4 * (wtype == GF_F32 ? sizeof(float) : sizeof(double));
+  void *wbuf = nullptr;
+  if (hipMalloc(&wbuf, wbytes) != hipSuccess) return set_error(ctx, GF_ENOMEM, "autotune buffer allocation failed");
+  Arena ar;
+  if ((st = ensure_scratch(ctx, arena_bytes({sizeof(int32_t) * n, 64, sizeof(double4) * n}), &ar))) {
+    (void)hipFree(wbuf);
+    return st;
+  }
+  WArgs a;
+  a.x = p->x; a.y = p->y; a.z = p->z; a.h = p->h; a.nx = p->nx; a.ny = p->ny; a.nz = p->nz; a.model = p->model;
+  a.row_ptr = nbr->row_ptr; a.col = nbr->col; a.sched = nullptr; a.nrows = n; a.n = n;
+  gf_ls_params prm;
+  gf_ls_params_default(&prm);
+  a.wf = make_weight_fn(prm.alpha_w);
+  a.kappa_max = prm.kappa_max;
+  a.w_out = wbuf; a.status = nullptr; a.kappa_out = nullptr;
+  a.queue = ar.take<int32_t>(n);
+  a.qcount = ar.take<int32_t>(16);
+  a.u = nullptr; a.y_out = nullptr; a.mask = 0;
+  double4 *pos = ar.take<double4>(n);
+  a.pos = pos;
+  hipLaunchKernelGGL(k_pack_pos, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, ctx->stream, p->x, p->y, p->z, p->h, n, pos);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    (void)hipFree(wbuf);
+    return set_error(ctx, GF_EHIP, "event creation failed");
+  }
+  const int sizes[3] = {4, 8, 16};
+  const int saved_profile = ctx->profile;
+  ctx->profile = 0;
+  for (int gsel = 0; gsel < 2 * GF_NBAND && !st; ++gsel) {
+    if (nbr->group_start[gsel + 1] <= nbr->group_start[gsel]) continue;
+    float best = INFINITY;
+    int bestT = ctx->wteam[gsel / GF_NBAND][gsel % GF_NBAND];
+    for (int t = 0; t < 3 && !st; ++t) {
+      float times[3];
+      for (int rep = -1; rep < 3 && !st; ++rep) {
+        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, a.qcount, 16);
+        if (rep >= 0) (void)hipEventRecord(e0, ctx->stream);
+        st = (wtype == GF_F32) ? launch_batched<GF_F32, false, true>(ctx, nbr, a, gsel, sizes[t])
+                               : launch_batched<GF_F64, false, false>(ctx, nbr, a, gsel, sizes[t]);
+        if (rep >= 0) {
+          (void)hipEventRecord(e1, ctx->stream);
+          (void)hipEventSynchronize(e1);
+          (void)hipEventElapsedTime(&times[rep], e0, e1);
+        }
+      }
+      if (st) break;
+      std::sort(times, times + 3);
+      if (times[1] < best) { best = times[1]; bestT = sizes[t]; }
+    }
+    ctx->wteam[gsel / GF_NBAND][gsel % GF_NBAND] = bestT;
+  }
+  // complete the stencils with the tuned configuration, then tune the application
+  if (!st) {
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, a.qcount, 16);
+    st = (wtype == GF_F32) ? launch_batched<GF_F32, false, true>(ctx, nbr, a) : launch_batched<GF_F64, false, false>(ctx, nbr, a);
+  }
+  if (!st) st = tune_apply(ctx, nbr, wbuf, wtype);
+  ctx->profile = saved_profile;
+  (void)hipStreamSynchronize(ctx->stream);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(wbuf);
+  if (st) return st;
+  if (team_out) {
+    for (int g = 0; g < 2 * GF_NBAND; ++g) {
+      team_out[g] = ctx->wteam[g / GF_NBAND][g % GF_NBAND];
+      team_out[2 * GF_NBAND + g] = ctx->ateam[g / GF_NBAND][g % GF_NBAND];
+    }
+  }
+  return GF_OK;
 }

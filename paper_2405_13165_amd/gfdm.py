@@ -72,7 +72,7 @@ EXPORTED = [
     "gf_pca_params_default", "gf_classify_pca", "gf_ls_params_default", "gf_gfdm_weights",
     "gf_apply_stencil", "gf_gfdm_weights_apply", "gf_poisson_assemble", "gf_solve_params_default",
     "gf_poisson_solve", "gf_transition_3d_to_2d", "gf_apply_stencil_adjoint",
-    "gf_gfdm_weights_adjoint", "gf_profile_enable", "gf_profile_read",
+    "gf_gfdm_weights_adjoint", "gf_profile_enable", "gf_profile_read", "gf_autotune",
 ]
 
 _lib = None
@@ -118,6 +118,7 @@ def load_library(path: str = LIB_PATH):
     L.gf_transition_3d_to_2d.argtypes = [P, PP, P] + [P] * 11
     L.gf_apply_stencil_adjoint.argtypes = [P, P, I32, P, U, P, P]
     L.gf_gfdm_weights_adjoint.argtypes = [P, PP, P, ctypes.POINTER(LsParams), U, P, P, P]
+    L.gf_autotune.argtypes = [P, PP, P, I32, P]
     L.gf_profile_enable.argtypes = [P, I32]
     L.gf_profile_read.argtypes = [P, ctypes.c_char_p, ctypes.c_size_t]
     for name in EXPORTED:
@@ -309,6 +310,15 @@ def gfdm_weights(ctx, p, nbr, prec=GF_BATCHED, wtype=GF_F32, params=None, out=No
     if stats:
         return w, {k: getattr(st, k) for k, _ in LsStats._fields_}
     return w
+
+
+def autotune(ctx, p, nbr, wtype=GF_F32):
+    """Pick team sizes per group for the stencil and application kernels.
+    Returns {'weights': [8 ints], 'apply': [8 ints]} (bulk bands 0-3, film bands 0-3)."""
+    out = (ctypes.c_int * 16)()
+    ctx._sync_stream()
+    ctx.check(ctx.lib.gf_autotune(ctx.handle, ctypes.byref(p.s), nbr.handle, wtype, out))
+    return {"weights": list(out[:8]), "apply": list(out[8:])}
 
 
 def _nops(mask):

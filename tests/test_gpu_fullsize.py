@@ -1,0 +1,177 @@
+"""Parity at the full workload sizes, in the launch configuration the bench
+times (autotuned team sizes, batched FP32 stencils), against the FP64 oracle.
+
+ - mixed bulk/film cloud, 503,944 particles: every neighbour list, every
+   stored stencil and every applied value;
+ - jet impact, 2.0M particles with uneven supports (13..228 neighbours):
+   every neighbour list, stencils of 20,000 sampled rows;
+ - differentiation cube, 10^6 particles: gradients with respect to field
+   values and positions at 100 sampled coordinates against central finite
+   differences of the oracle (local re-evaluation of the affected rows);
+ - projection cylinder, 4.0M rows: FP64 and mixed solves of a seeded
+   right-hand side, residual re-evaluated by the oracle on sampled rows.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_13165_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def g():
+    from paper_2405_13165_amd import gfdm
+    gfdm.load_library()
+    return gfdm
+
+
+@pytest.fixture(scope="module")
+def ctx(g):
+    c = g.Context(0)
+    yield c
+    c.close()
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def test_full_mixed_workload(ctx, g):
+    print("\n[full] mixed 503,944", flush=True)
+    d = W.mixed_block_film()
+    p = g.Particles.from_dict(ctx, d)
+    nb = g.build_neighbours(ctx, p)
+    rp_o, col_o = oracle.neighbours(d)
+    rp, col = nb.export()
+    assert np.array_equal(_np(rp), rp_o) and np.array_equal(_np(col), col_o)
+    g.autotune(ctx, p, nb, g.GF_F32)
+    f, *_ = W.test_field(d["x"], d["y"], d["z"])
+    u = torch.as_tensor(f, device=ctx.device)
+    status = torch.empty(p.n, dtype=torch.int8, device=ctx.device)
+    w32 = g.gfdm_weights(ctx, p, nb, g.GF_BATCHED, g.GF_F32, status=status)
+    y32 = g.apply_stencil(ctx, nb, w32, u)
+    w_o, st_o, _ = oracle.gfdm_weights(d, rp_o, col_o)
+    st = _np(status)
+    assert np.array_equal(np.where(st == 1, 0, st), st_o)
+    e = oracle.operator_error(_np(w32).astype(np.float64), w_o, rp_o)
+    print(f"[full] mixed FP32 operator error max {e.max():.3e}", flush=True)
+    assert e.max() <= 1e-6
+    y_o = oracle.apply(rp_o, col_o, w_o, f)
+    rid = np.repeat(np.arange(p.n), np.diff(rp_o))
+    du = np.abs(f[col_o] - f[rid])
+    y = _np(y32)
+    for s in range(4):
+        mag = np.bincount(rid, np.abs(w_o[:, s]) * du, minlength=p.n).max()
+        assert np.abs(y[s] - y_o[s]).max() <= 1e-6 * mag
+    # FP64 batched on the same launch configuration
+    w64 = g.gfdm_weights(ctx, p, nb, g.GF_BATCHED, g.GF_F64)
+    assert oracle.operator_error(_np(w64), w_o, rp_o).max() <= 1e-10
+    # fused call, stencils not stored
+    _, yf = g.gfdm_weights_apply(ctx, p, nb, u, wtype=g.GF_F32, store_weights=False)
+    assert (yf - y32).abs().max().item() <= 1e-9 * (y32.abs().max().item() + 1)
+
+
+def test_full_jet_uneven(ctx, g):
+    print("\n[full] jet 2.0M", flush=True)
+    d = W.jet_impact()
+    p = g.Particles.from_dict(ctx, d)
+    nb = g.build_neighbours(ctx, p)
+    rp_o, col_o = oracle.neighbours(d)
+    rp, col = nb.export()
+    assert np.array_equal(_np(rp), rp_o) and np.array_equal(_np(col), col_o)
+    g.autotune(ctx, p, nb, g.GF_F32)
+    status = torch.empty(p.n, dtype=torch.int8, device=ctx.device)
+    w32, stats = g.gfdm_weights(ctx, p, nb, g.GF_BATCHED, g.GF_F32, status=status, stats=True)
+    print(f"[full] jet stats {stats}", flush=True)
+    rows = np.sort(np.random.default_rng(11).choice(p.n, 20000, replace=False))
+    w_o, st_o, _ = oracle.gfdm_weights(d, rp_o, col_o, rows=rows)
+    st = _np(status)[rows]
+    assert np.array_equal(np.where(st == 1, 0, st), st_o[rows])
+    sel = np.concatenate([np.arange(rp_o[i], rp_o[i + 1]) for i in rows])
+    sub_rp = np.concatenate([[0], np.cumsum(np.diff(rp_o)[rows])])
+    e = oracle.operator_error(_np(w32)[sel].astype(np.float64), w_o[sel], sub_rp)
+    print(f"[full] jet FP32 operator error max {e.max():.3e} on {rows.size} rows", flush=True)
+    assert e.max() <= 1e-6
+
+
+def test_full_differentiation_fd(ctx, g):
+    print("\n[full] differentiation 1e6", flush=True)
+    d = W.diff_cube()
+    p = g.Particles.from_dict(ctx, d)
+    nb = g.build_neighbours(ctx, p)
+    rp, col = (a.cpu().numpy() for a in nb.export())
+    dev = ctx.device
+    u = torch.as_tensor(d["u"], device=dev)
+    x = torch.as_tensor(d["x"], device=dev)
+    y = torch.as_tensor(d["y"], device=dev)
+    z = torch.as_tensor(d["z"], device=dev)
+    gt = torch.as_tensor(d["g"], device=dev)
+    ur = u.clone().requires_grad_(True)
+    xr, yr, zr = (t.clone().requires_grad_(True) for t in (x, y, z))
+    out = g.stencil_op(ctx, p, nb, ur, xr, yr, zr, op_mask=g.OP_LAP, wtype=g.GF_F32)
+    loss = ((out[0] - gt) ** 2).sum()
+    gu, gx, gy, gz = torch.autograd.grad(loss, (ur, xr, yr, zr))
+    grads = {"u": _np(gu), "x": _np(gx), "y": _np(gy), "z": _np(gz)}
+    # oracle: central differences of the local loss (only rows whose stencil
+    # contains the perturbed particle change), eps = 1e-6, FP64
+    rng = np.random.default_rng(21)
+    X = np.stack([d["x"], d["y"], d["z"]], 1)
+    eps = 1e-6
+    checked = 0
+    for t in range(100):
+        i = int(rng.integers(p.n))
+        key = "u" if t < 50 else "xyz"[t % 3]
+        rows = np.unique(np.concatenate([[i], col[rp[i]:rp[i + 1]]]))
+        nbs = col[rp[i]:rp[i + 1]]
+        dist = np.sqrt(((X[nbs] - X[i]) ** 2).sum(1))
+        if np.any(np.abs(dist - 0.5 * (d["h"][i] + d["h"][nbs])) < 10 * eps):
+            continue
+
+        def local_loss(dd, uu):
+            # oracle stencils of the affected rows, applied in differenced form
+            w, _, _ = oracle.gfdm_weights(dd, rp, col, rows=rows)
+            tot = 0.0
+            for r in rows:
+                seg = slice(rp[r], rp[r + 1])
+                cj = col[seg]
+                yv = (w[seg, 3] * (uu[cj] - uu[r]))[cj != r].sum()
+                tot += (yv - d["g"][r]) ** 2
+            return tot
+
+        if key == "u":
+            up = d["u"].copy(); up[i] += eps
+            um = d["u"].copy(); um[i] -= eps
+            fd = (local_loss(d, up) - local_loss(d, um)) / (2 * eps)
+        else:
+            dp = dict(d); dp[key] = d[key].copy(); dp[key][i] += eps
+            dm = dict(d); dm[key] = d[key].copy(); dm[key][i] -= eps
+            fd = (local_loss(dp, d["u"]) - local_loss(dm, d["u"])) / (2 * eps)
+        got = grads[key][i]
+        scale = np.abs(grads[key]).max()
+        assert abs(got - fd) <= 1e-6 * scale + 1e-4 * abs(fd), (key, i, got, fd)
+        checked += 1
+    assert checked >= 90
+
+
+@pytest.mark.parametrize("mixed", [0, 1])
+def test_full_projection_solve(ctx, g, mixed):
+    print(f"\n[full] projection 4.0M mixed={mixed}", flush=True)
+    d = W.projection_cylinder()
+    p = g.Particles.from_dict(ctx, d)
+    nb = g.build_neighbours(ctx, p)
+    rp, col = (a.cpu().numpy() for a in nb.export())
+    w64 = g.gfdm_weights(ctx, p, nb, g.GF_BATCHED, g.GF_F64)
+    rhs = np.random.default_rng(31).uniform(-1.0, 1.0, p.n)   # seeded, independent of the device
+    x, st = g.poisson_solve(ctx, p, nb, w64, d["row_type"], torch.as_tensor(rhs, device=ctx.device),
+                            params=g.solve_params(mixed=mixed))
+    print(f"[full] projection stats {st}", flush=True)
+    assert st["converged"] == 1 and st["final_rel_res"] <= 1e-8
+    xs = _np(x)
+    rows = np.sort(np.random.default_rng(32).choice(p.n, 3000, replace=False))
+    w_o, _, _ = oracle.gfdm_weights(d, rp, col, rows=rows)
+    val = oracle.poisson_matrix(d, rp, col, w_o, d["row_type"])
+    r = np.array([rhs[i] - (val[rp[i]:rp[i + 1]] * xs[col[rp[i]:rp[i + 1]]]).sum() for i in rows])
+    assert np.abs(r).max() <= 1.01e-8 * np.linalg.norm(rhs)
