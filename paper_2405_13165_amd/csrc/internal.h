@@ -63,7 +63,23 @@ struct gf_nbr {
   int32_t *grouped = nullptr;  // [n] particles grouped by (model, band), Morton order inside
   int64_t group_start[2 * GF_NBAND + 1] = {0};  // host copy of the group offsets
   int32_t *rev = nullptr;      // [nnz] position of (j,i) for entry (i,j); built lazily
+  // Neighbour tiles: the rows of each group with at most kTileBandRow
+  // neighbours are cut, in group (Morton) order, into tiles of kTileRows
+  // rows.  tile_u holds, per tile, the sorted distinct neighbour indices of
+  // its rows (tile t owns tile_u[tile_off[t] .. tile_off[t+1])); slot[k] is
+  // the position of col[k] in its row's tile list.  Kernels stage a tile's
+  // list in LDS once and address it through slot[].
+  uint16_t *slot = nullptr;    // [nnz]
+  int32_t *tile_u = nullptr;   // [tile_off[ntiles]]
+  int64_t *tile_off = nullptr; // [ntiles + 1]
+  int64_t ntiles = 0;
+  int64_t tile_start[2 * GF_NBAND + 1] = {0};  // host: first tile of each group (tiled bands only)
+  int32_t tile_max[2 * GF_NBAND] = {0};        // host: largest tile list of each group
 };
+constexpr int kTileRows = 32;
+constexpr int kTileBand = 2;                   // bands 0..kTileBand are tiled
+constexpr int kTileBandRow = 128;              // = kBandHi[kTileBand]
+inline bool band_tiled(int band) { return band <= kTileBand; }
 
 // ------------------------------------------------------------------ errors
 gf_status set_error(gf_ctx *ctx, gf_status st, const char *fmt, ...);

@@ -195,8 +195,12 @@ __global__ void __launch_bounds__(kBlock) k_search(const int32_t *__restrict__ o
                                                    int64_t n, Grid g, int32_t *__restrict__ cnt,
                                                    int32_t *__restrict__ hist, int32_t *__restrict__ maxrow,
                                                    const int64_t *__restrict__ row_ptr, int32_t *__restrict__ col) {
-  int64_t sidx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (sidx >= n) return;
+  const int64_t sidx0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = sidx0 < n;
+  if (MODE == 1 && !valid) return;
+  // MODE 0 keeps the idle lanes of the last wave alive for the wave-wide
+  // histogram below; they search on behalf of particle n-1 and count nothing
+  const int64_t sidx = valid ? sidx0 : n - 1;
   const int32_t i = order[sidx];
   const double4 pi = sp[sidx];
   const int m = model[i];
@@ -230,11 +234,22 @@ __global__ void __launch_bounds__(kBlock) k_search(const int32_t *__restrict__ o
     }
   }
   if (MODE == 0) {
-    cnt[i] = c;
+    if (valid) cnt[i] = c;
     int band = 0;
     while (band < GF_NBAND - 1 && c > kBandHi[band]) ++band;
-    atomicAdd(&hist[m * GF_NBAND + band], 1);
-    atomicMax(maxrow, c);
+    // one atomic per wave and bin: same-address atomics from every particle
+    // serialise in L2 and used to dominate this kernel
+    const int bin = valid ? m * GF_NBAND + band : -1;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int b = 0; b < 2 * GF_NBAND; ++b) {
+      const unsigned long long mask = __ballot(bin == b);
+      if (lane == 0 && mask) atomicAdd(&hist[b], __popcll(mask));
+    }
+    int cm = valid ? c : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) cm = max(cm, __shfl_xor(cm, o, 64));
+    if (lane == 0) atomicMax(maxrow, cm);
   }
 }
 
@@ -289,6 +304,164 @@ __global__ void __launch_bounds__(kBlock) k_group_scatter(const int32_t *__restr
   if (flag[s]) grouped[base + pos[s]] = order[s];
 }
 
+// ---------------------------------------------------------------- tiles
+// Tiled groups, as passed to the tile kernels: tiles [tile_start[q],
+// tile_start[q+1]) cover rows [row_start[q], row_start[q] + nrows[q]) of the
+// grouped order.
+struct TileGroups {
+  int nq = 0;
+  int gsel[2 * GF_NBAND];
+  int64_t tile_start[2 * GF_NBAND + 1];
+  int64_t row_start[2 * GF_NBAND];
+  int64_t nrows[2 * GF_NBAND];
+};
+constexpr int kTileEntries = kTileRows * kTileBandRow;  // entries one tile can hold
+constexpr int kTileThreads = 256;
+
+__device__ inline int tile_group(const TileGroups &tg, int64_t t) {
+  int q = 0;
+  while (q + 1 < tg.nq && t >= tg.tile_start[q + 1]) ++q;
+  return q;
+}
+
+// number of neighbour entries of each tile
+__global__ void __launch_bounds__(kBlock) k_tile_entries(TileGroups tg, const int64_t *__restrict__ row_ptr,
+                                                         const int32_t *__restrict__ grouped,
+                                                         int32_t *__restrict__ ent) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= tg.tile_start[tg.nq]) return;
+  const int q = tile_group(tg, t);
+  const int64_t r0 = (t - tg.tile_start[q]) * kTileRows;
+  const int64_t r1 = min(r0 + kTileRows, tg.nrows[q]);
+  int64_t e = 0;
+  for (int64_t r = r0; r < r1; ++r) {
+    const int32_t i = grouped[tg.row_start[q] + r];
+    e += row_ptr[i + 1] - row_ptr[i];
+  }
+  ent[t] = (int32_t)e;
+}
+
+// One block per tile: sort the tile's (index, entry) pairs, number the
+// distinct indices in ascending order, write slot[] for every entry and the
+// distinct indices to uniq[ent_off[t] ...]; cnt[t] = number of distinct.
+__global__ void __launch_bounds__(kTileThreads) k_tile_unique(TileGroups tg, const int64_t *__restrict__ row_ptr,
+                                                              const int32_t *__restrict__ col,
+                                                              const int32_t *__restrict__ grouped,
+                                                              const int64_t *__restrict__ ent_off,
+                                                              uint16_t *__restrict__ slot,
+                                                              int32_t *__restrict__ uniq, int32_t *__restrict__ cnt,
+                                                              int32_t *__restrict__ grp_max) {
+  __shared__ uint64_t key[kTileEntries];
+  __shared__ int64_t rbase[kTileRows];
+  __shared__ int32_t rloc[kTileRows + 1];
+  __shared__ int32_t csum[kTileThreads];
+  const int64_t t = blockIdx.x;
+  const int q = tile_group(tg, t);
+  const int64_t r0 = (t - tg.tile_start[q]) * kTileRows;
+  const int R = (int)min((int64_t)kTileRows, tg.nrows[q] - r0);
+  const int tid = threadIdx.x;
+  if (tid < 64) {
+    int len = 0;
+    if (tid < R) {
+      const int32_t i = grouped[tg.row_start[q] + r0 + tid];
+      rbase[tid] = row_ptr[i];
+      len = (int)(row_ptr[i + 1] - row_ptr[i]);
+    }
+    int inc = len;  // inclusive wave scan
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(inc, o, 64);
+      if (tid >= o) inc += v;
+    }
+    if (tid < kTileRows) rloc[tid + 1] = inc;
+    if (tid == 0) rloc[0] = 0;
+  }
+  __syncthreads();
+  const int E = rloc[R];
+  int P = 1;
+  while (P < E) P <<= 1;
+  auto row_of = [&](int e) {  // row r with rloc[r] <= e < rloc[r+1]
+    int lo = 0, hi = R - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (rloc[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+  };
+  for (int e = tid; e < P; e += kTileThreads) {
+    if (e < E) {
+      const int r = row_of(e);
+      const int32_t j = col[rbase[r] + (e - rloc[r])];
+      key[e] = ((uint64_t)(uint32_t)j << 12) | (uint64_t)e;
+    } else {
+      key[e] = ~0ull;
+    }
+  }
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int e = tid; e < P; e += kTileThreads) {
+        const int u = e ^ j;
+        if (u > e) {
+          const uint64_t a = key[e], b = key[u];
+          if ((a > b) == ((e & k) == 0)) { key[e] = b; key[u] = a; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // each thread numbers a contiguous chunk of the sorted list
+  const int chunk = (P + kTileThreads - 1) / kTileThreads;
+  const int s0 = tid * chunk;
+  int c = 0;
+  for (int s = s0; s < min(s0 + chunk, E); ++s)
+    c += (s == 0 || (key[s] >> 12) != (key[s - 1] >> 12)) ? 1 : 0;
+  csum[tid] = c;
+  __syncthreads();
+  if (tid < 64) {  // exclusive scan of the 256 chunk counts by one wave
+    int v[4], tot = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) { v[u] = csum[tid * 4 + u]; tot += v[u]; }
+    int inc = tot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int w = __shfl_up(inc, o, 64);
+      if (tid >= o) inc += w;
+    }
+    int run = inc - tot;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) { csum[tid * 4 + u] = run; run += v[u]; }
+    if (tid == 63) {
+      cnt[t] = inc;
+      atomicMax(&grp_max[q], inc);
+    }
+  }
+  __syncthreads();
+  int uid = csum[tid] - 1;
+  const int64_t ubase = ent_off[t];
+  for (int s = s0; s < min(s0 + chunk, E); ++s) {
+    const uint64_t kv = key[s];
+    const int32_t j = (int32_t)(kv >> 12);
+    if (s == 0 || j != (int32_t)(key[s - 1] >> 12)) {
+      ++uid;
+      uniq[ubase + uid] = j;
+    }
+    const int e = (int)(kv & 0xfff);
+    const int r = row_of(e);
+    slot[rbase[r] + (e - rloc[r])] = (uint16_t)uid;
+  }
+}
+
+// uniq (at the entry offsets) -> tile_u (at the list offsets)
+__global__ void __launch_bounds__(kTileThreads) k_tile_compact(const int64_t *__restrict__ ent_off,
+                                                               const int64_t *__restrict__ u_off,
+                                                               const int32_t *__restrict__ uniq,
+                                                               int32_t *__restrict__ tile_u) {
+  const int64_t t = blockIdx.x;
+  const int64_t a = ent_off[t], b = u_off[t], m = u_off[t + 1] - b;
+  for (int64_t s = threadIdx.x; s < m; s += kTileThreads) tile_u[b + s] = uniq[a + s];
+}
+
 // reverse-edge map: rev[k] = position of (j, i) in row j for entry k = (i, j)
 __global__ void __launch_bounds__(kBlock) k_rev(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
                                                 int64_t n, int32_t *__restrict__ rev) {
@@ -319,6 +492,9 @@ void free_nbr(gf_nbr *nb) {
   if (nb->order) (void)hipFree(nb->order);
   if (nb->grouped) (void)hipFree(nb->grouped);
   if (nb->rev) (void)hipFree(nb->rev);
+  if (nb->slot) (void)hipFree(nb->slot);
+  if (nb->tile_u) (void)hipFree(nb->tile_u);
+  if (nb->tile_off) (void)hipFree(nb->tile_off);
   delete nb;
 }
 
@@ -355,6 +531,69 @@ gf_status ensure_rev(gf_ctx *ctx, gf_nbr *nbr) {
   GF_LAUNCH_CHECK(ctx);
   return GF_OK;
 }
+
+namespace {
+
+// Cut the tiled groups into tiles and build slot[], tile_u[], tile_off[].
+gf_status build_tiles(gf_ctx *ctx, gf_nbr *nb) {
+  hipStream_t sm = ctx->stream;
+  TileGroups tg;
+  int64_t nt = 0;
+  for (int gsel = 0; gsel < 2 * GF_NBAND; ++gsel) {
+    nb->tile_start[gsel] = nt;
+    const int64_t rows = nb->group_start[gsel + 1] - nb->group_start[gsel];
+    if (!band_tiled(gsel % GF_NBAND) || rows == 0) continue;
+    tg.gsel[tg.nq] = gsel;
+    tg.tile_start[tg.nq] = nt;
+    tg.row_start[tg.nq] = nb->group_start[gsel];
+    tg.nrows[tg.nq] = rows;
+    ++tg.nq;
+    nt += (rows + kTileRows - 1) / kTileRows;
+  }
+  nb->tile_start[2 * GF_NBAND] = nt;
+  tg.tile_start[tg.nq] = nt;
+  nb->ntiles = nt;
+  if (nt == 0) return GF_OK;
+  if (nt >= 0x7fffffff) return set_error(ctx, GF_ECAPACITY, "too many neighbour tiles");
+  if (hipMalloc(&nb->slot, sizeof(uint16_t) * std::max<int64_t>(nb->nnz, 1)) != hipSuccess ||
+      hipMalloc(&nb->tile_off, sizeof(int64_t) * (nt + 1)) != hipSuccess)
+    return set_error(ctx, GF_ENOMEM, "neighbour tile allocation failed");
+  Arena ar;
+  std::vector<size_t> sz = {sizeof(int32_t) * nt, sizeof(int64_t) * (nt + 1), sizeof(int64_t) * scan_tmp_elems(nt + 1),
+                            sizeof(int32_t) * std::max<int64_t>(nb->nnz, 1), sizeof(int32_t) * nt, 64};
+  gf_status st;
+  if ((st = ensure_scratch(ctx, arena_bytes(sz), &ar))) return st;
+  int32_t *ent = ar.take<int32_t>(nt);
+  int64_t *ent_off = ar.take<int64_t>(nt + 1);
+  int64_t *tmp64 = ar.take<int64_t>(scan_tmp_elems(nt + 1));
+  int32_t *uniq = ar.take<int32_t>(std::max<int64_t>(nb->nnz, 1));
+  int32_t *cnt = ar.take<int32_t>(nt);
+  int32_t *grp_max = ar.take<int32_t>(16);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, sm, grp_max, (int64_t)16, 0);
+  hipLaunchKernelGGL(k_tile_entries, dim3(grid_for(nt, kBlock)), dim3(kBlock), 0, sm, tg, nb->row_ptr, nb->grouped,
+                     ent);
+  GF_LAUNCH_CHECK(ctx);
+  if ((st = scan_i32_to_i64(ctx, ent, ent_off, nt, tmp64))) return st;
+  hipLaunchKernelGGL(k_tile_unique, dim3((unsigned)nt), dim3(kTileThreads), 0, sm, tg, nb->row_ptr, nb->col,
+                     nb->grouped, ent_off, nb->slot, uniq, cnt, grp_max);
+  GF_LAUNCH_CHECK(ctx);
+  if ((st = scan_i32_to_i64(ctx, cnt, nb->tile_off, nt, tmp64))) return st;
+  if ((st = ensure_host(ctx, 4096))) return st;
+  char *hp = (char *)ctx->host_pinned;
+  GF_HIP(ctx, hipMemcpyAsync(hp, grp_max, sizeof(int32_t) * 16, hipMemcpyDeviceToHost, sm));
+  GF_HIP(ctx, hipMemcpyAsync(hp + 128, nb->tile_off + nt, sizeof(int64_t), hipMemcpyDeviceToHost, sm));
+  GF_HIP(ctx, hipStreamSynchronize(sm));
+  for (int q = 0; q < tg.nq; ++q) nb->tile_max[tg.gsel[q]] = ((int32_t *)hp)[q];
+  const int64_t total = *(int64_t *)(hp + 128);
+  if (hipMalloc(&nb->tile_u, sizeof(int32_t) * std::max<int64_t>(total, 1)) != hipSuccess)
+    return set_error(ctx, GF_ENOMEM, "neighbour tile list allocation failed");
+  hipLaunchKernelGGL(k_tile_compact, dim3((unsigned)nt), dim3(kTileThreads), 0, sm, ent_off, nb->tile_off, uniq,
+                     nb->tile_u);
+  GF_LAUNCH_CHECK(ctx);
+  return GF_OK;
+}
+
+}  // namespace
 
 extern "C" gf_status gf_build_neighbours(gf_ctx *ctx, const gf_particles *p, int cross_model, gf_nbr **out) {
   if (!ctx) return GF_EINVAL;
@@ -514,6 +753,7 @@ extern "C" gf_status gf_build_neighbours(gf_ctx *ctx, const gf_particles *p, int
   if (hipGetLastError() != hipSuccess) return fail(set_error(ctx, GF_EHIP, "grouping kernels failed"));
   if (off != n) return fail(set_error(ctx, GF_EHIP, "internal error: grouping covers %lld of %lld", (long long)off,
                                       (long long)n));
+  if ((st = build_tiles(ctx, nb))) return fail(st);
   *out = nb;
   return GF_OK;
 }

@@ -4,18 +4,19 @@
 // Batched path: particles are grouped by model (10 monomials in 3D, 6 on the
 // film) and by neighbour-count band; inside a group they are taken in Morton
 // order.  Each particle is handled by a team of T lanes of a wave: the lanes
-// stride over the neighbours, accumulate their share of the packed FP64 Gram
-// matrix G = M^T W M in registers, and a butterfly sum gives every lane the
-// full G.  The team factors G (LDL^T), spreads the columns of G^{-1} over
-// its lanes to get the exact 1-norm condition number and the four target
-// solutions, and a second pass over the neighbours writes
-// c_j = w_j phi_j^T lambda (and, fused, applies the stencils to a field).
-// Particles whose condition number exceeds kappa_max, or whose pivots are not
-// positive, are queued and re-solved by a Householder QR of sqrt(W) M (one
-// wave per particle), which also decides rank deficiency.
+// stride over the neighbours and accumulate the weighted moments of the
+// scaled offsets, from which the team assembles G = M^T W M, inverts it by
+// Gauss-Jordan (exact 1-norm condition number from G^{-1}), and a second
+// pass over the neighbours writes c_j = w_j phi_j^T lambda (and, fused,
+// applies the stencils to a field).  Rows of the tiled bands are processed
+// one neighbour tile per block: the tile's distinct neighbour positions are
+// staged in LDS once and both passes read them there.  Particles whose
+// condition number exceeds kappa_max, or whose pivots are not positive, are
+// queued and re-solved by a Householder QR of sqrt(W) M (one wave per
+// particle), which also decides rank deficiency.
 //
-// Plain path: one work-item per particle in the caller's order, the same
-// FP64 arithmetic, FP64 output.
+// Plain path: one work-item per particle in the caller's order, an FP64 Gram
+// matrix with LDL^T solves, FP64 output.
 #include <algorithm>
 
 #include "stencil_common.h"
@@ -178,19 +179,6 @@ __device__ void weights_row(const WArgs &a, int32_t i, int lane) {
 }
 
 // ------------------------------------------------------------------ batched
-// Moment-based team path.  Per particle, a team of T >= M lanes:
-//  pass 1  each lane accumulates the weighted moments sum w X^a Y^b Z^c
-//          (a+b+c <= 4) of its neighbours and caches its first KC weights;
-//  reduce  butterfly over the team; the moments are staged in LDS;
-//  invert  lane r < M assembles row r of G from the moments and the team
-//          runs an in-place Gauss-Jordan inversion, one row per lane, the
-//          pivot row broadcast through LDS (G is SPD: no pivoting);
-//          ||G||_1 ||G^-1||_1 is the condition number; the target
-//          solutions lambda_s are read off the rows of G^-1 and shared
-//          through LDS;
-//  pass 2  each lane writes c_j = w_j phi_j . lambda_s for its neighbours.
-constexpr int kCacheW = 8;
-
 template <int M>
 struct GramTable {
   unsigned char v[M][M];
@@ -202,8 +190,13 @@ struct GramTable {
 __constant__ GramTable<10> kGram3 = GramTable<10>();
 __constant__ GramTable<6> kGram2 = GramTable<6>();
 
+// Per-team LDS (doubles): moments, later the scaled target solutions (the
+// two are never live together), the pivot row, and KC cached support
+// weights per lane.
 template <int M>
-constexpr int team_lds_doubles(int T) { return nmom<M>() + M + 1 + 4 * M + kCacheW * T; }
+constexpr int team_lds_doubles(int T, int KC) {
+  return (nmom<M>() > 4 * M ? nmom<M>() : 4 * M) + M + 1 + KC * T;
+}
 
 // orders the LDS traffic of the lanes of one wave around a hand-off
 __device__ inline void wave_sync() {
@@ -220,13 +213,44 @@ __device__ inline double nbr_weight_h(const WArgs &a, const RowGeom &g, double h
   return support_weight_q2<FASTW>(q2, a.wf);
 }
 
-template <int M, int T, int OUT, bool FUSED, bool FASTW>
-__device__ void weights_row_team(const WArgs &a, int32_t i, int lane, double *sm) {
+// Where a row finds the (x, y, z, h) of its neighbours.  idx(e) reads the
+// handle of CSR entry e, get(handle) the position; `dummy` is a valid handle
+// used for the loads issued past the end of a row.
+struct FetchGlobal {  // packed positions, gathered through col[]
+  const double4 *pos;
+  const int32_t *col;
+  int32_t dummy;
+  __device__ int32_t idx(int64_t e) const { return col[e]; }
+  __device__ double4 get(int32_t j) const { return pos[j]; }
+};
+struct FetchTile {    // the tile's positions staged in LDS, addressed by slot[]
+  const double4 *sp;
+  const uint16_t *slot;
+  int32_t dummy;
+  __device__ int32_t idx(int64_t e) const { return slot[e]; }
+  __device__ double4 get(int32_t s) const { return sp[s]; }
+};
+
+// Moment-based team path.  Per particle, a team of T lanes of one wave:
+//  pass 1  each lane accumulates the weighted moments sum w X^a Y^b Z^c
+//          (a+b+c <= 4) of its neighbours (and caches its first KC weights);
+//  reduce  butterfly over the team; the moments are staged in LDS;
+//  invert  the team assembles G from the moments (lane l owns rows
+//          l, l+T, ...) and runs an in-place Gauss-Jordan inversion with the
+//          pivot row broadcast through LDS (G is SPD: no pivoting);
+//          ||G||_1 ||G^-1||_1 is the condition number; the target solutions
+//          lambda_s are read off the rows of G^-1 and shared through LDS;
+//  pass 2  each lane writes c_j = w_j phi_j . lambda_s for its neighbours.
+// Neighbour loads are software-pipelined: the handle two neighbours ahead
+// and the position one neighbour ahead are in flight during the arithmetic.
+template <int M, int T, int OUT, bool FUSED, bool FASTW, int KC, class F>
+__device__ void weights_row_team(const WArgs &a, int32_t i, int lane, double *sm, const F &fetch) {
   constexpr int NM = nmom<M>();
+  constexpr int NL = NM > 4 * M ? NM : 4 * M;
   double *s_mom = sm;
-  double *s_prow = sm + NM;
-  double *s_lam = sm + NM + M + 1;
-  double *s_w = sm + NM + M + 1 + 4 * M;
+  double *s_lam = sm;
+  double *s_prow = sm + NL;
+  double *s_w = sm + NL + M + 1;
   const int64_t b = a.row_ptr[i];
   const int n = (int)(a.row_ptr[i + 1] - b);
   if (n < M) {
@@ -244,20 +268,26 @@ __device__ void weights_row_team(const WArgs &a, int32_t i, int lane, double *sm
   }
   RowGeom g;
   row_geom<M>(a, i, g);
-  // ---- pass 1: moments (the first kCacheW weights of each lane are kept in LDS)
+  // ---- pass 1: moments
   double mom[NM];
 #pragma unroll
   for (int p = 0; p < NM; ++p) mom[p] = 0.0;
-#pragma unroll 2
-  for (int k = lane; k < n; k += T) {
-    const int32_t j = a.col[b + k];
-    const double4 pj = a.pos[j];
-    const double dx = pj.x - g.xi, dy = pj.y - g.yi, dz = pj.z - g.zi;
-    const double w = nbr_weight_h<FASTW>(a, g, pj.w, dx, dy, dz);
-    if (k < kCacheW * T) s_w[k] = w;
-    double X, Y, Z;
-    local_xyz<M>(g, dx, dy, dz, X, Y, Z);
-    moments_add<M>(mom, w, X, Y, Z);
+  {
+    int32_t hn = (lane + T < n) ? fetch.idx(b + lane + T) : fetch.dummy;
+    double4 pc = fetch.get((lane < n) ? fetch.idx(b + lane) : fetch.dummy);
+#pragma unroll 1
+    for (int k = lane; k < n; k += T) {
+      const double4 pj = pc;
+      pc = fetch.get(hn);
+      hn = (k + 2 * T < n) ? fetch.idx(b + k + 2 * T) : fetch.dummy;
+      const double dx = pj.x - g.xi, dy = pj.y - g.yi, dz = pj.z - g.zi;
+      const double w = nbr_weight_h<FASTW>(a, g, pj.w, dx, dy, dz);
+      if constexpr (KC > 0)
+        if (k < KC * T) s_w[k] = w;
+      double X, Y, Z;
+      local_xyz<M>(g, dx, dy, dz, X, Y, Z);
+      moments_add<M>(mom, w, X, Y, Z);
+    }
   }
 #pragma unroll
   for (int p = 0; p < NM; ++p) mom[p] = team_sum(mom[p], T);
@@ -360,40 +390,47 @@ __device__ void weights_row_team(const WArgs &a, int32_t i, int lane, double *sm
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   double ui = 0.0;
   if constexpr (FUSED) ui = a.u[i];
-  auto emit = [&](int k, int32_t j, double w, double dx, double dy, double dz) {
-    double X, Y, Z, phi[M];
-    local_xyz<M>(g, dx, dy, dz, X, Y, Z);
-    basis<M>(X, Y, Z, phi);
-    double c[4];
+  {
+    int32_t hn = (lane + T < n) ? fetch.idx(b + lane + T) : fetch.dummy;
+    double4 pc = fetch.get((lane < n) ? fetch.idx(b + lane) : fetch.dummy);
+#pragma unroll 1
+    for (int k = lane; k < n; k += T) {
+      const double4 pj = pc;
+      pc = fetch.get(hn);
+      hn = (k + 2 * T < n) ? fetch.idx(b + k + 2 * T) : fetch.dummy;
+      const double dx = pj.x - g.xi, dy = pj.y - g.yi, dz = pj.z - g.zi;
+      double w;
+      if constexpr (KC > 0)
+        w = (k < KC * T) ? s_w[k] : nbr_weight_h<FASTW>(a, g, pj.w, dx, dy, dz);
+      else
+        w = nbr_weight_h<FASTW>(a, g, pj.w, dx, dy, dz);
+      double X, Y, Z, phi[M];
+      local_xyz<M>(g, dx, dy, dz, X, Y, Z);
+      basis<M>(X, Y, Z, phi);
+      double c[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      double t = 0.0;
+      for (int s = 0; s < 4; ++s) {
+        double t = 0.0;
 #pragma unroll
-      for (int q = 0; q < M; ++q) t += phi[q] * lam[s * M + q];
-      c[s] = w * t;
-    }
-    if constexpr (M == 6) {
-      const double cu = c[0], cv = c[1];
-      c[0] = g.t1[0] * cu + g.t2[0] * cv;
-      c[1] = g.t1[1] * cu + g.t2[1] * cv;
-      c[2] = g.t1[2] * cu + g.t2[2] * cv;
-    }
-    if (a.w_out) store_w<OUT>(a.w_out, b + k, c[0], c[1], c[2], c[3]);
-    if constexpr (FUSED) {
-      if (j != i) {
-        const double du = a.u[j] - ui;
+        for (int q = 0; q < M; ++q) t += phi[q] * lam[s * M + q];
+        c[s] = w * t;
+      }
+      if constexpr (M == 6) {
+        const double cu = c[0], cv = c[1];
+        c[0] = g.t1[0] * cu + g.t2[0] * cv;
+        c[1] = g.t1[1] * cu + g.t2[1] * cv;
+        c[2] = g.t1[2] * cu + g.t2[2] * cv;
+      }
+      if (a.w_out) store_w<OUT>(a.w_out, b + k, c[0], c[1], c[2], c[3]);
+      if constexpr (FUSED) {
+        const int32_t j = a.col[b + k];
+        if (j != i) {
+          const double du = a.u[j] - ui;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) acc[s] += ((OUT == GF_F32) ? (double)(float)c[s] : c[s]) * du;
+          for (int s = 0; s < 4; ++s) acc[s] += ((OUT == GF_F32) ? (double)(float)c[s] : c[s]) * du;
+        }
       }
     }
-  };
-#pragma unroll 2
-  for (int k = lane; k < n; k += T) {
-    const int32_t j = a.col[b + k];
-    const double4 pj = a.pos[j];
-    const double dx = pj.x - g.xi, dy = pj.y - g.yi, dz = pj.z - g.zi;
-    const double w = (k < kCacheW * T) ? s_w[k] : nbr_weight_h<FASTW>(a, g, pj.w, dx, dy, dz);
-    emit(k, j, w, dx, dy, dz);
   }
   if constexpr (FUSED) {
 #pragma unroll
@@ -403,15 +440,54 @@ __device__ void weights_row_team(const WArgs &a, int32_t i, int lane, double *sm
   if (lane == 0 && a.status) a.status[i] = 0;
 }
 
+// Untiled batched kernel (rows with more than kTileBandRow neighbours):
+// positions gathered from the packed array, weights of the first
+// kCacheW x T neighbours cached in LDS between the passes.
+constexpr int kCacheW = 8;
+
 template <int M, int T, int OUT, bool FUSED, bool FASTW>
 __global__ void __launch_bounds__(kBlock) k_weights_team(WArgs a) {
-  __shared__ double smem[(kBlock / T) * team_lds_doubles<M>(T)];
+  __shared__ double smem[(kBlock / T) * team_lds_doubles<M>(T, kCacheW)];
   const int64_t gt = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int64_t team = gt / T;
   const int lane = (int)(gt % T);
   if (team >= a.nrows) return;
-  double *sm = smem + (threadIdx.x / T) * team_lds_doubles<M>(T);
-  weights_row_team<M, T, OUT, FUSED, FASTW>(a, a.sched[team], lane, sm);
+  double *sm = smem + (threadIdx.x / T) * team_lds_doubles<M>(T, kCacheW);
+  const int32_t i = a.sched[team];
+  weights_row_team<M, T, OUT, FUSED, FASTW, kCacheW>(a, i, lane, sm, FetchGlobal{a.pos, a.col, i});
+}
+
+// Tiled batched kernel: one block per neighbour tile (kTileRows rows, one
+// team each).  The block stages the tile's distinct neighbour positions in
+// LDS (at most cap of them; a larger tile reads them from global memory)
+// and both passes address them through slot[].
+struct TileArgs {
+  const int64_t *off;  // tile list offsets (global tile ids)
+  const int32_t *u;    // tile lists
+  int64_t tile0;       // first tile of the group
+  int cap;             // LDS capacity in positions
+};
+
+template <int M, int T, int OUT, bool FUSED, bool FASTW>
+__global__ void __launch_bounds__(kTileRows * T) __attribute__((amdgpu_waves_per_eu(3)))
+k_weights_tile(WArgs a, TileArgs ta, const uint16_t *__restrict__ slot) {
+  extern __shared__ double4 s_dyn[];
+  const int64_t tl = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t u0 = ta.off[ta.tile0 + tl];
+  const int cnt = (int)(ta.off[ta.tile0 + tl + 1] - u0);
+  const bool staged = cnt <= ta.cap;
+  if (staged)
+    for (int s = threadIdx.x; s < cnt; s += blockDim.x) s_dyn[s] = a.pos[ta.u[u0 + s]];
+  __syncthreads();
+  const int team = threadIdx.x / T, lane = threadIdx.x % T;
+  const int64_t r = tl * kTileRows + team;
+  if (r >= a.nrows) return;
+  double *sm = reinterpret_cast<double *>(s_dyn + ta.cap) + team * team_lds_doubles<M>(T, 0);
+  const int32_t i = a.sched[r];
+  if (staged)
+    weights_row_team<M, T, OUT, FUSED, FASTW, 0>(a, i, lane, sm, FetchTile{s_dyn, slot, 0});
+  else
+    weights_row_team<M, T, OUT, FUSED, FASTW, 0>(a, i, lane, sm, FetchGlobal{a.pos, a.col, i});
 }
 
 __global__ void __launch_bounds__(kBlock) k_weights_plain(WArgs a) {
@@ -647,6 +723,30 @@ gf_status launch_team(gf_ctx *ctx, const WArgs &a, int T, const char *name) {
   return GF_OK;
 }
 
+// LDS positions a tile block may stage (larger tiles read global memory)
+constexpr int kTileCap = 1024;
+
+template <int M, int OUT, bool FUSED, bool FASTW>
+gf_status launch_tile(gf_ctx *ctx, const WArgs &a, const gf_nbr *nbr, int gsel, int T, const char *name) {
+  ProfScope prof(ctx, name);
+  TileArgs ta;
+  ta.off = nbr->tile_off;
+  ta.u = nbr->tile_u;
+  ta.tile0 = nbr->tile_start[gsel];
+  ta.cap = std::min(nbr->tile_max[gsel], kTileCap);
+  const int64_t ntl = nbr->tile_start[gsel + 1] - nbr->tile_start[gsel];
+  const size_t lds = sizeof(double4) * ta.cap + sizeof(double) * kTileRows * team_lds_doubles<M>(T, 0);
+  const dim3 grid(grid_for(ntl, 1)), block(kTileRows * T);
+  switch (T) {
+    case 4: hipLaunchKernelGGL((k_weights_tile<M, 4, OUT, FUSED, FASTW>), grid, block, lds, ctx->stream, a, ta, nbr->slot); break;
+    case 8: hipLaunchKernelGGL((k_weights_tile<M, 8, OUT, FUSED, FASTW>), grid, block, lds, ctx->stream, a, ta, nbr->slot); break;
+    case 16: hipLaunchKernelGGL((k_weights_tile<M, 16, OUT, FUSED, FASTW>), grid, block, lds, ctx->stream, a, ta, nbr->slot); break;
+    default: return set_error(ctx, GF_EINVAL, "unsupported team size %d", T);
+  }
+  GF_LAUNCH_CHECK(ctx);
+  return GF_OK;
+}
+
 // one launch per non-empty (model, band) group; only_group >= 0 restricts
 // the launches to that group and team_override > 0 replaces its team size
 // (used by the autotuner)
@@ -662,8 +762,14 @@ gf_status launch_batched(gf_ctx *ctx, const gf_nbr *nbr, WArgs a, int only_group
       a.nrows = s1 - s0;
       const int T = team_override > 0 ? team_override : ctx->wteam[m][band];
       const char *name = team_kernel_name(m, band, FUSED);
-      gf_status st = (m == 0) ? launch_team<10, OUT, FUSED, FASTW>(ctx, a, T, name)
-                              : launch_team<6, OUT, FUSED, FASTW>(ctx, a, T, name);
+      const bool tiled = band_tiled(band) && nbr->tile_start[gsel + 1] > nbr->tile_start[gsel];
+      gf_status st;
+      if (tiled)
+        st = (m == 0) ? launch_tile<10, OUT, FUSED, FASTW>(ctx, a, nbr, gsel, T, name)
+                      : launch_tile<6, OUT, FUSED, FASTW>(ctx, a, nbr, gsel, T, name);
+      else
+        st = (m == 0) ? launch_team<10, OUT, FUSED, FASTW>(ctx, a, T, name)
+                      : launch_team<6, OUT, FUSED, FASTW>(ctx, a, T, name);
       if (st) return st;
     }
   }
