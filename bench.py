@@ -5,9 +5,11 @@ Metric: particles/s for GFDM stencil weights + application (all four
 stencils d/dx, d/dy, d/dz, Laplacian applied to one scalar field), on the
 mixed bulk/film cloud of 503,944 particles (258,944 jittered-lattice bulk
 particles beside 245,000 film particles on z = 0, h = 3 x local spacing).
-value = N / (t_weights + t_apply) for the batched path with FP32 stencil
-storage (FP64 Gram solves, QR fallback); the plain FP64 path, the fused
-weights+apply call and the other steps of the hot path are timed beside it.
+value = N / t_step for the batched path: one gf_gfdm_weights_apply call that
+computes every stencil (FP64 moments and solves, QR fallback), stores it in
+FP32 and applies it to the field.  The same work as two calls (weights, then
+apply), the plain FP64 path and the other steps of the hot path are timed
+beside it.
 
 A step is one weights + apply pass over the resident cloud; K steps are timed
 with HIP events on the library's stream after W warm-up steps.  The FP64 CPU
@@ -79,12 +81,13 @@ def band_of(n):
     return len(BANDS)
 
 
-def algorithmic_costs(rp, model):
+def algorithmic_costs(rp, model, fused):
     """Per (model, band) launch of the stencil kernels: rows, nnz, FP64 flops
     and unique bytes of the FP32-output path.
     flops/row: Gram n m(m+1) + weighted monomials n m + targets 8 n m
-               + factorisation and inverse ~ m^3/3 + 2 m^3
-    bytes/row: 4 n (indices) + 16 n (FP32 stencils) + 32 (own x, y, z, h)."""
+               + factorisation and inverse ~ m^3/3 + 2 m^3 (+ 8 n applied)
+    bytes/row: 2 n (tile slots) + 16 n (FP32 stencils) + 32 (own x, y, z, h)
+               (+ 8 field value + 32 four results when fused)."""
     import numpy as np
     n_i = np.diff(rp)
     out = {}
@@ -95,8 +98,9 @@ def algorithmic_costs(rp, model):
             nn = n_i[(model == m) & (bands == b)]
             if nn.size == 0:
                 continue
-            flops = float((nn * (M * (M + 1) + M + 8 * M)).sum() + nn.size * (M ** 3 / 3 + 2 * M ** 3))
-            byts = float((20 * nn + 32).sum())
+            flops = float((nn * (M * (M + 1) + M + 8 * M + (8 if fused else 0))).sum()
+                          + nn.size * (M ** 3 / 3 + 2 * M ** 3))
+            byts = float((18 * nn + (72 if fused else 32)).sum())
             out[(m, b)] = dict(rows=int(nn.size), nnz=int(nn.sum()), flops=flops, bytes=byts)
     return out
 
@@ -175,7 +179,8 @@ def main():
     print(f"[bench] autotune {time.perf_counter() - t0:.2f}s: {teams}", file=sys.stderr, flush=True)
 
     if args.profile_only:
-        timed(step_batched, max(args.steps, 1), args.warmup)
+        timed(step_fused, max(args.steps, 1), args.warmup)
+        timed(step_batched, 2, 1)
         timed(step_plain, 2, 1)
         # a plain device copy of known size: calibrates the HBM byte counters
         # (FETCH_SIZE / WRITE_SIZE) read by rocprofv3 for the same run
@@ -187,28 +192,31 @@ def main():
               file=sys.stderr, flush=True)
         return
 
+    ms_fused = timed(step_fused, args.steps, args.warmup)
     ms_batched = timed(step_batched, args.steps, args.warmup)
     ms_plain = timed(step_plain, args.steps, args.warmup)
-    ms_fused = timed(step_fused, args.steps, args.warmup)
-    print(f"[bench] batched {ms_batched:.3f} ms  plain {ms_plain:.3f} ms  fused {ms_fused:.3f} ms",
+    print(f"[bench] fused {ms_fused:.3f} ms  separate calls {ms_batched:.3f} ms  plain {ms_plain:.3f} ms",
           file=sys.stderr, flush=True)
 
     # per-kernel times of the metric step (HIP events around each launch)
     ctx.profile(True)
     reps = max(3, min(args.steps, 10))
     for _ in range(reps):
-        step_batched()
+        step_fused()
     prof = ctx.profile_read()
+    for _ in range(reps):
+        step_batched()
+    prof_sep = ctx.profile_read()
     for _ in range(reps):
         step_plain()
     prof_plain = ctx.profile_read()
     ctx.profile(False)
-    costs = algorithmic_costs(rp, d["model"])
+    costs = algorithmic_costs(rp, d["model"], fused=True)
     kernels = {}
     for name, (cnt, tot) in prof.items():
         kernels[name] = {"launches": cnt, "avg_us": 1000.0 * tot / cnt}
     # dominant kernel: the (model, band) stencil launch with the largest time
-    weights_kernels = {k: v for k, v in kernels.items() if k.startswith("weights_") and "qr" not in k}
+    weights_kernels = {k: v for k, v in kernels.items() if k.startswith("weights_apply_")}
     dom = max(weights_kernels, key=lambda k: weights_kernels[k]["avg_us"] * weights_kernels[k]["launches"])
     m_dom = 0 if "_3d_" in dom else 1
     b_dom = int(dom.rsplit("_b", 1)[1])
@@ -236,24 +244,30 @@ def main():
     roof["algorithmic_per_launch"] = {"flops": flops_l, "bytes": bytes_l, "avg_launch_us": round(per_launch_s * 1e6, 2),
                                       "rows": costs[(m_dom, b_dom)]["rows"], "nnz": costs[(m_dom, b_dom)]["nnz"]}
 
-    # whole-step HBM view: unique bytes of weights + apply (FP32 stencils)
-    step_bytes = float(nnz) * (4 + 16) + N * 32 + float(nnz) * (4 + 16) + N * (8 + 32)
-    step_hbm_frac = step_bytes / (ms_batched * 1e-3) / 1e9 / PEAK_HBM_GBS
+    # whole-step HBM view: unique bytes of the fused step (slots, FP32
+    # stencils written, positions, field, four results)
+    step_bytes = float(nnz) * (2 + 16) + N * (32 + 8 + 32)
+    step_hbm_frac = step_bytes / (ms_fused * 1e-3) / 1e9 / PEAK_HBM_GBS
 
-    # ---- accuracy of the FP32 path against the FP64 plain path on the device
-    step_batched(); step_plain()
+    # ---- outputs of the metric step (stencils stored by the fused call and
+    # its results), of the separate calls, and of the plain FP64 path
+    step_batched()
+    torch.cuda.synchronize()
+    y32n = y32.cpu().numpy()
+    step_fused(); step_plain()
     torch.cuda.synchronize()
     w32n = w32.double().cpu().numpy()
     w64n = w64.cpu().numpy()
+    yfn = yf.cpu().numpy()
 
     result = {
         "metric": "particles/s for GFDM weights+apply; batched-FP32 vs plain-FP64 @1e-6 rel err",
-        "value": N / (ms_batched * 1e-3),
+        "value": N / (ms_fused * 1e-3),
         "unit": "particles/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_batched,
+        "ms_per_step": ms_fused,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -263,12 +277,16 @@ def main():
         "config": {"workload": "mixed bulk/film cloud: 258,944 jittered-lattice bulk particles beside "
                                "245,000 film particles on z=0, h = 3 x spacing (10 / 6 monomials)",
                    "n_particles": N, "nnz": nnz, "factor": args.factor},
-        "plain_f64": {"value": N / (ms_plain * 1e-3), "ms_per_step": ms_plain},
-        "fused_weights_apply_f32": {"value": N / (ms_fused * 1e-3), "ms_per_step": ms_fused},
-        "speedup_batched_vs_plain": ms_plain / ms_batched,
+        "step": "gf_gfdm_weights_apply: batched stencils stored in FP32 and applied (one call)",
+        "plain_f64": {"value": N / (ms_plain * 1e-3), "ms_per_step": ms_plain,
+                      "step": "gf_gfdm_weights(GF_PLAIN_F64) + gf_apply_stencil"},
+        "separate_calls_f32": {"value": N / (ms_batched * 1e-3), "ms_per_step": ms_batched,
+                               "step": "gf_gfdm_weights(GF_BATCHED, FP32) + gf_apply_stencil"},
+        "speedup_batched_vs_plain": ms_plain / ms_fused,
         "team_sizes": teams,
         "step_hbm_frac": round(step_hbm_frac, 4),
         "kernels_batched": kernels,
+        "kernels_separate_calls": {k: {"launches": c, "avg_us": 1000.0 * t / c} for k, (c, t) in prof_sep.items()},
         "kernels_plain": {k: {"launches": c, "avg_us": 1000.0 * t / c} for k, (c, t) in prof_plain.items()},
         "roofline": roof,
     }
@@ -345,11 +363,11 @@ def main():
                                   "sample": f"all {N} particles of the workload, weights + apply, mean of "
                                             f"{passes} passes ({t_o:.2f} s each; neighbour search "
                                             f"{t_nbr_o:.1f} s not included)"}
-        y32n = y32.cpu().numpy()
         result["operator_error"] = {
             "batched_f32_max": float(e32.max()), "batched_f32_p9999": float(np.quantile(e32, 0.9999)),
             "plain_f64_max": float(e64.max()),
-            "apply_f32_max_abs_rel": float(np.max(np.abs(y32n - y_o)) / np.max(np.abs(y_o))),
+            "fused_apply_max_abs_rel": float(np.max(np.abs(yfn - y_o)) / np.max(np.abs(y_o))),
+            "separate_apply_max_abs_rel": float(np.max(np.abs(y32n - y_o)) / np.max(np.abs(y_o))),
         }
         print(f"[bench] oracle {t_o:.1f}s; f32 err max {e32.max():.2e}, f64 err max {e64.max():.2e}",
               file=sys.stderr, flush=True)

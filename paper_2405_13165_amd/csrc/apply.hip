@@ -64,6 +64,70 @@ __global__ void __launch_bounds__(kBlock) k_apply(const int32_t *__restrict__ sc
   }
 }
 
+// Tiled application (rows of the tiled bands): one block per neighbour tile;
+// the field values of the tile's distinct neighbours are staged in LDS and
+// each entry reads its value through slot[] (2 bytes) instead of col[]
+// (4 bytes) plus a gather.  The diagonal entry contributes u_i - u_i = 0.
+template <int T, typename WT, typename IOT>
+__global__ void __launch_bounds__(kTileRows * T) k_apply_tile(const int32_t *__restrict__ sched, int64_t nrows,
+                                                              const int64_t *__restrict__ row_ptr,
+                                                              const int32_t *__restrict__ col,
+                                                              const uint16_t *__restrict__ slot,
+                                                              const int64_t *__restrict__ toff,
+                                                              const int32_t *__restrict__ tu, int64_t tile0, int cap,
+                                                              const void *__restrict__ w, unsigned mask,
+                                                              const IOT *__restrict__ u, IOT *__restrict__ out,
+                                                              int64_t n) {
+  extern __shared__ double s_u[];
+  const int64_t tl = xcd_block(blockIdx.x, gridDim.x);
+  const int team = threadIdx.x / T, lane = threadIdx.x % T;
+  const int64_t r = tl * kTileRows + team;
+  // row prologue first: its loads overlap the staging below
+  const bool live = r < nrows;
+  const int32_t i = live ? sched[r] : 0;
+  const int64_t b = live ? row_ptr[i] : 0, e = live ? row_ptr[i + 1] : 0;
+  const double ui = (double)u[i];
+  const int64_t u0 = toff[tile0 + tl];
+  const int cnt = (int)(toff[tile0 + tl + 1] - u0);
+  const bool staged = cnt <= cap;
+  if (staged)
+    for (int s = threadIdx.x; s < cnt; s += blockDim.x) s_u[s] = (double)u[tu[u0 + s]];
+  __syncthreads();
+  if (!live) return;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (staged) {
+#pragma unroll 4
+    for (int64_t k = b + lane; k < e; k += T) {
+      double c[4];
+      W4<WT>::load(w, k, c);
+      const double du = s_u[slot[k]] - ui;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc[s] += c[s] * du;
+    }
+  } else {
+    for (int64_t k = b + lane; k < e; k += T) {
+      double c[4];
+      W4<WT>::load(w, k, c);
+      const double du = (double)u[col[k]] - ui;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc[s] += c[s] * du;
+    }
+  }
+  if constexpr (T > 1) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc[s] = team_sum(acc[s], T);
+  }
+  if (lane == 0) {
+    int q = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      if (mask & (1u << s)) out[(int64_t)(q++) * n + i] = (IOT)acc[s];
+  }
+}
+
+// field values a tiled apply block may stage
+constexpr int kApplyCap = 2048;
+
 // ubar_j = sum_{i : j in S_i, i != j} c_ij ybar_i - ybar_j sum_{k in S_j, k != j} c_jk,
 // the first sum gathered through the reverse-edge map (entry (i,j) sits at
 // rev[k] for the entry k = (j,i) of row j).
@@ -106,6 +170,24 @@ gf_status launch_apply(gf_ctx *ctx, const gf_nbr *nbr, const void *w, unsigned m
     const IOT *uu = (const IOT *)u;
     IOT *oo = (IOT *)out;
     ProfScope prof(ctx, gsel < GF_NBAND ? "apply_3d" : "apply_film");
+    const int64_t t0 = nbr->tile_start[gsel], ntl = nbr->tile_start[gsel + 1] - t0;
+    if (band_tiled(gsel % GF_NBAND) && ntl > 0) {
+      const int cap = std::min(nbr->tile_max[gsel], kApplyCap);
+      const dim3 tgrid(grid_for(ntl, 1)), tblock(kTileRows * std::min(T, 32));
+      const size_t lds = sizeof(double) * cap;
+#define GF_APPLY_TILE(TT)                                                                                           \
+  hipLaunchKernelGGL((k_apply_tile<TT, WT, IOT>), tgrid, tblock, lds, ctx->stream, sched, s1 - s0, nbr->row_ptr,   \
+                     nbr->col, nbr->slot, nbr->tile_off, nbr->tile_u, t0, cap, w, mask, uu, oo, nbr->n)
+      switch (std::min(T, 32)) {
+        case 4: GF_APPLY_TILE(4); break;
+        case 8: GF_APPLY_TILE(8); break;
+        case 16: GF_APPLY_TILE(16); break;
+        default: GF_APPLY_TILE(32); break;
+      }
+#undef GF_APPLY_TILE
+      GF_LAUNCH_CHECK(ctx);
+      continue;
+    }
     switch (T) {
       case 4: hipLaunchKernelGGL((k_apply<4, WT, IOT>), grid, block, 0, ctx->stream, sched, s1 - s0, nbr->row_ptr, nbr->col, w, mask, uu, oo, nbr->n); break;
       case 8: hipLaunchKernelGGL((k_apply<8, WT, IOT>), grid, block, 0, ctx->stream, sched, s1 - s0, nbr->row_ptr, nbr->col, w, mask, uu, oo, nbr->n); break;

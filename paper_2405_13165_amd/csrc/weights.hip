@@ -190,12 +190,17 @@ struct GramTable {
 __constant__ GramTable<10> kGram3 = GramTable<10>();
 __constant__ GramTable<6> kGram2 = GramTable<6>();
 
-// Per-team LDS (doubles): moments, later the scaled target solutions (the
-// two are never live together), the pivot row, and KC cached support
-// weights per lane.
+// lanes of a team that take part in the moment transpose-reduction
+__host__ __device__ constexpr int red_lanes(int T) { return T < 8 ? T : 8; }
+
+__host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+// Per-team LDS (doubles): one area that holds in turn the reduction buffer,
+// the moments and the scaled target solutions; the pivot row; KC cached
+// support weights per lane.
 template <int M>
 constexpr int team_lds_doubles(int T, int KC) {
-  return (nmom<M>() > 4 * M ? nmom<M>() : 4 * M) + M + 1 + KC * T;
+  return cmax(cmax(nmom<M>(), 4 * M), red_lanes(T) * red_lanes(T)) + M + 1 + KC * T;
 }
 
 // orders the LDS traffic of the lanes of one wave around a hand-off
@@ -215,21 +220,57 @@ __device__ inline double nbr_weight_h(const WArgs &a, const RowGeom &g, double h
 
 // Where a row finds the (x, y, z, h) of its neighbours.  idx(e) reads the
 // handle of CSR entry e, get(handle) the position; `dummy` is a valid handle
-// used for the loads issued past the end of a row.
+// used for the loads issued past the end of a row.  kDeep: the position
+// itself is also loaded one neighbour ahead (worth it for global gathers).
 struct FetchGlobal {  // packed positions, gathered through col[]
+  static constexpr bool kDeep = true;
   const double4 *pos;
   const int32_t *col;
+  const double *u;     // field of the fused application
   int32_t dummy;
   __device__ int32_t idx(int64_t e) const { return col[e]; }
   __device__ double4 get(int32_t j) const { return pos[j]; }
+  __device__ double field(int32_t j) const { return u[j]; }
 };
-struct FetchTile {    // the tile's positions staged in LDS, addressed by slot[]
+struct FetchTile {    // the tile's positions (and field) staged in LDS, addressed by slot[]
+  static constexpr bool kDeep = false;
   const double4 *sp;
   const uint16_t *slot;
+  const double *su;
   int32_t dummy;
   __device__ int32_t idx(int64_t e) const { return slot[e]; }
   __device__ double4 get(int32_t s) const { return sp[s]; }
+  __device__ double field(int32_t s) const { return su[s]; }
 };
+
+// Visit the neighbours k = lane, lane + T, ... of the row starting at CSR
+// entry b, calling body(k, position, handle) with the loads software-pipelined.
+template <int T, class F, class Body>
+__device__ inline void for_neighbours(const F &fetch, int64_t b, int n, int lane, Body &&body) {
+  if constexpr (F::kDeep) {
+    int32_t hc = (lane < n) ? fetch.idx(b + lane) : fetch.dummy;
+    int32_t hn = (lane + T < n) ? fetch.idx(b + lane + T) : fetch.dummy;
+    double4 pc = fetch.get(hc);
+#pragma unroll 1
+    for (int k = lane; k < n; k += T) {
+      const double4 pj = pc;
+      const int32_t h = hc;
+      hc = hn;
+      pc = fetch.get(hn);
+      hn = (k + 2 * T < n) ? fetch.idx(b + k + 2 * T) : fetch.dummy;
+      body(k, pj, h);
+    }
+  } else {
+    int32_t hc = (lane < n) ? fetch.idx(b + lane) : fetch.dummy;
+#pragma unroll 1
+    for (int k = lane; k < n; k += T) {
+      const double4 pj = fetch.get(hc);
+      const int32_t h = hc;
+      hc = (k + T < n) ? fetch.idx(b + k + T) : fetch.dummy;
+      body(k, pj, h);
+    }
+  }
+}
 
 // Moment-based team path.  Per particle, a team of T lanes of one wave:
 //  pass 1  each lane accumulates the weighted moments sum w X^a Y^b Z^c
@@ -247,10 +288,13 @@ template <int M, int T, int OUT, bool FUSED, bool FASTW, int KC, class F>
 __device__ void weights_row_team(const WArgs &a, int32_t i, int lane, double *sm, const F &fetch) {
   constexpr int NM = nmom<M>();
   constexpr int NL = NM > 4 * M ? NM : 4 * M;
+  constexpr int R8 = red_lanes(T);
+  constexpr int NA = cmax(NL, R8 * R8);
+  double *s_red = sm;
   double *s_mom = sm;
   double *s_lam = sm;
-  double *s_prow = sm + NL;
-  double *s_w = sm + NL + M + 1;
+  double *s_prow = sm + NA;
+  double *s_w = sm + NA + M + 1;
   const int64_t b = a.row_ptr[i];
   const int n = (int)(a.row_ptr[i + 1] - b);
   if (n < M) {
@@ -272,29 +316,44 @@ __device__ void weights_row_team(const WArgs &a, int32_t i, int lane, double *sm
   double mom[NM];
 #pragma unroll
   for (int p = 0; p < NM; ++p) mom[p] = 0.0;
+  for_neighbours<T>(fetch, b, n, lane, [&](int k, const double4 &pj, int32_t) {
+    const double dx = pj.x - g.xi, dy = pj.y - g.yi, dz = pj.z - g.zi;
+    const double w = nbr_weight_h<FASTW>(a, g, pj.w, dx, dy, dz);
+    if constexpr (KC > 0)
+      if (k < KC * T) s_w[k] = w;
+    double X, Y, Z;
+    local_xyz<M>(g, dx, dy, dz, X, Y, Z);
+    moments_add<M>(mom, w, X, Y, Z);
+  });
+  // ---- team sum of the moments: butterflies down to R8 lanes, then a
+  // transpose through LDS in chunks of R8 moments (lane m of the chunk adds
+  // the R8 partials of moment c R8 + m in lane order)
+#pragma unroll
+  for (int o = T / 2; o >= R8; o >>= 1)
+#pragma unroll
+    for (int p = 0; p < NM; ++p) mom[p] += __shfl_xor(mom[p], o, T);
   {
-    int32_t hn = (lane + T < n) ? fetch.idx(b + lane + T) : fetch.dummy;
-    double4 pc = fetch.get((lane < n) ? fetch.idx(b + lane) : fetch.dummy);
-#pragma unroll 1
-    for (int k = lane; k < n; k += T) {
-      const double4 pj = pc;
-      pc = fetch.get(hn);
-      hn = (k + 2 * T < n) ? fetch.idx(b + k + 2 * T) : fetch.dummy;
-      const double dx = pj.x - g.xi, dy = pj.y - g.yi, dz = pj.z - g.zi;
-      const double w = nbr_weight_h<FASTW>(a, g, pj.w, dx, dy, dz);
-      if constexpr (KC > 0)
-        if (k < KC * T) s_w[k] = w;
-      double X, Y, Z;
-      local_xyz<M>(g, dx, dy, dz, X, Y, Z);
-      moments_add<M>(mom, w, X, Y, Z);
+    constexpr int NC = (NM + R8 - 1) / R8;
+    const int l8 = lane % R8;
+    double res[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+#pragma unroll
+      for (int m = 0; m < R8; ++m)
+        if (c * R8 + m < NM) s_red[m * R8 + l8] = mom[c * R8 + m];
+      wave_sync();
+      double t = s_red[l8 * R8];
+#pragma unroll
+      for (int q = 1; q < R8; ++q) t += s_red[l8 * R8 + q];
+      res[c] = t;
+      wave_sync();
     }
+    // the buffer is free again: the moments take its place
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      if (c * R8 + l8 < NM) s_mom[c * R8 + l8] = res[c];
+    wave_sync();
   }
-#pragma unroll
-  for (int p = 0; p < NM; ++p) mom[p] = team_sum(mom[p], T);
-#pragma unroll
-  for (int p = 0; p < NM; ++p)
-    if (p % T == lane) s_mom[p] = mom[p];
-  wave_sync();
   // ---- Gauss-Jordan inversion of G; lane owns rows lane + q T (q < NR)
   constexpr int NR = (M + T - 1) / T;
   double row[NR][M];
@@ -390,48 +449,37 @@ __device__ void weights_row_team(const WArgs &a, int32_t i, int lane, double *sm
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   double ui = 0.0;
   if constexpr (FUSED) ui = a.u[i];
-  {
-    int32_t hn = (lane + T < n) ? fetch.idx(b + lane + T) : fetch.dummy;
-    double4 pc = fetch.get((lane < n) ? fetch.idx(b + lane) : fetch.dummy);
-#pragma unroll 1
-    for (int k = lane; k < n; k += T) {
-      const double4 pj = pc;
-      pc = fetch.get(hn);
-      hn = (k + 2 * T < n) ? fetch.idx(b + k + 2 * T) : fetch.dummy;
-      const double dx = pj.x - g.xi, dy = pj.y - g.yi, dz = pj.z - g.zi;
-      double w;
-      if constexpr (KC > 0)
-        w = (k < KC * T) ? s_w[k] : nbr_weight_h<FASTW>(a, g, pj.w, dx, dy, dz);
-      else
-        w = nbr_weight_h<FASTW>(a, g, pj.w, dx, dy, dz);
-      double X, Y, Z, phi[M];
-      local_xyz<M>(g, dx, dy, dz, X, Y, Z);
-      basis<M>(X, Y, Z, phi);
-      double c[4];
+  for_neighbours<T>(fetch, b, n, lane, [&](int k, const double4 &pj, int32_t h) {
+    const double dx = pj.x - g.xi, dy = pj.y - g.yi, dz = pj.z - g.zi;
+    double w;
+    if constexpr (KC > 0)
+      w = (k < KC * T) ? s_w[k] : nbr_weight_h<FASTW>(a, g, pj.w, dx, dy, dz);
+    else
+      w = nbr_weight_h<FASTW>(a, g, pj.w, dx, dy, dz);
+    double X, Y, Z, phi[M];
+    local_xyz<M>(g, dx, dy, dz, X, Y, Z);
+    basis<M>(X, Y, Z, phi);
+    double c[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        double t = 0.0;
+    for (int q = 0; q < M; ++q)
 #pragma unroll
-        for (int q = 0; q < M; ++q) t += phi[q] * lam[s * M + q];
-        c[s] = w * t;
-      }
-      if constexpr (M == 6) {
-        const double cu = c[0], cv = c[1];
-        c[0] = g.t1[0] * cu + g.t2[0] * cv;
-        c[1] = g.t1[1] * cu + g.t2[1] * cv;
-        c[2] = g.t1[2] * cu + g.t2[2] * cv;
-      }
-      if (a.w_out) store_w<OUT>(a.w_out, b + k, c[0], c[1], c[2], c[3]);
-      if constexpr (FUSED) {
-        const int32_t j = a.col[b + k];
-        if (j != i) {
-          const double du = a.u[j] - ui;
+      for (int s = 0; s < 4; ++s) c[s] += phi[q] * lam[s * M + q];
 #pragma unroll
-          for (int s = 0; s < 4; ++s) acc[s] += ((OUT == GF_F32) ? (double)(float)c[s] : c[s]) * du;
-        }
-      }
+    for (int s = 0; s < 4; ++s) c[s] *= w;
+    if constexpr (M == 6) {
+      const double cu = c[0], cv = c[1];
+      c[0] = g.t1[0] * cu + g.t2[0] * cv;
+      c[1] = g.t1[1] * cu + g.t2[1] * cv;
+      c[2] = g.t1[2] * cu + g.t2[2] * cv;
     }
-  }
+    if (a.w_out) store_w<OUT>(a.w_out, b + k, c[0], c[1], c[2], c[3]);
+    if constexpr (FUSED) {
+      // the diagonal entry contributes u_i - u_i = 0
+      const double du = fetch.field(h) - ui;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc[s] += ((OUT == GF_F32) ? (double)(float)c[s] : c[s]) * du;
+    }
+  });
   if constexpr (FUSED) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) acc[s] = team_sum(acc[s], T);
@@ -454,7 +502,7 @@ __global__ void __launch_bounds__(kBlock) k_weights_team(WArgs a) {
   if (team >= a.nrows) return;
   double *sm = smem + (threadIdx.x / T) * team_lds_doubles<M>(T, kCacheW);
   const int32_t i = a.sched[team];
-  weights_row_team<M, T, OUT, FUSED, FASTW, kCacheW>(a, i, lane, sm, FetchGlobal{a.pos, a.col, i});
+  weights_row_team<M, T, OUT, FUSED, FASTW, kCacheW>(a, i, lane, sm, FetchGlobal{a.pos, a.col, a.u, i});
 }
 
 // Tiled batched kernel: one block per neighbour tile (kTileRows rows, one
@@ -469,25 +517,31 @@ struct TileArgs {
 };
 
 template <int M, int T, int OUT, bool FUSED, bool FASTW>
-__global__ void __launch_bounds__(kTileRows * T) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(kTileRows * T) __attribute__((amdgpu_waves_per_eu(T >= 8 ? 3 : 1)))
 k_weights_tile(WArgs a, TileArgs ta, const uint16_t *__restrict__ slot) {
   extern __shared__ double4 s_dyn[];
   const int64_t tl = xcd_block(blockIdx.x, gridDim.x);
   const int64_t u0 = ta.off[ta.tile0 + tl];
   const int cnt = (int)(ta.off[ta.tile0 + tl + 1] - u0);
   const bool staged = cnt <= ta.cap;
-  if (staged)
-    for (int s = threadIdx.x; s < cnt; s += blockDim.x) s_dyn[s] = a.pos[ta.u[u0 + s]];
+  double *s_u = reinterpret_cast<double *>(s_dyn + ta.cap);  // fused field values (cap of them)
+  if (staged) {
+    for (int s = threadIdx.x; s < cnt; s += blockDim.x) {
+      const int32_t j = ta.u[u0 + s];
+      s_dyn[s] = a.pos[j];
+      if constexpr (FUSED) s_u[s] = a.u[j];
+    }
+  }
   __syncthreads();
   const int team = threadIdx.x / T, lane = threadIdx.x % T;
   const int64_t r = tl * kTileRows + team;
   if (r >= a.nrows) return;
-  double *sm = reinterpret_cast<double *>(s_dyn + ta.cap) + team * team_lds_doubles<M>(T, 0);
+  double *sm = s_u + (FUSED ? ta.cap : 0) + team * team_lds_doubles<M>(T, 0);
   const int32_t i = a.sched[r];
   if (staged)
-    weights_row_team<M, T, OUT, FUSED, FASTW, 0>(a, i, lane, sm, FetchTile{s_dyn, slot, 0});
+    weights_row_team<M, T, OUT, FUSED, FASTW, 0>(a, i, lane, sm, FetchTile{s_dyn, slot, s_u, 0});
   else
-    weights_row_team<M, T, OUT, FUSED, FASTW, 0>(a, i, lane, sm, FetchGlobal{a.pos, a.col, i});
+    weights_row_team<M, T, OUT, FUSED, FASTW, 0>(a, i, lane, sm, FetchGlobal{a.pos, a.col, a.u, i});
 }
 
 __global__ void __launch_bounds__(kBlock) k_weights_plain(WArgs a) {
@@ -735,7 +789,8 @@ gf_status launch_tile(gf_ctx *ctx, const WArgs &a, const gf_nbr *nbr, int gsel, 
   ta.tile0 = nbr->tile_start[gsel];
   ta.cap = std::min(nbr->tile_max[gsel], kTileCap);
   const int64_t ntl = nbr->tile_start[gsel + 1] - nbr->tile_start[gsel];
-  const size_t lds = sizeof(double4) * ta.cap + sizeof(double) * kTileRows * team_lds_doubles<M>(T, 0);
+  const size_t lds = (sizeof(double4) + (FUSED ? sizeof(double) : 0)) * ta.cap +
+                     sizeof(double) * kTileRows * team_lds_doubles<M>(T, 0);
   const dim3 grid(grid_for(ntl, 1)), block(kTileRows * T);
   switch (T) {
     case 4: hipLaunchKernelGGL((k_weights_tile<M, 4, OUT, FUSED, FASTW>), grid, block, lds, ctx->stream, a, ta, nbr->slot); break;
