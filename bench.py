@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E, GB/s
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector
-BANDS = (24, 48, 128)        # neighbour-count bands of the batched kernels
+BANDS = (24, 48, 128)        # neighbour-count bands of the batched kernels (bands 0-2 are tiled)
 
 
 def parse():
@@ -92,16 +92,17 @@ def algorithmic_costs(rp, model, fused):
     n_i = np.diff(rp)
     out = {}
     bands = np.searchsorted(np.array(BANDS), n_i, side="left")
+    # launch units: the tiled bands 0-2 of a model run as one launch ("tiles"), band 3 alone
     for m in (0, 1):
         M = 10 if m == 0 else 6
-        for b in range(len(BANDS) + 1):
-            nn = n_i[(model == m) & (bands == b)]
+        for unit, sel in (("tiles", bands <= 2), ("b3", bands == 3)):
+            nn = n_i[(model == m) & sel]
             if nn.size == 0:
                 continue
             flops = float((nn * (M * (M + 1) + M + 8 * M + (8 if fused else 0))).sum()
                           + nn.size * (M ** 3 / 3 + 2 * M ** 3))
             byts = float((18 * nn + (72 if fused else 32)).sum())
-            out[(m, b)] = dict(rows=int(nn.size), nnz=int(nn.sum()), flops=flops, bytes=byts)
+            out[(m, unit)] = dict(rows=int(nn.size), nnz=int(nn.sum()), flops=flops, bytes=byts)
     return out
 
 
@@ -219,7 +220,7 @@ def main():
     weights_kernels = {k: v for k, v in kernels.items() if k.startswith("weights_apply_")}
     dom = max(weights_kernels, key=lambda k: weights_kernels[k]["avg_us"] * weights_kernels[k]["launches"])
     m_dom = 0 if "_3d_" in dom else 1
-    b_dom = int(dom.rsplit("_b", 1)[1])
+    b_dom = dom.rsplit("_", 1)[1]
     per_launch_s = kernels[dom]["avg_us"] * 1e-6
     flops_l = costs[(m_dom, b_dom)]["flops"]
     bytes_l = costs[(m_dom, b_dom)]["bytes"]
@@ -233,7 +234,7 @@ def main():
     else:
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(frac_hbm, 4), "traffic": None}
-    team_dom = teams["weights"][4 * m_dom + b_dom]
+    team_dom = teams["weights"][4 * m_dom + (2 if b_dom == "tiles" else 3)]
     traffic, traffic_src = measured_traffic(dom, team_dom)
     roof["traffic"] = round(traffic) if traffic is not None else None
     if traffic is not None:

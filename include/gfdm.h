@@ -190,13 +190,16 @@ gf_status gf_gfdm_weights(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr,
 gf_status gf_apply_stencil(gf_ctx *ctx, const gf_nbr *nbr, gf_dtype wtype, const void *w,
                            unsigned op_mask, gf_dtype io, const void *u, void *out);
 
-/* Autotuner for the batched kernels.  For every (model, neighbour-count band)
- * group of nbr, times the stencil kernel (weights of type wtype) and the
- * application kernel with teams of 4, 8 and 16 lanes per particle (median of
+/* Autotuner for the batched kernels.  For every launch unit of nbr (per
+ * model: the tiled rows with at most 128 neighbours, and the rows with more),
+ * times the stencil kernel (weights of type wtype) with teams of 4, 8 and 16
+ * lanes per particle and the application kernel with 4..64 lanes (median of
  * three runs each) and keeps the fastest team size in ctx; later calls on ctx
  * use it.  Allocates temporary buffers and synchronises.  team_out (host,
- * may be NULL) receives 16 ints: the chosen stencil team sizes of the groups
- * (bulk bands 0-3, film bands 0-3), then those of the application kernel. */
+ * may be NULL) receives 16 ints indexed by (model, band): the stencil team
+ * sizes (bulk bands 0-3, film bands 0-3; the tiled unit of a model reports
+ * in band 2, bands 0-1 keep their previous values), then those of the
+ * application kernel in the same layout. */
 gf_status gf_autotune(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr, gf_dtype wtype, int *team_out);
 
 /* Weights and application in one pass: computes the stencils exactly as

@@ -159,25 +159,25 @@ __global__ void __launch_bounds__(kBlock) k_apply_adjoint(const int64_t *__restr
 
 template <typename WT, typename IOT>
 gf_status launch_apply(gf_ctx *ctx, const gf_nbr *nbr, const void *w, unsigned mask, const void *u, void *out,
-                       int only_group = -1, int team_override = 0) {
-  for (int gsel = 0; gsel < 2 * GF_NBAND; ++gsel) {
-    if (only_group >= 0 && gsel != only_group) continue;
-    const int64_t s0 = nbr->group_start[gsel], s1 = nbr->group_start[gsel + 1];
-    if (s1 <= s0) continue;
-    const int T = team_override > 0 ? team_override : ctx->ateam[gsel / GF_NBAND][gsel % GF_NBAND];
-    const dim3 grid(grid_for((s1 - s0) * T, kBlock)), block(kBlock);
-    const int32_t *sched = nbr->grouped + s0;
-    const IOT *uu = (const IOT *)u;
-    IOT *oo = (IOT *)out;
-    ProfScope prof(ctx, gsel < GF_NBAND ? "apply_3d" : "apply_film");
-    const int64_t t0 = nbr->tile_start[gsel], ntl = nbr->tile_start[gsel + 1] - t0;
-    if (band_tiled(gsel % GF_NBAND) && ntl > 0) {
-      const int cap = std::min(nbr->tile_max[gsel], kApplyCap);
-      const dim3 tgrid(grid_for(ntl, 1)), tblock(kTileRows * std::min(T, 32));
+                       int only_unit = -1, int team_override = 0) {
+  LaunchUnit units[2 * GF_NBAND];
+  const int nu = launch_units(nbr, units);
+  const IOT *uu = (const IOT *)u;
+  IOT *oo = (IOT *)out;
+  for (int q = 0; q < nu; ++q) {
+    if (only_unit >= 0 && q != only_unit) continue;
+    const LaunchUnit &lu = units[q];
+    const int T = team_override > 0 ? team_override : ctx->ateam[lu.model][lu.band];
+    const int32_t *sched = nbr->grouped + lu.row0;
+    const int64_t nrows = lu.nrows;
+    ProfScope prof(ctx, lu.model == 0 ? "apply_3d" : "apply_film");
+    if (lu.tiled) {
+      const int cap = std::min(lu.tile_max, kApplyCap);
+      const dim3 tgrid(grid_for(lu.ntiles, 1)), tblock(kTileRows * std::min(T, 32));
       const size_t lds = sizeof(double) * cap;
 #define GF_APPLY_TILE(TT)                                                                                           \
-  hipLaunchKernelGGL((k_apply_tile<TT, WT, IOT>), tgrid, tblock, lds, ctx->stream, sched, s1 - s0, nbr->row_ptr,   \
-                     nbr->col, nbr->slot, nbr->tile_off, nbr->tile_u, t0, cap, w, mask, uu, oo, nbr->n)
+  hipLaunchKernelGGL((k_apply_tile<TT, WT, IOT>), tgrid, tblock, lds, ctx->stream, sched, nrows, nbr->row_ptr,      \
+                     nbr->col, nbr->slot, nbr->tile_off, nbr->tile_u, lu.tile0, cap, w, mask, uu, oo, nbr->n)
       switch (std::min(T, 32)) {
         case 4: GF_APPLY_TILE(4); break;
         case 8: GF_APPLY_TILE(8); break;
@@ -188,12 +188,13 @@ gf_status launch_apply(gf_ctx *ctx, const gf_nbr *nbr, const void *w, unsigned m
       GF_LAUNCH_CHECK(ctx);
       continue;
     }
+    const dim3 grid(grid_for(nrows * T, kBlock)), block(kBlock);
     switch (T) {
-      case 4: hipLaunchKernelGGL((k_apply<4, WT, IOT>), grid, block, 0, ctx->stream, sched, s1 - s0, nbr->row_ptr, nbr->col, w, mask, uu, oo, nbr->n); break;
-      case 8: hipLaunchKernelGGL((k_apply<8, WT, IOT>), grid, block, 0, ctx->stream, sched, s1 - s0, nbr->row_ptr, nbr->col, w, mask, uu, oo, nbr->n); break;
-      case 16: hipLaunchKernelGGL((k_apply<16, WT, IOT>), grid, block, 0, ctx->stream, sched, s1 - s0, nbr->row_ptr, nbr->col, w, mask, uu, oo, nbr->n); break;
-      case 32: hipLaunchKernelGGL((k_apply<32, WT, IOT>), grid, block, 0, ctx->stream, sched, s1 - s0, nbr->row_ptr, nbr->col, w, mask, uu, oo, nbr->n); break;
-      default: hipLaunchKernelGGL((k_apply<64, WT, IOT>), grid, block, 0, ctx->stream, sched, s1 - s0, nbr->row_ptr, nbr->col, w, mask, uu, oo, nbr->n); break;
+      case 4: hipLaunchKernelGGL((k_apply<4, WT, IOT>), grid, block, 0, ctx->stream, sched, nrows, nbr->row_ptr, nbr->col, w, mask, uu, oo, nbr->n); break;
+      case 8: hipLaunchKernelGGL((k_apply<8, WT, IOT>), grid, block, 0, ctx->stream, sched, nrows, nbr->row_ptr, nbr->col, w, mask, uu, oo, nbr->n); break;
+      case 16: hipLaunchKernelGGL((k_apply<16, WT, IOT>), grid, block, 0, ctx->stream, sched, nrows, nbr->row_ptr, nbr->col, w, mask, uu, oo, nbr->n); break;
+      case 32: hipLaunchKernelGGL((k_apply<32, WT, IOT>), grid, block, 0, ctx->stream, sched, nrows, nbr->row_ptr, nbr->col, w, mask, uu, oo, nbr->n); break;
+      default: hipLaunchKernelGGL((k_apply<64, WT, IOT>), grid, block, 0, ctx->stream, sched, nrows, nbr->row_ptr, nbr->col, w, mask, uu, oo, nbr->n); break;
     }
     GF_LAUNCH_CHECK(ctx);
   }
@@ -201,7 +202,7 @@ gf_status launch_apply(gf_ctx *ctx, const gf_nbr *nbr, const void *w, unsigned m
 }
 }  // namespace
 
-// Team-size search for the application kernel (FP64 field), per group.
+// Team-size search for the application kernel (FP64 field), per launch unit.
 gf_status tune_apply(gf_ctx *ctx, const gf_nbr *nbr, const void *w, gf_dtype wtype) {
   double *u = nullptr, *out = nullptr;
   if (hipMalloc(&u, sizeof(double) * nbr->n) != hipSuccess) return set_error(ctx, GF_ENOMEM, "tuning buffer");
@@ -215,16 +216,19 @@ gf_status tune_apply(gf_ctx *ctx, const gf_nbr *nbr, const void *w, gf_dtype wty
   (void)hipEventCreate(&e1);
   const int sizes[5] = {4, 8, 16, 32, 64};
   gf_status st = GF_OK;
-  for (int gsel = 0; gsel < 2 * GF_NBAND && !st; ++gsel) {
-    if (nbr->group_start[gsel + 1] <= nbr->group_start[gsel]) continue;
+  LaunchUnit units[2 * GF_NBAND];
+  const int nu = launch_units(nbr, units);
+  for (int q = 0; q < nu && !st; ++q) {
     float best = INFINITY;
-    int bestT = ctx->ateam[gsel / GF_NBAND][gsel % GF_NBAND];
-    for (int t = 0; t < 5 && !st; ++t) {
+    int bestT = ctx->ateam[units[q].model][units[q].band];
+    // tiled blocks hold kTileRows teams: at most 32 lanes each
+    const int nsizes = units[q].tiled ? 4 : 5;
+    for (int t = 0; t < nsizes && !st; ++t) {
       float times[3];
       for (int rep = -1; rep < 3 && !st; ++rep) {
         if (rep >= 0) (void)hipEventRecord(e0, ctx->stream);
-        st = (wtype == GF_F32) ? launch_apply<float, double>(ctx, nbr, w, 0xF, u, out, gsel, sizes[t])
-                               : launch_apply<double, double>(ctx, nbr, w, 0xF, u, out, gsel, sizes[t]);
+        st = (wtype == GF_F32) ? launch_apply<float, double>(ctx, nbr, w, 0xF, u, out, q, sizes[t])
+                               : launch_apply<double, double>(ctx, nbr, w, 0xF, u, out, q, sizes[t]);
         if (rep >= 0) {
           (void)hipEventRecord(e1, ctx->stream);
           (void)hipEventSynchronize(e1);
@@ -235,7 +239,7 @@ gf_status tune_apply(gf_ctx *ctx, const gf_nbr *nbr, const void *w, gf_dtype wty
       std::sort(times, times + 3);
       if (times[1] < best) { best = times[1]; bestT = sizes[t]; }
     }
-    ctx->ateam[gsel / GF_NBAND][gsel % GF_NBAND] = bestT;
+    ctx->ateam[units[q].model][units[q].band] = bestT;
   }
   (void)hipStreamSynchronize(ctx->stream);
   (void)hipEventDestroy(e0);

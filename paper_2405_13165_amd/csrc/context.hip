@@ -66,20 +66,20 @@ static hipEvent_t prof_event(gf_ctx *ctx) {
   return e;
 }
 
-ProfScope::ProfScope(gf_ctx *c, const char *name) : ctx(c) {
+ProfScope::ProfScope(gf_ctx *c, const char *name, hipStream_t s) : ctx(c), sm(s ? s : (c ? c->stream : nullptr)) {
   if (!ctx || !ctx->profile) return;
   gf_ctx::ProfRec r;
   r.name = name;
   r.start = prof_event(ctx);
   r.stop = prof_event(ctx);
   if (!r.start || !r.stop) return;
-  (void)hipEventRecord(r.start, ctx->stream);
+  (void)hipEventRecord(r.start, sm);
   idx = (int)ctx->prof_pending.size();
   ctx->prof_pending.push_back(r);
 }
 
 ProfScope::~ProfScope() {
-  if (idx >= 0) (void)hipEventRecord(ctx->prof_pending[idx].stop, ctx->stream);
+  if (idx >= 0) (void)hipEventRecord(ctx->prof_pending[idx].stop, sm);
 }
 
 extern "C" gf_status gf_profile_enable(gf_ctx *ctx, int on) {

@@ -37,14 +37,16 @@ struct gf_ctx {
   std::vector<hipEvent_t> prof_pool;
 };
 
-// Brackets a kernel launch with events on the context stream when profiling
-// is enabled (names must be string literals).
+// Brackets a kernel launch with events on the given stream (default: the
+// context stream) when profiling is enabled (names must be string literals).
 struct ProfScope {
   gf_ctx *ctx;
+  hipStream_t sm;
   int idx = -1;
-  ProfScope(gf_ctx *c, const char *name);
+  ProfScope(gf_ctx *c, const char *name, hipStream_t s = nullptr);
   ~ProfScope();
 };
+
 
 // Row groups of the batched kernels: particles of one model whose neighbour
 // count falls in one band, in Morton (cell) order.
@@ -63,23 +65,56 @@ struct gf_nbr {
   int32_t *grouped = nullptr;  // [n] particles grouped by (model, band), Morton order inside
   int64_t group_start[2 * GF_NBAND + 1] = {0};  // host copy of the group offsets
   int32_t *rev = nullptr;      // [nnz] position of (j,i) for entry (i,j); built lazily
-  // Neighbour tiles: the rows of each group with at most kTileBandRow
-  // neighbours are cut, in group (Morton) order, into tiles of kTileRows
-  // rows.  tile_u holds, per tile, the sorted distinct neighbour indices of
-  // its rows (tile t owns tile_u[tile_off[t] .. tile_off[t+1])); slot[k] is
-  // the position of col[k] in its row's tile list.  Kernels stage a tile's
-  // list in LDS once and address it through slot[].
+  // Neighbour tiles: per model, the rows of the bands 0..kTileBand (at most
+  // kTileBandRow neighbours; one contiguous range of the grouped order) are
+  // cut, in that order, into tiles of kTileRows rows.  tile_u holds, per
+  // tile, the sorted distinct neighbour indices of its rows (tile t owns
+  // tile_u[tile_off[t] .. tile_off[t+1])); slot[k] is the position of col[k]
+  // in its row's tile list.  Kernels stage a tile's list in LDS once and
+  // address it through slot[].
   uint16_t *slot = nullptr;    // [nnz]
   int32_t *tile_u = nullptr;   // [tile_off[ntiles]]
   int64_t *tile_off = nullptr; // [ntiles + 1]
   int64_t ntiles = 0;
-  int64_t tile_start[2 * GF_NBAND + 1] = {0};  // host: first tile of each group (tiled bands only)
-  int32_t tile_max[2 * GF_NBAND] = {0};        // host: largest tile list of each group
+  int64_t tile_start[3] = {0};  // host: tiles of model m are [tile_start[m], tile_start[m+1])
+  int32_t tile_max[2] = {0};    // host: largest tile list of each model
 };
 constexpr int kTileRows = 32;
 constexpr int kTileBand = 2;                   // bands 0..kTileBand are tiled
 constexpr int kTileBandRow = 128;              // = kBandHi[kTileBand]
-inline bool band_tiled(int band) { return band <= kTileBand; }
+
+// Launch units of the batched kernels: per model, the tiled rows (bands
+// 0..kTileBand) and each untiled band.  Team sizes live in
+// ctx->wteam/ateam[model][band] (band = kTileBand for the tiled unit).
+struct LaunchUnit {
+  int model, band;
+  bool tiled;
+  int64_t row0, nrows;    // range of gf_nbr::grouped
+  int64_t tile0, ntiles;  // tiled units: their tiles
+  int tile_max;
+};
+inline int launch_units(const gf_nbr *nb, LaunchUnit *out) {
+  int k = 0;
+  for (int m = 0; m < 2; ++m) {
+    const int64_t r0 = nb->group_start[m * GF_NBAND], r1 = nb->group_start[m * GF_NBAND + kTileBand + 1];
+    if (r1 > r0) {
+      out[k].model = m; out[k].band = kTileBand; out[k].tiled = nb->tile_start[m + 1] > nb->tile_start[m];
+      out[k].row0 = r0; out[k].nrows = r1 - r0;
+      out[k].tile0 = nb->tile_start[m]; out[k].ntiles = nb->tile_start[m + 1] - nb->tile_start[m];
+      out[k].tile_max = nb->tile_max[m];
+      ++k;
+    }
+    for (int band = kTileBand + 1; band < GF_NBAND; ++band) {
+      const int g = m * GF_NBAND + band;
+      if (nb->group_start[g + 1] <= nb->group_start[g]) continue;
+      out[k].model = m; out[k].band = band; out[k].tiled = false;
+      out[k].row0 = nb->group_start[g]; out[k].nrows = nb->group_start[g + 1] - nb->group_start[g];
+      out[k].tile0 = 0; out[k].ntiles = 0; out[k].tile_max = 0;
+      ++k;
+    }
+  }
+  return k;
+}
 
 // ------------------------------------------------------------------ errors
 gf_status set_error(gf_ctx *ctx, gf_status st, const char *fmt, ...);

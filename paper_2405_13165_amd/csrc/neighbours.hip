@@ -282,7 +282,8 @@ __global__ void __launch_bounds__(64) k_row_sort(const int64_t *__restrict__ row
   for (int t = threadIdx.x; t < len; t += 64) col[b + t] = buf[t];
 }
 
-// grouping: particles (in cell order) of group gsel, stable
+// grouping: particles (in cell order) of group gsel, stable; the tiled
+// bands 0..kTileBand share the group of band kTileBand
 __global__ void __launch_bounds__(kBlock) k_group_flag(const int32_t *__restrict__ order, const int32_t *__restrict__ cnt,
                                                        const int8_t *__restrict__ model, int64_t n, int gsel,
                                                        int32_t *__restrict__ flag) {
@@ -292,6 +293,7 @@ __global__ void __launch_bounds__(kBlock) k_group_flag(const int32_t *__restrict
   int c = cnt[i];
   int band = 0;
   while (band < GF_NBAND - 1 && c > kBandHi[band]) ++band;
+  if (band < kTileBand) band = kTileBand;  // the tiled bands form one Morton-ordered range
   flag[s] = (model[i] * GF_NBAND + band) == gsel ? 1 : 0;
 }
 
@@ -305,15 +307,15 @@ __global__ void __launch_bounds__(kBlock) k_group_scatter(const int32_t *__restr
 }
 
 // ---------------------------------------------------------------- tiles
-// Tiled groups, as passed to the tile kernels: tiles [tile_start[q],
-// tile_start[q+1]) cover rows [row_start[q], row_start[q] + nrows[q]) of the
-// grouped order.
+// Tiled row ranges (one per model), as passed to the tile kernels: tiles
+// [tile_start[q], tile_start[q+1]) cover rows [row_start[q], row_start[q] +
+// nrows[q]) of the grouped order; gsel[q] is the model.
 struct TileGroups {
   int nq = 0;
-  int gsel[2 * GF_NBAND];
-  int64_t tile_start[2 * GF_NBAND + 1];
-  int64_t row_start[2 * GF_NBAND];
-  int64_t nrows[2 * GF_NBAND];
+  int gsel[2];
+  int64_t tile_start[3];
+  int64_t row_start[2];
+  int64_t nrows[2];
 };
 constexpr int kTileEntries = kTileRows * kTileBandRow;  // entries one tile can hold
 constexpr int kTileThreads = 256;
@@ -539,18 +541,18 @@ gf_status build_tiles(gf_ctx *ctx, gf_nbr *nb) {
   hipStream_t sm = ctx->stream;
   TileGroups tg;
   int64_t nt = 0;
-  for (int gsel = 0; gsel < 2 * GF_NBAND; ++gsel) {
-    nb->tile_start[gsel] = nt;
-    const int64_t rows = nb->group_start[gsel + 1] - nb->group_start[gsel];
-    if (!band_tiled(gsel % GF_NBAND) || rows == 0) continue;
-    tg.gsel[tg.nq] = gsel;
+  for (int m = 0; m < 2; ++m) {
+    nb->tile_start[m] = nt;
+    const int64_t r0 = nb->group_start[m * GF_NBAND], r1 = nb->group_start[m * GF_NBAND + kTileBand + 1];
+    if (r1 <= r0) continue;
+    tg.gsel[tg.nq] = m;
     tg.tile_start[tg.nq] = nt;
-    tg.row_start[tg.nq] = nb->group_start[gsel];
-    tg.nrows[tg.nq] = rows;
+    tg.row_start[tg.nq] = r0;
+    tg.nrows[tg.nq] = r1 - r0;
     ++tg.nq;
-    nt += (rows + kTileRows - 1) / kTileRows;
+    nt += (r1 - r0 + kTileRows - 1) / kTileRows;
   }
-  nb->tile_start[2 * GF_NBAND] = nt;
+  nb->tile_start[2] = nt;
   tg.tile_start[tg.nq] = nt;
   nb->ntiles = nt;
   if (nt == 0) return GF_OK;
@@ -583,7 +585,7 @@ gf_status build_tiles(gf_ctx *ctx, gf_nbr *nb) {
   GF_HIP(ctx, hipMemcpyAsync(hp, grp_max, sizeof(int32_t) * 16, hipMemcpyDeviceToHost, sm));
   GF_HIP(ctx, hipMemcpyAsync(hp + 128, nb->tile_off + nt, sizeof(int64_t), hipMemcpyDeviceToHost, sm));
   GF_HIP(ctx, hipStreamSynchronize(sm));
-  for (int q = 0; q < tg.nq; ++q) nb->tile_max[tg.gsel[q]] = ((int32_t *)hp)[q];
+  for (int q = 0; q < tg.nq; ++q) nb->tile_max[tg.gsel[q]] = ((int32_t *)hp)[q];  // per model
   const int64_t total = *(int64_t *)(hp + 128);
   if (hipMalloc(&nb->tile_u, sizeof(int32_t) * std::max<int64_t>(total, 1)) != hipSuccess)
     return set_error(ctx, GF_ENOMEM, "neighbour tile list allocation failed");
@@ -723,6 +725,13 @@ extern "C" gf_status gf_build_neighbours(gf_ctx *ctx, const gf_particles *p, int
     return fail(set_error(ctx, GF_EHIP, "read-back of neighbour counts failed"));
   int32_t hist[2 * GF_NBAND];
   memcpy(hist, hsmall, sizeof(hist));
+  // rows of the tiled bands are grouped together (under band kTileBand) so
+  // that tiles stay spatially compact whatever the neighbour count
+  for (int m = 0; m < 2; ++m)
+    for (int band = 0; band < kTileBand; ++band) {
+      hist[m * GF_NBAND + kTileBand] += hist[m * GF_NBAND + band];
+      hist[m * GF_NBAND + band] = 0;
+    }
   nb->max_row = hsmall[8];
   nb->nnz = *(int64_t *)((char *)ctx->host_pinned + 128);
   if (nb->max_row > kMaxRow)

@@ -528,7 +528,7 @@ k_weights_tile(WArgs a, TileArgs ta, const uint16_t *__restrict__ slot) {
   if (staged) {
     for (int s = threadIdx.x; s < cnt; s += blockDim.x) {
       const int32_t j = ta.u[u0 + s];
-      s_dyn[s] = a.pos[j];
+      s_dyn[s] = make_double4(a.x[j], a.y[j], a.z[j], a.h[j]);
       if constexpr (FUSED) s_u[s] = a.u[j];
     }
   }
@@ -752,14 +752,12 @@ __global__ void __launch_bounds__(1024) k_ls_stats(const int8_t *__restrict__ st
   if (threadIdx.x == 0) *out_kmax = km[0];
 }
 
-// profiling names: one per (model, band) group
-const char *team_kernel_name(int model, int band, bool fused) {
-  static const char *names[2][2][GF_NBAND] = {
-      {{"weights_3d_b0", "weights_3d_b1", "weights_3d_b2", "weights_3d_b3"},
-       {"weights_film_b0", "weights_film_b1", "weights_film_b2", "weights_film_b3"}},
-      {{"weights_apply_3d_b0", "weights_apply_3d_b1", "weights_apply_3d_b2", "weights_apply_3d_b3"},
-       {"weights_apply_film_b0", "weights_apply_film_b1", "weights_apply_film_b2", "weights_apply_film_b3"}}};
-  return names[fused ? 1 : 0][model][band];
+// profiling names: one per launch unit
+const char *unit_kernel_name(const LaunchUnit &u, bool fused) {
+  static const char *names[2][2][2] = {{{"weights_3d_tiles", "weights_3d_b3"}, {"weights_film_tiles", "weights_film_b3"}},
+                                       {{"weights_apply_3d_tiles", "weights_apply_3d_b3"},
+                                        {"weights_apply_film_tiles", "weights_apply_film_b3"}}};
+  return names[fused ? 1 : 0][u.model][u.tiled ? 0 : 1];
 }
 
 template <int M, int OUT, bool FUSED, bool FASTW>
@@ -781,17 +779,16 @@ gf_status launch_team(gf_ctx *ctx, const WArgs &a, int T, const char *name) {
 constexpr int kTileCap = 1024;
 
 template <int M, int OUT, bool FUSED, bool FASTW>
-gf_status launch_tile(gf_ctx *ctx, const WArgs &a, const gf_nbr *nbr, int gsel, int T, const char *name) {
+gf_status launch_tile(gf_ctx *ctx, const WArgs &a, const gf_nbr *nbr, const LaunchUnit &u, int T, const char *name) {
   ProfScope prof(ctx, name);
   TileArgs ta;
   ta.off = nbr->tile_off;
   ta.u = nbr->tile_u;
-  ta.tile0 = nbr->tile_start[gsel];
-  ta.cap = std::min(nbr->tile_max[gsel], kTileCap);
-  const int64_t ntl = nbr->tile_start[gsel + 1] - nbr->tile_start[gsel];
+  ta.tile0 = u.tile0;
+  ta.cap = std::min(u.tile_max, kTileCap);
   const size_t lds = (sizeof(double4) + (FUSED ? sizeof(double) : 0)) * ta.cap +
                      sizeof(double) * kTileRows * team_lds_doubles<M>(T, 0);
-  const dim3 grid(grid_for(ntl, 1)), block(kTileRows * T);
+  const dim3 grid(grid_for(u.ntiles, 1)), block(kTileRows * T);
   switch (T) {
     case 4: hipLaunchKernelGGL((k_weights_tile<M, 4, OUT, FUSED, FASTW>), grid, block, lds, ctx->stream, a, ta, nbr->slot); break;
     case 8: hipLaunchKernelGGL((k_weights_tile<M, 8, OUT, FUSED, FASTW>), grid, block, lds, ctx->stream, a, ta, nbr->slot); break;
@@ -802,33 +799,39 @@ gf_status launch_tile(gf_ctx *ctx, const WArgs &a, const gf_nbr *nbr, int gsel, 
   return GF_OK;
 }
 
-// one launch per non-empty (model, band) group; only_group >= 0 restricts
-// the launches to that group and team_override > 0 replaces its team size
-// (used by the autotuner)
+// One launch per launch unit; only_unit >= 0 restricts the launches to that
+// unit and team_override > 0 replaces its team size (used by the autotuner).
 template <int OUT, bool FUSED, bool FASTW>
-gf_status launch_batched(gf_ctx *ctx, const gf_nbr *nbr, WArgs a, int only_group = -1, int team_override = 0) {
-  for (int m = 0; m < 2; ++m) {
-    for (int band = 0; band < GF_NBAND; ++band) {
-      const int gsel = m * GF_NBAND + band;
-      if (only_group >= 0 && gsel != only_group) continue;
-      const int64_t s0 = nbr->group_start[gsel], s1 = nbr->group_start[gsel + 1];
-      if (s1 <= s0) continue;
-      a.sched = nbr->grouped + s0;
-      a.nrows = s1 - s0;
-      const int T = team_override > 0 ? team_override : ctx->wteam[m][band];
-      const char *name = team_kernel_name(m, band, FUSED);
-      const bool tiled = band_tiled(band) && nbr->tile_start[gsel + 1] > nbr->tile_start[gsel];
-      gf_status st;
-      if (tiled)
-        st = (m == 0) ? launch_tile<10, OUT, FUSED, FASTW>(ctx, a, nbr, gsel, T, name)
-                      : launch_tile<6, OUT, FUSED, FASTW>(ctx, a, nbr, gsel, T, name);
-      else
-        st = (m == 0) ? launch_team<10, OUT, FUSED, FASTW>(ctx, a, T, name)
-                      : launch_team<6, OUT, FUSED, FASTW>(ctx, a, T, name);
-      if (st) return st;
-    }
+gf_status launch_batched(gf_ctx *ctx, const gf_nbr *nbr, WArgs a, int only_unit = -1, int team_override = 0) {
+  LaunchUnit units[2 * GF_NBAND];
+  const int nu = launch_units(nbr, units);
+  for (int q = 0; q < nu; ++q) {
+    if (only_unit >= 0 && q != only_unit) continue;
+    const LaunchUnit &u = units[q];
+    a.sched = nbr->grouped + u.row0;
+    a.nrows = u.nrows;
+    const int T = team_override > 0 ? team_override : ctx->wteam[u.model][u.band];
+    const char *name = unit_kernel_name(u, FUSED);
+    gf_status st;
+    if (u.tiled)
+      st = (u.model == 0) ? launch_tile<10, OUT, FUSED, FASTW>(ctx, a, nbr, u, T, name)
+                          : launch_tile<6, OUT, FUSED, FASTW>(ctx, a, nbr, u, T, name);
+    else
+      st = (u.model == 0) ? launch_team<10, OUT, FUSED, FASTW>(ctx, a, T, name)
+                          : launch_team<6, OUT, FUSED, FASTW>(ctx, a, T, name);
+    if (st) return st;
   }
   return GF_OK;
+}
+
+// whether any batched launch reads the packed positions (untiled units and
+// tiles whose list exceeds the LDS capacity gather them from global memory)
+bool needs_packed_positions(const gf_nbr *nbr) {
+  LaunchUnit units[2 * GF_NBAND];
+  const int nu = launch_units(nbr, units);
+  for (int q = 0; q < nu; ++q)
+    if (!units[q].tiled || units[q].tile_max > kTileCap) return true;
+  return false;
 }
 
 struct WeightsScratch {
@@ -881,7 +884,7 @@ gf_status weights_common(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr, 
   WArgs a;
   a.x = p->x; a.y = p->y; a.z = p->z; a.h = p->h; a.nx = p->nx; a.ny = p->ny; a.nz = p->nz; a.model = p->model;
   a.pos = pos;
-  if (prec == GF_BATCHED) {
+  if (prec == GF_BATCHED && needs_packed_positions(nbr)) {
     ProfScope prof(ctx, "pack_positions");
     hipLaunchKernelGGL(k_pack_pos, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, ctx->stream, p->x, p->y, p->z, p->h, n, pos);
     GF_LAUNCH_CHECK(ctx);
@@ -959,8 +962,8 @@ extern "C" gf_status gf_gfdm_weights_apply(gf_ctx *ctx, const gf_particles *p, c
 }
 
 // ------------------------------------------------------------------ autotuner
-// Times every (model, band) group of the batched stencil kernel with teams of
-// 4, 8 and 16 lanes (median of three launches after a warm-up) and keeps the
+// Times every launch unit of the batched stencil kernel with teams of 4, 8
+// and 16 lanes (median of three launches after a warm-up) and keeps the
 // fastest; then does the same for the application kernel.
 extern "C" gf_status gf_autotune(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr, gf_dtype wtype,
                                  int *team_out) {
@@ -1003,17 +1006,18 @@ extern "C" gf_status gf_autotune(gf_ctx *ctx, const gf_particles *p, const gf_nb
   const int sizes[3] = {4, 8, 16};
   const int saved_profile = ctx->profile;
   ctx->profile = 0;
-  for (int gsel = 0; gsel < 2 * GF_NBAND && !st; ++gsel) {
-    if (nbr->group_start[gsel + 1] <= nbr->group_start[gsel]) continue;
+  LaunchUnit units[2 * GF_NBAND];
+  const int nu = launch_units(nbr, units);
+  for (int q = 0; q < nu && !st; ++q) {
     float best = INFINITY;
-    int bestT = ctx->wteam[gsel / GF_NBAND][gsel % GF_NBAND];
+    int bestT = ctx->wteam[units[q].model][units[q].band];
     for (int t = 0; t < 3 && !st; ++t) {
       float times[3];
       for (int rep = -1; rep < 3 && !st; ++rep) {
         hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, a.qcount, 16);
         if (rep >= 0) (void)hipEventRecord(e0, ctx->stream);
-        st = (wtype == GF_F32) ? launch_batched<GF_F32, false, true>(ctx, nbr, a, gsel, sizes[t])
-                               : launch_batched<GF_F64, false, false>(ctx, nbr, a, gsel, sizes[t]);
+        st = (wtype == GF_F32) ? launch_batched<GF_F32, false, true>(ctx, nbr, a, q, sizes[t])
+                               : launch_batched<GF_F64, false, false>(ctx, nbr, a, q, sizes[t]);
         if (rep >= 0) {
           (void)hipEventRecord(e1, ctx->stream);
           (void)hipEventSynchronize(e1);
@@ -1024,7 +1028,7 @@ extern "C" gf_status gf_autotune(gf_ctx *ctx, const gf_particles *p, const gf_nb
       std::sort(times, times + 3);
       if (times[1] < best) { best = times[1]; bestT = sizes[t]; }
     }
-    ctx->wteam[gsel / GF_NBAND][gsel % GF_NBAND] = bestT;
+    ctx->wteam[units[q].model][units[q].band] = bestT;
   }
   // complete the stencils with the tuned configuration, then tune the application
   if (!st) {
