@@ -262,11 +262,13 @@ __device__ inline void for_neighbours(const F &fetch, int64_t b, int n, int lane
     }
   } else {
     int32_t hc = (lane < n) ? fetch.idx(b + lane) : fetch.dummy;
+    int32_t hn = (lane + T < n) ? fetch.idx(b + lane + T) : fetch.dummy;
 #pragma unroll 1
     for (int k = lane; k < n; k += T) {
       const double4 pj = fetch.get(hc);
       const int32_t h = hc;
-      hc = (k + T < n) ? fetch.idx(b + k + T) : fetch.dummy;
+      hc = hn;
+      hn = (k + 2 * T < n) ? fetch.idx(b + k + 2 * T) : fetch.dummy;
       body(k, pj, h);
     }
   }
