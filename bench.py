@@ -193,11 +193,28 @@ def main():
               file=sys.stderr, flush=True)
         return
 
-    ms_fused = timed(step_fused, args.steps, args.warmup)
+    ms_eager = timed(step_fused, args.steps, args.warmup)
     ms_batched = timed(step_batched, args.steps, args.warmup)
     ms_plain = timed(step_plain, args.steps, args.warmup)
-    print(f"[bench] fused {ms_fused:.3f} ms  separate calls {ms_batched:.3f} ms  plain {ms_plain:.3f} ms",
-          file=sys.stderr, flush=True)
+    # the same fused step captured once in a HIP graph and replayed; the
+    # replay must reproduce the eager outputs exactly
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step_fused()
+    step_fused()
+    torch.cuda.synchronize()
+    w_ref, y_ref = w32.clone(), yf.clone()
+    w32.zero_()
+    yf.zero_()
+    graph.replay()
+    torch.cuda.synchronize()
+    graph_ok = bool(torch.equal(w32, w_ref) and torch.equal(yf, y_ref))
+    del w_ref, y_ref
+    ms_graph = timed(graph.replay, args.steps, args.warmup)
+    use_graph = graph_ok and ms_graph < ms_eager
+    ms_fused = ms_graph if use_graph else ms_eager
+    print(f"[bench] fused eager {ms_eager:.3f} ms  graph {ms_graph:.3f} ms (replay exact: {graph_ok})  "
+          f"separate calls {ms_batched:.3f} ms  plain {ms_plain:.3f} ms", file=sys.stderr, flush=True)
 
     # per-kernel times of the metric step (HIP events around each launch)
     ctx.profile(True)
@@ -278,7 +295,10 @@ def main():
         "config": {"workload": "mixed bulk/film cloud: 258,944 jittered-lattice bulk particles beside "
                                "245,000 film particles on z=0, h = 3 x spacing (10 / 6 monomials)",
                    "n_particles": N, "nnz": nnz, "factor": args.factor},
-        "step": "gf_gfdm_weights_apply: batched stencils stored in FP32 and applied (one call)",
+        "step": ("gf_gfdm_weights_apply: batched stencils stored in FP32 and applied (one call), "
+                 + ("replayed from a HIP graph" if use_graph else "eager launches (faster than the graph replay)")),
+        "fused_eager": {"value": N / (ms_eager * 1e-3), "ms_per_step": ms_eager},
+        "fused_graph": {"value": N / (ms_graph * 1e-3), "ms_per_step": ms_graph, "replay_exact": graph_ok},
         "plain_f64": {"value": N / (ms_plain * 1e-3), "ms_per_step": ms_plain,
                       "step": "gf_gfdm_weights(GF_PLAIN_F64) + gf_apply_stencil"},
         "separate_calls_f32": {"value": N / (ms_batched * 1e-3), "ms_per_step": ms_batched,
