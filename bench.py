@@ -42,6 +42,10 @@ def parse():
     ap.add_argument("--no-rows", action="store_true", help="skip timing the other hot-path steps")
     ap.add_argument("--poisson", type=int, default=0,
                     help="also solve the pressure system on a jet cylinder of this many particles")
+    ap.add_argument("--jet", action="store_true",
+                    help="also time the fused step on the 2.0M-particle jet cloud (uneven neighbourhoods)")
+    ap.add_argument("--diff", action="store_true",
+                    help="also time forward + backward of the stencil operator on the 1e6-particle cube")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warm-up plus a few steps of the metric path and exit (for rocprofv3)")
     return ap.parse_args()
@@ -349,17 +353,84 @@ def main():
         A = torch.sparse_csr_tensor(rpp, colp.long(), val, size=(pp.n, pp.n))
         b = (A @ torch.as_tensor(dp["pstar"], device=ctx.device).unsqueeze(1)).squeeze(1)
         ps = {}
+        ps_n, ps_nnz = pp.n, nbp.nnz
         for mixed in (0, 1):
+            # one untimed solve, one timed solve, one profiled solve (per-iteration launch times)
+            g.poisson_solve(ctx, pp, nbp, wp, dp["row_type"], b, params=g.solve_params(mixed=mixed),
+                            raise_on_fail=False)
             torch.cuda.synchronize()
             t = time.perf_counter()
             x, st = g.poisson_solve(ctx, pp, nbp, wp, dp["row_type"], b, params=g.solve_params(mixed=mixed),
                                     raise_on_fail=False)
             torch.cuda.synchronize()
             el = time.perf_counter() - t
+            ctx.profile(True)
+            g.poisson_solve(ctx, pp, nbp, wp, dp["row_type"], b, params=g.solve_params(mixed=mixed),
+                            raise_on_fail=False)
+            prof_p = ctx.profile_read()
+            ctx.profile(False)
             err = ((x - torch.as_tensor(dp["pstar"], device=ctx.device)).norm() /
                    torch.as_tensor(dp["pstar"], device=ctx.device).norm()).item()
-            ps["mixed" if mixed else "plain_f64"] = dict(seconds=el, err_vs_pstar=err, **st)
-        result["poisson"] = {"n": pp.n, "nnz": nbp.nnz, **ps}
+            rec = dict(seconds=el, err_vs_pstar=err, **st)
+            # one Jacobi-BiCGStab iteration: two SpMV (values + column index per entry, x gathered,
+            # two vectors) and the vector updates (26 vector passes in all)
+            for name, vb in (("bicgstab_iter_f64", 8), ("bicgstab_iter_f32", 4)):
+                if name in prof_p:
+                    cnt, tot = prof_p[name]
+                    it_s = tot / cnt * 1e-3
+                    byts = 2.0 * ps_nnz * (vb + 4) + 26.0 * vb * ps_n
+                    rec[name] = {"iterations": cnt, "avg_us": round(it_s * 1e6, 1),
+                                 "algorithmic_bytes": byts, "GBs": round(byts / it_s / 1e9, 1),
+                                 "hbm_frac": round(byts / it_s / 1e9 / PEAK_HBM_GBS, 4)}
+            ps["mixed" if mixed else "plain_f64"] = rec
+            print(f"[bench] poisson mixed={mixed}: {el:.3f}s {rec}", file=sys.stderr, flush=True)
+        result["poisson"] = {"n": ps_n, "nnz": ps_nnz, **ps}
+        del dp, pp, nbp, wp, val, A, b, x
+
+    if args.jet:
+        dj = W.jet_impact()
+        pj = g.Particles.from_dict(ctx, dj)
+        nbj = g.build_neighbours(ctx, pj)
+        g.autotune(ctx, pj, nbj, g.GF_F32)
+        uj = torch.as_tensor(W.test_field(dj["x"], dj["y"], dj["z"])[0], device=ctx.device)
+        wj = torch.empty((nbj.nnz, 4), dtype=torch.float32, device=ctx.device)
+        yj = torch.empty((4, pj.n), dtype=torch.float64, device=ctx.device)
+        stj = torch.empty(pj.n, dtype=torch.int8, device=ctx.device)
+        ms_j = timed(lambda: g.gfdm_weights_apply(ctx, pj, nbj, uj, 0xF, g.GF_F32, w_out=wj, out=yj, status=stj),
+                     args.steps, args.warmup)
+        ctx.profile(True)
+        g.gfdm_weights_apply(ctx, pj, nbj, uj, 0xF, g.GF_F32, w_out=wj, out=yj, status=stj)
+        prof_j = ctx.profile_read()
+        ctx.profile(False)
+        counts = np.bincount(stj.cpu().numpy().astype(np.int64), minlength=4)
+        result["jet"] = {"n": pj.n, "nnz": nbj.nnz, "max_row": nbj.max_row, "ms_per_step": ms_j,
+                         "value": pj.n / (ms_j * 1e-3), "unit": "particles/s",
+                         "status_counts": {"ok": int(counts[0]), "qr_fallback": int(counts[1]),
+                                           "rank_deficient": int(counts[2]), "too_few": int(counts[3])},
+                         "kernels": {k: {"launches": c, "avg_us": 1000.0 * t / c} for k, (c, t) in prof_j.items()}}
+        print(f"[bench] jet: {ms_j:.3f} ms per fused step", file=sys.stderr, flush=True)
+        del dj, pj, nbj, uj, wj, yj, stj
+
+    if args.diff:
+        dd = W.diff_cube()
+        pd = g.Particles.from_dict(ctx, dd)
+        nbd = g.build_neighbours(ctx, pd)
+        ud = torch.as_tensor(dd["u"], device=ctx.device)
+        gd = torch.as_tensor(dd["g"], device=ctx.device)
+        xs = [torch.as_tensor(dd[k], device=ctx.device) for k in ("x", "y", "z")]
+
+        def fwd_bwd():
+            ur = ud.clone().requires_grad_(True)
+            xr, yr, zr = (t.clone().requires_grad_(True) for t in xs)
+            out = g.stencil_op(ctx, pd, nbd, ur, xr, yr, zr, op_mask=g.OP_LAP, wtype=g.GF_F32)
+            loss = ((out[0] - gd) ** 2).sum()
+            return torch.autograd.grad(loss, (ur, xr, yr, zr))
+
+        ms_d = timed(fwd_bwd, max(3, args.steps // 4), 1)
+        result["differentiation"] = {"n": pd.n, "nnz": nbd.nnz, "ms_forward_backward": ms_d,
+                                     "value": pd.n / (ms_d * 1e-3), "unit": "particles/s"}
+        print(f"[bench] differentiation: {ms_d:.3f} ms forward+backward", file=sys.stderr, flush=True)
+        del dd, pd, nbd
 
     # ---- CPU oracle baseline and operator error (oracle inputs never come from the device)
     if not args.no_cpu_baseline:

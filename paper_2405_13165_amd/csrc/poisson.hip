@@ -4,10 +4,14 @@
 //
 // The iteration runs as five fused kernels (direction update, SpMV + dot,
 // intermediate update, SpMV + two dots, solution/residual update + two dots).
-// Scalars (rho, alpha, omega, ...) stay on the device; every dot product is
-// a deterministic two-level reduction finished by the last block to arrive
-// (fixed summation order, counter reset by that block).  The host reads the
-// residual norm every few iterations.
+// Scalars (rho, alpha, omega, ...) stay on the device.  Every dot product is
+// a deterministic two-level reduction: the kernels that produce it run a
+// fixed grid of kRedBlocks blocks (grid-stride over the rows) and write one
+// partial per block; a one-block kernel adds the partials in block order and
+// updates the scalars.  The kernel boundary makes the partials visible (no
+// device-scope fences: on a chip whose XCDs have separate L2 caches each such
+// fence writes back an L2).  The host reads the residual norm every few
+// iterations.
 //
 // Mixed mode: the outer loop forms r = b - A x with FP64 matrix values and
 // vectors; the inner BiCGStab runs on FP32 matrix values and FP32 vectors
@@ -48,30 +52,37 @@ __device__ inline double block_sum(double v) {
   return r;
 }
 
-// Reduce NV values over the grid; returns true in the last block with the
-// totals in res (identical on every thread of that block).
+constexpr int kRedBlocks = 2048;   // blocks of the reducing kernels
+constexpr int kFinThreads = 1024;  // threads of the finishing kernels
+
+// one partial per block and value: part[k * gridDim.x + blockIdx.x]
 template <int NV>
-__device__ bool grid_reduce(const double v[NV], double *part, unsigned *counter, double res[NV]) {
-  __shared__ int last;
+__device__ inline void block_partials(const double v[NV], double *part) {
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     const double s = block_sum(v[k]);
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * NV + k] = s;
+    if (threadIdx.x == 0) part[(int64_t)k * gridDim.x + blockIdx.x] = s;
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = (atomicAdd(counter, 1u) == gridDim.x - 1) ? 1 : 0;
-  __syncthreads();
-  if (!last) return false;
-  __threadfence();
+}
+
+// sums of the partials of nblk blocks, in block order, on every thread
+template <int NV>
+__device__ inline void finish_partials(const double *part, int nblk, double res[NV]) {
+  __shared__ double sh[kFinThreads / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     double acc = 0.0;
-    for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x) acc += part[(int64_t)b * NV + k];
-    res[k] = block_sum(acc);
+    for (int b = threadIdx.x; b < nblk; b += kFinThreads) acc += part[(int64_t)k * nblk + b];
+    acc = wave_sum(acc);
+    __syncthreads();
+    if (lane == 0) sh[wid] = acc;
+    __syncthreads();
+    double r = 0.0;
+#pragma unroll
+    for (int w = 0; w < kFinThreads / 64; ++w) r += sh[w];
+    res[k] = r;
   }
-  if (threadIdx.x == 0) *counter = 0u;
-  return true;
 }
 
 // ---------------------------------------------------------------- assembly
@@ -110,18 +121,20 @@ __global__ void __launch_bounds__(kBlock) k_assemble(const int64_t *__restrict__
 }
 
 // ---------------------------------------------------------------- kernels
-// r = b - A x (FP64), optionally rhat = r and scalars reset; reduces (r,r)
-// and, if bb_too, (b,b).
+// Rows are taken by teams of kTeam lanes, grid-stride over the fixed grid.
+#define GF_TEAM_ROWS(row)                                                              \
+  const int64_t gt_ = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;                 \
+  const int lane = (int)(gt_ % kTeam);                                                 \
+  const int64_t nteams_ = (int64_t)gridDim.x * blockDim.x / kTeam;                     \
+  for (int64_t row = gt_ / kTeam; row < n; row += nteams_)
+
+// r = b - A x (FP64), optionally rhat = r; partials of (r,r) and (b,b)
 __global__ void __launch_bounds__(kBlock) k_residual(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
                                                      const double *__restrict__ val, const double *__restrict__ b,
                                                      const double *__restrict__ x, int64_t n, double *__restrict__ r,
-                                                     double *__restrict__ rhat, double *part, unsigned *counter, Scal *S,
-                                                     int reset) {
-  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t row = gt / kTeam;
-  const int lane = (int)(gt % kTeam);
+                                                     double *__restrict__ rhat, double *part) {
   double v[2] = {0.0, 0.0};
-  if (row < n) {
+  GF_TEAM_ROWS(row) {
     double acc = 0.0;
     for (int64_t k = row_ptr[row] + lane; k < row_ptr[row + 1]; k += kTeam) acc += val[k] * x[col[k]];
     acc = team_sum(acc, kTeam);
@@ -129,49 +142,57 @@ __global__ void __launch_bounds__(kBlock) k_residual(const int64_t *__restrict__
       const double ri = b[row] - acc;
       r[row] = ri;
       if (rhat) rhat[row] = ri;
-      v[0] = ri * ri;
-      v[1] = b[row] * b[row];
+      v[0] += ri * ri;
+      v[1] += b[row] * b[row];
     }
   }
-  double res[2];
-  if (grid_reduce<2>(v, part, counter, res) && threadIdx.x == 0) {
-    S->rr = res[0];
-    S->bb = res[1];
-    if (reset) {
-      S->rho = res[0];  // rhat = r
-      S->rho_old = 1.0;
-      S->alpha = 1.0;
-      S->omega = 1.0;
-      S->breakdown = 0;
-    }
-  }
+  block_partials<2>(v, part);
 }
 
-// x32 = (float) r64; rhat32 = x32; p = v = 0; scalars reset with rho = (r,r)
-template <typename XT>
-__global__ void __launch_bounds__(kBlock) k_inner_init(const double *__restrict__ r64, int64_t n, XT *__restrict__ r,
-                                                       XT *__restrict__ rhat, XT *__restrict__ p, XT *__restrict__ vv,
-                                                       XT *__restrict__ x, double *part, unsigned *counter, Scal *S) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double v[1] = {0.0};
-  if (i < n) {
-    const XT ri = (XT)r64[i];
-    r[i] = ri;
-    rhat[i] = ri;
-    p[i] = (XT)0;
-    vv[i] = (XT)0;
-    x[i] = (XT)0;
-    v[0] = (double)ri * (double)ri;
-  }
-  double res[1];
-  if (grid_reduce<1>(v, part, counter, res) && threadIdx.x == 0) {
-    S->rr = res[0];
+// scalars after a residual: rr, bb; with reset, a fresh BiCGStab start (rhat = r)
+__global__ void __launch_bounds__(kFinThreads) k_fin_residual(const double *part, int nblk, Scal *S, int reset) {
+  double res[2];
+  finish_partials<2>(part, nblk, res);
+  if (threadIdx.x != 0) return;
+  S->rr = res[0];
+  S->bb = res[1];
+  if (reset) {
     S->rho = res[0];
     S->rho_old = 1.0;
     S->alpha = 1.0;
     S->omega = 1.0;
     S->breakdown = 0;
   }
+}
+
+// x32 = (float) r64; rhat32 = x32; p = v = 0; partial of (r,r)
+template <typename XT>
+__global__ void __launch_bounds__(kBlock) k_inner_init(const double *__restrict__ r64, int64_t n, XT *__restrict__ r,
+                                                       XT *__restrict__ rhat, XT *__restrict__ p, XT *__restrict__ vv,
+                                                       XT *__restrict__ x, double *part) {
+  double v[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const XT ri = (XT)r64[i];
+    r[i] = ri;
+    rhat[i] = ri;
+    p[i] = (XT)0;
+    vv[i] = (XT)0;
+    x[i] = (XT)0;
+    v[0] += (double)ri * (double)ri;
+  }
+  block_partials<1>(v, part);
+}
+
+__global__ void __launch_bounds__(kFinThreads) k_fin_inner_init(const double *part, int nblk, Scal *S) {
+  double res[1];
+  finish_partials<1>(part, nblk, res);
+  if (threadIdx.x != 0) return;
+  S->rr = res[0];
+  S->rho = res[0];
+  S->rho_old = 1.0;
+  S->alpha = 1.0;
+  S->omega = 1.0;
+  S->breakdown = 0;
 }
 
 template <typename XT>
@@ -193,44 +214,46 @@ __global__ void __launch_bounds__(kBlock) k_update_p(const XT *__restrict__ r, c
   phat[i] = (XT)(pi * (double)dinv[i]);
 }
 
-// y = A xin; reduces (rhat, y) -> alpha = rho / (rhat, y)       [STAGE 0]
-// y = A xin; reduces (y, s), (y, y) -> omega = (t,s)/(t,t)       [STAGE 1]
-template <typename VT, typename XT, int STAGE>
+// y = A xin; partials of (other, y) and (y, y)
+template <typename VT, typename XT>
 __global__ void __launch_bounds__(kBlock) k_spmv_dot(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
                                                      const VT *__restrict__ val, const XT *__restrict__ xin, int64_t n,
                                                      XT *__restrict__ y, const XT *__restrict__ other, double *part,
-                                                     unsigned *counter, Scal *S) {
-  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t row = gt / kTeam;
-  const int lane = (int)(gt % kTeam);
-  const bool live = !S->breakdown;
+                                                     const Scal *__restrict__ S) {
   double v[2] = {0.0, 0.0};
-  if (row < n && live) {
-    double acc = 0.0;
-    for (int64_t k = row_ptr[row] + lane; k < row_ptr[row + 1]; k += kTeam) acc += (double)val[k] * (double)xin[col[k]];
-    acc = team_sum(acc, kTeam);
-    if (lane == 0) {
-      const XT yi = (XT)acc;
-      y[row] = yi;
-      const double o = (double)other[row];
-      v[0] = o * (double)yi;
-      v[1] = (double)yi * (double)yi;
+  if (!S->breakdown) {
+    GF_TEAM_ROWS(row) {
+      double acc = 0.0;
+      for (int64_t k = row_ptr[row] + lane; k < row_ptr[row + 1]; k += kTeam) acc += (double)val[k] * (double)xin[col[k]];
+      acc = team_sum(acc, kTeam);
+      if (lane == 0) {
+        const XT yi = (XT)acc;
+        y[row] = yi;
+        v[0] += (double)other[row] * (double)yi;
+        v[1] += (double)yi * (double)yi;
+      }
     }
   }
+  block_partials<2>(v, part);
+}
+
+// STAGE 0: alpha = rho / (rhat, v);  STAGE 1: omega = (t, s) / (t, t)
+template <int STAGE>
+__global__ void __launch_bounds__(kFinThreads) k_fin_spmv(const double *part, int nblk, Scal *S) {
   double res[2];
-  if (grid_reduce<2>(v, part, counter, res) && threadIdx.x == 0 && live) {
-    if (STAGE == 0) {
-      const double rv = res[0];
-      S->rv = rv;
-      if (rv == 0.0 || !isfinite(rv)) S->breakdown = 1;
-      else S->alpha = S->rho / rv;
-    } else {
-      S->ts = res[0];
-      S->tt = res[1];
-      if (res[1] == 0.0 || !isfinite(res[1])) S->breakdown = 2;
-      else S->omega = res[0] / res[1];
-      if (S->omega == 0.0) S->breakdown = 3;
-    }
+  finish_partials<2>(part, nblk, res);
+  if (threadIdx.x != 0 || S->breakdown) return;
+  if (STAGE == 0) {
+    const double rv = res[0];
+    S->rv = rv;
+    if (rv == 0.0 || !isfinite(rv)) S->breakdown = 1;
+    else S->alpha = S->rho / rv;
+  } else {
+    S->ts = res[0];
+    S->tt = res[1];
+    if (res[1] == 0.0 || !isfinite(res[1])) S->breakdown = 2;
+    else S->omega = res[0] / res[1];
+    if (S->omega == 0.0) S->breakdown = 3;
   }
 }
 
@@ -246,30 +269,34 @@ __global__ void __launch_bounds__(kBlock) k_update_s(const XT *__restrict__ r, c
   shat[i] = (XT)(si * (double)dinv[i]);
 }
 
-// x += alpha phat + omega shat; r = s - omega t; reduces (rhat, r), (r, r)
+// x += alpha phat + omega shat; r = s - omega t; partials of (rhat, r), (r, r)
 template <typename XT>
 __global__ void __launch_bounds__(kBlock) k_update_xr(const XT *__restrict__ phat, const XT *__restrict__ shat,
                                                       const XT *__restrict__ s, const XT *__restrict__ t,
                                                       const XT *__restrict__ rhat, int64_t n, XT *__restrict__ x,
-                                                      XT *__restrict__ r, double *part, unsigned *counter, Scal *S) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool live = !S->breakdown;
+                                                      XT *__restrict__ r, double *part, const Scal *__restrict__ S) {
   double v[2] = {0.0, 0.0};
-  if (i < n && live) {
+  if (!S->breakdown) {
     const double al = S->alpha, om = S->omega;
-    x[i] = (XT)((double)x[i] + al * (double)phat[i] + om * (double)shat[i]);
-    const double ri = (double)s[i] - om * (double)t[i];
-    r[i] = (XT)ri;
-    v[0] = (double)rhat[i] * (double)(XT)ri;
-    v[1] = (double)(XT)ri * (double)(XT)ri;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+      x[i] = (XT)((double)x[i] + al * (double)phat[i] + om * (double)shat[i]);
+      const double ri = (double)s[i] - om * (double)t[i];
+      r[i] = (XT)ri;
+      v[0] += (double)rhat[i] * (double)(XT)ri;
+      v[1] += (double)(XT)ri * (double)(XT)ri;
+    }
   }
+  block_partials<2>(v, part);
+}
+
+__global__ void __launch_bounds__(kFinThreads) k_fin_xr(const double *part, int nblk, Scal *S) {
   double res[2];
-  if (grid_reduce<2>(v, part, counter, res) && threadIdx.x == 0 && live) {
-    S->rho_old = S->rho;
-    S->rho = res[0];
-    S->rr = res[1];
-    if (res[0] == 0.0 || !isfinite(res[0])) S->breakdown = 4;
-  }
+  finish_partials<2>(part, nblk, res);
+  if (threadIdx.x != 0 || S->breakdown) return;
+  S->rho_old = S->rho;
+  S->rho = res[0];
+  S->rr = res[1];
+  if (res[0] == 0.0 || !isfinite(res[0])) S->breakdown = 4;
 }
 
 __global__ void __launch_bounds__(kBlock) k_add_f32(double *__restrict__ x, const float *__restrict__ d, int64_t n) {
@@ -285,11 +312,10 @@ struct Solver {
   gf_ctx *ctx;
   const gf_nbr *nbr;
   int64_t n;
-  double *part;
-  unsigned *counter;
+  double *part;  // [2 * kRedBlocks]
   Scal *S;
   Scal *hS;
-  unsigned grid_row, grid_team;
+  unsigned grid_row;
 };
 
 gf_status read_scal(Solver &sv) {
@@ -305,20 +331,32 @@ struct Vecs {
   XT *x, *r, *rhat, *p, *v, *phat, *s, *shat, *t;
 };
 
-// one BiCGStab iteration (5 launches)
+// r = b - A x (and rhat = r with reset) followed by its scalar update
+void launch_residual(Solver &sv, const double *val64, const double *rhs, const double *x, double *r, double *rhat,
+                     int reset) {
+  hipStream_t sm = sv.ctx->stream;
+  hipLaunchKernelGGL(k_residual, dim3(kRedBlocks), dim3(kBlock), 0, sm, sv.nbr->row_ptr, sv.nbr->col, val64, rhs, x,
+                     sv.n, r, rhat, sv.part);
+  hipLaunchKernelGGL(k_fin_residual, dim3(1), dim3(kFinThreads), 0, sm, sv.part, kRedBlocks, sv.S, reset);
+}
+
+// one BiCGStab iteration (5 launches + 3 one-block finishers)
 template <typename VT, typename XT>
 gf_status bicgstab_iter(Solver &sv, const Vecs<VT, XT> &V) {
   hipStream_t sm = sv.ctx->stream;
   const int64_t n = sv.n;
   ProfScope prof(sv.ctx, sizeof(VT) == 8 ? "bicgstab_iter_f64" : "bicgstab_iter_f32");
   hipLaunchKernelGGL((k_update_p<XT>), dim3(sv.grid_row), dim3(kBlock), 0, sm, V.r, V.v, V.dinv, n, V.p, V.phat, sv.S);
-  hipLaunchKernelGGL((k_spmv_dot<VT, XT, 0>), dim3(sv.grid_team), dim3(kBlock), 0, sm, sv.nbr->row_ptr, sv.nbr->col,
-                     V.val, V.phat, n, V.v, V.rhat, sv.part, sv.counter, sv.S);
+  hipLaunchKernelGGL((k_spmv_dot<VT, XT>), dim3(kRedBlocks), dim3(kBlock), 0, sm, sv.nbr->row_ptr, sv.nbr->col, V.val,
+                     V.phat, n, V.v, V.rhat, sv.part, sv.S);
+  hipLaunchKernelGGL((k_fin_spmv<0>), dim3(1), dim3(kFinThreads), 0, sm, sv.part, kRedBlocks, sv.S);
   hipLaunchKernelGGL((k_update_s<XT>), dim3(sv.grid_row), dim3(kBlock), 0, sm, V.r, V.v, V.dinv, n, V.s, V.shat, sv.S);
-  hipLaunchKernelGGL((k_spmv_dot<VT, XT, 1>), dim3(sv.grid_team), dim3(kBlock), 0, sm, sv.nbr->row_ptr, sv.nbr->col,
-                     V.val, V.shat, n, V.t, V.s, sv.part, sv.counter, sv.S);
-  hipLaunchKernelGGL((k_update_xr<XT>), dim3(sv.grid_row), dim3(kBlock), 0, sm, V.phat, V.shat, V.s, V.t, V.rhat, n,
-                     V.x, V.r, sv.part, sv.counter, sv.S);
+  hipLaunchKernelGGL((k_spmv_dot<VT, XT>), dim3(kRedBlocks), dim3(kBlock), 0, sm, sv.nbr->row_ptr, sv.nbr->col, V.val,
+                     V.shat, n, V.t, V.s, sv.part, sv.S);
+  hipLaunchKernelGGL((k_fin_spmv<1>), dim3(1), dim3(kFinThreads), 0, sm, sv.part, kRedBlocks, sv.S);
+  hipLaunchKernelGGL((k_update_xr<XT>), dim3(kRedBlocks), dim3(kBlock), 0, sm, V.phat, V.shat, V.s, V.t, V.rhat, n,
+                     V.x, V.r, sv.part, sv.S);
+  hipLaunchKernelGGL(k_fin_xr, dim3(1), dim3(kFinThreads), 0, sm, sv.part, kRedBlocks, sv.S);
   GF_LAUNCH_CHECK(sv.ctx);
   return GF_OK;
 }
@@ -386,9 +424,8 @@ extern "C" gf_status gf_poisson_solve(gf_ctx *ctx, const gf_particles *p, const 
   const int64_t n = p->n, nnz = nbr->nnz;
   const bool mixed = prm.mixed != 0;
   Arena ar;
-  const int nblk_team = (int)grid_for(n * kTeam, kBlock), nblk_row = (int)grid_for(n, kBlock);
-  const int nblk = std::max(nblk_team, nblk_row);
-  std::vector<size_t> sz = {sizeof(double) * nnz, sizeof(double) * n, sizeof(double) * 2 * nblk + 64, 64,
+  const int nblk_row = (int)grid_for(n, kBlock);
+  std::vector<size_t> sz = {sizeof(double) * nnz, sizeof(double) * n, sizeof(double) * 2 * kRedBlocks + 64,
                             sizeof(Scal), 64};
   for (int k = 0; k < 9; ++k) sz.push_back(sizeof(double) * n);
   if (mixed) {
@@ -399,8 +436,7 @@ extern "C" gf_status gf_poisson_solve(gf_ctx *ctx, const gf_particles *p, const 
   if ((st = ensure_scratch(ctx, arena_bytes(sz), &ar))) return st;
   double *val64 = ar.take<double>(nnz);
   double *dinv64 = ar.take<double>(n);
-  double *part = ar.take<double>(2 * nblk + 8);
-  unsigned *counter = ar.take<unsigned>(16);
+  double *part = ar.take<double>(2 * kRedBlocks + 8);
   Scal *S = ar.take<Scal>(1);
   int *bad = ar.take<int>(16);
   double *vec64[9];
@@ -413,14 +449,12 @@ extern "C" gf_status gf_poisson_solve(gf_ctx *ctx, const gf_particles *p, const 
   }
   if ((st = ensure_host(ctx, 4096))) return st;
   hipStream_t sm = ctx->stream;
-  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, sm, counter);
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, sm, (unsigned *)bad);
   if ((st = assemble_common(ctx, p, nbr, w64, row_type, prm.zeta, val64, val32, dinv64, dinv32, bad))) return st;
   Solver sv;
-  sv.ctx = ctx; sv.nbr = nbr; sv.n = n; sv.part = part; sv.counter = counter; sv.S = S;
+  sv.ctx = ctx; sv.nbr = nbr; sv.n = n; sv.part = part; sv.S = S;
   sv.hS = (Scal *)ctx->host_pinned;
   sv.grid_row = (unsigned)nblk_row;
-  sv.grid_team = (unsigned)nblk_team;
   int *hbad = (int *)((char *)ctx->host_pinned + 1024);
   GF_HIP(ctx, hipMemcpyAsync(hbad, bad, sizeof(int), hipMemcpyDeviceToHost, sm));
   // FP64 work vectors: x is the caller's array
@@ -429,8 +463,7 @@ extern "C" gf_status gf_poisson_solve(gf_ctx *ctx, const gf_particles *p, const 
   V64.r = vec64[0]; V64.rhat = vec64[1]; V64.p = vec64[2]; V64.v = vec64[3]; V64.phat = vec64[4];
   V64.s = vec64[5]; V64.shat = vec64[6]; V64.t = vec64[7];
   // initial residual
-  hipLaunchKernelGGL(k_residual, dim3(sv.grid_team), dim3(kBlock), 0, sm, nbr->row_ptr, nbr->col, val64, rhs, p_inout,
-                     n, V64.r, V64.rhat, part, counter, S, 1);
+  launch_residual(sv, val64, rhs, p_inout, V64.r, V64.rhat, 1);
   hipLaunchKernelGGL(k_zero_vecs<double>, dim3(sv.grid_row), dim3(kBlock), 0, sm, n, V64.p, V64.v);
   GF_LAUNCH_CHECK(ctx);
   if ((st = read_scal(sv))) return st;
@@ -460,8 +493,7 @@ extern "C" gf_status gf_poisson_solve(gf_ctx *ctx, const gf_particles *p, const 
           if (stats) *stats = sts;
           return set_error(ctx, GF_EBREAKDOWN, "BiCGStab broke down repeatedly (code %d)", sv.hS->breakdown);
         }
-        hipLaunchKernelGGL(k_residual, dim3(sv.grid_team), dim3(kBlock), 0, sm, nbr->row_ptr, nbr->col, val64, rhs,
-                           p_inout, n, V64.r, V64.rhat, part, counter, S, 1);
+        launch_residual(sv, val64, rhs, p_inout, V64.r, V64.rhat, 1);
         hipLaunchKernelGGL(k_zero_vecs<double>, dim3(sv.grid_row), dim3(kBlock), 0, sm, n, V64.p, V64.v);
         if ((st = read_scal(sv))) return st;
         rnorm = std::sqrt(sv.hS->rr);
@@ -470,8 +502,7 @@ extern "C" gf_status gf_poisson_solve(gf_ctx *ctx, const gf_particles *p, const 
       rnorm = std::sqrt(sv.hS->rr);
       if (rnorm <= target) {
         // replace the recursive residual by the true one
-        hipLaunchKernelGGL(k_residual, dim3(sv.grid_team), dim3(kBlock), 0, sm, nbr->row_ptr, nbr->col, val64, rhs,
-                           p_inout, n, V64.r, (double *)nullptr, part, counter, S, 0);
+        launch_residual(sv, val64, rhs, p_inout, V64.r, nullptr, 0);
         if ((st = read_scal(sv))) return st;
         rnorm = std::sqrt(sv.hS->rr);
       }
@@ -484,8 +515,9 @@ extern "C" gf_status gf_poisson_solve(gf_ctx *ctx, const gf_particles *p, const 
     while (rnorm > target && total < prm.maxit) {
       ++sts.outer_its;
       // inner solve of A32 d = r64 from d = 0
-      hipLaunchKernelGGL(k_inner_init<float>, dim3(sv.grid_row), dim3(kBlock), 0, sm, V64.r, n, V32.r, V32.rhat,
-                         V32.p, V32.v, V32.x, part, counter, S);
+      hipLaunchKernelGGL(k_inner_init<float>, dim3(kRedBlocks), dim3(kBlock), 0, sm, V64.r, n, V32.r, V32.rhat,
+                         V32.p, V32.v, V32.x, part);
+      hipLaunchKernelGGL(k_fin_inner_init, dim3(1), dim3(kFinThreads), 0, sm, part, kRedBlocks, S);
       GF_LAUNCH_CHECK(ctx);
       const double inner_target = prm.inner_rtol * rnorm;
       int it = 0;
@@ -501,8 +533,7 @@ extern "C" gf_status gf_poisson_solve(gf_ctx *ctx, const gf_particles *p, const 
         if (irn <= inner_target) break;
       }
       hipLaunchKernelGGL(k_add_f32, dim3(sv.grid_row), dim3(kBlock), 0, sm, p_inout, V32.x, n);
-      hipLaunchKernelGGL(k_residual, dim3(sv.grid_team), dim3(kBlock), 0, sm, nbr->row_ptr, nbr->col, val64, rhs,
-                         p_inout, n, V64.r, (double *)nullptr, part, counter, S, 0);
+      launch_residual(sv, val64, rhs, p_inout, V64.r, nullptr, 0);
       GF_LAUNCH_CHECK(ctx);
       if ((st = read_scal(sv))) return st;
       const double prev = rnorm;
