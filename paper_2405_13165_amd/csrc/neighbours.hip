@@ -166,6 +166,72 @@ __global__ void __launch_bounds__(kBlock) k_scatter(const int32_t *__restrict__ 
   order[cell_start[key[i]] + slot[i]] = (int32_t)i;
 }
 
+// Order the particles of each cell by a finer Morton key (kSubBits more bits
+// per axis), so that runs of the cell order stay spatially compact when a
+// cell is much larger than a typical support (uneven h).  One wave per cell,
+// bitonic sort in LDS; cells with more than kCellSort particles keep their
+// order.  The neighbour sets do not depend on this order.
+constexpr int kSubBits = 4;
+constexpr int kCellSort = 2048;
+
+__device__ inline uint64_t fine_key(double x, double y, double z, const Grid &g, int s) {
+  const double f = (double)(1 << kSubBits);
+  int c[3];
+  const double v[3] = {x, y, z};
+  for (int d = 0; d < 3; ++d) {
+    const double t = floor((v[d] - g.lo[s][d]) * g.inv_edge[s] * f);
+    const double hi = (double)g.dim[s][d] * f - 1.0;
+    c[d] = (int)(t < 0.0 ? 0.0 : (t > hi ? hi : t));
+  }
+  uint64_t key = 0;
+  int pos = 0;
+  for (int b = 0; b < 21; ++b)
+    for (int d = 0; d < 3; ++d) key |= (uint64_t)((c[d] >> b) & 1) << pos++;
+  return key;
+}
+
+__global__ void __launch_bounds__(64) k_cell_sort(const int32_t *__restrict__ cell_start, int64_t ncells,
+                                                  const double *__restrict__ x, const double *__restrict__ y,
+                                                  const double *__restrict__ z, const int8_t *__restrict__ model,
+                                                  Grid g, int32_t *__restrict__ order) {
+  __shared__ uint64_t kk[kCellSort];
+  __shared__ int32_t id[kCellSort];
+  for (int64_t c = blockIdx.x; c < ncells; c += gridDim.x) {
+    const int32_t b = cell_start[c], len = cell_start[c + 1] - b;
+    if (len <= 1 || len > kCellSort) continue;
+    int P = 1;
+    while (P < len) P <<= 1;
+    for (int t = threadIdx.x; t < P; t += 64) {
+      if (t < len) {
+        const int32_t i = order[b + t];
+        kk[t] = fine_key(x[i], y[i], z[i], g, grid_slot(g, model[i]));
+        id[t] = i;
+      } else {
+        kk[t] = ~0ull;
+        id[t] = 0x7fffffff;
+      }
+    }
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int t = threadIdx.x; t < P; t += 64) {
+          const int u = t ^ j;
+          if (u > t) {
+            const uint64_t a = kk[t], e = kk[u];
+            const int32_t ia = id[t], ie = id[u];
+            // ties (same sub-cell) by particle index: the order is deterministic
+            const bool gt = (a > e) || (a == e && ia > ie);
+            if (gt == ((t & k) == 0)) { kk[t] = e; kk[u] = a; id[t] = ie; id[u] = ia; }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int t = threadIdx.x; t < len; t += 64) order[b + t] = id[t];
+    __syncthreads();
+  }
+}
+
 __global__ void __launch_bounds__(kBlock) k_gather_pos(const int32_t *__restrict__ order, const double *__restrict__ x,
                                                        const double *__restrict__ y, const double *__restrict__ z,
                                                        const double *__restrict__ h, int64_t n,
@@ -710,6 +776,8 @@ extern "C" gf_status gf_build_neighbours(gf_ctx *ctx, const gf_particles *p, int
   if (hipGetLastError() != hipSuccess) return fail(set_error(ctx, GF_EHIP, "key kernel launch failed"));
   if ((st = scan_i32_to_i32(ctx, cell_start, cell_start, K, tmp32))) return fail(st);
   hipLaunchKernelGGL(k_scatter, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, key, slot, cell_start, n, nb->order);
+  hipLaunchKernelGGL(k_cell_sort, dim3((unsigned)std::min<int64_t>(K, 65536)), dim3(64), 0, sm, cell_start, K, p->x,
+                     p->y, p->z, p->model, g, nb->order);
   hipLaunchKernelGGL(k_gather_pos, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, nb->order, p->x, p->y, p->z, p->h,
                      n, sp);
   ProfScope prof_count(ctx, "nbr_count");
