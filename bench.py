@@ -372,13 +372,13 @@ def main():
             err = ((x - torch.as_tensor(dp["pstar"], device=ctx.device)).norm() /
                    torch.as_tensor(dp["pstar"], device=ctx.device).norm()).item()
             rec = dict(seconds=el, err_vs_pstar=err, **st)
-            # one Jacobi-BiCGStab iteration: two SpMV (values + column index per entry, x gathered,
-            # two vectors) and the vector updates (26 vector passes in all)
+            # one Jacobi-BiCGStab iteration: two SpMV on the neighbour tiles (value + 2-byte slot
+            # per entry; the vector is staged per tile) and the vector updates (26 vector passes)
             for name, vb in (("bicgstab_iter_f64", 8), ("bicgstab_iter_f32", 4)):
                 if name in prof_p:
                     cnt, tot = prof_p[name]
                     it_s = tot / cnt * 1e-3
-                    byts = 2.0 * ps_nnz * (vb + 4) + 26.0 * vb * ps_n
+                    byts = 2.0 * ps_nnz * (vb + 2) + 26.0 * vb * ps_n
                     rec[name] = {"iterations": cnt, "avg_us": round(it_s * 1e6, 1),
                                  "algorithmic_bytes": byts, "GBs": round(byts / it_s / 1e9, 1),
                                  "hbm_frac": round(byts / it_s / 1e9 / PEAK_HBM_GBS, 4)}

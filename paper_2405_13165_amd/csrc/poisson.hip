@@ -26,6 +26,7 @@ using namespace gfdm_dev;
 namespace {
 constexpr int kBlock = 256;
 constexpr int kTeam = 8;
+static_assert(kBlock / kTeam == kTileRows, "one team per row of a neighbour tile");
 
 struct Scal {
   double rho, rho_old, alpha, omega, rv, ts, tt, rr, bb;
@@ -86,6 +87,8 @@ __device__ inline void finish_partials(const double *part, int nblk, double res[
 }
 
 // ---------------------------------------------------------------- assembly
+// One team of kTeam lanes per row (grid-stride): the row's values, its
+// diagonal (found by the lane holding the self entry) and the Jacobi inverse.
 __global__ void __launch_bounds__(kBlock) k_assemble(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
                                                      const double *__restrict__ w, const int8_t *__restrict__ row_type,
                                                      const double *__restrict__ h, const double *__restrict__ nx,
@@ -93,31 +96,38 @@ __global__ void __launch_bounds__(kBlock) k_assemble(const int64_t *__restrict__
                                                      double zeta, int64_t n, double *__restrict__ val64,
                                                      float *__restrict__ val32, double *__restrict__ dinv64,
                                                      float *__restrict__ dinv32, int *__restrict__ bad) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int rt = row_type[i];
-  double nrm[3] = {0.0, 0.0, 0.0};
-  if (rt == GF_ROW_NEUMANN_COMBINED || rt == GF_ROW_NEUMANN) { nrm[0] = nx[i]; nrm[1] = ny[i]; nrm[2] = nz[i]; }
-  const double zf = zeta / h[i];
-  double diag = 0.0;
-  for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
-    const double2 *p = reinterpret_cast<const double2 *>(w) + 2 * k;
-    const double2 g01 = p[0], g23 = p[1];
-    const double ngrad = nrm[0] * g01.x + nrm[1] * g01.y + nrm[2] * g23.x;
-    double v;
-    switch (rt) {
-      case GF_ROW_INTERIOR: v = g23.y; break;
-      case GF_ROW_DIRICHLET: v = (col[k] == i) ? 1.0 : 0.0; break;
-      case GF_ROW_NEUMANN_COMBINED: v = g23.y + zf * ngrad; break;
-      default: v = ngrad; break;
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = (int)(gt % kTeam);
+  const int64_t nteams = (int64_t)gridDim.x * blockDim.x / kTeam;
+  for (int64_t i = gt / kTeam; i < n; i += nteams) {
+    const int rt = row_type[i];
+    double nrm[3] = {0.0, 0.0, 0.0};
+    if (rt == GF_ROW_NEUMANN_COMBINED || rt == GF_ROW_NEUMANN) { nrm[0] = nx[i]; nrm[1] = ny[i]; nrm[2] = nz[i]; }
+    const double zf = zeta / h[i];
+    double diag = 0.0;  // nonzero only on the lane that holds the self entry
+    for (int64_t k = row_ptr[i] + lane; k < row_ptr[i + 1]; k += kTeam) {
+      const double2 *p = reinterpret_cast<const double2 *>(w) + 2 * k;
+      const double2 g01 = p[0], g23 = p[1];
+      const double ngrad = nrm[0] * g01.x + nrm[1] * g01.y + nrm[2] * g23.x;
+      const bool self = col[k] == i;
+      double v;
+      switch (rt) {
+        case GF_ROW_INTERIOR: v = g23.y; break;
+        case GF_ROW_DIRICHLET: v = self ? 1.0 : 0.0; break;
+        case GF_ROW_NEUMANN_COMBINED: v = g23.y + zf * ngrad; break;
+        default: v = ngrad; break;
+      }
+      if (val64) val64[k] = v;
+      if (val32) val32[k] = (float)v;
+      if (self) diag = v;
     }
-    if (val64) val64[k] = v;
-    if (val32) val32[k] = (float)v;
-    if (col[k] == i) diag = v;
+    diag = team_sum(diag, kTeam);  // exactly the self value: the other lanes add zeros
+    if (lane == 0) {
+      if (rt < 0 || rt > 3 || diag == 0.0 || !isfinite(diag)) atomicAdd(bad, 1);
+      if (dinv64) dinv64[i] = (diag != 0.0) ? 1.0 / diag : 0.0;
+      if (dinv32) dinv32[i] = (diag != 0.0) ? (float)(1.0 / diag) : 0.0f;
+    }
   }
-  if (rt < 0 || rt > 3 || diag == 0.0 || !isfinite(diag)) atomicAdd(bad, 1);
-  if (dinv64) dinv64[i] = (diag != 0.0) ? 1.0 / diag : 0.0;
-  if (dinv32) dinv32[i] = (diag != 0.0) ? (float)(1.0 / diag) : 0.0f;
 }
 
 // ---------------------------------------------------------------- kernels
@@ -237,6 +247,84 @@ __global__ void __launch_bounds__(kBlock) k_spmv_dot(const int64_t *__restrict__
   block_partials<2>(v, part);
 }
 
+// Neighbour tiles of the matrix pattern (the neighbour handle's tiles): rows
+// of tile t are grouped[row0[m] + (t - tile_start[m]) kTileRows ...] for the
+// model m owning t; rows with more than kTileBandRow entries are listed per
+// model in grouped[b3_start[m] .. + b3_n[m]).
+struct SpmvTiles {
+  const int64_t *toff;
+  const int32_t *tu;
+  const uint16_t *slot;
+  const int32_t *grouped;
+  int64_t tile_start[3];
+  int64_t row0[2], nrows[2];
+  int64_t b3_start[2], b3_n[2];
+  int cap;  // LDS entries of the staged vector
+};
+
+// y = A xin over tiles: each block walks tiles (grid-stride); a tile stages
+// the entries of xin it references in LDS and its 32 rows (one team of
+// kTeam lanes each) read them through slot[]; then the untiled rows.
+// Partials of (other, y) and (y, y).
+template <typename VT, typename XT>
+__global__ void __launch_bounds__(kBlock) k_spmv_tiles(const int64_t *__restrict__ row_ptr,
+                                                       const int32_t *__restrict__ col, const VT *__restrict__ val,
+                                                       const XT *__restrict__ xin, XT *__restrict__ y,
+                                                       const XT *__restrict__ other, double *part,
+                                                       const Scal *__restrict__ S, SpmvTiles tl) {
+  extern __shared__ unsigned char s_raw[];
+  XT *sx = reinterpret_cast<XT *>(s_raw);
+  double v[2] = {0.0, 0.0};
+  const int team = threadIdx.x / kTeam, lane = threadIdx.x % kTeam;
+  auto finish_row = [&](int32_t row, double acc) {
+    acc = team_sum(acc, kTeam);
+    if (lane == 0) {
+      const XT yi = (XT)acc;
+      y[row] = yi;
+      v[0] += (double)other[row] * (double)yi;
+      v[1] += (double)yi * (double)yi;
+    }
+  };
+  if (!S->breakdown) {
+    const int64_t ntiles = tl.tile_start[2];
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+      const int m = (t >= tl.tile_start[1]) ? 1 : 0;
+      const int64_t r0 = (t - tl.tile_start[m]) * kTileRows;
+      const int64_t u0 = tl.toff[t];
+      const int cnt = (int)(tl.toff[t + 1] - u0);
+      const bool staged = cnt <= tl.cap;
+      __syncthreads();  // the previous tile is done with sx
+      if (staged)
+        for (int s = threadIdx.x; s < cnt; s += blockDim.x) sx[s] = xin[tl.tu[u0 + s]];
+      __syncthreads();
+      if (r0 + team < tl.nrows[m]) {
+        const int32_t row = tl.grouped[tl.row0[m] + r0 + team];
+        const int64_t b = row_ptr[row], e = row_ptr[row + 1];
+        double acc = 0.0;
+        if (staged) {
+#pragma unroll 8
+          for (int64_t k = b + lane; k < e; k += kTeam) acc += (double)val[k] * (double)sx[tl.slot[k]];
+        } else {
+          for (int64_t k = b + lane; k < e; k += kTeam) acc += (double)val[k] * (double)xin[col[k]];
+        }
+        finish_row(row, acc);
+      }
+    }
+    // untiled rows: teams grid-stride over each model's list
+    const int64_t gteam = (int64_t)blockIdx.x * (blockDim.x / kTeam) + team;
+    const int64_t nteams = (int64_t)gridDim.x * (blockDim.x / kTeam);
+    for (int m = 0; m < 2; ++m) {
+      for (int64_t q = gteam; q < tl.b3_n[m]; q += nteams) {
+        const int32_t row = tl.grouped[tl.b3_start[m] + q];
+        double acc = 0.0;
+        for (int64_t k = row_ptr[row] + lane; k < row_ptr[row + 1]; k += kTeam) acc += (double)val[k] * (double)xin[col[k]];
+        finish_row(row, acc);
+      }
+    }
+  }
+  block_partials<2>(v, part);
+}
+
 // STAGE 0: alpha = rho / (rhat, v);  STAGE 1: omega = (t, s) / (t, t)
 template <int STAGE>
 __global__ void __launch_bounds__(kFinThreads) k_fin_spmv(const double *part, int nblk, Scal *S) {
@@ -316,7 +404,41 @@ struct Solver {
   Scal *S;
   Scal *hS;
   unsigned grid_row;
+  bool tiled;    // the SpMV runs on the neighbour tiles
+  SpmvTiles tl;
 };
+
+// staged-vector capacity of the tiled SpMV (entries)
+constexpr int kSpmvCap = 2048;
+
+void init_spmv_tiles(Solver &sv) {
+  const gf_nbr *nb = sv.nbr;
+  sv.tiled = nb->ntiles > 0 && nb->slot && nb->tile_u && nb->tile_off;
+  SpmvTiles &t = sv.tl;
+  t.toff = nb->tile_off; t.tu = nb->tile_u; t.slot = nb->slot; t.grouped = nb->grouped;
+  for (int k = 0; k < 3; ++k) t.tile_start[k] = nb->tile_start[k];
+  int cap = 0;
+  for (int m = 0; m < 2; ++m) {
+    t.row0[m] = nb->group_start[m * GF_NBAND];
+    t.nrows[m] = nb->group_start[m * GF_NBAND + kTileBand + 1] - t.row0[m];
+    t.b3_start[m] = nb->group_start[m * GF_NBAND + kTileBand + 1];
+    t.b3_n[m] = nb->group_start[(m + 1) * GF_NBAND] - t.b3_start[m];
+    cap = std::max(cap, nb->tile_max[m]);
+  }
+  t.cap = std::min(cap, kSpmvCap);
+}
+
+// y = A xin with the partials of (other, y), (y, y)
+template <typename VT, typename XT>
+void launch_spmv(Solver &sv, const VT *val, const XT *xin, XT *y, const XT *other) {
+  hipStream_t sm = sv.ctx->stream;
+  if (sv.tiled)
+    hipLaunchKernelGGL((k_spmv_tiles<VT, XT>), dim3(kRedBlocks), dim3(kBlock), sizeof(XT) * sv.tl.cap, sm,
+                       sv.nbr->row_ptr, sv.nbr->col, val, xin, y, other, sv.part, sv.S, sv.tl);
+  else
+    hipLaunchKernelGGL((k_spmv_dot<VT, XT>), dim3(kRedBlocks), dim3(kBlock), 0, sm, sv.nbr->row_ptr, sv.nbr->col, val,
+                       xin, sv.n, y, other, sv.part, sv.S);
+}
 
 gf_status read_scal(Solver &sv) {
   GF_HIP(sv.ctx, hipMemcpyAsync(sv.hS, sv.S, sizeof(Scal), hipMemcpyDeviceToHost, sv.ctx->stream));
@@ -347,12 +469,10 @@ gf_status bicgstab_iter(Solver &sv, const Vecs<VT, XT> &V) {
   const int64_t n = sv.n;
   ProfScope prof(sv.ctx, sizeof(VT) == 8 ? "bicgstab_iter_f64" : "bicgstab_iter_f32");
   hipLaunchKernelGGL((k_update_p<XT>), dim3(sv.grid_row), dim3(kBlock), 0, sm, V.r, V.v, V.dinv, n, V.p, V.phat, sv.S);
-  hipLaunchKernelGGL((k_spmv_dot<VT, XT>), dim3(kRedBlocks), dim3(kBlock), 0, sm, sv.nbr->row_ptr, sv.nbr->col, V.val,
-                     V.phat, n, V.v, V.rhat, sv.part, sv.S);
+  launch_spmv<VT, XT>(sv, V.val, V.phat, V.v, V.rhat);
   hipLaunchKernelGGL((k_fin_spmv<0>), dim3(1), dim3(kFinThreads), 0, sm, sv.part, kRedBlocks, sv.S);
   hipLaunchKernelGGL((k_update_s<XT>), dim3(sv.grid_row), dim3(kBlock), 0, sm, V.r, V.v, V.dinv, n, V.s, V.shat, sv.S);
-  hipLaunchKernelGGL((k_spmv_dot<VT, XT>), dim3(kRedBlocks), dim3(kBlock), 0, sm, sv.nbr->row_ptr, sv.nbr->col, V.val,
-                     V.shat, n, V.t, V.s, sv.part, sv.S);
+  launch_spmv<VT, XT>(sv, V.val, V.shat, V.t, V.s);
   hipLaunchKernelGGL((k_fin_spmv<1>), dim3(1), dim3(kFinThreads), 0, sm, sv.part, kRedBlocks, sv.S);
   hipLaunchKernelGGL((k_update_xr<XT>), dim3(kRedBlocks), dim3(kBlock), 0, sm, V.phat, V.shat, V.s, V.t, V.rhat, n,
                      V.x, V.r, sv.part, sv.S);
@@ -376,7 +496,7 @@ extern "C" void gf_solve_params_default(gf_solve_params *p) {
 static gf_status assemble_common(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr, const double *w64,
                                  const int8_t *row_type, double zeta, double *val64, float *val32, double *dinv64,
                                  float *dinv32, int *bad) {
-  hipLaunchKernelGGL(k_assemble, dim3(grid_for(p->n, kBlock)), dim3(kBlock), 0, ctx->stream, nbr->row_ptr, nbr->col,
+  hipLaunchKernelGGL(k_assemble, dim3(kRedBlocks), dim3(kBlock), 0, ctx->stream, nbr->row_ptr, nbr->col,
                      w64, row_type, p->h, p->nx, p->ny, p->nz, zeta, p->n, val64, val32, dinv64, dinv32, bad);
   GF_LAUNCH_CHECK(ctx);
   return GF_OK;
@@ -455,6 +575,7 @@ extern "C" gf_status gf_poisson_solve(gf_ctx *ctx, const gf_particles *p, const 
   sv.ctx = ctx; sv.nbr = nbr; sv.n = n; sv.part = part; sv.S = S;
   sv.hS = (Scal *)ctx->host_pinned;
   sv.grid_row = (unsigned)nblk_row;
+  init_spmv_tiles(sv);
   int *hbad = (int *)((char *)ctx->host_pinned + 1024);
   GF_HIP(ctx, hipMemcpyAsync(hbad, bad, sizeof(int), hipMemcpyDeviceToHost, sm));
   // FP64 work vectors: x is the caller's array
