@@ -320,27 +320,40 @@ def main():
     if not args.no_rows:
         rows = {"build_neighbours_first_ms": t_nbr_first * 1e3}
 
-        def once(fn):
+        kern = {}
+
+        def once(fn, key=None):
+            """Wall time of one call after a warm-up call; with key, also the
+            library's own per-kernel times of that call."""
             fn()
             torch.cuda.synchronize()
+            if key:
+                ctx.profile(True)
             t = time.perf_counter()
             r = fn()
             torch.cuda.synchronize()
-            return (time.perf_counter() - t) * 1e3, r
+            el = (time.perf_counter() - t) * 1e3
+            if key:
+                kern[key] = {k: round(1000.0 * tt / c, 1) for k, (c, tt) in ctx.profile_read().items()}
+                ctx.profile(False)
+            return el, r
 
-        rows["build_neighbours_ms"], nb2 = once(lambda: g.build_neighbours(ctx, p))
+        rows["build_neighbours_ms"], nb2 = once(lambda: g.build_neighbours(ctx, p), "build_neighbours")
         del nb2
         xnb = g.build_neighbours(ctx, p, cross_model=True)
         rows["classify_pca_ms"], cl = once(lambda: g.classify_pca(ctx, p, nb, xnb, film_height=d["film_height"],
-                                                                 h3d=d["h3d"]))
+                                                                 h3d=d["h3d"]), "classify_pca")
         flag = cl[3]
         mass = torch.ones(N, dtype=torch.float64, device=ctx.device)
         rho = torch.full((N,), 1000.0, dtype=torch.float64, device=ctx.device)
-        rows["transition_ms"], _ = once(lambda: g.transition_3d_to_2d(ctx, p, nb, flag, mass, rho, u))
+        rows["transition_ms"], _ = once(lambda: g.transition_3d_to_2d(ctx, p, nb, flag, mass, rho, u), "transition")
         ybar = torch.ones((1, N), dtype=torch.float64, device=ctx.device)
-        rows["apply_adjoint_ms"], _ = once(lambda: g.apply_stencil_adjoint(ctx, nb, w32, ybar, g.OP_LAP))
-        rows["weights_adjoint_ms"], _ = once(lambda: g.gfdm_weights_adjoint(ctx, p, nb, u, ybar, g.OP_LAP))
+        rows["apply_adjoint_ms"], _ = once(lambda: g.apply_stencil_adjoint(ctx, nb, w32, ybar, g.OP_LAP),
+                                           "apply_adjoint")
+        rows["weights_adjoint_ms"], _ = once(lambda: g.gfdm_weights_adjoint(ctx, p, nb, u, ybar, g.OP_LAP),
+                                             "weights_adjoint")
         result["rows"] = rows
+        result["rows_kernels_us"] = kern
         result["flags"] = {"bulk_to_film": int((flag == 1).sum().item()), "film_to_bulk": int((flag == 2).sum().item())}
 
     if args.poisson:

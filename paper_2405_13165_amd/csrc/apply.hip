@@ -131,13 +131,17 @@ constexpr int kApplyCap = 2048;
 // ubar_j = sum_{i : j in S_i, i != j} c_ij ybar_i - ybar_j sum_{k in S_j, k != j} c_jk,
 // the first sum gathered through the reverse-edge map (entry (i,j) sits at
 // rev[k] for the entry k = (j,i) of row j).
+// One team of kAdjTeam lanes per row j (the lanes stride over the row).
+constexpr int kAdjTeam = 8;
 template <typename WT>
 __global__ void __launch_bounds__(kBlock) k_apply_adjoint(const int64_t *__restrict__ row_ptr,
                                                           const int32_t *__restrict__ col,
                                                           const int32_t *__restrict__ rev, const void *__restrict__ w,
                                                           unsigned mask, const double *__restrict__ ybar, int64_t n,
                                                           double *__restrict__ ubar) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gt = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const int64_t j = gt / kAdjTeam;
+  const int lane = (int)(gt % kAdjTeam);
   if (j >= n) return;
   int sel[4], K = 0;
   for (int s = 0; s < 4; ++s)
@@ -145,16 +149,18 @@ __global__ void __launch_bounds__(kBlock) k_apply_adjoint(const int64_t *__restr
   double yj[4];
   for (int q = 0; q < K; ++q) yj[q] = ybar[(int64_t)q * n + j];
   double acc = 0.0;
-  for (int64_t k = row_ptr[j]; k < row_ptr[j + 1]; ++k) {
+#pragma unroll 4
+  for (int64_t k = row_ptr[j] + lane; k < row_ptr[j + 1]; k += kAdjTeam) {
     const int32_t i = col[k];
     const int32_t kr = rev[k];
     if (i == j || kr < 0) continue;
     double cin[4], cout_[4];
-    W4<WT>::load(w, kr, cin);  // c_ij (row i, column j)
-    W4<WT>::load(w, k, cout_);     // c_ji (row j, column i)
+    W4<WT>::load(w, kr, cin);   // c_ij (row i, column j)
+    W4<WT>::load(w, k, cout_);  // c_ji (row j, column i)
     for (int q = 0; q < K; ++q) acc += cin[sel[q]] * ybar[(int64_t)q * n + i] - cout_[sel[q]] * yj[q];
   }
-  ubar[j] = acc;
+  acc = team_sum(acc, kAdjTeam);
+  if (lane == 0) ubar[j] = acc;
 }
 
 template <typename WT, typename IOT>
@@ -281,7 +287,7 @@ extern "C" gf_status gf_apply_stencil_adjoint(gf_ctx *ctx, const gf_nbr *nbr, gf
   if (wtype != GF_F32 && wtype != GF_F64) return set_error(ctx, GF_EINVAL, "unknown dtype");
   GF_HIP(ctx, hipSetDevice(ctx->device));
   if ((st = ensure_rev(ctx, const_cast<gf_nbr *>(nbr)))) return st;
-  const dim3 grid(grid_for(nbr->n, kBlock)), block(kBlock);
+  const dim3 grid(grid_for(nbr->n * kAdjTeam, kBlock)), block(kBlock);
   ProfScope prof(ctx, "apply_adjoint");
   if (wtype == GF_F32)
     hipLaunchKernelGGL(k_apply_adjoint<float>, grid, block, 0, ctx->stream, nbr->row_ptr, nbr->col, nbr->rev, w, op_mask, ybar, nbr->n, ubar);

@@ -384,7 +384,14 @@ struct TileGroups {
   int64_t nrows[2];
 };
 constexpr int kTileEntries = kTileRows * kTileBandRow;  // entries one tile can hold
-constexpr int kTileThreads = 256;
+constexpr int kTileThreads = 512;
+
+// orders the LDS traffic of the lanes of one wave
+__device__ inline void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __device__ inline int tile_group(const TileGroups &tg, int64_t t) {
   int q = 0;
@@ -466,6 +473,9 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_unique(TileGroups tg, con
     }
   }
   __syncthreads();
+  // Bitonic network.  Element e is handled by thread e mod kTileThreads, so a
+  // stage of distance j < 64 pairs lanes of one wave; a block barrier is
+  // only needed around stages of distance >= 64.
   for (int k = 2; k <= P; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
       for (int e = tid; e < P; e += kTileThreads) {
@@ -475,9 +485,12 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_unique(TileGroups tg, con
           if ((a > b) == ((e & k) == 0)) { key[e] = b; key[u] = a; }
         }
       }
-      __syncthreads();
+      const int jn = (j > 1) ? (j >> 1) : k;  // distance of the next stage
+      if (j >= 64 || jn >= 64) __syncthreads();
+      else wave_fence();
     }
   }
+  __syncthreads();
   // each thread numbers a contiguous chunk of the sorted list
   const int chunk = (P + kTileThreads - 1) / kTileThreads;
   const int s0 = tid * chunk;
@@ -486,10 +499,11 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_unique(TileGroups tg, con
     c += (s == 0 || (key[s] >> 12) != (key[s - 1] >> 12)) ? 1 : 0;
   csum[tid] = c;
   __syncthreads();
-  if (tid < 64) {  // exclusive scan of the 256 chunk counts by one wave
-    int v[4], tot = 0;
+  if (tid < 64) {  // exclusive scan of the chunk counts by one wave
+    constexpr int kPer = kTileThreads / 64;
+    int v[kPer], tot = 0;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) { v[u] = csum[tid * 4 + u]; tot += v[u]; }
+    for (int u = 0; u < kPer; ++u) { v[u] = csum[tid * kPer + u]; tot += v[u]; }
     int inc = tot;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -498,7 +512,7 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_unique(TileGroups tg, con
     }
     int run = inc - tot;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) { csum[tid * 4 + u] = run; run += v[u]; }
+    for (int u = 0; u < kPer; ++u) { csum[tid * kPer + u] = run; run += v[u]; }
     if (tid == 63) {
       cnt[t] = inc;
       atomicMax(&grp_max[q], inc);
@@ -531,15 +545,18 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_compact(const int64_t *__
 }
 
 // reverse-edge map: rev[k] = position of (j, i) in row j for entry k = (i, j)
+// (binary search in the sorted row j); a team of kRevTeam lanes per row i
+constexpr int kRevTeam = 8;
 __global__ void __launch_bounds__(kBlock) k_rev(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
                                                 int64_t n, int32_t *__restrict__ rev) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = gt / kRevTeam;
   if (i >= n) return;
-  for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
-    int32_t j = col[k];
+  for (int64_t k = row_ptr[i] + gt % kRevTeam; k < row_ptr[i + 1]; k += kRevTeam) {
+    const int32_t j = col[k];
     int64_t lo = row_ptr[j], hi = row_ptr[j + 1];
     while (lo < hi) {
-      int64_t mid = (lo + hi) >> 1;
+      const int64_t mid = (lo + hi) >> 1;
       if (col[mid] < i) lo = mid + 1; else hi = mid;
     }
     rev[k] = (lo < row_ptr[j + 1] && col[lo] == i) ? (int32_t)lo : -1;
@@ -590,11 +607,14 @@ extern "C" gf_status gf_nbr_export(gf_ctx *ctx, const gf_nbr *nbr, int64_t *row_
 
 gf_status ensure_rev(gf_ctx *ctx, gf_nbr *nbr) {
   if (nbr->rev) return GF_OK;
+  if (nbr->nnz > (int64_t)0x7fffffff)
+    return set_error(ctx, GF_ECAPACITY, "the reverse-edge map holds 32-bit positions; %lld entries exceed it",
+                     (long long)nbr->nnz);
   if (hipMalloc(&nbr->rev, sizeof(int32_t) * std::max<int64_t>(nbr->nnz, 1)) != hipSuccess) {
     nbr->rev = nullptr;
     return set_error(ctx, GF_ENOMEM, "reverse-edge map allocation failed");
   }
-  hipLaunchKernelGGL(k_rev, dim3(grid_for(nbr->n, kBlock)), dim3(kBlock), 0, ctx->stream, nbr->row_ptr, nbr->col,
+  hipLaunchKernelGGL(k_rev, dim3(grid_for(nbr->n * kRevTeam, kBlock)), dim3(kBlock), 0, ctx->stream, nbr->row_ptr, nbr->col,
                      nbr->n, nbr->rev);
   GF_LAUNCH_CHECK(ctx);
   return GF_OK;
@@ -769,6 +789,8 @@ extern "C" gf_status gf_build_neighbours(gf_ctx *ctx, const gf_particles *p, int
     return fail(set_error(ctx, GF_ENOMEM, "neighbour handle allocation failed"));
   }
 
+  {
+  ProfScope prof_cells(ctx, "nbr_cells");
   hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(K + 1, kBlock)), dim3(kBlock), 0, sm, cell_start, K + 1, 0);
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, sm, small, (int64_t)16, 0);
   hipLaunchKernelGGL(k_keys, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, p->x, p->y, p->z, p->model, n, g, key,
@@ -780,9 +802,12 @@ extern "C" gf_status gf_build_neighbours(gf_ctx *ctx, const gf_particles *p, int
                      p->y, p->z, p->model, g, nb->order);
   hipLaunchKernelGGL(k_gather_pos, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, nb->order, p->x, p->y, p->z, p->h,
                      n, sp);
+  }
+  {
   ProfScope prof_count(ctx, "nbr_count");
   hipLaunchKernelGGL(k_search<0>, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, nb->order, sp, p->model,
                      cell_start, n, g, cnt, small, small + 8, (const int64_t *)nullptr, (int32_t *)nullptr);
+  }
   if (hipGetLastError() != hipSuccess) return fail(set_error(ctx, GF_EHIP, "count kernel launch failed"));
   if ((st = scan_i32_to_i64(ctx, cnt, nb->row_ptr, n, tmp64))) return fail(st);
   int32_t *hsmall = (int32_t *)ctx->host_pinned;
@@ -807,14 +832,20 @@ extern "C" gf_status gf_build_neighbours(gf_ctx *ctx, const gf_particles *p, int
   if (nb->nnz >= (int64_t)1 << 40) return fail(set_error(ctx, GF_ECAPACITY, "too many neighbour pairs"));
   if (hipMalloc(&nb->col, sizeof(int32_t) * std::max<int64_t>(nb->nnz, 1)) != hipSuccess)
     return fail(set_error(ctx, GF_ENOMEM, "neighbour list allocation (%lld entries) failed", (long long)nb->nnz));
-  ProfScope prof_fill(ctx, "nbr_fill_sort");
+  {
+  ProfScope prof_fill(ctx, "nbr_fill");
   hipLaunchKernelGGL(k_search<1>, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, nb->order, sp, p->model,
                      cell_start, n, g, (int32_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr, nb->row_ptr,
                      nb->col);
+  }
+  {
+  ProfScope prof_sort(ctx, "nbr_row_sort");
   hipLaunchKernelGGL(k_row_sort, dim3((unsigned)n), dim3(64), 0, sm, nb->row_ptr, nb->col, n);
+  }
   if (hipGetLastError() != hipSuccess) return fail(set_error(ctx, GF_EHIP, "fill/sort kernel launch failed"));
 
   // ---- groups by (model, band), Morton order kept inside each group
+  ProfScope prof_group(ctx, "nbr_group_tiles");
   int64_t off = 0;
   for (int gsel = 0; gsel < 2 * GF_NBAND; ++gsel) {
     nb->group_start[gsel] = off;

@@ -1,14 +1,20 @@
 // Local PCA of every neighbourhood and the transition flags of Sec. 4.
 //
-// One work-item per particle, particles taken in cell (Morton) order so that
-// concurrently running waves gather overlapping neighbourhoods.  The 3x3
+// A team of kTeam lanes per particle.  Rows with at most 128 neighbours run
+// one neighbour tile per block: the tile's distinct neighbours (position,
+// index and kind) are staged in LDS and both passes read them through the
+// tile slots; rows with more neighbours gather from global memory.  The 3x3
 // covariance is built in two passes (centroid, then centred second moments)
 // from offsets relative to the particle itself, so an exactly planar
-// neighbourhood yields an exactly zero third eigenvalue.
-#include "internal.h"
+// neighbourhood yields an exactly zero third eigenvalue; one lane of the team
+// then runs the eigen solve and the classification.
+#include "stencil_common.h"
+
+using namespace gfdm_dev;
 
 namespace {
 constexpr int kBlock = 256;
+constexpr int kTeam = 4;
 
 // Symmetric 3x3 eigen-decomposition by Jacobi rotations (each rotation
 // annihilates one off-diagonal entry; sweeps until the off-diagonal mass is
@@ -62,8 +68,8 @@ struct PcaArgs {
   const double *nx, *ny, *nz;
   const int64_t *row_ptr;
   const int32_t *col;
-  const int32_t *order;
-  int64_t n;
+  const int32_t *sched;  // rows of the launch (a range of the grouped order)
+  int64_t nrows;
   const double *film_height, *h3d;
   const uint8_t *prev, *user;
   double eps_max, cos_theta;
@@ -72,35 +78,9 @@ struct PcaArgs {
   uint8_t *raw;
 };
 
-__global__ void __launch_bounds__(kBlock) k_pca_flags(PcaArgs a) {
-  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= a.n) return;
-  const int32_t i = a.order[s];
-  const int64_t b = a.row_ptr[i], e = a.row_ptr[i + 1];
-  const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
-  double mx = 0.0, my = 0.0, mz = 0.0;
-  int n_int = 0, n_fs = 0;
-  const bool need_kinds = a.raw && a.kind;
-  for (int64_t k = b; k < e; ++k) {
-    const int32_t j = a.col[k];
-    mx += a.x[j] - xi;
-    my += a.y[j] - yi;
-    mz += a.z[j] - zi;
-    if (need_kinds && j != i) {
-      const int kj = a.kind[j];
-      n_int += (kj == GF_KIND_INTERIOR);
-      n_fs += (kj == GF_KIND_FREE_SURFACE);
-    }
-  }
-  const double inv = 1.0 / (double)(e - b);
-  mx *= inv; my *= inv; mz *= inv;
-  double c00 = 0, c01 = 0, c02 = 0, c11 = 0, c12 = 0, c22 = 0;
-  for (int64_t k = b; k < e; ++k) {
-    const int32_t j = a.col[k];
-    const double dx = (a.x[j] - xi) - mx, dy = (a.y[j] - yi) - my, dz = (a.z[j] - zi) - mz;
-    c00 += dx * dx; c01 += dx * dy; c02 += dx * dz;
-    c11 += dy * dy; c12 += dy * dz; c22 += dz * dz;
-  }
+// eigen decomposition of the covariance, outputs and the flags of particle i
+__device__ void pca_finish(const PcaArgs &a, int32_t i, int n_int, int n_fs, double c00, double c01, double c02,
+                           double c11, double c12, double c22) {
   double lam[3], V[3][3];
   sym3_eigen(c00, c01, c02, c11, c12, c22, lam, V);
   // order descending; equal values keep their original order
@@ -143,6 +123,97 @@ __global__ void __launch_bounds__(kBlock) k_pca_flags(PcaArgs a) {
   a.raw[i] = f;
 }
 
+// A neighbour as (x, y, z, 4 index + kind code): the index and the code
+// (kind 0..2, anything else 3) are exact in the FP64 field.
+__device__ inline double pca_code(const PcaArgs &a, int32_t j) {
+  const int k = a.kind ? (int)a.kind[j] : 0;
+  return (double)(4 * (int64_t)j + ((k >= 0 && k <= 2) ? k : 3));
+}
+struct PcaTile {   // staged in LDS, addressed by slot[]
+  const double4 *sp;
+  const uint16_t *slot;
+  __device__ double4 operator()(const PcaArgs &, int64_t k) const { return sp[slot[k]]; }
+};
+struct PcaGlobal {
+  __device__ double4 operator()(const PcaArgs &a, int64_t k) const {
+    const int32_t j = a.col[k];
+    return make_double4(a.x[j], a.y[j], a.z[j], pca_code(a, j));
+  }
+};
+
+template <class F>
+__device__ void pca_row(const PcaArgs &a, int32_t i, int lane, const F &fetch) {
+  const int64_t b = a.row_ptr[i], e = a.row_ptr[i + 1];
+  const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
+  const bool need_kinds = a.raw && a.kind;
+  double mx = 0.0, my = 0.0, mz = 0.0;
+  int n_int = 0, n_fs = 0;
+  for (int64_t k = b + lane; k < e; k += kTeam) {
+    const double4 pj = fetch(a, k);
+    mx += pj.x - xi;
+    my += pj.y - yi;
+    mz += pj.z - zi;
+    if (need_kinds) {
+      const int64_t code = (int64_t)pj.w;
+      if ((code >> 2) != i) {
+        const int kj = (int)(code & 3);
+        n_int += (kj == GF_KIND_INTERIOR);
+        n_fs += (kj == GF_KIND_FREE_SURFACE);
+      }
+    }
+  }
+  mx = team_sum(mx, kTeam);
+  my = team_sum(my, kTeam);
+  mz = team_sum(mz, kTeam);
+  n_int = team_sum(n_int, kTeam);
+  n_fs = team_sum(n_fs, kTeam);
+  const double inv = 1.0 / (double)(e - b);
+  mx *= inv; my *= inv; mz *= inv;
+  double c[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t k = b + lane; k < e; k += kTeam) {
+    const double4 pj = fetch(a, k);
+    const double dx = (pj.x - xi) - mx, dy = (pj.y - yi) - my, dz = (pj.z - zi) - mz;
+    c[0] += dx * dx; c[1] += dx * dy; c[2] += dx * dz;
+    c[3] += dy * dy; c[4] += dy * dz; c[5] += dz * dz;
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) c[q] = team_sum(c[q], kTeam);
+  if (lane == 0) pca_finish(a, i, n_int, n_fs, c[0], c[1], c[2], c[3], c[4], c[5]);
+}
+
+// tiled rows: one neighbour tile per block, kTileRows teams
+__global__ void __launch_bounds__(kTileRows * kTeam) k_pca_tile(PcaArgs a, const int64_t *__restrict__ toff,
+                                                                const int32_t *__restrict__ tu,
+                                                                const uint16_t *__restrict__ slot, int64_t tile0,
+                                                                int cap) {
+  extern __shared__ double4 s_pos[];
+  const int64_t tl = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t u0 = toff[tile0 + tl];
+  const int cnt = (int)(toff[tile0 + tl + 1] - u0);
+  const bool staged = cnt <= cap;
+  if (staged) {
+    for (int s = threadIdx.x; s < cnt; s += blockDim.x) {
+      const int32_t j = tu[u0 + s];
+      s_pos[s] = make_double4(a.x[j], a.y[j], a.z[j], pca_code(a, j));
+    }
+  }
+  __syncthreads();
+  const int team = threadIdx.x / kTeam, lane = threadIdx.x % kTeam;
+  const int64_t r = tl * kTileRows + team;
+  if (r >= a.nrows) return;
+  const int32_t i = a.sched[r];
+  if (staged) pca_row(a, i, lane, PcaTile{s_pos, slot});
+  else pca_row(a, i, lane, PcaGlobal{});
+}
+
+// untiled rows: teams over the rows of the launch, gathers from global memory
+__global__ void __launch_bounds__(kBlock) k_pca_flags(PcaArgs a) {
+  const int64_t gt = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const int64_t r = gt / kTeam;
+  if (r >= a.nrows) return;
+  pca_row(a, a.sched[r], (int)(gt % kTeam), PcaGlobal{});
+}
+
 // smoothing rule 1 over the cross-model neighbourhood
 __global__ void __launch_bounds__(kBlock) k_smooth(const uint8_t *__restrict__ raw, const int8_t *__restrict__ model,
                                                    const int64_t *__restrict__ xrow, const int32_t *__restrict__ xcol,
@@ -162,6 +233,9 @@ __global__ void __launch_bounds__(kBlock) k_smooth(const uint8_t *__restrict__ r
   }
   flag[i] = f;
 }
+
+// neighbour positions a tile block may stage (larger tiles gather)
+constexpr int kPcaCap = 1024;
 }  // namespace
 
 extern "C" void gf_pca_params_default(gf_pca_params *p) {
@@ -193,14 +267,28 @@ extern "C" gf_status gf_classify_pca(gf_ctx *ctx, const gf_particles *p, const g
   PcaArgs a;
   a.x = p->x; a.y = p->y; a.z = p->z; a.model = p->model; a.kind = p->kind;
   a.nx = p->nx; a.ny = p->ny; a.nz = p->nz;
-  a.row_ptr = same->row_ptr; a.col = same->col; a.order = same->order; a.n = n;
+  a.row_ptr = same->row_ptr; a.col = same->col;
   a.film_height = film_height; a.h3d = h3d; a.prev = prev_transitioned; a.user = user_flag;
   a.eps_max = prm.eps_lambda_max; a.cos_theta = std::cos(prm.theta_star); a.literal = prm.literal_rule;
   a.lam = lam_3n; a.w3 = w3_3n; a.eps = eps_n; a.raw = raw;
   ProfScope prof(ctx, "pca_flags");
-  hipLaunchKernelGGL(k_pca_flags, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, ctx->stream, a);
-  GF_LAUNCH_CHECK(ctx);
+  LaunchUnit units[2 * GF_NBAND];
+  const int nu = launch_units(same, units);
+  for (int q = 0; q < nu; ++q) {
+    const LaunchUnit &u = units[q];
+    a.sched = same->grouped + u.row0;
+    a.nrows = u.nrows;
+    if (u.tiled) {
+      const int cap = std::min(u.tile_max, kPcaCap);
+      hipLaunchKernelGGL(k_pca_tile, dim3(grid_for(u.ntiles, 1)), dim3(kTileRows * kTeam), sizeof(double4) * cap,
+                         ctx->stream, a, same->tile_off, same->tile_u, same->slot, u.tile0, cap);
+    } else {
+      hipLaunchKernelGGL(k_pca_flags, dim3(grid_for(u.nrows * kTeam, kBlock)), dim3(kBlock), 0, ctx->stream, a);
+    }
+    GF_LAUNCH_CHECK(ctx);
+  }
   if (flag_n) {
+    ProfScope prof_s(ctx, "pca_smooth");
     hipLaunchKernelGGL(k_smooth, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, ctx->stream, raw, p->model,
                        cross ? cross->row_ptr : nullptr, cross ? cross->col : nullptr, n, flag_n);
     GF_LAUNCH_CHECK(ctx);
