@@ -167,25 +167,34 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_x(AArgs a) {
   adjoint_row<M>(a, a.sched[team], lane);
 }
 
-// xbar_j += sum_{k in row j, col[k] != j} (dbar[rev[k]] - dbar[k])
+// xbar_j += sum_{k in row j, col[k] != j} (dbar[rev[k]] - dbar[k]); a team
+// of kT lanes per row
 __global__ void __launch_bounds__(kBlock) k_adjoint_gather(const int64_t *__restrict__ row_ptr,
                                                            const int32_t *__restrict__ col,
                                                            const int32_t *__restrict__ rev,
                                                            const double *__restrict__ dbar, int64_t n,
                                                            double *__restrict__ xbar) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gt = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const int64_t j = gt / kT;
+  const int lane = (int)(gt % kT);
   if (j >= n) return;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  for (int64_t k = row_ptr[j]; k < row_ptr[j + 1]; ++k) {
+#pragma unroll 4
+  for (int64_t k = row_ptr[j] + lane; k < row_ptr[j + 1]; k += kT) {
     const int32_t kr = rev[k];
     if (col[k] == j || kr < 0) continue;
     s0 += dbar[3 * (int64_t)kr] - dbar[3 * k];
     s1 += dbar[3 * (int64_t)kr + 1] - dbar[3 * k + 1];
     s2 += dbar[3 * (int64_t)kr + 2] - dbar[3 * k + 2];
   }
-  xbar[3 * j] += s0;
-  xbar[3 * j + 1] += s1;
-  xbar[3 * j + 2] += s2;
+  s0 = team_sum(s0, kT);
+  s1 = team_sum(s1, kT);
+  s2 = team_sum(s2, kT);
+  if (lane == 0) {
+    xbar[3 * j] += s0;
+    xbar[3 * j + 1] += s1;
+    xbar[3 * j + 2] += s2;
+  }
 }
 }  // namespace
 
@@ -225,8 +234,11 @@ extern "C" gf_status gf_gfdm_weights_adjoint(gf_ctx *ctx, const gf_particles *p,
     else hipLaunchKernelGGL(k_adjoint_x<6>, grid, block, 0, ctx->stream, a);
     GF_LAUNCH_CHECK(ctx);
   }
-  hipLaunchKernelGGL(k_adjoint_gather, dim3(grid_for(p->n, kBlock)), dim3(kBlock), 0, ctx->stream, nbr->row_ptr,
-                     nbr->col, nbr->rev, a.dbar, p->n, xbar_3n);
-  GF_LAUNCH_CHECK(ctx);
+  {
+    ProfScope prof(ctx, "weights_adjoint_gather");
+    hipLaunchKernelGGL(k_adjoint_gather, dim3(grid_for(p->n * kT, kBlock)), dim3(kBlock), 0, ctx->stream,
+                       nbr->row_ptr, nbr->col, nbr->rev, a.dbar, p->n, xbar_3n);
+    GF_LAUNCH_CHECK(ctx);
+  }
   return GF_OK;
 }
