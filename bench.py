@@ -346,7 +346,11 @@ def main():
         flag = cl[3]
         mass = torch.ones(N, dtype=torch.float64, device=ctx.device)
         rho = torch.full((N,), 1000.0, dtype=torch.float64, device=ctx.device)
-        rows["transition_ms"], _ = once(lambda: g.transition_3d_to_2d(ctx, p, nb, flag, mass, rho, u), "transition")
+        # this cloud flags no particle (its bottom walls see interior neighbours only): the transition is
+        # timed with every bulk wall particle flagged, which deletes the layers above the bottom
+        tflag = torch.as_tensor(((d["model"] == 0) & (d["kind"] == W.WALL)).astype(np.uint8), device=ctx.device)
+        rows["transition_ms"], _ = once(lambda: g.transition_3d_to_2d(ctx, p, nb, tflag, mass, rho, u), "transition")
+        rows["apply_ms"], _ = once(lambda: g.apply_stencil(ctx, nb, w32, u, 0xF, out=y32), "apply")
         ybar = torch.ones((1, N), dtype=torch.float64, device=ctx.device)
         rows["apply_adjoint_ms"], _ = once(lambda: g.apply_stencil_adjoint(ctx, nb, w32, ybar, g.OP_LAP),
                                            "apply_adjoint")
@@ -354,6 +358,18 @@ def main():
                                              "weights_adjoint")
         result["rows"] = rows
         result["rows_kernels_us"] = kern
+        # algorithmic bytes of each row (per particle / per neighbour entry)
+        row_bytes = {"build_neighbours": 4.0 * nnz + 41.0 * N, "classify_pca": 4.0 * nnz + 106.0 * N,
+                     "apply": 18.0 * nnz + 40.0 * N, "transition": 4.0 * nnz + 48.0 * N,
+                     "apply_adjoint": 48.0 * nnz + 16.0 * N, "weights_adjoint": 80.0 * nnz + 56.0 * N}
+        roof_rows = {}
+        for key, byts in row_bytes.items():
+            us = sum(kern.get(key, {}).values())
+            if us > 0:
+                roof_rows[key] = {"kernel_us": round(us, 1), "algorithmic_bytes": byts,
+                                  "GBs": round(byts / (us * 1e-6) / 1e9, 1),
+                                  "hbm_frac": round(byts / (us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4)}
+        result["rows_roofline"] = roof_rows
         result["flags"] = {"bulk_to_film": int((flag == 1).sum().item()), "film_to_bulk": int((flag == 2).sum().item())}
 
     if args.poisson:
@@ -462,6 +478,39 @@ def main():
             passes += 1
         t_o = t_all / passes
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        # the other rows, once each on the same cloud (same inputs as the GPU rows above)
+        orows = {"build_neighbours_s": t_nbr_o}
+        if not args.no_rows:
+            xr_o, xc_o = oracle.neighbours(d, cross=True)   # input of the classification, not timed
+            t0 = time.perf_counter()
+            lam_o, w3_o, eps_o = oracle.pca(d, rp_o, col_o)
+            oracle.classify(d, rp_o, col_o, eps_o, w3_o, cross=(xr_o, xc_o), film_height=d["film_height"],
+                            h3d=d["h3d"])
+            orows["classify_pca_s"] = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            oracle.apply(rp_o, col_o, w_o, f)
+            orows["apply_s"] = time.perf_counter() - t0
+            tflag_o = ((d["model"] == 0) & (d["kind"] == W.WALL)).astype(np.uint8)
+            t0 = time.perf_counter()
+            oracle.transition_3d_to_2d(d, rp_o, col_o, tflag_o, np.ones(N), np.full(N, 1000.0), f)
+            orows["transition_s"] = time.perf_counter() - t0
+            yb_o = np.ones((1, N))
+            t0 = time.perf_counter()
+            oracle.apply_adjoint(rp_o, col_o, w_o, yb_o, 8)
+            orows["apply_adjoint_s"] = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            oracle.weights_adjoint_x(d, rp_o, col_o, f, yb_o, 8)
+            orows["weights_adjoint_s"] = time.perf_counter() - t0
+            for key in ("classify_pca", "apply", "transition", "apply_adjoint", "weights_adjoint"):
+                if key in result.get("rows_roofline", {}):
+                    rr = result["rows_roofline"][key]
+                    rr["oracle_s"] = round(orows[key + "_s"], 4)
+                    rr["speedup_vs_oracle"] = round(orows[key + "_s"] / (rr["kernel_us"] * 1e-6), 1)
+            if "build_neighbours" in result.get("rows_roofline", {}):
+                rr = result["rows_roofline"]["build_neighbours"]
+                rr["oracle_s"] = round(t_nbr_o, 4)
+                rr["speedup_vs_oracle"] = round(t_nbr_o / (rr["kernel_us"] * 1e-6), 1)
+        result["oracle_rows_s"] = orows
         e32 = oracle.operator_error(w32n, w_o, rp_o)
         e64 = oracle.operator_error(w64n, w_o, rp_o)
         result["cpu_baseline"] = {"value": N / t_o, "unit": "particles/s", "cores": cores, "kind": "oracle",
