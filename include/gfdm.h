@@ -98,6 +98,15 @@ const char *gf_version(void);
 gf_status gf_profile_enable(gf_ctx *ctx, int on);
 gf_status gf_profile_read(gf_ctx *ctx, char *buf, size_t len);
 
+/* LDS budget of the neighbour-tile kernels (stencils, application, PCA,
+ * pressure SpMV).  A block stages the distinct neighbours of its tile in LDS
+ * when there are at most `entries` of them (further capped by each kernel's
+ * own limit, 1024-2048) and otherwise reads them from global memory with the
+ * same arithmetic, so the results do not depend on it.  entries <= 0
+ * restores the kernels' own limits.  Lets callers trade LDS for occupancy and
+ * exercises the unstaged path.  Never fails for a valid ctx. */
+gf_status gf_set_tile_capacity(gf_ctx *ctx, int entries);
+
 /* ---------------------------------------------------------- neighbourhoods */
 /* Build S_i = { j : |x_j - x_i| <= (h_i + h_j)/2 } for every particle
  * (Sec. 2.2, Eq. Nbd), i in S_i.  cross_model = 0: only particles of the same

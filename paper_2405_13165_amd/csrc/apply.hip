@@ -178,7 +178,7 @@ gf_status launch_apply(gf_ctx *ctx, const gf_nbr *nbr, const void *w, unsigned m
     const int64_t nrows = lu.nrows;
     ProfScope prof(ctx, lu.model == 0 ? "apply_3d" : "apply_film");
     if (lu.tiled) {
-      const int cap = std::min(lu.tile_max, kApplyCap);
+      const int cap = std::min(lu.tile_max, tile_capacity(ctx, kApplyCap));
       const dim3 tgrid(grid_for(lu.ntiles, 1)), tblock(kTileRows * std::min(T, 32));
       const size_t lds = sizeof(double) * cap;
 #define GF_APPLY_TILE(TT)                                                                                           \

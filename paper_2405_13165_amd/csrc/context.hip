@@ -82,6 +82,12 @@ ProfScope::~ProfScope() {
   if (idx >= 0) (void)hipEventRecord(ctx->prof_pending[idx].stop, sm);
 }
 
+extern "C" gf_status gf_set_tile_capacity(gf_ctx *ctx, int entries) {
+  if (!ctx) return GF_EINVAL;
+  ctx->tile_cap = entries > 0 ? entries : 0;
+  return GF_OK;
+}
+
 extern "C" gf_status gf_profile_enable(gf_ctx *ctx, int on) {
   if (!ctx) return GF_EINVAL;
   ctx->profile = on ? 1 : 0;

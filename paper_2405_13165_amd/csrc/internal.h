@@ -27,6 +27,8 @@ struct gf_ctx {
   // kernels per (model, neighbour-count band); set by gf_autotune
   int wteam[2][4] = {{8, 8, 8, 16}, {8, 8, 8, 16}};
   int ateam[2][4] = {{4, 8, 8, 16}, {4, 8, 8, 16}};
+  // LDS staging limit of the tile kernels (gf_set_tile_capacity); 0 = their own
+  int tile_cap = 0;
   // optional per-kernel timing with HIP events (gf_profile_enable)
   int profile = 0;
   struct ProfRec {
@@ -86,6 +88,9 @@ constexpr int kTileBandRow = 128;              // = kBandHi[kTileBand]
 // Launch units of the batched kernels: per model, the tiled rows (bands
 // 0..kTileBand) and each untiled band.  Team sizes live in
 // ctx->wteam/ateam[model][band] (band = kTileBand for the tiled unit).
+// staging capacity of a tile kernel with its own limit `own`
+inline int tile_capacity(const gf_ctx *ctx, int own) { return (ctx && ctx->tile_cap > 0 && ctx->tile_cap < own) ? ctx->tile_cap : own; }
+
 struct LaunchUnit {
   int model, band;
   bool tiled;

@@ -279,7 +279,7 @@ extern "C" gf_status gf_classify_pca(gf_ctx *ctx, const gf_particles *p, const g
     a.sched = same->grouped + u.row0;
     a.nrows = u.nrows;
     if (u.tiled) {
-      const int cap = std::min(u.tile_max, kPcaCap);
+      const int cap = std::min(u.tile_max, tile_capacity(ctx, kPcaCap));
       hipLaunchKernelGGL(k_pca_tile, dim3(grid_for(u.ntiles, 1)), dim3(kTileRows * kTeam), sizeof(double4) * cap,
                          ctx->stream, a, same->tile_off, same->tile_u, same->slot, u.tile0, cap);
     } else {

@@ -425,7 +425,7 @@ void init_spmv_tiles(Solver &sv) {
     t.b3_n[m] = nb->group_start[(m + 1) * GF_NBAND] - t.b3_start[m];
     cap = std::max(cap, nb->tile_max[m]);
   }
-  t.cap = std::min(cap, kSpmvCap);
+  t.cap = std::min(cap, tile_capacity(sv.ctx, kSpmvCap));
 }
 
 // y = A xin with the partials of (other, y), (y, y)

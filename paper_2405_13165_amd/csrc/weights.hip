@@ -787,7 +787,7 @@ gf_status launch_tile(gf_ctx *ctx, const WArgs &a, const gf_nbr *nbr, const Laun
   ta.off = nbr->tile_off;
   ta.u = nbr->tile_u;
   ta.tile0 = u.tile0;
-  ta.cap = std::min(u.tile_max, kTileCap);
+  ta.cap = std::min(u.tile_max, tile_capacity(ctx, kTileCap));
   const size_t lds = (sizeof(double4) + (FUSED ? sizeof(double) : 0)) * ta.cap +
                      sizeof(double) * kTileRows * team_lds_doubles<M>(T, 0);
   const dim3 grid(grid_for(u.ntiles, 1)), block(kTileRows * T);
@@ -828,11 +828,11 @@ gf_status launch_batched(gf_ctx *ctx, const gf_nbr *nbr, WArgs a, int only_unit 
 
 // whether any batched launch reads the packed positions (untiled units and
 // tiles whose list exceeds the LDS capacity gather them from global memory)
-bool needs_packed_positions(const gf_nbr *nbr) {
+bool needs_packed_positions(const gf_ctx *ctx, const gf_nbr *nbr) {
   LaunchUnit units[2 * GF_NBAND];
   const int nu = launch_units(nbr, units);
   for (int q = 0; q < nu; ++q)
-    if (!units[q].tiled || units[q].tile_max > kTileCap) return true;
+    if (!units[q].tiled || units[q].tile_max > tile_capacity(ctx, kTileCap)) return true;
   return false;
 }
 
@@ -886,7 +886,7 @@ gf_status weights_common(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr, 
   WArgs a;
   a.x = p->x; a.y = p->y; a.z = p->z; a.h = p->h; a.nx = p->nx; a.ny = p->ny; a.nz = p->nz; a.model = p->model;
   a.pos = pos;
-  if (prec == GF_BATCHED && needs_packed_positions(nbr)) {
+  if (prec == GF_BATCHED && needs_packed_positions(ctx, nbr)) {
     ProfScope prof(ctx, "pack_positions");
     hipLaunchKernelGGL(k_pack_pos, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, ctx->stream, p->x, p->y, p->z, p->h, n, pos);
     GF_LAUNCH_CHECK(ctx);

@@ -72,7 +72,7 @@ EXPORTED = [
     "gf_pca_params_default", "gf_classify_pca", "gf_ls_params_default", "gf_gfdm_weights",
     "gf_apply_stencil", "gf_gfdm_weights_apply", "gf_poisson_assemble", "gf_solve_params_default",
     "gf_poisson_solve", "gf_transition_3d_to_2d", "gf_apply_stencil_adjoint",
-    "gf_gfdm_weights_adjoint", "gf_profile_enable", "gf_profile_read", "gf_autotune",
+    "gf_gfdm_weights_adjoint", "gf_profile_enable", "gf_profile_read", "gf_autotune", "gf_set_tile_capacity",
 ]
 
 _lib = None
@@ -120,6 +120,7 @@ def load_library(path: str = LIB_PATH):
     L.gf_gfdm_weights_adjoint.argtypes = [P, PP, P, ctypes.POINTER(LsParams), U, P, P, P]
     L.gf_autotune.argtypes = [P, PP, P, I32, P]
     L.gf_profile_enable.argtypes = [P, I32]
+    L.gf_set_tile_capacity.argtypes = [P, I32]
     L.gf_profile_read.argtypes = [P, ctypes.c_char_p, ctypes.c_size_t]
     for name in EXPORTED:
         getattr(L, name)  # every declared entry point must resolve
@@ -162,6 +163,10 @@ class Context:
     def profile(self, on: bool = True):
         """Bracket every library kernel with HIP events (gf_profile_enable)."""
         self.check(self.lib.gf_profile_enable(self.handle, int(on)))
+
+    def set_tile_capacity(self, entries: int = 0):
+        """LDS staging limit of the tile kernels (gf_set_tile_capacity); 0 restores the defaults."""
+        self.check(self.lib.gf_set_tile_capacity(self.handle, int(entries)))
 
     def profile_read(self):
         """{kernel name: (launches, total ms)} since the last read; synchronises."""

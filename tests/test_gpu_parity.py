@@ -403,3 +403,54 @@ def test_autograd_function(ctx, g):
     assert np.abs(_np(gu) - ub_o).max() <= 1e-9 * np.abs(ub_o).max()
     gxyz = np.stack([_np(gx), _np(gy), _np(gz)], 1)
     assert np.abs(gxyz - xb_o).max() <= 1e-9 * np.abs(xb_o).max()
+
+
+# ------------------------------------------------------------------ tiles
+def test_unstaged_tiles_match_staged(ctx, g):
+    """Tiles whose neighbour list exceeds the LDS capacity read global memory
+    with the same arithmetic: forcing every tile onto that path (capacity 16)
+    must reproduce the staged results: FP32-stored stencils and their
+    applications exactly; FP64 results to 1e-12 (the two inlined copies of
+    the row code may be contracted into FMAs differently by the compiler);
+    PCA and the pressure solutions likewise."""
+    d = CASES["jet_small"]()
+    p = _dev(ctx, d)
+    nb = g.build_neighbours(ctx, p)
+    u = torch.as_tensor(W.test_field(d["x"], d["y"], d["z"])[0], device=ctx.device)
+
+    def run():
+        out = {}
+        for wt, name in ((g.GF_F32, "f32"), (g.GF_F64, "f64")):
+            w, y = g.gfdm_weights_apply(ctx, p, nb, u, 0xF, wt)
+            out["w_" + name], out["yf_" + name] = w.clone(), y.clone()
+            out["ya_" + name] = g.apply_stencil(ctx, nb, w, u).clone()
+        lam, w3, eps, _ = g.classify_pca(ctx, p, nb, want_flags=False)
+        out["lam"], out["w3"] = lam.clone(), w3.clone()
+        return out
+
+    dq = W.projection_cylinder(20_000)
+    pq = _dev(ctx, dq)
+    nq = g.build_neighbours(ctx, pq)
+    wq = g.gfdm_weights(ctx, pq, nq, g.GF_BATCHED, g.GF_F64)
+    rhs = torch.as_tensor(np.random.default_rng(9).uniform(-1, 1, pq.n), device=ctx.device)
+
+    def solve():
+        return {f"x{m}": g.poisson_solve(ctx, pq, nq, wq, dq["row_type"], rhs, params=g.solve_params(mixed=m))[0]
+                for m in (0, 1)}
+
+    ref = run()
+    ref.update(solve())
+    ctx.set_tile_capacity(16)
+    try:
+        got = run()
+        got.update(solve())
+    finally:
+        ctx.set_tile_capacity(0)
+    for k in ("w_f32", "yf_f32", "ya_f32"):
+        assert torch.equal(ref[k], got[k]), k
+    # stencil-level differences of a few ulp are amplified by the cancellation
+    # of the differenced sums (terms ~1e2 x the result) and by the solver
+    tol = {"w_f64": 1e-12, "lam": 1e-12, "w3": 1e-12, "yf_f64": 1e-9, "ya_f64": 1e-9, "x0": 1e-8, "x1": 1e-8}
+    for k, t in tol.items():
+        scale = ref[k].abs().max().item()
+        assert (ref[k] - got[k]).abs().max().item() <= t * scale, k
