@@ -84,13 +84,28 @@ def _declare(L):
     L.orc_poisson_assemble.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_double, _P]
     L.orc_transition_3d_to_2d.restype = None
     L.orc_transition_3d_to_2d.argtypes = [_I64] + [_P] * 21
+    L.orc_film_height.restype = None
+    L.orc_film_height.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_double, _P]
+    L.orc_transition_2d_to_3d.restype = _I64
+    L.orc_transition_2d_to_3d.argtypes = ([_I64] + [_P] * 9 + [ctypes.c_double, ctypes.c_double]
+                                          + [_P] * 3 + [ctypes.c_int, _I64, _I64] + [_P] * 13
+                                          + [_I64, _P])
+    L.orc_buffer_flags.restype = None
+    L.orc_buffer_flags.argtypes = [_I64, _P, _P, _P, _P]
     L.orc_weights_adjoint_x.restype = None
     L.orc_weights_adjoint_x.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                         ctypes.c_double, ctypes.c_uint, _P, _P, _P]
 
 
 def _p(a):
-    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+    """Pointer to a numpy array's data.  The pointer object holds a reference
+    to the array, so a temporary (a contiguous copy of a strided view) lives
+    as long as the argument list that carries it."""
+    if a is None:
+        return None
+    ptr = ctypes.c_void_p(a.ctypes.data)
+    ptr._array = a
+    return ptr
 
 
 def _f64(a):
@@ -254,6 +269,187 @@ def transition_3d_to_2d(p, row_ptr, col, flag, mass, rho, phi):
     out["keep"] = keep
     out["owner"] = owner
     return out
+
+
+# Sharpness of the droplet kernel of Eq. (Height) and the spacing factors of
+# Sec. 2.3: the paper leaves them to the models it cites, so they are
+# parameters here (readings: alpha = 8; r_min = 0.2, r_max = 0.4, which keeps
+# the spacing h/3 of the synthetic clouds inside [r_min h, r_max h]).
+ALPHA_FILM = 8.0
+R_MIN = 0.2
+R_MAX = 0.4
+MAX_GAMMA = 1 << 16
+
+
+def film_height(p, row_ptr, col, diam, alpha=ALPHA_FILM):
+    """Eq. (Height): H_i = sum_{j in S_i} alpha/(pi h_j^2) exp(-alpha r_ij^2/h_j^2)
+    pi d_j^3/6 for film particles (S_i same-model), 0 for bulk particles."""
+    x, y, z, h, model = _pos(p)
+    n = x.shape[0]
+    H = np.zeros(n)
+    lib().orc_film_height(n, _p(x), _p(y), _p(z), _p(h), _p(model), _p(row_ptr), _p(col),
+                          _p(_f64(diam)), float(alpha), _p(H))
+    return H
+
+
+def _phi2(phi, n):
+    if phi is None:
+        return np.zeros((0, n))
+    a = np.ascontiguousarray(np.asarray(phi, dtype=np.float64).reshape(-1, n))
+    return a
+
+
+def transition_2d_to_3d(p, sel, height, h3d, mass, rho, phi=None, r_min=R_MIN, r_max=R_MAX,
+                        max_gamma=MAX_GAMMA):
+    """Sec. 5.2 / Alg. 4 for the film particles `sel` (ascending): each turns
+    into a 3D wall particle followed by gamma_i = ceil(H_i / psi~_i) added
+    particles at x_i + k psi_i n_i (Eq. psi~, Eq. gamma), mass split evenly,
+    density and fields copied.  Returns a dict of the new particle arrays
+    (rows of a source consecutive, k = 0..gamma) and `off`."""
+    x, y, z, h, model = _pos(p)
+    n = x.shape[0]
+    sel = np.ascontiguousarray(sel, dtype=np.int64)
+    ns = sel.shape[0]
+    ph = _phi2(phi, n)
+    nphi = ph.shape[0]
+    off = np.zeros(ns + 1, np.int64)
+    args = [ns, _p(sel), _p(x), _p(y), _p(z), _p(_f64(p["nx"])), _p(_f64(p["ny"])),
+            _p(_f64(p["nz"])), _p(_f64(height)), _p(_f64(h3d)), float(r_min), float(r_max),
+            _p(_f64(mass)), _p(_f64(rho)), _p(ph if nphi else None), nphi, n, int(max_gamma),
+            _p(off)]
+    L = lib()
+    total = L.orc_transition_2d_to_3d(*args, *([None] * 12), 0, None)
+    if total < 0:
+        raise ValueError("a particle needs more than max_gamma added particles")
+    o = {k: np.zeros(total) for k in ("x", "y", "z", "h", "nx", "ny", "nz", "mass", "rho")}
+    o["model"] = np.zeros(total, np.int8)
+    o["kind"] = np.zeros(total, np.int8)
+    o["phi"] = np.zeros((nphi, total))
+    o["src"] = np.zeros(total, np.int32)
+    L.orc_transition_2d_to_3d(*args, _p(o["x"]), _p(o["y"]), _p(o["z"]), _p(o["h"]),
+                              _p(o["model"]), _p(o["kind"]), _p(o["nx"]), _p(o["ny"]),
+                              _p(o["nz"]), _p(o["mass"]), _p(o["rho"]),
+                              _p(o["phi"] if nphi else None), total, _p(o["src"]))
+    o["height"] = np.zeros(total)
+    o["diam"] = np.zeros(total)
+    o["off"] = off
+    return o
+
+
+def buffer_flags(p, cross_row_ptr, cross_col):
+    """First loop of Alg. 5 (Sec. 6.1): particles with a particle of the other
+    model within their support, and those particles themselves."""
+    n = p["x"].shape[0]
+    flag = np.zeros(n, np.uint8)
+    lib().orc_buffer_flags(n, _p(_i8(p["model"])), _p(cross_row_ptr), _p(cross_col), _p(flag))
+    return flag
+
+
+_GHOST_KEYS = ("x", "y", "z", "h", "nx", "ny", "nz", "mass", "rho", "height", "diam")
+
+
+def buffer_zone(p, cross_row_ptr, cross_col, film_h, h_other, mass, rho, phi=None,
+                r_min=R_MIN, r_max=R_MAX, max_gamma=MAX_GAMMA):
+    """Ghost particles of Sec. 6.1 / Alg. 5, in the paper's order:
+    (1) flag particles near the other model; (2) put an intermediate ghost of
+    the same model on every flagged particle; (3) transition the ghosts: the
+    3D ghosts as in Sec. 5.1 with every wall ghost flagged (neighbourhoods of
+    Eq. (Nbd) among the 3D ghosts themselves; interior and free-surface ghosts
+    are mapped onto their nearest wall ghost and deleted), the 2D ghosts as
+    in Sec. 5.2.  h_other[i] is the resolution of the other model at particle
+    i: the h of the ghosts made from i, and the 3D resolution of psi~.
+    Ghosts come out ordered by source index (k = 0..gamma within a 2D source).
+    Returns (flag, dict of ghost arrays with 'src')."""
+    n = p["x"].shape[0]
+    flag = buffer_flags(p, cross_row_ptr, cross_col)
+    src = np.nonzero(flag)[0]
+    model = np.asarray(p["model"])
+    ph = _phi2(phi, n)
+    parts = []
+    # 3D intermediate ghosts -> 2D ghosts
+    g3 = src[model[src] == 0]
+    if g3.size:
+        sub = {k: np.ascontiguousarray(np.asarray(p[k])[g3]) for k in
+               ("x", "y", "z", "h", "model", "kind", "nx", "ny", "nz")}
+        rp, col = neighbours(sub)
+        wall = (sub["kind"] == 2).astype(np.uint8)
+        fields = ph[:, g3] if ph.shape[0] else np.zeros((1, g3.size))
+        trs = [transition_3d_to_2d(sub, rp, col, wall, np.asarray(mass)[g3],
+                                   np.asarray(rho)[g3], f) for f in fields]
+        keep = np.nonzero(wall)[0]
+        tr = trs[0]
+        g = {k: sub[k][keep].astype(np.float64) for k in ("x", "y", "z", "nx", "ny", "nz")}
+        g["h"] = np.asarray(h_other, dtype=np.float64)[g3][keep]
+        g["model"] = np.ones(keep.size, np.int8)
+        g["kind"] = np.full(keep.size, 2, np.int8)
+        g["mass"] = tr["mass"][keep]
+        g["rho"] = tr["rho"][keep]
+        g["height"] = tr["height"][keep]
+        g["diam"] = tr["diam"][keep]
+        g["phi"] = (np.stack([t["phi"][keep] for t in trs]) if ph.shape[0]
+                    else np.zeros((0, keep.size)))
+        g["src"] = g3[keep].astype(np.int32)
+        parts.append(g)
+    # 2D intermediate ghosts -> 3D ghosts
+    g2 = src[model[src] == 1]
+    if g2.size:
+        o = transition_2d_to_3d(p, g2, film_h, h_other, mass, rho, ph if ph.shape[0] else None,
+                                r_min, r_max, max_gamma)
+        o.pop("off")
+        parts.append(o)
+    if not parts:
+        out = {k: np.zeros(0) for k in _GHOST_KEYS}
+        out.update(model=np.zeros(0, np.int8), kind=np.zeros(0, np.int8),
+                   phi=np.zeros((ph.shape[0], 0)), src=np.zeros(0, np.int32))
+        return flag, out
+    out = {k: np.concatenate([q[k] for q in parts]) for k in _GHOST_KEYS + ("model", "kind", "src")}
+    out["phi"] = np.concatenate([q["phi"] for q in parts], axis=1)
+    order = np.argsort(out["src"], kind="stable")
+    out = {k: (v[:, order] if k == "phi" else v[order]) for k, v in out.items()}
+    return flag, out
+
+
+def extend_cloud(p, ghosts):
+    """Regular particles followed by ghost particles (one cloud)."""
+    keys = ("x", "y", "z", "h", "model", "kind", "nx", "ny", "nz")
+    return {k: np.concatenate([np.asarray(p[k]), np.asarray(ghosts[k]).astype(np.asarray(p[k]).dtype)])
+            for k in keys}
+
+
+def neighbours_rows(p, n_rows, cross=False):
+    """Extended neighbourhoods of Sec. 6.2: rows of particles [0, n_rows) hold
+    S_i of Eq. (Nbd) over the whole cloud (regular and ghost particles); the
+    particles beyond n_rows (ghosts) get no derivatives, their rows hold only
+    themselves."""
+    rp, col = neighbours(p, cross=cross)
+    n = rp.shape[0] - 1
+    lens = np.diff(rp).copy()
+    lens[n_rows:] = 1
+    rp2 = np.zeros(n + 1, np.int64)
+    np.cumsum(lens, out=rp2[1:])
+    keep = np.repeat(np.arange(n) < n_rows, np.diff(rp))
+    col2 = np.empty(int(rp2[-1]), np.int32)
+    reg = np.zeros(n, bool); reg[:n_rows] = True
+    pos = np.repeat(reg, lens)
+    col2[pos] = col[keep]
+    col2[~pos] = np.arange(n_rows, n, dtype=np.int32)
+    return rp2, col2
+
+
+def poisson_split_solve(p, row_ptr, col, w, row_type, n_regular, rhs, p_ghost, zeta=ZETA):
+    """Implicit step with ghost neighbours (Sec. 6.2): only regular particles
+    are unknowns; the ghost terms of each regular row use the known ghost
+    values and move to the right-hand side:
+        A_rr p_r = rhs_r - A_rg p_g."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    n = row_ptr.shape[0] - 1
+    val = poisson_matrix(p, row_ptr, col, w, row_type, zeta)
+    A = sp.csr_matrix((val, col, row_ptr), shape=(n, n))
+    Arr = A[:n_regular, :n_regular]
+    Arg = A[:n_regular, n_regular:]
+    b = np.asarray(rhs, dtype=np.float64)[:n_regular] - Arg @ np.asarray(p_ghost, dtype=np.float64)
+    return spla.spsolve(Arr.tocsc(), b)
 
 
 def operator_error(w, w_ref, row_ptr):

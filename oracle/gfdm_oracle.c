@@ -21,6 +21,10 @@
  *     Alg. 3)
  *   - adjoints of stencil application and of the stencil weights with respect
  *     to particle positions
+ *   - film height of the droplet model, Eq. (Height) in Sec. 2.4
+ *   - 2D->3D transition with particle addition and mass splitting (Sec. 5.2,
+ *     Eq. (psi~), Eq. (gamma), Alg. 4)
+ *   - the first loop of the ghost-particle procedure (Sec. 6.1, Alg. 5)
  */
 #include <math.h>
 #include <stdint.h>
@@ -842,6 +846,110 @@ void orc_transition_3d_to_2d(int64_t n, const double *x, const double *y, const 
     height_out[i] = H;
     diam_out[i] = cbrt(6.0 * m / (M_PI * rho_out[i]));
   }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Film height of the droplet model, Eq. (Height), Sec. 2.4: for a film        */
+/* particle i                                                                  */
+/*   H_i = sum_{j in S_i} alpha / (pi h_j^2) exp(-alpha |x_j - x_i|^2 / h_j^2) V_j */
+/* with the droplet volume V_j = pi d_j^3 / 6.  S_i is the same-model          */
+/* neighbourhood (it contains i).  3D particles get 0.                         */
+/* ------------------------------------------------------------------------- */
+void orc_film_height(int64_t n, const double *x, const double *y, const double *z,
+                     const double *h, const int8_t *model, const int64_t *row_ptr,
+                     const int32_t *col, const double *diam, double alpha, double *height) {
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int64_t i = 0; i < n; ++i) {
+    double H = 0.0;
+    if (model[i] == 1) {
+      for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+        int64_t j = col[k];
+        double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];
+        double r2 = (dx * dx + dy * dy) + dz * dz;
+        double hj2 = h[j] * h[j];
+        double vol = M_PI * diam[j] * diam[j] * diam[j] / 6.0;
+        H += alpha / (M_PI * hj2) * exp(-alpha * r2 / hj2) * vol;
+      }
+    }
+    height[i] = H;
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* 2D -> 3D transition, Sec. 5.2 and Alg. 4, of the film particles sel[0..ns) */
+/* (ascending).  For each source s with film height H, inward unit normal n   */
+/* and 3D resolution h3 at its location:                                      */
+/*   psi~ = (r_min h3 + r_max h3) / 2        Eq. (psi~)                        */
+/*   gamma = ceil(H / psi~)                  Eq. (gamma)   (0 if not H > 0)    */
+/*   psi = H / gamma                                                          */
+/* The source itself turns into a 3D wall particle and gamma particles are   */
+/* added at x + (k psi) n, k = 1..gamma; the one at k = gamma is a free-      */
+/* surface particle, the others interior.  Density and the nphi fields (each  */
+/* a column of length n) are copied; the mass is split evenly over the        */
+/* 1 + gamma particles; every new particle gets h = h3.  The particles of     */
+/* source s are written at off[s] .. off[s+1]-1 in the order k = 0..gamma.    */
+/* With ox == NULL only off[] is filled.  Returns the total count, or -1 if   */
+/* some gamma exceeds max_gamma.                                              */
+/* ------------------------------------------------------------------------- */
+int64_t orc_transition_2d_to_3d(int64_t ns, const int64_t *sel, const double *x, const double *y,
+                                const double *z, const double *nx, const double *ny,
+                                const double *nz, const double *H, const double *h3,
+                                double r_min, double r_max, const double *mass,
+                                const double *rho, const double *phi, int nphi, int64_t n,
+                                int64_t max_gamma, int64_t *off, double *ox, double *oy,
+                                double *oz, double *oh, int8_t *omodel, int8_t *okind,
+                                double *onx, double *ony, double *onz, double *omass,
+                                double *orho, double *ophi, int64_t cap, int32_t *osrc) {
+  off[0] = 0;
+  for (int64_t s = 0; s < ns; ++s) {
+    int64_t i = sel[s];
+    double psit = (r_min * h3[i] + r_max * h3[i]) / 2.0;
+    double g = H[i] > 0.0 ? ceil(H[i] / psit) : 0.0;
+    if (!(g <= (double)max_gamma)) return -1;
+    off[s + 1] = off[s] + 1 + (int64_t)g;
+  }
+  if (ox == NULL) return off[ns];
+  for (int64_t s = 0; s < ns; ++s) {
+    int64_t i = sel[s];
+    int64_t gam = off[s + 1] - off[s] - 1;
+    double psi = gam > 0 ? H[i] / (double)gam : 0.0;
+    for (int64_t k = 0; k <= gam; ++k) {
+      int64_t t = off[s] + k;
+      double step = (double)k * psi;
+      ox[t] = x[i] + step * nx[i];
+      oy[t] = y[i] + step * ny[i];
+      oz[t] = z[i] + step * nz[i];
+      oh[t] = h3[i];
+      omodel[t] = 0;
+      okind[t] = k == 0 ? KIND_WALL : (k == gam ? KIND_FREE_SURFACE : KIND_INTERIOR);
+      onx[t] = nx[i];
+      ony[t] = ny[i];
+      onz[t] = nz[i];
+      omass[t] = mass[i] / (double)(1 + gam);
+      orho[t] = rho[i];
+      for (int f = 0; f < nphi; ++f) ophi[(int64_t)f * cap + t] = phi[(int64_t)f * n + i];
+      osrc[t] = (int32_t)i;
+    }
+  }
+  return off[ns];
+}
+
+/* ------------------------------------------------------------------------- */
+/* Ghost particles, Sec. 6.1, first loop of Alg. 5: every particle i flags     */
+/* itself and each particle j of the other model within its support (the      */
+/* cross-model neighbourhood of Eq. (Nbd)).                                   */
+/* ------------------------------------------------------------------------- */
+void orc_buffer_flags(int64_t n, const int8_t *model, const int64_t *row_ptr, const int32_t *col,
+                      uint8_t *flag) {
+  for (int64_t i = 0; i < n; ++i) flag[i] = 0;
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+      int64_t j = col[k];
+      if (model[j] != model[i]) {
+        flag[i] = 1;
+        flag[j] = 1;
+      }
+    }
 }
 
 /* ------------------------------------------------------------------------- */

@@ -53,6 +53,18 @@ def concat(a: dict, b: dict) -> dict:
     return out
 
 
+def _droplets(model, film_height, spacing, rho0=1000.0):
+    """Droplet diameters, masses and densities: a film particle that stands for
+    an area spacing^2 of film of thickness film_height holds the volume
+    film_height * spacing^2 (diameter from V = pi d^3 / 6); a bulk particle
+    holds spacing^3."""
+    film = model == FILM
+    vol = np.where(film, film_height * spacing ** 2, spacing ** 3)
+    diam = np.where(film, np.cbrt(6.0 * vol / np.pi), 0.0)
+    rho = np.full(model.shape[0], rho0)
+    return dict(diam=diam, mass=rho * vol, rho=rho)
+
+
 def jittered_cube(n_axis: int, s: float, rng, jitter: float = 0.2):
     """n_axis^3 lattice with centres (i+1/2)s, each coordinate jittered by U(+-jitter*s)."""
     i = np.arange(n_axis)
@@ -137,9 +149,11 @@ def mixed_block_film(factor: int = 1, seed_extra: int = 0):
     nzv = np.concatenate([nzb, np.ones(nf)])
     film_height = np.concatenate([np.zeros(nb), rng.uniform(1e-3, 5e-3, nf)])
     h3d = np.full(nb + nf, 3.0 * sb)
+    h_other = np.concatenate([np.full(nb, 3.0 * sf), h3d[nb:]])
+    spacing = np.concatenate([np.full(nb, sb), np.full(nf, sf)])
     return _pack(x, y, z, h, model, kind, None, None, nzv,
-                 film_height=film_height, h3d=h3d, n_bulk=nb, n_film=nf,
-                 spacing_bulk=sb, spacing_film=sf)
+                 film_height=film_height, h3d=h3d, h_other=h_other, n_bulk=nb, n_film=nf,
+                 spacing_bulk=sb, spacing_film=sf, **_droplets(model, film_height, spacing))
 
 
 def _truncated_normal(rng, n, clip=2.0):
@@ -202,9 +216,12 @@ def jet_impact(n_bulk: int = 1_000_000, n_film: int = 1_000_000, seed_extra: int
     nzv = np.concatenate([np.where(kb == WALL, 1.0, 0.0), np.ones(n_film)])
     film_height = np.concatenate([np.zeros(nb), 5e-3 * 0.05 / r])
     h3d = np.full(nb + n_film, 3.0 * sb)
+    # film resolution at the jet's foot: the film's own h there
+    h_other = np.concatenate([np.full(nb, 4.74 * np.sqrt(2 * np.pi * 0.45 * 0.05 / n_film)), h3d[nb:]])
+    spacing = np.concatenate([np.full(nb, sb), sf])
     return _pack(x, y, z, np.concatenate([hb, hf]), model, kind, None, None, nzv,
-                 film_height=film_height, h3d=h3d, n_bulk=nb, n_film=n_film,
-                 spacing_bulk=sb)
+                 film_height=film_height, h3d=h3d, h_other=h_other, n_bulk=nb, n_film=n_film,
+                 spacing_bulk=sb, **_droplets(model, film_height, spacing))
 
 
 def fourier_field(x, y, z, rng, modes: int = 8):
