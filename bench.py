@@ -356,12 +356,32 @@ def main():
                                            "apply_adjoint")
         rows["weights_adjoint_ms"], _ = once(lambda: g.gfdm_weights_adjoint(ctx, p, nb, u, ybar, g.OP_LAP),
                                              "weights_adjoint")
+        # coupling layer: film height (Eq. Height), ghost particles of the buffer zone (Alg. 5), and the
+        # stencils over the extended neighbourhoods (regular + ghost particles, Sec. 6.2)
+        rows["film_height_ms"], _ = once(lambda: g.film_height(ctx, p, nb, d["diam"]), "film_height")
+        rows["buffer_zone_ms"], bz = once(lambda: g.buffer_zone(ctx, p, nb, xnb, d["film_height"], d["h_other"],
+                                                                d["mass"], d["rho"]), "buffer_zone")
+        ghosts = bz[1]
+        pe = g.extend_particles(ctx, p, ghosts)
+        rows["extended_build_ms"], nbe = once(lambda: g.build_neighbours(ctx, pe, n_rows=N), "extended_build")
+        ue = torch.cat([u, torch.as_tensor(W.test_field(ghosts["x"].cpu().numpy(), ghosts["y"].cpu().numpy(),
+                                                        ghosts["z"].cpu().numpy())[0], device=ctx.device)])
+        rows["extended_weights_apply_ms"], _ = once(
+            lambda: g.gfdm_weights_apply(ctx, pe, nbe, ue, wtype=g.GF_F32, store_weights=False),
+            "extended_weights_apply")
+        rows["buffer_zone_counts"] = {"flagged": int(bz[0].sum().item()), "ghosts": int(ghosts["x"].shape[0]),
+                                      "ghosts_3d": int((ghosts["model"] == 0).sum().item()),
+                                      "extended_nnz": nbe.nnz}
+        del nbe, pe
         result["rows"] = rows
         result["rows_kernels_us"] = kern
         # algorithmic bytes of each row (per particle / per neighbour entry)
+        film_nnz = float((np.diff(rp)[d["model"] == 1]).sum())
         row_bytes = {"build_neighbours": 4.0 * nnz + 41.0 * N, "classify_pca": 4.0 * nnz + 106.0 * N,
                      "apply": 18.0 * nnz + 40.0 * N, "transition": 4.0 * nnz + 48.0 * N,
-                     "apply_adjoint": 48.0 * nnz + 16.0 * N, "weights_adjoint": 80.0 * nnz + 56.0 * N}
+                     "apply_adjoint": 48.0 * nnz + 16.0 * N, "weights_adjoint": 80.0 * nnz + 56.0 * N,
+                     "film_height": 4.0 * film_nnz + 60.0 * float((d["model"] == 1).sum()) + 13.0 * N,
+                     "buffer_zone": 60.0 * N}
         roof_rows = {}
         for key, byts in row_bytes.items():
             us = sum(kern.get(key, {}).values())
@@ -501,7 +521,14 @@ def main():
             t0 = time.perf_counter()
             oracle.weights_adjoint_x(d, rp_o, col_o, f, yb_o, 8)
             orows["weights_adjoint_s"] = time.perf_counter() - t0
-            for key in ("classify_pca", "apply", "transition", "apply_adjoint", "weights_adjoint"):
+            t0 = time.perf_counter()
+            oracle.film_height(d, rp_o, col_o, d["diam"])
+            orows["film_height_s"] = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            oracle.buffer_zone(d, xr_o, xc_o, d["film_height"], d["h_other"], d["mass"], d["rho"])
+            orows["buffer_zone_s"] = time.perf_counter() - t0
+            for key in ("classify_pca", "apply", "transition", "apply_adjoint", "weights_adjoint",
+                        "film_height", "buffer_zone"):
                 if key in result.get("rows_roofline", {}):
                     rr = result["rows_roofline"][key]
                     rr["oracle_s"] = round(orows[key + "_s"], 4)

@@ -39,7 +39,7 @@ typedef enum {
   GF_ENOMEM = -2,      /* device allocation failed */
   GF_EHIP = -3,        /* a HIP runtime call failed */
   GF_ECAPACITY = -4,   /* a documented size limit was exceeded */
-  GF_ENOTCONV = -5,    /* iterative solve hit its iteration limit */
+  GF_ENOTCONV = -5,    /* iterative solve did not reach its tolerance */
   GF_EBREAKDOWN = -6   /* iterative solve broke down and could not restart */
 } gf_status;
 
@@ -119,6 +119,14 @@ gf_status gf_set_tile_capacity(gf_ctx *ctx, int entries);
  * The handle holds the CSR lists, the Morton processing order and the
  * grouping of particles used by the batched kernels. */
 gf_status gf_build_neighbours(gf_ctx *ctx, const gf_particles *p, int cross_model, gf_nbr **out);
+/* Extended neighbourhoods of a cloud whose particles [n_rows, n) are ghost
+ * particles (Sec. 6.2): the rows of particles [0, n_rows) hold S_i of
+ * Eq. (Nbd) over regular and ghost particles alike (S_i joined with the ghost
+ * neighbours S_i^g); no derivatives are taken at ghost particles, so a ghost's
+ * own row holds only itself.  0 <= n_rows <= n; n_rows = n is
+ * gf_build_neighbours.  Everything else as gf_build_neighbours. */
+gf_status gf_build_neighbours_rows(gf_ctx *ctx, const gf_particles *p, int cross_model, int64_t n_rows,
+                                   gf_nbr **out);
 /* n, nnz and the longest row of a neighbour handle (host outputs, any NULL). */
 gf_status gf_nbr_info(const gf_nbr *nbr, int64_t *n, int64_t *nnz, int32_t *max_row);
 /* Copy the CSR lists into caller buffers (device): row_ptr [n+1] int64,
@@ -257,7 +265,13 @@ typedef struct {
  * stencils w64.  Right-preconditioned BiCGStab with the Jacobi (diagonal)
  * preconditioner.  p_inout: initial guess in, solution out (FP64, device).
  * Synchronises (convergence checks).  Returns GF_ENOTCONV if the tolerance is
- * not reached within maxit; p_inout then holds the last iterate. */
+ * not reached within maxit, or (FP64 mode) if three restarts after
+ * breakdowns in a row fail to cut the true residual by 10% (the tolerance lies
+ * below the attainable accuracy); p_inout then holds the last iterate and
+ * stats->final_rel_res the residual reached.
+ * Ghost particles (Sec. 6.2): rows of type GF_ROW_DIRICHLET whose right-hand
+ * side and initial guess hold the known ghost values keep those values, and
+ * the regular rows then solve A_rr p_r = rhs_r - A_rg p_g. */
 gf_status gf_poisson_solve(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr,
                            const double *w64, const int8_t *row_type, const double *rhs,
                            double *p_inout, const gf_solve_params *params,
@@ -280,6 +294,96 @@ gf_status gf_transition_3d_to_2d(gf_ctx *ctx, const gf_particles *p, const gf_nb
                                  const double *phi, double *mass_out, double *rho_out,
                                  double *phi_out, double *height_out, double *diam_out,
                                  uint8_t *keep_out, int32_t *owner_out);
+
+/* ---------------------------------------------------------- coupling layer */
+/* Particles created by gf_transition_2d_to_3d or gf_buffer_zone: caller-owned
+ * device arrays (structure of arrays) with room for `cap` particles each.
+ * x, y, z, h, model, kind, nx, ny, nz, mass and rho are required when cap > 0;
+ * phi holds nphi fields, field f at phi[f * cap + t]; height, diam and src
+ * (index of the particle a new one was made from) may be NULL. */
+typedef struct {
+  int64_t cap;
+  double *x, *y, *z, *h;
+  int8_t *model, *kind;
+  double *nx, *ny, *nz;
+  double *mass, *rho;
+  double *phi;
+  double *height, *diam;
+  int32_t *src;
+} gf_new_particles;
+
+/* largest number of particles a 2D->3D transition adds to one film particle */
+enum { GF_MAX_GAMMA = 65536 };
+
+/* Film height of the droplet model (Eq. Height, Sec. 2.4): for every film
+ * particle i
+ *   H_i = sum_{j in S_i} alpha / (pi h_j^2) exp(-alpha |x_j - x_i|^2 / h_j^2) V_j,
+ * V_j = pi d_j^3 / 6, over the same-model neighbourhood `same` (which holds
+ * i); 3D particles get 0.  diam [n] FP64: droplet diameters (read for film
+ * particles).  alpha > 0: the paper obtains it from a mass-conservation
+ * condition of the droplet model it cites; here it is a parameter.
+ * height_out [n] FP64. */
+gf_status gf_film_height(gf_ctx *ctx, const gf_particles *p, const gf_nbr *same, const double *diam,
+                         double alpha, double *height_out);
+
+/* 2D -> 3D transition (Sec. 5.2, Alg. 4) of the film particles i with
+ * flag[i] == 2 (film -> bulk, as gf_classify_pca marks them).  With the film
+ * height H_i, the inward unit normal n_i and the 3D resolution h3d_i at the
+ * particle: psi~ = (r_min h3d_i + r_max h3d_i) / 2 (Eq. psi~), gamma_i =
+ * ceil(H_i / psi~) (Eq. gamma; 0 unless H_i > 0) and psi = H_i / gamma_i.
+ * Each such particle yields 1 + gamma_i 3D particles in `out`, consecutive
+ * and in ascending order of i: first the particle itself as a wall particle,
+ * then x_i + (k psi) n_i for k = 1..gamma_i, the last a free-surface particle
+ * and the others interior.  All get h = h3d_i, the normal n_i, density rho_i
+ * and the nphi fields of i (phi [nphi][n]) copied, the mass m_i / (1 +
+ * gamma_i), height = diam = 0 and src = i.  Not part of this call: the wall
+ * re-spacing of Alg. 4 and a free-surface check of the added particles
+ * (point-cloud management).  r_min > 0, r_max >= r_min: the spacing factors
+ * of Sec. 2.3.  *count (host) receives the number of new particles; above
+ * out->cap the call returns GF_ECAPACITY and writes nothing.  GF_EINVAL if
+ * some gamma_i would exceed GF_MAX_GAMMA.  Synchronises. */
+gf_status gf_transition_2d_to_3d(gf_ctx *ctx, const gf_particles *p, const uint8_t *flag,
+                                 const double *film_height, const double *h3d, double r_min,
+                                 double r_max, const double *mass, const double *rho,
+                                 const double *phi, int nphi, gf_new_particles *out,
+                                 int64_t *count);
+
+/* Buffer zone, first loop of Alg. 5 (Sec. 6.1): flag_out[i] = 1 iff a
+ * particle of the other model lies within the support of i (Eq. Nbd).  The
+ * relation is symmetric, so both particles of every cross-model pair are
+ * flagged.  same / cross: same-model and cross-model neighbourhoods of p
+ * (the flag is whether their rows differ in length).  flag_out uint8 [n]. */
+gf_status gf_buffer_flags(gf_ctx *ctx, const gf_particles *p, const gf_nbr *same,
+                          const gf_nbr *cross, uint8_t *flag_out);
+
+/* Ghost particles of the buffer zone (Sec. 6.1, Alg. 5).  Each particle
+ * flagged by gf_buffer_flags gets a ghost of its own model at its place, and
+ * the ghosts then change model:
+ *  - 3D ghosts as in Sec. 5.1 with every wall ghost transitioning: an
+ *    interior or free-surface ghost b is mapped onto the nearest wall ghost
+ *    of its support (smaller index on ties) and deleted; a wall ghost i
+ *    becomes a 2D ghost with rho and the fields averaged over i and the ghosts
+ *    mapped onto it, the masses lumped, height = max |(x_b - x_i) . n_i|
+ *    and diam = (6 m / (pi rho))^(1/3).  Interior or free-surface ghosts with
+ *    no wall ghost in their support are dropped.
+ *  - 2D ghosts as in gf_transition_2d_to_3d, with h_other as the 3D
+ *    resolution.
+ * h_other [n]: resolution of the other model at each particle (the h of the
+ * ghosts made from it).  film_height [n] (read for film particles), mass,
+ * rho [n], phi [nphi][n] FP64.  Ghosts come out in ascending order of their
+ * source particle (src), the 1 + gamma ghosts of a film particle in the
+ * order of gf_transition_2d_to_3d.  flag_out (uint8 [n], may be NULL)
+ * receives the buffer flags.  *count, capacity and errors as in
+ * gf_transition_2d_to_3d.  Synchronises.
+ * Derivatives with ghosts (Sec. 6.2): append the ghosts to the particles,
+ * build gf_build_neighbours_rows with n_rows = the regular count, then
+ * compute stencils as usual.  In an implicit solve give ghost rows type
+ * GF_ROW_DIRICHLET with the known ghost values as right-hand side and
+ * initial guess: the regular rows then solve A_rr p_r = b_r - A_rg p_g. */
+gf_status gf_buffer_zone(gf_ctx *ctx, const gf_particles *p, const gf_nbr *same, const gf_nbr *cross,
+                         const double *film_height, const double *h_other, double r_min,
+                         double r_max, const double *mass, const double *rho, const double *phi,
+                         int nphi, gf_new_particles *out, int64_t *count, uint8_t *flag_out);
 
 /* ---------------------------------------------------------- adjoints */
 /* Transpose of gf_apply_stencil with respect to u: ubar = C^T ybar, where

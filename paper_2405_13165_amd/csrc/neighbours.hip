@@ -254,11 +254,13 @@ __device__ inline bool in_support(double4 a, double4 b) {
   return d2 <= r * r;
 }
 
-// MODE 0: count (cnt[i] = |S_i|, group histogram, max row); MODE 1: fill col
+// MODE 0: count (cnt[i] = |S_i|, group histogram, max row); MODE 1: fill col.
+// Particles i >= n_rows (ghost particles) appear in the rows of others but
+// their own row holds only i.
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_search(const int32_t *__restrict__ order, const double4 *__restrict__ sp,
                                                    const int8_t *__restrict__ model, const int32_t *__restrict__ cell_start,
-                                                   int64_t n, Grid g, int32_t *__restrict__ cnt,
+                                                   int64_t n, int64_t n_rows, Grid g, int32_t *__restrict__ cnt,
                                                    int32_t *__restrict__ hist, int32_t *__restrict__ maxrow,
                                                    const int64_t *__restrict__ row_ptr, int32_t *__restrict__ col) {
   const int64_t sidx0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -277,6 +279,10 @@ __global__ void __launch_bounds__(kBlock) k_search(const int32_t *__restrict__ o
   int c = 0;
   int64_t out = 0;
   if (MODE == 1) out = row_ptr[i];
+  if (i >= n_rows) {
+    if (MODE == 1) col[out] = i;
+    c = 1;
+  } else
   for (int dz = -1; dz <= 1; ++dz) {
     int zz = cz + dz;
     if (zz < 0 || zz >= g.dim[s][2]) continue;
@@ -685,11 +691,20 @@ gf_status build_tiles(gf_ctx *ctx, gf_nbr *nb) {
 
 extern "C" gf_status gf_build_neighbours(gf_ctx *ctx, const gf_particles *p, int cross_model, gf_nbr **out) {
   if (!ctx) return GF_EINVAL;
+  if (!p) return set_error(ctx, GF_EINVAL, "particles are NULL");
+  return gf_build_neighbours_rows(ctx, p, cross_model, p->n, out);
+}
+
+extern "C" gf_status gf_build_neighbours_rows(gf_ctx *ctx, const gf_particles *p, int cross_model, int64_t n_rows,
+                                              gf_nbr **out) {
+  if (!ctx) return GF_EINVAL;
   if (!out) return set_error(ctx, GF_EINVAL, "out is NULL");
   *out = nullptr;
   gf_status st = check_particles(ctx, p, false, false);
   if (st) return st;
   const int64_t n = p->n;
+  if (n_rows < 0 || n_rows > n)
+    return set_error(ctx, GF_EINVAL, "n_rows = %lld outside [0, %lld]", (long long)n_rows, (long long)n);
   hipStream_t sm = ctx->stream;
 
   // ---- bounding boxes and validation
@@ -806,7 +821,7 @@ extern "C" gf_status gf_build_neighbours(gf_ctx *ctx, const gf_particles *p, int
   {
   ProfScope prof_count(ctx, "nbr_count");
   hipLaunchKernelGGL(k_search<0>, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, nb->order, sp, p->model,
-                     cell_start, n, g, cnt, small, small + 8, (const int64_t *)nullptr, (int32_t *)nullptr);
+                     cell_start, n, n_rows, g, cnt, small, small + 8, (const int64_t *)nullptr, (int32_t *)nullptr);
   }
   if (hipGetLastError() != hipSuccess) return fail(set_error(ctx, GF_EHIP, "count kernel launch failed"));
   if ((st = scan_i32_to_i64(ctx, cnt, nb->row_ptr, n, tmp64))) return fail(st);
@@ -835,7 +850,7 @@ extern "C" gf_status gf_build_neighbours(gf_ctx *ctx, const gf_particles *p, int
   {
   ProfScope prof_fill(ctx, "nbr_fill");
   hipLaunchKernelGGL(k_search<1>, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, nb->order, sp, p->model,
-                     cell_start, n, g, (int32_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr, nb->row_ptr,
+                     cell_start, n, n_rows, g, (int32_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr, nb->row_ptr,
                      nb->col);
   }
   {

@@ -603,6 +603,10 @@ extern "C" gf_status gf_poisson_solve(gf_ctx *ctx, const gf_particles *p, const 
   int total = 0;
   if (!mixed) {
     sts.outer_its = 1;
+    // true residual at the last restart; restarts that no longer reduce it
+    // mean the tolerance is below the attainable accuracy
+    double restart_rnorm = rnorm;
+    int stagnant = 0;
     while (rnorm > target && total < prm.maxit) {
       if ((st = bicgstab_iter<double, double>(sv, V64))) return st;
       ++total;
@@ -618,6 +622,9 @@ extern "C" gf_status gf_poisson_solve(gf_ctx *ctx, const gf_particles *p, const 
         hipLaunchKernelGGL(k_zero_vecs<double>, dim3(sv.grid_row), dim3(kBlock), 0, sm, n, V64.p, V64.v);
         if ((st = read_scal(sv))) return st;
         rnorm = std::sqrt(sv.hS->rr);
+        stagnant = rnorm < 0.9 * restart_rnorm ? 0 : stagnant + 1;
+        restart_rnorm = std::min(restart_rnorm, rnorm);
+        if (stagnant >= 3) break;
         continue;
       }
       rnorm = std::sqrt(sv.hS->rr);

@@ -66,6 +66,11 @@ class SolveStats(ctypes.Structure):
                 ("final_rel_res", ctypes.c_double)]
 
 
+class NewParticles(ctypes.Structure):
+    _fields_ = [("cap", ctypes.c_int64)] + [(k, ctypes.c_void_p) for k in (
+        "x", "y", "z", "h", "model", "kind", "nx", "ny", "nz", "mass", "rho", "phi", "height", "diam", "src")]
+
+
 EXPORTED = [
     "gf_version", "gf_create", "gf_set_stream", "gf_destroy", "gf_last_error",
     "gf_build_neighbours", "gf_nbr_info", "gf_nbr_export", "gf_nbr_free",
@@ -73,6 +78,7 @@ EXPORTED = [
     "gf_apply_stencil", "gf_gfdm_weights_apply", "gf_poisson_assemble", "gf_solve_params_default",
     "gf_poisson_solve", "gf_transition_3d_to_2d", "gf_apply_stencil_adjoint",
     "gf_gfdm_weights_adjoint", "gf_profile_enable", "gf_profile_read", "gf_autotune", "gf_set_tile_capacity",
+    "gf_build_neighbours_rows", "gf_film_height", "gf_transition_2d_to_3d", "gf_buffer_flags", "gf_buffer_zone",
 ]
 
 _lib = None
@@ -122,6 +128,12 @@ def load_library(path: str = LIB_PATH):
     L.gf_profile_enable.argtypes = [P, I32]
     L.gf_set_tile_capacity.argtypes = [P, I32]
     L.gf_profile_read.argtypes = [P, ctypes.c_char_p, ctypes.c_size_t]
+    L.gf_build_neighbours_rows.argtypes = [P, PP, I32, I64, ctypes.POINTER(P)]
+    L.gf_film_height.argtypes = [P, PP, P, P, D, P]
+    NP = ctypes.POINTER(NewParticles)
+    L.gf_transition_2d_to_3d.argtypes = [P, PP, P, P, P, D, D, P, P, P, I32, NP, ctypes.POINTER(I64)]
+    L.gf_buffer_flags.argtypes = [P, PP, P, P, P]
+    L.gf_buffer_zone.argtypes = [P, PP, P, P, P, P, D, D, P, P, P, I32, NP, ctypes.POINTER(I64), P]
     for name in EXPORTED:
         getattr(L, name)  # every declared entry point must resolve
     _lib = L
@@ -254,10 +266,16 @@ class Neighbours:
             pass
 
 
-def build_neighbours(ctx: Context, p: Particles, cross_model: bool = False) -> Neighbours:
+def build_neighbours(ctx: Context, p: Particles, cross_model: bool = False, n_rows=None) -> Neighbours:
+    """gf_build_neighbours, or gf_build_neighbours_rows when n_rows is given
+    (particles from n_rows on are ghosts: neighbours of others, rows of their own)."""
     h = ctypes.c_void_p()
     ctx._sync_stream()
-    ctx.check(ctx.lib.gf_build_neighbours(ctx.handle, ctypes.byref(p.s), int(cross_model), ctypes.byref(h)))
+    if n_rows is None:
+        ctx.check(ctx.lib.gf_build_neighbours(ctx.handle, ctypes.byref(p.s), int(cross_model), ctypes.byref(h)))
+    else:
+        ctx.check(ctx.lib.gf_build_neighbours_rows(ctx.handle, ctypes.byref(p.s), int(cross_model), int(n_rows),
+                                                   ctypes.byref(h)))
     return Neighbours(ctx, h)
 
 
@@ -402,6 +420,105 @@ def transition_3d_to_2d(ctx, p, nbr, flag, mass, rho, phi):
                                              _ptr(out["height"]), _ptr(out["diam"]), _ptr(out["keep"]),
                                              _ptr(out["owner"])))
     return out
+
+
+R_MIN, R_MAX, ALPHA_FILM = 0.2, 0.4, 8.0
+_NEW_F64 = ("x", "y", "z", "h", "nx", "ny", "nz", "mass", "rho", "height", "diam")
+
+
+def film_height(ctx, p, same, diam, alpha=ALPHA_FILM, out=None):
+    """gf_film_height: Eq. (Height) at film particles, 0 at bulk particles."""
+    dev = ctx.device
+    d = _dev_tensor(diam, torch.float64, dev)
+    out = torch.empty(p.n, dtype=torch.float64, device=dev) if out is None else out
+    ctx._sync_stream()
+    ctx.check(ctx.lib.gf_film_height(ctx.handle, ctypes.byref(p.s), same.handle, _ptr(d), float(alpha), _ptr(out)))
+    return out
+
+
+def _new_buffers(dev, cap, nphi):
+    c = max(int(cap), 1)
+    o = {k: torch.empty(c, dtype=torch.float64, device=dev) for k in _NEW_F64}
+    o["model"] = torch.empty(c, dtype=torch.int8, device=dev)
+    o["kind"] = torch.empty(c, dtype=torch.int8, device=dev)
+    o["src"] = torch.empty(c, dtype=torch.int32, device=dev)
+    o["phi"] = torch.empty((max(nphi, 1), c), dtype=torch.float64, device=dev)
+    st = NewParticles(int(cap), *[_ptr(o[k]) for k in ("x", "y", "z", "h", "model", "kind", "nx", "ny", "nz",
+                                                      "mass", "rho", "phi", "height", "diam", "src")])
+    return o, st
+
+
+def _phi_rows(phi, n, dev):
+    if phi is None:
+        return None, 0
+    t = _dev_tensor(phi, torch.float64, dev).reshape(-1, n).contiguous()
+    return t, int(t.shape[0])
+
+
+def _grow_call(ctx, call, nphi, guess_attr):
+    """Runs a call that writes new particles, growing the buffers once if the
+    first guess of the count was too small (the call reports the count)."""
+    dev = ctx.device
+    cap = getattr(ctx, guess_attr, 1024)
+    for _ in range(2):
+        o, st = _new_buffers(dev, cap, nphi)
+        cnt = ctypes.c_int64(0)
+        ctx._sync_stream()
+        status = call(ctypes.byref(st), ctypes.byref(cnt))
+        if status == GF_ECAPACITY and cnt.value > cap:
+            cap = cnt.value + cnt.value // 4 + 64
+            setattr(ctx, guess_attr, cap)
+            continue
+        ctx.check(status)
+        k = cnt.value
+        out = {key: (v[:nphi, :k] if key == "phi" else v[:k]) for key, v in o.items()}
+        return out
+    raise GfdmError(GF_ECAPACITY, "particle count changed between calls")
+
+
+def transition_2d_to_3d(ctx, p, flag, height, h3d, mass, rho, phi=None, r_min=R_MIN, r_max=R_MAX):
+    """gf_transition_2d_to_3d: dict of the new 3D particles (flag == 2 film particles)."""
+    dev = ctx.device
+    fl = _dev_tensor(flag, torch.uint8, dev)
+    H = _dev_tensor(height, torch.float64, dev)
+    h3 = _dev_tensor(h3d, torch.float64, dev)
+    m = _dev_tensor(mass, torch.float64, dev)
+    r = _dev_tensor(rho, torch.float64, dev)
+    ph, nphi = _phi_rows(phi, p.n, dev)
+    return _grow_call(ctx, lambda st, cnt: ctx.lib.gf_transition_2d_to_3d(
+        ctx.handle, ctypes.byref(p.s), _ptr(fl), _ptr(H), _ptr(h3), float(r_min), float(r_max), _ptr(m), _ptr(r),
+        _ptr(ph), nphi, st, cnt), nphi, "_cap_2d3d")
+
+
+def buffer_flags(ctx, p, same, cross, out=None):
+    """gf_buffer_flags: uint8 [n], 1 near a particle of the other model."""
+    out = torch.empty(p.n, dtype=torch.uint8, device=ctx.device) if out is None else out
+    ctx._sync_stream()
+    ctx.check(ctx.lib.gf_buffer_flags(ctx.handle, ctypes.byref(p.s), same.handle, cross.handle, _ptr(out)))
+    return out
+
+
+def buffer_zone(ctx, p, same, cross, film_h, h_other, mass, rho, phi=None, r_min=R_MIN, r_max=R_MAX):
+    """gf_buffer_zone: (buffer flags, dict of ghost particle arrays)."""
+    dev = ctx.device
+    H = _dev_tensor(film_h, torch.float64, dev)
+    ho = _dev_tensor(h_other, torch.float64, dev)
+    m = _dev_tensor(mass, torch.float64, dev)
+    r = _dev_tensor(rho, torch.float64, dev)
+    ph, nphi = _phi_rows(phi, p.n, dev)
+    flag = torch.empty(p.n, dtype=torch.uint8, device=dev)
+    g = _grow_call(ctx, lambda st, cnt: ctx.lib.gf_buffer_zone(
+        ctx.handle, ctypes.byref(p.s), same.handle, cross.handle, _ptr(H), _ptr(ho), float(r_min), float(r_max),
+        _ptr(m), _ptr(r), _ptr(ph), nphi, st, cnt, _ptr(flag)), nphi, "_cap_ghosts")
+    return flag, g
+
+
+def extend_particles(ctx, p, ghosts):
+    """Regular particles followed by the ghosts (Sec. 6.2), as one cloud."""
+    cat = lambda a, b: torch.cat([a, b.to(a.dtype)])
+    return Particles(ctx, cat(p.x, ghosts["x"]), cat(p.y, ghosts["y"]), cat(p.z, ghosts["z"]),
+                     cat(p.h, ghosts["h"]), cat(p.model, ghosts["model"]), cat(p.kind, ghosts["kind"]),
+                     cat(p.nx, ghosts["nx"]), cat(p.ny, ghosts["ny"]), cat(p.nz, ghosts["nz"]))
 
 
 def apply_stencil_adjoint(ctx, nbr, w, ybar, op_mask=0xF):

@@ -156,6 +156,46 @@ def test_full_differentiation_fd(ctx, g):
     assert checked >= 90
 
 
+def test_full_buffer_zone_and_extended_stencils(ctx, g):
+    print("\n[full] buffer zone, mixed 503,944", flush=True)
+    d = W.mixed_block_film()
+    n = d["x"].size
+    p = g.Particles.from_dict(ctx, d)
+    same = g.build_neighbours(ctx, p)
+    cross = g.build_neighbours(ctx, p, cross_model=True)
+    flag, gh = g.buffer_zone(ctx, p, same, cross, d["film_height"], d["h_other"], d["mass"], d["rho"],
+                             d["film_height"][None, :])
+    rp_c, col_c = oracle.neighbours(d, cross=True)
+    flag_o, gh_o = oracle.buffer_zone(d, rp_c, col_c, d["film_height"], d["h_other"], d["mass"], d["rho"],
+                                      d["film_height"][None, :])
+    assert np.array_equal(_np(flag), flag_o)
+    for key in ("model", "kind", "src", "x", "y", "z", "h", "mass", "rho", "height", "phi"):
+        assert np.array_equal(_np(gh[key]), gh_o[key]), key
+    assert np.all(np.abs(_np(gh["diam"]) - gh_o["diam"]) <= 1e-15 * gh_o["diam"])
+    # film height over the whole cloud
+    rp_s, col_s = oracle.neighbours(d)
+    H = _np(g.film_height(ctx, p, same, d["diam"]))
+    assert np.all(np.abs(H - oracle.film_height(d, rp_s, col_s, d["diam"])) <= 1e-13 * H)
+    # extended neighbourhoods and FP32 stencils in the batched launch configuration
+    pe = g.extend_particles(ctx, p, gh)
+    de = oracle.extend_cloud(d, gh_o)
+    nb = g.build_neighbours(ctx, pe, n_rows=n)
+    rp_o, col_o = oracle.neighbours_rows(de, n)
+    rp, col = nb.export()
+    assert np.array_equal(_np(rp), rp_o) and np.array_equal(_np(col), col_o)
+    g.autotune(ctx, pe, nb, g.GF_F32)
+    w32 = g.gfdm_weights(ctx, pe, nb, g.GF_BATCHED, g.GF_F32)
+    rid = np.repeat(np.arange(pe.n), np.diff(rp_o))
+    touched = np.unique(rid[(col_o >= n) & (rid < n)])
+    rows = np.unique(np.concatenate([touched, np.random.default_rng(41).choice(n, 5000, replace=False)]))
+    w_o, _, _ = oracle.gfdm_weights(de, rp_o, col_o, rows=rows)
+    sel = np.concatenate([np.arange(rp_o[i], rp_o[i + 1]) for i in rows])
+    sub_rp = np.concatenate([[0], np.cumsum(np.diff(rp_o)[rows])])
+    e = oracle.operator_error(_np(w32)[sel].astype(np.float64), w_o[sel], sub_rp)
+    print(f"[full] {touched.size} rows with ghost neighbours; FP32 operator error {e.max():.3e}", flush=True)
+    assert e.max() <= 1e-6
+
+
 @pytest.mark.parametrize("mixed", [0, 1])
 def test_full_projection_solve(ctx, g, mixed):
     print(f"\n[full] projection 4.0M mixed={mixed}", flush=True)
