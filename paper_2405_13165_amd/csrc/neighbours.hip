@@ -1,13 +1,16 @@
-// Neighbourhoods S_i of Eq. (Nbd) by a cell list over Morton-ordered cells.
+// Neighbourhoods S_i of Eq. (Nbd) by cell lists over Morton-ordered cells.
 //
 // Pipeline (one stream, one host read-back of sizes):
-//   bbox/validate -> cell keys + per-cell counts (atomics) -> scan -> scatter
-//   into cell order -> positions gathered in cell order -> per-particle count
-//   over the 27 surrounding cells -> scan -> fill -> per-row bitonic sort
-//   -> grouping of particles by (model, neighbour-count band) for the
-//   batched stencil kernels.
-// Cells are cubes of edge max(h) (per model, or over all particles for the
-// cross-model sets), so every member of S_i lies in the 27 cells around i.
+//   bbox/validate -> grid of each particle (model, support level) and its
+//   cell key + per-cell counts (atomics) -> scan -> scatter into cell order
+//   -> list of non-empty cells -> finer Morton order inside cells ->
+//   positions gathered in cell order -> per-cell search, count pass -> scan
+//   -> fill pass -> per-row sort -> grouping of particles by (model,
+//   neighbour-count band) for the batched stencil kernels -> neighbour tiles.
+// Each model has grids for up to four support levels (caps hmax, hmax/2,
+// ...); a cell of a grid is a cube of edge slightly above its cap, and a row
+// cell searches, in every grid of the requested models, the cells within
+// (h_row + cap)/2 of its particles.
 #include <algorithm>
 #include <cstring>
 
@@ -35,8 +38,17 @@ __device__ inline int wave_sum_i(int v) {
   return v;
 }
 
-// per model: lo[3], hi[3], hmax  (7 doubles) -> 14 doubles + invalid count
-constexpr int kBoxVals = 14;
+// orders the LDS traffic of the lanes of one wave
+__device__ inline void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// per model: lo[3], hi[3], hmax, hmin (8 doubles) -> 16 doubles + invalid count
+constexpr int kBoxVals = 16;
+// value k of the box is reduced with min (else max)
+__host__ __device__ inline bool box_is_min(int k) { return (k % 8) < 3 || (k % 8) == 7; }
 
 __global__ void __launch_bounds__(kBlock) k_bbox(const double *__restrict__ x, const double *__restrict__ y,
                                                  const double *__restrict__ z, const double *__restrict__ h,
@@ -44,8 +56,9 @@ __global__ void __launch_bounds__(kBlock) k_bbox(const double *__restrict__ x, c
                                                  double *__restrict__ part, int *__restrict__ bad_part) {
   double v[kBoxVals];
   for (int m = 0; m < 2; ++m) {
-    for (int d = 0; d < 3; ++d) { v[m * 7 + d] = INFINITY; v[m * 7 + 3 + d] = -INFINITY; }
-    v[m * 7 + 6] = 0.0;
+    for (int d = 0; d < 3; ++d) { v[m * 8 + d] = INFINITY; v[m * 8 + 3 + d] = -INFINITY; }
+    v[m * 8 + 6] = 0.0;
+    v[m * 8 + 7] = INFINITY;
   }
   int bad = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -57,27 +70,27 @@ __global__ void __launch_bounds__(kBlock) k_bbox(const double *__restrict__ x, c
     for (int mm = 0; mm < 2; ++mm) {
       if (mm != m) continue;
       for (int d = 0; d < 3; ++d) {
-        v[mm * 7 + d] = fmin(v[mm * 7 + d], p[d]);
-        v[mm * 7 + 3 + d] = fmax(v[mm * 7 + 3 + d], p[d]);
+        v[mm * 8 + d] = fmin(v[mm * 8 + d], p[d]);
+        v[mm * 8 + 3 + d] = fmax(v[mm * 8 + 3 + d], p[d]);
       }
-      v[mm * 7 + 6] = fmax(v[mm * 7 + 6], hi);
+      v[mm * 8 + 6] = fmax(v[mm * 8 + 6], hi);
+      v[mm * 8 + 7] = fmin(v[mm * 8 + 7], hi);
     }
   }
   __shared__ double sh[kBlock / 64][kBoxVals];
   __shared__ int shb[kBlock / 64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int k = 0; k < kBoxVals; ++k) {
-    int kk = k % 7;
-    double r = (kk < 3) ? wave_min(v[k]) : wave_max(v[k]);
+    double r = box_is_min(k) ? wave_min(v[k]) : wave_max(v[k]);
     if (lane == 0) sh[wid][k] = r;
   }
   int bs = wave_sum_i(bad);
   if (lane == 0) shb[wid] = bs;
   __syncthreads();
   if (threadIdx.x < kBoxVals) {
-    int k = threadIdx.x, kk = k % 7;
+    int k = threadIdx.x;
     double r = sh[0][k];
-    for (int w = 1; w < kBlock / 64; ++w) r = (kk < 3) ? fmin(r, sh[w][k]) : fmax(r, sh[w][k]);
+    for (int w = 1; w < kBlock / 64; ++w) r = box_is_min(k) ? fmin(r, sh[w][k]) : fmax(r, sh[w][k]);
     part[(int64_t)blockIdx.x * kBoxVals + k] = r;
   }
   if (threadIdx.x == 0) {
@@ -87,35 +100,63 @@ __global__ void __launch_bounds__(kBlock) k_bbox(const double *__restrict__ x, c
   }
 }
 
-__global__ void k_bbox_final(const double *__restrict__ part, const int *__restrict__ bad_part, int nblk,
-                             double *__restrict__ out, int *__restrict__ bad_out) {
-  int k = threadIdx.x;
-  if (k < kBoxVals) {
-    int kk = k % 7;
-    double r = part[k];
-    for (int b = 1; b < nblk; ++b) {
-      double t = part[(int64_t)b * kBoxVals + k];
-      r = (kk < 3) ? fmin(r, t) : fmax(r, t);
-    }
-    out[k] = r;
+// one block of kBboxFin threads: thread b takes block partial b (nblk <= kBboxFin)
+constexpr int kBboxFin = 1024;
+__global__ void __launch_bounds__(kBboxFin) k_bbox_final(const double *__restrict__ part,
+                                                         const int *__restrict__ bad_part, int nblk,
+                                                         double *__restrict__ out, int *__restrict__ bad_out) {
+  __shared__ double sh[kBboxFin / 64][kBoxVals];
+  __shared__ int shb[kBboxFin / 64];
+  const int b = threadIdx.x, lane = b & 63, wid = b >> 6;
+  const bool has = b < nblk;
+  for (int k = 0; k < kBoxVals; ++k) {
+    const bool lo = box_is_min(k);
+    const double t = has ? part[(int64_t)b * kBoxVals + k] : (lo ? INFINITY : -INFINITY);
+    const double r = lo ? wave_min(t) : wave_max(t);
+    if (lane == 0) sh[wid][k] = r;
   }
-  if (k == 0) {
-    int s = 0;
-    for (int b = 0; b < nblk; ++b) s += bad_part[b];
-    *bad_out = s;
+  const int bs = wave_sum_i(has ? bad_part[b] : 0);
+  if (lane == 0) shb[wid] = bs;
+  __syncthreads();
+  if (b < kBoxVals) {
+    const bool lo = box_is_min(b);
+    double r = sh[0][b];
+    for (int w = 1; w < kBboxFin / 64; ++w) r = lo ? fmin(r, sh[w][b]) : fmax(r, sh[w][b]);
+    out[b] = r;
+  }
+  if (b == 0) {
+    int sum = 0;
+    for (int w = 0; w < kBboxFin / 64; ++w) sum += shb[w];
+    *bad_out = sum;
   }
 }
 
 // -------------------------------------------------------------- grid
+// One cell grid per (model, level): level l of model m holds the particles
+// with hmax_m 2^-(l+1) < h <= hmax_m 2^-l (the last level takes the rest),
+// so a cell's edge follows the supports of its own particles.  A row cell
+// searches, in each target grid, the cells within (h_row + hcap_target)/2 of
+// its particles: uneven supports and dense fine regions do not inflate the
+// candidate sets of the others.
+constexpr int kMaxLevels = 4;
+constexpr int kMaxSlots = 2 * kMaxLevels;
 struct Grid {
-  double lo[2][3];
-  double inv_edge[2];
-  int dim[2][3];
-  int bits[2][3];
-  int64_t base[2];  // key offset of each model's cells
+  int nslots;
+  int slot0[3];              // slots of model m: [slot0[m], slot0[m + 1])
+  double lo[kMaxSlots][3];
+  double inv_edge[kMaxSlots];
+  double hcap[kMaxSlots];    // every particle of the slot has h <= hcap (0: model absent)
+  int dim[kMaxSlots][3];
+  int bits[kMaxSlots][3];
+  int64_t base[kMaxSlots];   // key offset of each slot's cells
   int64_t nkeys;
-  int per_model;    // 1: separate grids per model; 0: one grid for all
 };
+
+__host__ __device__ inline int slot_of(const Grid &g, int m, double h) {
+  int s = g.slot0[m];
+  while (s + 1 < g.slot0[m + 1] && h <= g.hcap[s + 1]) ++s;
+  return s;
+}
 
 __device__ inline int cell_of(double v, double lo, double inv_edge, int dim) {
   double t = floor((v - lo) * inv_edge);
@@ -136,20 +177,27 @@ __device__ inline int64_t morton(int cx, int cy, int cz, int bx, int by, int bz)
   return key;
 }
 
-__device__ inline int grid_slot(const Grid &g, int m) { return g.per_model ? m : 0; }
 
 __global__ void __launch_bounds__(kBlock) k_fill_i32(int32_t *a, int64_t n, int32_t v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     a[i] = v;
 }
 
+// key[i]: cell of particle i; counts[k]: particles per cell; slot_count[s]:
+// particles per grid
 __global__ void __launch_bounds__(kBlock) k_keys(const double *__restrict__ x, const double *__restrict__ y,
-                                                 const double *__restrict__ z, const int8_t *__restrict__ model,
-                                                 int64_t n, Grid g, int32_t *__restrict__ key,
-                                                 int32_t *__restrict__ slot, int32_t *__restrict__ counts) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                                 const double *__restrict__ z, const double *__restrict__ h,
+                                                 const int8_t *__restrict__ model, int64_t n, Grid g,
+                                                 int32_t *__restrict__ key, int32_t *__restrict__ slot,
+                                                 int32_t *__restrict__ counts, int32_t *__restrict__ slot_count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = i < n ? slot_of(g, model[i], h[i]) : -1;
+  // one atomic per wave and grid
+  for (int q = 0; q < g.nslots; ++q) {
+    const unsigned long long mask = __ballot(s == q);
+    if ((threadIdx.x & 63) == 0 && mask) atomicAdd(&slot_count[q], __popcll(mask));
+  }
   if (i >= n) return;
-  int s = grid_slot(g, model[i]);
   int cx = cell_of(x[i], g.lo[s][0], g.inv_edge[s], g.dim[s][0]);
   int cy = cell_of(y[i], g.lo[s][1], g.inv_edge[s], g.dim[s][1]);
   int cz = cell_of(z[i], g.lo[s][2], g.inv_edge[s], g.dim[s][2]);
@@ -164,6 +212,23 @@ __global__ void __launch_bounds__(kBlock) k_scatter(const int32_t *__restrict__ 
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   order[cell_start[key[i]] + slot[i]] = (int32_t)i;
+}
+
+// non-empty cells: head[s] = 1 where sorted position s starts a cell
+__global__ void __launch_bounds__(kBlock) k_cell_heads(const int32_t *__restrict__ order,
+                                                       const int32_t *__restrict__ key, int64_t n,
+                                                       int32_t *__restrict__ head) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  head[s] = (s == 0 || key[order[s]] != key[order[s - 1]]) ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(kBlock) k_cell_list(const int32_t *__restrict__ head,
+                                                      const int32_t *__restrict__ pos, int64_t n,
+                                                      int32_t *__restrict__ cells) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  if (head[s]) cells[pos[s]] = (int32_t)s;
 }
 
 // Order the particles of each cell by a finer Morton key (kSubBits more bits
@@ -190,21 +255,25 @@ __device__ inline uint64_t fine_key(double x, double y, double z, const Grid &g,
   return key;
 }
 
-__global__ void __launch_bounds__(64) k_cell_sort(const int32_t *__restrict__ cell_start, int64_t ncells,
-                                                  const double *__restrict__ x, const double *__restrict__ y,
-                                                  const double *__restrict__ z, const int8_t *__restrict__ model,
+// cells[c]: first sorted position of the c-th non-empty cell; *ncells and
+// the end n close the list
+__global__ void __launch_bounds__(64) k_cell_sort(const int32_t *__restrict__ cells, const int32_t *__restrict__ ncells,
+                                                  int64_t n, const double *__restrict__ x,
+                                                  const double *__restrict__ y, const double *__restrict__ z,
+                                                  const double *__restrict__ h, const int8_t *__restrict__ model,
                                                   Grid g, int32_t *__restrict__ order) {
   __shared__ uint64_t kk[kCellSort];
   __shared__ int32_t id[kCellSort];
-  for (int64_t c = blockIdx.x; c < ncells; c += gridDim.x) {
-    const int32_t b = cell_start[c], len = cell_start[c + 1] - b;
+  const int32_t nc = *ncells;
+  for (int64_t c = blockIdx.x; c < nc; c += gridDim.x) {
+    const int32_t b = cells[c], len = (c + 1 < nc ? cells[c + 1] : (int32_t)n) - b;
     if (len <= 1 || len > kCellSort) continue;
     int P = 1;
     while (P < len) P <<= 1;
     for (int t = threadIdx.x; t < P; t += 64) {
       if (t < len) {
         const int32_t i = order[b + t];
-        kk[t] = fine_key(x[i], y[i], z[i], g, grid_slot(g, model[i]));
+        kk[t] = fine_key(x[i], y[i], z[i], g, slot_of(g, model[i], h[i]));
         id[t] = i;
       } else {
         kk[t] = ~0ull;
@@ -254,104 +323,320 @@ __device__ inline bool in_support(double4 a, double4 b) {
   return d2 <= r * r;
 }
 
-// MODE 0: count (cnt[i] = |S_i|, group histogram, max row); MODE 1: fill col.
-// Particles i >= n_rows (ghost particles) appear in the rows of others but
-// their own row holds only i.
+// Neighbour search, one wave per non-empty cell (waves take the next cell from
+// a queue counter: bulk and film cells differ in cost), its rows in groups of
+// up to 64.  For each target grid (the row
+// model's grids, or all grids for cross-model sets) the cells within
+// R = (max h of the rows + hcap of the grid)/2 of the rows are taken 64 at a
+// time; their particles, numbered through a prefix sum of the cell ranges,
+// are tested 64 at a time (one per lane) against each row, and a ballot gives
+// the row's hits.  MODE 0: count (cnt[i] = |S_i|, group histogram, max row);
+// MODE 1: fill col (each row in candidate order; rows are sorted afterwards).
+// Both passes visit candidates in the same order, so the fill ends exactly at
+// the counted length.  With `stage`, the count pass also writes each row's
+// first kStage hits to stage[i * kStage ...], which saves the fill pass when
+// no row is longer.  Particles i >= n_rows (ghost particles) appear in the
+// rows of others but their own row holds only i.
+constexpr int kSearchBlock = 256;
+constexpr int kSearchWaves = kSearchBlock / 64;
+constexpr int kSearchWavesPerSimd = 6;  // occupancy the search kernels are compiled for
+constexpr int kQueueGrab = 4;           // cells a wave takes from the queue at once
+constexpr int kStage = 256;             // hits per row the count pass can stage
+
+// the value of v in lane r (r the same in every lane)
+__device__ inline int64_t readlane64(int64_t v, int r) {
+  return ((int64_t)__builtin_amdgcn_readlane((int)(v >> 32), r) << 32) |
+         (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, r);
+}
+
+// a value known to be the same in every lane, moved to scalar registers
+__device__ inline double uniform_f64(double v) {
+  const int64_t b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
+}
+
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_search(const int32_t *__restrict__ order, const double4 *__restrict__ sp,
-                                                   const int8_t *__restrict__ model, const int32_t *__restrict__ cell_start,
-                                                   int64_t n, int64_t n_rows, Grid g, int32_t *__restrict__ cnt,
-                                                   int32_t *__restrict__ hist, int32_t *__restrict__ maxrow,
-                                                   const int64_t *__restrict__ row_ptr, int32_t *__restrict__ col) {
-  const int64_t sidx0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = sidx0 < n;
-  if (MODE == 1 && !valid) return;
-  // MODE 0 keeps the idle lanes of the last wave alive for the wave-wide
-  // histogram below; they search on behalf of particle n-1 and count nothing
-  const int64_t sidx = valid ? sidx0 : n - 1;
-  const int32_t i = order[sidx];
-  const double4 pi = sp[sidx];
-  const int m = model[i];
-  const int s = grid_slot(g, m);
-  const int cx = cell_of(pi.x, g.lo[s][0], g.inv_edge[s], g.dim[s][0]);
-  const int cy = cell_of(pi.y, g.lo[s][1], g.inv_edge[s], g.dim[s][1]);
-  const int cz = cell_of(pi.z, g.lo[s][2], g.inv_edge[s], g.dim[s][2]);
-  int c = 0;
-  int64_t out = 0;
-  if (MODE == 1) out = row_ptr[i];
-  if (i >= n_rows) {
-    if (MODE == 1) col[out] = i;
-    c = 1;
-  } else
-  for (int dz = -1; dz <= 1; ++dz) {
-    int zz = cz + dz;
-    if (zz < 0 || zz >= g.dim[s][2]) continue;
-    for (int dy = -1; dy <= 1; ++dy) {
-      int yy = cy + dy;
-      if (yy < 0 || yy >= g.dim[s][1]) continue;
-      for (int dx = -1; dx <= 1; ++dx) {
-        int xx = cx + dx;
-        if (xx < 0 || xx >= g.dim[s][0]) continue;
-        int64_t k = g.base[s] + morton(xx, yy, zz, g.bits[s][0], g.bits[s][1], g.bits[s][2]);
-        int32_t b = cell_start[k], e = cell_start[k + 1];
-        for (int32_t t = b; t < e; ++t) {
-          if (in_support(pi, sp[t])) {
-            if (MODE == 1) {
-              if (c < kMaxRow) col[out + c] = order[t];
-            }
-            ++c;
-          }
+__global__ void __launch_bounds__(kSearchBlock) __attribute__((amdgpu_waves_per_eu(kSearchWavesPerSimd))) k_search(const int32_t *__restrict__ order,
+                                                         const double4 *__restrict__ sp,
+                                                         const int8_t *__restrict__ model,
+                                                         const int32_t *__restrict__ cell_start,
+                                                         const int32_t *__restrict__ cells,
+                                                         const int32_t *__restrict__ ncells,
+                                                         const int32_t *__restrict__ slot_count,
+                                                         int32_t *__restrict__ queue, int64_t n,
+                                                         int64_t n_rows, Grid g, int cross,
+                                                         int32_t *__restrict__ cnt, int32_t *__restrict__ hist,
+                                                         int32_t *__restrict__ maxrow,
+                                                         const int64_t *__restrict__ row_ptr,
+                                                         int32_t *__restrict__ col, int32_t *__restrict__ stage) {
+  __shared__ int32_t s_rb[kSearchWaves][64];    // first sorted position of each cell of the batch
+  __shared__ int32_t s_pref[kSearchWaves][65];  // candidates before each cell of the batch
+  __shared__ double4 s_row[kSearchWaves][64];   // positions of the current row group
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int32_t nc = *ncells;
+  int hist_local = 0;  // lane b < 2*GF_NBAND: rows counted in bin b (MODE 0)
+  int max_local = 0;
+  int32_t grab = 0, left = 0;
+  while (true) {
+    if (left == 0) {  // kQueueGrab cells per queue access
+      int32_t next = 0;
+      if (lane == 0) next = atomicAdd(queue, kQueueGrab);
+      grab = __builtin_amdgcn_readfirstlane(next);
+      left = kQueueGrab;
+    }
+    const int32_t ci = grab + (kQueueGrab - left);
+    --left;
+    if (ci >= nc) break;
+    const int32_t c0 = cells[ci];
+    const int32_t c1 = (ci + 1 < nc) ? cells[ci + 1] : (int32_t)n;
+    const int mrow = model[order[c0]];
+    const int t0 = cross ? 0 : g.slot0[mrow], t1 = cross ? g.nslots : g.slot0[mrow + 1];
+    for (int32_t rg = c0; rg < c1; rg += 64) {
+      const int nr = min(64, c1 - rg);
+      int32_t myi = -1;
+      bool ghost = false;
+      int64_t myoff = 0;
+      int mylen = 0;  // MODE 1: the row's CSR length (bounds every write)
+      double4 me = make_double4(0.0, 0.0, 0.0, 0.0);
+      if (lane < nr) {
+        myi = order[rg + lane];
+        me = sp[rg + lane];
+        s_row[w][lane] = me;
+        ghost = myi >= n_rows;
+        if (MODE == 1) {
+          myoff = row_ptr[myi];
+          mylen = (int)(row_ptr[myi + 1] - myoff);
+          if (ghost && mylen > 0) col[myoff] = myi;
+        } else if (stage) {
+          myoff = (int64_t)myi * kStage;
+          mylen = kStage;
+          if (ghost) stage[myoff] = myi;
         }
       }
+      const bool act = lane < nr && !ghost;
+      const double bx0 = uniform_f64(wave_min(act ? me.x : INFINITY));
+      const double bx1 = uniform_f64(wave_max(act ? me.x : -INFINITY));
+      const double by0 = uniform_f64(wave_min(act ? me.y : INFINITY));
+      const double by1 = uniform_f64(wave_max(act ? me.y : -INFINITY));
+      const double bz0 = uniform_f64(wave_min(act ? me.z : INFINITY));
+      const double bz1 = uniform_f64(wave_max(act ? me.z : -INFINITY));
+      const double hrow = uniform_f64(wave_max(act ? me.w : 0.0));
+      const uint64_t ghosts = __ballot(ghost);
+      wave_fence();
+      int run = 0;  // lane r < nr: hits of row r so far
+      for (int ts = t0; ts < t1; ++ts) {
+        if (hrow <= 0.0 || slot_count[ts] == 0) continue;  // no searching row, or an empty grid
+        // cells within R of the rows (1e-6 margin against rounding of the cell coordinates)
+        const double R = 0.5 * (hrow + g.hcap[ts]) * (1.0 + 1e-6);
+        const double b0[3] = {bx0, by0, bz0}, b1[3] = {bx1, by1, bz1};
+        int a0[3], ext[3];
+        bool none = false;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const double f0 = floor((b0[d] - R - g.lo[ts][d]) * g.inv_edge[ts]);
+          const double f1 = floor((b1[d] + R - g.lo[ts][d]) * g.inv_edge[ts]);
+          const double top = (double)(g.dim[ts][d] - 1);
+          none = none || f1 < 0.0 || f0 > top;
+          a0[d] = __builtin_amdgcn_readfirstlane((int)fmax(f0, 0.0));
+          ext[d] = __builtin_amdgcn_readfirstlane((int)fmin(f1, top)) - a0[d] + 1;
+        }
+        if (none) continue;
+        const int64_t nbox = (int64_t)ext[0] * ext[1] * ext[2];
+        for (int64_t kb = 0; kb < nbox; kb += 64) {
+          int len = 0, rb = 0;
+          const int64_t kc = kb + lane;
+          if (kc < nbox) {
+            const int ix = (int)(kc % ext[0]), iy = (int)((kc / ext[0]) % ext[1]), iz = (int)(kc / ((int64_t)ext[0] * ext[1]));
+            const int64_t key = g.base[ts] + morton(a0[0] + ix, a0[1] + iy, a0[2] + iz, g.bits[ts][0], g.bits[ts][1],
+                                                    g.bits[ts][2]);
+            rb = cell_start[key];
+            len = cell_start[key + 1] - rb;
+          }
+          int inc = len;
+#pragma unroll
+          for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += v;
+          }
+          s_rb[w][lane] = rb;
+          s_pref[w][lane + 1] = inc;
+          if (lane == 0) s_pref[w][0] = 0;
+          wave_fence();
+          const int C = __shfl(inc, 63, 64);
+          for (int cb = 0; cb < C; cb += 64) {
+            const int c = cb + lane;
+            const bool cv = c < C;
+            double4 q = make_double4(0.0, 0.0, 0.0, 0.0);
+            int32_t qj = 0;
+            if (cv) {
+              int k = 0;  // cell of candidate c: largest k with s_pref[k] <= c
+#pragma unroll
+              for (int step = 32; step > 0; step >>= 1)
+                if (k + step < 64 && s_pref[w][k + step] <= c) k += step;
+              const int32_t t = s_rb[w][k] + (c - s_pref[w][k]);
+              q = sp[t];
+              if (MODE == 1 || stage) qj = order[t];
+            }
+            // two rows per step: independent chains for the FP64 pipeline
+            for (int r = 0; r < nr; r += 2) {
+              const int r2 = min(r + 1, nr - 1);  // == r when r is the last row
+              const double4 pa = s_row[w][r], pb = s_row[w][r2];
+              const bool ha = cv && !((ghosts >> r) & 1) && in_support(pa, q);
+              const bool hb = r2 != r && cv && !((ghosts >> r2) & 1) && in_support(pb, q);
+              const uint64_t ma = __ballot(ha), mb = __ballot(hb);
+              if (MODE == 1 || stage) {
+                // each row's fill position and output offset, read from its lane (uniform)
+                const int run_a = __builtin_amdgcn_readlane(run, r), run_b = __builtin_amdgcn_readlane(run, r2);
+                const int64_t off_a = readlane64(myoff, r), off_b = readlane64(myoff, r2);
+                const int bef_a = __builtin_amdgcn_mbcnt_hi((uint32_t)(ma >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ma, 0));
+                const int bef_b = __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0));
+                const int pos_a = run_a + bef_a, pos_b = run_b + bef_b;
+                int32_t *out = MODE == 1 ? col : stage;
+                if (ha && pos_a < __builtin_amdgcn_readlane(mylen, r)) out[off_a + pos_a] = qj;
+                if (hb && pos_b < __builtin_amdgcn_readlane(mylen, r2)) out[off_b + pos_b] = qj;
+              }
+              if (lane == r) run += __popcll(ma);
+              if (r2 != r && lane == r2) run += __popcll(mb);
+            }
+          }
+          wave_fence();
+        }
+      }
+      if (MODE == 0) {
+        int bin = -1;
+        if (lane < nr) {
+          const int cc = ghost ? 1 : run;
+          cnt[myi] = cc;
+          int band = 0;
+          while (band < GF_NBAND - 1 && cc > kBandHi[band]) ++band;
+          bin = model[myi] * GF_NBAND + band;
+          max_local = max(max_local, cc);
+        }
+        // per-wave histogram, all lanes active: lane b counts bin b
+#pragma unroll
+        for (int b = 0; b < 2 * GF_NBAND; ++b) {
+          const int hb = __popcll(__ballot(bin == b));
+          if (lane == b) hist_local += hb;
+        }
+      }
+      wave_fence();
     }
   }
   if (MODE == 0) {
-    if (valid) cnt[i] = c;
-    int band = 0;
-    while (band < GF_NBAND - 1 && c > kBandHi[band]) ++band;
-    // one atomic per wave and bin: same-address atomics from every particle
-    // serialise in L2 and used to dominate this kernel
-    const int bin = valid ? m * GF_NBAND + band : -1;
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int b = 0; b < 2 * GF_NBAND; ++b) {
-      const unsigned long long mask = __ballot(bin == b);
-      if (lane == 0 && mask) atomicAdd(&hist[b], __popcll(mask));
-    }
-    int cm = valid ? c : 0;
+    if (lane < 2 * GF_NBAND && hist_local) atomicAdd(&hist[lane], hist_local);
+    int cm = max_local;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) cm = max(cm, __shfl_xor(cm, o, 64));
-    if (lane == 0) atomicMax(maxrow, cm);
+    if (lane == 0 && cm) atomicMax(maxrow, cm);
   }
 }
 
-// Sort each row ascending: one wave per row, bitonic network in LDS.
-__global__ void __launch_bounds__(64) k_row_sort(const int64_t *__restrict__ row_ptr, int32_t *__restrict__ col,
-                                                 int64_t n) {
-  __shared__ int32_t buf[kMaxRow];
-  const int64_t i = blockIdx.x;
-  if (i >= n) return;
-  const int64_t b = row_ptr[i];
-  const int len = (int)(row_ptr[i + 1] - b);
-  if (len <= 1) return;
-  int P = 1;
-  while (P < len) P <<= 1;
-  for (int t = threadIdx.x; t < P; t += 64) buf[t] = (t < len) ? col[b + t] : 0x7fffffff;
-  __syncthreads();
+// Sort each row ascending.  One wave per chunk of 64 rows (grid-stride over
+// chunks), the chunk's row offsets one per lane.  A row of up to 128 entries
+// is sorted in registers by a bitonic network of P = the next power of two
+// >= its length: lane l holds positions l and l + 64; exchanges at distance
+// 64 stay in the lane, shorter ones go through cross-lane shuffles.  The
+// next row's entries are loaded while the current one is sorted.  Rows with
+// more than 128 entries (LONG launches only) use a wave-private LDS buffer.
+constexpr int kSortBlock = 256;
+constexpr int kSortWaves = kSortBlock / 64;
+
+__device__ inline int32_t bitonic_pick(int32_t v, int32_t partner, int t, int j, int k) {
+  const bool up = (t & k) == 0;     // direction of this k-sequence
+  const bool lower = (t & j) == 0;  // t is the smaller position of its pair
+  return (lower == up) ? min(v, partner) : max(v, partner);
+}
+
+// the bitonic network for P (power of two, <= 128) elements, unrolled
+template <int P>
+__device__ inline void sort_net(int32_t &v0, int32_t &v1, int lane) {
+#pragma unroll
   for (int k = 2; k <= P; k <<= 1) {
+#pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int t = threadIdx.x; t < P; t += 64) {
-        int u = t ^ j;
-        if (u > t) {
-          int32_t a = buf[t], c = buf[u];
-          bool up = (t & k) == 0;
-          if ((a > c) == up) { buf[t] = c; buf[u] = a; }
-        }
+      if (j == 64) {
+        const int32_t lo = min(v0, v1), hi = max(v0, v1);
+        v0 = lo;
+        v1 = hi;
+      } else {
+        v0 = bitonic_pick(v0, __shfl_xor(v0, j, 64), lane, j, k);
+        if (P > 64) v1 = bitonic_pick(v1, __shfl_xor(v1, j, 64), lane + 64, j, k);
       }
-      __syncthreads();
     }
   }
-  for (int t = threadIdx.x; t < len; t += 64) col[b + t] = buf[t];
+}
+
+// STAGED: row i is read from stage[i * kStage ...] (the count pass's copy)
+// and written, sorted, to its CSR place; otherwise it is sorted in place.
+template <bool LONG, bool STAGED>
+__global__ void __launch_bounds__(kSortBlock) k_row_sort(const int64_t *__restrict__ row_ptr, int32_t *__restrict__ col,
+                                                         const int32_t *__restrict__ stage, int64_t n) {
+  extern __shared__ int32_t sort_buf[];  // LONG: kSortWaves x kMaxRow
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t nchunks = (n + 63) / 64;
+  for (int64_t ch = (int64_t)blockIdx.x * kSortWaves + w; ch < nchunks; ch += (int64_t)gridDim.x * kSortWaves) {
+    const int64_t i0 = ch * 64;
+    const int nr = (int)min((int64_t)64, n - i0);
+    int64_t rb = 0;
+    int rl = 0;
+    if (lane < nr) {
+      rb = row_ptr[i0 + lane];
+      rl = (int)(row_ptr[i0 + lane + 1] - rb);
+    }
+    auto src = [&](int r) -> const int32_t * {
+      return STAGED ? stage + (i0 + r) * (int64_t)kStage : col + readlane64(rb, r);
+    };
+    auto fetch = [&](int r, int32_t &a0, int32_t &a1) {
+      const int32_t *sr = src(r);
+      const int len = __builtin_amdgcn_readlane(rl, r);
+      a0 = (len <= 128 && lane < len) ? sr[lane] : 0x7fffffff;
+      a1 = (len <= 128 && lane + 64 < len) ? sr[lane + 64] : 0x7fffffff;
+    };
+    int32_t v0, v1;
+    fetch(0, v0, v1);
+    for (int r = 0; r < nr; ++r) {
+      const int64_t b = readlane64(rb, r);
+      const int len = __builtin_amdgcn_readlane(rl, r);
+      int32_t n0 = 0x7fffffff, n1 = 0x7fffffff;
+      if (r + 1 < nr) fetch(r + 1, n0, n1);
+      if (STAGED && len == 1) {
+        if (lane == 0) col[b] = v0;
+      } else if (len > 1 && len <= 128) {
+        if (len <= 8) sort_net<8>(v0, v1, lane);
+        else if (len <= 16) sort_net<16>(v0, v1, lane);
+        else if (len <= 32) sort_net<32>(v0, v1, lane);
+        else if (len <= 64) sort_net<64>(v0, v1, lane);
+        else sort_net<128>(v0, v1, lane);
+        if (lane < len) col[b + lane] = v0;
+        if (lane + 64 < len) col[b + lane + 64] = v1;
+      } else if (LONG && len > 128) {
+        int32_t *bw = sort_buf + w * kMaxRow;
+        const int32_t *sr = src(r);
+        int P = 1;
+        while (P < len) P <<= 1;
+        for (int t = lane; t < P; t += 64) bw[t] = (t < len) ? sr[t] : 0x7fffffff;
+        wave_fence();
+        for (int k = 2; k <= P; k <<= 1) {
+          for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = lane; t < P; t += 64) {
+              const int u = t ^ j;
+              if (u > t) {
+                const int32_t a = bw[t], c = bw[u];
+                if ((a > c) == ((t & k) == 0)) { bw[t] = c; bw[u] = a; }
+              }
+            }
+            wave_fence();
+          }
+        }
+        for (int t = lane; t < len; t += 64) col[b + t] = bw[t];
+        wave_fence();
+      }
+      v0 = n0;
+      v1 = n1;
+    }
+  }
 }
 
 // grouping: particles (in cell order) of group gsel, stable; the tiled
@@ -392,12 +677,6 @@ struct TileGroups {
 constexpr int kTileEntries = kTileRows * kTileBandRow;  // entries one tile can hold
 constexpr int kTileThreads = 512;
 
-// orders the LDS traffic of the lanes of one wave
-__device__ inline void wave_fence() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 __device__ inline int tile_group(const TileGroups &tg, int64_t t) {
   int q = 0;
@@ -422,9 +701,18 @@ __global__ void __launch_bounds__(kBlock) k_tile_entries(TileGroups tg, const in
   ent[t] = (int32_t)e;
 }
 
-// One block per tile: sort the tile's (index, entry) pairs, number the
-// distinct indices in ascending order, write slot[] for every entry and the
-// distinct indices to uniq[ent_off[t] ...]; cnt[t] = number of distinct.
+// One block per tile: collect the distinct indices of the tile's entries in
+// an LDS hash set, sort only those, give each its rank, then write slot[] =
+// rank of col[] for every entry and the sorted distinct indices to
+// uniq[ent_off[t] ...]; cnt[t] = number of distinct indices.  The result does
+// not depend on the order of the hash insertions.
+constexpr int kHashSize = 2 * kTileEntries;  // load factor <= 1/2: probes end
+static_assert((kHashSize & (kHashSize - 1)) == 0, "hash size must be a power of two");
+
+__device__ inline int hash_slot(int32_t j) {
+  return (int)(((uint32_t)j * 2654435761u) >> (32 - 13)) & (kHashSize - 1);
+}
+
 __global__ void __launch_bounds__(kTileThreads) k_tile_unique(TileGroups tg, const int64_t *__restrict__ row_ptr,
                                                               const int32_t *__restrict__ col,
                                                               const int32_t *__restrict__ grouped,
@@ -432,10 +720,13 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_unique(TileGroups tg, con
                                                               uint16_t *__restrict__ slot,
                                                               int32_t *__restrict__ uniq, int32_t *__restrict__ cnt,
                                                               int32_t *__restrict__ grp_max) {
-  __shared__ uint64_t key[kTileEntries];
+  static_assert(kHashSize == 1 << 13, "hash_slot takes 13 bits");
+  __shared__ int32_t hkey[kHashSize];
+  __shared__ uint16_t hrank[kHashSize];
+  __shared__ int32_t ulist[kTileEntries];
   __shared__ int64_t rbase[kTileRows];
   __shared__ int32_t rloc[kTileRows + 1];
-  __shared__ int32_t csum[kTileThreads];
+  __shared__ int32_t ucount;
   const int64_t t = blockIdx.x;
   const int q = tile_group(tg, t);
   const int64_t r0 = (t - tg.tile_start[q]) * kTileRows;
@@ -457,10 +748,10 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_unique(TileGroups tg, con
     if (tid < kTileRows) rloc[tid + 1] = inc;
     if (tid == 0) rloc[0] = 0;
   }
+  for (int h = tid; h < kHashSize; h += kTileThreads) hkey[h] = -1;
+  if (tid == 0) ucount = 0;
   __syncthreads();
-  const int E = rloc[R];
-  int P = 1;
-  while (P < E) P <<= 1;
+  const int E = rloc[R];  // <= kTileEntries: tiled rows hold at most kTileBandRow entries
   auto row_of = [&](int e) {  // row r with rloc[r] <= e < rloc[r+1]
     int lo = 0, hi = R - 1;
     while (lo < hi) {
@@ -469,26 +760,43 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_unique(TileGroups tg, con
     }
     return lo;
   };
-  for (int e = tid; e < P; e += kTileThreads) {
-    if (e < E) {
-      const int r = row_of(e);
-      const int32_t j = col[rbase[r] + (e - rloc[r])];
-      key[e] = ((uint64_t)(uint32_t)j << 12) | (uint64_t)e;
-    } else {
-      key[e] = ~0ull;
+  // the slot of j in the table (j is present)
+  auto find = [&](int32_t j) {
+    int h = hash_slot(j);
+    while (hkey[h] != j) h = (h + 1) & (kHashSize - 1);
+    return h;
+  };
+  // 1. distinct indices
+  for (int e = tid; e < E; e += kTileThreads) {
+    const int r = row_of(e);
+    const int32_t j = col[rbase[r] + (e - rloc[r])];
+    int h = hash_slot(j);
+    while (true) {
+      const int32_t prev = atomicCAS(&hkey[h], -1, j);
+      if (prev == -1) {
+        ulist[atomicAdd(&ucount, 1)] = j;
+        break;
+      }
+      if (prev == j) break;
+      h = (h + 1) & (kHashSize - 1);
     }
   }
   __syncthreads();
-  // Bitonic network.  Element e is handled by thread e mod kTileThreads, so a
-  // stage of distance j < 64 pairs lanes of one wave; a block barrier is
-  // only needed around stages of distance >= 64.
+  const int U = ucount;
+  int P = 1;
+  while (P < U) P <<= 1;
+  for (int s = U + tid; s < P; s += kTileThreads) ulist[s] = 0x7fffffff;
+  __syncthreads();
+  // 2. bitonic sort of the distinct indices.  Element s is handled by thread
+  // s mod kTileThreads, so a stage of distance < 64 pairs lanes of one wave;
+  // a block barrier is only needed around stages of distance >= 64.
   for (int k = 2; k <= P; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int e = tid; e < P; e += kTileThreads) {
-        const int u = e ^ j;
-        if (u > e) {
-          const uint64_t a = key[e], b = key[u];
-          if ((a > b) == ((e & k) == 0)) { key[e] = b; key[u] = a; }
+      for (int s = tid; s < P; s += kTileThreads) {
+        const int u = s ^ j;
+        if (u > s) {
+          const int32_t a = ulist[s], b = ulist[u];
+          if ((a > b) == ((s & k) == 0)) { ulist[s] = b; ulist[u] = a; }
         }
       }
       const int jn = (j > 1) ? (j >> 1) : k;  // distance of the next stage
@@ -497,46 +805,23 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_unique(TileGroups tg, con
     }
   }
   __syncthreads();
-  // each thread numbers a contiguous chunk of the sorted list
-  const int chunk = (P + kTileThreads - 1) / kTileThreads;
-  const int s0 = tid * chunk;
-  int c = 0;
-  for (int s = s0; s < min(s0 + chunk, E); ++s)
-    c += (s == 0 || (key[s] >> 12) != (key[s - 1] >> 12)) ? 1 : 0;
-  csum[tid] = c;
-  __syncthreads();
-  if (tid < 64) {  // exclusive scan of the chunk counts by one wave
-    constexpr int kPer = kTileThreads / 64;
-    int v[kPer], tot = 0;
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) { v[u] = csum[tid * kPer + u]; tot += v[u]; }
-    int inc = tot;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int w = __shfl_up(inc, o, 64);
-      if (tid >= o) inc += w;
-    }
-    int run = inc - tot;
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) { csum[tid * kPer + u] = run; run += v[u]; }
-    if (tid == 63) {
-      cnt[t] = inc;
-      atomicMax(&grp_max[q], inc);
-    }
+  // 3. ranks
+  const int64_t ubase = ent_off[t];
+  for (int s = tid; s < U; s += kTileThreads) {
+    const int32_t j = ulist[s];
+    hrank[find(j)] = (uint16_t)s;
+    uniq[ubase + s] = j;
+  }
+  if (tid == 0) {
+    cnt[t] = U;
+    atomicMax(&grp_max[q], U);
   }
   __syncthreads();
-  int uid = csum[tid] - 1;
-  const int64_t ubase = ent_off[t];
-  for (int s = s0; s < min(s0 + chunk, E); ++s) {
-    const uint64_t kv = key[s];
-    const int32_t j = (int32_t)(kv >> 12);
-    if (s == 0 || j != (int32_t)(key[s - 1] >> 12)) {
-      ++uid;
-      uniq[ubase + uid] = j;
-    }
-    const int e = (int)(kv & 0xfff);
+  // 4. slots
+  for (int e = tid; e < E; e += kTileThreads) {
     const int r = row_of(e);
-    slot[rbase[r] + (e - rloc[r])] = (uint16_t)uid;
+    const int64_t k = rbase[r] + (e - rloc[r]);
+    slot[k] = hrank[find(col[k])];
   }
 }
 
@@ -663,15 +948,18 @@ gf_status build_tiles(gf_ctx *ctx, gf_nbr *nb) {
   int32_t *uniq = ar.take<int32_t>(std::max<int64_t>(nb->nnz, 1));
   int32_t *cnt = ar.take<int32_t>(nt);
   int32_t *grp_max = ar.take<int32_t>(16);
-  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, sm, grp_max, (int64_t)16, 0);
-  hipLaunchKernelGGL(k_tile_entries, dim3(grid_for(nt, kBlock)), dim3(kBlock), 0, sm, tg, nb->row_ptr, nb->grouped,
-                     ent);
-  GF_LAUNCH_CHECK(ctx);
-  if ((st = scan_i32_to_i64(ctx, ent, ent_off, nt, tmp64))) return st;
-  hipLaunchKernelGGL(k_tile_unique, dim3((unsigned)nt), dim3(kTileThreads), 0, sm, tg, nb->row_ptr, nb->col,
-                     nb->grouped, ent_off, nb->slot, uniq, cnt, grp_max);
-  GF_LAUNCH_CHECK(ctx);
-  if ((st = scan_i32_to_i64(ctx, cnt, nb->tile_off, nt, tmp64))) return st;
+  {
+    ProfScope prof(ctx, "nbr_tile_unique");
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, sm, grp_max, (int64_t)16, 0);
+    hipLaunchKernelGGL(k_tile_entries, dim3(grid_for(nt, kBlock)), dim3(kBlock), 0, sm, tg, nb->row_ptr, nb->grouped,
+                       ent);
+    GF_LAUNCH_CHECK(ctx);
+    if ((st = scan_i32_to_i64(ctx, ent, ent_off, nt, tmp64))) return st;
+    hipLaunchKernelGGL(k_tile_unique, dim3((unsigned)nt), dim3(kTileThreads), 0, sm, tg, nb->row_ptr, nb->col,
+                       nb->grouped, ent_off, nb->slot, uniq, cnt, grp_max);
+    GF_LAUNCH_CHECK(ctx);
+    if ((st = scan_i32_to_i64(ctx, cnt, nb->tile_off, nt, tmp64))) return st;
+  }
   if ((st = ensure_host(ctx, 4096))) return st;
   char *hp = (char *)ctx->host_pinned;
   GF_HIP(ctx, hipMemcpyAsync(hp, grp_max, sizeof(int32_t) * 16, hipMemcpyDeviceToHost, sm));
@@ -681,6 +969,7 @@ gf_status build_tiles(gf_ctx *ctx, gf_nbr *nb) {
   const int64_t total = *(int64_t *)(hp + 128);
   if (hipMalloc(&nb->tile_u, sizeof(int32_t) * std::max<int64_t>(total, 1)) != hipSuccess)
     return set_error(ctx, GF_ENOMEM, "neighbour tile list allocation failed");
+  ProfScope prof(ctx, "nbr_tile_compact");
   hipLaunchKernelGGL(k_tile_compact, dim3((unsigned)nt), dim3(kTileThreads), 0, sm, ent_off, nb->tile_off, uniq,
                      nb->tile_u);
   GF_LAUNCH_CHECK(ctx);
@@ -718,7 +1007,8 @@ extern "C" gf_status gf_build_neighbours_rows(gf_ctx *ctx, const gf_particles *p
   int *bad = ar.take<int>(16);
   hipLaunchKernelGGL(k_bbox, dim3(nblk), dim3(kBlock), 0, sm, p->x, p->y, p->z, p->h, p->model, n, part, bad_part);
   GF_LAUNCH_CHECK(ctx);
-  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, sm, part, bad_part, nblk, box, bad);
+  static_assert(kBboxFin >= 1024, "one final thread per bounding-box block");
+  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(kBboxFin), 0, sm, part, bad_part, nblk, box, bad);
   GF_LAUNCH_CHECK(ctx);
   if ((st = ensure_host(ctx, 4096))) return st;
   double *hbox = (double *)ctx->host_pinned;
@@ -731,55 +1021,63 @@ extern "C" gf_status gf_build_neighbours_rows(gf_ctx *ctx, const gf_particles *p
   double bx[kBoxVals];
   memcpy(bx, hbox, sizeof(bx));
 
-  // ---- grids (edge slightly above max h so that rounding of the cell
-  // coordinate never hides a neighbour two cells away)
+  // ---- grids: per model, levels with halving support caps (Grid); a grid's
+  // edge is slightly above its cap so that rounding of the cell coordinate
+  // never hides a neighbour
   Grid g;
   memset(&g, 0, sizeof(g));
-  g.per_model = cross_model ? 0 : 1;
-  double lo[2][3], hi[2][3], hmax[2];
+  double lo[2][3], hi[2][3], hmx[2], hmn[2];
   for (int m = 0; m < 2; ++m) {
-    for (int d = 0; d < 3; ++d) { lo[m][d] = bx[m * 7 + d]; hi[m][d] = bx[m * 7 + 3 + d]; }
-    hmax[m] = bx[m * 7 + 6];
+    for (int d = 0; d < 3; ++d) { lo[m][d] = bx[m * 8 + d]; hi[m][d] = bx[m * 8 + 3 + d]; }
+    hmx[m] = bx[m * 8 + 6];
+    hmn[m] = bx[m * 8 + 7];
   }
-  if (!g.per_model) {  // merge into slot 0
-    for (int d = 0; d < 3; ++d) {
-      lo[0][d] = std::min(lo[0][d], lo[1][d]);
-      hi[0][d] = std::max(hi[0][d], hi[1][d]);
-    }
-    hmax[0] = std::max(hmax[0], hmax[1]);
-  }
-  const int nslots = g.per_model ? 2 : 1;
-  const int64_t key_budget = std::max<int64_t>(8 * n, 1 << 16);
+  const int64_t key_budget = std::max<int64_t>(4 * n, 1 << 16);  // per grid
   int64_t base = 0;
-  for (int s = 0; s < nslots; ++s) {
-    bool empty = !(hmax[s] > 0.0);
-    double edge = empty ? 1.0 : hmax[s] * (1.0 + 1e-9);
-    for (int it = 0; it < 200; ++it) {
-      int tb = 0;
-      for (int d = 0; d < 3; ++d) {
-        double span = empty ? 0.0 : hi[s][d] - lo[s][d];
-        double dd = std::floor(span / edge) + 1.0;
-        if (dd > 1e6) dd = 1e6;
-        g.dim[s][d] = (int)dd;
-        g.bits[s][d] = ceil_log2(g.dim[s][d]);
-        tb += g.bits[s][d];
+  int ns = 0;
+  for (int m = 0; m < 2; ++m) {
+    g.slot0[m] = ns;
+    const bool empty = !(hmx[m] > 0.0);
+    int L = 1;
+    if (!empty)
+      while (L < kMaxLevels && hmn[m] <= std::ldexp(hmx[m], -L)) ++L;
+    for (int l = 0; l < L; ++l, ++ns) {
+      g.hcap[ns] = empty ? 0.0 : std::ldexp(hmx[m], -l);
+      double edge = empty ? 1.0 : g.hcap[ns] * (1.0 + 1e-9);
+      for (int it = 0; it < 200; ++it) {
+        int tb = 0;
+        for (int d = 0; d < 3; ++d) {
+          double span = empty ? 0.0 : hi[m][d] - lo[m][d];
+          double dd = std::floor(span / edge) + 1.0;
+          if (dd > 1e6) dd = 1e6;
+          g.dim[ns][d] = (int)dd;
+          g.bits[ns][d] = ceil_log2(g.dim[ns][d]);
+          tb += g.bits[ns][d];
+        }
+        if (tb <= 30 && ((int64_t)1 << tb) <= key_budget) break;
+        edge *= 1.5;
       }
-      if (tb <= 30 && ((int64_t)1 << tb) <= key_budget) break;
-      edge *= 1.5;
+      for (int d = 0; d < 3; ++d) g.lo[ns][d] = empty ? 0.0 : lo[m][d];
+      g.inv_edge[ns] = 1.0 / edge;
+      g.base[ns] = base;
+      base += (int64_t)1 << (g.bits[ns][0] + g.bits[ns][1] + g.bits[ns][2]);
     }
-    for (int d = 0; d < 3; ++d) g.lo[s][d] = empty ? 0.0 : lo[s][d];
-    g.inv_edge[s] = 1.0 / edge;
-    g.base[s] = base;
-    base += (int64_t)1 << (g.bits[s][0] + g.bits[s][1] + g.bits[s][2]);
   }
+  g.slot0[2] = ns;
+  g.nslots = ns;
   g.nkeys = base;
   if (g.nkeys >= (int64_t)0x7fffffff) return set_error(ctx, GF_ECAPACITY, "cell grid too large");
 
   // ---- sort particles into cells
   const int64_t K = g.nkeys;
   sz = {sizeof(int32_t) * n, sizeof(int32_t) * n, sizeof(int32_t) * (K + 1), sizeof(int32_t) * scan_tmp_elems(K + 1),
-        sizeof(double4) * n, sizeof(int32_t) * n, sizeof(int64_t) * scan_tmp_elems(n + 1), sizeof(int32_t) * 16,
-        sizeof(int32_t) * n, sizeof(int32_t) * (n + 1), sizeof(int32_t) * scan_tmp_elems(n + 1)};
+        sizeof(double4) * n, sizeof(int32_t) * n, sizeof(int64_t) * scan_tmp_elems(n + 1), sizeof(int32_t) * 32,
+        sizeof(int32_t) * n, sizeof(int32_t) * (n + 1), sizeof(int32_t) * scan_tmp_elems(n + 1),
+        sizeof(int32_t) * n};
+  // rows staged by the count pass (kStage entries each) while that stays
+  // under 8 GB; rows found longer fall back to a fill pass
+  const bool use_stage = (double)n * kStage * sizeof(int32_t) <= 8e9;
+  if (use_stage) sz.push_back(sizeof(int32_t) * (size_t)n * kStage);
   if ((st = ensure_scratch(ctx, arena_bytes(sz), &ar))) return st;
   int32_t *key = ar.take<int32_t>(n);
   int32_t *slot = ar.take<int32_t>(n);
@@ -788,10 +1086,20 @@ extern "C" gf_status gf_build_neighbours_rows(gf_ctx *ctx, const gf_particles *p
   double4 *sp = ar.take<double4>(n);
   int32_t *cnt = ar.take<int32_t>(n);
   int64_t *tmp64 = ar.take<int64_t>(scan_tmp_elems(n + 1));
-  int32_t *small = ar.take<int32_t>(16);  // hist[8], maxrow
+  // hist[8], maxrow, -, queue counters of the two search passes [10], [11],
+  // particles per grid [16 .. 16 + kMaxSlots); zeroed before use
+  int32_t *small = ar.take<int32_t>(32);
+  int32_t *slot_count = small + 16;
   int32_t *gflag = ar.take<int32_t>(n);
   int32_t *gpos = ar.take<int32_t>(n + 1);
   int32_t *tmpg = ar.take<int32_t>(scan_tmp_elems(n + 1));
+  // list of non-empty cells (first sorted position of each); the cell heads
+  // and their scan borrow the grouping arrays, which are free until the fill
+  // pass has finished
+  int32_t *cells = ar.take<int32_t>(n);
+  int32_t *stage = use_stage ? ar.take<int32_t>((size_t)n * kStage) : nullptr;
+  int32_t *head = gflag, *cpos = gpos;
+  const int32_t *ncells = cpos + n;
 
   gf_nbr *nb = new gf_nbr();
   nb->device = ctx->device;
@@ -807,21 +1115,28 @@ extern "C" gf_status gf_build_neighbours_rows(gf_ctx *ctx, const gf_particles *p
   {
   ProfScope prof_cells(ctx, "nbr_cells");
   hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(K + 1, kBlock)), dim3(kBlock), 0, sm, cell_start, K + 1, 0);
-  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, sm, small, (int64_t)16, 0);
-  hipLaunchKernelGGL(k_keys, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, p->x, p->y, p->z, p->model, n, g, key,
-                     slot, cell_start);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, sm, small, (int64_t)32, 0);
+  hipLaunchKernelGGL(k_keys, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, p->x, p->y, p->z, p->h, p->model, n, g,
+                     key, slot, cell_start, slot_count);
   if (hipGetLastError() != hipSuccess) return fail(set_error(ctx, GF_EHIP, "key kernel launch failed"));
   if ((st = scan_i32_to_i32(ctx, cell_start, cell_start, K, tmp32))) return fail(st);
   hipLaunchKernelGGL(k_scatter, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, key, slot, cell_start, n, nb->order);
-  hipLaunchKernelGGL(k_cell_sort, dim3((unsigned)std::min<int64_t>(K, 65536)), dim3(64), 0, sm, cell_start, K, p->x,
-                     p->y, p->z, p->model, g, nb->order);
+  hipLaunchKernelGGL(k_cell_heads, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, nb->order, key, n, head);
+  if ((st = scan_i32_to_i32(ctx, head, cpos, n, tmpg))) return fail(st);
+  hipLaunchKernelGGL(k_cell_list, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, head, cpos, n, cells);
+  hipLaunchKernelGGL(k_cell_sort, dim3((unsigned)std::min<int64_t>(n, 16384)), dim3(64), 0, sm, cells, ncells, n,
+                     p->x, p->y, p->z, p->h, p->model, g, nb->order);
   hipLaunchKernelGGL(k_gather_pos, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, nb->order, p->x, p->y, p->z, p->h,
                      n, sp);
   }
+  // one wave per non-empty cell from a queue; as many waves as fit at once
+  const dim3 search_grid((unsigned)std::max<int64_t>(
+      1, std::min<int64_t>((n + kSearchWaves - 1) / kSearchWaves, (int64_t)ctx->num_cu * kSearchWavesPerSimd)));
   {
   ProfScope prof_count(ctx, "nbr_count");
-  hipLaunchKernelGGL(k_search<0>, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, nb->order, sp, p->model,
-                     cell_start, n, n_rows, g, cnt, small, small + 8, (const int64_t *)nullptr, (int32_t *)nullptr);
+  hipLaunchKernelGGL(k_search<0>, search_grid, dim3(kSearchBlock), 0, sm, nb->order, sp, p->model, cell_start, cells,
+                     ncells, slot_count, small + 10, n, n_rows, g, cross_model ? 1 : 0, cnt, small, small + 8,
+                     (const int64_t *)nullptr, (int32_t *)nullptr, stage);
   }
   if (hipGetLastError() != hipSuccess) return fail(set_error(ctx, GF_EHIP, "count kernel launch failed"));
   if ((st = scan_i32_to_i64(ctx, cnt, nb->row_ptr, n, tmp64))) return fail(st);
@@ -847,21 +1162,36 @@ extern "C" gf_status gf_build_neighbours_rows(gf_ctx *ctx, const gf_particles *p
   if (nb->nnz >= (int64_t)1 << 40) return fail(set_error(ctx, GF_ECAPACITY, "too many neighbour pairs"));
   if (hipMalloc(&nb->col, sizeof(int32_t) * std::max<int64_t>(nb->nnz, 1)) != hipSuccess)
     return fail(set_error(ctx, GF_ENOMEM, "neighbour list allocation (%lld entries) failed", (long long)nb->nnz));
-  {
-  ProfScope prof_fill(ctx, "nbr_fill");
-  hipLaunchKernelGGL(k_search<1>, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, nb->order, sp, p->model,
-                     cell_start, n, n_rows, g, (int32_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr, nb->row_ptr,
-                     nb->col);
+  const bool staged = use_stage && nb->max_row <= kStage;
+  if (!staged) {
+    ProfScope prof_fill(ctx, "nbr_fill");
+    hipLaunchKernelGGL(k_search<1>, search_grid, dim3(kSearchBlock), 0, sm, nb->order, sp, p->model, cell_start,
+                       cells, ncells, slot_count, small + 11, n, n_rows, g, cross_model ? 1 : 0, (int32_t *)nullptr,
+                       (int32_t *)nullptr, (int32_t *)nullptr, nb->row_ptr, nb->col, (int32_t *)nullptr);
   }
   {
-  ProfScope prof_sort(ctx, "nbr_row_sort");
-  hipLaunchKernelGGL(k_row_sort, dim3((unsigned)n), dim3(64), 0, sm, nb->row_ptr, nb->col, n);
+    // staged rows: sorted on their way into the CSR; else sorted in place
+    ProfScope prof_sort(ctx, "nbr_row_sort");
+    const int64_t nchunks = (n + 63) / 64;
+    const dim3 sgrid((unsigned)std::max<int64_t>(1, std::min<int64_t>((nchunks + kSortWaves - 1) / kSortWaves, 4096)));
+    const size_t lds = nb->max_row > 128 ? sizeof(int32_t) * kSortWaves * kMaxRow : 0;
+    if (staged && nb->max_row > 128)
+      hipLaunchKernelGGL((k_row_sort<true, true>), sgrid, dim3(kSortBlock), lds, sm, nb->row_ptr, nb->col, stage, n);
+    else if (staged)
+      hipLaunchKernelGGL((k_row_sort<false, true>), sgrid, dim3(kSortBlock), 0, sm, nb->row_ptr, nb->col, stage, n);
+    else if (nb->max_row > 128)
+      hipLaunchKernelGGL((k_row_sort<true, false>), sgrid, dim3(kSortBlock), lds, sm, nb->row_ptr, nb->col,
+                         (const int32_t *)nullptr, n);
+    else
+      hipLaunchKernelGGL((k_row_sort<false, false>), sgrid, dim3(kSortBlock), 0, sm, nb->row_ptr, nb->col,
+                         (const int32_t *)nullptr, n);
   }
   if (hipGetLastError() != hipSuccess) return fail(set_error(ctx, GF_EHIP, "fill/sort kernel launch failed"));
 
   // ---- groups by (model, band), Morton order kept inside each group
-  ProfScope prof_group(ctx, "nbr_group_tiles");
   int64_t off = 0;
+  {
+  ProfScope prof_group(ctx, "nbr_group");
   for (int gsel = 0; gsel < 2 * GF_NBAND; ++gsel) {
     nb->group_start[gsel] = off;
     if (hist[gsel] == 0) continue;
@@ -873,6 +1203,7 @@ extern "C" gf_status gf_build_neighbours_rows(gf_ctx *ctx, const gf_particles *p
     off += hist[gsel];
   }
   nb->group_start[2 * GF_NBAND] = off;
+  }
   if (hipGetLastError() != hipSuccess) return fail(set_error(ctx, GF_EHIP, "grouping kernels failed"));
   if (off != n) return fail(set_error(ctx, GF_EHIP, "internal error: grouping covers %lld of %lld", (long long)off,
                                       (long long)n));

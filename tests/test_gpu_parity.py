@@ -80,6 +80,28 @@ def test_neighbours_edge_cases(ctx, g):
     _nbr_equal(ctx, g, d2, cross=True)
 
 
+def test_neighbours_long_rows(ctx, g):
+    # rows of 129-256 entries (staged by the count pass, sorted in LDS), rows
+    # above 256 (fill pass, in-place sort), a few rows above 500 entries, and
+    # a row beyond the 2,048-entry limit
+    base = W.plain_cube(20)
+    s = 0.01
+    for hf in (3.6, 4.5):
+        d = dict(base)
+        d["h"] = np.full(base["x"].size, hf * s)
+        p, nb, rp, col = _nbr_equal(ctx, g, d)
+        print(f"[neighbours] h = {hf} s: longest row {np.diff(rp).max()}", flush=True)
+    d = dict(base)
+    d["h"] = np.full(base["x"].size, 3.0 * s)
+    d["h"][[2105, 4210, 4211]] = 7.0 * s   # interior particles of the 20^3 lattice
+    p, nb, rp, col = _nbr_equal(ctx, g, d)
+    assert np.diff(rp).max() > 500
+    d["h"][5] = 40.0 * s
+    with pytest.raises(g.GfdmError) as e:
+        g.build_neighbours(ctx, _dev(ctx, d))
+    assert e.value.status == g.GF_ECAPACITY
+
+
 def test_invalid_inputs_are_rejected(ctx, g):
     d = W.plain_cube(4)
     d["h"] = d["h"].copy(); d["h"][3] = 0.0
