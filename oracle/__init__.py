@@ -452,6 +452,45 @@ def poisson_split_solve(p, row_ptr, col, w, row_type, n_regular, rhs, p_ghost, z
     return spla.spsolve(Arr.tocsc(), b)
 
 
+def transition_3d_to_2d_cloud(p, row_ptr, col, flag, mass, rho, phi=None, film_height=None, diam=None,
+                              h_film=None):
+    """Sec. 5.1, Alg. 3 carried to the end: the particles mapped onto a
+    transitioning wall particle are deleted and the flagged particles become
+    film particles ("remove from the 3D structure, add to the 2D one").  The
+    data mapping of every field is the one of transition_3d_to_2d.  Returns a
+    dict describing the new cloud in the caller's order without the deleted
+    particles: positions and normals copied; h = h_film (or h) for
+    transitioned particles; model 1 and kind wall for transitioned particles;
+    mass, rho, phi lumped / averaged for them and copied otherwise; height =
+    H for transitioned particles, the given film height for film particles,
+    0 for bulk; diam likewise; src = original index."""
+    n = p["x"].shape[0]
+    ph = _phi2(phi, n)
+    fields = ph if ph.shape[0] else np.zeros((1, n))
+    trs = [transition_3d_to_2d(p, row_ptr, col, flag, mass, rho, f) for f in fields]
+    tr = trs[0]
+    keep = np.nonzero(tr["keep"] == 1)[0]
+    moved = np.asarray(flag)[keep] == 1
+    model = np.asarray(p["model"])[keep].astype(np.int8)
+    out = {k: np.asarray(p[k], dtype=np.float64)[keep].copy() for k in ("x", "y", "z", "nx", "ny", "nz")}
+    h = np.asarray(p["h"], dtype=np.float64)[keep].copy()
+    if h_film is not None:
+        h[moved] = np.asarray(h_film, dtype=np.float64)[keep][moved]
+    out["h"] = h
+    out["model"] = np.where(moved, 1, model).astype(np.int8)
+    out["kind"] = np.where(moved, 2, np.asarray(p["kind"])[keep]).astype(np.int8)
+    out["mass"] = tr["mass"][keep]
+    out["rho"] = tr["rho"][keep]
+    out["phi"] = (np.stack([t["phi"][keep] for t in trs]) if ph.shape[0] else np.zeros((0, keep.size)))
+    film = model == 1
+    hgt = np.where(film, 0.0 if film_height is None else np.asarray(film_height)[keep], 0.0)
+    dia = np.where(film, 0.0 if diam is None else np.asarray(diam)[keep], 0.0)
+    out["height"] = np.where(moved, tr["height"][keep], hgt)
+    out["diam"] = np.where(moved, tr["diam"][keep], dia)
+    out["src"] = keep.astype(np.int32)
+    return out
+
+
 def operator_error(w, w_ref, row_ptr):
     """Per row and stencil: |c - c_ref|_2 / |c_ref|_2 over the row's entries.
     Rows/stencils whose reference is identically zero are reported as the

@@ -309,3 +309,48 @@ def test_implicit_split_equals_pinned_ghost_rows():
     # and the ghost values matter: without them the solution changes
     x0 = oracle.poisson_split_solve(e, rp, col, w, rt, n, rhs, np.zeros_like(pg))
     assert np.abs(x0 - x_split).max() > 1e-6
+
+
+# --------------------------------------------------------------------------- Alg. 3, whole cloud
+def test_transition_cloud_hand_example():
+    # the hand example of Sec. 5.1 (walls A, B flagged; p, q -> A, r -> B; s kept)
+    X = np.array([[0, 0, 0], [1, 0, 0], [3, 0, 0], [0.2, 0, 0.3], [0.5, 0, 0.4], [0.9, 0, 0.3],
+                  [2.4, 0, 0.2]], float)
+    n = X.shape[0]
+    p = dict(x=X[:, 0], y=X[:, 1], z=X[:, 2], h=np.full(n, 3.2), model=np.zeros(n, np.int8),
+             kind=np.array([2, 2, 2, 0, 0, 0, 1], np.int8), nx=np.zeros(n), ny=np.zeros(n),
+             nz=np.array([1.0, 1.0, 1.0, 0, 0, 0, 0]))
+    rp, col = oracle.neighbours(p)
+    flag = np.array([1, 1, 0, 0, 0, 0, 0], np.uint8)
+    m = np.array([1.0, 2.0, 4.0, 8.0, 16.0, 32.0, 64.0])
+    rho = np.array([1000.0, 1000, 1000, 900, 1100, 1000, 1000])
+    phi = np.array([[1.0, 2, 3, 4, 5, 6, 7], [10.0, 20, 30, 40, 50, 60, 70]])
+    o = oracle.transition_3d_to_2d_cloud(p, rp, col, flag, m, rho, phi, h_film=np.full(n, 0.5))
+    assert o["src"].tolist() == [0, 1, 2, 6]          # p, q, r deleted
+    assert o["model"].tolist() == [1, 1, 0, 0]
+    assert o["kind"].tolist() == [2, 2, 2, 1]
+    assert o["h"].tolist() == [0.5, 0.5, 3.2, 3.2]
+    assert o["mass"].tolist() == [25.0, 34.0, 4.0, 64.0]
+    assert o["phi"][0].tolist() == [(1 + 4 + 5) / 3, (2 + 6) / 2, 3.0, 7.0]
+    assert o["phi"][1].tolist() == [(10 + 40 + 50) / 3, (20 + 60) / 2, 30.0, 70.0]
+    assert o["height"].tolist() == [0.4, 0.3, 0.0, 0.0]
+    assert o["x"].tolist() == [0.0, 1.0, 3.0, 2.4]
+
+
+def test_transition_cloud_conserves_mass_and_counts():
+    p = W.shallow_cylinder()
+    rp, col = oracle.neighbours(p)
+    lam, w3, eps = oracle.pca(p, rp, col)
+    flag = oracle.classify(p, rp, col, eps, w3, cross=oracle.neighbours(p, cross=True))
+    n = p["x"].shape[0]
+    o = oracle.transition_3d_to_2d_cloud(p, rp, col, flag, p["mass"], p["rho"],
+                                         np.stack([p["x"], p["z"]]))
+    assert abs(o["mass"].sum() - p["mass"].sum()) <= 1e-13 * p["mass"].sum()
+    moved = (flag == 1)
+    assert (o["model"] == 1).sum() == moved.sum() + (p["model"] == 1).sum()
+    # every deleted particle was an interior / free-surface bulk particle
+    gone = np.setdiff1d(np.arange(n), o["src"])
+    assert gone.size > 0 and np.all(p["kind"][gone] != W.WALL) and np.all(p["model"][gone] == 0)
+    # a field that is the same everywhere stays the same after averaging
+    o2 = oracle.transition_3d_to_2d_cloud(p, rp, col, flag, p["mass"], p["rho"], np.full((1, n), 7.25))
+    assert np.all(o2["phi"] == 7.25)
