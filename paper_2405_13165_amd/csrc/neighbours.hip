@@ -257,6 +257,41 @@ __device__ inline uint64_t fine_key(double x, double y, double z, const Grid &g,
 
 // cells[c]: first sorted position of the c-th non-empty cell; *ncells and
 // the end n close the list
+// Cells of up to kCellSortReg particles, one wave per cell, in registers.
+// Inside a cell the fine keys differ only in their kSubBits low bits per axis
+// (the interleaved low 3 * kSubBits bits), so (those bits, particle index)
+// packed in 64 bits orders the cell exactly as the full comparison does.
+constexpr int kCellSortReg = 64;
+constexpr int kCellSortWaves = 4;
+__global__ void __launch_bounds__(64 * kCellSortWaves) k_cell_sort_reg(
+    const int32_t *__restrict__ cells, const int32_t *__restrict__ ncells, int64_t n, const double *__restrict__ x,
+    const double *__restrict__ y, const double *__restrict__ z, const double *__restrict__ h,
+    const int8_t *__restrict__ model, Grid g, int32_t *__restrict__ order) {
+  const int lane = threadIdx.x & 63;
+  const int32_t nc = *ncells;
+  const int64_t stride = (int64_t)gridDim.x * kCellSortWaves;
+  for (int64_t c = (int64_t)blockIdx.x * kCellSortWaves + (threadIdx.x >> 6); c < nc; c += stride) {
+    const int32_t b = cells[c], len = (c + 1 < nc ? cells[c + 1] : (int32_t)n) - b;
+    if (len <= 1 || len > kCellSortReg) continue;
+    uint64_t v = ~0ull;
+    if (lane < len) {
+      const int32_t i = order[b + lane];
+      const uint64_t sub = fine_key(x[i], y[i], z[i], g, slot_of(g, model[i], h[i])) & ((1ull << (3 * kSubBits)) - 1);
+      v = (sub << 32) | (uint32_t)i;
+    }
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        const uint64_t p = __shfl_xor(v, j, 64);
+        const bool up = (lane & k) == 0, lower = (lane & j) == 0;
+        v = (lower == up) ? (v < p ? v : p) : (v < p ? p : v);
+      }
+    }
+    if (lane < len) order[b + lane] = (int32_t)(uint32_t)v;
+  }
+}
+
 __global__ void __launch_bounds__(64) k_cell_sort(const int32_t *__restrict__ cells, const int32_t *__restrict__ ncells,
                                                   int64_t n, const double *__restrict__ x,
                                                   const double *__restrict__ y, const double *__restrict__ z,
@@ -267,7 +302,7 @@ __global__ void __launch_bounds__(64) k_cell_sort(const int32_t *__restrict__ ce
   const int32_t nc = *ncells;
   for (int64_t c = blockIdx.x; c < nc; c += gridDim.x) {
     const int32_t b = cells[c], len = (c + 1 < nc ? cells[c + 1] : (int32_t)n) - b;
-    if (len <= 1 || len > kCellSort) continue;
+    if (len <= kCellSortReg || len > kCellSort) continue;  // small cells: k_cell_sort_reg
     int P = 1;
     while (P < len) P <<= 1;
     for (int t = threadIdx.x; t < P; t += 64) {
@@ -702,10 +737,10 @@ __global__ void __launch_bounds__(kBlock) k_tile_entries(TileGroups tg, const in
 }
 
 // One block per tile: collect the distinct indices of the tile's entries in
-// an LDS hash set, sort only those, give each its rank, then write slot[] =
-// rank of col[] for every entry and the sorted distinct indices to
-// uniq[ent_off[t] ...]; cnt[t] = number of distinct indices.  The result does
-// not depend on the order of the hash insertions.
+// an LDS hash set, sort only those, write them to uniq[ent_off[t] ...], then
+// slot[] = rank of col[] in the sorted list (binary search) for every entry;
+// cnt[t] = number of distinct indices.  The result does not depend on the
+// order of the hash insertions.
 constexpr int kHashSize = 2 * kTileEntries;  // load factor <= 1/2: probes end
 static_assert((kHashSize & (kHashSize - 1)) == 0, "hash size must be a power of two");
 
@@ -722,7 +757,6 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_unique(TileGroups tg, con
                                                               int32_t *__restrict__ grp_max) {
   static_assert(kHashSize == 1 << 13, "hash_slot takes 13 bits");
   __shared__ int32_t hkey[kHashSize];
-  __shared__ uint16_t hrank[kHashSize];
   __shared__ int32_t ulist[kTileEntries];
   __shared__ int64_t rbase[kTileRows];
   __shared__ int32_t rloc[kTileRows + 1];
@@ -759,12 +793,6 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_unique(TileGroups tg, con
       if (rloc[mid] <= e) lo = mid; else hi = mid - 1;
     }
     return lo;
-  };
-  // the slot of j in the table (j is present)
-  auto find = [&](int32_t j) {
-    int h = hash_slot(j);
-    while (hkey[h] != j) h = (h + 1) & (kHashSize - 1);
-    return h;
   };
   // 1. distinct indices
   for (int e = tid; e < E; e += kTileThreads) {
@@ -805,23 +833,25 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_unique(TileGroups tg, con
     }
   }
   __syncthreads();
-  // 3. ranks
+  // 3. the sorted distinct indices
   const int64_t ubase = ent_off[t];
-  for (int s = tid; s < U; s += kTileThreads) {
-    const int32_t j = ulist[s];
-    hrank[find(j)] = (uint16_t)s;
-    uniq[ubase + s] = j;
-  }
+  for (int s = tid; s < U; s += kTileThreads) uniq[ubase + s] = ulist[s];
   if (tid == 0) {
     cnt[t] = U;
     atomicMax(&grp_max[q], U);
   }
-  __syncthreads();
-  // 4. slots
+  // 4. slots: rank of each entry in the sorted list (present, so the lower
+  // bound is an exact match)
   for (int e = tid; e < E; e += kTileThreads) {
     const int r = row_of(e);
     const int64_t k = rbase[r] + (e - rloc[r]);
-    slot[k] = hrank[find(col[k])];
+    const int32_t j = col[k];
+    int lo = 0, hi = U - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (ulist[mid] < j) lo = mid + 1; else hi = mid;
+    }
+    slot[k] = (uint16_t)lo;
   }
 }
 
@@ -1124,7 +1154,10 @@ extern "C" gf_status gf_build_neighbours_rows(gf_ctx *ctx, const gf_particles *p
   hipLaunchKernelGGL(k_cell_heads, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, nb->order, key, n, head);
   if ((st = scan_i32_to_i32(ctx, head, cpos, n, tmpg))) return fail(st);
   hipLaunchKernelGGL(k_cell_list, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, head, cpos, n, cells);
-  hipLaunchKernelGGL(k_cell_sort, dim3((unsigned)std::min<int64_t>(n, 16384)), dim3(64), 0, sm, cells, ncells, n,
+  hipLaunchKernelGGL(k_cell_sort_reg, dim3((unsigned)std::min<int64_t>((n + kCellSortWaves - 1) / kCellSortWaves, 4096)),
+                     dim3(64 * kCellSortWaves), 0, sm, cells, ncells, n, p->x, p->y, p->z, p->h, p->model, g,
+                     nb->order);
+  hipLaunchKernelGGL(k_cell_sort, dim3((unsigned)std::min<int64_t>(n, 2048)), dim3(64), 0, sm, cells, ncells, n,
                      p->x, p->y, p->z, p->h, p->model, g, nb->order);
   hipLaunchKernelGGL(k_gather_pos, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, nb->order, p->x, p->y, p->z, p->h,
                      n, sp);
