@@ -385,6 +385,25 @@ gf_status gf_buffer_zone(gf_ctx *ctx, const gf_particles *p, const gf_nbr *same,
                          double r_max, const double *mass, const double *rho, const double *phi,
                          int nphi, gf_new_particles *out, int64_t *count, uint8_t *flag_out);
 
+/* The 3D -> 2D transition applied to the cloud (Sec. 5.1, Alg. 3, including
+ * its last loop: the transitioning particles leave the 3D model and join the
+ * 2D one).  Deletion sets and data mapping as in gf_transition_3d_to_2d, for
+ * density and every one of the nphi fields (phi [nphi][n]).  out receives the
+ * new cloud: the particles of p in their order, without the deleted ones;
+ * positions and normals copied; flagged particles (flag[i] == 1) become film
+ * particles (model 1, kind wall) with h = h_film[i] (the film resolution at
+ * their place; h_i if h_film is NULL), lumped mass, averaged density and
+ * fields, height = max |(x_b - x_i) . n_i| and diam = (6 m/(pi rho))^(1/3);
+ * all others keep h, model, kind, mass, density and fields, and film
+ * particles their film_height and diam (either may be NULL: 0; bulk: 0).
+ * src = index in p.  nbr: same-model neighbourhoods.  *count, capacity and
+ * errors as in gf_transition_2d_to_3d.  Synchronises. */
+gf_status gf_transition_3d_to_2d_cloud(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr,
+                                       const uint8_t *flag, const double *mass, const double *rho,
+                                       const double *phi, int nphi, const double *film_height,
+                                       const double *diam, const double *h_film,
+                                       gf_new_particles *out, int64_t *count);
+
 /* ---------------------------------------------------------- adjoints */
 /* Transpose of gf_apply_stencil with respect to u: ubar = C^T ybar, where
  * ybar [K][n] FP64 holds dL/dout; ubar [n] FP64 is overwritten.

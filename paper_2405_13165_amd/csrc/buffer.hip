@@ -69,16 +69,6 @@ __device__ inline bool layers(double H, double h3, double r_min, double r_max, i
   return true;
 }
 
-struct NewOut {
-  double *x, *y, *z, *h;
-  int8_t *model, *kind;
-  double *nx, *ny, *nz;
-  double *mass, *rho, *phi;
-  double *height, *diam;
-  int32_t *src;
-  int64_t cap;
-};
-
 struct Src {
   const double *x, *y, *z, *nx, *ny, *nz;
   const int8_t *model, *kind;
@@ -251,26 +241,6 @@ __global__ void __launch_bounds__(kBlock) k_write_ghosts(Src s, const int64_t *_
   if (o.src) o.src[t] = (int32_t)i;
 }
 
-NewOut new_out(const gf_new_particles *o) {
-  NewOut r;
-  r.x = o->x; r.y = o->y; r.z = o->z; r.h = o->h;
-  r.model = o->model; r.kind = o->kind;
-  r.nx = o->nx; r.ny = o->ny; r.nz = o->nz;
-  r.mass = o->mass; r.rho = o->rho; r.phi = o->phi;
-  r.height = o->height; r.diam = o->diam; r.src = o->src;
-  r.cap = o->cap;
-  return r;
-}
-
-gf_status check_out(gf_ctx *ctx, const gf_new_particles *o, int nphi, int64_t *count) {
-  if (!o || !count) return set_error(ctx, GF_EINVAL, "out and count are required");
-  if (o->cap < 0) return set_error(ctx, GF_EINVAL, "out->cap is negative");
-  if (o->cap > 0 && (!o->x || !o->y || !o->z || !o->h || !o->model || !o->kind || !o->nx || !o->ny || !o->nz ||
-                     !o->mass || !o->rho || (nphi > 0 && !o->phi)))
-    return set_error(ctx, GF_EINVAL, "out is missing a required array");
-  return GF_OK;
-}
-
 // counts -> offsets (device scan) -> total and error count read back
 gf_status offsets(gf_ctx *ctx, const int32_t *cnt, int64_t *off, int64_t n, int64_t *tmp, const int32_t *bad,
                   int64_t *total, int32_t *nbad) {
@@ -289,6 +259,15 @@ __global__ void __launch_bounds__(64) k_zero_bad(int32_t *bad) {
   if (threadIdx.x == 0) bad[0] = 0;
 }
 }  // namespace
+
+gf_status check_out(gf_ctx *ctx, const gf_new_particles *o, int nphi, int64_t *count) {
+  if (!o || !count) return set_error(ctx, GF_EINVAL, "out and count are required");
+  if (o->cap < 0) return set_error(ctx, GF_EINVAL, "out->cap is negative");
+  if (o->cap > 0 && (!o->x || !o->y || !o->z || !o->h || !o->model || !o->kind || !o->nx || !o->ny || !o->nz ||
+                     !o->mass || !o->rho || (nphi > 0 && !o->phi)))
+    return set_error(ctx, GF_EINVAL, "out is missing a required array");
+  return GF_OK;
+}
 
 extern "C" gf_status gf_film_height(gf_ctx *ctx, const gf_particles *p, const gf_nbr *same, const double *diam,
                                     double alpha, double *height_out) {

@@ -121,6 +121,31 @@ inline int launch_units(const gf_nbr *nb, LaunchUnit *out) {
   return k;
 }
 
+// ------------------------------------------------------------------ new particles
+// device view of a gf_new_particles output (entry points that create particles)
+struct NewOut {
+  double *x, *y, *z, *h;
+  int8_t *model, *kind;
+  double *nx, *ny, *nz;
+  double *mass, *rho, *phi;
+  double *height, *diam;
+  int32_t *src;
+  int64_t cap;
+};
+
+inline NewOut new_out(const gf_new_particles *o) {
+  NewOut r;
+  r.x = o->x; r.y = o->y; r.z = o->z; r.h = o->h;
+  r.model = o->model; r.kind = o->kind;
+  r.nx = o->nx; r.ny = o->ny; r.nz = o->nz;
+  r.mass = o->mass; r.rho = o->rho; r.phi = o->phi;
+  r.height = o->height; r.diam = o->diam; r.src = o->src;
+  r.cap = o->cap;
+  return r;
+}
+// argument check of a gf_new_particles output with nphi fields and its count
+gf_status check_out(gf_ctx *ctx, const gf_new_particles *o, int nphi, int64_t *count);
+
 // ------------------------------------------------------------------ errors
 gf_status set_error(gf_ctx *ctx, gf_status st, const char *fmt, ...);
 

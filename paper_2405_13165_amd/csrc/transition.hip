@@ -1,4 +1,7 @@
-// 3D -> 2D transition of flagged wall particles (Sec. 5.1, Alg. 3).
+// 3D -> 2D transition of flagged wall particles (Sec. 5.1, Alg. 3), as
+// per-particle outputs (gf_transition_3d_to_2d) or applied to the cloud
+// (gf_transition_3d_to_2d_cloud: deleted particles compacted away, the
+// transitioning ones turned into film particles, every field mapped).
 //
 // Two gather passes over the (symmetric) same-model neighbourhoods, no
 // atomics: (1) every interior / free-surface bulk particle b that has a
@@ -82,7 +85,135 @@ __global__ void __launch_bounds__(kBlock) k_lump(const double *__restrict__ x, c
   height_out[i] = H;
   diam_out[i] = cbrt(6.0 * m / (3.14159265358979323846 * rho_out[i]));
 }
+
+__global__ void __launch_bounds__(kBlock) k_keep32(const uint8_t *__restrict__ keep, int64_t n,
+                                                   int32_t *__restrict__ k32) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) k32[i] = keep[i];
+}
+
+struct CloudIn {
+  const double *x, *y, *z, *nx, *ny, *nz, *h;
+  const int8_t *model, *kind;
+  const double *mass, *rho, *phi;
+  int nphi;
+  const double *film_height, *diam, *h_film;
+  int64_t n;
+};
+
+// The new cloud: kept particles at pos[i]; flagged particles become film
+// particles with the data of the particles mapped onto them (ascending index
+// order, as in k_lump), the others are copied.
+__global__ void __launch_bounds__(kBlock) k_cloud_write(CloudIn c, const int64_t *__restrict__ row_ptr,
+                                                        const int32_t *__restrict__ col,
+                                                        const uint8_t *__restrict__ flag,
+                                                        const int32_t *__restrict__ owner,
+                                                        const uint8_t *__restrict__ keep,
+                                                        const int64_t *__restrict__ pos, NewOut o) {
+#pragma clang fp contract(off)
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= c.n || !keep[i]) return;
+  const int64_t t = pos[i];
+  o.x[t] = c.x[i];
+  o.y[t] = c.y[i];
+  o.z[t] = c.z[i];
+  o.nx[t] = c.nx[i];
+  o.ny[t] = c.ny[i];
+  o.nz[t] = c.nz[i];
+  if (o.src) o.src[t] = (int32_t)i;
+  if (flag[i] != 1) {
+    const bool film = c.model[i] == GF_MODEL_FILM;
+    o.h[t] = c.h[i];
+    o.model[t] = c.model[i];
+    o.kind[t] = c.kind[i];
+    o.mass[t] = c.mass[i];
+    o.rho[t] = c.rho[i];
+    for (int f = 0; f < c.nphi; ++f) o.phi[(int64_t)f * o.cap + t] = c.phi[(int64_t)f * c.n + i];
+    if (o.height) o.height[t] = (film && c.film_height) ? c.film_height[i] : 0.0;
+    if (o.diam) o.diam[t] = (film && c.diam) ? c.diam[i] : 0.0;
+    return;
+  }
+  double m = c.mass[i], r = c.rho[i], H = 0.0;
+  int64_t cnt = 0;
+  const double xi = c.x[i], yi = c.y[i], zi = c.z[i], a = c.nx[i], bb = c.ny[i], cc = c.nz[i];
+  const int64_t k0 = row_ptr[i], k1 = row_ptr[i + 1];
+  for (int64_t k = k0; k < k1; ++k) {
+    const int32_t b = col[k];
+    if (owner[b] != (int32_t)i) continue;
+    m += c.mass[b];
+    r += c.rho[b];
+    const double dn = fabs((c.x[b] - xi) * a + (c.y[b] - yi) * bb + (c.z[b] - zi) * cc);
+    H = fmax(H, dn);
+    ++cnt;
+  }
+  const double rho_new = r / (double)(1 + cnt);
+  for (int f = 0; f < c.nphi; ++f) {
+    const double *ph = c.phi + (int64_t)f * c.n;
+    double acc = ph[i];
+    for (int64_t k = k0; k < k1; ++k) {
+      const int32_t b = col[k];
+      if (owner[b] == (int32_t)i) acc += ph[b];
+    }
+    o.phi[(int64_t)f * o.cap + t] = acc / (double)(1 + cnt);
+  }
+  o.h[t] = c.h_film ? c.h_film[i] : c.h[i];
+  o.model[t] = GF_MODEL_FILM;
+  o.kind[t] = GF_KIND_WALL;
+  o.mass[t] = m;
+  o.rho[t] = rho_new;
+  if (o.height) o.height[t] = H;
+  if (o.diam) o.diam[t] = cbrt(6.0 * m / (3.14159265358979323846 * rho_new));
+}
 }  // namespace
+
+extern "C" gf_status gf_transition_3d_to_2d_cloud(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr,
+                                                  const uint8_t *flag, const double *mass, const double *rho,
+                                                  const double *phi, int nphi, const double *film_height,
+                                                  const double *diam, const double *h_film,
+                                                  gf_new_particles *out, int64_t *count) {
+  if (!ctx) return GF_EINVAL;
+  gf_status st = check_particles(ctx, p, true, true);
+  if (st) return st;
+  if ((st = check_nbr(ctx, nbr, p->n))) return st;
+  if (nbr->cross) return set_error(ctx, GF_EINVAL, "the transition uses same-model neighbourhoods");
+  if (!flag || !mass || !rho) return set_error(ctx, GF_EINVAL, "flag, mass and rho are required");
+  if (nphi < 0 || (nphi > 0 && !phi)) return set_error(ctx, GF_EINVAL, "nphi < 0 or phi missing");
+  if ((st = check_out(ctx, out, nphi, count))) return st;
+  *count = 0;
+  const int64_t n = p->n;
+  Arena ar;
+  std::vector<size_t> sz = {sizeof(uint8_t) * n, sizeof(int32_t) * n, sizeof(int32_t) * n, sizeof(int64_t) * (n + 1),
+                            sizeof(int64_t) * scan_tmp_elems(n + 1)};
+  if ((st = ensure_scratch(ctx, arena_bytes(sz), &ar))) return st;
+  uint8_t *keep = ar.take<uint8_t>(n);
+  int32_t *owner = ar.take<int32_t>(n);
+  int32_t *k32 = ar.take<int32_t>(n);
+  int64_t *pos = ar.take<int64_t>(n + 1);
+  int64_t *tmp = ar.take<int64_t>(scan_tmp_elems(n + 1));
+  const dim3 grid(grid_for(n, kBlock)), block(kBlock);
+  {
+    ProfScope prof(ctx, "transition_cloud_owner");
+    hipLaunchKernelGGL(k_owner, grid, block, 0, ctx->stream, p->x, p->y, p->z, p->model, p->kind, nbr->row_ptr,
+                       nbr->col, flag, n, keep, owner);
+    hipLaunchKernelGGL(k_keep32, grid, block, 0, ctx->stream, keep, n, k32);
+    GF_LAUNCH_CHECK(ctx);
+    if ((st = scan_i32_to_i64(ctx, k32, pos, n, tmp))) return st;
+  }
+  if ((st = ensure_host(ctx, 64))) return st;
+  GF_HIP(ctx, hipMemcpyAsync(ctx->host_pinned, pos + n, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+  GF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  const int64_t total = *(int64_t *)ctx->host_pinned;
+  *count = total;
+  if (total > out->cap)
+    return set_error(ctx, GF_ECAPACITY, "%lld particles remain, capacity %lld", (long long)total, (long long)out->cap);
+  CloudIn c{p->x, p->y, p->z, p->nx, p->ny, p->nz, p->h, p->model, p->kind, mass, rho, phi, nphi,
+            film_height, diam, h_film, n};
+  ProfScope prof(ctx, "transition_cloud_write");
+  hipLaunchKernelGGL(k_cloud_write, grid, block, 0, ctx->stream, c, nbr->row_ptr, nbr->col, flag, owner, keep, pos,
+                     new_out(out));
+  GF_LAUNCH_CHECK(ctx);
+  return GF_OK;
+}
 
 extern "C" gf_status gf_transition_3d_to_2d(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr, const uint8_t *flag,
                                             const double *mass, const double *rho, const double *phi,

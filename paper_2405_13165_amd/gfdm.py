@@ -79,6 +79,7 @@ EXPORTED = [
     "gf_poisson_solve", "gf_transition_3d_to_2d", "gf_apply_stencil_adjoint",
     "gf_gfdm_weights_adjoint", "gf_profile_enable", "gf_profile_read", "gf_autotune", "gf_set_tile_capacity",
     "gf_build_neighbours_rows", "gf_film_height", "gf_transition_2d_to_3d", "gf_buffer_flags", "gf_buffer_zone",
+    "gf_transition_3d_to_2d_cloud",
 ]
 
 _lib = None
@@ -134,6 +135,7 @@ def load_library(path: str = LIB_PATH):
     L.gf_transition_2d_to_3d.argtypes = [P, PP, P, P, P, D, D, P, P, P, I32, NP, ctypes.POINTER(I64)]
     L.gf_buffer_flags.argtypes = [P, PP, P, P, P]
     L.gf_buffer_zone.argtypes = [P, PP, P, P, P, P, D, D, P, P, P, I32, NP, ctypes.POINTER(I64), P]
+    L.gf_transition_3d_to_2d_cloud.argtypes = [P, PP, P, P, P, P, P, I32, P, P, P, NP, ctypes.POINTER(I64)]
     for name in EXPORTED:
         getattr(L, name)  # every declared entry point must resolve
     _lib = L
@@ -511,6 +513,23 @@ def buffer_zone(ctx, p, same, cross, film_h, h_other, mass, rho, phi=None, r_min
         ctx.handle, ctypes.byref(p.s), same.handle, cross.handle, _ptr(H), _ptr(ho), float(r_min), float(r_max),
         _ptr(m), _ptr(r), _ptr(ph), nphi, st, cnt, _ptr(flag)), nphi, "_cap_ghosts")
     return flag, g
+
+
+def transition_3d_to_2d_cloud(ctx, p, nbr, flag, mass, rho, phi=None, film_height=None, diam=None, h_film=None):
+    """gf_transition_3d_to_2d_cloud: dict of the new cloud (deleted particles
+    left out, flagged ones turned into film particles, fields mapped)."""
+    dev = ctx.device
+    fl = _dev_tensor(flag, torch.uint8, dev)
+    m = _dev_tensor(mass, torch.float64, dev)
+    r = _dev_tensor(rho, torch.float64, dev)
+    fh = _dev_tensor(film_height, torch.float64, dev)
+    dm = _dev_tensor(diam, torch.float64, dev)
+    hf = _dev_tensor(h_film, torch.float64, dev)
+    ph, nphi = _phi_rows(phi, p.n, dev)
+    ctx._cap_cloud = max(getattr(ctx, "_cap_cloud", 0), p.n)   # never more particles than before
+    return _grow_call(ctx, lambda st, cnt: ctx.lib.gf_transition_3d_to_2d_cloud(
+        ctx.handle, ctypes.byref(p.s), nbr.handle, _ptr(fl), _ptr(m), _ptr(r), _ptr(ph), nphi, _ptr(fh), _ptr(dm),
+        _ptr(hf), st, cnt), nphi, "_cap_cloud")
 
 
 def extend_particles(ctx, p, ghosts):

@@ -260,3 +260,31 @@ def test_implicit_split_with_ghost_rows(ctx, g):
     print(f"[split] its {st['inner_its_total']}, oracle residual {rel:.2e}, solution difference {dx:.2e}")
     assert rel <= 1e-7
     assert dx <= 1e-4
+
+
+# --------------------------------------------------------------------------- Alg. 3 on the cloud
+@pytest.mark.parametrize("case", ["mixed2_walls", "cylinder_pca"])
+def test_transition_cloud_matches_oracle(ctx, g, case):
+    if case == "cylinder_pca":
+        d = W.shallow_cylinder()
+        rp, col = oracle.neighbours(d)
+        lam, w3, eps = oracle.pca(d, rp, col)
+        flag = oracle.classify(d, rp, col, eps, w3, cross=oracle.neighbours(d, cross=True))
+    else:
+        # every bulk wall flagged: the layers above the bottom are deleted
+        d = W.mixed_block_film(factor=2)
+        rp, col = oracle.neighbours(d)
+        flag = ((d["model"] == 0) & (d["kind"] == W.WALL)).astype(np.uint8)
+    n = d["x"].size
+    rng = np.random.default_rng(n)
+    phi = rng.uniform(-1, 1, (3, n))
+    fh = d.get("film_height", np.zeros(n))
+    dm = d.get("diam", np.zeros(n))
+    hf = np.full(n, 0.004)
+    p = g.Particles.from_dict(ctx, d)
+    nb = g.build_neighbours(ctx, p)
+    o = g.transition_3d_to_2d_cloud(ctx, p, nb, flag, d["mass"], d["rho"], phi, fh, dm, hf)
+    o_o = oracle.transition_3d_to_2d_cloud(d, rp, col, flag, d["mass"], d["rho"], phi, fh, dm, hf)
+    print(f"[cloud] {case}: {n} -> {o_o['x'].size} particles, {int((flag == 1).sum())} to film", flush=True)
+    assert o_o["x"].size < n
+    _compare_new(o, o_o, case)
