@@ -156,6 +156,49 @@ def mixed_block_film(factor: int = 1, seed_extra: int = 0):
                  spacing_bulk=sb, spacing_film=sf, **_droplets(model, film_height, spacing))
 
 
+def advdiff_plate(h: float = 0.06, layers: int = 4, seed_extra: int = 0):
+    """Plate for the advection-diffusion analogue (Sec. 7.3): film particles
+    on [0,2]x[0,1.5] outside x in (0.75, 1.25) and a 3D block of `layers`
+    lattice layers on [0.75,1.25]x[0,1.5] (bottom layer wall, normal +z; top
+    layer free surface, normal -z, both pointing into the fluid), spacing
+    s = h/3, jitter U(+-0.2 s) in the plane, support h everywhere.  The film
+    thickness is the block's height, so the 2D->3D ghost columns match it.
+    T0 is a Gaussian of width 0.1 around (1.0, 0.75), constant in depth."""
+    rng = rng_for(7, seed_extra)
+    s = h / 3.0
+    nxf = int(round(2.0 / s)); nyf = int(round(1.5 / s))
+    jj, ii = np.meshgrid(np.arange(nyf), np.arange(nxf), indexing="ij")
+    xf = (ii.ravel() + 0.5) * s; yf = (jj.ravel() + 0.5) * s
+    keep = (xf < 0.75) | (xf > 1.25)
+    xf, yf = xf[keep], yf[keep]
+    xf = xf + rng.uniform(-0.2 * s, 0.2 * s, xf.size); yf = yf + rng.uniform(-0.2 * s, 0.2 * s, yf.size)
+    nbx = int(round(0.5 / s))
+    kk, jb, ib = np.meshgrid(np.arange(layers), np.arange(nyf), np.arange(nbx), indexing="ij")
+    xb = 0.75 + (ib.ravel() + 0.5) * s; yb = (jb.ravel() + 0.5) * s; zb = kk.ravel() * s
+    xb = xb + rng.uniform(-0.2 * s, 0.2 * s, xb.size); yb = yb + rng.uniform(-0.2 * s, 0.2 * s, yb.size)
+    kind_b = np.where(kk.ravel() == 0, WALL, np.where(kk.ravel() == layers - 1, FREE_SURFACE, INTERIOR))
+    nb, nf = xb.size, xf.size
+    x = np.concatenate([xb, xf]); y = np.concatenate([yb, yf]); z = np.concatenate([zb, np.zeros(nf)])
+    model = np.concatenate([np.zeros(nb, np.int8), np.ones(nf, np.int8)])
+    kind = np.concatenate([kind_b.astype(np.int8), np.full(nf, WALL, np.int8)])
+    nzv = np.concatenate([np.where(kind_b == WALL, 1.0, np.where(kind_b == FREE_SURFACE, -1.0, 0.0)), np.ones(nf)])
+    depth = (layers - 1) * s
+    film_height = np.concatenate([np.zeros(nb), np.full(nf, depth)])
+    hh = np.full(nb + nf, h)
+    T0 = np.exp(-((x - 1.0) ** 2 + (y - 0.75) ** 2) / (2 * 0.1 ** 2))
+    spacing = np.full(nb + nf, s)
+    return _pack(x, y, z, hh, model, kind, None, None, nzv, film_height=film_height, h3d=hh.copy(),
+                 h_other=hh.copy(), T0=T0, n_bulk=nb, n_film=nf, spacing=s, depth=depth,
+                 **_droplets(model, film_height, spacing))
+
+
+def advdiff_exact(x, y, t, kappa, sigma0=0.1, x0=1.0, y0=0.75):
+    """Heat equation in the plane from a Gaussian of width sigma0: the width
+    grows to sqrt(sigma0^2 + 2 kappa t) and the peak falls accordingly."""
+    s2 = sigma0 ** 2 + 2.0 * kappa * t
+    return sigma0 ** 2 / s2 * np.exp(-((x - x0) ** 2 + (y - y0) ** 2) / (2.0 * s2))
+
+
 def _truncated_normal(rng, n, clip=2.0):
     zeta = rng.standard_normal(n)
     bad = np.abs(zeta) > clip

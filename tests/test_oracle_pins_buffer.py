@@ -354,3 +354,33 @@ def test_transition_cloud_conserves_mass_and_counts():
     # a field that is the same everywhere stays the same after averaging
     o2 = oracle.transition_3d_to_2d_cloud(p, rp, col, flag, p["mass"], p["rho"], np.full((1, n), 7.25))
     assert np.all(o2["phi"] == 7.25)
+
+
+# --------------------------------------------------------------------------- Sec. 7.3 analogue
+def _advdiff_errors(h, kappa=5e-3, t_end=0.5, factor=0.25, ghost_scale=1.0):
+    d = W.advdiff_plate(h)
+    steps = int(np.ceil(t_end / (factor * 0.05 * h * h / kappa)))
+    T, _ = oracle.advdiff_run(d, h, kappa, t_end, steps, ghost_scale=ghost_scale)
+    ex = W.advdiff_exact(d["x"], d["y"], t_end, kappa)
+    e2 = np.sqrt(((T - ex) ** 2).sum() / (ex ** 2).sum())
+    einf = np.abs(T - ex).max() / ex.max()
+    return e2, einf
+
+
+def test_advdiff_converges_at_second_order():
+    # against the exact heat-kernel solution of the Gaussian (constant in
+    # depth), the coupled 2D / 3D / ghost discretisation converges at about
+    # second order, as the paper reports for its analogue (Table 2)
+    e_c = _advdiff_errors(0.12)
+    e_f = _advdiff_errors(0.06)
+    order2 = np.log2(e_c[0] / e_f[0])
+    orderi = np.log2(e_c[1] / e_f[1])
+    assert e_f[0] < 1e-2 and order2 > 1.7 and orderi > 1.5, (e_c, e_f, order2, orderi)
+
+
+def test_advdiff_needs_the_ghost_data():
+    # without the ghost values the block and the film do not exchange heat:
+    # the error grows several-fold (about 5x at h = 0.06)
+    e_g = _advdiff_errors(0.06)
+    e_0 = _advdiff_errors(0.06, ghost_scale=0.0)
+    assert e_0[0] > 4 * e_g[0]
