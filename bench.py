@@ -46,6 +46,9 @@ def parse():
                     help="also time the fused step on the 2.0M-particle jet cloud (uneven neighbourhoods)")
     ap.add_argument("--diff", action="store_true",
                     help="also time forward + backward of the stencil operator on the 1e6-particle cube")
+    ap.add_argument("--advdiff", action="store_true",
+                    help="also run the diffusion analogue of the advection-diffusion test (Sec. 7.3) at "
+                         "h = 0.06, 0.03, 0.015 against its exact solution (convergence study)")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warm-up plus a few steps of the metric path and exit (for rocprofv3)")
     return ap.parse_args()
@@ -435,6 +438,29 @@ def main():
             print(f"[bench] poisson mixed={mixed}: {el:.3f}s {rec}", file=sys.stderr, flush=True)
         result["poisson"] = {"n": ps_n, "nnz": ps_nnz, **ps}
         del dp, pp, nbp, wp, val, A, b, x
+
+    if args.advdiff:
+        from paper_2405_13165_amd.advdiff import DiffusionPlate
+        kappa, t_end = 5e-3, 0.5
+        study = []
+        for hh in (0.06, 0.03, 0.015):
+            da = W.advdiff_plate(hh)
+            steps = int(np.ceil(t_end / (0.25 * 0.05 * hh * hh / kappa)))
+            plate = DiffusionPlate(ctx, da, W.advdiff_rows(da, hh), kappa, t_end / steps)
+            Ta, info = plate.run(steps)
+            Ta = Ta.cpu().numpy()
+            ex = W.advdiff_exact(da["x"], da["y"], t_end, kappa)
+            rec = {"h": hh, "n_3d": int(da["n_bulk"]), "n_2d": int(da["n_film"]), "ghosts": plate.n_ghosts,
+                   "steps": steps, "eps2": float(np.sqrt(((Ta - ex) ** 2).sum() / (ex ** 2).sum())),
+                   "epsinf": float(np.abs(Ta - ex).max() / ex.max()), "seconds": round(info["seconds"], 3),
+                   "ms_per_step": round(1e3 * info["seconds"] / steps, 3), "bicgstab_its": info["bicgstab_its"]}
+            if study:
+                rec["order_eps2"] = round(float(np.log2(study[-1]["eps2"] / rec["eps2"])), 2)
+                rec["order_epsinf"] = round(float(np.log2(study[-1]["epsinf"] / rec["epsinf"])), 2)
+            study.append(rec)
+            print(f"[bench] advdiff {rec}", file=sys.stderr, flush=True)
+            del plate
+        result["advdiff"] = {"kappa": kappa, "t_end": t_end, "study": study}
 
     if args.jet:
         dj = W.jet_impact()

@@ -230,7 +230,7 @@ gf_status gf_gfdm_weights_apply(gf_ctx *ctx, const gf_particles *p, const gf_nbr
 
 /* ---------------------------------------------------------- pressure solve */
 enum { GF_ROW_INTERIOR = 0, GF_ROW_DIRICHLET = 1, GF_ROW_NEUMANN_COMBINED = 2,
-       GF_ROW_NEUMANN = 3 };
+       GF_ROW_NEUMANN = 3, GF_ROW_IMPLICIT = 4 };
 
 /* Pressure-system matrix values on the neighbour pattern (implicit pressure
  * Poisson step of the projection scheme, Sec. 2.3; PDE + zeta*BC rows of
@@ -250,6 +250,8 @@ typedef struct {
   int inner_maxit;    /* mixed: inner iteration limit per refinement, 2000 */
   double zeta;        /* combined Neumann rows, 0.3 (Sec. 7.2) */
   int check_every;    /* iterations between host convergence checks, 4 */
+  double implicit_a;  /* a of GF_ROW_IMPLICIT rows, A_ij = delta_ij - a c_ij^lap: one
+                         implicit Euler step of a diffusion equation (a = dt kappa), 0 */
 } gf_solve_params;
 void gf_solve_params_default(gf_solve_params *p);
 
@@ -271,7 +273,10 @@ typedef struct {
  * stats->final_rel_res the residual reached.
  * Ghost particles (Sec. 6.2): rows of type GF_ROW_DIRICHLET whose right-hand
  * side and initial guess hold the known ghost values keep those values, and
- * the regular rows then solve A_rr p_r = rhs_r - A_rg p_g. */
+ * the regular rows then solve A_rr p_r = rhs_r - A_rg p_g.
+ * Besides the row types of gf_poisson_assemble, rows of type GF_ROW_IMPLICIT
+ * (A_ij = delta_ij - a c_ij^lap, a = params->implicit_a) give implicit Euler
+ * steps of a diffusion equation (gf_poisson_assemble rejects them). */
 gf_status gf_poisson_solve(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr,
                            const double *w64, const int8_t *row_type, const double *rhs,
                            double *p_inout, const gf_solve_params *params,

@@ -491,31 +491,17 @@ def transition_3d_to_2d_cloud(p, row_ptr, col, flag, mass, rho, phi=None, film_h
     return out
 
 
-def advdiff_rows(d, n_regular, n_ext, h):
-    """Row roles of the diffusion analogue on the extended cloud: the 3D
-    block's top and bottom layers carry a zero normal flux (Neumann rows), the
-    outer edge of the plate (within h/2 of it) is held at zero (Dirichlet),
-    ghost rows hold their known values (Dirichlet), every other regular row
-    is an implicit Euler row of the diffusion equation (type 4)."""
-    x, y = d["x"], d["y"]
-    rt = np.full(n_ext, 4, np.int8)
-    rt[:n_regular][(np.asarray(d["model"]) == 0) & (np.asarray(d["kind"]) != 0)] = 3
-    outer = (x < 0.5 * h) | (x > 2 - 0.5 * h) | (y < 0.5 * h) | (y > 1.5 - 0.5 * h)
-    rt[:n_regular][outer] = 1
-    rt[n_regular:] = 1
-    return rt
-
-
-def advdiff_run(d, h, kappa, t_end, steps, r_min=R_MIN, r_max=R_MAX, ghost_scale=1.0):
+def advdiff_run(d, rows, kappa, t_end, steps, r_min=R_MIN, r_max=R_MAX, ghost_scale=1.0):
     """Diffusion of T (Eq. AdvDiff with the Lagrangian motion left out: the
     cloud is static, so the interfaces are fixed and, as Sec. 6.2 prescribes
     for that case, the ghosts keep their places and only their data is
     recomputed every step).  Each step: ghost values from the buffer-zone
     data mapping (Alg. 5) of the current T; then one implicit Euler step
     (I - dt kappa Lap) T^{n+1} = T^n over the extended neighbourhoods, with
-    the rows of advdiff_rows, solved exactly (sparse LU).  Returns T at t_end
-    and the row roles.  ghost_scale multiplies the ghost values (1: the
-    method; 0: a control without coupling)."""
+    regular rows of the given roles (4: implicit diffusion row, 3: zero
+    normal flux, 1: held at zero; ghost rows hold their values), solved
+    exactly (sparse LU).  Returns T at t_end.  ghost_scale multiplies the
+    ghost values (1: the method; 0: a control without coupling)."""
     import scipy.sparse as sp
     import scipy.sparse.linalg as spla
     n = d["x"].shape[0]
@@ -527,7 +513,7 @@ def advdiff_run(d, h, kappa, t_end, steps, r_min=R_MIN, r_max=R_MAX, ghost_scale
     ne = e["x"].shape[0]
     rp, col = neighbours_rows(e, n)
     w, _, _ = gfdm_weights(e, rp, col)
-    rt = advdiff_rows(d, n, ne, h)
+    rt = np.concatenate([np.asarray(rows, dtype=np.int8), np.ones(ne - n, np.int8)])
     dt = t_end / steps
     lap = poisson_matrix(e, rp, col, w, np.zeros(ne, np.int8))
     bc = poisson_matrix(e, rp, col, w, np.where(rt == 4, 0, rt).astype(np.int8))
@@ -540,7 +526,7 @@ def advdiff_run(d, h, kappa, t_end, steps, r_min=R_MIN, r_max=R_MAX, ghost_scale
         rhs = np.concatenate([T, ghost_scale * g["phi"][0]])
         rhs[:n][rt[:n] != 4] = 0.0
         T = lu.solve(rhs)[:n]
-    return T, rt
+    return T
 
 
 def operator_error(w, w_ref, row_ptr):

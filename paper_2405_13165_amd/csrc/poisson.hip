@@ -93,7 +93,8 @@ __global__ void __launch_bounds__(kBlock) k_assemble(const int64_t *__restrict__
                                                      const double *__restrict__ w, const int8_t *__restrict__ row_type,
                                                      const double *__restrict__ h, const double *__restrict__ nx,
                                                      const double *__restrict__ ny, const double *__restrict__ nz,
-                                                     double zeta, int64_t n, double *__restrict__ val64,
+                                                     double zeta, double a, int max_type, int64_t n,
+                                                     double *__restrict__ val64,
                                                      float *__restrict__ val32, double *__restrict__ dinv64,
                                                      float *__restrict__ dinv32, int *__restrict__ bad) {
   const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -115,6 +116,7 @@ __global__ void __launch_bounds__(kBlock) k_assemble(const int64_t *__restrict__
         case GF_ROW_INTERIOR: v = g23.y; break;
         case GF_ROW_DIRICHLET: v = self ? 1.0 : 0.0; break;
         case GF_ROW_NEUMANN_COMBINED: v = g23.y + zf * ngrad; break;
+        case GF_ROW_IMPLICIT: v = (self ? 1.0 : 0.0) - a * g23.y; break;
         default: v = ngrad; break;
       }
       if (val64) val64[k] = v;
@@ -123,7 +125,7 @@ __global__ void __launch_bounds__(kBlock) k_assemble(const int64_t *__restrict__
     }
     diag = team_sum(diag, kTeam);  // exactly the self value: the other lanes add zeros
     if (lane == 0) {
-      if (rt < 0 || rt > 3 || diag == 0.0 || !isfinite(diag)) atomicAdd(bad, 1);
+      if (rt < 0 || rt > max_type || diag == 0.0 || !isfinite(diag)) atomicAdd(bad, 1);
       if (dinv64) dinv64[i] = (diag != 0.0) ? 1.0 / diag : 0.0;
       if (dinv32) dinv32[i] = (diag != 0.0) ? (float)(1.0 / diag) : 0.0f;
     }
@@ -491,13 +493,16 @@ extern "C" void gf_solve_params_default(gf_solve_params *p) {
   p->inner_maxit = 2000;
   p->zeta = 0.3;
   p->check_every = 4;
+  p->implicit_a = 0.0;
 }
 
+// a: coefficient of GF_ROW_IMPLICIT rows; max_type: largest row type accepted
 static gf_status assemble_common(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr, const double *w64,
-                                 const int8_t *row_type, double zeta, double *val64, float *val32, double *dinv64,
-                                 float *dinv32, int *bad) {
+                                 const int8_t *row_type, double zeta, double a, int max_type, double *val64,
+                                 float *val32, double *dinv64, float *dinv32, int *bad) {
   hipLaunchKernelGGL(k_assemble, dim3(kRedBlocks), dim3(kBlock), 0, ctx->stream, nbr->row_ptr, nbr->col,
-                     w64, row_type, p->h, p->nx, p->ny, p->nz, zeta, p->n, val64, val32, dinv64, dinv32, bad);
+                     w64, row_type, p->h, p->nx, p->ny, p->nz, zeta, a, max_type, p->n, val64, val32, dinv64, dinv32,
+                     bad);
   GF_LAUNCH_CHECK(ctx);
   return GF_OK;
 }
@@ -523,7 +528,8 @@ extern "C" gf_status gf_poisson_assemble(gf_ctx *ctx, const gf_particles *p, con
   if ((st = ensure_scratch(ctx, arena_bytes({64}), &ar))) return st;
   int *bad = ar.take<int>(16);
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, ctx->stream, (unsigned *)bad);
-  return assemble_common(ctx, p, nbr, w64, row_type, zeta, val_out, nullptr, nullptr, nullptr, bad);
+  return assemble_common(ctx, p, nbr, w64, row_type, zeta, 0.0, GF_ROW_NEUMANN, val_out, nullptr, nullptr, nullptr,
+                         bad);
 }
 
 extern "C" gf_status gf_poisson_solve(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr, const double *w64,
@@ -570,7 +576,9 @@ extern "C" gf_status gf_poisson_solve(gf_ctx *ctx, const gf_particles *p, const 
   if ((st = ensure_host(ctx, 4096))) return st;
   hipStream_t sm = ctx->stream;
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, sm, (unsigned *)bad);
-  if ((st = assemble_common(ctx, p, nbr, w64, row_type, prm.zeta, val64, val32, dinv64, dinv32, bad))) return st;
+  if ((st = assemble_common(ctx, p, nbr, w64, row_type, prm.zeta, prm.implicit_a, GF_ROW_IMPLICIT, val64, val32,
+                            dinv64, dinv32, bad)))
+    return st;
   Solver sv;
   sv.ctx = ctx; sv.nbr = nbr; sv.n = n; sv.part = part; sv.S = S;
   sv.hS = (Scal *)ctx->host_pinned;

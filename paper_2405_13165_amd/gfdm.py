@@ -20,7 +20,7 @@ GF_OK, GF_EINVAL, GF_ENOMEM, GF_EHIP, GF_ECAPACITY, GF_ENOTCONV, GF_EBREAKDOWN =
 GF_F64, GF_F32 = 0, 1
 GF_PLAIN_F64, GF_BATCHED = 0, 1
 OP_DX, OP_DY, OP_DZ, OP_LAP = 1, 2, 4, 8
-ROW_INTERIOR, ROW_DIRICHLET, ROW_NEUMANN_COMBINED, ROW_NEUMANN = 0, 1, 2, 3
+ROW_INTERIOR, ROW_DIRICHLET, ROW_NEUMANN_COMBINED, ROW_NEUMANN, ROW_IMPLICIT = 0, 1, 2, 3, 4
 
 _STATUS_NAMES = {0: "GF_OK", -1: "GF_EINVAL", -2: "GF_ENOMEM", -3: "GF_EHIP", -4: "GF_ECAPACITY",
                  -5: "GF_ENOTCONV", -6: "GF_EBREAKDOWN"}
@@ -57,7 +57,7 @@ class LsStats(ctypes.Structure):
 class SolveParams(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("maxit", ctypes.c_int), ("mixed", ctypes.c_int),
                 ("inner_rtol", ctypes.c_double), ("inner_maxit", ctypes.c_int),
-                ("zeta", ctypes.c_double), ("check_every", ctypes.c_int)]
+                ("zeta", ctypes.c_double), ("check_every", ctypes.c_int), ("implicit_a", ctypes.c_double)]
 
 
 class SolveStats(ctypes.Structure):

@@ -192,6 +192,18 @@ def advdiff_plate(h: float = 0.06, layers: int = 4, seed_extra: int = 0):
                  **_droplets(model, film_height, spacing))
 
 
+def advdiff_rows(d, h):
+    """Row roles of the plate's regular particles (the problem's boundary
+    conditions): 3 (zero normal flux) on the 3D block's top and bottom
+    layers, 1 (held at zero) within h/2 of the plate's outer edge, 4 (implicit
+    diffusion row) elsewhere.  Ghost rows are appended as 1 (known values)."""
+    x, y = d["x"], d["y"]
+    rt = np.full(x.shape[0], 4, np.int8)
+    rt[(np.asarray(d["model"]) == BULK) & (np.asarray(d["kind"]) != INTERIOR)] = 3
+    rt[(x < 0.5 * h) | (x > 2 - 0.5 * h) | (y < 0.5 * h) | (y > 1.5 - 0.5 * h)] = 1
+    return rt
+
+
 def advdiff_exact(x, y, t, kappa, sigma0=0.1, x0=1.0, y0=0.75):
     """Heat equation in the plane from a Gaussian of width sigma0: the width
     grows to sqrt(sigma0^2 + 2 kappa t) and the peak falls accordingly."""
