@@ -11,8 +11,10 @@
 //   dbar_j   = (d phi / d d)^T phibar_j + wbar_j dw/dd,   d = x_j - x_i,
 // and x_j gains dbar_j, x_i loses it.  The stencils are recomputed (nothing
 // is stored but the neighbour lists).  Per-entry contributions go to scratch
-// and are gathered per particle through the reverse-edge map, so the result
-// is deterministic (no atomics).  The Gram system is solved by LDL^T in FP64;
+// with the rows laid out in grouped (Morton) order and are gathered per
+// particle, in the same order, through the reverse-edge map: the twin entry
+// (j, i) of (i, j) lies in a Morton-near row, so the gather stays in L2.  No
+// atomics: the result is deterministic.  The Gram system is solved by LDL^T in FP64;
 // rows whose Gram matrix is not positive definite contribute nothing.
 #include "stencil_common.h"
 
@@ -31,11 +33,12 @@ struct AArgs {
   WeightFn wf;
   unsigned mask;
   const double *u, *ybar;
-  double *dbar;  // [nnz][3]
+  double *dbar;  // [nnz][3], rows in grouped order
+  const int64_t *gbase;  // per team: offset of its row in dbar (grouped row offsets)
 };
 
 template <int M>
-__device__ void adjoint_row(const AArgs &a, int32_t i, int lane) {
+__device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane) {
   const int64_t b = a.row_ptr[i];
   const int n = (int)(a.row_ptr[i + 1] - b);
   RowGeom g;
@@ -62,7 +65,7 @@ __device__ void adjoint_row(const AArgs &a, int32_t i, int lane) {
   if (ok) ok = ldlt<M>(G, dinv);
   if (!ok) {
     for (int k = lane; k < n; k += kT) {
-      double *d = a.dbar + 3 * (b + k);
+      double *d = a.dbar + 3 * (ob + k);
       d[0] = 0.0; d[1] = 0.0; d[2] = 0.0;
     }
     return;
@@ -128,7 +131,7 @@ __device__ void adjoint_row(const AArgs &a, int32_t i, int lane) {
   }
   for (int k = lane; k < n; k += kT) {
     const int32_t j = a.col[b + k];
-    double *out = a.dbar + 3 * (b + k);
+    double *out = a.dbar + 3 * (ob + k);
     if (j == i) { out[0] = 0.0; out[1] = 0.0; out[2] = 0.0; continue; }
     const double dx = a.x[j] - g.xi, dy = a.y[j] - g.yi, dz = a.z[j] - g.zi;
     const double d2 = dx * dx + dy * dy + dz * dz;
@@ -164,28 +167,31 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_x(AArgs a) {
   const int64_t team = gt / kT;
   const int lane = (int)(gt % kT);
   if (team >= a.nrows) return;
-  adjoint_row<M>(a, a.sched[team], lane);
+  adjoint_row<M>(a, a.sched[team], a.gbase[team], lane);
 }
 
-// xbar_j += sum_{k in row j, col[k] != j} (dbar[rev[k]] - dbar[k]); a team
-// of kT lanes per row
-__global__ void __launch_bounds__(kBlock) k_adjoint_gather(const int64_t *__restrict__ row_ptr,
-                                                           const int32_t *__restrict__ col,
-                                                           const int32_t *__restrict__ rev,
+// xbar_j += sum over entries (j, i) of row j, i != j, of dbar(i, j) -
+// dbar(j, i); rows in grouped order, a team of kT lanes per row; the twin
+// dbar(i, j) sits at grev[g] (a Morton-near row).
+__global__ void __launch_bounds__(kBlock) k_adjoint_gather(const int32_t *__restrict__ grouped,
+                                                           const int64_t *__restrict__ grow_ptr,
+                                                           const int32_t *__restrict__ grev,
                                                            const double *__restrict__ dbar, int64_t n,
                                                            double *__restrict__ xbar) {
   const int64_t gt = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  const int64_t j = gt / kT;
+  const int64_t t = gt / kT;
   const int lane = (int)(gt % kT);
-  if (j >= n) return;
+  if (t >= n) return;
+  const int32_t j = grouped[t];
+  const int64_t g0 = grow_ptr[t], g1 = grow_ptr[t + 1];
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll 4
-  for (int64_t k = row_ptr[j] + lane; k < row_ptr[j + 1]; k += kT) {
-    const int32_t kr = rev[k];
-    if (col[k] == j || kr < 0) continue;
-    s0 += dbar[3 * (int64_t)kr] - dbar[3 * k];
-    s1 += dbar[3 * (int64_t)kr + 1] - dbar[3 * k + 1];
-    s2 += dbar[3 * (int64_t)kr + 2] - dbar[3 * k + 2];
+  for (int64_t gk = g0 + lane; gk < g1; gk += kT) {
+    const int32_t tw = grev[gk];
+    if (tw < 0) continue;
+    s0 += dbar[3 * (int64_t)tw] - dbar[3 * gk];
+    s1 += dbar[3 * (int64_t)tw + 1] - dbar[3 * gk + 1];
+    s2 += dbar[3 * (int64_t)tw + 2] - dbar[3 * gk + 2];
   }
   s0 = team_sum(s0, kT);
   s1 = team_sum(s1, kT);
@@ -213,7 +219,7 @@ extern "C" gf_status gf_gfdm_weights_adjoint(gf_ctx *ctx, const gf_particles *p,
   gf_ls_params prm;
   gf_ls_params_default(&prm);
   if (params) prm = *params;
-  if ((st = ensure_rev(ctx, const_cast<gf_nbr *>(nbr)))) return st;
+  if ((st = ensure_grouped_rows(ctx, const_cast<gf_nbr *>(nbr)))) return st;
   Arena ar;
   if ((st = ensure_scratch(ctx, arena_bytes({sizeof(double) * 3 * (size_t)std::max<int64_t>(nbr->nnz, 1)}), &ar)))
     return st;
@@ -227,6 +233,7 @@ extern "C" gf_status gf_gfdm_weights_adjoint(gf_ctx *ctx, const gf_particles *p,
     const int64_t s0 = nbr->group_start[m * GF_NBAND], s1 = nbr->group_start[(m + 1) * GF_NBAND];
     if (s1 <= s0) continue;
     a.sched = nbr->grouped + s0;
+    a.gbase = nbr->grow_ptr + s0;
     a.nrows = s1 - s0;
     const dim3 grid(grid_for(a.nrows * kT, kBlock)), block(kBlock);
     ProfScope prof(ctx, m == 0 ? "weights_adjoint_3d" : "weights_adjoint_film");
@@ -237,7 +244,7 @@ extern "C" gf_status gf_gfdm_weights_adjoint(gf_ctx *ctx, const gf_particles *p,
   {
     ProfScope prof(ctx, "weights_adjoint_gather");
     hipLaunchKernelGGL(k_adjoint_gather, dim3(grid_for(p->n * kT, kBlock)), dim3(kBlock), 0, ctx->stream,
-                       nbr->row_ptr, nbr->col, nbr->rev, a.dbar, p->n, xbar_3n);
+                       nbr->grouped, nbr->grow_ptr, nbr->grev, a.dbar, p->n, xbar_3n);
     GF_LAUNCH_CHECK(ctx);
   }
   return GF_OK;

@@ -67,6 +67,13 @@ struct gf_nbr {
   int32_t *grouped = nullptr;  // [n] particles grouped by (model, band), Morton order inside
   int64_t group_start[2 * GF_NBAND + 1] = {0};  // host copy of the group offsets
   int32_t *rev = nullptr;      // [nnz] position of (j,i) for entry (i,j); built lazily
+  // rows in grouped (Morton) order, built lazily: grow_ptr[t] = entries of the
+  // rows grouped[0..t), gpos[i] = position of particle i in grouped
+  int64_t *grow_ptr = nullptr; // [n+1]
+  int32_t *gpos = nullptr;     // [n]
+  // grev[g]: position, in the grouped layout, of the twin (j, i) of the entry
+  // (i, j) at grouped position g; -1 for self entries and missing twins
+  int32_t *grev = nullptr;     // [nnz]
   // Neighbour tiles: per model, the rows of the bands 0..kTileBand (at most
   // kTileBandRow neighbours; one contiguous range of the grouped order) are
   // cut, in that order, into tiles of kTileRows rows.  tile_u holds, per
@@ -179,6 +186,8 @@ gf_status ensure_host(gf_ctx *ctx, size_t bytes);
 gf_status check_particles(gf_ctx *ctx, const gf_particles *p, bool need_kind, bool need_normals);
 gf_status check_nbr(gf_ctx *ctx, const gf_nbr *nbr, int64_t n);
 gf_status ensure_rev(gf_ctx *ctx, gf_nbr *nbr);
+// grouped row offsets, positions and twin map (needs the reverse-edge map)
+gf_status ensure_grouped_rows(gf_ctx *ctx, gf_nbr *nbr);
 gf_status tune_apply(gf_ctx *ctx, const gf_nbr *nbr, const void *w, gf_dtype wtype);
 
 // device-wide exclusive scans (in place allowed): out[k] = sum_{t<k} in[t],

@@ -901,6 +901,9 @@ void free_nbr(gf_nbr *nb) {
   if (nb->slot) (void)hipFree(nb->slot);
   if (nb->tile_u) (void)hipFree(nb->tile_u);
   if (nb->tile_off) (void)hipFree(nb->tile_off);
+  if (nb->grow_ptr) (void)hipFree(nb->grow_ptr);
+  if (nb->gpos) (void)hipFree(nb->gpos);
+  if (nb->grev) (void)hipFree(nb->grev);
   delete nb;
 }
 
@@ -937,6 +940,68 @@ gf_status ensure_rev(gf_ctx *ctx, gf_nbr *nbr) {
   }
   hipLaunchKernelGGL(k_rev, dim3(grid_for(nbr->n * kRevTeam, kBlock)), dim3(kBlock), 0, ctx->stream, nbr->row_ptr, nbr->col,
                      nbr->n, nbr->rev);
+  GF_LAUNCH_CHECK(ctx);
+  return GF_OK;
+}
+
+namespace {
+__global__ void __launch_bounds__(kBlock) k_grouped_len(const int32_t *__restrict__ grouped,
+                                                        const int64_t *__restrict__ row_ptr, int64_t n,
+                                                        int32_t *__restrict__ len, int32_t *__restrict__ gpos) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int32_t i = grouped[t];
+  len[t] = (int32_t)(row_ptr[i + 1] - row_ptr[i]);
+  gpos[i] = (int32_t)t;
+}
+// grev for the rows in grouped order, a team of kRevTeam lanes per row
+__global__ void __launch_bounds__(kBlock) k_grouped_rev(const int32_t *__restrict__ grouped,
+                                                        const int64_t *__restrict__ row_ptr,
+                                                        const int32_t *__restrict__ col,
+                                                        const int32_t *__restrict__ rev,
+                                                        const int64_t *__restrict__ grow_ptr,
+                                                        const int32_t *__restrict__ gpos, int64_t n,
+                                                        int32_t *__restrict__ grev) {
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = gt / kRevTeam;
+  const int lane = (int)(gt % kRevTeam);
+  if (t >= n) return;
+  const int32_t i = grouped[t];
+  const int64_t b = row_ptr[i], len = row_ptr[i + 1] - b, ob = grow_ptr[t];
+  for (int64_t o = lane; o < len; o += kRevTeam) {
+    const int32_t j = col[b + o];
+    const int32_t kr = rev[b + o];
+    grev[ob + o] = (j == i || kr < 0) ? -1 : (int32_t)(grow_ptr[gpos[j]] + (kr - row_ptr[j]));
+  }
+}
+}  // namespace
+
+gf_status ensure_grouped_rows(gf_ctx *ctx, gf_nbr *nbr) {
+  if (nbr->grev) return GF_OK;
+  gf_status st = ensure_rev(ctx, nbr);  // also checks that positions fit 32 bits
+  if (st) return st;
+  const int64_t n = nbr->n;
+  if (hipMalloc(&nbr->grow_ptr, sizeof(int64_t) * (n + 1)) != hipSuccess ||
+      hipMalloc(&nbr->gpos, sizeof(int32_t) * n) != hipSuccess ||
+      hipMalloc(&nbr->grev, sizeof(int32_t) * std::max<int64_t>(nbr->nnz, 1)) != hipSuccess) {
+    if (nbr->grow_ptr) (void)hipFree(nbr->grow_ptr);
+    if (nbr->gpos) (void)hipFree(nbr->gpos);
+    nbr->grow_ptr = nullptr;
+    nbr->gpos = nullptr;
+    nbr->grev = nullptr;
+    return set_error(ctx, GF_ENOMEM, "grouped row offsets allocation failed");
+  }
+  Arena ar;
+  if ((st = ensure_scratch(ctx, arena_bytes({sizeof(int32_t) * n, sizeof(int64_t) * scan_tmp_elems(n + 1)}), &ar)))
+    return st;
+  int32_t *len = ar.take<int32_t>(n);
+  int64_t *tmp = ar.take<int64_t>(scan_tmp_elems(n + 1));
+  hipLaunchKernelGGL(k_grouped_len, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, ctx->stream, nbr->grouped,
+                     nbr->row_ptr, n, len, nbr->gpos);
+  GF_LAUNCH_CHECK(ctx);
+  if ((st = scan_i32_to_i64(ctx, len, nbr->grow_ptr, n, tmp))) return st;
+  hipLaunchKernelGGL(k_grouped_rev, dim3(grid_for(n * kRevTeam, kBlock)), dim3(kBlock), 0, ctx->stream, nbr->grouped,
+                     nbr->row_ptr, nbr->col, nbr->rev, nbr->grow_ptr, nbr->gpos, n, nbr->grev);
   GF_LAUNCH_CHECK(ctx);
   return GF_OK;
 }
