@@ -529,6 +529,71 @@ def advdiff_run(d, rows, kappa, t_end, steps, r_min=R_MIN, r_max=R_MAX, ghost_sc
     return T
 
 
+_CLOUD_KEYS = ("x", "y", "z", "h", "model", "kind", "nx", "ny", "nz", "mass", "rho", "T", "H", "edge")
+
+
+def _rows_of(c, h):
+    """Row roles: zero normal flux on 3D walls and free surfaces, zero on the
+    plate's edge, implicit diffusion rows elsewhere (as W.advdiff_rows)."""
+    rt = np.full(c["x"].shape[0], 4, np.int8)
+    rt[(c["model"] == 0) & (c["kind"] != 0)] = 3
+    rt[c["edge"] > 0.5] = 1
+    return rt
+
+
+def advect_step(c, h, kappa, dt, x0=1.0, x1=2.0, r_min=R_MIN, r_max=R_MAX):
+    """One model-adaptive step of the advection-diffusion case (Sec. 7.3):
+    Lagrangian move with v = (1, 0, 0); film particles inside [x0, x1]
+    transition to 3D (Sec. 5.2), 3D wall particles beyond x1 transition to
+    2D with their columns (Sec. 5.1); then ghosts (Alg. 5), extended
+    neighbourhoods (Sec. 6.2) and one implicit Euler diffusion step, solved
+    exactly.  c: dict of particle arrays (_CLOUD_KEYS); returns the new one.
+    The film thickness H and the edge marker travel as fields."""
+    c = {k: np.asarray(v).copy() for k, v in c.items()}
+    c["x"] = c["x"] + dt * 1.0
+    # 2D -> 3D
+    flag2 = ((c["model"] == 1) & (c["x"] >= x0) & (c["x"] <= x1))
+    if flag2.any():
+        sel = np.nonzero(flag2)[0]
+        o = transition_2d_to_3d(c, sel, c["H"], c["h"], c["mass"], c["rho"], np.stack([c["T"], c["edge"]]),
+                                r_min, r_max)
+        keep = np.nonzero(~flag2)[0]
+        new = {k: o[k] for k in ("x", "y", "z", "h", "model", "kind", "nx", "ny", "nz", "mass", "rho")}
+        new["T"] = o["phi"][0]
+        new["edge"] = o["phi"][1]
+        new["H"] = np.zeros(o["x"].size)
+        c = {k: np.concatenate([c[k][keep], new[k].astype(c[k].dtype)]) for k in _CLOUD_KEYS}
+    # 3D -> 2D
+    flag1 = ((c["model"] == 0) & (c["kind"] == 2) & (c["x"] > x1)).astype(np.uint8)
+    if flag1.any():
+        rp, col = neighbours(c)
+        o = transition_3d_to_2d_cloud(c, rp, col, flag1, c["mass"], c["rho"], np.stack([c["T"], c["edge"]]),
+                                      film_height=c["H"], h_film=c["h"])
+        c = {k: o[k] for k in ("x", "y", "z", "h", "model", "kind", "nx", "ny", "nz", "mass", "rho")}
+        c["T"] = o["phi"][0]
+        c["edge"] = o["phi"][1]
+        c["H"] = o["height"]
+    # ghosts, extended neighbourhoods, one implicit diffusion step
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    n = c["x"].size
+    rpc, colc = neighbours(c, cross=True)
+    _, g = buffer_zone(c, rpc, colc, c["H"], c["h"], c["mass"], c["rho"], c["T"][None, :], r_min, r_max)
+    e = extend_cloud(c, g)
+    ne = e["x"].size
+    rp, col = neighbours_rows(e, n)
+    w, _, _ = gfdm_weights(e, rp, col)
+    rt = np.concatenate([_rows_of(c, h), np.ones(ne - n, np.int8)])
+    lap = poisson_matrix(e, rp, col, w, np.zeros(ne, np.int8))
+    bc = poisson_matrix(e, rp, col, w, np.where(rt == 4, 0, rt).astype(np.int8))
+    rid = np.repeat(np.arange(ne), np.diff(rp))
+    val = np.where(rt[rid] == 4, (col == rid).astype(np.float64) - dt * kappa * lap, bc)
+    rhs = np.concatenate([c["T"], g["phi"][0]])
+    rhs[:n][rt[:n] != 4] = 0.0
+    c["T"] = spla.spsolve(sp.csr_matrix((val, col, rp), shape=(ne, ne)).tocsc(), rhs)[:n]
+    return c
+
+
 def operator_error(w, w_ref, row_ptr):
     """Per row and stencil: |c - c_ref|_2 / |c_ref|_2 over the row's entries.
     Rows/stencils whose reference is identically zero are reported as the
