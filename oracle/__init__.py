@@ -548,7 +548,8 @@ def advect_step(c, h, kappa, dt, x0=1.0, x1=2.0, r_min=R_MIN, r_max=R_MAX):
     2D with their columns (Sec. 5.1); then ghosts (Alg. 5), extended
     neighbourhoods (Sec. 6.2) and one implicit Euler diffusion step, solved
     exactly.  c: dict of particle arrays (_CLOUD_KEYS); returns the new one.
-    The film thickness H and the edge marker travel as fields."""
+    The film thickness H and the edge marker travel as fields.  With
+    kappa = 0 (pure advection) the step ends after the transitions."""
     c = {k: np.asarray(v).copy() for k, v in c.items()}
     c["x"] = c["x"] + dt * 1.0
     # 2D -> 3D
@@ -573,6 +574,8 @@ def advect_step(c, h, kappa, dt, x0=1.0, x1=2.0, r_min=R_MIN, r_max=R_MAX):
         c["T"] = o["phi"][0]
         c["edge"] = o["phi"][1]
         c["H"] = o["height"]
+    if kappa == 0.0:
+        return c
     # ghosts, extended neighbourhoods, one implicit diffusion step
     import scipy.sparse as sp
     import scipy.sparse.linalg as spla

@@ -80,13 +80,16 @@ class AdvectPlate:
     neighbourhoods and the stencils are rebuilt at every step, since every
     particle has moved, and one implicit Euler diffusion step follows
     (zero normal flux on 3D walls and free surfaces, zero on the plate's
-    outer edge).  The temperature and a 0/1 marker of the plate's edge are
+    outer edge); with kappa = 0 (pure advection) a step ends after the
+    transitions.  The temperature and a 0/1 marker of the plate's edge are
     carried through both transitions as mapped fields; the film thickness is
     carried by the film particles.  Each transition, build and solve runs in
     the library's kernels; this class moves the particles, selects the
     flagged ones and concatenates buffers."""
 
     def __init__(self, ctx, d, kappa, dt, x0=1.0, x1=2.0, rtol=1e-12):
+        # (x0, x1) = (-inf, inf) turns the whole plate into 3D at the first
+        # step and keeps it there: the full-3D run of the same case
         self.ctx = ctx
         self.kappa, self.dt, self.x0, self.x1 = kappa, dt, x0, x1
         dev = ctx.device
@@ -137,6 +140,8 @@ class AdvectPlate:
             c["T"], c["edge"], c["H"] = o["phi"][0], o["phi"][1], o["height"]
             self.stats["to_2d"] += int(f1.sum())
         self.c = c
+        if self.kappa == 0.0:
+            return
         # ghosts, extended neighbourhoods, stencils, one implicit step
         p = self._particles()
         n = p.n

@@ -204,16 +204,19 @@ def advdiff_rows(d, h):
     return rt
 
 
-def advect_plate(h: float = 0.06, layers: int = 4, seed_extra: int = 0):
-    """Initial cloud of the model-adaptive advection-diffusion case (Sec. 7.3):
-    a film of particles on [0,2.5]x[0,1.5] (spacing s = h/3, jitter U(+-0.2 s)),
-    all 2D at t = 0, film thickness (layers-1) s, support h.  T0 is a Gaussian
-    of width 0.1 around (0.6, 0.75), constant in depth.  `edge` marks the
-    particles within h/2 of the plate's outer edge (they carry it as they
-    move and change model)."""
+def advect_plate(h: float = 0.06, layers: int = 4, seed_extra: int = 0, lx: float = 2.5, ly: float = 1.5,
+                 ic: str = "gauss", center=(0.6, 0.75), radius: float = 0.2, sigma: float = 0.1):
+    """Initial cloud of the model-adaptive advection(-diffusion) case
+    (Sec. 7.3): a film of particles on [0,lx]x[0,ly] (spacing s = h/3, jitter
+    U(+-0.2 s)), all 2D at t = 0, film thickness (layers-1) s, support h.
+    T0, constant in depth, is a Gaussian of width sigma around `center`
+    (ic="gauss") or 1 inside the disc of the given radius around it and 0
+    outside (ic="disc", Eq. (AdvDiff_IC)).  `edge` marks the particles within
+    h/2 of the plate's outer edge (they carry it as they move and change
+    model)."""
     rng = rng_for(8, seed_extra)
     s = h / 3.0
-    nx_ = int(round(2.5 / s)); ny_ = int(round(1.5 / s))
+    nx_ = int(round(lx / s)); ny_ = int(round(ly / s))
     jj, ii = np.meshgrid(np.arange(ny_), np.arange(nx_), indexing="ij")
     x = (ii.ravel() + 0.5) * s + rng.uniform(-0.2 * s, 0.2 * s, ii.size)
     y = (jj.ravel() + 0.5) * s + rng.uniform(-0.2 * s, 0.2 * s, ii.size)
@@ -221,8 +224,12 @@ def advect_plate(h: float = 0.06, layers: int = 4, seed_extra: int = 0):
     depth = (layers - 1) * s
     film_height = np.full(n, depth)
     model = np.ones(n, np.int8)
-    T0 = np.exp(-((x - 0.6) ** 2 + (y - 0.75) ** 2) / (2 * 0.1 ** 2))
-    edge = ((x < 0.5 * h) | (x > 2.5 - 0.5 * h) | (y < 0.5 * h) | (y > 1.5 - 0.5 * h)).astype(np.float64)
+    r2 = (x - center[0]) ** 2 + (y - center[1]) ** 2
+    if ic == "disc":
+        T0 = (r2 <= radius * radius).astype(np.float64)
+    else:
+        T0 = np.exp(-r2 / (2 * sigma ** 2))
+    edge = ((x < 0.5 * h) | (x > lx - 0.5 * h) | (y < 0.5 * h) | (y > ly - 0.5 * h)).astype(np.float64)
     return _pack(x, y, np.zeros(n), np.full(n, h), model, np.full(n, WALL, np.int8), None, None, np.ones(n),
                  film_height=film_height, T0=T0, edge=edge, spacing=s, depth=depth,
                  **_droplets(model, film_height, np.full(n, s)))

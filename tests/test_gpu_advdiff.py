@@ -102,3 +102,25 @@ def test_model_adaptive_advection_accuracy(ctx):
     print(f"\n[advect] h={h} e2={e2:.3e} {info}")
     assert np.all(g["model"] == 1) and g["x"].size == d["x"].size
     assert e2 < 1e-2
+
+
+def test_pure_advection_matches_oracle_and_is_exact(ctx):
+    # kappa = 0: the Lagrangian move and the two transitions only; the disc
+    # arrives at t = 2 unchanged (values exactly 0 / 1)
+    from paper_2405_13165_amd.advdiff import AdvectPlate
+    d = W.advect_plate(0.1, lx=3.0, ly=1.0, ic="disc", center=(0.5, 0.5))
+    c, info = AdvectPlate(ctx, d, 0.0, 2.0 / 40).run(40)
+    g = {k: v.cpu().numpy() for k, v in c.items()}
+    print(f"\n[advect] pure advection {info}")
+    c_o = {k: np.asarray(d[k]).copy() for k in ("x", "y", "z", "h", "model", "kind", "nx", "ny", "nz", "mass",
+                                                "rho")}
+    c_o["T"], c_o["H"], c_o["edge"] = d["T0"].copy(), d["film_height"].copy(), d["edge"].copy()
+    for _ in range(40):
+        c_o = oracle.advect_step(c_o, 0.1, 0.0, 2.0 / 40)
+    assert info["to_3d"] > 0 and info["to_2d"] == info["to_3d"]
+    assert g["x"].size == c_o["x"].size == d["x"].size
+    assert np.array_equal(g["model"], c_o["model"]) and np.array_equal(g["T"], c_o["T"])
+    for k in ("x", "y", "H", "mass"):
+        assert np.abs(g[k] - c_o[k]).max() <= 1e-12 * (1 + np.abs(c_o[k]).max()), k
+    ex = ((g["x"] - 2.5) ** 2 + (g["y"] - 0.5) ** 2 <= 0.04).astype(np.float64)
+    assert np.array_equal(g["T"], ex)

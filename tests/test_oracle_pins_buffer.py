@@ -417,3 +417,23 @@ def test_model_adaptive_advection_round_trip():
     e2 = np.sqrt(((c["T"] - ex) ** 2).sum() / (ex ** 2).sum())
     einf = np.abs(c["T"] - ex).max() / ex.max()
     assert e2 < 0.04 and einf < 0.07, (e2, einf)
+
+
+def test_pure_advection_transfers_data_exactly():
+    # kappa = 0 (Sec. 7.3, pure advection): the plate [0,3]x[0,1] passes the
+    # 3D window [1,2]; since the field is constant in depth, the transitions
+    # in both directions move it without loss, and at t = 2 it equals the
+    # initial field moved by 2: exactly for the disc of Eq. (AdvDiff_IC)
+    # (values 0 / 1), to rounding of the moved positions for a Gaussian
+    for ic, tol in (("disc", 0.0), ("gauss", 1e-12)):
+        d = W.advect_plate(0.1, lx=3.0, ly=1.0, ic=ic, center=(0.5, 0.5))
+        c = _advect_cloud(d)
+        saw3d = 0
+        for _ in range(40):
+            c = oracle.advect_step(c, 0.1, 0.0, 2.0 / 40)
+            saw3d = max(saw3d, int((c["model"] == 0).sum()))
+        assert saw3d > d["x"].size and c["x"].size == d["x"].size and np.all(c["model"] == 1)
+        r2 = (c["x"] - 2.5) ** 2 + (c["y"] - 0.5) ** 2
+        ex = (r2 <= 0.04).astype(np.float64) if ic == "disc" else np.exp(-r2 / (2 * 0.1 ** 2))
+        assert np.abs(c["T"] - ex).max() <= tol, ic
+        assert np.allclose(c["H"], d["depth"], rtol=1e-12, atol=0)
