@@ -91,6 +91,9 @@ struct gf_nbr {
 constexpr int kTileRows = 32;
 constexpr int kTileBand = 2;                   // bands 0..kTileBand are tiled
 constexpr int kTileBandRow = 128;              // = kBandHi[kTileBand]
+// entries of padding after the slot array (and the solver's matrix values),
+// so that the SpMV can read a row's entries in aligned groups of four
+constexpr int kQuadPad = 4;
 
 // Launch units of the batched kernels: per model, the tiled rows (bands
 // 0..kTileBand) and each untiled band.  Team sizes live in

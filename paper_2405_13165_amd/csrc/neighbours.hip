@@ -1029,7 +1029,7 @@ gf_status build_tiles(gf_ctx *ctx, gf_nbr *nb) {
   nb->ntiles = nt;
   if (nt == 0) return GF_OK;
   if (nt >= 0x7fffffff) return set_error(ctx, GF_ECAPACITY, "too many neighbour tiles");
-  if (hipMalloc(&nb->slot, sizeof(uint16_t) * std::max<int64_t>(nb->nnz, 1)) != hipSuccess ||
+  if (hipMalloc(&nb->slot, sizeof(uint16_t) * (nb->nnz + kQuadPad)) != hipSuccess ||
       hipMalloc(&nb->tile_off, sizeof(int64_t) * (nt + 1)) != hipSuccess)
     return set_error(ctx, GF_ENOMEM, "neighbour tile allocation failed");
   Arena ar;

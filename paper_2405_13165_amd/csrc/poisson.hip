@@ -249,6 +249,11 @@ __global__ void __launch_bounds__(kBlock) k_spmv_dot(const int64_t *__restrict__
   block_partials<2>(v, part);
 }
 
+// two values in one load
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
+
 // Neighbour tiles of the matrix pattern (the neighbour handle's tiles): rows
 // of tile t are grouped[row0[m] + (t - tile_start[m]) kTileRows ...] for the
 // model m owning t; rows with more than kTileBandRow entries are listed per
@@ -264,18 +269,42 @@ struct SpmvTiles {
   int cap;  // LDS entries of the staged vector
 };
 
-// y = A xin over tiles: each block walks tiles (grid-stride); a tile stages
-// the entries of xin it references in LDS and its 32 rows (one team of
-// kTeam lanes each) read them through slot[]; then the untiled rows.
+// y = A xin over tiles.  The tiles are cut into eight contiguous slices,
+// one per XCD (blocks are dealt to the XCDs in turn, so block b runs on
+// XCD b mod 8 and neighbouring tiles, which share most of their lists,
+// meet in one L2); the G = gridDim.x / 8 blocks of a slice walk it with
+// stride G.  A tile's 32 rows (one team of kTeam lanes each) read the
+// entries of xin it references from LDS through slot[]; tiles whose list
+// exceeds the LDS capacity gather through col[].  Then the untiled rows.
 // Partials of (other, y) and (y, y).
-template <typename VT, typename XT>
+//
+// The walk is software-pipelined so that a tile costs about one memory
+// latency instead of the chain tile offset -> tile list -> xin gather and
+// row index -> row extent -> values: while the rows of tile t are summed
+// from one LDS buffer, the loads for the following tiles are in flight:
+// the xin entries of t+G (held in registers, written to the other buffer
+// at the end of the step), the tile lists of t+2G, the tile offsets of
+// t+3G, the row extents of t+G and the row indices of t+2G.  None of them
+// depends on a load of the same step.  One barrier per tile separates the
+// buffers.
+//
+// A row's entries are read in aligned quads (4q .. 4q+3): lane l of the team
+// takes the quads q0 + l, q0 + l + kTeam, ... (at most kQ of them for a row
+// of kTileBandRow entries), all loaded before any is used, so one load moves
+// 32 B of values or 8 B of slots instead of 8 B or 2 B.  A quad may reach
+// up to three entries into the neighbouring rows: those are read (the value
+// and slot arrays carry kQuadPad entries of padding) but not used.
+// K = staged entries per thread (K * kBlock >= LDS capacity).
+constexpr int kQ = kTileBandRow / (4 * kTeam) + 1;
+
+template <typename VT, typename XT, int K>
 __global__ void __launch_bounds__(kBlock) k_spmv_tiles(const int64_t *__restrict__ row_ptr,
                                                        const int32_t *__restrict__ col, const VT *__restrict__ val,
                                                        const XT *__restrict__ xin, XT *__restrict__ y,
                                                        const XT *__restrict__ other, double *part,
                                                        const Scal *__restrict__ S, SpmvTiles tl) {
   extern __shared__ unsigned char s_raw[];
-  XT *sx = reinterpret_cast<XT *>(s_raw);
+  XT *sb = reinterpret_cast<XT *>(s_raw);  // two buffers of tl.cap entries
   double v[2] = {0.0, 0.0};
   const int team = threadIdx.x / kTeam, lane = threadIdx.x % kTeam;
   auto finish_row = [&](int32_t row, double acc) {
@@ -288,29 +317,129 @@ __global__ void __launch_bounds__(kBlock) k_spmv_tiles(const int64_t *__restrict
     }
   };
   if (!S->breakdown) {
-    const int64_t ntiles = tl.tile_start[2];
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-      const int m = (t >= tl.tile_start[1]) ? 1 : 0;
-      const int64_t r0 = (t - tl.tile_start[m]) * kTileRows;
-      const int64_t u0 = tl.toff[t];
-      const int cnt = (int)(tl.toff[t + 1] - u0);
-      const bool staged = cnt <= tl.cap;
-      __syncthreads();  // the previous tile is done with sx
-      if (staged)
-        for (int s = threadIdx.x; s < cnt; s += blockDim.x) sx[s] = xin[tl.tu[u0 + s]];
-      __syncthreads();
-      if (r0 + team < tl.nrows[m]) {
-        const int32_t row = tl.grouped[tl.row0[m] + r0 + team];
-        const int64_t b = row_ptr[row], e = row_ptr[row + 1];
-        double acc = 0.0;
-        if (staged) {
-#pragma unroll 8
-          for (int64_t k = b + lane; k < e; k += kTeam) acc += (double)val[k] * (double)sx[tl.slot[k]];
-        } else {
-          for (int64_t k = b + lane; k < e; k += kTeam) acc += (double)val[k] * (double)xin[col[k]];
-        }
-        finish_row(row, acc);
+    const int nslice = gridDim.x % 8 == 0 ? 8 : 1;
+    const int slice = blockIdx.x % nslice;
+    const int64_t G = gridDim.x / nslice;
+    const int64_t nt = tl.tile_start[2] * (slice + 1) / nslice;  // end of this block's slice
+    const int cap = tl.cap;
+    // list offset and length of tile t (length -1 past the last tile)
+    auto extent = [&](int64_t t, int64_t &u0, int &cnt) {
+      if (t < nt) {
+        u0 = tl.toff[t];
+        cnt = (int)(tl.toff[t + 1] - u0);
+      } else {
+        u0 = 0;
+        cnt = -1;
       }
+    };
+    // this thread's share of a staged tile's list (-1: nothing)
+    auto load_list = [&](int64_t u0, int cnt, int32_t idx[K]) {
+      const bool staged = cnt >= 0 && cnt <= cap;
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const int s = threadIdx.x + j * kBlock;
+        idx[j] = (staged && s < cnt) ? tl.tu[u0 + s] : -1;
+      }
+    };
+    // this team's row of tile t (-1: none)
+    auto team_row = [&](int64_t t) -> int32_t {
+      if (t >= nt) return -1;  // (past the slice: the tile belongs to another one)
+      const int m = (t >= tl.tile_start[1]) ? 1 : 0;
+      const int64_t r = (t - tl.tile_start[m]) * kTileRows + team;
+      return r < tl.nrows[m] ? tl.grouped[tl.row0[m] + r] : -1;
+    };
+    auto gather = [&](const int32_t idx[K], XT xv[K]) {
+#pragma unroll
+      for (int j = 0; j < K; ++j) xv[j] = idx[j] >= 0 ? xin[idx[j]] : (XT)0;
+    };
+    auto put = [&](XT *buf, const XT xv[K], int cnt) {
+      if (cnt < 0 || cnt > cap) return;
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const int s = threadIdx.x + j * kBlock;
+        if (s < cnt) buf[s] = xv[j];
+      }
+    };
+
+    // prologue: tile t staged, the loads of t+G and t+2G issued
+    int64_t t = tl.tile_start[2] * slice / nslice + blockIdx.x / nslice;
+    int64_t u0_0, u0_1, u0_2;
+    int c0, c1, c2;
+    extent(t, u0_0, c0);
+    extent(t + G, u0_1, c1);
+    extent(t + 2 * G, u0_2, c2);
+    int32_t idx1[K];
+    {
+      int32_t idx0[K];
+      XT x0[K];
+      load_list(u0_0, c0, idx0);
+      gather(idx0, x0);
+      put(sb, x0, c0);
+    }
+    load_list(u0_1, c1, idx1);
+    int32_t row_c = team_row(t), row_n = team_row(t + G);
+    int64_t b_c = 0, e_c = 0;
+    if (row_c >= 0) {
+      b_c = row_ptr[row_c];
+      e_c = row_ptr[row_c + 1];
+    }
+    __syncthreads();
+    int cur = 0;
+    for (; t < nt; t += G) {
+      XT xn[K];
+      gather(idx1, xn);  // entries of t+G
+      int32_t idx2[K];
+      load_list(u0_2, c2, idx2);  // list of t+2G
+      int64_t u0_3;
+      int c3;
+      extent(t + 3 * G, u0_3, c3);
+      int64_t b_n = 0, e_n = 0;
+      if (row_n >= 0) {  // row extent of t+G
+        b_n = row_ptr[row_n];
+        e_n = row_ptr[row_n + 1];
+      }
+      const int32_t row_nn = team_row(t + 2 * G);
+      if (row_c >= 0) {
+        double acc = 0.0;
+        if (c0 <= cap) {
+          const XT *buf = sb + cur * cap;
+          typename Vec2<VT>::type va[kQ], vb[kQ];
+          ushort4 ss[kQ];
+          const int64_t q0 = (b_c >> 2) + lane;
+#pragma unroll
+          for (int j = 0; j < kQ; ++j) {
+            const int64_t k = 4 * (q0 + j * kTeam);
+            if (k < e_c) {
+              va[j] = *reinterpret_cast<const typename Vec2<VT>::type *>(val + k);
+              vb[j] = *reinterpret_cast<const typename Vec2<VT>::type *>(val + k + 2);
+              ss[j] = *reinterpret_cast<const ushort4 *>(tl.slot + k);
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < kQ; ++j) {
+            const int64_t k = 4 * (q0 + j * kTeam);
+            if (k < e_c) {
+              if (k >= b_c) acc += (double)va[j].x * (double)buf[ss[j].x];
+              if (k + 1 >= b_c && k + 1 < e_c) acc += (double)va[j].y * (double)buf[ss[j].y];
+              if (k + 2 >= b_c && k + 2 < e_c) acc += (double)vb[j].x * (double)buf[ss[j].z];
+              if (k + 3 < e_c) acc += (double)vb[j].y * (double)buf[ss[j].w];
+            }
+          }
+        } else {
+          for (int64_t k = b_c + lane; k < e_c; k += kTeam) acc += (double)val[k] * (double)xin[col[k]];
+        }
+        finish_row(row_c, acc);
+      }
+      put(sb + (cur ^ 1) * cap, xn, c1);
+      __syncthreads();
+      cur ^= 1;
+      c0 = c1;
+      u0_1 = u0_2; c1 = c2;
+      u0_2 = u0_3; c2 = c3;
+#pragma unroll
+      for (int j = 0; j < K; ++j) idx1[j] = idx2[j];
+      row_c = row_n; b_c = b_n; e_c = e_n;
+      row_n = row_nn;
     }
     // untiled rows: teams grid-stride over each model's list
     const int64_t gteam = (int64_t)blockIdx.x * (blockDim.x / kTeam) + team;
@@ -408,10 +537,12 @@ struct Solver {
   unsigned grid_row;
   bool tiled;    // the SpMV runs on the neighbour tiles
   SpmvTiles tl;
+  int tiles_grid[2] = {0, 0};  // blocks of the tiled SpMV (FP64, FP32 vectors), set at first use
 };
 
 // staged-vector capacity of the tiled SpMV (entries)
 constexpr int kSpmvCap = 2048;
+static_assert(kSpmvCap <= 8 * kBlock, "the tiled SpMV stages at most 8 entries per thread");
 
 void init_spmv_tiles(Solver &sv) {
   const gf_nbr *nb = sv.nbr;
@@ -430,16 +561,43 @@ void init_spmv_tiles(Solver &sv) {
   t.cap = std::min(cap, tile_capacity(sv.ctx, kSpmvCap));
 }
 
-// y = A xin with the partials of (other, y), (y, y)
+// Blocks of the tiled SpMV: as many as are resident at once (a block walks
+// its tiles to the end, so a block that waits for a slot would add its whole
+// walk to the time), a multiple of 8, at most kRedBlocks.
+template <typename VT, typename XT, int K>
+int spmv_tiles_grid(const Solver &sv, size_t lds) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmv_tiles<VT, XT, K>, kBlock, lds) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  return std::max(8, std::min(kRedBlocks, per_cu * sv.ctx->num_cu) / 8 * 8);
+}
+
+// y = A xin with the partials of (other, y), (y, y); returns the number of
+// partials (blocks) written
+template <typename VT, typename XT, int K>
+int launch_spmv_tiles(Solver &sv, const VT *val, const XT *xin, XT *y, const XT *other) {
+  const size_t lds = 2 * sizeof(XT) * (size_t)sv.tl.cap;
+  int &grid = sv.tiles_grid[sizeof(XT) == 8 ? 0 : 1];
+  if (grid == 0) grid = spmv_tiles_grid<VT, XT, K>(sv, lds);
+  hipLaunchKernelGGL((k_spmv_tiles<VT, XT, K>), dim3(grid), dim3(kBlock), lds, sv.ctx->stream, sv.nbr->row_ptr,
+                     sv.nbr->col, val, xin, y, other, sv.part, sv.S, sv.tl);
+  return grid;
+}
+
 template <typename VT, typename XT>
-void launch_spmv(Solver &sv, const VT *val, const XT *xin, XT *y, const XT *other) {
-  hipStream_t sm = sv.ctx->stream;
-  if (sv.tiled)
-    hipLaunchKernelGGL((k_spmv_tiles<VT, XT>), dim3(kRedBlocks), dim3(kBlock), sizeof(XT) * sv.tl.cap, sm,
-                       sv.nbr->row_ptr, sv.nbr->col, val, xin, y, other, sv.part, sv.S, sv.tl);
-  else
-    hipLaunchKernelGGL((k_spmv_dot<VT, XT>), dim3(kRedBlocks), dim3(kBlock), 0, sm, sv.nbr->row_ptr, sv.nbr->col, val,
-                       xin, sv.n, y, other, sv.part, sv.S);
+int launch_spmv(Solver &sv, const VT *val, const XT *xin, XT *y, const XT *other) {
+  if (sv.tiled) {
+    const int k = (sv.tl.cap + kBlock - 1) / kBlock;
+    if (k <= 1) return launch_spmv_tiles<VT, XT, 1>(sv, val, xin, y, other);
+    if (k <= 2) return launch_spmv_tiles<VT, XT, 2>(sv, val, xin, y, other);
+    if (k <= 3) return launch_spmv_tiles<VT, XT, 3>(sv, val, xin, y, other);
+    if (k <= 4) return launch_spmv_tiles<VT, XT, 4>(sv, val, xin, y, other);
+    return launch_spmv_tiles<VT, XT, 8>(sv, val, xin, y, other);
+  }
+  hipLaunchKernelGGL((k_spmv_dot<VT, XT>), dim3(kRedBlocks), dim3(kBlock), 0, sv.ctx->stream, sv.nbr->row_ptr,
+                     sv.nbr->col, val, xin, sv.n, y, other, sv.part, sv.S);
+  return kRedBlocks;
 }
 
 gf_status read_scal(Solver &sv) {
@@ -471,11 +629,11 @@ gf_status bicgstab_iter(Solver &sv, const Vecs<VT, XT> &V) {
   const int64_t n = sv.n;
   ProfScope prof(sv.ctx, sizeof(VT) == 8 ? "bicgstab_iter_f64" : "bicgstab_iter_f32");
   hipLaunchKernelGGL((k_update_p<XT>), dim3(sv.grid_row), dim3(kBlock), 0, sm, V.r, V.v, V.dinv, n, V.p, V.phat, sv.S);
-  launch_spmv<VT, XT>(sv, V.val, V.phat, V.v, V.rhat);
-  hipLaunchKernelGGL((k_fin_spmv<0>), dim3(1), dim3(kFinThreads), 0, sm, sv.part, kRedBlocks, sv.S);
+  int nb = launch_spmv<VT, XT>(sv, V.val, V.phat, V.v, V.rhat);
+  hipLaunchKernelGGL((k_fin_spmv<0>), dim3(1), dim3(kFinThreads), 0, sm, sv.part, nb, sv.S);
   hipLaunchKernelGGL((k_update_s<XT>), dim3(sv.grid_row), dim3(kBlock), 0, sm, V.r, V.v, V.dinv, n, V.s, V.shat, sv.S);
-  launch_spmv<VT, XT>(sv, V.val, V.shat, V.t, V.s);
-  hipLaunchKernelGGL((k_fin_spmv<1>), dim3(1), dim3(kFinThreads), 0, sm, sv.part, kRedBlocks, sv.S);
+  nb = launch_spmv<VT, XT>(sv, V.val, V.shat, V.t, V.s);
+  hipLaunchKernelGGL((k_fin_spmv<1>), dim3(1), dim3(kFinThreads), 0, sm, sv.part, nb, sv.S);
   hipLaunchKernelGGL((k_update_xr<XT>), dim3(kRedBlocks), dim3(kBlock), 0, sm, V.phat, V.shat, V.s, V.t, V.rhat, n,
                      V.x, V.r, sv.part, sv.S);
   hipLaunchKernelGGL(k_fin_xr, dim3(1), dim3(kFinThreads), 0, sm, sv.part, kRedBlocks, sv.S);
@@ -551,16 +709,16 @@ extern "C" gf_status gf_poisson_solve(gf_ctx *ctx, const gf_particles *p, const 
   const bool mixed = prm.mixed != 0;
   Arena ar;
   const int nblk_row = (int)grid_for(n, kBlock);
-  std::vector<size_t> sz = {sizeof(double) * nnz, sizeof(double) * n, sizeof(double) * 2 * kRedBlocks + 64,
+  std::vector<size_t> sz = {sizeof(double) * (nnz + kQuadPad), sizeof(double) * n, sizeof(double) * 2 * kRedBlocks + 64,
                             sizeof(Scal), 64};
   for (int k = 0; k < 9; ++k) sz.push_back(sizeof(double) * n);
   if (mixed) {
-    sz.push_back(sizeof(float) * nnz);
+    sz.push_back(sizeof(float) * (nnz + kQuadPad));
     sz.push_back(sizeof(float) * n);
     for (int k = 0; k < 9; ++k) sz.push_back(sizeof(float) * n);
   }
   if ((st = ensure_scratch(ctx, arena_bytes(sz), &ar))) return st;
-  double *val64 = ar.take<double>(nnz);
+  double *val64 = ar.take<double>(nnz + kQuadPad);
   double *dinv64 = ar.take<double>(n);
   double *part = ar.take<double>(2 * kRedBlocks + 8);
   Scal *S = ar.take<Scal>(1);
@@ -569,7 +727,7 @@ extern "C" gf_status gf_poisson_solve(gf_ctx *ctx, const gf_particles *p, const 
   for (int k = 0; k < 9; ++k) vec64[k] = ar.take<double>(n);
   float *val32 = nullptr, *dinv32 = nullptr, *vec32[9] = {nullptr};
   if (mixed) {
-    val32 = ar.take<float>(nnz);
+    val32 = ar.take<float>(nnz + kQuadPad);
     dinv32 = ar.take<float>(n);
     for (int k = 0; k < 9; ++k) vec32[k] = ar.take<float>(n);
   }
