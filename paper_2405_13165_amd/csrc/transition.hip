@@ -10,10 +10,19 @@
 // ascending index order, the particles b of S_i mapped to it (b is in S_i
 // because neighbourhoods are symmetric).  Sums run in the same order as the
 // definition reads, so the lumped masses are reproducible.
+//
+// Each scan runs on a team of kTT lanes per particle (lane l takes the
+// entries k0 + l, k0 + l + kTT, ...), so a particle waits for about
+// |S|/kTT dependent loads instead of |S|.  The nearest wall particle is the
+// team minimum of (distance, index), which keeps the smallest index among
+// equal distances as an ascending scan does; the lumped sums walk each chunk
+// of kTT entries lane by lane, i.e. in ascending entry order.
 #include "internal.h"
 
 namespace {
 constexpr int kBlock = 256;
+constexpr int kTT = 8;  // lanes per particle in the neighbourhood scans
+static_assert(64 % kTT == 0, "a team lies within a wave");
 
 __global__ void __launch_bounds__(kBlock) k_owner(const double *__restrict__ x, const double *__restrict__ y,
                                                   const double *__restrict__ z, const int8_t *__restrict__ model,
@@ -21,28 +30,42 @@ __global__ void __launch_bounds__(kBlock) k_owner(const double *__restrict__ x, 
                                                   const int32_t *__restrict__ col, const uint8_t *__restrict__ flag,
                                                   int64_t n, uint8_t *__restrict__ keep, int32_t *__restrict__ owner) {
 #pragma clang fp contract(off)
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= n) return;
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t b = gt / kTT;
+  const int lane = (int)(gt % kTT);
+  if (b >= n) return;  // (the whole team)
   int32_t own = -1;
   if (model[b] == GF_MODEL_BULK && kind[b] != GF_KIND_WALL) {
-    bool cand = false;
-    for (int64_t k = row_ptr[b]; k < row_ptr[b + 1] && !cand; ++k) cand = flag[col[k]] == 1;
+    const int64_t k0 = row_ptr[b], k1 = row_ptr[b + 1];
+    int cand = 0;
+    for (int64_t k = k0 + lane; k < k1; k += kTT) cand |= flag[col[k]] == 1;
+    for (int o = kTT >> 1; o > 0; o >>= 1) cand |= __shfl_xor(cand, o, kTT);
     if (cand) {
       int32_t best = -1;
       double bestd = INFINITY;
       const double xb = x[b], yb = y[b], zb = z[b];
-      for (int64_t k = row_ptr[b]; k < row_ptr[b + 1]; ++k) {
+      for (int64_t k = k0 + lane; k < k1; k += kTT) {
         const int32_t j = col[k];
         if (kind[j] != GF_KIND_WALL || model[j] != GF_MODEL_BULK) continue;
         const double dx = x[j] - xb, dy = y[j] - yb, dz = z[j] - zb;
         const double d2 = (dx * dx + dy * dy) + dz * dz;
         if (d2 < bestd) { bestd = d2; best = j; }  // ascending j: ties keep the smaller index
       }
+      for (int o = kTT >> 1; o > 0; o >>= 1) {
+        const double od = __shfl_xor(bestd, o, kTT);
+        const int32_t oj = __shfl_xor(best, o, kTT);
+        if (oj >= 0 && (best < 0 || od < bestd || (od == bestd && oj < best))) {
+          bestd = od;
+          best = oj;
+        }
+      }
       if (best >= 0 && flag[best] == 1) own = best;
     }
   }
-  owner[b] = own;
-  keep[b] = own < 0 ? 1 : 0;
+  if (lane == 0) {
+    owner[b] = own;
+    keep[b] = own < 0 ? 1 : 0;
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) k_lump(const double *__restrict__ x, const double *__restrict__ y,
@@ -56,34 +79,55 @@ __global__ void __launch_bounds__(kBlock) k_lump(const double *__restrict__ x, c
                                                  double *__restrict__ phi_out, double *__restrict__ height_out,
                                                  double *__restrict__ diam_out) {
 #pragma clang fp contract(off)
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = gt / kTT;
+  const int lane = (int)(gt % kTT);
+  if (i >= n) return;  // (the whole team)
   if (flag[i] != 1) {
-    mass_out[i] = keep[i] ? mass[i] : 0.0;
-    rho_out[i] = rho[i];
-    phi_out[i] = phi[i];
-    height_out[i] = 0.0;
-    diam_out[i] = 0.0;
+    if (lane == 0) {
+      mass_out[i] = keep[i] ? mass[i] : 0.0;
+      rho_out[i] = rho[i];
+      phi_out[i] = phi[i];
+      height_out[i] = 0.0;
+      diam_out[i] = 0.0;
+    }
     return;
   }
   double m = mass[i], r = rho[i], p = phi[i], H = 0.0;
   int64_t cnt = 0;
   const double xi = x[i], yi = y[i], zi = z[i], a = nx[i], bb = ny[i], c = nz[i];
-  for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
-    const int32_t b = col[k];
-    if (owner[b] != (int32_t)i) continue;
-    m += mass[b];
-    r += rho[b];
-    p += phi[b];
-    const double dn = fabs((x[b] - xi) * a + (y[b] - yi) * bb + (z[b] - zi) * c);
-    H = fmax(H, dn);
-    ++cnt;
+  const int64_t k0 = row_ptr[i], k1 = row_ptr[i + 1];
+  for (int64_t kc = k0; kc < k1; kc += kTT) {
+    const int64_t k = kc + lane;
+    int hit = 0;
+    double mb = 0.0, rb = 0.0, pb = 0.0, db = 0.0;
+    if (k < k1) {
+      const int32_t b = col[k];
+      if (owner[b] == (int32_t)i) {
+        hit = 1;
+        mb = mass[b];
+        rb = rho[b];
+        pb = phi[b];
+        db = fabs((x[b] - xi) * a + (y[b] - yi) * bb + (z[b] - zi) * c);
+      }
+    }
+    for (int l = 0; l < kTT; ++l) {  // ascending entry order
+      if (__shfl(hit, l, kTT)) {
+        m += __shfl(mb, l, kTT);
+        r += __shfl(rb, l, kTT);
+        p += __shfl(pb, l, kTT);
+        H = fmax(H, __shfl(db, l, kTT));
+        ++cnt;
+      }
+    }
   }
-  mass_out[i] = m;
-  rho_out[i] = r / (double)(1 + cnt);
-  phi_out[i] = p / (double)(1 + cnt);
-  height_out[i] = H;
-  diam_out[i] = cbrt(6.0 * m / (3.14159265358979323846 * rho_out[i]));
+  if (lane == 0) {
+    mass_out[i] = m;
+    rho_out[i] = r / (double)(1 + cnt);
+    phi_out[i] = p / (double)(1 + cnt);
+    height_out[i] = H;
+    diam_out[i] = cbrt(6.0 * m / (3.14159265358979323846 * rho_out[i]));
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) k_keep32(const uint8_t *__restrict__ keep, int64_t n,
@@ -101,19 +145,17 @@ struct CloudIn {
   int64_t n;
 };
 
-// The new cloud: kept particles at pos[i]; flagged particles become film
-// particles with the data of the particles mapped onto them (ascending index
-// order, as in k_lump), the others are copied.
-__global__ void __launch_bounds__(kBlock) k_cloud_write(CloudIn c, const int64_t *__restrict__ row_ptr,
-                                                        const int32_t *__restrict__ col,
-                                                        const uint8_t *__restrict__ flag,
-                                                        const int32_t *__restrict__ owner,
-                                                        const uint8_t *__restrict__ keep,
-                                                        const int64_t *__restrict__ pos, NewOut o) {
-#pragma clang fp contract(off)
+// The new cloud: kept particles at pos[i].  k_cloud_copy copies every kept
+// particle that is not flagged; k_cloud_lump (a team per particle) turns the
+// flagged ones into film particles with the data of the particles mapped
+// onto them (ascending index order, as in k_lump).
+__global__ void __launch_bounds__(kBlock) k_cloud_copy(CloudIn c, const uint8_t *__restrict__ flag,
+                                                       const uint8_t *__restrict__ keep,
+                                                       const int64_t *__restrict__ pos, NewOut o) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= c.n || !keep[i]) return;
+  if (i >= c.n || !keep[i] || flag[i] == 1) return;
   const int64_t t = pos[i];
+  const bool film = c.model[i] == GF_MODEL_FILM;
   o.x[t] = c.x[i];
   o.y[t] = c.y[i];
   o.z[t] = c.z[i];
@@ -121,41 +163,82 @@ __global__ void __launch_bounds__(kBlock) k_cloud_write(CloudIn c, const int64_t
   o.ny[t] = c.ny[i];
   o.nz[t] = c.nz[i];
   if (o.src) o.src[t] = (int32_t)i;
-  if (flag[i] != 1) {
-    const bool film = c.model[i] == GF_MODEL_FILM;
-    o.h[t] = c.h[i];
-    o.model[t] = c.model[i];
-    o.kind[t] = c.kind[i];
-    o.mass[t] = c.mass[i];
-    o.rho[t] = c.rho[i];
-    for (int f = 0; f < c.nphi; ++f) o.phi[(int64_t)f * o.cap + t] = c.phi[(int64_t)f * c.n + i];
-    if (o.height) o.height[t] = (film && c.film_height) ? c.film_height[i] : 0.0;
-    if (o.diam) o.diam[t] = (film && c.diam) ? c.diam[i] : 0.0;
-    return;
-  }
+  o.h[t] = c.h[i];
+  o.model[t] = c.model[i];
+  o.kind[t] = c.kind[i];
+  o.mass[t] = c.mass[i];
+  o.rho[t] = c.rho[i];
+  for (int f = 0; f < c.nphi; ++f) o.phi[(int64_t)f * o.cap + t] = c.phi[(int64_t)f * c.n + i];
+  if (o.height) o.height[t] = (film && c.film_height) ? c.film_height[i] : 0.0;
+  if (o.diam) o.diam[t] = (film && c.diam) ? c.diam[i] : 0.0;
+}
+
+__global__ void __launch_bounds__(kBlock) k_cloud_lump(CloudIn c, const int64_t *__restrict__ row_ptr,
+                                                       const int32_t *__restrict__ col,
+                                                       const uint8_t *__restrict__ flag,
+                                                       const int32_t *__restrict__ owner,
+                                                       const uint8_t *__restrict__ keep,
+                                                       const int64_t *__restrict__ pos, NewOut o) {
+#pragma clang fp contract(off)
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = gt / kTT;
+  const int lane = (int)(gt % kTT);
+  if (i >= c.n || flag[i] != 1 || !keep[i]) return;  // (the whole team)
+  const int64_t t = pos[i];
   double m = c.mass[i], r = c.rho[i], H = 0.0;
   int64_t cnt = 0;
   const double xi = c.x[i], yi = c.y[i], zi = c.z[i], a = c.nx[i], bb = c.ny[i], cc = c.nz[i];
   const int64_t k0 = row_ptr[i], k1 = row_ptr[i + 1];
-  for (int64_t k = k0; k < k1; ++k) {
-    const int32_t b = col[k];
-    if (owner[b] != (int32_t)i) continue;
-    m += c.mass[b];
-    r += c.rho[b];
-    const double dn = fabs((c.x[b] - xi) * a + (c.y[b] - yi) * bb + (c.z[b] - zi) * cc);
-    H = fmax(H, dn);
-    ++cnt;
+  for (int64_t kc = k0; kc < k1; kc += kTT) {
+    const int64_t k = kc + lane;
+    int hit = 0;
+    double mb = 0.0, rb = 0.0, db = 0.0;
+    if (k < k1) {
+      const int32_t b = col[k];
+      if (owner[b] == (int32_t)i) {
+        hit = 1;
+        mb = c.mass[b];
+        rb = c.rho[b];
+        db = fabs((c.x[b] - xi) * a + (c.y[b] - yi) * bb + (c.z[b] - zi) * cc);
+      }
+    }
+    for (int l = 0; l < kTT; ++l) {  // ascending entry order
+      if (__shfl(hit, l, kTT)) {
+        m += __shfl(mb, l, kTT);
+        r += __shfl(rb, l, kTT);
+        H = fmax(H, __shfl(db, l, kTT));
+        ++cnt;
+      }
+    }
   }
   const double rho_new = r / (double)(1 + cnt);
   for (int f = 0; f < c.nphi; ++f) {
     const double *ph = c.phi + (int64_t)f * c.n;
     double acc = ph[i];
-    for (int64_t k = k0; k < k1; ++k) {
-      const int32_t b = col[k];
-      if (owner[b] == (int32_t)i) acc += ph[b];
+    for (int64_t kc = k0; kc < k1; kc += kTT) {
+      const int64_t k = kc + lane;
+      int hit = 0;
+      double vb = 0.0;
+      if (k < k1) {
+        const int32_t b = col[k];
+        if (owner[b] == (int32_t)i) {
+          hit = 1;
+          vb = ph[b];
+        }
+      }
+      for (int l = 0; l < kTT; ++l)
+        if (__shfl(hit, l, kTT)) acc += __shfl(vb, l, kTT);
     }
-    o.phi[(int64_t)f * o.cap + t] = acc / (double)(1 + cnt);
+    if (lane == 0) o.phi[(int64_t)f * o.cap + t] = acc / (double)(1 + cnt);
   }
+  if (lane != 0) return;
+  o.x[t] = c.x[i];
+  o.y[t] = c.y[i];
+  o.z[t] = c.z[i];
+  o.nx[t] = c.nx[i];
+  o.ny[t] = c.ny[i];
+  o.nz[t] = c.nz[i];
+  if (o.src) o.src[t] = (int32_t)i;
   o.h[t] = c.h_film ? c.h_film[i] : c.h[i];
   o.model[t] = GF_MODEL_FILM;
   o.kind[t] = GF_KIND_WALL;
@@ -190,10 +273,10 @@ extern "C" gf_status gf_transition_3d_to_2d_cloud(gf_ctx *ctx, const gf_particle
   int32_t *k32 = ar.take<int32_t>(n);
   int64_t *pos = ar.take<int64_t>(n + 1);
   int64_t *tmp = ar.take<int64_t>(scan_tmp_elems(n + 1));
-  const dim3 grid(grid_for(n, kBlock)), block(kBlock);
+  const dim3 grid(grid_for(n, kBlock)), tgrid(grid_for(n * kTT, kBlock)), block(kBlock);
   {
     ProfScope prof(ctx, "transition_cloud_owner");
-    hipLaunchKernelGGL(k_owner, grid, block, 0, ctx->stream, p->x, p->y, p->z, p->model, p->kind, nbr->row_ptr,
+    hipLaunchKernelGGL(k_owner, tgrid, block, 0, ctx->stream, p->x, p->y, p->z, p->model, p->kind, nbr->row_ptr,
                        nbr->col, flag, n, keep, owner);
     hipLaunchKernelGGL(k_keep32, grid, block, 0, ctx->stream, keep, n, k32);
     GF_LAUNCH_CHECK(ctx);
@@ -209,7 +292,8 @@ extern "C" gf_status gf_transition_3d_to_2d_cloud(gf_ctx *ctx, const gf_particle
   CloudIn c{p->x, p->y, p->z, p->nx, p->ny, p->nz, p->h, p->model, p->kind, mass, rho, phi, nphi,
             film_height, diam, h_film, n};
   ProfScope prof(ctx, "transition_cloud_write");
-  hipLaunchKernelGGL(k_cloud_write, grid, block, 0, ctx->stream, c, nbr->row_ptr, nbr->col, flag, owner, keep, pos,
+  hipLaunchKernelGGL(k_cloud_copy, grid, block, 0, ctx->stream, c, flag, keep, pos, new_out(out));
+  hipLaunchKernelGGL(k_cloud_lump, tgrid, block, 0, ctx->stream, c, nbr->row_ptr, nbr->col, flag, owner, keep, pos,
                      new_out(out));
   GF_LAUNCH_CHECK(ctx);
   return GF_OK;
@@ -227,12 +311,12 @@ extern "C" gf_status gf_transition_3d_to_2d(gf_ctx *ctx, const gf_particles *p, 
   if (!flag || !mass || !rho || !phi || !mass_out || !rho_out || !phi_out || !height_out || !diam_out || !keep_out ||
       !owner_out)
     return set_error(ctx, GF_EINVAL, "all arrays are required");
-  const dim3 grid(grid_for(p->n, kBlock)), block(kBlock);
+  const dim3 tgrid(grid_for(p->n * kTT, kBlock)), block(kBlock);
   ProfScope prof(ctx, "transition_3d_to_2d");
-  hipLaunchKernelGGL(k_owner, grid, block, 0, ctx->stream, p->x, p->y, p->z, p->model, p->kind, nbr->row_ptr, nbr->col,
+  hipLaunchKernelGGL(k_owner, tgrid, block, 0, ctx->stream, p->x, p->y, p->z, p->model, p->kind, nbr->row_ptr, nbr->col,
                      flag, p->n, keep_out, owner_out);
   GF_LAUNCH_CHECK(ctx);
-  hipLaunchKernelGGL(k_lump, grid, block, 0, ctx->stream, p->x, p->y, p->z, p->nx, p->ny, p->nz, nbr->row_ptr,
+  hipLaunchKernelGGL(k_lump, tgrid, block, 0, ctx->stream, p->x, p->y, p->z, p->nx, p->ny, p->nz, nbr->row_ptr,
                      nbr->col, flag, owner_out, keep_out, mass, rho, phi, p->n, mass_out, rho_out, phi_out,
                      height_out, diam_out);
   GF_LAUNCH_CHECK(ctx);
