@@ -119,7 +119,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the stencil path runs on a single MI355X "
-              "(multi-GPU sharding is described in DESIGN.md but not built); use --gpus 1",
+              "(sharding over several GPUs is not built); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 
@@ -379,7 +379,8 @@ def main():
         del nbe, pe
         result["rows"] = rows
         result["rows_kernels_us"] = kern
-        # algorithmic bytes of each row (per particle / per neighbour entry)
+        # algorithmic bytes of each row: per particle (N) and per neighbour entry (nnz) the bytes a
+        # row must read or write at least once
         film_nnz = float((np.diff(rp)[d["model"] == 1]).sum())
         row_bytes = {"build_neighbours": 4.0 * nnz + 41.0 * N, "classify_pca": 4.0 * nnz + 106.0 * N,
                      "apply": 18.0 * nnz + 40.0 * N, "transition": 4.0 * nnz + 48.0 * N,
