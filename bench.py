@@ -58,6 +58,37 @@ def parse():
 KERNEL_SOURCES = ("weights.hip", "stencil_common.h", "internal.h", "apply.hip")
 
 
+def measure_hbm(dev):
+    """Achievable HBM bandwidth of this GPU, for reference beside the published
+    peak: a 1 GiB device-to-device copy (1 GiB read + 1 GiB written) and a
+    4 GiB streaming read (a sum), each the mean of 10 runs between events after
+    2 warm-ups.  Outside every timed region; the buffers are freed after."""
+    import torch
+    x = torch.ones(1 << 29, dtype=torch.float64, device=dev)
+    y = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+
+    def ms(fn):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 10
+
+    copy_ms = ms(lambda: y.copy_(x[: y.numel()]))
+    read_ms = ms(lambda: x.sum())
+    out = {"copy_GBs": round(2 * 8 * y.numel() / (copy_ms * 1e-3) / 1e9, 1),
+           "read_GBs": round(8 * x.numel() / (read_ms * 1e-3) / 1e9, 1),
+           "method": "1 GiB device copy (read + write) and 4 GiB sum, torch ops timed with events"}
+    del x, y
+    torch.cuda.empty_cache()
+    return out
+
+
 def measured_traffic(launch, team):
     """HBM bytes per launch of `launch` at team size `team`, from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE summary (already scaled by the copy
@@ -319,6 +350,9 @@ def main():
         "kernels_plain": {k: {"launches": c, "avg_us": 1000.0 * t / c} for k, (c, t) in prof_plain.items()},
         "roofline": roof,
     }
+    hbm_meas = measure_hbm(ctx.device)
+    result["hbm_measured"] = hbm_meas
+    roof["other_roof"]["hbm_frac_of_measured_copy"] = round(gbs / hbm_meas["copy_GBs"], 4)
 
     # ---- other hot-path steps (timed once each after a warm-up call)
     if not args.no_rows:
@@ -393,7 +427,8 @@ def main():
             if us > 0:
                 roof_rows[key] = {"kernel_us": round(us, 1), "algorithmic_bytes": byts,
                                   "GBs": round(byts / (us * 1e-6) / 1e9, 1),
-                                  "hbm_frac": round(byts / (us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4)}
+                                  "hbm_frac": round(byts / (us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4),
+                                  "frac_of_measured_copy": round(byts / (us * 1e-6) / 1e9 / hbm_meas["copy_GBs"], 4)}
         result["rows_roofline"] = roof_rows
         result["flags"] = {"bulk_to_film": int((flag == 1).sum().item()), "film_to_bulk": int((flag == 2).sum().item())}
 
@@ -435,7 +470,8 @@ def main():
                     byts = 2.0 * ps_nnz * (vb + 2) + 26.0 * vb * ps_n
                     rec[name] = {"iterations": cnt, "avg_us": round(it_s * 1e6, 1),
                                  "algorithmic_bytes": byts, "GBs": round(byts / it_s / 1e9, 1),
-                                 "hbm_frac": round(byts / it_s / 1e9 / PEAK_HBM_GBS, 4)}
+                                 "hbm_frac": round(byts / it_s / 1e9 / PEAK_HBM_GBS, 4),
+                                 "frac_of_measured_copy": round(byts / it_s / 1e9 / hbm_meas["copy_GBs"], 4)}
             ps["mixed" if mixed else "plain_f64"] = rec
             print(f"[bench] poisson mixed={mixed}: {el:.3f}s {rec}", file=sys.stderr, flush=True)
         result["poisson"] = {"n": ps_n, "nnz": ps_nnz, **ps}
