@@ -2,7 +2,8 @@
 times (autotuned team sizes, batched FP32 stencils), against the FP64 oracle.
 
  - mixed bulk/film cloud, 503,944 particles: every neighbour list, every
-   stored stencil and every applied value;
+   stored stencil and every applied value; every PCA output and flag, and
+   every output of the transition with all bulk wall particles flagged;
  - jet impact, 2.0M particles with uneven supports (13..228 neighbours):
    every neighbour list, stencils of 20,000 sampled rows;
  - differentiation cube, 10^6 particles: gradients with respect to field
@@ -72,6 +73,52 @@ def test_full_mixed_workload(ctx, g):
     # fused call, stencils not stored
     _, yf = g.gfdm_weights_apply(ctx, p, nb, u, wtype=g.GF_F32, store_weights=False)
     assert (yf - y32).abs().max().item() <= 1e-9 * (y32.abs().max().item() + 1)
+
+
+def test_full_mixed_pca_and_transition(ctx, g):
+    # a3 and a7 on the full mixed cloud as the bench times them: PCA with the
+    # cross-model smoothing lists, film heights and h_3D; the transition with
+    # every bulk wall particle flagged (which deletes the layers above the
+    # bottom).  Every output against the oracle.
+    import math
+    print("\n[full] mixed 503,944: PCA + transition", flush=True)
+    d = W.mixed_block_film()
+    n = d["x"].size
+    p = g.Particles.from_dict(ctx, d)
+    nb = g.build_neighbours(ctx, p)
+    xnb = g.build_neighbours(ctx, p, cross_model=True)
+    rp, col = oracle.neighbours(d)
+    xr, xc = oracle.neighbours(d, cross=True)
+    lam, w3, eps, flag = g.classify_pca(ctx, p, nb, xnb, film_height=d["film_height"], h3d=d["h3d"])
+    lam_o, w3_o, eps_o = oracle.pca(d, rp, col)
+    flag_o = oracle.classify(d, rp, col, eps_o, w3_o, cross=(xr, xc), film_height=d["film_height"], h3d=d["h3d"])
+    lam, w3, eps, flag = _np(lam), _np(w3), _np(eps), _np(flag)
+    scale = np.maximum(lam_o[:, :1], 1e-300)
+    assert np.all(np.abs(lam - lam_o) <= 1e-10 * scale)
+    fin = np.isfinite(eps_o)
+    assert np.array_equal(np.isfinite(eps), fin)
+    assert np.all(np.abs(eps[fin] - eps_o[fin]) <= 1e-10)
+    gap = (lam_o[:, 1] - lam_o[:, 2]) > 1e-8 * lam_o[:, 0]
+    assert np.all(np.abs((w3 * w3_o).sum(1))[gap] >= 1 - 1e-10)
+    # flags: identical away from the thresholds (where rounding may decide)
+    nd = np.abs(w3_o[:, 0] * d["nx"] + w3_o[:, 1] * d["ny"] + w3_o[:, 2] * d["nz"])
+    band = (np.abs(eps_o - oracle.EPS_LAMBDA_MAX) <= 1e-8) | (np.abs(nd - math.cos(oracle.THETA_STAR)) <= 1e-8)
+    print(f"[full] flags {np.bincount(flag_o, minlength=3).tolist()}, {int(band.sum())} in the threshold band",
+          flush=True)
+    assert np.array_equal(flag[~band], flag_o[~band])
+    tflag = ((d["model"] == 0) & (d["kind"] == W.WALL)).astype(np.uint8)
+    mass = np.ones(n)
+    rho = np.full(n, 1000.0)
+    phi, *_ = W.test_field(d["x"], d["y"], d["z"])
+    t = g.transition_3d_to_2d(ctx, p, nb, tflag, mass, rho, phi)
+    t_o = oracle.transition_3d_to_2d(d, rp, col, tflag, mass, rho, phi)
+    for k in ("keep", "owner", "mass", "rho", "phi", "height"):
+        assert np.array_equal(_np(t[k]), t_o[k]), k
+    assert np.allclose(_np(t["diam"]), t_o["diam"], rtol=1e-15, atol=0)
+    deleted = int((t_o["keep"] == 0).sum())
+    print(f"[full] transition: {int(tflag.sum())} flagged, {deleted} deleted", flush=True)
+    assert deleted > 0
+    assert abs(_np(t["mass"]).sum() - mass.sum()) <= 1e-12 * mass.sum()
 
 
 def test_full_jet_uneven(ctx, g):
