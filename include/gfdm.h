@@ -258,7 +258,8 @@ void gf_solve_params_default(gf_solve_params *p);
 typedef struct {
   int outer_its;        /* refinement steps (1 in plain mode) */
   int inner_its_total;  /* BiCGStab iterations in total */
-  int restarts;         /* breakdown restarts */
+  int restarts;         /* restarts from the true residual: after a breakdown, or after a
+                           half step that solved the system (t = A shat = 0) */
   int converged;
   double final_rel_res; /* ||b - A x|| / ||b|| in FP64 at exit */
 } gf_solve_stats;

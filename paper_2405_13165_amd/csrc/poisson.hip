@@ -31,7 +31,7 @@ static_assert(kBlock / kTeam == kTileRows, "one team per row of a neighbour tile
 struct Scal {
   double rho, rho_old, alpha, omega, rv, ts, tt, rr, bb;
   int breakdown;
-  int pad;
+  int half;  // the half step solved the system (t = A shat = 0)
 };
 
 // ---------------------------------------------------------------- reductions
@@ -174,6 +174,7 @@ __global__ void __launch_bounds__(kFinThreads) k_fin_residual(const double *part
     S->alpha = 1.0;
     S->omega = 1.0;
     S->breakdown = 0;
+    S->half = 0;
   }
 }
 
@@ -205,6 +206,7 @@ __global__ void __launch_bounds__(kFinThreads) k_fin_inner_init(const double *pa
   S->alpha = 1.0;
   S->omega = 1.0;
   S->breakdown = 0;
+  S->half = 0;
 }
 
 template <typename XT>
@@ -470,9 +472,18 @@ __global__ void __launch_bounds__(kFinThreads) k_fin_spmv(const double *part, in
   } else {
     S->ts = res[0];
     S->tt = res[1];
-    if (res[1] == 0.0 || !isfinite(res[1])) S->breakdown = 2;
-    else S->omega = res[0] / res[1];
-    if (S->omega == 0.0) S->breakdown = 3;
+    if (res[1] == 0.0) {
+      // t = A shat = 0, so s = 0 for a nonsingular A: x + alpha phat already
+      // solves the system.  Take that step (omega = 0) and restart from the
+      // true residual afterwards (code 5).
+      S->omega = 0.0;
+      S->half = 1;
+    } else if (!isfinite(res[1])) {
+      S->breakdown = 2;
+    } else {
+      S->omega = res[0] / res[1];
+      if (S->omega == 0.0) S->breakdown = 3;
+    }
   }
 }
 
@@ -515,7 +526,8 @@ __global__ void __launch_bounds__(kFinThreads) k_fin_xr(const double *part, int 
   S->rho_old = S->rho;
   S->rho = res[0];
   S->rr = res[1];
-  if (res[0] == 0.0 || !isfinite(res[0])) S->breakdown = 4;
+  if (S->half) S->breakdown = 5;
+  else if (res[0] == 0.0 || !isfinite(res[0])) S->breakdown = 4;
 }
 
 __global__ void __launch_bounds__(kBlock) k_add_f32(double *__restrict__ x, const float *__restrict__ d, int64_t n) {

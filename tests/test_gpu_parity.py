@@ -243,6 +243,40 @@ def test_weights_degenerate_rows(ctx, g):
         assert np.all(_np(w) == 0)
 
 
+def test_tiny_clouds_through_the_path(ctx, g):
+    # one and three bulk wall particles (rows shorter than the 10 monomials):
+    # neighbourhoods and PCA as the oracle; zero stencils with status 3 on
+    # every path, zero applications; identity (Dirichlet) rows solve to the
+    # right-hand side; a transition with nothing flagged keeps everything.
+    # An empty cloud is rejected.
+    for nn in (1, 3):
+        d = dict(x=0.01 * np.arange(nn), y=np.zeros(nn), z=np.zeros(nn), h=np.full(nn, 0.05),
+                 model=np.zeros(nn, np.int8), kind=np.full(nn, W.WALL, np.int8), nx=np.zeros(nn),
+                 ny=np.zeros(nn), nz=np.ones(nn))
+        p, nb, rp, col = _nbr_equal(ctx, g, d)
+        lam, w3, eps, flag = g.classify_pca(ctx, p, nb)
+        lam_o, w3_o, eps_o = oracle.pca(d, rp, col)
+        assert np.allclose(_np(lam), lam_o, rtol=1e-12, atol=0)
+        fin = np.isfinite(eps_o)
+        assert np.array_equal(np.isfinite(_np(eps)), fin) and np.allclose(_np(eps)[fin], eps_o[fin], atol=1e-12)
+        assert np.array_equal(_np(flag), oracle.classify(d, rp, col, eps_o, w3_o))
+        u = torch.as_tensor(np.arange(nn, dtype=np.float64) + 1.0, device=ctx.device)
+        for prec, wt in ((g.GF_PLAIN_F64, g.GF_F64), (g.GF_BATCHED, g.GF_F64), (g.GF_BATCHED, g.GF_F32)):
+            status = torch.empty(nn, dtype=torch.int8, device=ctx.device)
+            w = g.gfdm_weights(ctx, p, nb, prec, wt, status=status)
+            assert np.all(_np(status) == 3) and np.all(_np(w) == 0)
+            assert np.all(_np(g.apply_stencil(ctx, nb, w, u)) == 0)
+        w64 = g.gfdm_weights(ctx, p, nb, g.GF_BATCHED, g.GF_F64)
+        x, st = g.poisson_solve(ctx, p, nb, w64, np.ones(nn, np.int8), u)
+        assert st["converged"] == 1 and np.allclose(_np(x), _np(u), rtol=1e-14, atol=0)
+        t = g.transition_3d_to_2d(ctx, p, nb, np.zeros(nn, np.uint8), np.ones(nn), np.full(nn, 1000.0), _np(u))
+        assert np.all(_np(t["keep"]) == 1) and np.array_equal(_np(t["mass"]), np.ones(nn))
+    empty = dict(x=np.zeros(0), y=np.zeros(0), z=np.zeros(0), h=np.zeros(0), model=np.zeros(0, np.int8))
+    with pytest.raises(g.GfdmError) as e:
+        g.build_neighbours(ctx, _dev(ctx, empty))
+    assert e.value.status == g.GF_EINVAL
+
+
 # ------------------------------------------------------------------ application
 def _apply_err(y, y_o, rp, col, w_o, u):
     # condition-aware: |y - y_ref| / max_i sum_j |c_ij (u_j - u_i)|
