@@ -277,6 +277,47 @@ def test_tiny_clouds_through_the_path(ctx, g):
     assert e.value.status == g.GF_EINVAL
 
 
+def test_film_only_cloud(ctx, g):
+    # only film particles (no 3D grids, no bulk launch units): neighbour
+    # lists (same and cross model), PCA and the film flags of Eq. (2Dto3Dcond),
+    # stencils and their application, the film height, and the 2D->3D
+    # transition of the flagged particles, all against the oracle
+    m = W.mixed_block_film(factor=4)
+    sel = np.nonzero(m["model"] == 1)[0]
+    d = {k: (v[sel] if isinstance(v, np.ndarray) and v.shape[:1] == m["x"].shape else v) for k, v in m.items()}
+    n = sel.size
+    H = d["h3d"] * np.where(np.arange(n) % 3 == 0, 1.5, 0.5)  # every third particle thick enough for 3D
+    p, nb, rp, col = _nbr_equal(ctx, g, d)
+    xnb = g.build_neighbours(ctx, p, cross_model=True)
+    xr, xc = oracle.neighbours(d, cross=True)
+    assert np.array_equal(_np(xnb.export()[1]), xc)
+    lam, w3, eps, flag = g.classify_pca(ctx, p, nb, xnb, film_height=H, h3d=d["h3d"])
+    lam_o, w3_o, eps_o = oracle.pca(d, rp, col)
+    flag_o = oracle.classify(d, rp, col, eps_o, w3_o, cross=(xr, xc), film_height=H, h3d=d["h3d"])
+    assert np.all(np.abs(_np(lam) - lam_o) <= 1e-10 * np.maximum(lam_o[:, :1], 1e-300))
+    assert np.array_equal(_np(flag), flag_o) and (flag_o == 2).sum() > 0
+    w_o, st_o, _ = oracle.gfdm_weights(d, rp, col)
+    f, *_ = W.test_field(d["x"], d["y"], d["z"])
+    u = torch.as_tensor(f, device=ctx.device)
+    y_o = oracle.apply(rp, col, w_o, f)
+    for wt, tol in ((g.GF_F64, 1e-10), (g.GF_F32, 1e-6)):
+        status = torch.empty(n, dtype=torch.int8, device=ctx.device)
+        w = g.gfdm_weights(ctx, p, nb, g.GF_BATCHED, wt, status=status)
+        assert _status_match(_np(status), st_o)
+        assert oracle.operator_error(_np(w).astype(np.float64), w_o, rp).max() <= tol
+        assert _apply_err(_np(g.apply_stencil(ctx, nb, w, u)), y_o, rp, col, w_o, f) <= tol
+    Hf = _np(g.film_height(ctx, p, nb, d["diam"]))
+    Hf_o = oracle.film_height(d, rp, col, d["diam"])
+    assert np.all(np.abs(Hf - Hf_o) <= 1e-13 * Hf_o)
+    sel2 = np.nonzero(flag_o == 2)[0]
+    o = g.transition_2d_to_3d(ctx, p, _np(flag), H, d["h3d"], d["mass"], d["rho"])
+    o_o = oracle.transition_2d_to_3d(d, sel2, H, d["h3d"], d["mass"], d["rho"])
+    assert o["x"].shape[0] == o_o["x"].size > 2 * sel2.size
+    for k in ("model", "kind", "src", "x", "y", "z", "h", "nx", "ny", "nz", "mass", "rho", "height"):
+        assert np.array_equal(_np(o[k]), o_o[k]), k
+    assert np.all(np.abs(_np(o["diam"]) - o_o["diam"]) <= 1e-15 * o_o["diam"])
+
+
 # ------------------------------------------------------------------ application
 def _apply_err(y, y_o, rp, col, w_o, u):
     # condition-aware: |y - y_ref| / max_i sum_j |c_ij (u_j - u_i)|
