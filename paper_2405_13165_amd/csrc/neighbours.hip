@@ -183,27 +183,49 @@ __global__ void __launch_bounds__(kBlock) k_fill_i32(int32_t *a, int64_t n, int3
     a[i] = v;
 }
 
-// key[i]: cell of particle i; counts[k]: particles per cell; slot_count[s]:
-// particles per grid
+// key[i]: cell of particle i; counts[k]: particles per cell
 __global__ void __launch_bounds__(kBlock) k_keys(const double *__restrict__ x, const double *__restrict__ y,
                                                  const double *__restrict__ z, const double *__restrict__ h,
                                                  const int8_t *__restrict__ model, int64_t n, Grid g,
                                                  int32_t *__restrict__ key, int32_t *__restrict__ slot,
-                                                 int32_t *__restrict__ counts, int32_t *__restrict__ slot_count) {
+                                                 int32_t *__restrict__ counts) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int s = i < n ? slot_of(g, model[i], h[i]) : -1;
-  // one atomic per wave and grid
-  for (int q = 0; q < g.nslots; ++q) {
-    const unsigned long long mask = __ballot(s == q);
-    if ((threadIdx.x & 63) == 0 && mask) atomicAdd(&slot_count[q], __popcll(mask));
-  }
   if (i >= n) return;
+  const int s = slot_of(g, model[i], h[i]);
   int cx = cell_of(x[i], g.lo[s][0], g.inv_edge[s], g.dim[s][0]);
   int cy = cell_of(y[i], g.lo[s][1], g.inv_edge[s], g.dim[s][1]);
   int cz = cell_of(z[i], g.lo[s][2], g.inv_edge[s], g.dim[s][2]);
   int32_t k = (int32_t)(g.base[s] + morton(cx, cy, cz, g.bits[s][0], g.bits[s][1], g.bits[s][2]));
   key[i] = k;
-  slot[i] = atomicAdd(&counts[k], 1);
+  // Slot within the cell.  Neighbouring particles mostly share a cell, and
+  // 64 atomics on one counter serialise, so the lanes of the wave with the
+  // same cell share one atomic: the lowest of them reserves their count and
+  // each takes base + its rank among them.  (The order within a cell is
+  // re-sorted later; only the set of slots 0..count-1 matters.)
+  const int lane = threadIdx.x & 63;
+  unsigned long long todo = __ballot(1);
+  int32_t mine = 0;
+  while (todo) {
+    const int leader = __builtin_ctzll(todo);
+    const int32_t lk = __shfl(k, leader, 64);
+    const unsigned long long same = __ballot(k == lk) & todo;
+    int32_t base = 0;
+    if (lane == leader) base = atomicAdd(&counts[lk], (int32_t)__popcll(same));
+    base = __shfl(base, leader, 64);
+    if ((same >> lane) & 1ull) mine = base + (int32_t)__popcll(same & ((1ull << lane) - 1ull));
+    todo &= ~same;
+  }
+  slot[i] = mine;
+}
+
+// particles per grid from the scanned cell counts (the cells of a grid are
+// one key range; cell_start[nkeys] = n)
+__global__ void k_slot_count(const int32_t *__restrict__ cell_start, Grid g, int32_t *__restrict__ slot_count) {
+  const int q = threadIdx.x;
+  if (q < g.nslots) {
+    const int64_t e = (q + 1 < g.nslots) ? g.base[q + 1] : g.nkeys;
+    slot_count[q] = cell_start[e] - cell_start[g.base[q]];
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) k_scatter(const int32_t *__restrict__ key, const int32_t *__restrict__ slot,
@@ -1212,9 +1234,10 @@ extern "C" gf_status gf_build_neighbours_rows(gf_ctx *ctx, const gf_particles *p
   hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(K + 1, kBlock)), dim3(kBlock), 0, sm, cell_start, K + 1, 0);
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, sm, small, (int64_t)32, 0);
   hipLaunchKernelGGL(k_keys, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, p->x, p->y, p->z, p->h, p->model, n, g,
-                     key, slot, cell_start, slot_count);
+                     key, slot, cell_start);
   if (hipGetLastError() != hipSuccess) return fail(set_error(ctx, GF_EHIP, "key kernel launch failed"));
   if ((st = scan_i32_to_i32(ctx, cell_start, cell_start, K, tmp32))) return fail(st);
+  hipLaunchKernelGGL(k_slot_count, dim3(1), dim3(64), 0, sm, cell_start, g, slot_count);
   hipLaunchKernelGGL(k_scatter, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, key, slot, cell_start, n, nb->order);
   hipLaunchKernelGGL(k_cell_heads, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, nb->order, key, n, head);
   if ((st = scan_i32_to_i32(ctx, head, cpos, n, tmpg))) return fail(st);
