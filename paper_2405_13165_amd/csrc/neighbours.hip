@@ -625,6 +625,34 @@ __device__ inline void sort_net(int32_t &v0, int32_t &v1, int lane) {
   }
 }
 
+// the bitonic network for 256 elements, four per lane (position lane + 64 r
+// in v[r]): distances 128 and 64 compare registers of one lane, shorter ones
+// exchange through the wave
+__device__ inline void sort_net256(int32_t v[4], int lane) {
+  auto cx = [](int32_t &a, int32_t &b, int t, int k) {  // a at position t, b at t + distance
+    const bool up = (t & k) == 0;
+    const int32_t lo = min(a, b), hi = max(a, b);
+    a = up ? lo : hi;
+    b = up ? hi : lo;
+  };
+#pragma unroll
+  for (int k = 2; k <= 256; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      if (j == 128) {
+        cx(v[0], v[2], lane, k);
+        cx(v[1], v[3], lane + 64, k);
+      } else if (j == 64) {
+        cx(v[0], v[1], lane, k);
+        cx(v[2], v[3], lane + 128, k);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = bitonic_pick(v[r], __shfl_xor(v[r], j, 64), lane + 64 * r, j, k);
+      }
+    }
+  }
+}
+
 // STAGED: row i is read from stage[i * kStage ...] (the count pass's copy)
 // and written, sorted, to its CSR place; otherwise it is sorted in place.
 template <bool LONG, bool STAGED>
@@ -645,30 +673,42 @@ __global__ void __launch_bounds__(kSortBlock) k_row_sort(const int64_t *__restri
     auto src = [&](int r) -> const int32_t * {
       return STAGED ? stage + (i0 + r) * (int64_t)kStage : col + readlane64(rb, r);
     };
-    auto fetch = [&](int r, int32_t &a0, int32_t &a1) {
+    // rows of up to kRegRow entries are held in registers (NV per lane)
+    constexpr int NV = LONG ? 4 : 2;
+    constexpr int kRegRow = 64 * NV;
+    auto fetch = [&](int r, int32_t a[NV]) {
       const int32_t *sr = src(r);
       const int len = __builtin_amdgcn_readlane(rl, r);
-      a0 = (len <= 128 && lane < len) ? sr[lane] : 0x7fffffff;
-      a1 = (len <= 128 && lane + 64 < len) ? sr[lane + 64] : 0x7fffffff;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) a[q] = (len <= kRegRow && lane + 64 * q < len) ? sr[lane + 64 * q] : 0x7fffffff;
     };
-    int32_t v0, v1;
-    fetch(0, v0, v1);
+    int32_t v[NV];
+    fetch(0, v);
     for (int r = 0; r < nr; ++r) {
       const int64_t b = readlane64(rb, r);
       const int len = __builtin_amdgcn_readlane(rl, r);
-      int32_t n0 = 0x7fffffff, n1 = 0x7fffffff;
-      if (r + 1 < nr) fetch(r + 1, n0, n1);
+      int32_t nx[NV];
+#pragma unroll
+      for (int q = 0; q < NV; ++q) nx[q] = 0x7fffffff;
+      if (r + 1 < nr) fetch(r + 1, nx);
       if (STAGED && len == 1) {
-        if (lane == 0) col[b] = v0;
+        if (lane == 0) col[b] = v[0];
       } else if (len > 1 && len <= 128) {
-        if (len <= 8) sort_net<8>(v0, v1, lane);
-        else if (len <= 16) sort_net<16>(v0, v1, lane);
-        else if (len <= 32) sort_net<32>(v0, v1, lane);
-        else if (len <= 64) sort_net<64>(v0, v1, lane);
-        else sort_net<128>(v0, v1, lane);
-        if (lane < len) col[b + lane] = v0;
-        if (lane + 64 < len) col[b + lane + 64] = v1;
-      } else if (LONG && len > 128) {
+        if (len <= 8) sort_net<8>(v[0], v[1], lane);
+        else if (len <= 16) sort_net<16>(v[0], v[1], lane);
+        else if (len <= 32) sort_net<32>(v[0], v[1], lane);
+        else if (len <= 64) sort_net<64>(v[0], v[1], lane);
+        else sort_net<128>(v[0], v[1], lane);
+        if (lane < len) col[b + lane] = v[0];
+        if (lane + 64 < len) col[b + lane + 64] = v[1];
+      } else if (LONG && len > 128 && len <= kRegRow) {
+        if constexpr (LONG) {
+          sort_net256(v, lane);
+#pragma unroll
+          for (int q = 0; q < NV; ++q)
+            if (lane + 64 * q < len) col[b + lane + 64 * q] = v[q];
+        }
+      } else if (LONG && len > kRegRow) {
         int32_t *bw = sort_buf + w * kMaxRow;
         const int32_t *sr = src(r);
         int P = 1;
@@ -690,8 +730,8 @@ __global__ void __launch_bounds__(kSortBlock) k_row_sort(const int64_t *__restri
         for (int t = lane; t < len; t += 64) col[b + t] = bw[t];
         wave_fence();
       }
-      v0 = n0;
-      v1 = n1;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) v[q] = nx[q];
     }
   }
 }
