@@ -290,7 +290,7 @@ def main():
     else:
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(frac_hbm, 4), "traffic": None}
-    team_dom = teams["weights"][4 * m_dom + (2 if b_dom == "tiles" else 3)]
+    team_dom = teams["fused"][4 * m_dom + (2 if b_dom == "tiles" else 3)]
     traffic, traffic_src = measured_traffic(dom, team_dom)
     roof["traffic"] = round(traffic) if traffic is not None else None
     if traffic is not None:
@@ -563,7 +563,7 @@ def main():
         dj = W.jet_impact()
         pj = g.Particles.from_dict(ctx, dj)
         nbj = g.build_neighbours(ctx, pj)
-        g.autotune(ctx, pj, nbj, g.GF_F32)
+        teams_j = g.autotune(ctx, pj, nbj, g.GF_F32)
         uj = torch.as_tensor(W.test_field(dj["x"], dj["y"], dj["z"])[0], device=ctx.device)
         wj = torch.empty((nbj.nnz, 4), dtype=torch.float32, device=ctx.device)
         yj = torch.empty((4, pj.n), dtype=torch.float64, device=ctx.device)
@@ -575,7 +575,21 @@ def main():
         prof_j = ctx.profile_read()
         ctx.profile(False)
         counts = np.bincount(stj.cpu().numpy().astype(np.int64), minlength=4)
+        # neighbour builds (same and cross model), wall time of one build after a warm-up
+        build_ms = {}
+        for cross in (False, True):
+            g.build_neighbours(ctx, pj, cross_model=cross).close()
+            best = float("inf")
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                nbx = g.build_neighbours(ctx, pj, cross_model=cross)
+                torch.cuda.synchronize()
+                best = min(best, (time.perf_counter() - t0) * 1e3)
+                nbx.close()
+            build_ms["cross_model" if cross else "same_model"] = round(best, 3)
         result["jet"] = {"n": pj.n, "nnz": nbj.nnz, "max_row": nbj.max_row, "ms_per_step": ms_j,
+                         "build_neighbours_ms": build_ms, "team_sizes": teams_j,
                          "value": pj.n / (ms_j * 1e-3), "unit": "particles/s",
                          "status_counts": {"ok": int(counts[0]), "qr_fallback": int(counts[1]),
                                            "rank_deficient": int(counts[2]), "too_few": int(counts[3])},

@@ -212,11 +212,13 @@ gf_status gf_apply_stencil(gf_ctx *ctx, const gf_nbr *nbr, gf_dtype wtype, const
  * times the stencil kernel (weights of type wtype) with teams of 4, 8 and 16
  * lanes per particle and the application kernel with 4..64 lanes (median of
  * three runs each) and keeps the fastest team size in ctx; later calls on ctx
- * use it.  Allocates temporary buffers and synchronises.  team_out (host,
- * may be NULL) receives 16 ints indexed by (model, band): the stencil team
- * sizes (bulk bands 0-3, film bands 0-3; the tiled unit of a model reports
- * in band 2, bands 0-1 keep their previous values), then those of the
- * application kernel in the same layout. */
+ * use it.  The fused kernel of gf_gfdm_weights_apply (stencils stored and
+ * applied to a field) is tuned on its own.  Allocates temporary buffers and
+ * synchronises.  team_out (host, may be NULL) receives 24 ints indexed by
+ * (model, band): the stencil team sizes (bulk bands 0-3, film bands 0-3; the
+ * tiled unit of a model reports in band 2, bands 0-1 keep their previous
+ * values), then those of the application kernel, then those of the fused
+ * kernel, in the same layout. */
 gf_status gf_autotune(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr, gf_dtype wtype, int *team_out);
 
 /* Weights and application in one pass: computes the stencils exactly as

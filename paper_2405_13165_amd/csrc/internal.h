@@ -26,6 +26,7 @@ struct gf_ctx {
   // team sizes (lanes per particle) of the batched stencil and application
   // kernels per (model, neighbour-count band); set by gf_autotune
   int wteam[2][4] = {{8, 8, 8, 16}, {8, 8, 8, 16}};
+  int fteam[2][4] = {{8, 8, 8, 16}, {8, 8, 8, 16}};  // fused stencil + application kernel
   int ateam[2][4] = {{4, 8, 8, 16}, {4, 8, 8, 16}};
   // LDS staging limit of the tile kernels (gf_set_tile_capacity); 0 = their own
   int tile_cap = 0;
@@ -97,7 +98,7 @@ constexpr int kQuadPad = 4;
 
 // Launch units of the batched kernels: per model, the tiled rows (bands
 // 0..kTileBand) and each untiled band.  Team sizes live in
-// ctx->wteam/ateam[model][band] (band = kTileBand for the tiled unit).
+// ctx->wteam/fteam/ateam[model][band] (band = kTileBand for the tiled unit).
 // staging capacity of a tile kernel with its own limit `own`
 inline int tile_capacity(const gf_ctx *ctx, int own) { return (ctx && ctx->tile_cap > 0 && ctx->tile_cap < own) ? ctx->tile_cap : own; }
 

@@ -1141,6 +1141,35 @@ extern "C" gf_status gf_build_neighbours(gf_ctx *ctx, const gf_particles *p, int
   return gf_build_neighbours_rows(ctx, p, cross_model, p->n, out);
 }
 
+// the grid of each model's last (smallest-support) level alone: every
+// particle of the model falls in its cells, which hold few particles each
+static Grid finest_grid(const Grid &g) {
+  Grid g1;
+  memset(&g1, 0, sizeof(g1));
+  int ns = 0;
+  int64_t base = 0;
+  for (int m = 0; m < 2; ++m) {
+    g1.slot0[m] = ns;
+    if (g.slot0[m + 1] > g.slot0[m]) {
+      const int s = g.slot0[m + 1] - 1;
+      for (int d = 0; d < 3; ++d) {
+        g1.lo[ns][d] = g.lo[s][d];
+        g1.dim[ns][d] = g.dim[s][d];
+        g1.bits[ns][d] = g.bits[s][d];
+      }
+      g1.inv_edge[ns] = g.inv_edge[s];
+      g1.hcap[ns] = g.hcap[s];
+      g1.base[ns] = base;
+      base += (int64_t)1 << (g.bits[s][0] + g.bits[s][1] + g.bits[s][2]);
+      ++ns;
+    }
+  }
+  g1.slot0[2] = ns;
+  g1.nslots = ns;
+  g1.nkeys = base;
+  return g1;
+}
+
 extern "C" gf_status gf_build_neighbours_rows(gf_ctx *ctx, const gf_particles *p, int cross_model, int64_t n_rows,
                                               gf_nbr **out) {
   if (!ctx) return GF_EINVAL;
@@ -1230,7 +1259,7 @@ extern "C" gf_status gf_build_neighbours_rows(gf_ctx *ctx, const gf_particles *p
   sz = {sizeof(int32_t) * n, sizeof(int32_t) * n, sizeof(int32_t) * (K + 1), sizeof(int32_t) * scan_tmp_elems(K + 1),
         sizeof(double4) * n, sizeof(int32_t) * n, sizeof(int64_t) * scan_tmp_elems(n + 1), sizeof(int32_t) * 32,
         sizeof(int32_t) * n, sizeof(int32_t) * (n + 1), sizeof(int32_t) * scan_tmp_elems(n + 1),
-        sizeof(int32_t) * n};
+        sizeof(int32_t) * n, sizeof(int32_t) * n};
   // rows staged by the count pass (kStage entries each) while that stays
   // under 8 GB; rows found longer fall back to a fill pass
   const bool use_stage = (double)n * kStage * sizeof(int32_t) <= 8e9;
@@ -1254,6 +1283,7 @@ extern "C" gf_status gf_build_neighbours_rows(gf_ctx *ctx, const gf_particles *p
   // and their scan borrow the grouping arrays, which are free until the fill
   // pass has finished
   int32_t *cells = ar.take<int32_t>(n);
+  int32_t *order1 = ar.take<int32_t>(n);  // model-wide cell order for the grouping (several levels)
   int32_t *stage = use_stage ? ar.take<int32_t>((size_t)n * kStage) : nullptr;
   int32_t *head = gflag, *cpos = gpos;
   const int32_t *ncells = cpos + n;
@@ -1349,17 +1379,45 @@ extern "C" gf_status gf_build_neighbours_rows(gf_ctx *ctx, const gf_particles *p
   }
   if (hipGetLastError() != hipSuccess) return fail(set_error(ctx, GF_EHIP, "fill/sort kernel launch failed"));
 
-  // ---- groups by (model, band), Morton order kept inside each group
+  // ---- groups by (model, band), Morton order kept inside each group.  The
+  // cell order is level by level when a model has several support levels, so
+  // a tile cut from it would gather particles of one level from a wide
+  // region; the grouping then follows a model-wide order instead: the cells
+  // of each model's smallest-support grid in Morton order, fine Morton key
+  // inside each cell (the same kernels on a grid with one level per model).
+  // The arrays of the first cell pass are free once the rows are written.
+  const int32_t *gorder = nb->order;
+  if (g.slot0[1] - g.slot0[0] > 1 || g.slot0[2] - g.slot0[1] > 1) {
+    ProfScope prof_o(ctx, "nbr_order");
+    const Grid g1 = finest_grid(g);
+    const int64_t K1 = g1.nkeys;  // <= K: the slots of g1 are slots of g
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(K1 + 1, kBlock)), dim3(kBlock), 0, sm, cell_start, K1 + 1, 0);
+    hipLaunchKernelGGL(k_keys, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, p->x, p->y, p->z, p->h, p->model, n,
+                       g1, key, slot, cell_start);
+    if ((st = scan_i32_to_i32(ctx, cell_start, cell_start, K1, tmp32))) return fail(st);
+    hipLaunchKernelGGL(k_scatter, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, key, slot, cell_start, n, order1);
+    hipLaunchKernelGGL(k_cell_heads, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, order1, key, n, head);
+    if ((st = scan_i32_to_i32(ctx, head, cpos, n, tmpg))) return fail(st);
+    hipLaunchKernelGGL(k_cell_list, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, head, cpos, n, cells);
+    hipLaunchKernelGGL(k_cell_sort_reg,
+                       dim3((unsigned)std::min<int64_t>((n + kCellSortWaves - 1) / kCellSortWaves, 4096)),
+                       dim3(64 * kCellSortWaves), 0, sm, cells, ncells, n, p->x, p->y, p->z, p->h, p->model, g1,
+                       order1);
+    hipLaunchKernelGGL(k_cell_sort, dim3((unsigned)std::min<int64_t>(n, 2048)), dim3(64), 0, sm, cells, ncells, n,
+                       p->x, p->y, p->z, p->h, p->model, g1, order1);
+    if (hipGetLastError() != hipSuccess) return fail(set_error(ctx, GF_EHIP, "order kernels failed"));
+    gorder = order1;
+  }
   int64_t off = 0;
   {
   ProfScope prof_group(ctx, "nbr_group");
   for (int gsel = 0; gsel < 2 * GF_NBAND; ++gsel) {
     nb->group_start[gsel] = off;
     if (hist[gsel] == 0) continue;
-    hipLaunchKernelGGL(k_group_flag, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, nb->order, cnt, p->model, n,
+    hipLaunchKernelGGL(k_group_flag, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, gorder, cnt, p->model, n,
                        gsel, gflag);
     if ((st = scan_i32_to_i32(ctx, gflag, gpos, n, tmpg))) return fail(st);
-    hipLaunchKernelGGL(k_group_scatter, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, nb->order, gflag, gpos, n,
+    hipLaunchKernelGGL(k_group_scatter, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, sm, gorder, gflag, gpos, n,
                        off, nb->grouped);
     off += hist[gsel];
   }

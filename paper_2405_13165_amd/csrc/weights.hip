@@ -812,7 +812,7 @@ gf_status launch_batched(gf_ctx *ctx, const gf_nbr *nbr, WArgs a, int only_unit 
     const LaunchUnit &u = units[q];
     a.sched = nbr->grouped + u.row0;
     a.nrows = u.nrows;
-    const int T = team_override > 0 ? team_override : ctx->wteam[u.model][u.band];
+    const int T = team_override > 0 ? team_override : (FUSED ? ctx->fteam : ctx->wteam)[u.model][u.band];
     const char *name = unit_kernel_name(u, FUSED);
     gf_status st;
     if (u.tiled)
@@ -966,7 +966,8 @@ extern "C" gf_status gf_gfdm_weights_apply(gf_ctx *ctx, const gf_particles *p, c
 // ------------------------------------------------------------------ autotuner
 // Times every launch unit of the batched stencil kernel with teams of 4, 8
 // and 16 lanes (median of three launches after a warm-up) and keeps the
-// fastest; then does the same for the application kernel.
+// fastest; then the fused stencil + application kernel (more registers, so
+// its best team size may differ), then the application kernel.
 extern "C" gf_status gf_autotune(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr, gf_dtype wtype,
                                  int *team_out) {
   if (!ctx) return GF_EINVAL;
@@ -982,7 +983,8 @@ extern "C" gf_status gf_autotune(gf_ctx *ctx, const gf_particles *p, const gf_nb
   void *wbuf = nullptr;
   if (hipMalloc(&wbuf, wbytes) != hipSuccess) return set_error(ctx, GF_ENOMEM, "autotune buffer allocation failed");
   Arena ar;
-  if ((st = ensure_scratch(ctx, arena_bytes({sizeof(int32_t) * n, 64, sizeof(double4) * n}), &ar))) {
+  if ((st = ensure_scratch(ctx, arena_bytes({sizeof(int32_t) * n, 64, sizeof(double4) * n, sizeof(double) * n,
+                                             sizeof(double) * 4 * n}), &ar))) {
     (void)hipFree(wbuf);
     return st;
   }
@@ -1005,33 +1007,47 @@ extern "C" gf_status gf_autotune(gf_ctx *ctx, const gf_particles *p, const gf_nb
     (void)hipFree(wbuf);
     return set_error(ctx, GF_EHIP, "event creation failed");
   }
+  double *tu_field = ar.take<double>(n);
+  double *tu_out = ar.take<double>(4 * n);
+  (void)hipMemsetAsync(tu_field, 0, sizeof(double) * n, ctx->stream);
   const int sizes[3] = {4, 8, 16};
   const int saved_profile = ctx->profile;
   ctx->profile = 0;
   LaunchUnit units[2 * GF_NBAND];
   const int nu = launch_units(nbr, units);
-  for (int q = 0; q < nu && !st; ++q) {
-    float best = INFINITY;
-    int bestT = ctx->wteam[units[q].model][units[q].band];
-    for (int t = 0; t < 3 && !st; ++t) {
-      float times[3];
-      for (int rep = -1; rep < 3 && !st; ++rep) {
-        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, a.qcount, 16);
-        if (rep >= 0) (void)hipEventRecord(e0, ctx->stream);
-        st = (wtype == GF_F32) ? launch_batched<GF_F32, false, true>(ctx, nbr, a, q, sizes[t])
-                               : launch_batched<GF_F64, false, false>(ctx, nbr, a, q, sizes[t]);
-        if (rep >= 0) {
-          (void)hipEventRecord(e1, ctx->stream);
-          (void)hipEventSynchronize(e1);
-          (void)hipEventElapsedTime(&times[rep], e0, e1);
+  const bool f32 = wtype == GF_F32;
+  auto tune = [&](int (*team)[4], bool fused) {
+    for (int q = 0; q < nu && !st; ++q) {
+      float best = INFINITY;
+      int bestT = team[units[q].model][units[q].band];
+      for (int t = 0; t < 3 && !st; ++t) {
+        float times[3];
+        for (int rep = -1; rep < 3 && !st; ++rep) {
+          hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, a.qcount, 16);
+          if (rep >= 0) (void)hipEventRecord(e0, ctx->stream);
+          if (fused)
+            st = f32 ? launch_batched<GF_F32, true, true>(ctx, nbr, a, q, sizes[t])
+                     : launch_batched<GF_F64, true, false>(ctx, nbr, a, q, sizes[t]);
+          else
+            st = f32 ? launch_batched<GF_F32, false, true>(ctx, nbr, a, q, sizes[t])
+                     : launch_batched<GF_F64, false, false>(ctx, nbr, a, q, sizes[t]);
+          if (rep >= 0) {
+            (void)hipEventRecord(e1, ctx->stream);
+            (void)hipEventSynchronize(e1);
+            (void)hipEventElapsedTime(&times[rep], e0, e1);
+          }
         }
+        if (st) break;
+        std::sort(times, times + 3);
+        if (times[1] < best) { best = times[1]; bestT = sizes[t]; }
       }
-      if (st) break;
-      std::sort(times, times + 3);
-      if (times[1] < best) { best = times[1]; bestT = sizes[t]; }
+      team[units[q].model][units[q].band] = bestT;
     }
-    ctx->wteam[units[q].model][units[q].band] = bestT;
-  }
+  };
+  tune(ctx->wteam, false);
+  a.u = tu_field; a.y_out = tu_out; a.mask = 0xF;
+  tune(ctx->fteam, true);
+  a.u = nullptr; a.y_out = nullptr; a.mask = 0;
   // complete the stencils with the tuned configuration, then tune the application
   if (!st) {
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, a.qcount, 16);
@@ -1048,6 +1064,7 @@ extern "C" gf_status gf_autotune(gf_ctx *ctx, const gf_particles *p, const gf_nb
     for (int g = 0; g < 2 * GF_NBAND; ++g) {
       team_out[g] = ctx->wteam[g / GF_NBAND][g % GF_NBAND];
       team_out[2 * GF_NBAND + g] = ctx->ateam[g / GF_NBAND][g % GF_NBAND];
+      team_out[4 * GF_NBAND + g] = ctx->fteam[g / GF_NBAND][g % GF_NBAND];
     }
   }
   return GF_OK;

@@ -338,12 +338,12 @@ def gfdm_weights(ctx, p, nbr, prec=GF_BATCHED, wtype=GF_F32, params=None, out=No
 
 
 def autotune(ctx, p, nbr, wtype=GF_F32):
-    """Pick team sizes per group for the stencil and application kernels.
-    Returns {'weights': [8 ints], 'apply': [8 ints]} (bulk bands 0-3, film bands 0-3)."""
-    out = (ctypes.c_int * 16)()
+    """Pick team sizes per group for the stencil, application and fused kernels.
+    Returns {'weights', 'apply', 'fused': [8 ints]} (bulk bands 0-3, film bands 0-3)."""
+    out = (ctypes.c_int * 24)()
     ctx._sync_stream()
     ctx.check(ctx.lib.gf_autotune(ctx.handle, ctypes.byref(p.s), nbr.handle, wtype, out))
-    return {"weights": list(out[:8]), "apply": list(out[8:])}
+    return {"weights": list(out[:8]), "apply": list(out[8:16]), "fused": list(out[16:24])}
 
 
 def _nops(mask):
