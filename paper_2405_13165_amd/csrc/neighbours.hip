@@ -799,8 +799,9 @@ __global__ void __launch_bounds__(kBlock) k_tile_entries(TileGroups tg, const in
 }
 
 // One block per tile: collect the distinct indices of the tile's entries in
-// an LDS hash set, sort only those, write them to uniq[ent_off[t] ...], then
-// slot[] = rank of col[] in the sorted list (binary search) for every entry;
+// an LDS hash set, sort only those (each one's rank is the number of smaller
+// ones), write them to uniq[ent_off[t] ...], then slot[] = rank of col[] in
+// the sorted list (binary search) for every entry;
 // cnt[t] = number of distinct indices.  The result does not depend on the
 // order of the hash insertions.
 constexpr int kHashSize = 2 * kTileEntries;  // load factor <= 1/2: probes end
@@ -819,7 +820,7 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_unique(TileGroups tg, con
                                                               int32_t *__restrict__ grp_max) {
   static_assert(kHashSize == 1 << 13, "hash_slot takes 13 bits");
   __shared__ int32_t hkey[kHashSize];
-  __shared__ int32_t ulist[kTileEntries];
+  __shared__ __attribute__((aligned(16))) int32_t ulist[kTileEntries];
   __shared__ int64_t rbase[kTileRows];
   __shared__ int32_t rloc[kTileRows + 1];
   __shared__ int32_t ucount;
@@ -873,31 +874,28 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_unique(TileGroups tg, con
   }
   __syncthreads();
   const int U = ucount;
-  int P = 1;
-  while (P < U) P <<= 1;
-  for (int s = U + tid; s < P; s += kTileThreads) ulist[s] = 0x7fffffff;
+  // 2. rank of each distinct index = number of smaller distinct indices; the
+  // list is read four at a time (padded to a multiple of four), every lane
+  // of a wave reading the same address (an LDS broadcast), no barrier per
+  // step.  The sorted list goes to the hash table's storage, free now.
+  const int U4 = (U + 3) & ~3;
+  for (int s = U + tid; s < U4; s += kTileThreads) ulist[s] = 0x7fffffff;
   __syncthreads();
-  // 2. bitonic sort of the distinct indices.  Element s is handled by thread
-  // s mod kTileThreads, so a stage of distance < 64 pairs lanes of one wave;
-  // a block barrier is only needed around stages of distance >= 64.
-  for (int k = 2; k <= P; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int s = tid; s < P; s += kTileThreads) {
-        const int u = s ^ j;
-        if (u > s) {
-          const int32_t a = ulist[s], b = ulist[u];
-          if ((a > b) == ((s & k) == 0)) { ulist[s] = b; ulist[u] = a; }
-        }
-      }
-      const int jn = (j > 1) ? (j >> 1) : k;  // distance of the next stage
-      if (j >= 64 || jn >= 64) __syncthreads();
-      else wave_fence();
+  int32_t *sorted = hkey;
+  for (int s = tid; s < U; s += kTileThreads) {
+    const int32_t v = ulist[s];
+    int r = 0;
+    const int4 *l4 = reinterpret_cast<const int4 *>(ulist);
+    for (int c = 0; c < U4 / 4; ++c) {
+      const int4 w4 = l4[c];
+      r += (w4.x < v) + (w4.y < v) + (w4.z < v) + (w4.w < v);
     }
+    sorted[r] = v;
   }
   __syncthreads();
   // 3. the sorted distinct indices
   const int64_t ubase = ent_off[t];
-  for (int s = tid; s < U; s += kTileThreads) uniq[ubase + s] = ulist[s];
+  for (int s = tid; s < U; s += kTileThreads) uniq[ubase + s] = sorted[s];
   if (tid == 0) {
     cnt[t] = U;
     atomicMax(&grp_max[q], U);
@@ -911,7 +909,7 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_unique(TileGroups tg, con
     int lo = 0, hi = U - 1;
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
-      if (ulist[mid] < j) lo = mid + 1; else hi = mid;
+      if (sorted[mid] < j) lo = mid + 1; else hi = mid;
     }
     slot[k] = (uint16_t)lo;
   }
