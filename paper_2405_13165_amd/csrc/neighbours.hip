@@ -5,8 +5,10 @@
 //   cell key + per-cell counts (atomics) -> scan -> scatter into cell order
 //   -> list of non-empty cells -> finer Morton order inside cells ->
 //   positions gathered in cell order -> per-cell search, count pass -> scan
-//   -> fill pass -> per-row sort -> grouping of particles by (model,
-//   neighbour-count band) for the batched stencil kernels -> neighbour tiles.
+//   -> fill pass -> per-row sort -> (several support levels: a second cell
+//   pass over each model's finest grid, a model-wide Morton order) ->
+//   grouping of particles by (model, neighbour-count band) for the batched
+//   stencil kernels -> neighbour tiles.
 // Each model has grids for up to four support levels (caps hmax, hmax/2,
 // ...); a cell of a grid is a cube of edge slightly above its cap, and a row
 // cell searches, in every grid of the requested models, the cells within
@@ -736,7 +738,7 @@ __global__ void __launch_bounds__(kSortBlock) k_row_sort(const int64_t *__restri
   }
 }
 
-// grouping: particles (in cell order) of group gsel, stable; the tiled
+// grouping: particles (in the given order) of group gsel, stable; the tiled
 // bands 0..kTileBand share the group of band kTileBand
 __global__ void __launch_bounds__(kBlock) k_group_flag(const int32_t *__restrict__ order, const int32_t *__restrict__ cnt,
                                                        const int8_t *__restrict__ model, int64_t n, int gsel,
