@@ -37,7 +37,11 @@ struct AArgs {
   const int64_t *gbase;  // per team: offset of its row in dbar (grouped row offsets)
 };
 
-template <int M>
+// SEL: the stencils (bits of the op mask) the kernel carries; stencils
+// outside SEL have no adjoint (ybar = 0) and their terms are not formed.
+// The general kernel carries all four; the common single-operator cases
+// (Laplacian, gradient) get their own, with far fewer registers.
+template <int M, unsigned SEL>
 __device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane) {
   const int64_t b = a.row_ptr[i];
   const int n = (int)(a.row_ptr[i + 1] - b);
@@ -74,6 +78,7 @@ __device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane) {
   double lam[4][M];
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
+    if (!((SEL >> s) & 1u)) continue;
 #pragma unroll
     for (int r = 0; r < M; ++r) lam[s][r] = 0.0;
     if constexpr (M == 10) {
@@ -110,7 +115,7 @@ __device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane) {
 #pragma unroll
   for (int s = 0; s < 4; ++s)
 #pragma unroll
-    for (int r = 0; r < M; ++r) mu[s][r] = 0.0;
+    for (int r = 0; r < M; ++r) mu[s][r] = 0.0;  // (entries outside SEL are never read)
   for (int k = lane; k < n; k += kT) {
     const int32_t j = a.col[b + k];
     const double dx = a.x[j] - g.xi, dy = a.y[j] - g.yi, dz = a.z[j] - g.zi;
@@ -119,12 +124,15 @@ __device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane) {
     monomials<M>(g, dx, dy, dz, phi);
     chatbar(j, cb);
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+    for (int s = 0; s < 4; ++s) {
+      if (!((SEL >> s) & 1u)) continue;
 #pragma unroll
       for (int r = 0; r < M; ++r) mu[s][r] += cb[s] * w * phi[r];
+    }
   }
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
+    if (!((SEL >> s) & 1u)) continue;
 #pragma unroll
     for (int r = 0; r < M; ++r) mu[s][r] = team_sum(mu[s][r], kT);
     ldlt_solve<M>(G, dinv, mu[s]);
@@ -145,6 +153,7 @@ __device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane) {
     for (int q = 0; q < M; ++q) pb[q] = 0.0;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
+      if (!((SEL >> s) & 1u)) continue;
       double pl = 0.0, mp = 0.0;
 #pragma unroll
       for (int q = 0; q < M; ++q) { pl += phi[q] * lam[s][q]; mp += mu[s][q] * phi[q]; }
@@ -161,13 +170,20 @@ __device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane) {
   }
 }
 
-template <int M>
+template <int M, unsigned SEL>
 __global__ void __launch_bounds__(kBlock) k_adjoint_x(AArgs a) {
   const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t team = gt / kT;
   const int lane = (int)(gt % kT);
   if (team >= a.nrows) return;
-  adjoint_row<M>(a, a.sched[team], a.gbase[team], lane);
+  adjoint_row<M, SEL>(a, a.sched[team], a.gbase[team], lane);
+}
+
+template <int M>
+void launch_adjoint_x(hipStream_t sm, dim3 grid, dim3 block, const AArgs &a) {
+  if (a.mask == 8u) hipLaunchKernelGGL((k_adjoint_x<M, 8u>), grid, block, 0, sm, a);       // Laplacian
+  else if (a.mask == 7u) hipLaunchKernelGGL((k_adjoint_x<M, 7u>), grid, block, 0, sm, a);  // gradient
+  else hipLaunchKernelGGL((k_adjoint_x<M, 15u>), grid, block, 0, sm, a);
 }
 
 // xbar_j += sum over entries (j, i) of row j, i != j, of dbar(i, j) -
@@ -237,8 +253,8 @@ extern "C" gf_status gf_gfdm_weights_adjoint(gf_ctx *ctx, const gf_particles *p,
     a.nrows = s1 - s0;
     const dim3 grid(grid_for(a.nrows * kT, kBlock)), block(kBlock);
     ProfScope prof(ctx, m == 0 ? "weights_adjoint_3d" : "weights_adjoint_film");
-    if (m == 0) hipLaunchKernelGGL(k_adjoint_x<10>, grid, block, 0, ctx->stream, a);
-    else hipLaunchKernelGGL(k_adjoint_x<6>, grid, block, 0, ctx->stream, a);
+    if (m == 0) launch_adjoint_x<10>(ctx->stream, grid, block, a);
+    else launch_adjoint_x<6>(ctx->stream, grid, block, a);
     GF_LAUNCH_CHECK(ctx);
   }
   {
