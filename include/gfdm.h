@@ -427,7 +427,10 @@ gf_status gf_apply_stencil_adjoint(gf_ctx *ctx, const gf_nbr *nbr, gf_dtype wtyp
  * gf_apply_stencil(gf_gfdm_weights(p), u), given ybar = dL/dout [K][n] FP64
  * and u [n] FP64.  The stencils are recomputed, not stored.  xbar_3n
  * ([n][3] FP64) is accumulated (+=).  Rows with status 2 or 3 contribute
- * nothing (their stencils are constant zero). */
+ * nothing (their stencils are constant zero).  Each entry (i, j) moves x_i;
+ * it moves x_j through the twin entry (j, i), so with extended
+ * neighbourhoods (gf_build_neighbours_rows) the ghost particles, whose rows
+ * hold only themselves, receive nothing. */
 gf_status gf_gfdm_weights_adjoint(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr,
                                   const gf_ls_params *params, unsigned op_mask,
                                   const double *u, const double *ybar, double *xbar_3n);

@@ -34,6 +34,7 @@ struct AArgs {
   unsigned mask;
   const double *u, *ybar;
   double *dbar;  // [nnz][3], rows in grouped order
+  double *xbar;  // [n][3]: each row subtracts its own entries' sum here
   const int64_t *gbase;  // per team: offset of its row in dbar (grouped row offsets)
 };
 
@@ -137,6 +138,7 @@ __device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane) {
     for (int r = 0; r < M; ++r) mu[s][r] = team_sum(mu[s][r], kT);
     ldlt_solve<M>(G, dinv, mu[s]);
   }
+  double own[3] = {0.0, 0.0, 0.0};  // this lane's share of sum_j dbar(i, j)
   for (int k = lane; k < n; k += kT) {
     const int32_t j = a.col[b + k];
     double *out = a.dbar + 3 * (ob + k);
@@ -167,6 +169,16 @@ __device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane) {
     out[0] = dd[0] + f * dx;
     out[1] = dd[1] + f * dy;
     out[2] = dd[2] + f * dz;
+    own[0] += out[0];
+    own[1] += out[1];
+    own[2] += out[2];
+  }
+  // x_i loses every dbar(i, j), whether or not (j, i) is listed
+#pragma unroll
+  for (int c = 0; c < 3; ++c) own[c] = team_sum(own[c], kT);
+  if (lane == 0) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a.xbar[3 * (int64_t)i + c] -= own[c];
   }
 }
 
@@ -186,9 +198,12 @@ void launch_adjoint_x(hipStream_t sm, dim3 grid, dim3 block, const AArgs &a) {
   else hipLaunchKernelGGL((k_adjoint_x<M, 15u>), grid, block, 0, sm, a);
 }
 
-// xbar_j += sum over entries (j, i) of row j, i != j, of dbar(i, j) -
-// dbar(j, i); rows in grouped order, a team of kT lanes per row; the twin
-// dbar(i, j) sits at grev[g] (a Morton-near row).
+// xbar_j += sum over entries (j, i) of row j, i != j, of dbar(i, j) (x_j gains
+// what row i differentiated with respect to it; the row's own entries were
+// subtracted by the row kernel); rows in grouped order, a team of kT lanes
+// per row; the twin dbar(i, j) sits at grev[g] (a Morton-near row).  An entry
+// (j, i) without a twin (i a ghost particle whose row holds only itself)
+// adds nothing.
 __global__ void __launch_bounds__(kBlock) k_adjoint_gather(const int32_t *__restrict__ grouped,
                                                            const int64_t *__restrict__ grow_ptr,
                                                            const int32_t *__restrict__ grev,
@@ -205,9 +220,9 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_gather(const int32_t *__rest
   for (int64_t gk = g0 + lane; gk < g1; gk += kT) {
     const int32_t tw = grev[gk];
     if (tw < 0) continue;
-    s0 += dbar[3 * (int64_t)tw] - dbar[3 * gk];
-    s1 += dbar[3 * (int64_t)tw + 1] - dbar[3 * gk + 1];
-    s2 += dbar[3 * (int64_t)tw + 2] - dbar[3 * gk + 2];
+    s0 += dbar[3 * (int64_t)tw];
+    s1 += dbar[3 * (int64_t)tw + 1];
+    s2 += dbar[3 * (int64_t)tw + 2];
   }
   s0 = team_sum(s0, kT);
   s1 = team_sum(s1, kT);
@@ -245,6 +260,7 @@ extern "C" gf_status gf_gfdm_weights_adjoint(gf_ctx *ctx, const gf_particles *p,
   a.wf = make_weight_fn(prm.alpha_w);
   a.mask = op_mask; a.u = u; a.ybar = ybar;
   a.dbar = ar.take<double>(3 * (size_t)std::max<int64_t>(nbr->nnz, 1));
+  a.xbar = xbar_3n;
   for (int m = 0; m < 2; ++m) {
     const int64_t s0 = nbr->group_start[m * GF_NBAND], s1 = nbr->group_start[(m + 1) * GF_NBAND];
     if (s1 <= s0) continue;

@@ -218,6 +218,32 @@ def test_extended_neighbourhoods_and_stencils(ctx, g, factor):
     assert np.all(_np(y)[:, n:] == 0.0)
 
 
+def test_position_adjoint_over_extended_neighbourhoods(ctx, g):
+    # ghost neighbours have no rows of their own, so the entries (i, g) have
+    # no twin (g, i); x_i still loses every dbar(i, j).  The regular
+    # particles' gradients match the oracle's definition (Laplacian-only and
+    # a general operator set), and a second call accumulates onto the first.
+    d, n, pe, de = _extended(ctx, g, 4)
+    m = pe.n
+    nb = g.build_neighbours(ctx, pe, n_rows=n)
+    rp, col = (a.cpu().numpy() for a in nb.export())
+    rid = np.repeat(np.arange(m), np.diff(rp))
+    assert np.any((col >= n) & (rid < n))   # rows with ghost neighbours
+    f, *_ = W.test_field(de["x"], de["y"], de["z"])
+    u = torch.as_tensor(f, device=ctx.device)
+    yb = np.random.default_rng(17).uniform(-1, 1, (2, m))
+    for mask, k in ((g.OP_LAP, 1), (g.OP_LAP | g.OP_DX, 2)):
+        xb_o = oracle.weights_adjoint_x(de, rp, col, f, yb[:k], op_mask=mask)
+        ybt = torch.as_tensor(yb[:k], device=ctx.device)
+        xbar = g.gfdm_weights_adjoint(ctx, pe, nb, u, ybt, op_mask=mask)
+        first = _np(xbar).copy()
+        err = np.abs(first[:n] - xb_o[:n]).max() / np.abs(xb_o[:n]).max()
+        print(f"[adjoint, ghosts] mask {mask}: rel err {err:.2e}", flush=True)
+        assert err <= 1e-9
+        g.gfdm_weights_adjoint(ctx, pe, nb, u, ybt, op_mask=mask, xbar=xbar)
+        assert np.abs(_np(xbar) - 2 * first).max() <= 1e-12 * np.abs(first).max()
+
+
 def test_implicit_split_with_ghost_rows(ctx, g):
     d, n, pe, de = _extended(ctx, g, 4)
     m = pe.n
