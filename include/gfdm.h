@@ -418,7 +418,10 @@ gf_status gf_transition_3d_to_2d_cloud(gf_ctx *ctx, const gf_particles *p, const
 /* ---------------------------------------------------------- adjoints */
 /* Transpose of gf_apply_stencil with respect to u: ubar = C^T ybar, where
  * ybar [K][n] FP64 holds dL/dout; ubar [n] FP64 is overwritten.
- * Deterministic (gathers through the reverse-edge map, no atomics). */
+ * Deterministic (gathers through the reverse-edge map, no atomics).  With
+ * extended neighbourhoods (gf_build_neighbours_rows) the ghost particles,
+ * whose rows hold only themselves, receive nothing from the rows that list
+ * them; every other term is as for symmetric lists. */
 gf_status gf_apply_stencil_adjoint(gf_ctx *ctx, const gf_nbr *nbr, gf_dtype wtype,
                                    const void *w, unsigned op_mask, const double *ybar,
                                    double *ubar);

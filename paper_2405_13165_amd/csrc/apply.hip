@@ -130,7 +130,8 @@ constexpr int kApplyCap = 2048;
 
 // ubar_j = sum_{i : j in S_i, i != j} c_ij ybar_i - ybar_j sum_{k in S_j, k != j} c_jk,
 // the first sum gathered through the reverse-edge map (entry (i,j) sits at
-// rev[k] for the entry k = (j,i) of row j).
+// rev[k] for the entry k = (j,i) of row j); an entry of row j without a twin
+// (towards a ghost particle, which has no row) adds only its own term.
 // One team of kAdjTeam lanes per row j (the lanes stride over the row).
 constexpr int kAdjTeam = 8;
 template <typename WT>
@@ -152,12 +153,13 @@ __global__ void __launch_bounds__(kBlock) k_apply_adjoint(const int64_t *__restr
 #pragma unroll 4
   for (int64_t k = row_ptr[j] + lane; k < row_ptr[j + 1]; k += kAdjTeam) {
     const int32_t i = col[k];
-    const int32_t kr = rev[k];
-    if (i == j || kr < 0) continue;
-    double cin[4], cout_[4];
-    W4<WT>::load(w, kr, cin);   // c_ij (row i, column j)
-    W4<WT>::load(w, k, cout_);  // c_ji (row j, column i)
-    for (int q = 0; q < K; ++q) acc += cin[sel[q]] * ybar[(int64_t)q * n + i] - cout_[sel[q]] * yj[q];
+    const int32_t kr = rev[k];  // < 0: (i, j) is not listed (i a ghost particle without a row)
+    if (i == j) continue;
+    double cin[4] = {0.0, 0.0, 0.0, 0.0}, cout_[4];
+    if (kr >= 0) W4<WT>::load(w, kr, cin);  // c_ij (row i, column j)
+    W4<WT>::load(w, k, cout_);              // c_ji (row j, column i)
+    for (int q = 0; q < K; ++q)
+      acc += (kr >= 0 ? cin[sel[q]] * ybar[(int64_t)q * n + i] : 0.0) - cout_[sel[q]] * yj[q];
   }
   acc = team_sum(acc, kAdjTeam);
   if (lane == 0) ubar[j] = acc;

@@ -242,6 +242,12 @@ def test_position_adjoint_over_extended_neighbourhoods(ctx, g):
         assert err <= 1e-9
         g.gfdm_weights_adjoint(ctx, pe, nb, u, ybt, op_mask=mask, xbar=xbar)
         assert np.abs(_np(xbar) - 2 * first).max() <= 1e-12 * np.abs(first).max()
+    # the application adjoint likewise: u_i loses c_ig ybar_i for ghost neighbours g
+    w64 = g.gfdm_weights(ctx, pe, nb, g.GF_BATCHED, g.GF_F64)
+    yb4 = np.random.default_rng(18).uniform(-1, 1, (4, m))
+    ub = _np(g.apply_stencil_adjoint(ctx, nb, w64, torch.as_tensor(yb4, device=ctx.device)))
+    ub_o = oracle.apply_adjoint(rp, col, _np(w64), yb4)
+    assert np.abs(ub[:n] - ub_o[:n]).max() <= 1e-12 * np.abs(ub_o[:n]).max()
 
 
 def test_implicit_split_with_ghost_rows(ctx, g):
