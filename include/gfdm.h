@@ -84,6 +84,10 @@ typedef struct {
 /* Create a context on HIP device `device`.  stream: a hipStream_t to enqueue
  * on, or NULL for the default (null) stream. */
 gf_status gf_create(int device, void *stream, gf_ctx **out);
+/* Enqueue later calls on `stream`.  The calls of a context share its scratch
+ * memory, so the new stream first waits for the work the context enqueued on
+ * the previous one (an event; skipped while `stream` is being captured into a
+ * graph, where the caller orders the capture).  Does not synchronise. */
 gf_status gf_set_stream(gf_ctx *ctx, void *stream);
 void gf_destroy(gf_ctx *ctx);
 /* Message of the last failed call on ctx ("" if none).  Owned by ctx. */

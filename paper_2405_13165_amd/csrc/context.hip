@@ -35,7 +35,22 @@ extern "C" gf_status gf_create(int device, void *stream, gf_ctx **out) {
 
 extern "C" gf_status gf_set_stream(gf_ctx *ctx, void *stream) {
   if (!ctx) return GF_EINVAL;
-  ctx->stream = (hipStream_t)stream;
+  const hipStream_t s = (hipStream_t)stream;
+  if (s == ctx->stream) return GF_OK;
+  // Every call of a context uses its scratch arena, so work enqueued on the
+  // new stream must not overtake what the context enqueued on the old one:
+  // the new stream waits for an event recorded on the old stream.  (Not
+  // while the new stream is being captured into a graph: a captured stream
+  // cannot wait on work outside the capture; the caller orders it.)
+  GF_HIP(ctx, hipSetDevice(ctx->device));
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  GF_HIP(ctx, hipStreamIsCapturing(s, &cap));
+  if (cap == hipStreamCaptureStatusNone) {
+    if (!ctx->stream_order) GF_HIP(ctx, hipEventCreateWithFlags(&ctx->stream_order, hipEventDisableTiming));
+    GF_HIP(ctx, hipEventRecord(ctx->stream_order, ctx->stream));
+    GF_HIP(ctx, hipStreamWaitEvent(s, ctx->stream_order, 0));
+  }
+  ctx->stream = s;
   return GF_OK;
 }
 
@@ -47,6 +62,7 @@ extern "C" void gf_destroy(gf_ctx *ctx) {
     (void)hipFree(ctx->scratch);
   }
   if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
+  if (ctx->stream_order) (void)hipEventDestroy(ctx->stream_order);
   for (auto &r : ctx->prof_pending) {
     (void)hipEventDestroy(r.start);
     (void)hipEventDestroy(r.stop);

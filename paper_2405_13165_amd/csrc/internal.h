@@ -20,6 +20,8 @@ struct gf_ctx {
   // call on this context
   void *scratch = nullptr;
   size_t scratch_bytes = 0;
+  // orders the context's work across gf_set_stream (the calls share scratch)
+  hipEvent_t stream_order = nullptr;
   // small pinned host buffer for read-backs
   void *host_pinned = nullptr;
   size_t host_pinned_bytes = 0;

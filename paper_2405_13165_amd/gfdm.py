@@ -168,7 +168,7 @@ class Context:
 
     def _sync_stream(self):
         s = torch.cuda.current_stream(self.device).cuda_stream
-        self.lib.gf_set_stream(self.handle, ctypes.c_void_p(s))
+        self.check(self.lib.gf_set_stream(self.handle, ctypes.c_void_p(s)))
 
     def check(self, st):
         if st != GF_OK:

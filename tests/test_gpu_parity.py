@@ -243,6 +243,25 @@ def test_weights_degenerate_rows(ctx, g):
         assert np.all(_np(w) == 0)
 
 
+def test_calls_on_a_side_stream(ctx, g):
+    # the binding enqueues on torch's current stream: a side stream gives the
+    # same results, and a call back on the default stream right after waits
+    # for the context's work on the side stream (shared scratch)
+    d = CASES["mixed_small"]()
+    p, nb, rp, col = _nbr_equal(ctx, g, d)
+    u = torch.as_tensor(W.test_field(d["x"], d["y"], d["z"])[0], device=ctx.device)
+    w_ref, y_ref = g.gfdm_weights_apply(ctx, p, nb, u, wtype=g.GF_F32)
+    s = torch.cuda.Stream(device=ctx.device)
+    s.wait_stream(torch.cuda.current_stream(ctx.device))
+    with torch.cuda.stream(s):
+        nb2 = g.build_neighbours(ctx, p)
+        w2, y2 = g.gfdm_weights_apply(ctx, p, nb2, u, wtype=g.GF_F32)
+    w3, y3 = g.gfdm_weights_apply(ctx, p, nb, u, wtype=g.GF_F32)
+    torch.cuda.synchronize()
+    for a, b in ((w_ref, w2), (y_ref, y2), (w_ref, w3), (y_ref, y3)):
+        assert torch.equal(a, b)
+
+
 def test_tiny_clouds_through_the_path(ctx, g):
     # one and three bulk wall particles (rows shorter than the 10 monomials):
     # neighbourhoods and PCA as the oracle; zero stencils with status 3 on
