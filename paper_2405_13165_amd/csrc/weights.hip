@@ -49,14 +49,21 @@ struct WArgs {
   unsigned mask;
 };
 
+// The stencils are written once and read by a later kernel, after this one has
+// left L2: non-temporal stores keep them from evicting the neighbour
+// positions and the tile lists that this kernel re-reads.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 template <int OUT>
 __device__ inline void store_w(void *w, int64_t k, double c0, double c1, double c2, double c3) {
   if constexpr (OUT == GF_F32) {
-    reinterpret_cast<float4 *>(w)[k] = make_float4((float)c0, (float)c1, (float)c2, (float)c3);
+    const f32x4 v = {(float)c0, (float)c1, (float)c2, (float)c3};
+    __builtin_nontemporal_store(v, reinterpret_cast<f32x4 *>(w) + k);
   } else {
-    double2 *p = reinterpret_cast<double2 *>(w) + 2 * k;
-    p[0] = make_double2(c0, c1);
-    p[1] = make_double2(c2, c3);
+    f64x2 *p = reinterpret_cast<f64x2 *>(w) + 2 * k;
+    const f64x2 v0 = {c0, c1}, v1 = {c2, c3};
+    __builtin_nontemporal_store(v0, p);
+    __builtin_nontemporal_store(v1, p + 1);
   }
 }
 
