@@ -50,20 +50,30 @@ struct WArgs {
 };
 
 // The stencils are written once and read by a later kernel, after this one has
-// left L2: non-temporal stores keep them from evicting the neighbour
-// positions and the tile lists that this kernel re-reads.
+// left L2.  NT: non-temporal stores, which keep them from evicting the
+// neighbour positions and tile lists the kernel re-reads; they bypass the
+// merging of partial lines in L2, so they pay only where each store
+// instruction covers whole aligned lines (the team kernels' pass 2).  Scattered
+// stores (one row per lane) go through L2.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
-template <int OUT>
+template <int OUT, bool NT = false>
 __device__ inline void store_w(void *w, int64_t k, double c0, double c1, double c2, double c3) {
   if constexpr (OUT == GF_F32) {
     const f32x4 v = {(float)c0, (float)c1, (float)c2, (float)c3};
-    __builtin_nontemporal_store(v, reinterpret_cast<f32x4 *>(w) + k);
+    f32x4 *p = reinterpret_cast<f32x4 *>(w) + k;
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
   } else {
     f64x2 *p = reinterpret_cast<f64x2 *>(w) + 2 * k;
     const f64x2 v0 = {c0, c1}, v1 = {c2, c3};
-    __builtin_nontemporal_store(v0, p);
-    __builtin_nontemporal_store(v1, p + 1);
+    if constexpr (NT) {
+      __builtin_nontemporal_store(v0, p);
+      __builtin_nontemporal_store(v1, p + 1);
+    } else {
+      p[0] = v0;
+      p[1] = v1;
+    }
   }
 }
 
@@ -250,33 +260,35 @@ struct FetchTile {    // the tile's positions (and field) staged in LDS, address
   __device__ double field(int32_t s) const { return su[s]; }
 };
 
-// Visit the neighbours k = lane, lane + T, ... of the row starting at CSR
-// entry b, calling body(k, position, handle) with the loads software-pipelined.
+// Visit the neighbours k = k0, k0 + T, ... (k0 in (-T, T); negative k are
+// skipped) of the row starting at CSR entry b, calling body(k, position,
+// handle) with the loads software-pipelined.
 template <int T, class F, class Body>
-__device__ inline void for_neighbours(const F &fetch, int64_t b, int n, int lane, Body &&body) {
+__device__ inline void for_neighbours(const F &fetch, int64_t b, int n, int k0, Body &&body) {
+  auto in = [n](int k) { return k >= 0 && k < n; };
   if constexpr (F::kDeep) {
-    int32_t hc = (lane < n) ? fetch.idx(b + lane) : fetch.dummy;
-    int32_t hn = (lane + T < n) ? fetch.idx(b + lane + T) : fetch.dummy;
+    int32_t hc = in(k0) ? fetch.idx(b + k0) : fetch.dummy;
+    int32_t hn = in(k0 + T) ? fetch.idx(b + k0 + T) : fetch.dummy;
     double4 pc = fetch.get(hc);
 #pragma unroll 1
-    for (int k = lane; k < n; k += T) {
+    for (int k = k0; k < n; k += T) {
       const double4 pj = pc;
       const int32_t h = hc;
       hc = hn;
       pc = fetch.get(hn);
       hn = (k + 2 * T < n) ? fetch.idx(b + k + 2 * T) : fetch.dummy;
-      body(k, pj, h);
+      if (k >= 0) body(k, pj, h);
     }
   } else {
-    int32_t hc = (lane < n) ? fetch.idx(b + lane) : fetch.dummy;
-    int32_t hn = (lane + T < n) ? fetch.idx(b + lane + T) : fetch.dummy;
+    int32_t hc = in(k0) ? fetch.idx(b + k0) : fetch.dummy;
+    int32_t hn = in(k0 + T) ? fetch.idx(b + k0 + T) : fetch.dummy;
 #pragma unroll 1
-    for (int k = lane; k < n; k += T) {
+    for (int k = k0; k < n; k += T) {
       const double4 pj = fetch.get(hc);
       const int32_t h = hc;
       hc = hn;
       hn = (k + 2 * T < n) ? fetch.idx(b + k + 2 * T) : fetch.dummy;
-      body(k, pj, h);
+      if (k >= 0) body(k, pj, h);
     }
   }
 }
@@ -458,7 +470,9 @@ __device__ void weights_row_team(const WArgs &a, int32_t i, int lane, double *sm
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   double ui = 0.0;
   if constexpr (FUSED) ui = a.u[i];
-  for_neighbours<T>(fetch, b, n, lane, [&](int k, const double4 &pj, int32_t h) {
+  // the team's stores of one step cover whole aligned T-entry blocks
+  const int k0 = a.w_out ? lane - (int)(b & (T - 1)) : lane;
+  for_neighbours<T>(fetch, b, n, k0, [&](int k, const double4 &pj, int32_t h) {
     const double dx = pj.x - g.xi, dy = pj.y - g.yi, dz = pj.z - g.zi;
     double w;
     if constexpr (KC > 0)
@@ -481,7 +495,7 @@ __device__ void weights_row_team(const WArgs &a, int32_t i, int lane, double *sm
       c[1] = g.t1[1] * cu + g.t2[1] * cv;
       c[2] = g.t1[2] * cu + g.t2[2] * cv;
     }
-    if (a.w_out) store_w<OUT>(a.w_out, b + k, c[0], c[1], c[2], c[3]);
+    if (a.w_out) store_w<OUT, true>(a.w_out, b + k, c[0], c[1], c[2], c[3]);
     if constexpr (FUSED) {
       // the diagonal entry contributes u_i - u_i = 0
       const double du = fetch.field(h) - ui;
