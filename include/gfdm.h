@@ -228,6 +228,18 @@ gf_status gf_apply_stencil(gf_ctx *ctx, const gf_nbr *nbr, gf_dtype wtype, const
  * kernel, in the same layout. */
 gf_status gf_autotune(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr, gf_dtype wtype, int *team_out);
 
+/* Sets the team sizes (lanes per particle) that later calls on ctx use, in
+ * the layout of gf_autotune's team_out: 24 ints, the stencil kernel's (bulk
+ * bands 0-3, film bands 0-3; a model's tiled rows use band 2), then the
+ * application kernel's, then the fused kernel's.  Stencil and fused entries
+ * take 4, 8 or 16, application entries 4, 8, 16, 32 or 64; 0 keeps the
+ * current size.  teams may be NULL (nothing changes).  previous (host, may be
+ * NULL) receives the 24 sizes in effect before the call.  Any other value
+ * -> GF_EINVAL and nothing changes.  For reproducible configurations and
+ * tests; the results of every size agree to rounding (the team sums run in a
+ * different order). */
+gf_status gf_set_team_sizes(gf_ctx *ctx, const int *teams, int *previous);
+
 /* Weights and application in one pass: computes the stencils exactly as
  * gf_gfdm_weights (GF_BATCHED) and, while they are in registers, applies them
  * to u (FP64) -> out [K][n] FP64 as gf_apply_stencil does.  w_out may be NULL

@@ -318,3 +318,25 @@ gf_status scan_i32_to_i64(gf_ctx *ctx, const int32_t *in, int64_t *out, int64_t 
 gf_status scan_i32_to_i32(gf_ctx *ctx, const int32_t *in, int32_t *out, int64_t n, int32_t *tmp) {
   return scan_impl<int32_t, int32_t>(ctx, in, out, n, tmp);
 }
+
+extern "C" gf_status gf_set_team_sizes(gf_ctx *ctx, const int *teams, int *previous) {
+  if (!ctx) return GF_EINVAL;
+  int (*const tab[3])[GF_NBAND] = {ctx->wteam, ctx->ateam, ctx->fteam};
+  if (teams) {
+    for (int q = 0; q < 3 * 2 * GF_NBAND; ++q) {
+      const int t = teams[q];
+      const bool apply = q / (2 * GF_NBAND) == 1;
+      const bool ok = t == 0 || t == 4 || t == 8 || t == 16 || (apply && (t == 32 || t == 64));
+      if (!ok)
+        return set_error(ctx, GF_EINVAL, "team size %d at position %d (stencil and fused kernels: 4, 8 or 16; "
+                         "application: 4, 8, 16, 32 or 64; 0 keeps the current size)", t, q);
+    }
+  }
+  for (int q = 0; q < 3 * 2 * GF_NBAND; ++q) {
+    const int k = q / (2 * GF_NBAND), g = q % (2 * GF_NBAND);
+    int &slot = tab[k][g / GF_NBAND][g % GF_NBAND];
+    if (previous) previous[q] = slot;
+    if (teams && teams[q] > 0) slot = teams[q];
+  }
+  return GF_OK;
+}

@@ -77,7 +77,7 @@ EXPORTED = [
     "gf_pca_params_default", "gf_classify_pca", "gf_ls_params_default", "gf_gfdm_weights",
     "gf_apply_stencil", "gf_gfdm_weights_apply", "gf_poisson_assemble", "gf_solve_params_default",
     "gf_poisson_solve", "gf_transition_3d_to_2d", "gf_apply_stencil_adjoint",
-    "gf_gfdm_weights_adjoint", "gf_profile_enable", "gf_profile_read", "gf_autotune", "gf_set_tile_capacity",
+    "gf_gfdm_weights_adjoint", "gf_profile_enable", "gf_profile_read", "gf_autotune", "gf_set_team_sizes", "gf_set_tile_capacity",
     "gf_build_neighbours_rows", "gf_film_height", "gf_transition_2d_to_3d", "gf_buffer_flags", "gf_buffer_zone",
     "gf_transition_3d_to_2d_cloud",
 ]
@@ -126,6 +126,7 @@ def load_library(path: str = LIB_PATH):
     L.gf_apply_stencil_adjoint.argtypes = [P, P, I32, P, U, P, P]
     L.gf_gfdm_weights_adjoint.argtypes = [P, PP, P, ctypes.POINTER(LsParams), U, P, P, P]
     L.gf_autotune.argtypes = [P, PP, P, I32, P]
+    L.gf_set_team_sizes.argtypes = [P, P, P]
     L.gf_profile_enable.argtypes = [P, I32]
     L.gf_set_tile_capacity.argtypes = [P, I32]
     L.gf_profile_read.argtypes = [P, ctypes.c_char_p, ctypes.c_size_t]
@@ -344,6 +345,23 @@ def autotune(ctx, p, nbr, wtype=GF_F32):
     ctx._sync_stream()
     ctx.check(ctx.lib.gf_autotune(ctx.handle, ctypes.byref(p.s), nbr.handle, wtype, out))
     return {"weights": list(out[:8]), "apply": list(out[8:16]), "fused": list(out[16:24])}
+
+
+def set_team_sizes(ctx, weights=None, apply=None, fused=None):
+    """Set the team sizes of the stencil, application and fused kernels (each a
+    list of 8 ints in gf_autotune's layout, 0 = keep; None keeps all 8).
+    Returns the previous sizes as {'weights', 'apply', 'fused'}."""
+    teams = (ctypes.c_int * 24)()
+    for k, v in enumerate((weights, apply, fused)):
+        if v is not None:
+            if len(v) != 8:
+                raise ValueError("8 team sizes per kernel")
+            for q in range(8):
+                teams[8 * k + q] = int(v[q])
+    prev = (ctypes.c_int * 24)()
+    ctx._sync_stream()
+    ctx.check(ctx.lib.gf_set_team_sizes(ctx.handle, teams, prev))
+    return {"weights": list(prev[:8]), "apply": list(prev[8:16]), "fused": list(prev[16:24])}
 
 
 def _nops(mask):

@@ -395,6 +395,46 @@ def test_fused_weights_apply(ctx, g, wtype):
     assert torch.equal(y_nostore, y)
 
 
+@pytest.mark.parametrize("team,ateam", [(4, 64), (8, 32), (16, 4)])
+def test_every_team_size(ctx, g, team, ateam):
+    # the batched stencil kernels (tiled and untiled rows, FP64 and FP32
+    # output, separate and fused) and the application kernel at forced team
+    # sizes, against the oracle; the team decides where each lane's stores
+    # start (pass 2 runs on blocks aligned to the team width)
+    prev = g.set_team_sizes(ctx, [team] * 8, [ateam] * 8, [team] * 8)
+    try:
+        for name in ("mixed_small", "jet_small"):
+            print(f"\n[team {team} / apply {ateam}] {name}", flush=True)
+            d = CASES[name]()
+            p, nb, rp, col = _nbr_equal(ctx, g, d)
+            w_o, st_o, _ = oracle.gfdm_weights(d, rp, col)
+            f, *_ = W.test_field(d["x"], d["y"], d["z"])
+            u = torch.as_tensor(f, device=ctx.device)
+            y_o = oracle.apply(rp, col, w_o, f)
+            for wt, tol in ((g.GF_F64, 1e-10), (g.GF_F32, 1e-6)):
+                status = torch.empty(p.n, dtype=torch.int8, device=ctx.device)
+                w = g.gfdm_weights(ctx, p, nb, g.GF_BATCHED, wt, status=status)
+                assert _status_match(_np(status), st_o)
+                e = oracle.operator_error(_np(w).astype(np.float64), w_o, rp)
+                assert e.max() <= tol, (name, wt, e.max())
+                y = _np(g.apply_stencil(ctx, nb, w, u))
+                assert _apply_err(y, y_o, rp, col, w_o, f) <= tol
+                wf, yf = g.gfdm_weights_apply(ctx, p, nb, u, wtype=wt)
+                assert torch.equal(wf, w)
+                assert _apply_err(_np(yf), y_o, rp, col, w_o, f) <= tol
+    finally:
+        g.set_team_sizes(ctx, prev["weights"], prev["apply"], prev["fused"])
+    assert g.set_team_sizes(ctx) == prev
+
+
+def test_team_sizes_reject_bad_values(ctx, g):
+    before = g.set_team_sizes(ctx)
+    for kw in ({"weights": [32] * 8}, {"fused": [2] * 8}, {"apply": [3] * 8}, {"apply": [128] * 8}):
+        with pytest.raises(g.GfdmError):
+            g.set_team_sizes(ctx, **kw)
+        assert g.set_team_sizes(ctx) == before
+
+
 # ------------------------------------------------------------------ pressure
 @pytest.mark.parametrize("rows", ["neumann", "combined"])
 def test_poisson_assemble_and_solve(ctx, g, rows):
