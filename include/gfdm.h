@@ -196,7 +196,8 @@ typedef struct {
  * minimum-norm solution (sum c_j^2 / w_j) of the exactness conditions, i.e.
  * c = W M (M^T W M)^{-1} d.  Output w_out [nnz][4] in `wtype` (FP64 or FP32;
  * GF_PLAIN_F64 requires FP64): physical weights for d/dx, d/dy, d/dz and the
- * Laplacian, aligned with the neighbour CSR.  Film rows hold the surface
+ * Laplacian, aligned with the neighbour CSR; w_out must be 16-byte aligned
+ * (else GF_EINVAL: the kernels write whole 16-byte vectors).  Film rows hold the surface
  * gradient as global x, y, z components and the surface Laplacian.
  * status_n (int8, device, may be NULL): 0 ok, 1 solved by the FP64 QR
  * fallback, 2 rank deficient (zero weights), 3 fewer neighbours than
@@ -209,8 +210,8 @@ gf_status gf_gfdm_weights(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr,
 /* Apply stencils (Eq. GFDM_Definition) in differenced form:
  *   out[s][i] = sum_{j in S_i, j != i} c_ij^s (u_j - u_i)
  * for each operator s selected in op_mask (bit order dx, dy, dz, lap),
- * stacked [K][n].  Weights of type wtype; u and out of type io; sums are
- * accumulated in FP64. */
+ * stacked [K][n].  Weights of type wtype, 16-byte aligned (else GF_EINVAL);
+ * u and out of type io; sums are accumulated in FP64. */
 gf_status gf_apply_stencil(gf_ctx *ctx, const gf_nbr *nbr, gf_dtype wtype, const void *w,
                            unsigned op_mask, gf_dtype io, const void *u, void *out);
 

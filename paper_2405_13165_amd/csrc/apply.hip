@@ -265,6 +265,7 @@ extern "C" gf_status gf_apply_stencil(gf_ctx *ctx, const gf_nbr *nbr, gf_dtype w
   if (st) return st;
   if (nbr->cross) return set_error(ctx, GF_EINVAL, "stencils live on same-model neighbourhoods");
   if (!w || !u || !out) return set_error(ctx, GF_EINVAL, "w, u and out are required");
+  if (reinterpret_cast<uintptr_t>(w) & 15) return set_error(ctx, GF_EINVAL, "w must be 16-byte aligned");
   if ((op_mask & 0xF) == 0 || (op_mask & ~0xFu)) return set_error(ctx, GF_EINVAL, "op_mask must select 1..4 operators");
   if ((wtype != GF_F32 && wtype != GF_F64) || (io != GF_F32 && io != GF_F64))
     return set_error(ctx, GF_EINVAL, "unknown dtype");
@@ -285,6 +286,7 @@ extern "C" gf_status gf_apply_stencil_adjoint(gf_ctx *ctx, const gf_nbr *nbr, gf
   if (st) return st;
   if (nbr->cross) return set_error(ctx, GF_EINVAL, "stencils live on same-model neighbourhoods");
   if (!w || !ybar || !ubar) return set_error(ctx, GF_EINVAL, "w, ybar and ubar are required");
+  if (reinterpret_cast<uintptr_t>(w) & 15) return set_error(ctx, GF_EINVAL, "w must be 16-byte aligned");
   if ((op_mask & 0xF) == 0 || (op_mask & ~0xFu)) return set_error(ctx, GF_EINVAL, "op_mask must select 1..4 operators");
   if (wtype != GF_F32 && wtype != GF_F64) return set_error(ctx, GF_EINVAL, "unknown dtype");
   GF_HIP(ctx, hipSetDevice(ctx->device));

@@ -879,6 +879,7 @@ gf_status weights_common(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr, 
   if (wtype != GF_F64 && wtype != GF_F32) return set_error(ctx, GF_EINVAL, "unknown weight type %d", (int)wtype);
   if (prec == GF_PLAIN_F64 && wtype != GF_F64) return set_error(ctx, GF_EINVAL, "GF_PLAIN_F64 writes FP64 weights");
   if (!w_out && !fused) return set_error(ctx, GF_EINVAL, "w_out is NULL");
+  if (reinterpret_cast<uintptr_t>(w_out) & 15) return set_error(ctx, GF_EINVAL, "w_out must be 16-byte aligned");
   if (fused && (!u || !out || (op_mask & 0xF) == 0 || (op_mask & ~0xFu)))
     return set_error(ctx, GF_EINVAL, "fused application needs u, out and a non-empty op mask");
   gf_ls_params prm;

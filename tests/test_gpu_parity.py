@@ -116,6 +116,18 @@ def test_invalid_inputs_are_rejected(ctx, g):
     d["model"] = d["model"].copy(); d["model"][0] = 3
     with pytest.raises(g.GfdmError):
         g.build_neighbours(ctx, _dev(ctx, d))
+    # stencil arrays must be 16-byte aligned (the kernels move whole 16-byte
+    # vectors); the check runs on the host, before any launch
+    d = W.plain_cube(6)
+    p = _dev(ctx, d)
+    nb = g.build_neighbours(ctx, p)
+    buf = torch.zeros(nb.nnz * 4 + 1, dtype=torch.float32, device=ctx.device)
+    wmis = buf[1:].view(nb.nnz, 4)
+    u = torch.zeros(p.n, dtype=torch.float64, device=ctx.device)
+    with pytest.raises(g.GfdmError, match="aligned"):
+        g.apply_stencil(ctx, nb, wmis, u)
+    with pytest.raises(g.GfdmError, match="aligned"):
+        g.gfdm_weights_apply(ctx, p, nb, u, wtype=g.GF_F32, w_out=wmis)
 
 
 # ------------------------------------------------------------------ PCA / flags
