@@ -73,6 +73,8 @@ def _declare(L):
     L.orc_gfdm_weights.restype = None
     L.orc_gfdm_weights.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                    ctypes.c_double, _P, _I64, _P, _P, _P]
+    L.orc_gram_kappa.restype = None
+    L.orc_gram_kappa.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_double, _P]
     L.orc_gfdm_weights_normal_ld.restype = None
     L.orc_gfdm_weights_normal_ld.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                              ctypes.c_double, _P]
@@ -179,6 +181,19 @@ def gfdm_weights(p, row_ptr, col, alpha_w=ALPHA_W, rows=None):
                            _p(_f64(p["ny"])), _p(_f64(p["nz"])), _p(row_ptr), _p(col), alpha_w,
                            _p(r), 0 if r is None else r.shape[0], _p(w), _p(status), _p(kappa))
     return w, status, kappa
+
+
+def gram_kappa(p, row_ptr, col, alpha_w=ALPHA_W):
+    """Per particle kappa_1(G) = ||G||_1 ||G^-1||_1 of the Gram matrix
+    G = M^T W M = R^T R of the stencil's least-squares problem (scaled local
+    coordinates): the condition estimate behind the FP64 fallback.  0 where
+    n_i < m, inf where the QR test finds the problem rank deficient."""
+    x, y, z, h, model = _pos(p)
+    n = x.shape[0]
+    k = np.zeros(n)
+    lib().orc_gram_kappa(n, _p(x), _p(y), _p(z), _p(h), _p(model), _p(_f64(p["nx"])), _p(_f64(p["ny"])),
+                         _p(_f64(p["nz"])), _p(row_ptr), _p(col), alpha_w, _p(k))
+    return k
 
 
 def gfdm_weights_normal_ld(p, row_ptr, col, alpha_w=ALPHA_W):

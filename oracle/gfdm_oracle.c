@@ -631,6 +631,55 @@ void orc_gfdm_weights(int64_t n, const double *x, const double *y, const double 
   }
 }
 
+/* Condition number of the least-squares Gram matrix G = M^T W M = R^T R of
+ * particle i in the scaled local coordinates of Eq. (GFDM_Definition):
+ * kappa_1(G) = ||G||_1 ||G^{-1}||_1 with G^{-1} = R^{-1} R^{-T}.  This is the
+ * per-particle condition estimate that decides whether a particle's stencil
+ * must be recomputed by the FP64 Householder form (spec precision
+ * scheme; the paper itself solves every local problem the same way).
+ * 0 for status 3 (n_i < m), +inf for status 2 (rank deficient). */
+void orc_gram_kappa(int64_t n, const double *x, const double *y, const double *z,
+                    const double *h, const int8_t *model, const double *nx, const double *ny,
+                    const double *nz, const int64_t *row_ptr, const int32_t *col, double alpha_w,
+                    double *kappa_gram) {
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t i = 0; i < n; ++i) {
+    ls_t L;
+    ls_factor(&L, i, x, y, z, h, model, nx, ny, nz, row_ptr, col, alpha_w);
+    if (L.status == 3) { kappa_gram[i] = 0.0; ls_free(&L); continue; }
+    if (L.status == 2) { kappa_gram[i] = INFINITY; ls_free(&L); continue; }
+    int m = L.m;
+    double G[100] = {0}, Rinv[100] = {0}, Ginv[100] = {0};
+    for (int r = 0; r < m; ++r)          /* G = R^T R */
+      for (int c = 0; c < m; ++c) {
+        double acc = 0;
+        for (int t = 0; t < m; ++t) acc += L.R[t * 10 + r] * L.R[t * 10 + c];
+        G[r * 10 + c] = acc;
+      }
+    for (int c = 0; c < m; ++c)          /* R^{-1} by back substitution */
+      for (int r = m - 1; r >= 0; --r) {
+        double acc = (r == c) ? 1.0 : 0.0;
+        for (int t = r + 1; t < m; ++t) acc -= L.R[r * 10 + t] * Rinv[t * 10 + c];
+        Rinv[r * 10 + c] = acc / L.R[r * 10 + r];
+      }
+    for (int r = 0; r < m; ++r)          /* G^{-1} = R^{-1} R^{-T} */
+      for (int c = 0; c < m; ++c) {
+        double acc = 0;
+        for (int t = 0; t < m; ++t) acc += Rinv[r * 10 + t] * Rinv[c * 10 + t];
+        Ginv[r * 10 + c] = acc;
+      }
+    double n1 = 0, n1i = 0;
+    for (int c = 0; c < m; ++c) {
+      double sg = 0, si = 0;
+      for (int r = 0; r < m; ++r) { sg += fabs(G[r * 10 + c]); si += fabs(Ginv[r * 10 + c]); }
+      if (sg > n1) n1 = sg;
+      if (si > n1i) n1i = si;
+    }
+    kappa_gram[i] = n1 * n1i;
+    ls_free(&L);
+  }
+}
+
 /* The same stencil from the normal equations G lambda = d, G = M^T W M,
  * c_j = w_j phi_j^T lambda, in long double with a Cholesky solve.  Used only
  * to cross-check the Householder form (the two are algebraically equal). */
