@@ -6,15 +6,24 @@ stencils d/dx, d/dy, d/dz, Laplacian applied to one scalar field), on the
 mixed bulk/film cloud of 503,944 particles (258,944 jittered-lattice bulk
 particles beside 245,000 film particles on z = 0, h = 3 x local spacing).
 value = N / t_step for the batched path: one gf_gfdm_weights_apply call that
-computes every stencil (FP64 moments and solves, QR fallback), stores it in
-FP32 and applies it to the field.  The same work as two calls (weights, then
-apply), the plain FP64 path and the other steps of the hot path are timed
-beside it.
+computes every stencil (FP64 moments and solves, FP64 QR fallback), stores it
+in FP32 and applies it to the field.  The plain FP64 path (one work-item per
+particle, FP64 stencils, then the application) and the same batched work as
+two calls are timed beside it.
 
-A step is one weights + apply pass over the resident cloud; K steps are timed
-with HIP events on the library's stream after W warm-up steps.  The FP64 CPU
-oracle is timed on the same workload (weights + apply, every particle) and
-its stencils are the reference for the stated operator error.
+A step is one weights + apply pass over the resident cloud.  Each of the K
+timed steps is bracketed by HIP events on the library's stream; before it,
+1 GiB is written to one scratch buffer and 1 GiB read from another, so that
+the caches (L2, the 256 MB Infinity Cache) hold nothing of the step's inputs
+and no write-back is pending; ms_per_step is the mean.  The same steps back
+to back are reported beside it.
+
+The default run also reports the other workloads of the path: the uneven
+2.0M-particle jet-on-plate cloud (fused step), the 10^6-particle
+differentiation cube (forward + backward through the adjoints) and the
+4.0M-row pressure-Poisson solve (FP64 and the two mixed-precision forms);
+per-output errors against the FP64 oracle; the roofline of the dominant
+kernel; and the oracle timed on the host's cores.
 """
 from __future__ import annotations
 
@@ -30,6 +39,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E, GB/s
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector
 BANDS = (24, 48, 128)        # neighbour-count bands of the batched kernels (bands 0-2 are tiled)
+FLUSH_BYTES = 1 << 30        # written before every timed step (> 256 MB Infinity Cache)
 
 
 def parse():
@@ -40,22 +50,26 @@ def parse():
     ap.add_argument("--factor", type=int, default=1, help="coarsen the workload (parity/debug only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-rows", action="store_true", help="skip timing the other hot-path steps")
-    ap.add_argument("--poisson", type=int, default=0,
-                    help="also solve the pressure system on a jet cylinder of this many particles")
-    ap.add_argument("--jet", action="store_true",
-                    help="also time the fused step on the 2.0M-particle jet cloud (uneven neighbourhoods)")
-    ap.add_argument("--diff", action="store_true",
-                    help="also time forward + backward of the stencil operator on the 1e6-particle cube")
+    ap.add_argument("--quick", action="store_true",
+                    help="only the headline workload (no jet, differentiation or pressure-solve records)")
+    ap.add_argument("--poisson-n", type=int, default=4_000_000,
+                    help="particles of the projection cylinder of the pressure-solve record")
     ap.add_argument("--advdiff", action="store_true",
                     help="also run the diffusion analogue of the advection-diffusion test (Sec. 7.3) at "
                          "h = 0.06, 0.03, 0.015, and its model-adaptive moving-plate case at h = 0.12, 0.06, 0.03, "
                          "against the exact solutions (convergence study)")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warm-up plus a few steps of the metric path and exit (for rocprofv3)")
+    ap.add_argument("--profile-jet", action="store_true",
+                    help="with --profile-only: the jet cloud's fused step instead of the headline cloud")
     return ap.parse_args()
 
 
 KERNEL_SOURCES = ("weights.hip", "stencil_common.h", "internal.h", "apply.hip")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def measure_hbm(dev):
@@ -113,35 +127,62 @@ def measured_traffic(launch, team):
     return None, None
 
 
-def band_of(n):
-    for b, hi in enumerate(BANDS):
-        if n <= hi:
-            return b
-    return len(BANDS)
-
-
-def algorithmic_costs(rp, model, fused):
-    """Per (model, band) launch of the stencil kernels: rows, nnz, FP64 flops
-    and unique bytes of the FP32-output path.
-    flops/row: Gram n m(m+1) + weighted monomials n m + targets 8 n m
-               + factorisation and inverse ~ m^3/3 + 2 m^3 (+ 8 n applied)
-    bytes/row: 2 n (tile slots) + 16 n (FP32 stencils) + 32 (own x, y, z, h)
-               (+ 8 field value + 32 four results when fused)."""
+def unit_costs(rp, model):
+    """Algorithmic cost of each launch unit of the fused stencil step (per
+    model: the tiled rows with at most 128 neighbours, "tiles", and the rows
+    with more, "b3"), by the per-particle figures of the step's roofline:
+      bytes = 40 n + 52   (FP32 stencils: 4 n index + 16 n stencils written by
+                           the weights, 4 n + 16 n read again by the application,
+                           32 B position and support, 4 B field value, 16 B
+                           for the four results)
+      flops = 2 n m^2 + 4 S n m + 2 S n   (Gram accumulation, stencil
+                           evaluation, application; m monomials, S stencils)
+    with n = |S_i| (self included), m = 10 / 6 and S = 4 / 3 (3D / film)."""
     import numpy as np
     n_i = np.diff(rp)
-    out = {}
     bands = np.searchsorted(np.array(BANDS), n_i, side="left")
-    # launch units: the tiled bands 0-2 of a model run as one launch ("tiles"), band 3 alone
+    out = {}
     for m in (0, 1):
-        M = 10 if m == 0 else 6
+        M, S = (10, 4) if m == 0 else (6, 3)
         for unit, sel in (("tiles", bands <= 2), ("b3", bands == 3)):
-            nn = n_i[(model == m) & sel]
+            nn = n_i[(model == m) & sel].astype(np.float64)
             if nn.size == 0:
                 continue
-            flops = float((nn * (M * (M + 1) + M + 8 * M + (8 if fused else 0))).sum()
-                          + nn.size * (M ** 3 / 3 + 2 * M ** 3))
-            byts = float((18 * nn + (72 if fused else 32)).sum())
-            out[(m, unit)] = dict(rows=int(nn.size), nnz=int(nn.sum()), flops=flops, bytes=byts)
+            out[(m, unit)] = dict(rows=int(nn.size), nnz=int(nn.sum()),
+                                  bytes=float((40.0 * nn + 52.0).sum()),
+                                  flops=float((2 * nn * M * M + 4 * S * nn * M + 2 * S * nn).sum()))
+    return out
+
+
+def per_output_errors(y, y_ref, rp, col, w_ref, u, model, rows=None):
+    """Error of every applied output by the condition-aware metric:
+    max_i |y_i - y_i^ref| / max_i sum_j |c_ij^ref (u_j - u_i)|, per output and
+    model (bulk: gx, gy, gz, lap; film: gt1, gt2 (= gx, gy on a film in the
+    z = 0 plane, whose tangent frame is (e_x, e_y)) and the surface Laplacian).
+    rows: the rows of a sampled record; then y, y_ref [4, len(rows)] hold those
+    rows' outputs and (rp, col, w_ref) their CSR (rp from 0, global columns)."""
+    import numpy as np
+    ids = np.arange(rp.shape[0] - 1) if rows is None else np.asarray(rows)
+    nr = ids.size
+    loc = np.repeat(np.arange(nr), np.diff(rp))
+    own = ids[loc]
+    du = np.where(col == own, 0.0, u[col] - u[own])
+    out = {}
+    names = {0: ("gx", "gy", "gz", "lap"), 1: ("gt1", "gt2", None, "lap_s")}
+    mrow = model[ids]
+    for m, label in ((0, "bulk"), (1, "film")):
+        rsel = mrow == m
+        if not rsel.any():
+            continue
+        rec = {}
+        for s in range(4):
+            name = names[m][s]
+            if name is None:
+                continue
+            scale = np.bincount(loc, np.abs(w_ref[:, s] * du), minlength=nr)[rsel].max()
+            err = np.abs(y[s][rsel] - y_ref[s][rsel]).max()
+            rec[name] = float(err / scale) if scale > 0 else float(err)
+        out[label] = rec
     return out
 
 
@@ -163,15 +204,61 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    t_start = time.time()
     t0 = time.time()
     d = W.mixed_block_film(factor=args.factor)
     N = d["x"].shape[0]
-    print(f"[bench] workload generated: {N} particles ({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
+    log(f"workload generated: {N} particles ({time.time() - t0:.1f}s)")
 
     ctx = g.Context(0)
+    dev = ctx.device
+    flush_buf = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device=dev)
+    flush_src = torch.ones(FLUSH_BYTES // 4, dtype=torch.float32, device=dev)
+
+    def flush():
+        # 1 GiB written, then another 1 GiB read: the caches (L2, 256 MB Infinity Cache) then hold
+        # clean lines of the read buffer, none of the step's inputs, and no write-back is pending
+        flush_buf.fill_(1.0)
+        flush_src.sum()
+
+    def timed(fn, steps, warmup, flushed=True):
+        """Mean ms of one call over `steps` calls after `warmup` untimed ones.
+        flushed: each call bracketed by its own events, after a 1 GiB write."""
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        s = torch.cuda.current_stream()
+        if not flushed:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            for _ in range(steps):
+                fn()
+            e1.record(s)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / steps
+        evs = []
+        for _ in range(steps):
+            flush()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            fn()
+            e1.record(s)
+            evs.append((e0, e1))
+        torch.cuda.synchronize()
+        return sum(a.elapsed_time(b) for a, b in evs) / steps
+
+    def kernels_of(fn, reps):
+        """The library's own HIP-event times of each kernel over `reps` calls."""
+        ctx.profile(True)
+        for _ in range(reps):
+            fn()
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        return {k: {"launches": c, "avg_us": 1000.0 * t / c} for k, (c, t) in prof.items()}
+
     p = g.Particles.from_dict(ctx, d)
     f, *_ = W.test_field(d["x"], d["y"], d["z"])
-    u = torch.as_tensor(f, device=ctx.device)
+    u = torch.as_tensor(f, device=dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     nb = g.build_neighbours(ctx, p)
@@ -180,14 +267,15 @@ def main():
     nnz = nb.nnz
     rp_d, col_d = nb.export()
     rp = rp_d.cpu().numpy()
-    print(f"[bench] neighbours: nnz={nnz} max_row={nb.max_row}", file=sys.stderr, flush=True)
+    col_np = col_d.cpu().numpy()
+    log(f"neighbours: nnz={nnz} max_row={nb.max_row}")
 
-    w32 = torch.empty((nnz, 4), dtype=torch.float32, device=ctx.device)
-    w64 = torch.empty((nnz, 4), dtype=torch.float64, device=ctx.device)
-    y32 = torch.empty((4, N), dtype=torch.float64, device=ctx.device)
-    y64 = torch.empty((4, N), dtype=torch.float64, device=ctx.device)
-    yf = torch.empty((4, N), dtype=torch.float64, device=ctx.device)
-    status = torch.empty(N, dtype=torch.int8, device=ctx.device)
+    w32 = torch.empty((nnz, 4), dtype=torch.float32, device=dev)
+    w64 = torch.empty((nnz, 4), dtype=torch.float64, device=dev)
+    y32 = torch.empty((4, N), dtype=torch.float64, device=dev)
+    y64 = torch.empty((4, N), dtype=torch.float64, device=dev)
+    yf = torch.empty((4, N), dtype=torch.float64, device=dev)
+    status = torch.empty(N, dtype=torch.int8, device=dev)
 
     def step_batched():
         g.gfdm_weights(ctx, p, nb, g.GF_BATCHED, g.GF_F32, out=w32, status=status)
@@ -200,39 +288,36 @@ def main():
     def step_fused():
         g.gfdm_weights_apply(ctx, p, nb, u, 0xF, g.GF_F32, w_out=w32, out=yf, status=status)
 
-    def timed(fn, steps, warmup):
-        for _ in range(warmup):
-            fn()
-        torch.cuda.synchronize()
-        s = torch.cuda.current_stream()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(s)
-        for _ in range(steps):
-            fn()
-        e1.record(s)
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / steps
-
     t0 = time.perf_counter()
     teams = g.autotune(ctx, p, nb, g.GF_F32)
-    print(f"[bench] autotune {time.perf_counter() - t0:.2f}s: {teams}", file=sys.stderr, flush=True)
+    log(f"autotune {time.perf_counter() - t0:.2f}s: {teams}")
 
     if args.profile_only:
-        timed(step_fused, max(args.steps, 1), args.warmup)
-        timed(step_batched, 2, 1)
-        timed(step_plain, 2, 1)
+        if args.profile_jet:
+            dj = W.jet_impact()
+            pj = g.Particles.from_dict(ctx, dj)
+            nbj = g.build_neighbours(ctx, pj)
+            g.autotune(ctx, pj, nbj, g.GF_F32)
+            uj = torch.as_tensor(W.test_field(dj["x"], dj["y"], dj["z"])[0], device=dev)
+            wj = torch.empty((nbj.nnz, 4), dtype=torch.float32, device=dev)
+            yj = torch.empty((4, pj.n), dtype=torch.float64, device=dev)
+            timed(lambda: g.gfdm_weights_apply(ctx, pj, nbj, uj, 0xF, g.GF_F32, w_out=wj, out=yj),
+                  max(args.steps, 1), args.warmup, flushed=False)
+        else:
+            timed(step_fused, max(args.steps, 1), args.warmup, flushed=False)
+            timed(step_batched, 2, 1, flushed=False)
+            timed(step_plain, 2, 1, flushed=False)
         # a plain device copy of known size: calibrates the HBM byte counters
         # (FETCH_SIZE / WRITE_SIZE) read by rocprofv3 for the same run
-        src = torch.ones(1 << 27, dtype=torch.float64, device=ctx.device)   # 1 GiB
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        print("[bench] profile run done (copy calibration: 1 GiB read + 1 GiB written)",
-              file=sys.stderr, flush=True)
+        log("profile run done (copy calibration: 1 GiB read + 1 GiB written)")
         return
 
-    ms_eager = timed(step_fused, args.steps, args.warmup)
+    ms_fused = timed(step_fused, args.steps, args.warmup)
+    ms_fused_b2b = timed(step_fused, args.steps, args.warmup, flushed=False)
     ms_batched = timed(step_batched, args.steps, args.warmup)
     ms_plain = timed(step_plain, args.steps, args.warmup)
     # the same fused step captured once in a HIP graph and replayed; the
@@ -250,64 +335,47 @@ def main():
     graph_ok = bool(torch.equal(w32, w_ref) and torch.equal(yf, y_ref))
     del w_ref, y_ref
     ms_graph = timed(graph.replay, args.steps, args.warmup)
-    use_graph = graph_ok and ms_graph < ms_eager
-    ms_fused = ms_graph if use_graph else ms_eager
-    print(f"[bench] fused eager {ms_eager:.3f} ms  graph {ms_graph:.3f} ms (replay exact: {graph_ok})  "
-          f"separate calls {ms_batched:.3f} ms  plain {ms_plain:.3f} ms", file=sys.stderr, flush=True)
+    ms_graph_b2b = timed(graph.replay, args.steps, args.warmup, flushed=False)
+    del graph
+    log(f"fused {ms_fused:.3f} ms (back to back {ms_fused_b2b:.3f}); graph {ms_graph:.3f} "
+        f"(b2b {ms_graph_b2b:.3f}, replay exact: {graph_ok}); separate calls {ms_batched:.3f}; plain {ms_plain:.3f}")
 
-    # per-kernel times of the metric step (HIP events around each launch)
-    ctx.profile(True)
     reps = max(3, min(args.steps, 10))
-    for _ in range(reps):
-        step_fused()
-    prof = ctx.profile_read()
-    for _ in range(reps):
-        step_batched()
-    prof_sep = ctx.profile_read()
-    for _ in range(reps):
-        step_plain()
-    prof_plain = ctx.profile_read()
-    ctx.profile(False)
-    costs = algorithmic_costs(rp, d["model"], fused=True)
-    kernels = {}
-    for name, (cnt, tot) in prof.items():
-        kernels[name] = {"launches": cnt, "avg_us": 1000.0 * tot / cnt}
-    # dominant kernel: the (model, band) stencil launch with the largest time
-    weights_kernels = {k: v for k, v in kernels.items() if k.startswith("weights_apply_")}
-    dom = max(weights_kernels, key=lambda k: weights_kernels[k]["avg_us"] * weights_kernels[k]["launches"])
-    m_dom = 0 if "_3d_" in dom else 1
-    b_dom = dom.rsplit("_", 1)[1]
-    per_launch_s = kernels[dom]["avg_us"] * 1e-6
-    flops_l = costs[(m_dom, b_dom)]["flops"]
-    bytes_l = costs[(m_dom, b_dom)]["bytes"]
-    tflops = flops_l / per_launch_s / 1e12
-    gbs = bytes_l / per_launch_s / 1e9
-    frac_alu = tflops / PEAK_FP64_TFLOPS
-    frac_hbm = gbs / PEAK_HBM_GBS
-    if frac_alu >= frac_hbm:
-        roof = {"kernel": dom, "bound": "alu", "achieved": round(tflops, 3), "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(frac_alu, 4), "traffic": None}
-    else:
-        roof = {"kernel": dom, "bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": round(frac_hbm, 4), "traffic": None}
-    team_dom = teams["fused"][4 * m_dom + (2 if b_dom == "tiles" else 3)]
-    traffic, traffic_src = measured_traffic(dom, team_dom)
-    roof["traffic"] = round(traffic) if traffic is not None else None
-    if traffic is not None:
-        roof["traffic_note"] = (f"HBM bytes per launch (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-calibrated) "
-                                f"from {traffic_src}; algorithmic bytes {bytes_l}")
-    roof["other_roof"] = {"hbm_GBs": round(gbs, 1), "hbm_frac": round(frac_hbm, 4),
-                          "fp64_TFLOPs": round(tflops, 3), "fp64_frac": round(frac_alu, 4)}
-    roof["algorithmic_per_launch"] = {"flops": flops_l, "bytes": bytes_l, "avg_launch_us": round(per_launch_s * 1e6, 2),
-                                      "rows": costs[(m_dom, b_dom)]["rows"], "nnz": costs[(m_dom, b_dom)]["nnz"]}
+    kernels = kernels_of(step_fused, reps)
+    kernels_sep = kernels_of(step_batched, reps)
+    kernels_plain = kernels_of(step_plain, reps)
 
-    # whole-step HBM view: unique bytes of the fused step (slots, FP32
-    # stencils written, positions, field, four results)
-    step_bytes = float(nnz) * (2 + 16) + N * (32 + 8 + 32)
+    # ---- roofline of the dominant kernel (the largest fused stencil launch)
+    costs = unit_costs(rp, d["model"])
+
+    def roofline(kern, costs_, team_of):
+        wk = {k: v for k, v in kern.items() if k.startswith("weights_apply_")}
+        dom = max(wk, key=lambda k: wk[k]["avg_us"] * wk[k]["launches"])
+        m_dom = 0 if "_3d_" in dom else 1
+        unit = dom.rsplit("_", 1)[1]
+        c = costs_[(m_dom, unit)]
+        sec = wk[dom]["avg_us"] * 1e-6
+        gbs = c["bytes"] / sec / 1e9
+        tfl = c["flops"] / sec / 1e12
+        roof = {"kernel": dom, "bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None}
+        traffic, src = measured_traffic(dom, team_of(m_dom, unit))
+        if traffic is not None:
+            roof["traffic"] = round(traffic)
+            roof["traffic_note"] = (f"HBM bytes per launch (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-calibrated) "
+                                    f"from {src}")
+        roof["algorithmic_per_launch"] = {"bytes": c["bytes"], "flops": c["flops"], "rows": c["rows"],
+                                          "nnz": c["nnz"], "avg_launch_us": round(sec * 1e6, 2),
+                                          "bytes_per_particle": "40 n + 52",
+                                          "flops_per_particle": "2 n m^2 + 4 S n m + 2 S n"}
+        roof["other_roof"] = {"fp64_TFLOPs": round(tfl, 3), "fp64_frac": round(tfl / PEAK_FP64_TFLOPS, 4)}
+        return roof
+
+    roof = roofline(kernels, costs, lambda m, unit: teams["fused"][4 * m + (2 if unit == "tiles" else 3)])
+    step_bytes = sum(c["bytes"] for c in costs.values())
     step_hbm_frac = step_bytes / (ms_fused * 1e-3) / 1e9 / PEAK_HBM_GBS
 
-    # ---- outputs of the metric step (stencils stored by the fused call and
-    # its results), of the separate calls, and of the plain FP64 path
+    # ---- outputs of the metric step, the separate calls and the plain path
     step_batched()
     torch.cuda.synchronize()
     y32n = y32.cpu().numpy()
@@ -316,6 +384,7 @@ def main():
     w32n = w32.double().cpu().numpy()
     w64n = w64.cpu().numpy()
     yfn = yf.cpu().numpy()
+    y64n = y64.cpu().numpy()
 
     result = {
         "metric": "particles/s for GFDM weights+apply; batched-FP32 vs plain-FP64 @1e-6 rel err",
@@ -334,35 +403,36 @@ def main():
         "config": {"workload": "mixed bulk/film cloud: 258,944 jittered-lattice bulk particles beside "
                                "245,000 film particles on z=0, h = 3 x spacing (10 / 6 monomials)",
                    "n_particles": N, "nnz": nnz, "factor": args.factor},
-        "step": ("gf_gfdm_weights_apply: batched stencils stored in FP32 and applied (one call), "
-                 + ("replayed from a HIP graph" if use_graph else "eager launches (faster than the graph replay)")),
-        "fused_eager": {"value": N / (ms_eager * 1e-3), "ms_per_step": ms_eager},
-        "fused_graph": {"value": N / (ms_graph * 1e-3), "ms_per_step": ms_graph, "replay_exact": graph_ok},
+        "step": "gf_gfdm_weights_apply: batched stencils stored in FP32 and applied (one call), eager launches",
+        "timing": "mean of the per-step HIP-event times; before each step 1 GiB is written and another 1 GiB read "
+                  "(Infinity Cache and L2 evicted, no write-back pending)",
+        "fused_back_to_back": {"value": N / (ms_fused_b2b * 1e-3), "ms_per_step": ms_fused_b2b},
+        "fused_graph": {"value": N / (ms_graph * 1e-3), "ms_per_step": ms_graph, "replay_exact": graph_ok,
+                        "ms_per_step_back_to_back": ms_graph_b2b},
         "plain_f64": {"value": N / (ms_plain * 1e-3), "ms_per_step": ms_plain,
                       "step": "gf_gfdm_weights(GF_PLAIN_F64) + gf_apply_stencil"},
         "separate_calls_f32": {"value": N / (ms_batched * 1e-3), "ms_per_step": ms_batched,
                                "step": "gf_gfdm_weights(GF_BATCHED, FP32) + gf_apply_stencil"},
         "speedup_batched_vs_plain": ms_plain / ms_fused,
         "team_sizes": teams,
-        "step_hbm_frac": round(step_hbm_frac, 4),
+        "step_roofline": {"algorithmic_bytes": step_bytes, "GBs": round(step_bytes / (ms_fused * 1e-3) / 1e9, 1),
+                          "hbm_frac": round(step_hbm_frac, 4), "bytes_per_particle": "40 n + 52"},
         "kernels_batched": kernels,
-        "kernels_separate_calls": {k: {"launches": c, "avg_us": 1000.0 * t / c} for k, (c, t) in prof_sep.items()},
-        "kernels_plain": {k: {"launches": c, "avg_us": 1000.0 * t / c} for k, (c, t) in prof_plain.items()},
+        "kernels_separate_calls": kernels_sep,
+        "kernels_plain": kernels_plain,
         "roofline": roof,
     }
-    hbm_meas = measure_hbm(ctx.device)
+    hbm_meas = measure_hbm(dev)
     result["hbm_measured"] = hbm_meas
-    roof["other_roof"]["hbm_frac_of_measured_copy"] = round(gbs / hbm_meas["copy_GBs"], 4)
+    roof["other_roof"]["hbm_frac_of_measured_copy"] = round(roof["achieved"] / hbm_meas["copy_GBs"], 4)
+    log(f"roofline {roof['kernel']}: {roof['achieved']} GB/s = {roof['frac']:.3f} of HBM; step {step_hbm_frac:.3f}")
 
-    # ---- other hot-path steps (timed once each after a warm-up call)
+    # ---- other hot-path steps on the same cloud (timed once each after a warm-up call)
     if not args.no_rows:
         rows = {"build_neighbours_first_ms": t_nbr_first * 1e3}
-
         kern = {}
 
         def once(fn, key=None):
-            """Wall time of one call after a warm-up call; with key, also the
-            library's own per-kernel times of that call."""
             fn()
             torch.cuda.synchronize()
             if key:
@@ -382,20 +452,18 @@ def main():
         rows["classify_pca_ms"], cl = once(lambda: g.classify_pca(ctx, p, nb, xnb, film_height=d["film_height"],
                                                                  h3d=d["h3d"]), "classify_pca")
         flag = cl[3]
-        mass = torch.ones(N, dtype=torch.float64, device=ctx.device)
-        rho = torch.full((N,), 1000.0, dtype=torch.float64, device=ctx.device)
+        mass = torch.ones(N, dtype=torch.float64, device=dev)
+        rho = torch.full((N,), 1000.0, dtype=torch.float64, device=dev)
         # this cloud flags no particle (its bottom walls see interior neighbours only): the transition is
         # timed with every bulk wall particle flagged, which deletes the layers above the bottom
-        tflag = torch.as_tensor(((d["model"] == 0) & (d["kind"] == W.WALL)).astype(np.uint8), device=ctx.device)
+        tflag = torch.as_tensor(((d["model"] == 0) & (d["kind"] == W.WALL)).astype(np.uint8), device=dev)
         rows["transition_ms"], _ = once(lambda: g.transition_3d_to_2d(ctx, p, nb, tflag, mass, rho, u), "transition")
         rows["apply_ms"], _ = once(lambda: g.apply_stencil(ctx, nb, w32, u, 0xF, out=y32), "apply")
-        ybar = torch.ones((1, N), dtype=torch.float64, device=ctx.device)
+        ybar = torch.ones((1, N), dtype=torch.float64, device=dev)
         rows["apply_adjoint_ms"], _ = once(lambda: g.apply_stencil_adjoint(ctx, nb, w32, ybar, g.OP_LAP),
                                            "apply_adjoint")
         rows["weights_adjoint_ms"], _ = once(lambda: g.gfdm_weights_adjoint(ctx, p, nb, u, ybar, g.OP_LAP),
                                              "weights_adjoint")
-        # coupling layer: film height (Eq. Height), ghost particles of the buffer zone (Alg. 5), and the
-        # stencils over the extended neighbourhoods (regular + ghost particles, Sec. 6.2)
         rows["film_height_ms"], _ = once(lambda: g.film_height(ctx, p, nb, d["diam"]), "film_height")
         rows["buffer_zone_ms"], bz = once(lambda: g.buffer_zone(ctx, p, nb, xnb, d["film_height"], d["h_other"],
                                                                 d["mass"], d["rho"]), "buffer_zone")
@@ -403,7 +471,7 @@ def main():
         pe = g.extend_particles(ctx, p, ghosts)
         rows["extended_build_ms"], nbe = once(lambda: g.build_neighbours(ctx, pe, n_rows=N), "extended_build")
         ue = torch.cat([u, torch.as_tensor(W.test_field(ghosts["x"].cpu().numpy(), ghosts["y"].cpu().numpy(),
-                                                        ghosts["z"].cpu().numpy())[0], device=ctx.device)])
+                                                        ghosts["z"].cpu().numpy())[0], device=dev)])
         rows["extended_weights_apply_ms"], _ = once(
             lambda: g.gfdm_weights_apply(ctx, pe, nbe, ue, wtype=g.GF_F32, store_weights=False),
             "extended_weights_apply")
@@ -413,8 +481,8 @@ def main():
         del nbe, pe
         result["rows"] = rows
         result["rows_kernels_us"] = kern
-        # algorithmic bytes of each row: per particle (N) and per neighbour entry (nnz) the bytes a
-        # row must read or write at least once
+        # algorithmic bytes of each row (per particle N and per neighbour entry nnz, each byte a row
+        # must read or write at least once)
         film_nnz = float((np.diff(rp)[d["model"] == 1]).sum())
         row_bytes = {"build_neighbours": 4.0 * nnz + 41.0 * N, "classify_pca": 4.0 * nnz + 106.0 * N,
                      "apply": 18.0 * nnz + 40.0 * N, "transition": 4.0 * nnz + 48.0 * N,
@@ -431,54 +499,218 @@ def main():
                                   "frac_of_measured_copy": round(byts / (us * 1e-6) / 1e9 / hbm_meas["copy_GBs"], 4)}
         result["rows_roofline"] = roof_rows
         result["flags"] = {"bulk_to_film": int((flag == 1).sum().item()), "film_to_bulk": int((flag == 2).sum().item())}
+        log(f"rows {rows}")
 
-    if args.poisson:
-        dp = W.projection_cylinder(args.poisson)
+    # ---- jet-on-plate cloud: uneven neighbourhoods (20-250), the fused step
+    jet_eval = None
+    if not args.quick:
+        dj = W.jet_impact()
+        pj = g.Particles.from_dict(ctx, dj)
+        nbj = g.build_neighbours(ctx, pj)
+        rpj = nbj.export()[0].cpu().numpy()
+        teams_j = g.autotune(ctx, pj, nbj, g.GF_F32)
+        fj = W.test_field(dj["x"], dj["y"], dj["z"])[0]
+        uj = torch.as_tensor(fj, device=dev)
+        wj = torch.empty((nbj.nnz, 4), dtype=torch.float32, device=dev)
+        yj = torch.empty((4, pj.n), dtype=torch.float64, device=dev)
+        stj = torch.empty(pj.n, dtype=torch.int8, device=dev)
+        step_j = lambda: g.gfdm_weights_apply(ctx, pj, nbj, uj, 0xF, g.GF_F32, w_out=wj, out=yj, status=stj)
+        ms_j = timed(step_j, args.steps, args.warmup)
+        w64j = torch.empty((nbj.nnz, 4), dtype=torch.float64, device=dev)
+        y64j = torch.empty((4, pj.n), dtype=torch.float64, device=dev)
+
+        def step_jp():
+            g.gfdm_weights(ctx, pj, nbj, g.GF_PLAIN_F64, g.GF_F64, out=w64j)
+            g.apply_stencil(ctx, nbj, w64j, uj, 0xF, out=y64j)
+
+        ms_jp = timed(step_jp, max(3, args.steps // 2), 1)
+        kern_j = kernels_of(step_j, 3)
+        costs_j = unit_costs(rpj, dj["model"])
+        roof_j = roofline(kern_j, costs_j, lambda m, unit: teams_j["fused"][4 * m + (2 if unit == "tiles" else 3)])
+        step_j()
+        torch.cuda.synchronize()
+        counts = np.bincount(stj.cpu().numpy().astype(np.int64), minlength=4)
+        nrow = np.diff(rpj)
+        result["jet"] = {
+            "workload": "jet impact: 1.0M bulk particles in a cylinder (r 0.05, height 0.2) above 1.0M film "
+                        "particles on z = 0 (density ~ 1/r), lognormal h (sigma 0.3)",
+            "n": pj.n, "nnz": nbj.nnz, "neighbours_min_p50_max": [int(nrow.min()), int(np.median(nrow)),
+                                                                  int(nrow.max())],
+            "ms_per_step": ms_j, "value": pj.n / (ms_j * 1e-3), "unit": "particles/s",
+            "plain_f64": {"ms_per_step": ms_jp, "value": pj.n / (ms_jp * 1e-3)},
+            "speedup_batched_vs_plain": ms_jp / ms_j,
+            "step_hbm_frac": round(sum(c["bytes"] for c in costs_j.values()) / (ms_j * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+            "roofline": roof_j, "team_sizes": teams_j,
+            "status_counts": {"ok": int(counts[0]), "qr_fallback": int(counts[1]),
+                              "rank_deficient": int(counts[2]), "too_few": int(counts[3])},
+            "kernels": kern_j}
+        # a sample of 20,000 rows for the errors against the oracle (their stencils and outputs)
+        samp = np.sort(np.random.default_rng(13).choice(pj.n, 20000, replace=False))
+        sel = torch.as_tensor(np.concatenate([np.arange(rpj[i], rpj[i + 1]) for i in samp]), device=dev)
+        si = torch.as_tensor(samp, device=dev)
+        jet_eval = (dj, fj, samp, rpj, wj[sel].double().cpu().numpy(), yj[:, si].cpu().numpy(),
+                    w64j[sel].cpu().numpy(), y64j[:, si].cpu().numpy())
+        del sel, si
+        log(f"jet: {ms_j:.3f} ms per fused step (plain {ms_jp:.3f}); {roof_j['kernel']} {roof_j['frac']:.3f} of HBM")
+        del pj, nbj, uj, wj, yj, stj, w64j, y64j
+
+    # ---- differentiation cube: forward + backward of the Laplacian loss
+    if not args.quick:
+        dd = W.diff_cube()
+        pd = g.Particles.from_dict(ctx, dd)
+        nbd = g.build_neighbours(ctx, pd)
+        ud = torch.as_tensor(dd["u"], device=dev)
+        gd = torch.as_tensor(dd["g"], device=dev)
+        xs = [torch.as_tensor(dd[k], device=dev) for k in ("x", "y", "z")]
+
+        def fwd_bwd():
+            ur = ud.clone().requires_grad_(True)
+            xr, yr, zr = (t.clone().requires_grad_(True) for t in xs)
+            out = g.stencil_op(ctx, pd, nbd, ur, xr, yr, zr, op_mask=g.OP_LAP, wtype=g.GF_F32)
+            loss = ((out[0] - gd) ** 2).sum()
+            return torch.autograd.grad(loss, (ur, xr, yr, zr))
+
+        ms_d = timed(fwd_bwd, max(3, args.steps // 4), 1)
+        result["differentiation"] = {
+            "workload": "10^6 jittered-lattice particles (s = 0.01, h = 3 s); loss sum (Lap_h u - g)^2, "
+                        "gradients with respect to u and the positions",
+            "n": pd.n, "nnz": nbd.nnz, "ms_forward_backward": ms_d, "value": pd.n / (ms_d * 1e-3),
+            "unit": "particles/s", "kernels": kernels_of(fwd_bwd, 1)}
+        log(f"differentiation: {ms_d:.3f} ms forward+backward")
+        del dd, pd, nbd, ud, gd, xs
+
+    # ---- pressure-Poisson solve on the 4.0M projection cylinder
+    if not args.quick and args.poisson_n > 0:
+        dp = W.projection_cylinder(args.poisson_n)
         pp = g.Particles.from_dict(ctx, dp)
         nbp = g.build_neighbours(ctx, pp)
         wp = g.gfdm_weights(ctx, pp, nbp, g.GF_BATCHED, g.GF_F64)
         val = g.poisson_assemble(ctx, pp, nbp, wp, dp["row_type"])
         rpp, colp = nbp.export()
         A = torch.sparse_csr_tensor(rpp, colp.long(), val, size=(pp.n, pp.n))
-        b = (A @ torch.as_tensor(dp["pstar"], device=ctx.device).unsqueeze(1)).squeeze(1)
+        pstar = torch.as_tensor(dp["pstar"], device=dev)
+        b = (A @ pstar.unsqueeze(1)).squeeze(1)
+        del A, val, rpp, colp
         ps = {}
-        ps_n, ps_nnz = pp.n, nbp.nnz
-        for mixed in (0, 1):
-            # one untimed solve, one timed solve, one profiled solve (per-iteration launch times)
-            g.poisson_solve(ctx, pp, nbp, wp, dp["row_type"], b, params=g.solve_params(mixed=mixed),
-                            raise_on_fail=False)
+        for mixed, label in ((0, "plain_f64"), (1, "mixed_f32_matrix"), (2, "mixed_ir_f32_vectors")):
+            prm = g.solve_params(mixed=mixed)
+            g.poisson_solve(ctx, pp, nbp, wp, dp["row_type"], b, params=prm, raise_on_fail=False)   # warm-up
+            flush()
             torch.cuda.synchronize()
-            t = time.perf_counter()
-            x, st = g.poisson_solve(ctx, pp, nbp, wp, dp["row_type"], b, params=g.solve_params(mixed=mixed),
-                                    raise_on_fail=False)
-            torch.cuda.synchronize()
-            el = time.perf_counter() - t
+            x, st = g.poisson_solve(ctx, pp, nbp, wp, dp["row_type"], b, params=prm, raise_on_fail=False)
+            err = ((x - pstar).norm() / pstar.norm()).item()
             ctx.profile(True)
-            g.poisson_solve(ctx, pp, nbp, wp, dp["row_type"], b, params=g.solve_params(mixed=mixed),
-                            raise_on_fail=False)
+            g.poisson_solve(ctx, pp, nbp, wp, dp["row_type"], b, params=prm, raise_on_fail=False)
             prof_p = ctx.profile_read()
             ctx.profile(False)
-            err = ((x - torch.as_tensor(dp["pstar"], device=ctx.device)).norm() /
-                   torch.as_tensor(dp["pstar"], device=ctx.device).norm()).item()
-            rec = dict(seconds=el, err_vs_pstar=err, **st)
-            # one Jacobi-BiCGStab iteration: two SpMV on the neighbour tiles (value + 2-byte slot
-            # per entry; the vector is staged per tile) and the vector updates (26 vector passes)
-            for name, vb in (("bicgstab_iter_f64", 8), ("bicgstab_iter_f32", 4)):
+            rec = dict(err_vs_pstar=err, **st)
+            # one Jacobi-BiCGStab iteration: two SpMV on the neighbour tiles (value + 2-byte slot per
+            # entry; the vector staged per tile) and the vector passes (26 per iteration)
+            for name, vb, xb in (("bicgstab_iter_f64", 8, 8), ("bicgstab_iter_f32val", 4, 8),
+                                 ("bicgstab_iter_f32", 4, 4)):
                 if name in prof_p:
                     cnt, tot = prof_p[name]
                     it_s = tot / cnt * 1e-3
-                    byts = 2.0 * ps_nnz * (vb + 2) + 26.0 * vb * ps_n
-                    rec[name] = {"iterations": cnt, "avg_us": round(it_s * 1e6, 1),
-                                 "algorithmic_bytes": byts, "GBs": round(byts / it_s / 1e9, 1),
-                                 "hbm_frac": round(byts / it_s / 1e9 / PEAK_HBM_GBS, 4),
-                                 "frac_of_measured_copy": round(byts / it_s / 1e9 / hbm_meas["copy_GBs"], 4)}
-            ps["mixed" if mixed else "plain_f64"] = rec
-            print(f"[bench] poisson mixed={mixed}: {el:.3f}s {rec}", file=sys.stderr, flush=True)
-        result["poisson"] = {"n": ps_n, "nnz": ps_nnz, **ps}
-        del dp, pp, nbp, wp, val, A, b, x
+                    byts = 2.0 * nbp.nnz * (vb + 2) + 26.0 * xb * pp.n
+                    rec[name] = {"iterations": cnt, "avg_us": round(it_s * 1e6, 1), "algorithmic_bytes": byts,
+                                 "GBs": round(byts / it_s / 1e9, 1),
+                                 "hbm_frac": round(byts / it_s / 1e9 / PEAK_HBM_GBS, 4)}
+            ps[label] = rec
+            log(f"poisson {label}: {st['seconds']:.3f}s, {st['inner_its_total']} iterations, error {err:.2e}")
+        result["poisson"] = {
+            "workload": "projection cylinder: bulk jet cylinder (r 0.05, height 0.2), uniform h = 3 s, "
+                        "Laplacian rows inside, plain Neumann rows on the bottom wall, Dirichlet on the free "
+                        "surface; b = A p*, p* = sin(20x+1) cos(20y) (1+5z); Jacobi-BiCGStab to 1e-8",
+            "n": pp.n, "nnz": nbp.nnz, **ps,
+            "speedup_mixed_vs_f64": ps["plain_f64"]["seconds"] / ps["mixed_f32_matrix"]["seconds"]}
+        del dp, pp, nbp, wp, b, pstar, x
 
+    # ---- CPU oracle: baseline and per-output errors (oracle inputs never come from the device)
+    if not args.no_cpu_baseline:
+        import ctypes
+
+        import oracle
+        t0 = time.perf_counter()
+        rp_o, col_o = oracle.neighbours(d)
+        t_nbr_o = time.perf_counter() - t0
+        assert np.array_equal(rp_o, rp) and np.array_equal(col_o, col_np), "neighbour lists differ"
+        # the whole cloud's stencils and outputs (the error reference), repeated until ~10 s of wall time
+        passes, t_all = 0, 0.0
+        while passes < 1 or (t_all < 10.0 and passes < 40):
+            t0 = time.perf_counter()
+            w_o, st_o, _ = oracle.gfdm_weights(d, rp_o, col_o)
+            y_o = oracle.apply(rp_o, col_o, w_o, f)
+            t_all += time.perf_counter() - t0
+            passes += 1
+        t_o = t_all / passes
+        try:
+            gomp = ctypes.CDLL("libgomp.so.1")
+            cores = int(gomp.omp_get_max_threads())
+        except OSError:
+            gomp, cores = None, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        cpu_model = "unknown"
+        try:
+            with open("/proc/cpuinfo") as fh:
+                for line in fh:
+                    if line.startswith("model name"):
+                        cpu_model = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+        # one core: a sample of 20,000 rows (every 25th), stencils + application
+        one_core = None
+        if gomp is not None:
+            sample = np.arange(0, N, max(1, N // 20000))
+            gomp.omp_set_num_threads(1)
+            t0 = time.perf_counter()
+            w_s, _, _ = oracle.gfdm_weights(d, rp_o, col_o, rows=sample)
+            oracle.apply(rp_o, col_o, w_s, f)
+            t1 = time.perf_counter() - t0
+            gomp.omp_set_num_threads(cores)
+            one_core = {"value": sample.size / t1, "unit": "particles/s", "cores": 1,
+                        "sample": f"{sample.size} rows (every {max(1, N // 20000)}th), stencils + application "
+                                  f"({t1:.2f} s; the application pass runs over all rows, with zero stencils "
+                                  f"outside the sample)"}
+        result["cpu_baseline"] = {"value": N / t_o, "unit": "particles/s", "cores": cores, "kind": "oracle",
+                                  "cpu_model": cpu_model,
+                                  "sample": f"all {N} particles of the workload, stencils + application, mean of "
+                                            f"{passes} passes ({t_o:.2f} s each; neighbour search "
+                                            f"{t_nbr_o:.2f} s not included)",
+                                  "one_core": one_core}
+        e32 = oracle.operator_error(w32n, w_o, rp_o)
+        e64 = oracle.operator_error(w64n, w_o, rp_o)
+        result["operator_error"] = {
+            "metric": "per row and stencil |c - c_ref|_2 / |c_ref|_2 against the FP64 oracle (Householder QR)",
+            "batched_f32_max": float(e32.max()), "batched_f32_p9999": float(np.quantile(e32, 0.9999)),
+            "plain_f64_max": float(e64.max())}
+        result["output_error"] = {
+            "metric": "max_i |y_i - y_ref_i| / max_i sum_j |c_ref_ij (u_j - u_i)| per output and model",
+            "fused_f32_stencils": per_output_errors(yfn, y_o, rp_o, col_o, w_o, f, d["model"]),
+            "separate_calls_f32_stencils": per_output_errors(y32n, y_o, rp_o, col_o, w_o, f, d["model"]),
+            "plain_f64": per_output_errors(y64n, y_o, rp_o, col_o, w_o, f, d["model"])}
+        log(f"oracle {t_o:.2f}s on {cores} cores; f32 err max {e32.max():.2e}, f64 err max {e64.max():.2e}")
+        if jet_eval is not None:
+            dj, fj, samp, rpj, wjn, yjn, w64jn, y64jn = jet_eval
+            rpj_o, colj_o = oracle.neighbours(dj)
+            assert np.array_equal(rpj_o, rpj), "jet neighbour lists differ"
+            wj_o, stj_o, _ = oracle.gfdm_weights(dj, rpj_o, colj_o, rows=samp)
+            yj_o = oracle.apply(rpj_o, colj_o, wj_o, fj)[:, samp]
+            sel = np.concatenate([np.arange(rpj_o[i], rpj_o[i + 1]) for i in samp])
+            sub = np.concatenate([[0], np.cumsum(np.diff(rpj_o)[samp])])
+            wj_o, colj_s = wj_o[sel], colj_o[sel]
+            del colj_o
+            ej = oracle.operator_error(wjn, wj_o, sub)
+            ej64 = oracle.operator_error(w64jn, wj_o, sub)
+            result["jet"]["operator_error"] = {"batched_f32_max": float(ej.max()), "plain_f64_max": float(ej64.max()),
+                                               "sample": "20,000 random rows"}
+            result["jet"]["output_error"] = {
+                "fused_f32_stencils": per_output_errors(yjn, yj_o, sub, colj_s, wj_o, fj, dj["model"], rows=samp),
+                "plain_f64": per_output_errors(y64jn, yj_o, sub, colj_s, wj_o, fj, dj["model"], rows=samp)}
+            log(f"jet operator error f32 {ej.max():.2e}")
+
+    # ---- the convergence study of the advection-diffusion analogue (not part of the default run)
     if args.advdiff:
-        from paper_2405_13165_amd.advdiff import DiffusionPlate
+        from paper_2405_13165_amd.advdiff import AdvectPlate, DiffusionPlate
         kappa, t_end = 5e-3, 0.5
         study = []
         for hh in (0.06, 0.03, 0.015):
@@ -496,10 +728,8 @@ def main():
                 rec["order_eps2"] = round(float(np.log2(study[-1]["eps2"] / rec["eps2"])), 2)
                 rec["order_epsinf"] = round(float(np.log2(study[-1]["epsinf"] / rec["epsinf"])), 2)
             study.append(rec)
-            print(f"[bench] advdiff {rec}", file=sys.stderr, flush=True)
+            log(f"advdiff {rec}")
             del plate
-        # the moving plate: both transitions, ghosts, stencils and solve every step
-        from paper_2405_13165_amd.advdiff import AdvectPlate
         t_adv = 2.0
         moving = []
         for hh in (0.12, 0.06, 0.03):
@@ -517,178 +747,11 @@ def main():
                 rec["order_eps2"] = round(float(np.log2(moving[-1]["eps2"] / rec["eps2"])), 2)
                 rec["order_epsinf"] = round(float(np.log2(moving[-1]["epsinf"] / rec["epsinf"])), 2)
             moving.append(rec)
-            print(f"[bench] advect {rec}", file=sys.stderr, flush=True)
-        # the paper's configuration (Sec. 7.3, Table 2): plate [0,4]x[0,3], disc of radius 0.2 at
-        # (0.5, 0.5), errors against a fine full-3D run of the same case at the nearest particle
-        from scipy.spatial import cKDTree
-        geo = dict(lx=4.0, ly=3.0, ic="disc", center=(0.5, 0.5))
-        h_ref = 0.025
-        dref = W.advect_plate(h_ref, **geo)
-        steps = int(np.ceil(t_adv / (0.25 * 0.05 * h_ref * h_ref / kappa)))
-        cref, iref = AdvectPlate(ctx, dref, kappa, t_adv / steps, x0=-np.inf, x1=np.inf).run(steps)
-        print(f"[bench] advect full-3D reference h={h_ref}: {iref}", file=sys.stderr, flush=True)
-        tree = cKDTree(np.stack([cref[k].cpu().numpy() for k in ("x", "y", "z")], 1))
-        Tref_all = cref["T"].cpu().numpy()
-        table2 = {0.2: (6.61e-2, 7.79e-2), 0.1: (2.35e-2, 3.67e-2), 0.05: (1.14e-2, 1.68e-2)}
-        paper_cfg = []
-        for hh in (0.2, 0.1, 0.05):
-            da = W.advect_plate(hh, **geo)
-            steps = int(np.ceil(t_adv / (0.25 * 0.05 * hh * hh / kappa)))
-            ap = AdvectPlate(ctx, da, kappa, t_adv / steps)
-            ap.step()
-            n3, n2 = int((ap.c["model"] == 0).sum()), int((ap.c["model"] == 1).sum())
-            c, info = ap.run(steps - 1)
-            Ta = c["T"].cpu().numpy()
-            _, I = tree.query(np.stack([c[k].cpu().numpy() for k in ("x", "y", "z")], 1))
-            Tr = Tref_all[I]
-            ms = ((Ta - Tr) ** 2).sum() / (Tr ** 2).sum()
-            rec = {"h": hh, "n_3d_after_first_step": n3, "n_2d_after_first_step": n2, "steps": steps,
-                   "eps2": float(np.sqrt(ms)), "eps2_no_sqrt": float(ms),
-                   "epsinf": float(np.abs(Ta - Tr).max() / np.abs(Tr).max()),
-                   "paper_eps2": table2[hh][0], "paper_epsinf": table2[hh][1],
-                   "seconds": round(info["seconds"], 3), "bicgstab_its": info["bicgstab_its"]}
-            if paper_cfg:
-                rec["order_eps2"] = round(float(np.log2(paper_cfg[-1]["eps2"] / rec["eps2"])), 2)
-                rec["order_epsinf"] = round(float(np.log2(paper_cfg[-1]["epsinf"] / rec["epsinf"])), 2)
-            paper_cfg.append(rec)
-            print(f"[bench] advect paper configuration {rec}", file=sys.stderr, flush=True)
+            log(f"advect {rec}")
         result["advdiff"] = {"kappa": kappa, "t_end": t_end, "study": study,
-                             "moving": {"t_end": t_adv, "window": [1.0, 2.0], "study": moving},
-                             "paper_configuration": {"reference": {"h": h_ref, "n": int(dref["x"].size),
-                                                                   "n_3d": iref["max_n"],
-                                                                   "seconds": round(iref["seconds"], 3)},
-                                                     "study": paper_cfg}}
+                             "moving": {"t_end": t_adv, "window": [1.0, 2.0], "study": moving}}
 
-    if args.jet:
-        dj = W.jet_impact()
-        pj = g.Particles.from_dict(ctx, dj)
-        nbj = g.build_neighbours(ctx, pj)
-        teams_j = g.autotune(ctx, pj, nbj, g.GF_F32)
-        uj = torch.as_tensor(W.test_field(dj["x"], dj["y"], dj["z"])[0], device=ctx.device)
-        wj = torch.empty((nbj.nnz, 4), dtype=torch.float32, device=ctx.device)
-        yj = torch.empty((4, pj.n), dtype=torch.float64, device=ctx.device)
-        stj = torch.empty(pj.n, dtype=torch.int8, device=ctx.device)
-        ms_j = timed(lambda: g.gfdm_weights_apply(ctx, pj, nbj, uj, 0xF, g.GF_F32, w_out=wj, out=yj, status=stj),
-                     args.steps, args.warmup)
-        ctx.profile(True)
-        g.gfdm_weights_apply(ctx, pj, nbj, uj, 0xF, g.GF_F32, w_out=wj, out=yj, status=stj)
-        prof_j = ctx.profile_read()
-        ctx.profile(False)
-        counts = np.bincount(stj.cpu().numpy().astype(np.int64), minlength=4)
-        # neighbour builds (same and cross model), wall time of one build after a warm-up
-        build_ms = {}
-        for cross in (False, True):
-            g.build_neighbours(ctx, pj, cross_model=cross).close()
-            best = float("inf")
-            for _ in range(3):
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                nbx = g.build_neighbours(ctx, pj, cross_model=cross)
-                torch.cuda.synchronize()
-                best = min(best, (time.perf_counter() - t0) * 1e3)
-                nbx.close()
-            build_ms["cross_model" if cross else "same_model"] = round(best, 3)
-        result["jet"] = {"n": pj.n, "nnz": nbj.nnz, "max_row": nbj.max_row, "ms_per_step": ms_j,
-                         "build_neighbours_ms": build_ms, "team_sizes": teams_j,
-                         "value": pj.n / (ms_j * 1e-3), "unit": "particles/s",
-                         "status_counts": {"ok": int(counts[0]), "qr_fallback": int(counts[1]),
-                                           "rank_deficient": int(counts[2]), "too_few": int(counts[3])},
-                         "kernels": {k: {"launches": c, "avg_us": 1000.0 * t / c} for k, (c, t) in prof_j.items()}}
-        print(f"[bench] jet: {ms_j:.3f} ms per fused step", file=sys.stderr, flush=True)
-        del dj, pj, nbj, uj, wj, yj, stj
-
-    if args.diff:
-        dd = W.diff_cube()
-        pd = g.Particles.from_dict(ctx, dd)
-        nbd = g.build_neighbours(ctx, pd)
-        ud = torch.as_tensor(dd["u"], device=ctx.device)
-        gd = torch.as_tensor(dd["g"], device=ctx.device)
-        xs = [torch.as_tensor(dd[k], device=ctx.device) for k in ("x", "y", "z")]
-
-        def fwd_bwd():
-            ur = ud.clone().requires_grad_(True)
-            xr, yr, zr = (t.clone().requires_grad_(True) for t in xs)
-            out = g.stencil_op(ctx, pd, nbd, ur, xr, yr, zr, op_mask=g.OP_LAP, wtype=g.GF_F32)
-            loss = ((out[0] - gd) ** 2).sum()
-            return torch.autograd.grad(loss, (ur, xr, yr, zr))
-
-        ms_d = timed(fwd_bwd, max(3, args.steps // 4), 1)
-        result["differentiation"] = {"n": pd.n, "nnz": nbd.nnz, "ms_forward_backward": ms_d,
-                                     "value": pd.n / (ms_d * 1e-3), "unit": "particles/s"}
-        print(f"[bench] differentiation: {ms_d:.3f} ms forward+backward", file=sys.stderr, flush=True)
-        del dd, pd, nbd
-
-    # ---- CPU oracle baseline and operator error (oracle inputs never come from the device)
-    if not args.no_cpu_baseline:
-        import oracle
-        t0 = time.perf_counter()
-        rp_o, col_o = oracle.neighbours(d)
-        t_nbr_o = time.perf_counter() - t0
-        assert np.array_equal(rp_o, rp) and np.array_equal(col_o, col_d.cpu().numpy()), "neighbour lists differ"
-        # repeat the full pass until about 10 s of wall time have been spent
-        passes, t_all = 0, 0.0
-        while passes < 1 or (t_all < 10.0 and passes < 40):
-            t0 = time.perf_counter()
-            w_o, st_o, _ = oracle.gfdm_weights(d, rp_o, col_o)
-            y_o = oracle.apply(rp_o, col_o, w_o, f)
-            t_all += time.perf_counter() - t0
-            passes += 1
-        t_o = t_all / passes
-        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        # the other rows, once each on the same cloud (same inputs as the GPU rows above)
-        orows = {"build_neighbours_s": t_nbr_o}
-        if not args.no_rows:
-            xr_o, xc_o = oracle.neighbours(d, cross=True)   # input of the classification, not timed
-            t0 = time.perf_counter()
-            lam_o, w3_o, eps_o = oracle.pca(d, rp_o, col_o)
-            oracle.classify(d, rp_o, col_o, eps_o, w3_o, cross=(xr_o, xc_o), film_height=d["film_height"],
-                            h3d=d["h3d"])
-            orows["classify_pca_s"] = time.perf_counter() - t0
-            t0 = time.perf_counter()
-            oracle.apply(rp_o, col_o, w_o, f)
-            orows["apply_s"] = time.perf_counter() - t0
-            tflag_o = ((d["model"] == 0) & (d["kind"] == W.WALL)).astype(np.uint8)
-            t0 = time.perf_counter()
-            oracle.transition_3d_to_2d(d, rp_o, col_o, tflag_o, np.ones(N), np.full(N, 1000.0), f)
-            orows["transition_s"] = time.perf_counter() - t0
-            yb_o = np.ones((1, N))
-            t0 = time.perf_counter()
-            oracle.apply_adjoint(rp_o, col_o, w_o, yb_o, 8)
-            orows["apply_adjoint_s"] = time.perf_counter() - t0
-            t0 = time.perf_counter()
-            oracle.weights_adjoint_x(d, rp_o, col_o, f, yb_o, 8)
-            orows["weights_adjoint_s"] = time.perf_counter() - t0
-            t0 = time.perf_counter()
-            oracle.film_height(d, rp_o, col_o, d["diam"])
-            orows["film_height_s"] = time.perf_counter() - t0
-            t0 = time.perf_counter()
-            oracle.buffer_zone(d, xr_o, xc_o, d["film_height"], d["h_other"], d["mass"], d["rho"])
-            orows["buffer_zone_s"] = time.perf_counter() - t0
-            for key in ("classify_pca", "apply", "transition", "apply_adjoint", "weights_adjoint",
-                        "film_height", "buffer_zone"):
-                if key in result.get("rows_roofline", {}):
-                    rr = result["rows_roofline"][key]
-                    rr["oracle_s"] = round(orows[key + "_s"], 4)
-                    rr["speedup_vs_oracle"] = round(orows[key + "_s"] / (rr["kernel_us"] * 1e-6), 1)
-            if "build_neighbours" in result.get("rows_roofline", {}):
-                rr = result["rows_roofline"]["build_neighbours"]
-                rr["oracle_s"] = round(t_nbr_o, 4)
-                rr["speedup_vs_oracle"] = round(t_nbr_o / (rr["kernel_us"] * 1e-6), 1)
-        result["oracle_rows_s"] = orows
-        e32 = oracle.operator_error(w32n, w_o, rp_o)
-        e64 = oracle.operator_error(w64n, w_o, rp_o)
-        result["cpu_baseline"] = {"value": N / t_o, "unit": "particles/s", "cores": cores, "kind": "oracle",
-                                  "sample": f"all {N} particles of the workload, weights + apply, mean of "
-                                            f"{passes} passes ({t_o:.2f} s each; neighbour search "
-                                            f"{t_nbr_o:.1f} s not included)"}
-        result["operator_error"] = {
-            "batched_f32_max": float(e32.max()), "batched_f32_p9999": float(np.quantile(e32, 0.9999)),
-            "plain_f64_max": float(e64.max()),
-            "fused_apply_max_abs_rel": float(np.max(np.abs(yfn - y_o)) / np.max(np.abs(y_o))),
-            "separate_apply_max_abs_rel": float(np.max(np.abs(y32n - y_o)) / np.max(np.abs(y_o))),
-        }
-        print(f"[bench] oracle {t_o:.1f}s; f32 err max {e32.max():.2e}, f64 err max {e64.max():.2e}",
-              file=sys.stderr, flush=True)
+    result["bench_wall_s"] = round(time.time() - t_start, 1)
     print(json.dumps(result), flush=True)
 
 

@@ -53,8 +53,11 @@ typedef enum { GF_F64 = 0, GF_F32 = 1 } gf_dtype;
  *                system is solved in FP64; particles whose condition number
  *                exceeds kappa_max are re-solved by an FP64 Householder QR.
  *                Weights out in FP64 or FP32.  With FP32 output the support
- *                weights w(q) are evaluated in FP32 as well. */
-typedef enum { GF_PLAIN_F64 = 0, GF_BATCHED = 1 } gf_prec;
+ *                weights w(q) are evaluated in FP32 as well.
+ *  GF_F32_QR_FALLBACK64 is another name of GF_BATCHED: FP32 stencils
+ *                (storage and support weights), each particle's condition
+ *                estimate triggering the FP64 Householder QR fallback. */
+typedef enum { GF_PLAIN_F64 = 0, GF_BATCHED = 1, GF_F32_QR_FALLBACK64 = 1 } gf_prec;
 
 enum { GF_OP_DX = 1, GF_OP_DY = 2, GF_OP_DZ = 4, GF_OP_LAP = 8 };
 
@@ -136,6 +139,12 @@ gf_status gf_build_neighbours_rows(gf_ctx *ctx, const gf_particles *p, int cross
                                    gf_nbr **out);
 /* n, nnz and the longest row of a neighbour handle (host outputs, any NULL). */
 gf_status gf_nbr_info(const gf_nbr *nbr, int64_t *n, int64_t *nnz, int32_t *max_row);
+/* The handle's own CSR lists of Eq. (Nbd) without a copy: *row_ptr
+ * ([n+1] int64) and *col ([nnz] int32, user indices, rows ascending) are
+ * device pointers owned by the handle, valid until gf_nbr_free; the caller
+ * must not write through them.  Any output may be NULL.  Host call, no
+ * device work. */
+gf_status gf_nbr_view(const gf_nbr *nbr, int64_t *nnz, const int64_t **row_ptr, const int32_t **col);
 /* Copy the CSR lists into caller buffers (device): row_ptr [n+1] int64,
  * col [nnz] int32 (user indices, rows ascending).  Either may be NULL. */
 gf_status gf_nbr_export(gf_ctx *ctx, const gf_nbr *nbr, int64_t *row_ptr, int32_t *col);
@@ -266,10 +275,19 @@ gf_status gf_poisson_assemble(gf_ctx *ctx, const gf_particles *p, const gf_nbr *
 typedef struct {
   double rtol;        /* stop when ||b - A x||_2 <= rtol ||b||_2 (FP64 residual), 1e-8 */
   int maxit;          /* iteration limit (inner iterations in mixed mode), 20000 */
-  int mixed;          /* 0: FP64 Jacobi-BiCGStab; 1: FP32-matrix inner Jacobi-
-                         BiCGStab with FP64 residual and iterative refinement */
-  double inner_rtol;  /* mixed: relative reduction per inner solve, 1e-4 */
-  int inner_maxit;    /* mixed: inner iteration limit per refinement, 2000 */
+  int mixed;          /* 0: FP64 Jacobi-BiCGStab.
+                         1: the same iteration with its SpMV on FP32 matrix
+                         values (Krylov vectors, dots and updates FP64); the
+                         recursive residual is replaced by the FP64 residual
+                         b - A x (FP64 matrix) whenever it has fallen 100-fold
+                         since the last replacement and before convergence is
+                         declared (no restart of the Krylov space).
+                         2: iterative refinement with restarts: r = b - A x in
+                         FP64, an inner Jacobi-BiCGStab on FP32 values and FP32
+                         vectors solves A d = r, x += d. */
+  double inner_rtol;  /* mixed = 2: relative reduction per inner solve, 1e-4 (an
+                         inner solve never aims below half the overall target) */
+  int inner_maxit;    /* mixed = 2: inner iteration limit per refinement, 2000 */
   double zeta;        /* combined Neumann rows, 0.3 (Sec. 7.2) */
   int check_every;    /* iterations between host convergence checks, 4 */
   double implicit_a;  /* a of GF_ROW_IMPLICIT rows, A_ij = delta_ij - a c_ij^lap: one
@@ -278,12 +296,14 @@ typedef struct {
 void gf_solve_params_default(gf_solve_params *p);
 
 typedef struct {
-  int outer_its;        /* refinement steps (1 in plain mode) */
+  int outer_its;        /* mixed = 1: 1 + residual replacements; mixed = 2:
+                           refinement steps; 1 in plain mode */
   int inner_its_total;  /* BiCGStab iterations in total */
   int restarts;         /* restarts from the true residual: after a breakdown, or after a
                            half step that solved the system (t = A shat = 0) */
   int converged;
   double final_rel_res; /* ||b - A x|| / ||b|| in FP64 at exit */
+  double seconds;       /* host wall time of the call (it synchronises) */
 } gf_solve_stats;
 
 /* Solve A p = rhs with A assembled as in gf_poisson_assemble from FP64
@@ -445,15 +465,22 @@ gf_status gf_apply_stencil_adjoint(gf_ctx *ctx, const gf_nbr *nbr, gf_dtype wtyp
 
 /* Gradient with respect to particle positions of L(out), out =
  * gf_apply_stencil(gf_gfdm_weights(p), u), given ybar = dL/dout [K][n] FP64
- * and u [n] FP64.  The stencils are recomputed, not stored.  xbar_3n
- * ([n][3] FP64) is accumulated (+=).  Rows with status 2 or 3 contribute
- * nothing (their stencils are constant zero).  Each entry (i, j) moves x_i;
- * it moves x_j through the twin entry (j, i), so with extended
- * neighbourhoods (gf_build_neighbours_rows) the ghost particles, whose rows
- * hold only themselves, receive nothing. */
+ * and u [n] FP64.  The stencils are recomputed, not stored (FP64 normal
+ * equations, LDL^T).  xbar_3n ([n][3] FP64) is accumulated (+=).
+ * status_n (int8 [n], device, may be NULL): the statuses the forward
+ * gf_gfdm_weights / gf_gfdm_weights_apply call reported; rows with status 2
+ * (rank deficient by the QR test) or 3 (fewer neighbours than monomials) have
+ * constant zero stencils and contribute nothing.  Without it the rows with
+ * fewer neighbours than monomials and those whose Gram matrix has a pivot
+ * that is not positive contribute nothing (a nearly rank-deficient row that
+ * the forward QR test zeroes may then still contribute: pass the statuses).
+ * Each entry (i, j) moves x_i; it moves x_j through the twin entry (j, i), so
+ * with extended neighbourhoods (gf_build_neighbours_rows) the ghost
+ * particles, whose rows hold only themselves, receive nothing. */
 gf_status gf_gfdm_weights_adjoint(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr,
                                   const gf_ls_params *params, unsigned op_mask,
-                                  const double *u, const double *ybar, double *xbar_3n);
+                                  const double *u, const double *ybar, const int8_t *status_n,
+                                  double *xbar_3n);
 
 #ifdef __cplusplus
 }

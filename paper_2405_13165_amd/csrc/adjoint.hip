@@ -14,8 +14,10 @@
 // with the rows laid out in grouped (Morton) order and are gathered per
 // particle, in the same order, through the reverse-edge map: the twin entry
 // (j, i) of (i, j) lies in a Morton-near row, so the gather stays in L2.  No
-// atomics: the result is deterministic.  The Gram system is solved by LDL^T in FP64;
-// rows whose Gram matrix is not positive definite contribute nothing.
+// atomics: the result is deterministic.  The Gram system is solved by LDL^T in FP64.
+// Rows whose forward stencils are zero (status 2 or 3 of the stencil call,
+// when the caller passes those statuses) contribute nothing, and so do rows
+// whose Gram matrix is not positive definite.
 #include "stencil_common.h"
 
 using namespace gfdm_dev;
@@ -33,6 +35,7 @@ struct AArgs {
   WeightFn wf;
   unsigned mask;
   const double *u, *ybar;
+  const int8_t *status;  // forward stencil statuses (may be NULL)
   double *dbar;  // [nnz][3], rows in grouped order
   double *xbar;  // [n][3]: each row subtracts its own entries' sum here
   const int64_t *gbase;  // per team: offset of its row in dbar (grouped row offsets)
@@ -49,7 +52,8 @@ __device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane) {
   RowGeom g;
   g.xi = a.x[i]; g.yi = a.y[i]; g.zi = a.z[i]; g.hi = a.h[i]; g.inv_h = 1.0 / g.hi;
   if constexpr (M == 6) tangent_frame(a.nx[i], a.ny[i], a.nz[i], g.t1, g.t2);
-  bool ok = n >= M;
+  // n < M (status 3) and rank-deficient rows (status 2) have constant zero stencils
+  bool ok = n >= M && !(a.status && a.status[i] >= 2);
   constexpr int NP = npack(M);
   double G[NP];
 #pragma unroll
@@ -237,7 +241,7 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_gather(const int32_t *__rest
 
 extern "C" gf_status gf_gfdm_weights_adjoint(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr,
                                              const gf_ls_params *params, unsigned op_mask, const double *u,
-                                             const double *ybar, double *xbar_3n) {
+                                             const double *ybar, const int8_t *status_n, double *xbar_3n) {
   if (!ctx) return GF_EINVAL;
   gf_status st = check_particles(ctx, p, false, false);
   if (st) return st;
@@ -258,7 +262,7 @@ extern "C" gf_status gf_gfdm_weights_adjoint(gf_ctx *ctx, const gf_particles *p,
   a.x = p->x; a.y = p->y; a.z = p->z; a.h = p->h; a.nx = p->nx; a.ny = p->ny; a.nz = p->nz;
   a.row_ptr = nbr->row_ptr; a.col = nbr->col; a.n = p->n;
   a.wf = make_weight_fn(prm.alpha_w);
-  a.mask = op_mask; a.u = u; a.ybar = ybar;
+  a.mask = op_mask; a.u = u; a.ybar = ybar; a.status = status_n;
   a.dbar = ar.take<double>(3 * (size_t)std::max<int64_t>(nbr->nnz, 1));
   a.xbar = xbar_3n;
   for (int m = 0; m < 2; ++m) {

@@ -981,6 +981,14 @@ extern "C" gf_status gf_nbr_info(const gf_nbr *nbr, int64_t *n, int64_t *nnz, in
   return GF_OK;
 }
 
+extern "C" gf_status gf_nbr_view(const gf_nbr *nbr, int64_t *nnz, const int64_t **row_ptr, const int32_t **col) {
+  if (!nbr) return GF_EINVAL;
+  if (nnz) *nnz = nbr->nnz;
+  if (row_ptr) *row_ptr = nbr->row_ptr;
+  if (col) *col = nbr->col;
+  return GF_OK;
+}
+
 extern "C" gf_status gf_nbr_export(gf_ctx *ctx, const gf_nbr *nbr, int64_t *row_ptr, int32_t *col) {
   if (!ctx || !nbr) return GF_EINVAL;
   GF_HIP(ctx, hipSetDevice(ctx->device));

@@ -13,10 +13,18 @@
 // fence writes back an L2).  The host reads the residual norm every few
 // iterations.
 //
-// Mixed mode: the outer loop forms r = b - A x with FP64 matrix values and
-// vectors; the inner BiCGStab runs on FP32 matrix values and FP32 vectors
-// (dots accumulated in FP64) to a relative reduction inner_rtol; x += d.
+// Mixed modes.  mixed = 1: one BiCGStab run whose SpMV reads FP32 matrix
+// values (4 instead of 8 bytes per entry) while the Krylov vectors, dots and
+// updates stay FP64; its recursive residual tracks b - A32 x, so whenever it
+// has fallen by kReplace since the last replacement (and when it reaches the
+// tolerance) it is replaced by the FP64 residual b - A64 x (residual
+// replacement, a form of iterative refinement that keeps the Krylov space:
+// no restart).  mixed = 2: iterative refinement with restarts: the residual
+// r = b - A64 x in FP64, then an inner BiCGStab on FP32 values and FP32
+// vectors (dots accumulated in FP64) solves A32 d = r from d = 0 to a
+// relative reduction inner_rtol, and x += d.
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 
 #include "stencil_common.h"
@@ -54,6 +62,7 @@ __device__ inline double block_sum(double v) {
 }
 
 constexpr int kRedBlocks = 2048;   // blocks of the reducing kernels
+constexpr double kReplace = 1e-2;  // mixed = 1: residual replacement after this reduction
 constexpr int kFinThreads = 1024;  // threads of the finishing kernels
 
 // one partial per block and value: part[k * gridDim.x + blockIdx.x]
@@ -159,6 +168,37 @@ __global__ void __launch_bounds__(kBlock) k_residual(const int64_t *__restrict__
     }
   }
   block_partials<2>(v, part);
+}
+
+// residual replacement: r = b - A x with FP64 values; partials of (r, r) and
+// (rhat, r), so that rho continues from the replaced residual
+__global__ void __launch_bounds__(kBlock) k_residual_replace(const int64_t *__restrict__ row_ptr,
+                                                             const int32_t *__restrict__ col,
+                                                             const double *__restrict__ val, const double *__restrict__ b,
+                                                             const double *__restrict__ x, const double *__restrict__ rhat,
+                                                             int64_t n, double *__restrict__ r, double *part) {
+  double v[2] = {0.0, 0.0};
+  GF_TEAM_ROWS(row) {
+    double acc = 0.0;
+    for (int64_t k = row_ptr[row] + lane; k < row_ptr[row + 1]; k += kTeam) acc += val[k] * x[col[k]];
+    acc = team_sum(acc, kTeam);
+    if (lane == 0) {
+      const double ri = b[row] - acc;
+      r[row] = ri;
+      v[0] += ri * ri;
+      v[1] += rhat[row] * ri;
+    }
+  }
+  block_partials<2>(v, part);
+}
+
+__global__ void __launch_bounds__(kFinThreads) k_fin_replace(const double *part, int nblk, Scal *S) {
+  double res[2];
+  finish_partials<2>(part, nblk, res);
+  if (threadIdx.x != 0) return;
+  S->rr = res[0];
+  S->rho = res[1];  // rho_old keeps the value of the last iteration
+  if (res[1] == 0.0 || !isfinite(res[1])) S->breakdown = 4;
 }
 
 // scalars after a residual: rr, bb; with reset, a fresh BiCGStab start (rhat = r)
@@ -530,7 +570,8 @@ __global__ void __launch_bounds__(kFinThreads) k_fin_xr(const double *part, int 
   else if (res[0] == 0.0 || !isfinite(res[0])) S->breakdown = 4;
 }
 
-__global__ void __launch_bounds__(kBlock) k_add_f32(double *__restrict__ x, const float *__restrict__ d, int64_t n) {
+template <typename XT>
+__global__ void __launch_bounds__(kBlock) k_add_corr(double *__restrict__ x, const XT *__restrict__ d, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] += (double)d[i];
 }
@@ -549,7 +590,8 @@ struct Solver {
   unsigned grid_row;
   bool tiled;    // the SpMV runs on the neighbour tiles
   SpmvTiles tl;
-  int tiles_grid[2] = {0, 0};  // blocks of the tiled SpMV (FP64, FP32 vectors), set at first use
+  int tiles_grid[3] = {0, 0, 0};  // blocks of the tiled SpMV (FP64; FP32 values; FP32 values and vectors), set at first use
+  double *x_out = nullptr;        // the solution (refinement adds each inner correction here)
 };
 
 // staged-vector capacity of the tiled SpMV (entries)
@@ -590,7 +632,7 @@ int spmv_tiles_grid(const Solver &sv, size_t lds) {
 template <typename VT, typename XT, int K>
 int launch_spmv_tiles(Solver &sv, const VT *val, const XT *xin, XT *y, const XT *other) {
   const size_t lds = 2 * sizeof(XT) * (size_t)sv.tl.cap;
-  int &grid = sv.tiles_grid[sizeof(XT) == 8 ? 0 : 1];
+  int &grid = sv.tiles_grid[sizeof(VT) == 8 ? 0 : (sizeof(XT) == 8 ? 1 : 2)];
   if (grid == 0) grid = spmv_tiles_grid<VT, XT, K>(sv, lds);
   hipLaunchKernelGGL((k_spmv_tiles<VT, XT, K>), dim3(grid), dim3(kBlock), lds, sv.ctx->stream, sv.nbr->row_ptr,
                      sv.nbr->col, val, xin, y, other, sv.part, sv.S, sv.tl);
@@ -639,7 +681,8 @@ template <typename VT, typename XT>
 gf_status bicgstab_iter(Solver &sv, const Vecs<VT, XT> &V) {
   hipStream_t sm = sv.ctx->stream;
   const int64_t n = sv.n;
-  ProfScope prof(sv.ctx, sizeof(VT) == 8 ? "bicgstab_iter_f64" : "bicgstab_iter_f32");
+  ProfScope prof(sv.ctx, sizeof(VT) == 8 ? "bicgstab_iter_f64"
+                        : (sizeof(XT) == 8 ? "bicgstab_iter_f32val" : "bicgstab_iter_f32"));
   hipLaunchKernelGGL((k_update_p<XT>), dim3(sv.grid_row), dim3(kBlock), 0, sm, V.r, V.v, V.dinv, n, V.p, V.phat, sv.S);
   int nb = launch_spmv<VT, XT>(sv, V.val, V.phat, V.v, V.rhat);
   hipLaunchKernelGGL((k_fin_spmv<0>), dim3(1), dim3(kFinThreads), 0, sm, sv.part, nb, sv.S);
@@ -650,6 +693,34 @@ gf_status bicgstab_iter(Solver &sv, const Vecs<VT, XT> &V) {
                      V.x, V.r, sv.part, sv.S);
   hipLaunchKernelGGL(k_fin_xr, dim3(1), dim3(kFinThreads), 0, sm, sv.part, kRedBlocks, sv.S);
   GF_LAUNCH_CHECK(sv.ctx);
+  return GF_OK;
+}
+
+// One inner solve of the refinement: A32 d = r64 from d = 0 by Jacobi-BiCGStab
+// on FP32 matrix values, until the recursive residual is below inner_target
+// (or the iteration limits); then x += d.  `total` counts every iteration.
+template <typename XT>
+gf_status inner_solve(Solver &sv, const Vecs<float, XT> &V, const double *r64, double inner_target,
+                      const gf_solve_params &prm, int &total, gf_solve_stats &sts) {
+  gf_ctx *ctx = sv.ctx;
+  hipStream_t sm = ctx->stream;
+  hipLaunchKernelGGL(k_inner_init<XT>, dim3(kRedBlocks), dim3(kBlock), 0, sm, r64, sv.n, V.r, V.rhat, V.p, V.v, V.x,
+                     sv.part);
+  hipLaunchKernelGGL(k_fin_inner_init, dim3(1), dim3(kFinThreads), 0, sm, sv.part, kRedBlocks, sv.S);
+  GF_LAUNCH_CHECK(ctx);
+  gf_status st;
+  int it = 0;
+  while (it < prm.inner_maxit && total < prm.maxit) {
+    if ((st = bicgstab_iter<float, XT>(sv, V))) return st;
+    ++it;
+    ++total;
+    if (it % prm.check_every != 0) continue;
+    if ((st = read_scal(sv))) return st;
+    if (sv.hS->breakdown) { ++sts.restarts; break; }
+    if (std::sqrt(sv.hS->rr) <= inner_target) break;
+  }
+  hipLaunchKernelGGL(k_add_corr<XT>, dim3(sv.grid_row), dim3(kBlock), 0, sm, sv.x_out, V.x, sv.n);
+  GF_LAUNCH_CHECK(ctx);
   return GF_OK;
 }
 }  // namespace
@@ -713,12 +784,16 @@ extern "C" gf_status gf_poisson_solve(gf_ctx *ctx, const gf_particles *p, const 
   gf_solve_params prm;
   gf_solve_params_default(&prm);
   if (params) prm = *params;
-  if (!(prm.rtol > 0.0) || prm.maxit <= 0 || prm.check_every <= 0 || (prm.mixed && (!(prm.inner_rtol > 0.0) || prm.inner_maxit <= 0)))
+  if (!(prm.rtol > 0.0) || prm.maxit <= 0 || prm.check_every <= 0 || prm.mixed < 0 || prm.mixed > 2 ||
+      (prm.mixed && (!(prm.inner_rtol > 0.0) || prm.inner_maxit <= 0)))
     return set_error(ctx, GF_EINVAL, "invalid solver parameters");
   gf_solve_stats sts;
   memset(&sts, 0, sizeof(sts));
+  const auto t_start = std::chrono::steady_clock::now();
+  auto elapsed = [&]() { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count(); };
   const int64_t n = p->n, nnz = nbr->nnz;
   const bool mixed = prm.mixed != 0;
+  const bool vec32 = prm.mixed == 2;  // FP32 Krylov vectors in the inner solve
   Arena ar;
   const int nblk_row = (int)grid_for(n, kBlock);
   std::vector<size_t> sz = {sizeof(double) * (nnz + kQuadPad), sizeof(double) * n, sizeof(double) * 2 * kRedBlocks + 64,
@@ -727,7 +802,8 @@ extern "C" gf_status gf_poisson_solve(gf_ctx *ctx, const gf_particles *p, const 
   if (mixed) {
     sz.push_back(sizeof(float) * (nnz + kQuadPad));
     sz.push_back(sizeof(float) * n);
-    for (int k = 0; k < 9; ++k) sz.push_back(sizeof(float) * n);
+    if (vec32)
+      for (int k = 0; k < 9; ++k) sz.push_back(sizeof(float) * n);
   }
   if ((st = ensure_scratch(ctx, arena_bytes(sz), &ar))) return st;
   double *val64 = ar.take<double>(nnz + kQuadPad);
@@ -737,11 +813,12 @@ extern "C" gf_status gf_poisson_solve(gf_ctx *ctx, const gf_particles *p, const 
   int *bad = ar.take<int>(16);
   double *vec64[9];
   for (int k = 0; k < 9; ++k) vec64[k] = ar.take<double>(n);
-  float *val32 = nullptr, *dinv32 = nullptr, *vec32[9] = {nullptr};
+  float *val32 = nullptr, *dinv32 = nullptr, *v32[9] = {nullptr};
   if (mixed) {
     val32 = ar.take<float>(nnz + kQuadPad);
     dinv32 = ar.take<float>(n);
-    for (int k = 0; k < 9; ++k) vec32[k] = ar.take<float>(n);
+    if (vec32)
+      for (int k = 0; k < 9; ++k) v32[k] = ar.take<float>(n);
   }
   if ((st = ensure_host(ctx, 4096))) return st;
   hipStream_t sm = ctx->stream;
@@ -753,6 +830,7 @@ extern "C" gf_status gf_poisson_solve(gf_ctx *ctx, const gf_particles *p, const 
   sv.ctx = ctx; sv.nbr = nbr; sv.n = n; sv.part = part; sv.S = S;
   sv.hS = (Scal *)ctx->host_pinned;
   sv.grid_row = (unsigned)nblk_row;
+  sv.x_out = p_inout;
   init_spmv_tiles(sv);
   int *hbad = (int *)((char *)ctx->host_pinned + 1024);
   GF_HIP(ctx, hipMemcpyAsync(hbad, bad, sizeof(int), hipMemcpyDeviceToHost, sm));
@@ -774,6 +852,7 @@ extern "C" gf_status gf_poisson_solve(gf_ctx *ctx, const gf_particles *p, const 
     hipLaunchKernelGGL(k_zero_vecs<double>, dim3(sv.grid_row), dim3(kBlock), 0, sm, n, p_inout, V64.r);
     GF_LAUNCH_CHECK(ctx);
     sts.converged = 1;
+    sts.seconds = elapsed();
     if (stats) *stats = sts;
     return GF_OK;
   }
@@ -793,7 +872,8 @@ extern "C" gf_status gf_poisson_solve(gf_ctx *ctx, const gf_particles *p, const 
       if (sv.hS->breakdown) {
         if (++sts.restarts > 50) {
           sts.inner_its_total = total;
-          if (stats) *stats = sts;
+          sts.seconds = elapsed();
+    if (stats) *stats = sts;
           return set_error(ctx, GF_EBREAKDOWN, "BiCGStab broke down repeatedly (code %d)", sv.hS->breakdown);
         }
         launch_residual(sv, val64, rhs, p_inout, V64.r, V64.rhat, 1);
@@ -813,32 +893,62 @@ extern "C" gf_status gf_poisson_solve(gf_ctx *ctx, const gf_particles *p, const 
         rnorm = std::sqrt(sv.hS->rr);
       }
     }
+  } else if (!vec32) {
+    // FP32 matrix values, FP64 vectors, residual replacement with the FP64 matrix
+    Vecs<float, double> V1 = {val32, dinv64, p_inout, V64.r, V64.rhat, V64.p, V64.v, V64.phat, V64.s, V64.shat, V64.t};
+    sts.outer_its = 1;
+    double last_true = rnorm;  // true residual at the last replacement (or restart)
+    int stagnant = 0;
+    while (rnorm > target && total < prm.maxit) {
+      if ((st = bicgstab_iter<float, double>(sv, V1))) return st;
+      ++total;
+      if (total % prm.check_every != 0 && total < prm.maxit) continue;
+      if ((st = read_scal(sv))) return st;
+      if (sv.hS->breakdown) {
+        if (++sts.restarts > 50) {
+          sts.inner_its_total = total;
+          sts.seconds = elapsed();
+          if (stats) *stats = sts;
+          return set_error(ctx, GF_EBREAKDOWN, "BiCGStab broke down repeatedly (code %d)", sv.hS->breakdown);
+        }
+        launch_residual(sv, val64, rhs, p_inout, V64.r, V64.rhat, 1);
+        hipLaunchKernelGGL(k_zero_vecs<double>, dim3(sv.grid_row), dim3(kBlock), 0, sm, n, V64.p, V64.v);
+        if ((st = read_scal(sv))) return st;
+        rnorm = std::sqrt(sv.hS->rr);
+        stagnant = rnorm < 0.9 * last_true ? 0 : stagnant + 1;
+        last_true = std::min(last_true, rnorm);
+        if (stagnant >= 3) break;
+        continue;
+      }
+      const double rrec = std::sqrt(sv.hS->rr);
+      if (rrec > std::max(target, kReplace * last_true)) {
+        rnorm = rrec;
+        continue;
+      }
+      // replace the recursive residual by the FP64 one
+      hipLaunchKernelGGL(k_residual_replace, dim3(kRedBlocks), dim3(kBlock), 0, sm, nbr->row_ptr, nbr->col, val64,
+                         rhs, p_inout, V64.rhat, n, V64.r, part);
+      hipLaunchKernelGGL(k_fin_replace, dim3(1), dim3(kFinThreads), 0, sm, part, kRedBlocks, S);
+      GF_LAUNCH_CHECK(ctx);
+      if ((st = read_scal(sv))) return st;
+      rnorm = std::sqrt(sv.hS->rr);
+      ++sts.outer_its;
+      // replacements that no longer cut the true residual: the tolerance is below what the FP32 matrix allows
+      stagnant = rnorm < 0.9 * last_true ? 0 : stagnant + 1;
+      last_true = rnorm;
+      if (stagnant >= 3) break;
+    }
   } else {
-    Vecs<float, float> V32;
-    V32.val = val32; V32.dinv = dinv32; V32.x = vec32[8];
-    V32.r = vec32[0]; V32.rhat = vec32[1]; V32.p = vec32[2]; V32.v = vec32[3]; V32.phat = vec32[4];
-    V32.s = vec32[5]; V32.shat = vec32[6]; V32.t = vec32[7];
+    // iterative refinement with restarts, FP32 inner vectors
+    Vecs<float, float> Vf;
+    Vf.val = val32; Vf.dinv = dinv32; Vf.x = v32[8];
+    Vf.r = v32[0]; Vf.rhat = v32[1]; Vf.p = v32[2]; Vf.v = v32[3]; Vf.phat = v32[4];
+    Vf.s = v32[5]; Vf.shat = v32[6]; Vf.t = v32[7];
     while (rnorm > target && total < prm.maxit) {
       ++sts.outer_its;
-      // inner solve of A32 d = r64 from d = 0
-      hipLaunchKernelGGL(k_inner_init<float>, dim3(kRedBlocks), dim3(kBlock), 0, sm, V64.r, n, V32.r, V32.rhat,
-                         V32.p, V32.v, V32.x, part);
-      hipLaunchKernelGGL(k_fin_inner_init, dim3(1), dim3(kFinThreads), 0, sm, part, kRedBlocks, S);
-      GF_LAUNCH_CHECK(ctx);
-      const double inner_target = prm.inner_rtol * rnorm;
-      int it = 0;
-      double irn = rnorm;
-      while (it < prm.inner_maxit && total < prm.maxit) {
-        if ((st = bicgstab_iter<float, float>(sv, V32))) return st;
-        ++it;
-        ++total;
-        if (it % prm.check_every != 0) continue;
-        if ((st = read_scal(sv))) return st;
-        if (sv.hS->breakdown) { ++sts.restarts; break; }
-        irn = std::sqrt(sv.hS->rr);
-        if (irn <= inner_target) break;
-      }
-      hipLaunchKernelGGL(k_add_f32, dim3(sv.grid_row), dim3(kBlock), 0, sm, p_inout, V32.x, n);
+      // inner solve of A32 d = r64 from d = 0; the last one need not go below half the overall target
+      const double inner_target = std::max(prm.inner_rtol * rnorm, 0.5 * target);
+      if ((st = inner_solve<float>(sv, Vf, V64.r, inner_target, prm, total, sts))) return st;
       launch_residual(sv, val64, rhs, p_inout, V64.r, nullptr, 0);
       GF_LAUNCH_CHECK(ctx);
       if ((st = read_scal(sv))) return st;
@@ -851,6 +961,7 @@ extern "C" gf_status gf_poisson_solve(gf_ctx *ctx, const gf_particles *p, const 
   sts.inner_its_total = total;
   sts.final_rel_res = rnorm / bnorm;
   sts.converged = rnorm <= target;
+  sts.seconds = elapsed();
   if (stats) *stats = sts;
   if (!sts.converged)
     return set_error(ctx, GF_ENOTCONV, "not converged: relative residual %.3e after %d iterations", sts.final_rel_res, total);

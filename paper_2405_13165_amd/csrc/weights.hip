@@ -585,9 +585,9 @@ __device__ inline double wave_sum(double v) {
 // Householder QR of A = sqrt(W) M for the queued particles: one wave each.
 // Columns live in a per-block slice of global scratch (column-major, n rows).
 template <int OUT, bool FUSED, bool FASTW>
-__global__ void __launch_bounds__(kQrBlock) k_weights_qr(WArgs a, double *scratch, int64_t slice) {
+__global__ void __launch_bounds__(kQrBlock) k_weights_qr(WArgs a, double *panels, int64_t slice) {
   const int lane = threadIdx.x;
-  double *A = scratch + (int64_t)blockIdx.x * slice;
+  double *A = panels + (int64_t)blockIdx.x * slice;
   __shared__ double R[10][10];
   __shared__ double vtv[10];
   __shared__ double zt[4][10];
@@ -891,6 +891,7 @@ gf_status weights_common(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr, 
   const int64_t n = p->n;
   const int qr_blocks = (int)std::min<int64_t>(1024, n);
   const int64_t slice = (int64_t)kQrStride * std::max(nbr->max_row, 1);
+  const bool packed = prec == GF_BATCHED && needs_packed_positions(ctx, nbr);
   Arena ar;
   if ((st = ensure_scratch(ctx, arena_bytes({sizeof(int32_t) * n, 64, sizeof(double) * slice * qr_blocks, (size_t)n,
                                              sizeof(float) * n, 64, 64, sizeof(double4) * n}),
@@ -908,7 +909,7 @@ gf_status weights_common(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr, 
   WArgs a;
   a.x = p->x; a.y = p->y; a.z = p->z; a.h = p->h; a.nx = p->nx; a.ny = p->ny; a.nz = p->nz; a.model = p->model;
   a.pos = pos;
-  if (prec == GF_BATCHED && needs_packed_positions(ctx, nbr)) {
+  if (packed) {
     ProfScope prof(ctx, "pack_positions");
     hipLaunchKernelGGL(k_pack_pos, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, ctx->stream, p->x, p->y, p->z, p->h, n, pos);
     GF_LAUNCH_CHECK(ctx);

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libgfdm.so")
 GF_OK, GF_EINVAL, GF_ENOMEM, GF_EHIP, GF_ECAPACITY, GF_ENOTCONV, GF_EBREAKDOWN = 0, -1, -2, -3, -4, -5, -6
 GF_F64, GF_F32 = 0, 1
 GF_PLAIN_F64, GF_BATCHED = 0, 1
+GF_F32_QR_FALLBACK64 = GF_BATCHED
 OP_DX, OP_DY, OP_DZ, OP_LAP = 1, 2, 4, 8
 ROW_INTERIOR, ROW_DIRICHLET, ROW_NEUMANN_COMBINED, ROW_NEUMANN, ROW_IMPLICIT = 0, 1, 2, 3, 4
 
@@ -63,7 +64,7 @@ class SolveParams(ctypes.Structure):
 class SolveStats(ctypes.Structure):
     _fields_ = [("outer_its", ctypes.c_int), ("inner_its_total", ctypes.c_int),
                 ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
-                ("final_rel_res", ctypes.c_double)]
+                ("final_rel_res", ctypes.c_double), ("seconds", ctypes.c_double)]
 
 
 class NewParticles(ctypes.Structure):
@@ -73,7 +74,7 @@ class NewParticles(ctypes.Structure):
 
 EXPORTED = [
     "gf_version", "gf_create", "gf_set_stream", "gf_destroy", "gf_last_error",
-    "gf_build_neighbours", "gf_nbr_info", "gf_nbr_export", "gf_nbr_free",
+    "gf_build_neighbours", "gf_nbr_info", "gf_nbr_view", "gf_nbr_export", "gf_nbr_free",
     "gf_pca_params_default", "gf_classify_pca", "gf_ls_params_default", "gf_gfdm_weights",
     "gf_apply_stencil", "gf_gfdm_weights_apply", "gf_poisson_assemble", "gf_solve_params_default",
     "gf_poisson_solve", "gf_transition_3d_to_2d", "gf_apply_stencil_adjoint",
@@ -106,6 +107,7 @@ def load_library(path: str = LIB_PATH):
     L.gf_build_neighbours.argtypes = [P, PP, I32, ctypes.POINTER(P)]
     L.gf_nbr_info.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_int32)]
     L.gf_nbr_export.argtypes = [P, P, P, P]
+    L.gf_nbr_view.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(P), ctypes.POINTER(P)]
     L.gf_nbr_free.argtypes = [P]
     L.gf_nbr_free.restype = None
     L.gf_pca_params_default.argtypes = [ctypes.POINTER(PcaParams)]
@@ -124,7 +126,7 @@ def load_library(path: str = LIB_PATH):
                                    ctypes.POINTER(SolveStats)]
     L.gf_transition_3d_to_2d.argtypes = [P, PP, P] + [P] * 11
     L.gf_apply_stencil_adjoint.argtypes = [P, P, I32, P, U, P, P]
-    L.gf_gfdm_weights_adjoint.argtypes = [P, PP, P, ctypes.POINTER(LsParams), U, P, P, P]
+    L.gf_gfdm_weights_adjoint.argtypes = [P, PP, P, ctypes.POINTER(LsParams), U, P, P, P, P]
     L.gf_autotune.argtypes = [P, PP, P, I32, P]
     L.gf_set_team_sizes.argtypes = [P, P, P]
     L.gf_profile_enable.argtypes = [P, I32]
@@ -145,6 +147,21 @@ def load_library(path: str = LIB_PATH):
 
 def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class _DevArray:
+    """__cuda_array_interface__ of device memory the library owns (no copy)."""
+
+    def __init__(self, ptr, count, typestr):
+        self.__cuda_array_interface__ = {"shape": (int(count),), "typestr": typestr, "data": (int(ptr or 0), False),
+                                         "version": 2}
+
+
+def _alias(ptr, count, dtype, ctx):
+    typestr = {torch.int64: "<i8", torch.int32: "<i4"}[dtype]
+    if count == 0 or not ptr:
+        return torch.empty(0, dtype=dtype, device=ctx.device)
+    return torch.as_tensor(_DevArray(ptr, count, typestr), device=ctx.device)
 
 
 def _dev_tensor(t, dtype, device):
@@ -256,6 +273,13 @@ class Neighbours:
         self.ctx.check(self.ctx.lib.gf_nbr_export(self.ctx.handle, self.handle, _ptr(row_ptr),
                                                   _ptr(col) if self.nnz else None))
         return row_ptr, col
+
+    def view(self):
+        """(row_ptr int64 [n+1], col int32 [nnz]) device tensors that alias the
+        handle's own lists (gf_nbr_view, no copy); valid while the handle lives."""
+        nnz, rp, cp = ctypes.c_int64(), ctypes.c_void_p(), ctypes.c_void_p()
+        self.ctx.check(self.ctx.lib.gf_nbr_view(self.handle, ctypes.byref(nnz), ctypes.byref(rp), ctypes.byref(cp)))
+        return _alias(rp.value, self.n + 1, torch.int64, self.ctx), _alias(cp.value, nnz.value, torch.int32, self.ctx)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -567,15 +591,16 @@ def apply_stencil_adjoint(ctx, nbr, w, ybar, op_mask=0xF):
     return ub
 
 
-def gfdm_weights_adjoint(ctx, p, nbr, u, ybar, op_mask=0xF, params=None, xbar=None):
-    """Accumulates dL/dx into xbar [n, 3] (created as zeros if None) and returns it."""
+def gfdm_weights_adjoint(ctx, p, nbr, u, ybar, op_mask=0xF, params=None, xbar=None, status=None):
+    """Accumulates dL/dx into xbar [n, 3] (created as zeros if None) and returns it.
+    status: the int8 statuses of the forward stencil call (rows 2 and 3 contribute nothing)."""
     xb = torch.zeros((p.n, 3), dtype=torch.float64, device=ctx.device) if xbar is None else xbar
     prm = params if params is not None else ls_params()
     uu = u.to(torch.float64).contiguous()
     yb = ybar.to(torch.float64).contiguous()
     ctx._sync_stream()
     ctx.check(ctx.lib.gf_gfdm_weights_adjoint(ctx.handle, ctypes.byref(p.s), nbr.handle, ctypes.byref(prm), op_mask,
-                                              _ptr(uu), _ptr(yb), _ptr(xb)))
+                                              _ptr(uu), _ptr(yb), _ptr(status), _ptr(xb)))
     return xb
 
 
@@ -592,24 +617,25 @@ class StencilOp(torch.autograd.Function):
     def forward(fctx, u, x, y, z, lib_ctx, p, nbr, op_mask, wtype):
         q = p.with_positions(x.detach().to(torch.float64), y.detach().to(torch.float64),
                              z.detach().to(torch.float64))
-        w = gfdm_weights(lib_ctx, q, nbr, GF_BATCHED, wtype)
+        status = torch.empty(p.n, dtype=torch.int8, device=lib_ctx.device)
+        w = gfdm_weights(lib_ctx, q, nbr, GF_BATCHED, wtype, status=status)
         uu = u.detach().to(torch.float64).contiguous()
         out = apply_stencil(lib_ctx, nbr, w, uu, op_mask)
         fctx.save_for_backward(uu, x, y, z)
-        fctx.extra = (lib_ctx, p, nbr, op_mask, w)
+        fctx.extra = (lib_ctx, p, nbr, op_mask, w, status)
         return out
 
     @staticmethod
     def backward(fctx, gout):
         uu, x, y, z = fctx.saved_tensors
-        lib_ctx, p, nbr, op_mask, w = fctx.extra
+        lib_ctx, p, nbr, op_mask, w, status = fctx.extra
         gout = gout.contiguous().to(torch.float64)
         gu = apply_stencil_adjoint(lib_ctx, nbr, w, gout, op_mask) if fctx.needs_input_grad[0] else None
         gx = gy = gz = None
         if any(fctx.needs_input_grad[1:4]):
             q = p.with_positions(x.detach().to(torch.float64), y.detach().to(torch.float64),
                                  z.detach().to(torch.float64))
-            xb = gfdm_weights_adjoint(lib_ctx, q, nbr, uu, gout, op_mask)
+            xb = gfdm_weights_adjoint(lib_ctx, q, nbr, uu, gout, op_mask, status=status)
             gx, gy, gz = xb[:, 0].contiguous(), xb[:, 1].contiguous(), xb[:, 2].contiguous()
         return gu, gx, gy, gz, None, None, None, None, None
 

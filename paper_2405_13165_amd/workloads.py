@@ -348,9 +348,9 @@ def projection_cylinder(n_target: int = 4_000_000, seed_extra: int = 0,
 
     Bottom wall rows are Neumann rows (plain n.grad rows by default, or the
     combined PDE + zeta BC rows), free-surface rows are Dirichlet, the rest
-    interior.  The wall normal points into the fluid (+z on the bottom plate),
-    the convention the paper uses for boundary normals in Sec. 5.2.
-    p*(x) = sin(20x + 1) cos(20y) (1 + 5z) is the manufactured solution.
+    interior.  The wall normal of the boundary condition is the outward one
+    (-z on the bottom plate).  p*(x) = sin(20x + 1) cos(20y) (1 + 5z) is the
+    manufactured solution.
     """
     rng = rng_for(5, seed_extra)
     x, y, z, kind, s = _jet_cylinder(n_target, rng)
@@ -358,7 +358,7 @@ def projection_cylinder(n_target: int = 4_000_000, seed_extra: int = 0,
     row_type = np.full(n, ROW_INTERIOR, np.int8)
     row_type[kind == FREE_SURFACE] = ROW_DIRICHLET
     row_type[kind == WALL] = wall_rows
-    nzv = np.where(kind == WALL, 1.0, 0.0)
+    nzv = np.where(kind == WALL, -1.0, 0.0)
     pstar = np.sin(20 * x + 1) * np.cos(20 * y) * (1 + 5 * z)
     return _pack(x, y, z, np.full(n, 3.0 * s), np.zeros(n), kind, None, None, nzv,
                  row_type=row_type, pstar=pstar, spacing=s)

@@ -448,10 +448,29 @@ def test_team_sizes_reject_bad_values(ctx, g):
 
 
 # ------------------------------------------------------------------ pressure
-@pytest.mark.parametrize("rows", ["neumann", "combined"])
+def sp_dense(rp, col, val):
+    import scipy.sparse as sp
+    n = rp.shape[0] - 1
+    return sp.csr_matrix((val, col, rp), shape=(n, n)).toarray()
+
+
+def _wall_normals(d, sign):
+    q = dict(d)
+    q["nz"] = np.where(d["kind"] == W.WALL, sign, 0.0)
+    return q
+
+
+# Pressure rows (Sec. 2.3, PDE + zeta BC of Sec. 7.2) on the 4,144-row cylinder:
+# plain Neumann walls (the projection workload) and combined rows with the
+# outward (-z) and the inward (+z) wall normal.  The solve runs on the oracle's
+# own stencils (uploaded), so the system is the oracle's matrix and the GPU
+# solution must match its sparse LU solution; a second solve on the library's
+# own FP64 stencils checks the whole path.  The LU solution of these systems
+# has a relative residual of ~4e-14 (kappa_2 = 1.1e5 Neumann, 1.0e7 combined).
+@pytest.mark.parametrize("rows", ["neumann", "combined_out", "combined_in"])
 def test_poisson_assemble_and_solve(ctx, g, rows):
     wr = W.ROW_NEUMANN_PLAIN if rows == "neumann" else W.ROW_NEUMANN_COMBINED
-    d = W.projection_cylinder(4000, wall_rows=wr)
+    d = _wall_normals(W.projection_cylinder(4000, wall_rows=wr), 1.0 if rows == "combined_in" else -1.0)
     p, nb, rp, col = _nbr_equal(ctx, g, d)
     w_o, _, _ = oracle.gfdm_weights(d, rp, col)
     val_o = oracle.poisson_matrix(d, rp, col, w_o, d["row_type"])
@@ -463,18 +482,39 @@ def test_poisson_assemble_and_solve(ctx, g, rows):
     b = oracle.csr_matvec(rp, col, val_o, d["pstar"])
     x_o = oracle.poisson_solve(rp, col, val_o, b)
     bt = torch.as_tensor(b, device=ctx.device)
-    # Jacobi-preconditioned BiCGStab on the combined PDE + zeta BC rows has
-    # eigenvalues on both sides of the imaginary axis; it converges in FP64
-    # only, so the FP32-inner refinement is exercised on the Neumann rows.
-    for mixed in ((0, 1) if rows == "neumann" else (0,)):
-        x, st = g.poisson_solve(ctx, p, nb, w64, d["row_type"], bt,
-                                params=g.solve_params(rtol=1e-12, mixed=mixed, maxit=20000))
+    w_up = torch.as_tensor(w_o, device=ctx.device)
+    # where conditioning rules out the 1e-10 bar (combined rows, kappa_2 = 1.0e7), the difference
+    # of two solutions is held to its bound (|r| + |r_LU|) / sigma_min, sigma_min from a dense SVD
+    r_o = b - oracle.csr_matvec(rp, col, val_o, x_o)
+    smin = None
+    if rows != "neumann":
+        import scipy.linalg
+        smin = scipy.linalg.svdvals(sp_dense(rp, col, val_o)).min()
+    # the FP32-vector inner solve (mixed = 2) cannot follow the slow Krylov convergence of the
+    # combined rows (its inner solves stall near 1e-3); it is run on the Neumann rows only
+    for mixed in ((0, 1, 2) if rows == "neumann" else (0, 1)):
+        x, st = g.poisson_solve(ctx, p, nb, w_up, d["row_type"], bt,
+                                params=g.solve_params(rtol=1e-13, mixed=mixed, maxit=20000))
         print(f"\n[poisson] rows={rows} mixed={mixed} stats={st}", flush=True)
         x = _np(x)
         assert st["converged"] == 1
         r = b - oracle.csr_matvec(rp, col, val_o, x)
-        assert np.linalg.norm(r) <= 1.01e-12 * np.linalg.norm(b)
-        assert np.linalg.norm(x - x_o) <= 1e-9 * np.linalg.norm(x_o)
+        assert np.linalg.norm(r) <= 1.5e-13 * np.linalg.norm(b)
+        diff = np.linalg.norm(x - x_o)
+        print(f"[poisson] rows={rows} mixed={mixed}: |x - x_LU| / |x_LU| = {diff / np.linalg.norm(x_o):.2e}"
+              + (f", bound {(np.linalg.norm(r) + np.linalg.norm(r_o)) / smin / np.linalg.norm(x_o):.2e}"
+                 if smin else ""), flush=True)
+        if smin is None:
+            assert diff <= 1e-10 * np.linalg.norm(x_o)
+        else:
+            assert diff <= (np.linalg.norm(r) + np.linalg.norm(r_o)) / smin
+    # the whole path: the library's own FP64 stencils (within 1e-10 of the oracle's)
+    x, st = g.poisson_solve(ctx, p, nb, w64, d["row_type"], bt, params=g.solve_params(rtol=1e-13))
+    x = _np(x)
+    r = b - oracle.csr_matvec(rp, col, val_o, x)
+    print(f"[poisson] rows={rows} own stencils: residual {np.linalg.norm(r) / np.linalg.norm(b):.2e}, "
+          f"error {np.linalg.norm(x - x_o) / np.linalg.norm(x_o):.2e}", flush=True)
+    assert np.linalg.norm(r) <= 1e-9 * np.linalg.norm(b)
 
 
 def test_poisson_zero_rhs_and_bad_rows(ctx, g):
@@ -625,3 +665,89 @@ def test_unstaged_tiles_match_staged(ctx, g):
         for k, t in tol.items():
             scale = ref[k].abs().max().item()
             assert (ref[k] - got[k]).abs().max().item() <= t * scale, (cap, k)
+
+
+# ------------------------------------------------------------------ condition numbers
+@pytest.mark.parametrize("name", ["plain_cube_20k", "mixed_small", "jet_small", "cylinder"])
+def test_kappa_matches_oracle_gram(ctx, g, name):
+    # kappa_n of the stencil call is the 1-norm condition number of the Gram
+    # matrix G of the local least-squares problem (it decides the FP64 QR
+    # fallback); the oracle forms it from its Householder factor, G = R^T R
+    d = CASES[name]()
+    p, nb, rp, col = _nbr_equal(ctx, g, d)
+    k_o = oracle.gram_kappa(d, rp, col)
+    fin = np.isfinite(k_o) & (k_o > 0)
+    for prec, wt in ((g.GF_BATCHED, g.GF_F32), (g.GF_BATCHED, g.GF_F64), (g.GF_PLAIN_F64, g.GF_F64)):
+        kap = torch.empty(p.n, dtype=torch.float32, device=ctx.device)
+        g.gfdm_weights(ctx, p, nb, prec, wt, kappa=kap)
+        k = _np(kap).astype(np.float64)
+        rel = np.abs(k[fin] - k_o[fin]) / k_o[fin]
+        # FP32 storage (6e-8) plus the FP64 inversion error, ~kappa * 1e-16
+        tol = 1e-6 + 1e-14 * k_o[fin]
+        print(f"\n[kappa] {name} prec={prec} wt={wt}: {int(fin.sum())} finite, max rel "
+              f"{rel.max() if fin.any() else 0.0:.2e}, {int(np.isinf(k_o).sum())} rank deficient", flush=True)
+        assert np.all(rel <= tol)
+        assert np.all(k[k_o == 0] == 0)
+        # rows the oracle finds rank deficient must exceed the fallback threshold (or have no finite estimate)
+        bad = np.isinf(k_o)
+        assert np.all(~np.isfinite(k[bad]) | (k[bad] > g.ls_params().kappa_max))
+
+
+# ------------------------------------------------------------------ adjoint on rank-deficient rows
+def _coplanar_cloud():
+    # a jittered cube plus a separate patch of 60 particles on a tilted plane:
+    # the patch's 3D rows are rank deficient (status 2, zero stencils)
+    d = W.diff_cube(n_axis=10)
+    n0 = d["x"].size
+    rng = np.random.default_rng(77)
+    a = np.array([1.0, 0.3, 0.2]); a /= np.linalg.norm(a)
+    b = np.cross(a, [0.1, 0.2, 1.0]); b /= np.linalg.norm(b)
+    s, t = rng.uniform(0, 0.06, 60), rng.uniform(0, 0.06, 60)
+    P = np.array([2.0, 2.0, 2.0]) + s[:, None] * a + t[:, None] * b
+    m = P.shape[0]
+    out = {k: np.concatenate([d[k], P[:, c]]) for c, k in enumerate("xyz")}
+    out["h"] = np.concatenate([d["h"], np.full(m, 0.05)])
+    out["model"] = np.zeros(n0 + m, np.int8)
+    out["kind"] = np.zeros(n0 + m, np.int8)
+    for k in ("nx", "ny", "nz"):
+        out[k] = np.zeros(n0 + m)
+    out["u"] = np.concatenate([d["u"], np.sin(7 * P[:, 0])])
+    return out, n0
+
+
+def test_weights_adjoint_skips_rank_deficient_rows(ctx, g):
+    d, n0 = _coplanar_cloud()
+    p, nb, rp, col = _nbr_equal(ctx, g, d)
+    w_o, st_o, _ = oracle.gfdm_weights(d, rp, col)
+    assert np.all(st_o[n0:] == 2) and np.all(st_o[:n0] == 0)
+    status = torch.empty(p.n, dtype=torch.int8, device=ctx.device)
+    g.gfdm_weights(ctx, p, nb, g.GF_BATCHED, g.GF_F32, status=status)
+    assert _status_match(_np(status), st_o)
+    u = d["u"]
+    yb = np.random.default_rng(3).standard_normal((1, p.n))
+    xb_o = oracle.weights_adjoint_x(d, rp, col, u, yb, op_mask=oracle.OP_LAP)
+    assert np.all(xb_o[n0:] == 0)
+    xb = _np(g.gfdm_weights_adjoint(ctx, p, nb, torch.as_tensor(u, device=ctx.device),
+                                    torch.as_tensor(yb, device=ctx.device), op_mask=g.OP_LAP, status=status))
+    assert np.all(xb[n0:] == 0)
+    err = np.abs(xb - xb_o).max() / np.abs(xb_o).max()
+    print(f"\n[adjoint x, rank-deficient rows skipped] rel err {err:.3e}", flush=True)
+    assert err <= 1e-9
+    # autograd through the operator carries the statuses of its forward call
+    ur = torch.as_tensor(u, device=ctx.device).requires_grad_(True)
+    xr, yr, zr = (torch.as_tensor(d[k], device=ctx.device).requires_grad_(True) for k in "xyz")
+    out = g.stencil_op(ctx, p, nb, ur, xr, yr, zr, op_mask=g.OP_LAP, wtype=g.GF_F64)
+    gx, = torch.autograd.grad((out[0] * torch.as_tensor(yb[0], device=ctx.device)).sum(), (xr,))
+    assert torch.all(gx[n0:] == 0)
+    assert np.abs(_np(gx) - xb_o[:, 0]).max() <= 1e-9 * np.abs(xb_o).max()
+
+
+# ------------------------------------------------------------------ zero-copy neighbour view
+def test_nbr_view_aliases_the_handle_lists(ctx, g):
+    d = CASES["mixed_small"]()
+    p, nb, rp, col = _nbr_equal(ctx, g, d)
+    vr, vc = nb.view()
+    assert vr.data_ptr() != 0 and vc.numel() == nb.nnz
+    assert np.array_equal(_np(vr), rp) and np.array_equal(_np(vc), col)
+    er, ec = nb.export()
+    assert er.data_ptr() != vr.data_ptr() and ec.data_ptr() != vc.data_ptr()
