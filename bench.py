@@ -55,13 +55,16 @@ def parse():
     ap.add_argument("--poisson-n", type=int, default=4_000_000,
                     help="particles of the projection cylinder of the pressure-solve record")
     ap.add_argument("--advdiff", action="store_true",
-                    help="also run the diffusion analogue of the advection-diffusion test (Sec. 7.3) at "
+                    help="also run the diffusion analogue of the advection-diffusion test (Sec. 7.2) at "
                          "h = 0.06, 0.03, 0.015, and its model-adaptive moving-plate case at h = 0.12, 0.06, 0.03, "
                          "against the exact solutions (convergence study)")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warm-up plus a few steps of the metric path and exit (for rocprofv3)")
     ap.add_argument("--profile-jet", action="store_true",
                     help="with --profile-only: the jet cloud's fused step instead of the headline cloud")
+    ap.add_argument("--profile-graph", action="store_true",
+                    help="with --profile-only: 30 eager fused steps, then 30 replays of the step captured in a "
+                         "HIP graph (for a kernel trace comparing the two)")
     return ap.parse_args()
 
 
@@ -291,6 +294,28 @@ def main():
     t0 = time.perf_counter()
     teams = g.autotune(ctx, p, nb, g.GF_F32)
     log(f"autotune {time.perf_counter() - t0:.2f}s: {teams}")
+
+    if args.profile_only and args.profile_graph:
+        for _ in range(3):
+            step_fused()
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step_fused()
+        torch.cuda.synchronize()
+        marker = torch.empty(1 << 20, device=dev)
+        marker.fill_(0)          # separates the eager steps from the replays in the trace
+        for _ in range(30):
+            step_fused()
+        torch.cuda.synchronize()
+        marker.fill_(1)
+        for _ in range(30):
+            graph.replay()
+        torch.cuda.synchronize()
+        marker.fill_(2)
+        torch.cuda.synchronize()
+        log("profile run done (30 eager steps, 30 graph replays)")
+        return
 
     if args.profile_only:
         if args.profile_jet:

@@ -557,7 +557,7 @@ def _rows_of(c, h):
 
 
 def advect_step(c, h, kappa, dt, x0=1.0, x1=2.0, r_min=R_MIN, r_max=R_MAX):
-    """One model-adaptive step of the advection-diffusion case (Sec. 7.3):
+    """One model-adaptive step of the advection-diffusion case (Sec. 7.2):
     Lagrangian move with v = (1, 0, 0); film particles inside [x0, x1]
     transition to 3D (Sec. 5.2), 3D wall particles beyond x1 transition to
     2D with their columns (Sec. 5.1); then ghosts (Alg. 5), extended

@@ -1,4 +1,4 @@
-"""Diffusion analogue of the advection-diffusion test (Sec. 7.3) on the
+"""Diffusion analogue of the advection-diffusion test (Sec. 7.2) on the
 library: a static plate of film particles with a 3D block in its middle
 (fixed interfaces), so the ghost particles of the buffer zone keep their
 places and only their data is recomputed each step (Sec. 6.2).  Each step:
@@ -72,7 +72,7 @@ _FIELDS = ("x", "y", "z", "h", "model", "kind", "nx", "ny", "nz", "mass", "rho")
 
 
 class AdvectPlate:
-    """The model-adaptive case of the advection-diffusion test (Sec. 7.3): a
+    """The model-adaptive case of the advection-diffusion test (Sec. 7.2): a
     film plate moves with v = (1, 0, 0) through the window x0 <= x <= x1.
     Film particles that enter the window turn into 3D columns (Sec. 5.2),
     3D wall particles that leave it collapse back onto the film with their

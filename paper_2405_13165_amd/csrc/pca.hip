@@ -1,13 +1,15 @@
 // Local PCA of every neighbourhood and the transition flags of Sec. 4.
 //
-// A team of kTeam lanes per particle.  Rows with at most 128 neighbours run
-// one neighbour tile per block: the tile's distinct neighbours (position,
-// index and kind) are staged in LDS and both passes read them through the
-// tile slots; rows with more neighbours gather from global memory.  The 3x3
-// covariance is built in two passes (centroid, then centred second moments)
-// from offsets relative to the particle itself, so an exactly planar
-// neighbourhood yields an exactly zero third eigenvalue; one lane of the team
-// then runs the eigen solve and the classification.
+// A team of kTeam lanes per particle builds the 3x3 covariance in two passes
+// (centroid, then centred second moments) from offsets relative to the
+// particle itself, so an exactly planar neighbourhood yields an exactly zero
+// third eigenvalue.  Rows with at most 128 neighbours are processed by
+// neighbour tiles: a block takes kPcaTiles consecutive tiles, stages each
+// tile's distinct neighbours (position, index and kind) in LDS in turn, and
+// keeps the covariances and neighbour-kind counts of all its rows in LDS;
+// then every thread of the block runs the eigen solve and the classification
+// of one row, so the serial 3x3 Jacobi solves use every lane.  Rows with more
+// neighbours gather from global memory, and one lane of the team solves.
 #include "stencil_common.h"
 
 using namespace gfdm_dev;
@@ -141,13 +143,16 @@ struct PcaGlobal {
   }
 };
 
+// covariance (c00 c01 c02 c11 c12 c22) and the counts of interior and
+// free-surface neighbours of row i, complete on every lane of the team
 template <class F>
-__device__ void pca_row(const PcaArgs &a, int32_t i, int lane, const F &fetch) {
+__device__ void pca_cov(const PcaArgs &a, int32_t i, int lane, const F &fetch, double c[6], int &n_int, int &n_fs) {
   const int64_t b = a.row_ptr[i], e = a.row_ptr[i + 1];
   const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
   const bool need_kinds = a.raw && a.kind;
   double mx = 0.0, my = 0.0, mz = 0.0;
-  int n_int = 0, n_fs = 0;
+  n_int = 0;
+  n_fs = 0;
   for (int64_t k = b + lane; k < e; k += kTeam) {
     const double4 pj = fetch(a, k);
     mx += pj.x - xi;
@@ -169,7 +174,8 @@ __device__ void pca_row(const PcaArgs &a, int32_t i, int lane, const F &fetch) {
   n_fs = team_sum(n_fs, kTeam);
   const double inv = 1.0 / (double)(e - b);
   mx *= inv; my *= inv; mz *= inv;
-  double c[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < 6; ++q) c[q] = 0.0;
   for (int64_t k = b + lane; k < e; k += kTeam) {
     const double4 pj = fetch(a, k);
     const double dx = (pj.x - xi) - mx, dy = (pj.y - yi) - my, dz = (pj.z - zi) - mz;
@@ -178,32 +184,56 @@ __device__ void pca_row(const PcaArgs &a, int32_t i, int lane, const F &fetch) {
   }
 #pragma unroll
   for (int q = 0; q < 6; ++q) c[q] = team_sum(c[q], kTeam);
-  if (lane == 0) pca_finish(a, i, n_int, n_fs, c[0], c[1], c[2], c[3], c[4], c[5]);
 }
 
-// tiled rows: one neighbour tile per block, kTileRows teams
+// Tiled rows: kPcaTiles consecutive neighbour tiles per block (kTileRows
+// teams of kTeam lanes, so a block has as many threads as its rows).
+constexpr int kPcaTiles = kTeam;
+constexpr int kPcaRows = kTileRows * kPcaTiles;  // rows of a block = its threads
 __global__ void __launch_bounds__(kTileRows * kTeam) k_pca_tile(PcaArgs a, const int64_t *__restrict__ toff,
                                                                 const int32_t *__restrict__ tu,
                                                                 const uint16_t *__restrict__ slot, int64_t tile0,
-                                                                int cap) {
+                                                                int64_t ntiles, int cap) {
   extern __shared__ double4 s_pos[];
-  const int64_t tl = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t u0 = toff[tile0 + tl];
-  const int cnt = (int)(toff[tile0 + tl + 1] - u0);
-  const bool staged = cnt <= cap;
-  if (staged) {
-    for (int s = threadIdx.x; s < cnt; s += blockDim.x) {
-      const int32_t j = tu[u0 + s];
-      s_pos[s] = make_double4(a.x[j], a.y[j], a.z[j], pca_code(a, j));
-    }
-  }
-  __syncthreads();
+  __shared__ double s_cov[6][kPcaRows];
+  __shared__ int s_cnt[2][kPcaRows];
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int team = threadIdx.x / kTeam, lane = threadIdx.x % kTeam;
-  const int64_t r = tl * kTileRows + team;
+  for (int q = 0; q < kPcaTiles; ++q) {
+    const int64_t tl = blk * kPcaTiles + q;
+    if (tl >= ntiles) break;  // uniform over the block
+    const int64_t u0 = toff[tile0 + tl];
+    const int cnt = (int)(toff[tile0 + tl + 1] - u0);
+    const bool staged = cnt <= cap;
+    if (staged) {
+      for (int s = threadIdx.x; s < cnt; s += blockDim.x) {
+        const int32_t j = tu[u0 + s];
+        s_pos[s] = make_double4(a.x[j], a.y[j], a.z[j], pca_code(a, j));
+      }
+    }
+    __syncthreads();
+    const int64_t r = tl * kTileRows + team;
+    if (r < a.nrows) {
+      double c[6];
+      int n_int, n_fs;
+      if (staged) pca_cov(a, a.sched[r], lane, PcaTile{s_pos, slot}, c, n_int, n_fs);
+      else pca_cov(a, a.sched[r], lane, PcaGlobal{}, c, n_int, n_fs);
+      if (lane == 0) {
+        const int t = q * kTileRows + team;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) s_cov[k][t] = c[k];
+        s_cnt[0][t] = n_int;
+        s_cnt[1][t] = n_fs;
+      }
+    }
+    __syncthreads();  // the staging buffer is rewritten by the next tile
+  }
+  // one row per thread: eigen solve and classification
+  const int t = threadIdx.x;
+  const int64_t r = blk * kPcaRows + t;
   if (r >= a.nrows) return;
-  const int32_t i = a.sched[r];
-  if (staged) pca_row(a, i, lane, PcaTile{s_pos, slot});
-  else pca_row(a, i, lane, PcaGlobal{});
+  pca_finish(a, a.sched[r], s_cnt[0][t], s_cnt[1][t], s_cov[0][t], s_cov[1][t], s_cov[2][t], s_cov[3][t],
+             s_cov[4][t], s_cov[5][t]);
 }
 
 // untiled rows: teams over the rows of the launch, gathers from global memory
@@ -211,7 +241,11 @@ __global__ void __launch_bounds__(kBlock) k_pca_flags(PcaArgs a) {
   const int64_t gt = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int64_t r = gt / kTeam;
   if (r >= a.nrows) return;
-  pca_row(a, a.sched[r], (int)(gt % kTeam), PcaGlobal{});
+  const int32_t i = a.sched[r];
+  double c[6];
+  int n_int, n_fs;
+  pca_cov(a, i, (int)(gt % kTeam), PcaGlobal{}, c, n_int, n_fs);
+  if (gt % kTeam == 0) pca_finish(a, i, n_int, n_fs, c[0], c[1], c[2], c[3], c[4], c[5]);
 }
 
 // smoothing rule 1 over the cross-model neighbourhood
@@ -280,8 +314,9 @@ extern "C" gf_status gf_classify_pca(gf_ctx *ctx, const gf_particles *p, const g
     a.nrows = u.nrows;
     if (u.tiled) {
       const int cap = std::min(u.tile_max, tile_capacity(ctx, kPcaCap));
-      hipLaunchKernelGGL(k_pca_tile, dim3(grid_for(u.ntiles, 1)), dim3(kTileRows * kTeam), sizeof(double4) * cap,
-                         ctx->stream, a, same->tile_off, same->tile_u, same->slot, u.tile0, cap);
+      hipLaunchKernelGGL(k_pca_tile, dim3(grid_for(u.ntiles, kPcaTiles)), dim3(kTileRows * kTeam),
+                         sizeof(double4) * cap, ctx->stream, a, same->tile_off, same->tile_u, same->slot, u.tile0,
+                         u.ntiles, cap);
     } else {
       hipLaunchKernelGGL(k_pca_flags, dim3(grid_for(u.nrows * kTeam, kBlock)), dim3(kBlock), 0, ctx->stream, a);
     }

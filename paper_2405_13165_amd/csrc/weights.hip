@@ -207,17 +207,19 @@ struct GramTable {
 __constant__ GramTable<10> kGram3 = GramTable<10>();
 __constant__ GramTable<6> kGram2 = GramTable<6>();
 
-// lanes of a team that take part in the moment transpose-reduction
-__host__ __device__ constexpr int red_lanes(int T) { return T < 8 ? T : 8; }
+// lanes of a team that take part in the moment transpose-reduction (the
+// team's partial sums are first folded down to this many lanes)
+__host__ __device__ constexpr int red_lanes(int T) { return T < 4 ? T : 4; }
 
 __host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
 // Per-team LDS (doubles): one area that holds in turn the reduction buffer,
-// the moments and the scaled target solutions; the pivot row; KC cached
-// support weights per lane.
+// the moments, the Gauss-Jordan pivot row and the scaled target solutions
+// (an even count, so that every team area starts on a 16-byte boundary);
+// then KC cached support weights per lane.
 template <int M>
 constexpr int team_lds_doubles(int T, int KC) {
-  return cmax(cmax(nmom<M>(), 4 * M), red_lanes(T) * red_lanes(T)) + M + 1 + KC * T;
+  return ((cmax(cmax(nmom<M>(), 4 * M), cmax(red_lanes(T) * red_lanes(T), M + 1)) + 1) & ~1) + KC * T;
 }
 
 // orders the LDS traffic of the lanes of one wave around a hand-off
@@ -238,7 +240,7 @@ __device__ inline double nbr_weight_h(const WArgs &a, const RowGeom &g, double h
 // Where a row finds the (x, y, z, h) of its neighbours.  idx(e) reads the
 // handle of CSR entry e, get(handle) the position; `dummy` is a valid handle
 // used for the loads issued past the end of a row.  kDeep: the position
-// itself is also loaded one neighbour ahead (worth it for global gathers).
+// itself is also loaded one neighbour ahead (global gathers and LDS reads).
 struct FetchGlobal {  // packed positions, gathered through col[]
   static constexpr bool kDeep = true;
   const double4 *pos;
@@ -250,7 +252,7 @@ struct FetchGlobal {  // packed positions, gathered through col[]
   __device__ double field(int32_t j) const { return u[j]; }
 };
 struct FetchTile {    // the tile's positions (and field) staged in LDS, addressed by slot[]
-  static constexpr bool kDeep = false;
+  static constexpr bool kDeep = true;
   const double4 *sp;
   const uint16_t *slot;
   const double *su;
@@ -314,8 +316,8 @@ __device__ void weights_row_team(const WArgs &a, int32_t i, int lane, double *sm
   double *s_red = sm;
   double *s_mom = sm;
   double *s_lam = sm;
-  double *s_prow = sm + NA;
-  double *s_w = sm + NA + M + 1;
+  double *s_prow = sm;
+  double *s_w = sm + (((cmax(NA, M + 1)) + 1) & ~1);
   const int64_t b = a.row_ptr[i];
   const int n = (int)(a.row_ptr[i + 1] - b);
   if (n < M) {
@@ -392,6 +394,7 @@ __device__ void weights_row_team(const WArgs &a, int32_t i, int lane, double *sm
     }
     gsum = fmax(gsum, sacc);
   }
+  wave_sync();  // the pivot rows overwrite the moments
   bool okp = true;
 #pragma unroll
   for (int k = 0; k < M; ++k) {
@@ -434,7 +437,9 @@ __device__ void weights_row_team(const WArgs &a, int32_t i, int lane, double *sm
   }
   const double gnorm = team_max(gsum, T);
   const double inorm = team_max(isum, T);
-  const double kappa = gnorm * inorm;
+  // a pivot that is not positive: G is not positive definite (rank deficient
+  // or numerically so), reported as an infinite condition number
+  const double kappa = okp ? gnorm * inorm : INFINITY;
   // lambda_s[r] from row r of G^{-1} (= column r)
 #pragma unroll
   for (int q = 0; q < NR; ++q) {
@@ -559,7 +564,7 @@ k_weights_tile(WArgs a, TileArgs ta, const uint16_t *__restrict__ slot) {
   const int team = threadIdx.x / T, lane = threadIdx.x % T;
   const int64_t r = tl * kTileRows + team;
   if (r >= a.nrows) return;
-  double *sm = s_u + (FUSED ? ta.cap : 0) + team * team_lds_doubles<M>(T, 0);
+  double *sm = s_u + (FUSED ? ((ta.cap + 1) & ~1) : 0) + team * team_lds_doubles<M>(T, 0);
   const int32_t i = a.sched[r];
   if (staged)
     weights_row_team<M, T, OUT, FUSED, FASTW, 0>(a, i, lane, sm, FetchTile{s_dyn, slot, s_u, 0});
@@ -809,7 +814,7 @@ gf_status launch_tile(gf_ctx *ctx, const WArgs &a, const gf_nbr *nbr, const Laun
   ta.u = nbr->tile_u;
   ta.tile0 = u.tile0;
   ta.cap = std::min(u.tile_max, tile_capacity(ctx, kTileCap));
-  const size_t lds = (sizeof(double4) + (FUSED ? sizeof(double) : 0)) * ta.cap +
+  const size_t lds = sizeof(double4) * ta.cap + (FUSED ? sizeof(double) * ((ta.cap + 1) & ~1) : 0) +
                      sizeof(double) * kTileRows * team_lds_doubles<M>(T, 0);
   const dim3 grid(grid_for(u.ntiles, 1)), block(kTileRows * T);
   switch (T) {

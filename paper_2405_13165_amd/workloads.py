@@ -157,7 +157,7 @@ def mixed_block_film(factor: int = 1, seed_extra: int = 0):
 
 
 def advdiff_plate(h: float = 0.06, layers: int = 4, seed_extra: int = 0):
-    """Plate for the advection-diffusion analogue (Sec. 7.3): film particles
+    """Plate for the advection-diffusion analogue (Sec. 7.2): film particles
     on [0,2]x[0,1.5] outside x in (0.75, 1.25) and a 3D block of `layers`
     lattice layers on [0.75,1.25]x[0,1.5] (bottom layer wall, normal +z; top
     layer free surface, normal -z, both pointing into the fluid), spacing
@@ -207,7 +207,7 @@ def advdiff_rows(d, h):
 def advect_plate(h: float = 0.06, layers: int = 4, seed_extra: int = 0, lx: float = 2.5, ly: float = 1.5,
                  ic: str = "gauss", center=(0.6, 0.75), radius: float = 0.2, sigma: float = 0.1):
     """Initial cloud of the model-adaptive advection(-diffusion) case
-    (Sec. 7.3): a film of particles on [0,lx]x[0,ly] (spacing s = h/3, jitter
+    (Sec. 7.2): a film of particles on [0,lx]x[0,ly] (spacing s = h/3, jitter
     U(+-0.2 s)), all 2D at t = 0, film thickness (layers-1) s, support h.
     T0, constant in depth, is a Gaussian of width sigma around `center`
     (ic="gauss") or 1 inside the disc of the given radius around it and 0

@@ -1,4 +1,4 @@
-"""The diffusion analogue of the advection-diffusion test (Sec. 7.3) on the
+"""The diffusion analogue of the advection-diffusion test (Sec. 7.2) on the
 GPU library against the oracle's time loop (same cloud, same ghosts, same
 implicit steps; the oracle solves each step exactly by sparse LU), and its
 accuracy against the exact heat-kernel solution."""

@@ -356,7 +356,7 @@ def test_transition_cloud_conserves_mass_and_counts():
     assert np.all(o2["phi"] == 7.25)
 
 
-# --------------------------------------------------------------------------- Sec. 7.3 analogue
+# --------------------------------------------------------------------------- Sec. 7.2 analogue
 def _advdiff_errors(h, kappa=5e-3, t_end=0.5, factor=0.25, ghost_scale=1.0):
     d = W.advdiff_plate(h)
     steps = int(np.ceil(t_end / (factor * 0.05 * h * h / kappa)))
@@ -420,7 +420,7 @@ def test_model_adaptive_advection_round_trip():
 
 
 def test_pure_advection_transfers_data_exactly():
-    # kappa = 0 (Sec. 7.3, pure advection): the plate [0,3]x[0,1] passes the
+    # kappa = 0 (Sec. 7.2, pure advection): the plate [0,3]x[0,1] passes the
     # 3D window [1,2]; since the field is constant in depth, the transitions
     # in both directions move it without loss, and at t = 2 it equals the
     # initial field moved by 2: exactly for the disc of Eq. (AdvDiff_IC)
