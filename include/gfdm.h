@@ -259,6 +259,26 @@ gf_status gf_gfdm_weights_apply(gf_ctx *ctx, const gf_particles *p, const gf_nbr
                                 unsigned op_mask, const double *u, double *out,
                                 int8_t *status_n);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, hosts that forbid hipMalloc): the same
+ * computation and outputs as gf_gfdm_weights_apply, with every temporary
+ * buffer (fallback queue and its counter, QR panels, packed positions) taken
+ * from a fixed workspace of gf_noalloc_workspace_bytes() = 128 MiB that the
+ * library holds on each device until the process ends.  The call allocates
+ * nothing (no hipMalloc / hipFree, no growth of the context's arena); the
+ * caller still passes inputs and outputs.  A call whose workspace would exceed
+ * the fixed size (about 4 n bytes + 30 KiB per neighbour of the longest row,
+ * plus 32 n bytes when rows with more than 128 neighbours exist) returns
+ * GF_ECAPACITY before any launch.  Every call on a device shares that device's
+ * workspace (it keeps the last call's contents; the call clears its counter
+ * itself): calls that overlap on one device, from any context or stream,
+ * race and must be ordered by the caller. */
+gf_status gf_gfdm_weights_apply_noalloc(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr,
+                                        const gf_ls_params *params, gf_dtype wtype, void *w_out,
+                                        unsigned op_mask, const double *u, double *out,
+                                        int8_t *status_n);
+size_t gf_noalloc_workspace_bytes(void);
+
 /* ---------------------------------------------------------- pressure solve */
 enum { GF_ROW_INTERIOR = 0, GF_ROW_DIRICHLET = 1, GF_ROW_NEUMANN_COMBINED = 2,
        GF_ROW_NEUMANN = 3, GF_ROW_IMPLICIT = 4 };

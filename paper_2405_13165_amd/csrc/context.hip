@@ -29,6 +29,8 @@ extern "C" gf_status gf_create(int device, void *stream, gf_ctx **out) {
   if (hipSetDevice(device) != hipSuccess) { delete ctx; return GF_EHIP; }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cu = prop.multiProcessorCount;
+  const gf_status st = fixed_scratch_init(ctx);
+  if (st != GF_OK) { delete ctx; return st; }
   *out = ctx;
   return GF_OK;
 }

@@ -20,6 +20,9 @@ struct gf_ctx {
   // call on this context
   void *scratch = nullptr;
   size_t scratch_bytes = 0;
+  // device address of the library's fixed workspace on this context's device
+  // (used by the entry points that allocate nothing); set by gf_create
+  void *fixed_scratch = nullptr;
   // orders the context's work across gf_set_stream (the calls share scratch)
   hipEvent_t stream_order = nullptr;
   // small pinned host buffer for read-backs
@@ -185,6 +188,9 @@ struct Arena {
   }
 };
 size_t arena_bytes(const std::vector<size_t> &sizes);
+// looks up (once per device, with the device current) the address of the
+// fixed workspace used by gf_gfdm_weights_apply_noalloc and stores it in ctx
+gf_status fixed_scratch_init(gf_ctx *ctx);
 gf_status ensure_scratch(gf_ctx *ctx, size_t bytes, Arena *arena);
 gf_status ensure_host(gf_ctx *ctx, size_t bytes);
 

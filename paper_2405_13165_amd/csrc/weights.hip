@@ -18,6 +18,7 @@
 // Plain path: one work-item per particle in the caller's order, an FP64 Gram
 // matrix with LDL^T solves, FP64 output.
 #include <algorithm>
+#include <mutex>
 
 #include "stencil_common.h"
 
@@ -862,6 +863,13 @@ bool needs_packed_positions(const gf_ctx *ctx, const gf_nbr *nbr) {
   return false;
 }
 
+// The fixed workspace of gf_gfdm_weights_apply_noalloc: a device array of
+// the library (one copy per device, held until the process ends).  Host code
+// never uses its name as an address: gf_create looks up its device address
+// once per device (fixed_scratch_init) and kernels receive that address.
+constexpr size_t kFixedScratchBytes = size_t(128) << 20;
+constexpr int kFixedQrBlocks = 256;  // blocks of the QR fallback in that mode (the grid strides over the queue)
+
 struct WeightsScratch {
   int32_t *queue, *qcount;
   double *qr;
@@ -873,9 +881,12 @@ struct WeightsScratch {
   double *kmax;
 };
 
+// fixed: carve the scratch from the library's fixed workspace (no
+// allocation; GF_ECAPACITY if it does not fit) instead of the context arena.
 gf_status weights_common(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr, gf_prec prec,
                          const gf_ls_params *params, gf_dtype wtype, void *w_out, int8_t *status_n, float *kappa_n,
-                         gf_ls_stats *stats, bool fused, unsigned op_mask, const double *u, double *out) {
+                         gf_ls_stats *stats, bool fused, unsigned op_mask, const double *u, double *out,
+                         bool fixed = false) {
   gf_status st = check_particles(ctx, p, false, false);
   if (st) return st;
   if ((st = check_nbr(ctx, nbr, p->n))) return st;
@@ -894,23 +905,41 @@ gf_status weights_common(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr, 
   bool has_film = nbr->group_start[2 * GF_NBAND] > nbr->group_start[GF_NBAND];
   if (has_film && (!p->nx || !p->ny || !p->nz)) return set_error(ctx, GF_EINVAL, "film particles need normals");
   const int64_t n = p->n;
-  const int qr_blocks = (int)std::min<int64_t>(1024, n);
+  const int qr_blocks = (int)std::min<int64_t>(fixed ? kFixedQrBlocks : 1024, n);
   const int64_t slice = (int64_t)kQrStride * std::max(nbr->max_row, 1);
   const bool packed = prec == GF_BATCHED && needs_packed_positions(ctx, nbr);
   Arena ar;
-  if ((st = ensure_scratch(ctx, arena_bytes({sizeof(int32_t) * n, 64, sizeof(double) * slice * qr_blocks, (size_t)n,
-                                             sizeof(float) * n, 64, 64, sizeof(double4) * n}),
-                           &ar)))
-    return st;
   WeightsScratch ws;
-  ws.queue = ar.take<int32_t>(n);
-  ws.qcount = ar.take<int32_t>(16);
-  ws.qr = ar.take<double>(slice * qr_blocks);
-  ws.status = ar.take<int8_t>(n);
-  ws.kappa = ar.take<float>(n);
-  ws.counts = ar.take<long long>(4);
-  ws.kmax = ar.take<double>(1);
-  double4 *pos = ar.take<double4>(n);
+  double4 *pos = nullptr;
+  if (fixed) {
+    // only what the fused call uses: queue, counter, QR panels, packed positions
+    const size_t need = arena_bytes({sizeof(int32_t) * n, 64, sizeof(double) * slice * qr_blocks,
+                                     packed ? sizeof(double4) * n : 0});
+    if (need > kFixedScratchBytes)
+      return set_error(ctx, GF_ECAPACITY, "the workspace of this call needs %zu bytes, the fixed workspace holds %zu "
+                       "(%lld particles, longest row %d)", need, kFixedScratchBytes, (long long)n, (int)nbr->max_row);
+    if (!ctx->fixed_scratch) return set_error(ctx, GF_EHIP, "fixed workspace address unknown");
+    ar.base = (char *)ctx->fixed_scratch;
+    ar.off = 0;
+    ws.queue = ar.take<int32_t>(n);
+    ws.qcount = ar.take<int32_t>(16);
+    ws.qr = ar.take<double>(slice * qr_blocks);
+    if (packed) pos = ar.take<double4>(n);
+    ws.status = nullptr; ws.kappa = nullptr; ws.counts = nullptr; ws.kmax = nullptr;
+  } else {
+    if ((st = ensure_scratch(ctx, arena_bytes({sizeof(int32_t) * n, 64, sizeof(double) * slice * qr_blocks, (size_t)n,
+                                               sizeof(float) * n, 64, 64, sizeof(double4) * n}),
+                             &ar)))
+      return st;
+    ws.queue = ar.take<int32_t>(n);
+    ws.qcount = ar.take<int32_t>(16);
+    ws.qr = ar.take<double>(slice * qr_blocks);
+    ws.status = ar.take<int8_t>(n);
+    ws.kappa = ar.take<float>(n);
+    ws.counts = ar.take<long long>(4);
+    ws.kmax = ar.take<double>(1);
+    pos = ar.take<double4>(n);
+  }
   WArgs a;
   a.x = p->x; a.y = p->y; a.z = p->z; a.h = p->h; a.nx = p->nx; a.ny = p->ny; a.nz = p->nz; a.model = p->model;
   a.pos = pos;
@@ -923,8 +952,8 @@ gf_status weights_common(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr, 
   a.wf = make_weight_fn(prm.alpha_w);
   a.kappa_max = prm.kappa_max;
   a.w_out = w_out;
-  a.status = status_n ? status_n : ((stats) ? ws.status : nullptr);
-  a.kappa_out = kappa_n ? kappa_n : ((stats) ? ws.kappa : nullptr);
+  a.status = status_n ? status_n : ((stats && !fixed) ? ws.status : nullptr);
+  a.kappa_out = kappa_n ? kappa_n : ((stats && !fixed) ? ws.kappa : nullptr);
   a.queue = ws.queue;
   a.qcount = ws.qcount;
   a.u = u; a.y_out = out; a.mask = op_mask;
@@ -952,7 +981,7 @@ gf_status weights_common(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr, 
     else hipLaunchKernelGGL((k_weights_qr<GF_F64, true, false>), dim3(qr_blocks), dim3(kQrBlock), 0, ctx->stream, a, ws.qr, slice);
   }
   GF_LAUNCH_CHECK(ctx);
-  if (stats) {
+  if (stats && !fixed) {
     hipLaunchKernelGGL(k_ls_stats, dim3(1), dim3(1024), 0, ctx->stream, a.status, a.kappa_out, n, ws.counts, ws.kmax);
     GF_LAUNCH_CHECK(ctx);
     if ((st = ensure_host(ctx, 4096))) return st;
@@ -990,6 +1019,41 @@ extern "C" gf_status gf_gfdm_weights_apply(gf_ctx *ctx, const gf_particles *p, c
   return weights_common(ctx, p, nbr, GF_BATCHED, params, wtype, w_out, status_n, nullptr, nullptr, true, op_mask, u,
                         out);
 }
+
+// ------------------------------------------------------------------ fixed workspace
+static __device__ __align__(256) unsigned char scratch[kFixedScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_fixed_mutex;
+void *g_fixed_ptr[kMaxDevices] = {nullptr};
+}  // namespace
+
+gf_status fixed_scratch_init(gf_ctx *ctx) {
+  if (ctx->device < 0 || ctx->device >= kMaxDevices)
+    return set_error(ctx, GF_ECAPACITY, "device index %d beyond %d", ctx->device, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_fixed_mutex);
+  if (!g_fixed_ptr[ctx->device]) {
+    GF_HIP(ctx, hipSetDevice(ctx->device));
+    void *ptr = nullptr;
+    GF_HIP(ctx, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return set_error(ctx, GF_EHIP, "hipGetSymbolAddress returned no address for the fixed workspace");
+    g_fixed_ptr[ctx->device] = ptr;
+  }
+  ctx->fixed_scratch = g_fixed_ptr[ctx->device];
+  return GF_OK;
+}
+
+extern "C" gf_status gf_gfdm_weights_apply_noalloc(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr,
+                                                   const gf_ls_params *params, gf_dtype wtype, void *w_out,
+                                                   unsigned op_mask, const double *u, double *out,
+                                                   int8_t *status_n) {
+  if (!ctx) return GF_EINVAL;
+  return weights_common(ctx, p, nbr, GF_BATCHED, params, wtype, w_out, status_n, nullptr, nullptr, true, op_mask, u,
+                        out, true);
+}
+
+extern "C" size_t gf_noalloc_workspace_bytes(void) { return kFixedScratchBytes; }
 
 // ------------------------------------------------------------------ autotuner
 // Times every launch unit of the batched stencil kernel with teams of 4, 8

@@ -80,7 +80,7 @@ EXPORTED = [
     "gf_poisson_solve", "gf_transition_3d_to_2d", "gf_apply_stencil_adjoint",
     "gf_gfdm_weights_adjoint", "gf_profile_enable", "gf_profile_read", "gf_autotune", "gf_set_team_sizes", "gf_set_tile_capacity",
     "gf_build_neighbours_rows", "gf_film_height", "gf_transition_2d_to_3d", "gf_buffer_flags", "gf_buffer_zone",
-    "gf_transition_3d_to_2d_cloud",
+    "gf_transition_3d_to_2d_cloud", "gf_gfdm_weights_apply_noalloc", "gf_noalloc_workspace_bytes",
 ]
 
 _lib = None
@@ -119,6 +119,9 @@ def load_library(path: str = LIB_PATH):
                                   ctypes.POINTER(LsStats)]
     L.gf_apply_stencil.argtypes = [P, P, I32, P, U, I32, P, P]
     L.gf_gfdm_weights_apply.argtypes = [P, PP, P, ctypes.POINTER(LsParams), I32, P, U, P, P, P]
+    L.gf_gfdm_weights_apply_noalloc.argtypes = [P, PP, P, ctypes.POINTER(LsParams), I32, P, U, P, P, P]
+    L.gf_noalloc_workspace_bytes.argtypes = []
+    L.gf_noalloc_workspace_bytes.restype = ctypes.c_size_t
     L.gf_poisson_assemble.argtypes = [P, PP, P, P, P, D, P]
     L.gf_solve_params_default.argtypes = [ctypes.POINTER(SolveParams)]
     L.gf_solve_params_default.restype = None
@@ -413,6 +416,19 @@ def gfdm_weights_apply(ctx, p, nbr, u, op_mask=0xF, wtype=GF_F32, params=None, s
     ctx.check(ctx.lib.gf_gfdm_weights_apply(ctx.handle, ctypes.byref(p.s), nbr.handle, ctypes.byref(prm), wtype,
                                             _ptr(w), op_mask, _ptr(u), _ptr(o), _ptr(status)))
     return w, o
+
+
+def gfdm_weights_apply_noalloc(ctx, p, nbr, u, w_out, out, op_mask=0xF, params=None, status=None, wtype=None):
+    """gf_gfdm_weights_apply_noalloc: as gfdm_weights_apply with caller-given
+    outputs (w_out may be None: stencils of type wtype, default FP32, are
+    applied and discarded) and no allocation inside the library."""
+    if wtype is None:
+        wtype = GF_F32 if (w_out is None or w_out.dtype == torch.float32) else GF_F64
+    prm = params if params is not None else ls_params()
+    ctx._sync_stream()
+    ctx.check(ctx.lib.gf_gfdm_weights_apply_noalloc(ctx.handle, ctypes.byref(p.s), nbr.handle, ctypes.byref(prm),
+                                                    wtype, _ptr(w_out), op_mask, _ptr(u), _ptr(out), _ptr(status)))
+    return w_out, out
 
 
 def poisson_assemble(ctx, p, nbr, w64, row_type, zeta=0.3):
