@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--no-rows", action="store_true", help="skip timing the other hot-path steps")
     ap.add_argument("--quick", action="store_true",
                     help="only the headline workload (no jet, differentiation or pressure-solve records)")
+    ap.add_argument("--records", default="jet,diff,poisson",
+                    help="comma list of the further records to run: jet, diff, poisson (default: all)")
     ap.add_argument("--poisson-n", type=int, default=4_000_000,
                     help="particles of the projection cylinder of the pressure-solve record")
     ap.add_argument("--advdiff", action="store_true",
@@ -208,6 +210,7 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     t_start = time.time()
+    records = set() if args.quick else {r.strip() for r in args.records.split(",") if r.strip()}
     t0 = time.time()
     d = W.mixed_block_film(factor=args.factor)
     N = d["x"].shape[0]
@@ -224,13 +227,21 @@ def main():
         flush_buf.fill_(1.0)
         flush_src.sum()
 
-    def timed(fn, steps, warmup, flushed=True):
+    def timed(fn, steps, warmup, flushed=True, kernels=False):
         """Mean ms of one call over `steps` calls after `warmup` untimed ones.
-        flushed: each call bracketed by its own events, after a 1 GiB write."""
+        flushed: each call bracketed by its own events, after the cache flush.
+        kernels: also return the library's HIP-event times of each of its kernels
+        over the same timed calls ({name: {launches, avg_us}})."""
         for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
         s = torch.cuda.current_stream()
+        if kernels:
+            ctx.profile(True)
+            ms = timed(fn, steps, 0, flushed)
+            prof = ctx.profile_read()
+            ctx.profile(False)
+            return ms, {k: {"launches": c, "avg_us": 1000.0 * t / c} for k, (c, t) in prof.items()}
         if not flushed:
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(s)
@@ -341,7 +352,7 @@ def main():
         log("profile run done (copy calibration: 1 GiB read + 1 GiB written)")
         return
 
-    ms_fused = timed(step_fused, args.steps, args.warmup)
+    ms_fused, kernels = timed(step_fused, args.steps, args.warmup, kernels=True)
     ms_fused_b2b = timed(step_fused, args.steps, args.warmup, flushed=False)
     ms_batched = timed(step_batched, args.steps, args.warmup)
     ms_plain = timed(step_plain, args.steps, args.warmup)
@@ -366,14 +377,14 @@ def main():
         f"(b2b {ms_graph_b2b:.3f}, replay exact: {graph_ok}); separate calls {ms_batched:.3f}; plain {ms_plain:.3f}")
 
     reps = max(3, min(args.steps, 10))
-    kernels = kernels_of(step_fused, reps)
+    kernels_b2b = kernels_of(step_fused, reps)
     kernels_sep = kernels_of(step_batched, reps)
     kernels_plain = kernels_of(step_plain, reps)
 
     # ---- roofline of the dominant kernel (the largest fused stencil launch)
     costs = unit_costs(rp, d["model"])
 
-    def roofline(kern, costs_, team_of):
+    def roofline(kern, costs_, team_of, kern_b2b=None):
         wk = {k: v for k, v in kern.items() if k.startswith("weights_apply_")}
         dom = max(wk, key=lambda k: wk[k]["avg_us"] * wk[k]["launches"])
         m_dom = 0 if "_3d_" in dom else 1
@@ -394,9 +405,15 @@ def main():
                                           "bytes_per_particle": "40 n + 52",
                                           "flops_per_particle": "2 n m^2 + 4 S n m + 2 S n"}
         roof["other_roof"] = {"fp64_TFLOPs": round(tfl, 3), "fp64_frac": round(tfl / PEAK_FP64_TFLOPS, 4)}
+        roof["timing"] = "HIP events around each launch inside the timed (cache-flushed) steps"
+        if kern_b2b and dom in kern_b2b:
+            sec_b = kern_b2b[dom]["avg_us"] * 1e-6
+            roof["other_roof"]["back_to_back"] = {"avg_launch_us": round(sec_b * 1e6, 2),
+                                                  "GBs": round(c["bytes"] / sec_b / 1e9, 1),
+                                                  "hbm_frac": round(c["bytes"] / sec_b / 1e9 / PEAK_HBM_GBS, 4)}
         return roof
 
-    roof = roofline(kernels, costs, lambda m, unit: teams["fused"][4 * m + (2 if unit == "tiles" else 3)])
+    roof = roofline(kernels, costs, lambda m, unit: teams["fused"][4 * m + (2 if unit == "tiles" else 3)], kernels_b2b)
     step_bytes = sum(c["bytes"] for c in costs.values())
     step_hbm_frac = step_bytes / (ms_fused * 1e-3) / 1e9 / PEAK_HBM_GBS
 
@@ -443,6 +460,7 @@ def main():
         "step_roofline": {"algorithmic_bytes": step_bytes, "GBs": round(step_bytes / (ms_fused * 1e-3) / 1e9, 1),
                           "hbm_frac": round(step_hbm_frac, 4), "bytes_per_particle": "40 n + 52"},
         "kernels_batched": kernels,
+        "kernels_batched_back_to_back": kernels_b2b,
         "kernels_separate_calls": kernels_sep,
         "kernels_plain": kernels_plain,
         "roofline": roof,
@@ -528,7 +546,7 @@ def main():
 
     # ---- jet-on-plate cloud: uneven neighbourhoods (20-250), the fused step
     jet_eval = None
-    if not args.quick:
+    if "jet" in records:
         dj = W.jet_impact()
         pj = g.Particles.from_dict(ctx, dj)
         nbj = g.build_neighbours(ctx, pj)
@@ -540,7 +558,7 @@ def main():
         yj = torch.empty((4, pj.n), dtype=torch.float64, device=dev)
         stj = torch.empty(pj.n, dtype=torch.int8, device=dev)
         step_j = lambda: g.gfdm_weights_apply(ctx, pj, nbj, uj, 0xF, g.GF_F32, w_out=wj, out=yj, status=stj)
-        ms_j = timed(step_j, args.steps, args.warmup)
+        ms_j, kern_j = timed(step_j, args.steps, args.warmup, kernels=True)
         w64j = torch.empty((nbj.nnz, 4), dtype=torch.float64, device=dev)
         y64j = torch.empty((4, pj.n), dtype=torch.float64, device=dev)
 
@@ -549,7 +567,6 @@ def main():
             g.apply_stencil(ctx, nbj, w64j, uj, 0xF, out=y64j)
 
         ms_jp = timed(step_jp, max(3, args.steps // 2), 1)
-        kern_j = kernels_of(step_j, 3)
         costs_j = unit_costs(rpj, dj["model"])
         roof_j = roofline(kern_j, costs_j, lambda m, unit: teams_j["fused"][4 * m + (2 if unit == "tiles" else 3)])
         step_j()
@@ -580,7 +597,7 @@ def main():
         del pj, nbj, uj, wj, yj, stj, w64j, y64j
 
     # ---- differentiation cube: forward + backward of the Laplacian loss
-    if not args.quick:
+    if "diff" in records:
         dd = W.diff_cube()
         pd = g.Particles.from_dict(ctx, dd)
         nbd = g.build_neighbours(ctx, pd)
@@ -605,7 +622,7 @@ def main():
         del dd, pd, nbd, ud, gd, xs
 
     # ---- pressure-Poisson solve on the 4.0M projection cylinder
-    if not args.quick and args.poisson_n > 0:
+    if "poisson" in records and args.poisson_n > 0:
         dp = W.projection_cylinder(args.poisson_n)
         pp = g.Particles.from_dict(ctx, dp)
         nbp = g.build_neighbours(ctx, pp)

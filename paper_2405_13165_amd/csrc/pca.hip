@@ -1,15 +1,17 @@
 // Local PCA of every neighbourhood and the transition flags of Sec. 4.
 //
-// A team of kTeam lanes per particle builds the 3x3 covariance in two passes
-// (centroid, then centred second moments) from offsets relative to the
-// particle itself, so an exactly planar neighbourhood yields an exactly zero
-// third eigenvalue.  Rows with at most 128 neighbours are processed by
-// neighbour tiles: a block takes kPcaTiles consecutive tiles, stages each
-// tile's distinct neighbours (position, index and kind) in LDS in turn, and
-// keeps the covariances and neighbour-kind counts of all its rows in LDS;
-// then every thread of the block runs the eigen solve and the classification
-// of one row, so the serial 3x3 Jacobi solves use every lane.  Rows with more
-// neighbours gather from global memory, and one lane of the team solves.
+// A team of kTeam lanes per particle.  Rows with at most 128 neighbours run
+// one neighbour tile per block: the tile's distinct neighbours (position and
+// kind) are staged in LDS and read through the tile slots, which each lane
+// loads in aligned quads, all before the first is used; rows with more
+// neighbours gather from global memory.  One pass accumulates the sums of
+// the offsets d = x_j - x_i and of their products, and the covariance about
+// the centroid follows as sum d d^T - (sum d)(sum d)^T / n: offsets relative
+// to the particle itself keep an exactly planar neighbourhood exactly planar
+// (its third eigenvalue is exactly zero), and with |d| <= h the subtraction
+// loses no more than a few ulp of the largest eigenvalue.  The neighbour
+// kinds are counted in 16-bit fields of one integer.  One lane of the team
+// then runs the eigen solve and the classification.
 #include "stencil_common.h"
 
 using namespace gfdm_dev;
@@ -125,115 +127,110 @@ __device__ void pca_finish(const PcaArgs &a, int32_t i, int n_int, int n_fs, dou
   a.raw[i] = f;
 }
 
-// A neighbour as (x, y, z, 4 index + kind code): the index and the code
-// (kind 0..2, anything else 3) are exact in the FP64 field.
+// A neighbour as (x, y, z, 16 * kind code), the code being the kind 0..2 or 3
+// for anything else: the shift that counts it in its 16-bit field.
 __device__ inline double pca_code(const PcaArgs &a, int32_t j) {
   const int k = a.kind ? (int)a.kind[j] : 0;
-  return (double)(4 * (int64_t)j + ((k >= 0 && k <= 2) ? k : 3));
+  return (double)(16 * ((k >= 0 && k <= 2) ? k : 3));
 }
 struct PcaTile {   // staged in LDS, addressed by slot[]
+  static constexpr bool kQuads = true;
   const double4 *sp;
   const uint16_t *slot;
   __device__ double4 operator()(const PcaArgs &, int64_t k) const { return sp[slot[k]]; }
 };
 struct PcaGlobal {
+  static constexpr bool kQuads = false;
   __device__ double4 operator()(const PcaArgs &a, int64_t k) const {
     const int32_t j = a.col[k];
     return make_double4(a.x[j], a.y[j], a.z[j], pca_code(a, j));
   }
 };
 
-// covariance (c00 c01 c02 c11 c12 c22) and the counts of interior and
-// free-surface neighbours of row i, complete on every lane of the team
+constexpr int kPq = 128 / (4 * kTeam) + 1;  // quads per lane for rows of at most 128 entries
 template <class F>
-__device__ void pca_cov(const PcaArgs &a, int32_t i, int lane, const F &fetch, double c[6], int &n_int, int &n_fs) {
+__device__ void pca_row(const PcaArgs &a, int32_t i, int lane, const F &fetch) {
   const int64_t b = a.row_ptr[i], e = a.row_ptr[i + 1];
   const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
   const bool need_kinds = a.raw && a.kind;
+  double c[6];
+  int n_int = 0, n_fs = 0;
+  uint64_t kinds = 0;
   double mx = 0.0, my = 0.0, mz = 0.0;
-  n_int = 0;
-  n_fs = 0;
-  for (int64_t k = b + lane; k < e; k += kTeam) {
-    const double4 pj = fetch(a, k);
-    mx += pj.x - xi;
-    my += pj.y - yi;
-    mz += pj.z - zi;
-    if (need_kinds) {
-      const int64_t code = (int64_t)pj.w;
-      if ((code >> 2) != i) {
-        const int kj = (int)(code & 3);
-        n_int += (kj == GF_KIND_INTERIOR);
-        n_fs += (kj == GF_KIND_FREE_SURFACE);
+  double sxx = 0.0, sxy = 0.0, sxz = 0.0, syy = 0.0, syz = 0.0, szz = 0.0;
+  auto visit = [&](const double4 &pj) {
+    const double dx = pj.x - xi, dy = pj.y - yi, dz = pj.z - zi;
+    mx += dx; my += dy; mz += dz;
+    sxx += dx * dx; sxy += dx * dy; sxz += dx * dz;
+    syy += dy * dy; syz += dy * dz; szz += dz * dz;
+    if (need_kinds) kinds += (uint64_t)1 << (int)pj.w;
+  };
+  if constexpr (F::kQuads) {
+    // entries 4q .. 4q+3 of the aligned quads q0 + lane, q0 + lane + kTeam, ...; a quad may reach
+    // up to three entries into the neighbouring rows (padded slot array): those are skipped
+    const int64_t q0 = (b >> 2) + lane;
+    ushort4 ss[kPq];
+#pragma unroll
+    for (int j = 0; j < kPq; ++j) {
+      const int64_t k = 4 * (q0 + j * kTeam);
+      if (k < e) ss[j] = *reinterpret_cast<const ushort4 *>(fetch.slot + k);
+    }
+#pragma unroll
+    for (int j = 0; j < kPq; ++j) {
+      const int64_t k = 4 * (q0 + j * kTeam);
+      if (k < e) {
+        if (k >= b) visit(fetch.sp[ss[j].x]);
+        if (k + 1 >= b && k + 1 < e) visit(fetch.sp[ss[j].y]);
+        if (k + 2 >= b && k + 2 < e) visit(fetch.sp[ss[j].z]);
+        if (k + 3 < e) visit(fetch.sp[ss[j].w]);
       }
     }
+  } else {
+    for (int64_t k = b + lane; k < e; k += kTeam) visit(fetch(a, k));
   }
   mx = team_sum(mx, kTeam);
   my = team_sum(my, kTeam);
   mz = team_sum(mz, kTeam);
-  n_int = team_sum(n_int, kTeam);
-  n_fs = team_sum(n_fs, kTeam);
-  const double inv = 1.0 / (double)(e - b);
-  mx *= inv; my *= inv; mz *= inv;
-#pragma unroll
-  for (int q = 0; q < 6; ++q) c[q] = 0.0;
-  for (int64_t k = b + lane; k < e; k += kTeam) {
-    const double4 pj = fetch(a, k);
-    const double dx = (pj.x - xi) - mx, dy = (pj.y - yi) - my, dz = (pj.z - zi) - mz;
-    c[0] += dx * dx; c[1] += dx * dy; c[2] += dx * dz;
-    c[3] += dy * dy; c[4] += dy * dz; c[5] += dz * dz;
+  if (need_kinds) {
+    kinds = team_sum(kinds, kTeam);
+    // i is in S_i once: remove its own kind
+    const int ko = (int)a.kind[i];
+    kinds -= (uint64_t)1 << (16 * ((ko >= 0 && ko <= 2) ? ko : 3));
+    n_int = (int)(kinds & 0xFFFF);
+    n_fs = (int)((kinds >> 16) & 0xFFFF);
   }
-#pragma unroll
-  for (int q = 0; q < 6; ++q) c[q] = team_sum(c[q], kTeam);
+  sxx = team_sum(sxx, kTeam); sxy = team_sum(sxy, kTeam); sxz = team_sum(sxz, kTeam);
+  syy = team_sum(syy, kTeam); syz = team_sum(syz, kTeam); szz = team_sum(szz, kTeam);
+  const double inv = 1.0 / (double)(e - b);
+  const double cx = mx * inv, cy = my * inv, cz = mz * inv;
+  c[0] = sxx - mx * cx; c[1] = sxy - mx * cy; c[2] = sxz - mx * cz;
+  c[3] = syy - my * cy; c[4] = syz - my * cz; c[5] = szz - mz * cz;
+  if (lane == 0) pca_finish(a, i, n_int, n_fs, c[0], c[1], c[2], c[3], c[4], c[5]);
 }
 
-// Tiled rows: kPcaTiles consecutive neighbour tiles per block (kTileRows
-// teams of kTeam lanes, so a block has as many threads as its rows).
-constexpr int kPcaTiles = kTeam;
-constexpr int kPcaRows = kTileRows * kPcaTiles;  // rows of a block = its threads
+// tiled rows: one neighbour tile per block, kTileRows teams
 __global__ void __launch_bounds__(kTileRows * kTeam) k_pca_tile(PcaArgs a, const int64_t *__restrict__ toff,
                                                                 const int32_t *__restrict__ tu,
                                                                 const uint16_t *__restrict__ slot, int64_t tile0,
-                                                                int64_t ntiles, int cap) {
+                                                                int cap) {
   extern __shared__ double4 s_pos[];
-  __shared__ double s_cov[6][kPcaRows];
-  __shared__ int s_cnt[2][kPcaRows];
-  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const int team = threadIdx.x / kTeam, lane = threadIdx.x % kTeam;
-  for (int q = 0; q < kPcaTiles; ++q) {
-    const int64_t tl = blk * kPcaTiles + q;
-    if (tl >= ntiles) break;  // uniform over the block
-    const int64_t u0 = toff[tile0 + tl];
-    const int cnt = (int)(toff[tile0 + tl + 1] - u0);
-    const bool staged = cnt <= cap;
-    if (staged) {
-      for (int s = threadIdx.x; s < cnt; s += blockDim.x) {
-        const int32_t j = tu[u0 + s];
-        s_pos[s] = make_double4(a.x[j], a.y[j], a.z[j], pca_code(a, j));
-      }
+  const int64_t tl = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t u0 = toff[tile0 + tl];
+  const int cnt = (int)(toff[tile0 + tl + 1] - u0);
+  const bool staged = cnt <= cap;
+  if (staged) {
+    for (int s = threadIdx.x; s < cnt; s += blockDim.x) {
+      const int32_t j = tu[u0 + s];
+      s_pos[s] = make_double4(a.x[j], a.y[j], a.z[j], pca_code(a, j));
     }
-    __syncthreads();
-    const int64_t r = tl * kTileRows + team;
-    if (r < a.nrows) {
-      double c[6];
-      int n_int, n_fs;
-      if (staged) pca_cov(a, a.sched[r], lane, PcaTile{s_pos, slot}, c, n_int, n_fs);
-      else pca_cov(a, a.sched[r], lane, PcaGlobal{}, c, n_int, n_fs);
-      if (lane == 0) {
-        const int t = q * kTileRows + team;
-#pragma unroll
-        for (int k = 0; k < 6; ++k) s_cov[k][t] = c[k];
-        s_cnt[0][t] = n_int;
-        s_cnt[1][t] = n_fs;
-      }
-    }
-    __syncthreads();  // the staging buffer is rewritten by the next tile
   }
-  // one row per thread: eigen solve and classification
-  const int t = threadIdx.x;
-  const int64_t r = blk * kPcaRows + t;
+  __syncthreads();
+  const int team = threadIdx.x / kTeam, lane = threadIdx.x % kTeam;
+  const int64_t r = tl * kTileRows + team;
   if (r >= a.nrows) return;
-  pca_finish(a, a.sched[r], s_cnt[0][t], s_cnt[1][t], s_cov[0][t], s_cov[1][t], s_cov[2][t], s_cov[3][t],
-             s_cov[4][t], s_cov[5][t]);
+  const int32_t i = a.sched[r];
+  if (staged) pca_row(a, i, lane, PcaTile{s_pos, slot});
+  else pca_row(a, i, lane, PcaGlobal{});
 }
 
 // untiled rows: teams over the rows of the launch, gathers from global memory
@@ -241,11 +238,7 @@ __global__ void __launch_bounds__(kBlock) k_pca_flags(PcaArgs a) {
   const int64_t gt = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int64_t r = gt / kTeam;
   if (r >= a.nrows) return;
-  const int32_t i = a.sched[r];
-  double c[6];
-  int n_int, n_fs;
-  pca_cov(a, i, (int)(gt % kTeam), PcaGlobal{}, c, n_int, n_fs);
-  if (gt % kTeam == 0) pca_finish(a, i, n_int, n_fs, c[0], c[1], c[2], c[3], c[4], c[5]);
+  pca_row(a, a.sched[r], (int)(gt % kTeam), PcaGlobal{});
 }
 
 // smoothing rule 1 over the cross-model neighbourhood
@@ -314,9 +307,8 @@ extern "C" gf_status gf_classify_pca(gf_ctx *ctx, const gf_particles *p, const g
     a.nrows = u.nrows;
     if (u.tiled) {
       const int cap = std::min(u.tile_max, tile_capacity(ctx, kPcaCap));
-      hipLaunchKernelGGL(k_pca_tile, dim3(grid_for(u.ntiles, kPcaTiles)), dim3(kTileRows * kTeam),
-                         sizeof(double4) * cap, ctx->stream, a, same->tile_off, same->tile_u, same->slot, u.tile0,
-                         u.ntiles, cap);
+      hipLaunchKernelGGL(k_pca_tile, dim3(grid_for(u.ntiles, 1)), dim3(kTileRows * kTeam), sizeof(double4) * cap,
+                         ctx->stream, a, same->tile_off, same->tile_u, same->slot, u.tile0, cap);
     } else {
       hipLaunchKernelGGL(k_pca_flags, dim3(grid_for(u.nrows * kTeam, kBlock)), dim3(kBlock), 0, ctx->stream, a);
     }

@@ -244,6 +244,7 @@ __device__ inline double nbr_weight_h(const WArgs &a, const RowGeom &g, double h
 // itself is also loaded one neighbour ahead (global gathers and LDS reads).
 struct FetchGlobal {  // packed positions, gathered through col[]
   static constexpr bool kDeep = true;
+  static constexpr bool kQuads = false;
   const double4 *pos;
   const int32_t *col;
   const double *u;     // field of the fused application
@@ -254,6 +255,7 @@ struct FetchGlobal {  // packed positions, gathered through col[]
 };
 struct FetchTile {    // the tile's positions (and field) staged in LDS, addressed by slot[]
   static constexpr bool kDeep = true;
+  static constexpr bool kQuads = true;  // slots may be read in aligned groups of four
   const double4 *sp;
   const uint16_t *slot;
   const double *su;
@@ -340,7 +342,7 @@ __device__ void weights_row_team(const WArgs &a, int32_t i, int lane, double *sm
   double mom[NM];
 #pragma unroll
   for (int p = 0; p < NM; ++p) mom[p] = 0.0;
-  for_neighbours<T>(fetch, b, n, lane, [&](int k, const double4 &pj, int32_t) {
+  auto acc1 = [&](int k, const double4 &pj, int32_t) {
     const double dx = pj.x - g.xi, dy = pj.y - g.yi, dz = pj.z - g.zi;
     const double w = nbr_weight_h<FASTW>(a, g, pj.w, dx, dy, dz);
     if constexpr (KC > 0)
@@ -348,7 +350,33 @@ __device__ void weights_row_team(const WArgs &a, int32_t i, int lane, double *sm
     double X, Y, Z;
     local_xyz<M>(g, dx, dy, dz, X, Y, Z);
     moments_add<M>(mom, w, X, Y, Z);
-  });
+  };
+  if constexpr (F::kQuads && KC == 0) {
+    // tiled rows (at most kTileBandRow entries): lane l takes the aligned quads of
+    // slots q0 + l, q0 + l + T, ..., all loaded before the first is used; a quad may
+    // reach up to three entries into the neighbouring rows (the slot array is
+    // padded): those are skipped
+    constexpr int kQ1 = kTileBandRow / (4 * T) + 1;
+    const int64_t q0 = (b >> 2) + lane, e = b + n;
+    ushort4 ss[kQ1];
+#pragma unroll
+    for (int j = 0; j < kQ1; ++j) {
+      const int64_t k = 4 * (q0 + j * T);
+      if (k < e) ss[j] = *reinterpret_cast<const ushort4 *>(fetch.slot + k);
+    }
+#pragma unroll
+    for (int j = 0; j < kQ1; ++j) {
+      const int64_t k = 4 * (q0 + j * T);
+      if (k < e) {
+        if (k >= b) acc1(0, fetch.get(ss[j].x), 0);
+        if (k + 1 >= b && k + 1 < e) acc1(0, fetch.get(ss[j].y), 0);
+        if (k + 2 >= b && k + 2 < e) acc1(0, fetch.get(ss[j].z), 0);
+        if (k + 3 < e) acc1(0, fetch.get(ss[j].w), 0);
+      }
+    }
+  } else {
+    for_neighbours<T>(fetch, b, n, lane, acc1);
+  }
   // ---- team sum of the moments: butterflies down to R8 lanes, then a
   // transpose through LDS in chunks of R8 moments (lane m of the chunk adds
   // the R8 partials of moment c R8 + m in lane order)
