@@ -218,11 +218,13 @@ static inline unsigned grid_for(int64_t work_items, int block) {
 // support weight parameters shared by the stencil kernels
 struct WeightFn {
   double alpha, ea, inv_den;  // e^{-a}, 1/(1 - e^{-a})
+  double nl2a;                // -a log2(e)
 };
 static inline WeightFn make_weight_fn(double alpha) {
   WeightFn f;
   f.alpha = alpha;
   f.ea = std::exp(-alpha);
   f.inv_den = 1.0 / (1.0 - f.ea);
+  f.nl2a = -alpha * 1.4426950408889634;
   return f;
 }

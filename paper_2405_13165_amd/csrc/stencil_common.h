@@ -88,6 +88,21 @@ __device__ inline double support_weight_q2(double q2, const WeightFn &wf) {
     return (exp(-wf.alpha * q2) - wf.ea) * wf.inv_den;
   }
 }
+// e^{-a q^2} - e^{-a}: the support weight without its normalising factor
+// 1 / (1 - e^{-a}).  A common factor of all weights of a row cancels from the
+// stencils (G scales by it, the target solutions by its inverse), so the
+// batched kernels leave it out.  Same evaluation as above.
+template <bool FASTW>
+__device__ inline double support_weight_raw_q2(double q2, const WeightFn &wf) {
+  if constexpr (FASTW) {
+    const double t = q2 * wf.nl2a;
+    const double k = rint(t);
+    const float e = __builtin_amdgcn_exp2f((float)fma(q2, wf.nl2a, -k));
+    return ldexp((double)e, (int)k) - wf.ea;
+  } else {
+    return exp(-wf.alpha * q2) - wf.ea;
+  }
+}
 // the same with q^2 = d2 / r^2
 template <bool FASTW>
 __device__ inline double support_weight(double d2, double r, const WeightFn &wf) {
@@ -216,59 +231,102 @@ __host__ __device__ constexpr int gram_moment(int r, int c) {
     return kMom2.idx[kExp2[r][0] + kExp2[c][0]][kExp2[r][1] + kExp2[c][1]];
 }
 
-// scaled local coordinates (X, Y, Z) or (U, V, 0)
+// degree of monomial a of the basis
 template <int M>
-__device__ inline void local_xyz(const RowGeom &g, double dx, double dy, double dz, double &X, double &Y,
+__host__ __device__ constexpr int mono_deg(int a) {
+  return M == 10 ? kExp3[a][0] + kExp3[a][1] + kExp3[a][2] : kExp2[a][0] + kExp2[a][1];
+}
+
+// Unscaled local coordinates of a neighbour: (dx, dy, dz) in 3D, the offset
+// projected on the tangent frame (U, V, 0) on a film.  The batched kernels
+// work in these and move the powers of 1/h_i onto the per-row quantities (the
+// moments when G is assembled, the target solutions before pass 2), where
+// they cost a few operations per row instead of per neighbour.
+template <int M>
+__device__ inline void local_raw(const RowGeom &g, double dx, double dy, double dz, double &X, double &Y,
                                  double &Z) {
   if constexpr (M == 10) {
-    X = dx * g.inv_h; Y = dy * g.inv_h; Z = dz * g.inv_h;
+    X = dx; Y = dy; Z = dz;
   } else {
-    X = (dx * g.t1[0] + dy * g.t1[1] + dz * g.t1[2]) * g.inv_h;
-    Y = (dx * g.t2[0] + dy * g.t2[1] + dz * g.t2[2]) * g.inv_h;
+    X = fma(dz, g.t1[2], fma(dy, g.t1[1], dx * g.t1[0]));
+    Y = fma(dz, g.t2[2], fma(dy, g.t2[1], dx * g.t2[0]));
     Z = 0.0;
   }
 }
 
+// mom += w X^a Y^b Z^c for every a + b + c <= 4.  Every monomial of degree 3
+// or 4 is (w times a monomial of degree 2) times a monomial of degree 1 or 2,
+// so 15 products (6 on a film) feed the 35 (15) accumulations.
 template <int M>
-__device__ inline void moments_add(double mom[nmom<M>()], double w, double X, double Y, double Z) {
-  double wx[5], py[5];
-  wx[0] = w;
-#pragma unroll
-  for (int a = 1; a < 5; ++a) wx[a] = wx[a - 1] * X;
-  py[0] = 1.0;
-#pragma unroll
-  for (int b = 1; b < 5; ++b) py[b] = py[b - 1] * Y;
+__device__ inline void moments_add_raw(double mom[nmom<M>()], double w, double X, double Y, double Z) {
   if constexpr (M == 10) {
-    double pz[5];
-    pz[0] = 1.0;
-#pragma unroll
-    for (int c = 1; c < 5; ++c) pz[c] = pz[c - 1] * Z;
-#pragma unroll
-    for (int a = 0; a <= 4; ++a)
-#pragma unroll
-      for (int b = 0; a + b <= 4; ++b) {
-        const double t = (b == 0) ? wx[a] : wx[a] * py[b];
-#pragma unroll
-        for (int c = 0; a + b + c <= 4; ++c) mom[kMom3.idx[a][b][c]] += (c == 0) ? t : t * pz[c];
-      }
+    constexpr auto I = [](int a, int b, int c) { return kMom3.idx[a][b][c]; };
+    const double wx = w * X, wy = w * Y, wz = w * Z;
+    const double xx = X * X, yy = Y * Y, zz = Z * Z, xy = X * Y, xz = X * Z, yz = Y * Z;
+    const double wxx = wx * X, wyy = wy * Y, wzz = wz * Z, wxy = wx * Y, wxz = wx * Z, wyz = wy * Z;
+    mom[I(0, 0, 0)] += w;
+    mom[I(1, 0, 0)] += wx; mom[I(0, 1, 0)] += wy; mom[I(0, 0, 1)] += wz;
+    mom[I(2, 0, 0)] += wxx; mom[I(0, 2, 0)] += wyy; mom[I(0, 0, 2)] += wzz;
+    mom[I(1, 1, 0)] += wxy; mom[I(1, 0, 1)] += wxz; mom[I(0, 1, 1)] += wyz;
+    mom[I(3, 0, 0)] = fma(wxx, X, mom[I(3, 0, 0)]);
+    mom[I(2, 1, 0)] = fma(wxx, Y, mom[I(2, 1, 0)]);
+    mom[I(2, 0, 1)] = fma(wxx, Z, mom[I(2, 0, 1)]);
+    mom[I(1, 2, 0)] = fma(wyy, X, mom[I(1, 2, 0)]);
+    mom[I(0, 3, 0)] = fma(wyy, Y, mom[I(0, 3, 0)]);
+    mom[I(0, 2, 1)] = fma(wyy, Z, mom[I(0, 2, 1)]);
+    mom[I(1, 0, 2)] = fma(wzz, X, mom[I(1, 0, 2)]);
+    mom[I(0, 1, 2)] = fma(wzz, Y, mom[I(0, 1, 2)]);
+    mom[I(0, 0, 3)] = fma(wzz, Z, mom[I(0, 0, 3)]);
+    mom[I(1, 1, 1)] = fma(wxy, Z, mom[I(1, 1, 1)]);
+    mom[I(4, 0, 0)] = fma(wxx, xx, mom[I(4, 0, 0)]);
+    mom[I(3, 1, 0)] = fma(wxx, xy, mom[I(3, 1, 0)]);
+    mom[I(3, 0, 1)] = fma(wxx, xz, mom[I(3, 0, 1)]);
+    mom[I(2, 2, 0)] = fma(wxx, yy, mom[I(2, 2, 0)]);
+    mom[I(2, 1, 1)] = fma(wxx, yz, mom[I(2, 1, 1)]);
+    mom[I(2, 0, 2)] = fma(wxx, zz, mom[I(2, 0, 2)]);
+    mom[I(1, 3, 0)] = fma(wyy, xy, mom[I(1, 3, 0)]);
+    mom[I(0, 4, 0)] = fma(wyy, yy, mom[I(0, 4, 0)]);
+    mom[I(1, 2, 1)] = fma(wyy, xz, mom[I(1, 2, 1)]);
+    mom[I(0, 3, 1)] = fma(wyy, yz, mom[I(0, 3, 1)]);
+    mom[I(0, 2, 2)] = fma(wyy, zz, mom[I(0, 2, 2)]);
+    mom[I(1, 0, 3)] = fma(wzz, xz, mom[I(1, 0, 3)]);
+    mom[I(0, 1, 3)] = fma(wzz, yz, mom[I(0, 1, 3)]);
+    mom[I(0, 0, 4)] = fma(wzz, zz, mom[I(0, 0, 4)]);
+    mom[I(1, 1, 2)] = fma(wzz, xy, mom[I(1, 1, 2)]);
   } else {
-#pragma unroll
-    for (int a = 0; a <= 4; ++a)
-#pragma unroll
-      for (int b = 0; a + b <= 4; ++b) mom[kMom2.idx[a][b]] += (b == 0) ? wx[a] : wx[a] * py[b];
+    constexpr auto I = [](int a, int b) { return kMom2.idx[a][b]; };
+    const double wu = w * X, wv = w * Y;
+    const double uu = X * X, vv = Y * Y, uv = X * Y;
+    const double wuu = wu * X, wvv = wv * Y, wuv = wu * Y;
+    mom[I(0, 0)] += w;
+    mom[I(1, 0)] += wu; mom[I(0, 1)] += wv;
+    mom[I(2, 0)] += wuu; mom[I(0, 2)] += wvv; mom[I(1, 1)] += wuv;
+    mom[I(3, 0)] = fma(wuu, X, mom[I(3, 0)]);
+    mom[I(2, 1)] = fma(wuu, Y, mom[I(2, 1)]);
+    mom[I(1, 2)] = fma(wvv, X, mom[I(1, 2)]);
+    mom[I(0, 3)] = fma(wvv, Y, mom[I(0, 3)]);
+    mom[I(4, 0)] = fma(wuu, uu, mom[I(4, 0)]);
+    mom[I(3, 1)] = fma(wuu, uv, mom[I(3, 1)]);
+    mom[I(2, 2)] = fma(wuu, vv, mom[I(2, 2)]);
+    mom[I(1, 3)] = fma(wvv, uv, mom[I(1, 3)]);
+    mom[I(0, 4)] = fma(wvv, vv, mom[I(0, 4)]);
   }
 }
 
-// monomials phi(X, Y, Z) of the basis
+// sum_a l[a] phi_a(X, Y, Z) over the quadratic basis, in nested (Horner) form:
+// l0 + X (l1 + l4 X + l7 Y + l8 Z) + Y (l2 + l5 Y + l9 Z) + Z (l3 + l6 Z)
+// (film: l0 + U (l1 + l3 U + l5 V) + V (l2 + l4 V)); 9 (5) fused multiply-adds
 template <int M>
-__device__ inline void basis(double X, double Y, double Z, double phi[M]) {
+__device__ inline double poly_eval(const double *l, double X, double Y, double Z) {
   if constexpr (M == 10) {
-    phi[0] = 1.0; phi[1] = X; phi[2] = Y; phi[3] = Z;
-    phi[4] = X * X; phi[5] = Y * Y; phi[6] = Z * Z;
-    phi[7] = X * Y; phi[8] = X * Z; phi[9] = Y * Z;
+    const double ax = fma(l[8], Z, fma(l[7], Y, fma(l[4], X, l[1])));
+    const double ay = fma(l[9], Z, fma(l[5], Y, l[2]));
+    const double az = fma(l[6], Z, l[3]);
+    return fma(Z, az, fma(Y, ay, fma(X, ax, l[0])));
   } else {
-    phi[0] = 1.0; phi[1] = X; phi[2] = Y;
-    phi[3] = X * X; phi[4] = Y * Y; phi[5] = X * Y;
+    const double au = fma(l[5], Y, fma(l[3], X, l[1]));
+    const double av = fma(l[4], Y, l[2]);
+    return fma(Y, av, fma(X, au, l[0]));
   }
 }
 

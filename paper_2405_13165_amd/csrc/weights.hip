@@ -5,10 +5,10 @@
 // film) and by neighbour-count band; inside a group they are taken in Morton
 // order.  Each particle is handled by a team of T lanes of a wave: the lanes
 // stride over the neighbours and accumulate the weighted moments of the
-// scaled offsets, from which the team assembles G = M^T W M, inverts it by
-// Gauss-Jordan (exact 1-norm condition number from G^{-1}), and a second
-// pass over the neighbours writes c_j = w_j phi_j^T lambda (and, fused,
-// applies the stencils to a field).  Rows of the tiled bands are processed
+// offsets, from which the team assembles G = M^T W M, inverts it by
+// Gauss-Jordan (exact 1-norm condition number of the Gram matrix of the
+// offsets scaled by 1/h_i), and a second pass over the neighbours writes
+// c_j = w_j phi_j^T lambda (and, fused, applies the stencils to a field).  Rows of the tiled bands are processed
 // one neighbour tile per block: the tile's distinct neighbour positions are
 // staged in LDS once and both passes read them there.  Particles whose
 // condition number exceeds kappa_max, or whose pivots are not positive, are
@@ -230,12 +230,27 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Unnormalised support weight of a neighbour at offset d with support h_j.
+// Equal supports (the common case): q^2 = |d|^2 / h_i^2.  Otherwise
+// r_ij = (h_i + h_j) / 2 and q^2 = |d|^2 (2 / (h_i + h_j))^2, with the
+// reciprocal taken from the hardware estimate and two Newton steps (each
+// squares the relative error) instead of a full division.
 template <bool FASTW>
-__device__ inline double nbr_weight_h(const WArgs &a, const RowGeom &g, double hj, double dx, double dy, double dz) {
-  const double d2 = dx * dx + dy * dy + dz * dz;
-  // equal supports (the common case) need no division: r_ij = h_i
-  const double q2 = (hj == g.hi) ? d2 * (g.inv_h * g.inv_h) : d2 / (0.25 * (g.hi + hj) * (g.hi + hj));
-  return support_weight_q2<FASTW>(q2, a.wf);
+__device__ inline double nbr_weight_raw(const WArgs &a, const RowGeom &g, double ih2, double hj, double dx, double dy,
+                                        double dz) {
+  const double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
+  double q2;
+  if (hj == g.hi) {
+    q2 = d2 * ih2;
+  } else {
+    const double sh = g.hi + hj;
+    double r = __builtin_amdgcn_rcp(sh);
+    r = fma(r, fma(-sh, r, 1.0), r);
+    r = fma(r, fma(-sh, r, 1.0), r);
+    const double tr = 2.0 * r;
+    q2 = d2 * (tr * tr);
+  }
+  return support_weight_raw_q2<FASTW>(q2, a.wf);
 }
 
 // Where a row finds the (x, y, z, h) of its neighbours.  idx(e) reads the
@@ -300,13 +315,16 @@ __device__ inline void for_neighbours(const F &fetch, int64_t b, int n, int k0, 
 
 // Moment-based team path.  Per particle, a team of T lanes of one wave:
 //  pass 1  each lane accumulates the weighted moments sum w X^a Y^b Z^c
-//          (a+b+c <= 4) of its neighbours (and caches its first KC weights);
+//          (a+b+c <= 4) of its neighbours' offsets (and caches its first KC
+//          weights); the weights leave out their normalising factor, which
+//          cancels from the stencils;
 //  reduce  butterfly over the team; the moments are staged in LDS;
 //  invert  the team assembles G from the moments (lane l owns rows
 //          l, l+T, ...) and runs an in-place Gauss-Jordan inversion with the
-//          pivot row broadcast through LDS (G is SPD: no pivoting);
-//          ||G||_1 ||G^-1||_1 is the condition number; the target solutions
-//          lambda_s are read off the rows of G^-1 and shared through LDS;
+//          pivot row broadcast through LDS (G is SPD: no pivoting); the
+//          condition number is ||G_s||_1 ||G_s^-1||_1 of G_s, the Gram matrix
+//          of the offsets scaled by 1/h_i; the target solutions lambda_s are
+//          read off the rows of G^-1 and shared through LDS;
 //  pass 2  each lane writes c_j = w_j phi_j . lambda_s for its neighbours.
 // Neighbour loads are software-pipelined: the handle two neighbours ahead
 // and the position one neighbour ahead are in flight during the arithmetic.
@@ -338,18 +356,20 @@ __device__ void weights_row_team(const WArgs &a, int32_t i, int lane, double *sm
   }
   RowGeom g;
   row_geom<M>(a, i, g);
-  // ---- pass 1: moments
+  const double ih = g.inv_h, ih2 = ih * ih;
+  // ---- pass 1: moments of the unscaled local coordinates (the powers of
+  // 1/h_i are applied to G when it is assembled)
   double mom[NM];
 #pragma unroll
   for (int p = 0; p < NM; ++p) mom[p] = 0.0;
   auto acc1 = [&](int k, const double4 &pj, int32_t) {
     const double dx = pj.x - g.xi, dy = pj.y - g.yi, dz = pj.z - g.zi;
-    const double w = nbr_weight_h<FASTW>(a, g, pj.w, dx, dy, dz);
+    const double w = nbr_weight_raw<FASTW>(a, g, ih2, pj.w, dx, dy, dz);
     if constexpr (KC > 0)
       if (k < KC * T) s_w[k] = w;
     double X, Y, Z;
-    local_xyz<M>(g, dx, dy, dz, X, Y, Z);
-    moments_add<M>(mom, w, X, Y, Z);
+    local_raw<M>(g, dx, dy, dz, X, Y, Z);
+    moments_add_raw<M>(mom, w, X, Y, Z);
   };
   if constexpr (F::kQuads && KC == 0) {
     // tiled rows (at most kTileBandRow entries): lane l takes the aligned quads of
@@ -406,8 +426,18 @@ __device__ void weights_row_team(const WArgs &a, int32_t i, int lane, double *sm
       if (c * R8 + l8 < NM) s_mom[c * R8 + l8] = res[c];
     wave_sync();
   }
-  // ---- Gauss-Jordan inversion of G; lane owns rows lane + q T (q < NR)
+  // ---- Gauss-Jordan inversion of G; lane owns rows lane + q T (q < NR).
+  // G is the Gram matrix of the unscaled monomials.  With D = diag(h_i^-deg a),
+  // the matrix of the scaled coordinates d / h_i is D G D: its inverse gives the
+  // same stencils (the powers of h_i cancel against the physical scaling of
+  // the targets: column 1 of G^-1 is the x-derivative stencil's coefficient
+  // vector as it stands), elimination without pivoting on an SPD matrix is
+  // unaffected by the diagonal scaling, and only the condition number is taken
+  // of D G D, whose row sums are d_r sum_c |G_rc| d_c (those of its inverse
+  // sum_c |G^-1_rc| / (d_r d_c)).
   constexpr int NR = (M + T - 1) / T;
+  constexpr int NLIN = M == 10 ? 3 : 2;  // monomials 1..NLIN are linear, the rest quadratic
+  auto deg_rt = [](int r) { return (r == 0) ? 0 : (r <= NLIN ? 1 : 2); };
   double row[NR][M];
   double gsum = 0.0;
 #pragma unroll
@@ -419,9 +449,11 @@ __device__ void weights_row_team(const WArgs &a, int32_t i, int lane, double *sm
     for (int c = 0; c < M; ++c) {
       const int mi = own ? (M == 10 ? kGram3.v[r][c] : kGram2.v[r][c]) : 0;
       row[q][c] = own ? s_mom[mi] : 0.0;
-      sacc += fabs(row[q][c]);
+      const double dc = mono_deg<M>(c) == 0 ? 1.0 : (mono_deg<M>(c) == 1 ? ih : ih2);
+      sacc = fma(fabs(row[q][c]), dc, sacc);
     }
-    gsum = fmax(gsum, sacc);
+    const int dg = deg_rt(r);
+    gsum = fmax(gsum, sacc * (dg == 0 ? 1.0 : (dg == 1 ? ih : ih2)));
   }
   wave_sync();  // the pivot rows overwrite the moments
   bool okp = true;
@@ -457,33 +489,43 @@ __device__ void weights_row_team(const WArgs &a, int32_t i, int lane, double *sm
     wave_sync();
   }
   double isum = 0.0;
+  {
+    const double h = g.hi, h2 = h * h;
 #pragma unroll
-  for (int q = 0; q < NR; ++q) {
-    double sacc = 0.0;
+    for (int q = 0; q < NR; ++q) {
+      double sacc = 0.0;
 #pragma unroll
-    for (int c = 0; c < M; ++c) sacc += fabs(row[q][c]);
-    isum = fmax(isum, (lane + q * T < M) ? sacc : 0.0);
+      for (int c = 0; c < M; ++c) {
+        const double hc = mono_deg<M>(c) == 0 ? 1.0 : (mono_deg<M>(c) == 1 ? h : h2);
+        sacc = fma(fabs(row[q][c]), hc, sacc);
+      }
+      const int dg = deg_rt(lane + q * T);
+      isum = fmax(isum, (lane + q * T < M) ? sacc * (dg == 0 ? 1.0 : (dg == 1 ? h : h2)) : 0.0);
+    }
   }
   const double gnorm = team_max(gsum, T);
   const double inorm = team_max(isum, T);
   // a pivot that is not positive: G is not positive definite (rank deficient
   // or numerically so), reported as an infinite condition number
   const double kappa = okp ? gnorm * inorm : INFINITY;
-  // lambda_s[r] from row r of G^{-1} (= column r)
+  // lambda_s[r] from row r of G^{-1} (= column r): the coefficients of the
+  // unscaled monomials in the stencils of the physical derivatives; on a film
+  // s = 0, 1 are the two tangential derivatives (s = 2 unused), which pass 2
+  // turns into the x, y, z components
 #pragma unroll
   for (int q = 0; q < NR; ++q) {
     const int r = lane + q * T;
     if (r < M) {
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
+        if (M == 6 && s == 2) continue;
         double v = 0.0;
 #pragma unroll
         for (int c = 1; c < M; ++c) {
           const double cf = target_coef<M>(s, c);
           if (cf != 0.0) v += cf * row[q][c];
         }
-        // physical scaling: first derivatives / h, Laplacian / h^2
-        s_lam[s * M + r] = v * (s == 3 ? g.inv_h * g.inv_h : g.inv_h);
+        s_lam[s * M + r] = v;
       }
     }
   }
@@ -510,31 +552,35 @@ __device__ void weights_row_team(const WArgs &a, int32_t i, int lane, double *sm
     const double dx = pj.x - g.xi, dy = pj.y - g.yi, dz = pj.z - g.zi;
     double w;
     if constexpr (KC > 0)
-      w = (k < KC * T) ? s_w[k] : nbr_weight_h<FASTW>(a, g, pj.w, dx, dy, dz);
+      w = (k < KC * T) ? s_w[k] : nbr_weight_raw<FASTW>(a, g, ih2, pj.w, dx, dy, dz);
     else
-      w = nbr_weight_h<FASTW>(a, g, pj.w, dx, dy, dz);
-    double X, Y, Z, phi[M];
-    local_xyz<M>(g, dx, dy, dz, X, Y, Z);
-    basis<M>(X, Y, Z, phi);
-    double c[4] = {0.0, 0.0, 0.0, 0.0};
+      w = nbr_weight_raw<FASTW>(a, g, ih2, pj.w, dx, dy, dz);
+    double X, Y, Z;
+    local_raw<M>(g, dx, dy, dz, X, Y, Z);
+    double c[4];
+    if constexpr (M == 10) {
 #pragma unroll
-    for (int q = 0; q < M; ++q)
+      for (int s = 0; s < 4; ++s) c[s] = w * poly_eval<M>(lam + s * M, X, Y, Z);
+    } else {
+      const double wu = w * poly_eval<M>(lam, X, Y, Z), wv = w * poly_eval<M>(lam + M, X, Y, Z);
 #pragma unroll
-      for (int s = 0; s < 4; ++s) c[s] += phi[q] * lam[s * M + q];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) c[s] *= w;
-    if constexpr (M == 6) {
-      const double cu = c[0], cv = c[1];
-      c[0] = g.t1[0] * cu + g.t2[0] * cv;
-      c[1] = g.t1[1] * cu + g.t2[1] * cv;
-      c[2] = g.t1[2] * cu + g.t2[2] * cv;
+      for (int s = 0; s < 3; ++s) c[s] = fma(g.t2[s], wv, g.t1[s] * wu);
+      c[3] = w * poly_eval<M>(lam + 3 * M, X, Y, Z);
     }
-    if (a.w_out) store_w<OUT, true>(a.w_out, b + k, c[0], c[1], c[2], c[3]);
+    if constexpr (OUT == GF_F32) {
+      // rounded once: the stored stencils are also the ones applied
+      const f32x4 v = {(float)c[0], (float)c[1], (float)c[2], (float)c[3]};
+      if (a.w_out) __builtin_nontemporal_store(v, reinterpret_cast<f32x4 *>(a.w_out) + (b + k));
+#pragma unroll
+      for (int s = 0; s < 4; ++s) c[s] = (double)v[s];
+    } else {
+      if (a.w_out) store_w<OUT, true>(a.w_out, b + k, c[0], c[1], c[2], c[3]);
+    }
     if constexpr (FUSED) {
       // the diagonal entry contributes u_i - u_i = 0
       const double du = fetch.field(h) - ui;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) acc[s] += ((OUT == GF_F32) ? (double)(float)c[s] : c[s]) * du;
+      for (int s = 0; s < 4; ++s) acc[s] = fma(c[s], du, acc[s]);
     }
   });
   if constexpr (FUSED) {
