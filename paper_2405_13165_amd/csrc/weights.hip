@@ -313,6 +313,39 @@ __device__ inline void for_neighbours(const F &fetch, int64_t b, int n, int k0, 
   }
 }
 
+// What a row reads before its neighbours: its extent, position, support,
+// frame and field value, and (tiled rows) the slot quads of pass 1.  The tile
+// kernel loads these before it stages the tile, so that their latency (three
+// dependent reads: schedule, row extent, slots) overlaps the staging.
+template <int T, bool QUADS>
+struct RowPre {
+  int32_t i;
+  int64_t b;
+  int n;
+  RowGeom g;
+  double ui;
+  ushort4 ss[QUADS ? kTileBandRow / (4 * T) + 1 : 1];
+};
+
+template <int M, int T, bool FUSED, bool QUADS>
+__device__ inline void row_pre(const WArgs &a, const uint16_t *slot, int32_t i, int lane, RowPre<T, QUADS> &p) {
+  p.i = i;
+  p.b = a.row_ptr[i];
+  p.n = (int)(a.row_ptr[i + 1] - p.b);
+  row_geom<M>(a, i, p.g);
+  p.ui = FUSED ? a.u[i] : 0.0;
+  if constexpr (QUADS) {
+    // lane l takes the aligned quads of slots q0 + l, q0 + l + T, ...
+    constexpr int kQ1 = kTileBandRow / (4 * T) + 1;
+    const int64_t q0 = (p.b >> 2) + lane, e = p.b + p.n;
+#pragma unroll
+    for (int j = 0; j < kQ1; ++j) {
+      const int64_t k = 4 * (q0 + j * T);
+      if (k < e) p.ss[j] = *reinterpret_cast<const ushort4 *>(slot + k);
+    }
+  }
+}
+
 // Moment-based team path.  Per particle, a team of T lanes of one wave:
 //  pass 1  each lane accumulates the weighted moments sum w X^a Y^b Z^c
 //          (a+b+c <= 4) of its neighbours' offsets (and caches its first KC
@@ -328,8 +361,8 @@ __device__ inline void for_neighbours(const F &fetch, int64_t b, int n, int k0, 
 //  pass 2  each lane writes c_j = w_j phi_j . lambda_s for its neighbours.
 // Neighbour loads are software-pipelined: the handle two neighbours ahead
 // and the position one neighbour ahead are in flight during the arithmetic.
-template <int M, int T, int OUT, bool FUSED, bool FASTW, int KC, class F>
-__device__ void weights_row_team(const WArgs &a, int32_t i, int lane, double *sm, const F &fetch) {
+template <int M, int T, int OUT, bool FUSED, bool FASTW, int KC, class F, bool Q>
+__device__ void weights_row_team(const WArgs &a, const RowPre<T, Q> &pre, int lane, double *sm, const F &fetch) {
   constexpr int NM = nmom<M>();
   constexpr int NL = NM > 4 * M ? NM : 4 * M;
   constexpr int R8 = red_lanes(T);
@@ -339,8 +372,9 @@ __device__ void weights_row_team(const WArgs &a, int32_t i, int lane, double *sm
   double *s_lam = sm;
   double *s_prow = sm;
   double *s_w = sm + (((cmax(NA, M + 1)) + 1) & ~1);
-  const int64_t b = a.row_ptr[i];
-  const int n = (int)(a.row_ptr[i + 1] - b);
+  const int32_t i = pre.i;
+  const int64_t b = pre.b;
+  const int n = pre.n;
   if (n < M) {
     if (a.w_out)
       for (int k = lane; k < n; k += T) store_w<OUT>(a.w_out, b + k, 0.0, 0.0, 0.0, 0.0);
@@ -354,11 +388,9 @@ __device__ void weights_row_team(const WArgs &a, int32_t i, int lane, double *sm
     }
     return;
   }
-  RowGeom g;
-  row_geom<M>(a, i, g);
+  const RowGeom &g = pre.g;
   const double ih = g.inv_h, ih2 = ih * ih;
-  // ---- pass 1: moments of the unscaled local coordinates (the powers of
-  // 1/h_i are applied to G when it is assembled)
+  // ---- pass 1: moments of the unscaled local coordinates
   double mom[NM];
 #pragma unroll
   for (int p = 0; p < NM; ++p) mom[p] = 0.0;
@@ -373,17 +405,21 @@ __device__ void weights_row_team(const WArgs &a, int32_t i, int lane, double *sm
   };
   if constexpr (F::kQuads && KC == 0) {
     // tiled rows (at most kTileBandRow entries): lane l takes the aligned quads of
-    // slots q0 + l, q0 + l + T, ..., all loaded before the first is used; a quad may
-    // reach up to three entries into the neighbouring rows (the slot array is
-    // padded): those are skipped
+    // slots q0 + l, q0 + l + T, ..., all loaded before the first is used (with the
+    // row, by row_pre, where the team is at least 8 wide); a quad may reach up to
+    // three entries into the neighbouring rows (the slot array is padded): those
+    // are skipped
     constexpr int kQ1 = kTileBandRow / (4 * T) + 1;
     const int64_t q0 = (b >> 2) + lane, e = b + n;
-    ushort4 ss[kQ1];
+    ushort4 ssl[Q ? 1 : kQ1];
+    if constexpr (!Q) {
 #pragma unroll
-    for (int j = 0; j < kQ1; ++j) {
-      const int64_t k = 4 * (q0 + j * T);
-      if (k < e) ss[j] = *reinterpret_cast<const ushort4 *>(fetch.slot + k);
+      for (int j = 0; j < kQ1; ++j) {
+        const int64_t k = 4 * (q0 + j * T);
+        if (k < e) ssl[j] = *reinterpret_cast<const ushort4 *>(fetch.slot + k);
+      }
     }
+    const ushort4 *ss = Q ? pre.ss : ssl;
 #pragma unroll
     for (int j = 0; j < kQ1; ++j) {
       const int64_t k = 4 * (q0 + j * T);
@@ -544,8 +580,7 @@ __device__ void weights_row_team(const WArgs &a, int32_t i, int lane, double *sm
 #pragma unroll
   for (int q = 0; q < 4 * M; ++q) lam[q] = s_lam[q];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  double ui = 0.0;
-  if constexpr (FUSED) ui = a.u[i];
+  const double ui = pre.ui;
   // the team's stores of one step cover whole aligned T-entry blocks
   const int k0 = a.w_out ? lane - (int)(b & (T - 1)) : lane;
   for_neighbours<T>(fetch, b, n, k0, [&](int k, const double4 &pj, int32_t h) {
@@ -604,8 +639,9 @@ __global__ void __launch_bounds__(kBlock) k_weights_team(WArgs a) {
   const int lane = (int)(gt % T);
   if (team >= a.nrows) return;
   double *sm = smem + (threadIdx.x / T) * team_lds_doubles<M>(T, kCacheW);
-  const int32_t i = a.sched[team];
-  weights_row_team<M, T, OUT, FUSED, FASTW, kCacheW>(a, i, lane, sm, FetchGlobal{a.pos, a.col, a.u, i});
+  RowPre<T, false> pre;
+  row_pre<M, T, FUSED, false>(a, nullptr, a.sched[team], lane, pre);
+  weights_row_team<M, T, OUT, FUSED, FASTW, kCacheW>(a, pre, lane, sm, FetchGlobal{a.pos, a.col, a.u, pre.i});
 }
 
 // Tiled batched kernel: one block per neighbour tile (kTileRows rows, one
@@ -628,6 +664,12 @@ k_weights_tile(WArgs a, TileArgs ta, const uint16_t *__restrict__ slot) {
   const int cnt = (int)(ta.off[ta.tile0 + tl + 1] - u0);
   const bool staged = cnt <= ta.cap;
   double *s_u = reinterpret_cast<double *>(s_dyn + ta.cap);  // fused field values (cap of them)
+  const int team = threadIdx.x / T, lane = threadIdx.x % T;
+  const int64_t r = tl * kTileRows + team;
+  const bool live = r < a.nrows;
+  // (narrower teams hold more quads per lane: they load them in pass 1)
+  RowPre<T, (T >= 8)> pre;
+  if (live) row_pre<M, T, FUSED, (T >= 8)>(a, slot, a.sched[r], lane, pre);
   if (staged) {
     for (int s = threadIdx.x; s < cnt; s += blockDim.x) {
       const int32_t j = ta.u[u0 + s];
@@ -636,15 +678,12 @@ k_weights_tile(WArgs a, TileArgs ta, const uint16_t *__restrict__ slot) {
     }
   }
   __syncthreads();
-  const int team = threadIdx.x / T, lane = threadIdx.x % T;
-  const int64_t r = tl * kTileRows + team;
-  if (r >= a.nrows) return;
+  if (!live) return;
   double *sm = s_u + (FUSED ? ((ta.cap + 1) & ~1) : 0) + team * team_lds_doubles<M>(T, 0);
-  const int32_t i = a.sched[r];
   if (staged)
-    weights_row_team<M, T, OUT, FUSED, FASTW, 0>(a, i, lane, sm, FetchTile{s_dyn, slot, s_u, 0});
+    weights_row_team<M, T, OUT, FUSED, FASTW, 0>(a, pre, lane, sm, FetchTile{s_dyn, slot, s_u, 0});
   else
-    weights_row_team<M, T, OUT, FUSED, FASTW, 0>(a, i, lane, sm, FetchGlobal{a.pos, a.col, a.u, i});
+    weights_row_team<M, T, OUT, FUSED, FASTW, 0>(a, pre, lane, sm, FetchGlobal{a.pos, a.col, a.u, pre.i});
 }
 
 __global__ void __launch_bounds__(kBlock) k_weights_plain(WArgs a) {
