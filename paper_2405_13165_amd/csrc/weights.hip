@@ -231,16 +231,17 @@ __device__ inline void wave_sync() {
 }
 
 // Unnormalised support weight of a neighbour at offset d with support h_j.
-// Equal supports (the common case): q^2 = |d|^2 / h_i^2.  Otherwise
+// Equal supports (the common case; UNI: known for the whole tile, no test per
+// neighbour): q^2 = |d|^2 / h_i^2.  Otherwise
 // r_ij = (h_i + h_j) / 2 and q^2 = |d|^2 (2 / (h_i + h_j))^2, with the
 // reciprocal taken from the hardware estimate and two Newton steps (each
 // squares the relative error) instead of a full division.
-template <bool FASTW>
+template <bool FASTW, bool UNI>
 __device__ inline double nbr_weight_raw(const WArgs &a, const RowGeom &g, double ih2, double hj, double dx, double dy,
                                         double dz) {
   const double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
   double q2;
-  if (hj == g.hi) {
+  if (UNI || hj == g.hi) {
     q2 = d2 * ih2;
   } else {
     const double sh = g.hi + hj;
@@ -361,7 +362,7 @@ __device__ inline void row_pre(const WArgs &a, const uint16_t *slot, int32_t i, 
 //  pass 2  each lane writes c_j = w_j phi_j . lambda_s for its neighbours.
 // Neighbour loads are software-pipelined: the handle two neighbours ahead
 // and the position one neighbour ahead are in flight during the arithmetic.
-template <int M, int T, int OUT, bool FUSED, bool FASTW, int KC, class F, bool Q>
+template <int M, int T, int OUT, bool FUSED, bool FASTW, int KC, bool UNI, class F, bool Q>
 __device__ void weights_row_team(const WArgs &a, const RowPre<T, Q> &pre, int lane, double *sm, const F &fetch) {
   constexpr int NM = nmom<M>();
   constexpr int NL = NM > 4 * M ? NM : 4 * M;
@@ -396,7 +397,7 @@ __device__ void weights_row_team(const WArgs &a, const RowPre<T, Q> &pre, int la
   for (int p = 0; p < NM; ++p) mom[p] = 0.0;
   auto acc1 = [&](int k, const double4 &pj, int32_t) {
     const double dx = pj.x - g.xi, dy = pj.y - g.yi, dz = pj.z - g.zi;
-    const double w = nbr_weight_raw<FASTW>(a, g, ih2, pj.w, dx, dy, dz);
+    const double w = nbr_weight_raw<FASTW, UNI>(a, g, ih2, pj.w, dx, dy, dz);
     if constexpr (KC > 0)
       if (k < KC * T) s_w[k] = w;
     double X, Y, Z;
@@ -498,7 +499,10 @@ __device__ void weights_row_team(const WArgs &a, const RowPre<T, Q> &pre, int la
     const int kq = k / T;
     if (lane == k % T) {
       const double piv = row[kq][k];
-      const double ip = 1.0 / piv;
+      // 1 / piv from the hardware estimate and two Newton steps
+      double ip = __builtin_amdgcn_rcp(piv);
+      ip = fma(ip, fma(-piv, ip, 1.0), ip);
+      ip = fma(ip, fma(-piv, ip, 1.0), ip);
       row[kq][k] = 1.0;
 #pragma unroll
       for (int c = 0; c < M; ++c) row[kq][c] *= ip;
@@ -587,9 +591,9 @@ __device__ void weights_row_team(const WArgs &a, const RowPre<T, Q> &pre, int la
     const double dx = pj.x - g.xi, dy = pj.y - g.yi, dz = pj.z - g.zi;
     double w;
     if constexpr (KC > 0)
-      w = (k < KC * T) ? s_w[k] : nbr_weight_raw<FASTW>(a, g, ih2, pj.w, dx, dy, dz);
+      w = (k < KC * T) ? s_w[k] : nbr_weight_raw<FASTW, UNI>(a, g, ih2, pj.w, dx, dy, dz);
     else
-      w = nbr_weight_raw<FASTW>(a, g, ih2, pj.w, dx, dy, dz);
+      w = nbr_weight_raw<FASTW, UNI>(a, g, ih2, pj.w, dx, dy, dz);
     double X, Y, Z;
     local_raw<M>(g, dx, dy, dz, X, Y, Z);
     double c[4];
@@ -641,7 +645,7 @@ __global__ void __launch_bounds__(kBlock) k_weights_team(WArgs a) {
   double *sm = smem + (threadIdx.x / T) * team_lds_doubles<M>(T, kCacheW);
   RowPre<T, false> pre;
   row_pre<M, T, FUSED, false>(a, nullptr, a.sched[team], lane, pre);
-  weights_row_team<M, T, OUT, FUSED, FASTW, kCacheW>(a, pre, lane, sm, FetchGlobal{a.pos, a.col, a.u, pre.i});
+  weights_row_team<M, T, OUT, FUSED, FASTW, kCacheW, false>(a, pre, lane, sm, FetchGlobal{a.pos, a.col, a.u, pre.i});
 }
 
 // Tiled batched kernel: one block per neighbour tile (kTileRows rows, one
@@ -670,20 +674,29 @@ k_weights_tile(WArgs a, TileArgs ta, const uint16_t *__restrict__ slot) {
   // (narrower teams hold more quads per lane: they load them in pass 1)
   RowPre<T, (T >= 8)> pre;
   if (live) row_pre<M, T, FUSED, (T >= 8)>(a, slot, a.sched[r], lane, pre);
+  // uni: every staged support equals the first (then also each row's own, as
+  // a row is its own neighbour), so no row needs the per-neighbour test
+  int same = 1;
   if (staged) {
+    const double h0 = a.h[ta.u[u0]];
     for (int s = threadIdx.x; s < cnt; s += blockDim.x) {
       const int32_t j = ta.u[u0 + s];
-      s_dyn[s] = make_double4(a.x[j], a.y[j], a.z[j], a.h[j]);
+      const double hj = a.h[j];
+      s_dyn[s] = make_double4(a.x[j], a.y[j], a.z[j], hj);
+      same &= hj == h0;
       if constexpr (FUSED) s_u[s] = a.u[j];
     }
   }
-  __syncthreads();
+  const bool uni = __syncthreads_and(same) != 0;
   if (!live) return;
   double *sm = s_u + (FUSED ? ((ta.cap + 1) & ~1) : 0) + team * team_lds_doubles<M>(T, 0);
   if (staged)
-    weights_row_team<M, T, OUT, FUSED, FASTW, 0>(a, pre, lane, sm, FetchTile{s_dyn, slot, s_u, 0});
+    if (uni)
+      weights_row_team<M, T, OUT, FUSED, FASTW, 0, true>(a, pre, lane, sm, FetchTile{s_dyn, slot, s_u, 0});
+    else
+      weights_row_team<M, T, OUT, FUSED, FASTW, 0, false>(a, pre, lane, sm, FetchTile{s_dyn, slot, s_u, 0});
   else
-    weights_row_team<M, T, OUT, FUSED, FASTW, 0>(a, pre, lane, sm, FetchGlobal{a.pos, a.col, a.u, pre.i});
+    weights_row_team<M, T, OUT, FUSED, FASTW, 0, false>(a, pre, lane, sm, FetchGlobal{a.pos, a.col, a.u, pre.i});
 }
 
 __global__ void __launch_bounds__(kBlock) k_weights_plain(WArgs a) {
