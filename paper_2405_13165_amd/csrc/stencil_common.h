@@ -91,16 +91,17 @@ __device__ inline double support_weight_q2(double q2, const WeightFn &wf) {
 // e^{-a q^2} - e^{-a}: the support weight without its normalising factor
 // 1 / (1 - e^{-a}).  A common factor of all weights of a row cancels from the
 // stencils (G scales by it, the target solutions by its inverse), so the
-// batched kernels leave it out.  Same evaluation as above.
+// batched kernels leave it out.  Given q^2 = d2 s as d2 and cs = s (-a log2 e),
+// t = d2 cs is the base-2 exponent; FASTW evaluates it as above.
 template <bool FASTW>
-__device__ inline double support_weight_raw_q2(double q2, const WeightFn &wf) {
+__device__ inline double support_weight_raw(double d2, double cs, const WeightFn &wf) {
   if constexpr (FASTW) {
-    const double t = q2 * wf.nl2a;
+    const double t = d2 * cs;
     const double k = rint(t);
-    const float e = __builtin_amdgcn_exp2f((float)fma(q2, wf.nl2a, -k));
+    const float e = __builtin_amdgcn_exp2f((float)fma(d2, cs, -k));
     return ldexp((double)e, (int)k) - wf.ea;
   } else {
-    return exp(-wf.alpha * q2) - wf.ea;
+    return exp2(d2 * cs) - wf.ea;
   }
 }
 // the same with q^2 = d2 / r^2

@@ -237,21 +237,22 @@ __device__ inline void wave_sync() {
 // reciprocal taken from the hardware estimate and two Newton steps (each
 // squares the relative error) instead of a full division.
 template <bool FASTW, bool UNI>
-__device__ inline double nbr_weight_raw(const WArgs &a, const RowGeom &g, double ih2, double hj, double dx, double dy,
-                                        double dz) {
+__device__ inline double nbr_weight_raw(const WArgs &a, const RowGeom &g, double cs_row, double hj, double dx,
+                                        double dy, double dz) {
+  // cs: 1 / r_ij^2 times -a log2(e); cs_row = that of r_ij = h_i
   const double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
-  double q2;
+  double cs;
   if (UNI || hj == g.hi) {
-    q2 = d2 * ih2;
+    cs = cs_row;
   } else {
     const double sh = g.hi + hj;
     double r = __builtin_amdgcn_rcp(sh);
     r = fma(r, fma(-sh, r, 1.0), r);
     r = fma(r, fma(-sh, r, 1.0), r);
     const double tr = 2.0 * r;
-    q2 = d2 * (tr * tr);
+    cs = (tr * tr) * a.wf.nl2a;
   }
-  return support_weight_raw_q2<FASTW>(q2, a.wf);
+  return support_weight_raw<FASTW>(d2, cs, a.wf);
 }
 
 // Where a row finds the (x, y, z, h) of its neighbours.  idx(e) reads the
@@ -390,14 +391,14 @@ __device__ void weights_row_team(const WArgs &a, const RowPre<T, Q> &pre, int la
     return;
   }
   const RowGeom &g = pre.g;
-  const double ih = g.inv_h, ih2 = ih * ih;
+  const double ih = g.inv_h, ih2 = ih * ih, cs_row = ih2 * a.wf.nl2a;
   // ---- pass 1: moments of the unscaled local coordinates
   double mom[NM];
 #pragma unroll
   for (int p = 0; p < NM; ++p) mom[p] = 0.0;
   auto acc1 = [&](int k, const double4 &pj, int32_t) {
     const double dx = pj.x - g.xi, dy = pj.y - g.yi, dz = pj.z - g.zi;
-    const double w = nbr_weight_raw<FASTW, UNI>(a, g, ih2, pj.w, dx, dy, dz);
+    const double w = nbr_weight_raw<FASTW, UNI>(a, g, cs_row, pj.w, dx, dy, dz);
     if constexpr (KC > 0)
       if (k < KC * T) s_w[k] = w;
     double X, Y, Z;
@@ -591,9 +592,9 @@ __device__ void weights_row_team(const WArgs &a, const RowPre<T, Q> &pre, int la
     const double dx = pj.x - g.xi, dy = pj.y - g.yi, dz = pj.z - g.zi;
     double w;
     if constexpr (KC > 0)
-      w = (k < KC * T) ? s_w[k] : nbr_weight_raw<FASTW, UNI>(a, g, ih2, pj.w, dx, dy, dz);
+      w = (k < KC * T) ? s_w[k] : nbr_weight_raw<FASTW, UNI>(a, g, cs_row, pj.w, dx, dy, dz);
     else
-      w = nbr_weight_raw<FASTW, UNI>(a, g, ih2, pj.w, dx, dy, dz);
+      w = nbr_weight_raw<FASTW, UNI>(a, g, cs_row, pj.w, dx, dy, dz);
     double X, Y, Z;
     local_raw<M>(g, dx, dy, dz, X, Y, Z);
     double c[4];
@@ -916,14 +917,14 @@ const char *unit_kernel_name(const LaunchUnit &u, bool fused) {
 }
 
 template <int M, int OUT, bool FUSED, bool FASTW>
-gf_status launch_team(gf_ctx *ctx, const WArgs &a, int T, const char *name) {
-  ProfScope prof(ctx, name);
+gf_status launch_team(gf_ctx *ctx, hipStream_t st, const WArgs &a, int T, const char *name) {
+  ProfScope prof(ctx, name, st);
   const int64_t threads = a.nrows * (int64_t)T;
   const dim3 grid(grid_for(threads, kBlock)), block(kBlock);
   switch (T) {
-    case 4: hipLaunchKernelGGL((k_weights_team<M, 4, OUT, FUSED, FASTW>), grid, block, 0, ctx->stream, a); break;
-    case 8: hipLaunchKernelGGL((k_weights_team<M, 8, OUT, FUSED, FASTW>), grid, block, 0, ctx->stream, a); break;
-    case 16: hipLaunchKernelGGL((k_weights_team<M, 16, OUT, FUSED, FASTW>), grid, block, 0, ctx->stream, a); break;
+    case 4: hipLaunchKernelGGL((k_weights_team<M, 4, OUT, FUSED, FASTW>), grid, block, 0, st, a); break;
+    case 8: hipLaunchKernelGGL((k_weights_team<M, 8, OUT, FUSED, FASTW>), grid, block, 0, st, a); break;
+    case 16: hipLaunchKernelGGL((k_weights_team<M, 16, OUT, FUSED, FASTW>), grid, block, 0, st, a); break;
     default: return set_error(ctx, GF_EINVAL, "unsupported team size %d", T);
   }
   GF_LAUNCH_CHECK(ctx);
@@ -934,8 +935,9 @@ gf_status launch_team(gf_ctx *ctx, const WArgs &a, int T, const char *name) {
 constexpr int kTileCap = 1024;
 
 template <int M, int OUT, bool FUSED, bool FASTW>
-gf_status launch_tile(gf_ctx *ctx, const WArgs &a, const gf_nbr *nbr, const LaunchUnit &u, int T, const char *name) {
-  ProfScope prof(ctx, name);
+gf_status launch_tile(gf_ctx *ctx, hipStream_t st, const WArgs &a, const gf_nbr *nbr, const LaunchUnit &u, int T,
+                      const char *name) {
+  ProfScope prof(ctx, name, st);
   TileArgs ta;
   ta.off = nbr->tile_off;
   ta.u = nbr->tile_u;
@@ -945,9 +947,9 @@ gf_status launch_tile(gf_ctx *ctx, const WArgs &a, const gf_nbr *nbr, const Laun
                      sizeof(double) * kTileRows * team_lds_doubles<M>(T, 0);
   const dim3 grid(grid_for(u.ntiles, 1)), block(kTileRows * T);
   switch (T) {
-    case 4: hipLaunchKernelGGL((k_weights_tile<M, 4, OUT, FUSED, FASTW>), grid, block, lds, ctx->stream, a, ta, nbr->slot); break;
-    case 8: hipLaunchKernelGGL((k_weights_tile<M, 8, OUT, FUSED, FASTW>), grid, block, lds, ctx->stream, a, ta, nbr->slot); break;
-    case 16: hipLaunchKernelGGL((k_weights_tile<M, 16, OUT, FUSED, FASTW>), grid, block, lds, ctx->stream, a, ta, nbr->slot); break;
+    case 4: hipLaunchKernelGGL((k_weights_tile<M, 4, OUT, FUSED, FASTW>), grid, block, lds, st, a, ta, nbr->slot); break;
+    case 8: hipLaunchKernelGGL((k_weights_tile<M, 8, OUT, FUSED, FASTW>), grid, block, lds, st, a, ta, nbr->slot); break;
+    case 16: hipLaunchKernelGGL((k_weights_tile<M, 16, OUT, FUSED, FASTW>), grid, block, lds, st, a, ta, nbr->slot); break;
     default: return set_error(ctx, GF_EINVAL, "unsupported team size %d", T);
   }
   GF_LAUNCH_CHECK(ctx);
@@ -969,11 +971,11 @@ gf_status launch_batched(gf_ctx *ctx, const gf_nbr *nbr, WArgs a, int only_unit 
     const char *name = unit_kernel_name(u, FUSED);
     gf_status st;
     if (u.tiled)
-      st = (u.model == 0) ? launch_tile<10, OUT, FUSED, FASTW>(ctx, a, nbr, u, T, name)
-                          : launch_tile<6, OUT, FUSED, FASTW>(ctx, a, nbr, u, T, name);
+      st = (u.model == 0) ? launch_tile<10, OUT, FUSED, FASTW>(ctx, ctx->stream, a, nbr, u, T, name)
+                          : launch_tile<6, OUT, FUSED, FASTW>(ctx, ctx->stream, a, nbr, u, T, name);
     else
-      st = (u.model == 0) ? launch_team<10, OUT, FUSED, FASTW>(ctx, a, T, name)
-                          : launch_team<6, OUT, FUSED, FASTW>(ctx, a, T, name);
+      st = (u.model == 0) ? launch_team<10, OUT, FUSED, FASTW>(ctx, ctx->stream, a, T, name)
+                          : launch_team<6, OUT, FUSED, FASTW>(ctx, ctx->stream, a, T, name);
     if (st) return st;
   }
   return GF_OK;
