@@ -45,53 +45,99 @@ struct AArgs {
 // outside SEL have no adjoint (ybar = 0) and their terms are not formed.
 // The general kernel carries all four; the common single-operator cases
 // (Laplacian, gradient) get their own, with far fewer registers.
+//
+// A team of kT lanes per particle, in the form of the batched stencil kernel:
+// G from the weighted moments of the offsets (team sum through LDS), its
+// inverse by team Gauss-Jordan (lane owns rows lane + q kT), lambda_s and
+// mu_s shared through the team's LDS area.  Everything is written in the
+// unscaled offsets d (monomials of d, physical targets), where lambda_s are
+// the coefficients of the physical stencils as they stand; the weights leave
+// out their normalising factor 1 / (1 - e^{-a}): a common factor of the
+// weights cancels from the stencils and from every term below (G and v_s
+// scale with it, lambda_s and mu_s with its inverse, dw/dd with it).
+template <int M>
+constexpr int adj_lds_doubles() {  // per team: reduction / moments / pivot row, then lambda (4M), mu (4M)
+  return ((cmax(cmax(nmom<M>(), red_lanes(kT) * red_lanes(kT)), cmax(M + 1, 8 * M)) + 1) & ~1);
+}
+
 template <int M, unsigned SEL>
-__device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane) {
+__device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane, double *sm) {
+  constexpr int T = kT;
+  constexpr int NM = nmom<M>();
+  constexpr int NR = (M + T - 1) / T;
   const int64_t b = a.row_ptr[i];
   const int n = (int)(a.row_ptr[i + 1] - b);
   RowGeom g;
-  g.xi = a.x[i]; g.yi = a.y[i]; g.zi = a.z[i]; g.hi = a.h[i]; g.inv_h = 1.0 / g.hi;
+  g.xi = a.x[i]; g.yi = a.y[i]; g.zi = a.z[i]; g.hi = a.h[i]; g.inv_h = 1.0;  // unscaled monomials
   if constexpr (M == 6) tangent_frame(a.nx[i], a.ny[i], a.nz[i], g.t1, g.t2);
-  // n < M (status 3) and rank-deficient rows (status 2) have constant zero stencils
-  bool ok = n >= M && !(a.status && a.status[i] >= 2);
-  constexpr int NP = npack(M);
-  double G[NP];
-#pragma unroll
-  for (int p = 0; p < NP; ++p) G[p] = 0.0;
-  if (ok) {
-    for (int k = lane; k < n; k += kT) {
-      const int32_t j = a.col[b + k];
-      const double dx = a.x[j] - g.xi, dy = a.y[j] - g.yi, dz = a.z[j] - g.zi;
-      const double w = support_weight<false>(dx * dx + dy * dy + dz * dz, 0.5 * (g.hi + a.h[j]), a.wf);
-      double phi[M];
-      monomials<M>(g, dx, dy, dz, phi);
-      gram_add<M>(G, phi, w);
-    }
-#pragma unroll
-    for (int p = 0; p < NP; ++p) G[p] = team_sum(G[p], kT);
-  }
-  double dinv[M];
-  if (ok) ok = ldlt<M>(G, dinv);
-  if (!ok) {
-    for (int k = lane; k < n; k += kT) {
+  auto zero_out = [&]() {
+    for (int k = lane; k < n; k += T) {
       double *d = a.dbar + 3 * (ob + k);
       d[0] = 0.0; d[1] = 0.0; d[2] = 0.0;
     }
+  };
+  // n < M (status 3) and rank-deficient rows (status 2) have constant zero stencils
+  if (n < M || (a.status && a.status[i] >= 2)) {
+    zero_out();
     return;
   }
-  // lambda_s = G^{-1} d_s (dimensionless targets)
-  double lam[4][M];
+  // unnormalised weight e^{-a q^2} - e^{-a}, q^2 = |d|^2 / r^2, r = (h_i + h_j) / 2;
+  // e = e^{-a q^2} and ir2 = 1 / r^2 give dw/dd = -2 a e ir2 d
+  auto weight = [&](double hj, double d2, double &e, double &ir2) {
+    const double r = 0.5 * (g.hi + hj);
+    ir2 = 1.0 / (r * r);
+    e = exp(-a.wf.alpha * (d2 * ir2));
+    return e - a.wf.ea;
+  };
+  // ---- pass 1: moments
+  double mom[NM];
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    if (!((SEL >> s) & 1u)) continue;
+  for (int p = 0; p < NM; ++p) mom[p] = 0.0;
+  for (int k = lane; k < n; k += T) {
+    const int32_t j = a.col[b + k];
+    const double dx = a.x[j] - g.xi, dy = a.y[j] - g.yi, dz = a.z[j] - g.zi;
+    double e, ir2;
+    const double w = weight(a.h[j], fma(dz, dz, fma(dy, dy, dx * dx)), e, ir2);
+    double X, Y, Z;
+    local_raw<M>(g, dx, dy, dz, X, Y, Z);
+    moments_add_raw<M>(mom, w, X, Y, Z);
+  }
+  team_moment_sum<M, T>(mom, lane, sm);
+  // ---- G^{-1}
+  double row[NR][M];
 #pragma unroll
-    for (int r = 0; r < M; ++r) lam[s][r] = 0.0;
-    if constexpr (M == 10) {
-      if (s < 3) lam[s][s + 1] = 1.0; else { lam[s][4] = 2.0; lam[s][5] = 2.0; lam[s][6] = 2.0; }
-    } else {
-      if (s < 2) lam[s][s + 1] = 1.0; else if (s == 3) { lam[s][3] = 2.0; lam[s][4] = 2.0; }
+  for (int q = 0; q < NR; ++q) {
+    const int r = lane + q * T;
+    const bool own = r < M;
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      const int mi = own ? (M == 10 ? kGram3.v[r][c] : kGram2.v[r][c]) : 0;
+      row[q][c] = own ? sm[mi] : 0.0;
     }
-    ldlt_solve<M>(G, dinv, lam[s]);
+  }
+  wave_sync();  // the pivot rows overwrite the moments
+  if (!team_gauss_jordan<M, T>(row, lane, sm)) {  // G not positive definite (same on every lane)
+    zero_out();
+    return;
+  }
+  // lambda_s = G^{-1} t_s (the target of stencil s), row r on the lane that owns it
+  double *s_lam = sm, *s_mu = sm + 4 * M;
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    const int r = lane + q * T;
+    if (r < M) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        if (!((SEL >> s) & 1u)) continue;
+        double v = 0.0;
+#pragma unroll
+        for (int c = 1; c < M; ++c) {
+          const double cf = target_coef<M>(s, c);
+          if (cf != 0.0) v += cf * row[q][c];
+        }
+        s_lam[s * M + r] = v;
+      }
+    }
   }
   // ybar of this row, per stencil s (zero if not selected)
   double yb[4] = {0.0, 0.0, 0.0, 0.0};
@@ -101,56 +147,84 @@ __device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane) {
       if (a.mask & (1u << s)) yb[s] = a.ybar[(int64_t)(q++) * a.n + i];
   }
   const double ui = a.u[i];
-  const double ih = g.inv_h, ih2 = g.inv_h * g.inv_h;
-  // chatbar_j for the dimensionless stencils of this particle
+  // chatbar_js = dL / dc_js for the stencils the kernel forms (on a film the
+  // tangential ones, s = 0, 1, of which the stored x, y, z stencils are the
+  // combinations t1 c_0 + t2 c_1)
   auto chatbar = [&](int32_t j, double cb[4]) {
     const double du = (j != i) ? (a.u[j] - ui) : 0.0;
     if constexpr (M == 10) {
-      cb[0] = yb[0] * du * ih; cb[1] = yb[1] * du * ih; cb[2] = yb[2] * du * ih;
+      cb[0] = yb[0] * du; cb[1] = yb[1] * du; cb[2] = yb[2] * du;
     } else {
-      const double gx = yb[0] * du * ih, gy = yb[1] * du * ih, gz = yb[2] * du * ih;
+      const double gx = yb[0] * du, gy = yb[1] * du, gz = yb[2] * du;
       cb[0] = g.t1[0] * gx + g.t1[1] * gy + g.t1[2] * gz;
       cb[1] = g.t2[0] * gx + g.t2[1] * gy + g.t2[2] * gz;
       cb[2] = 0.0;
     }
-    cb[3] = yb[3] * du * ih2;
+    cb[3] = yb[3] * du;
   };
-  // lambdabar_s = sum_j chatbar_js w_j phi_j
-  double mu[4][M];
+  // ---- pass 2: v_s = sum_j chatbar_js w_j phi_j
+  double v[4][M];
 #pragma unroll
   for (int s = 0; s < 4; ++s)
 #pragma unroll
-    for (int r = 0; r < M; ++r) mu[s][r] = 0.0;  // (entries outside SEL are never read)
-  for (int k = lane; k < n; k += kT) {
+    for (int r = 0; r < M; ++r) v[s][r] = 0.0;  // (entries outside SEL are never read)
+  for (int k = lane; k < n; k += T) {
     const int32_t j = a.col[b + k];
     const double dx = a.x[j] - g.xi, dy = a.y[j] - g.yi, dz = a.z[j] - g.zi;
-    const double w = support_weight<false>(dx * dx + dy * dy + dz * dz, 0.5 * (g.hi + a.h[j]), a.wf);
+    double e, ir2;
+    const double w = weight(a.h[j], fma(dz, dz, fma(dy, dy, dx * dx)), e, ir2);
     double phi[M], cb[4];
     monomials<M>(g, dx, dy, dz, phi);
     chatbar(j, cb);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       if (!((SEL >> s) & 1u)) continue;
+      const double cw = cb[s] * w;
 #pragma unroll
-      for (int r = 0; r < M; ++r) mu[s][r] += cb[s] * w * phi[r];
+      for (int r = 0; r < M; ++r) v[s][r] = fma(cw, phi[r], v[s][r]);
     }
   }
+  // ---- mu_s = G^{-1} v_s, row r on the lane that owns it
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     if (!((SEL >> s) & 1u)) continue;
 #pragma unroll
-    for (int r = 0; r < M; ++r) mu[s][r] = team_sum(mu[s][r], kT);
-    ldlt_solve<M>(G, dinv, mu[s]);
+    for (int r = 0; r < M; ++r) v[s][r] = team_sum(v[s][r], T);
   }
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    const int r = lane + q * T;
+    if (r < M) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        if (!((SEL >> s) & 1u)) continue;
+        double m = 0.0;
+#pragma unroll
+        for (int c = 0; c < M; ++c) m = fma(row[q][c], v[s][c], m);
+        s_mu[s * M + r] = m;
+      }
+    }
+  }
+  wave_sync();
+  double lam[4][M], mu[4][M];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    if (!((SEL >> s) & 1u)) continue;
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      lam[s][r] = s_lam[s * M + r];
+      mu[s][r] = s_mu[s * M + r];
+    }
+  }
+  // ---- pass 3: dbar_j per entry
   double own[3] = {0.0, 0.0, 0.0};  // this lane's share of sum_j dbar(i, j)
-  for (int k = lane; k < n; k += kT) {
+  for (int k = lane; k < n; k += T) {
     const int32_t j = a.col[b + k];
     double *out = a.dbar + 3 * (ob + k);
     if (j == i) { out[0] = 0.0; out[1] = 0.0; out[2] = 0.0; continue; }
     const double dx = a.x[j] - g.xi, dy = a.y[j] - g.yi, dz = a.z[j] - g.zi;
-    const double d2 = dx * dx + dy * dy + dz * dz;
-    const double r = 0.5 * (g.hi + a.h[j]);
-    const double w = support_weight<false>(d2, r, a.wf);
+    double e, ir2;
+    const double w = weight(a.h[j], fma(dz, dz, fma(dy, dy, dx * dx)), e, ir2);
     double phi[M], cb[4];
     monomials<M>(g, dx, dy, dz, phi);
     chatbar(j, cb);
@@ -162,14 +236,14 @@ __device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane) {
       if (!((SEL >> s) & 1u)) continue;
       double pl = 0.0, mp = 0.0;
 #pragma unroll
-      for (int q = 0; q < M; ++q) { pl += phi[q] * lam[s][q]; mp += mu[s][q] * phi[q]; }
-      wb += cb[s] * pl - mp * pl;
+      for (int q = 0; q < M; ++q) { pl = fma(phi[q], lam[s][q], pl); mp = fma(mu[s][q], phi[q], mp); }
+      wb += (cb[s] - mp) * pl;
 #pragma unroll
-      for (int q = 0; q < M; ++q) pb[q] += cb[s] * w * lam[s][q] - w * (mu[s][q] * pl + lam[s][q] * mp);
+      for (int q = 0; q < M; ++q) pb[q] += w * ((cb[s] - mp) * lam[s][q] - pl * mu[s][q]);
     }
     double dd[3];
     monomials_grad_dot<M>(g, dx, dy, dz, pb, dd);
-    const double f = wb * support_weight_dfac(d2, r, a.wf);
+    const double f = wb * (-2.0 * a.wf.alpha * e * ir2);
     out[0] = dd[0] + f * dx;
     out[1] = dd[1] + f * dy;
     out[2] = dd[2] + f * dz;
@@ -179,7 +253,7 @@ __device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane) {
   }
   // x_i loses every dbar(i, j), whether or not (j, i) is listed
 #pragma unroll
-  for (int c = 0; c < 3; ++c) own[c] = team_sum(own[c], kT);
+  for (int c = 0; c < 3; ++c) own[c] = team_sum(own[c], T);
   if (lane == 0) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) a.xbar[3 * (int64_t)i + c] -= own[c];
@@ -188,11 +262,13 @@ __device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane) {
 
 template <int M, unsigned SEL>
 __global__ void __launch_bounds__(kBlock) k_adjoint_x(AArgs a) {
+  __shared__ double smem[(kBlock / kT) * adj_lds_doubles<M>()];
   const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t team = gt / kT;
   const int lane = (int)(gt % kT);
   if (team >= a.nrows) return;
-  adjoint_row<M, SEL>(a, a.sched[team], a.gbase[team], lane);
+  adjoint_row<M, SEL>(a, a.sched[team], a.gbase[team], lane,
+                      smem + (threadIdx.x / kT) * adj_lds_doubles<M>());
 }
 
 template <int M>

@@ -331,6 +331,113 @@ __device__ inline double poly_eval(const double *l, double X, double Y, double Z
   }
 }
 
+// ---------------------------------------------------------------- team solve
+// The batched stencil kernels give each particle a team of T lanes of one
+// wave.  Entry (r, c) of the Gram matrix is the moment kGram[r][c].
+template <int M>
+struct GramTable {
+  unsigned char v[M][M];
+  constexpr GramTable() : v{} {
+    for (int r = 0; r < M; ++r)
+      for (int c = 0; c < M; ++c) v[r][c] = (unsigned char)gram_moment<M>(r, c);
+  }
+};
+static __constant__ GramTable<10> kGram3 = GramTable<10>();
+static __constant__ GramTable<6> kGram2 = GramTable<6>();
+
+// lanes of a team that take part in the moment transpose-reduction (the
+// team's partial sums are first folded down to this many lanes)
+__host__ __device__ constexpr int red_lanes(int T) { return T < 4 ? T : 4; }
+
+__host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+// orders the LDS traffic of the lanes of one wave around a hand-off
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Team sum of the moments, left in s[0 .. nmom): butterflies down to R8
+// lanes, then a transpose through LDS in chunks of R8 moments (lane m of the
+// chunk adds the R8 partials of moment c R8 + m in lane order).  s holds at
+// least max(nmom, R8 R8) doubles of the team's LDS.
+template <int M, int T>
+__device__ inline void team_moment_sum(double (&mom)[nmom<M>()], int lane, double *s) {
+  constexpr int NM = nmom<M>();
+  constexpr int R8 = red_lanes(T);
+#pragma unroll
+  for (int o = T / 2; o >= R8; o >>= 1)
+#pragma unroll
+    for (int p = 0; p < NM; ++p) mom[p] += __shfl_xor(mom[p], o, T);
+  constexpr int NC = (NM + R8 - 1) / R8;
+  const int l8 = lane % R8;
+  double res[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+#pragma unroll
+    for (int m = 0; m < R8; ++m)
+      if (c * R8 + m < NM) s[m * R8 + l8] = mom[c * R8 + m];
+    wave_sync();
+    double t = s[l8 * R8];
+#pragma unroll
+    for (int q = 1; q < R8; ++q) t += s[l8 * R8 + q];
+    res[c] = t;
+    wave_sync();
+  }
+  // the buffer is free again: the moments take its place
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+    if (c * R8 + l8 < NM) s[c * R8 + l8] = res[c];
+  wave_sync();
+}
+
+// In-place Gauss-Jordan inversion of the team's SPD matrix (no pivoting):
+// lane owns rows lane + q T (q < NR), the pivot row goes to the other lanes
+// through s_prow (M + 1 doubles of the team's LDS).  Afterwards row[q][:] is
+// row lane + q T of the inverse.  Returns false if a pivot is not positive
+// (or not finite): the matrix is not positive definite.
+template <int M, int T>
+__device__ inline bool team_gauss_jordan(double (&row)[(M + T - 1) / T][M], int lane, double *s_prow) {
+  constexpr int NR = (M + T - 1) / T;
+  bool okp = true;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const int kq = k / T;
+    if (lane == k % T) {
+      const double piv = row[kq][k];
+      // 1 / piv from the hardware estimate and two Newton steps
+      double ip = __builtin_amdgcn_rcp(piv);
+      ip = fma(ip, fma(-piv, ip, 1.0), ip);
+      ip = fma(ip, fma(-piv, ip, 1.0), ip);
+      row[kq][k] = 1.0;
+#pragma unroll
+      for (int c = 0; c < M; ++c) row[kq][c] *= ip;
+#pragma unroll
+      for (int c = 0; c < M; ++c) s_prow[c] = row[kq][c];
+      s_prow[M] = piv;
+    }
+    wave_sync();
+    double pr[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) pr[c] = s_prow[c];
+    const double piv = s_prow[M];
+    okp = okp && (piv > 0.0) && isfinite(piv);
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const int r = lane + q * T;
+      if (r < M && r != k) {
+        const double f = row[q][k];
+        row[q][k] = 0.0;
+#pragma unroll
+        for (int c = 0; c < M; ++c) row[q][c] -= f * pr[c];
+      }
+    }
+    wave_sync();
+  }
+  return okp;
+}
+
 // Consecutive workgroups are dispatched round-robin over the 8 XCDs of the
 // chip, each with its own L2.  Remap so that XCD k processes the k-th
 // contiguous slice of the (Morton-ordered) work: neighbouring particles then

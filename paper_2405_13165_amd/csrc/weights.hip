@@ -197,23 +197,6 @@ __device__ void weights_row(const WArgs &a, int32_t i, int lane) {
 }
 
 // ------------------------------------------------------------------ batched
-template <int M>
-struct GramTable {
-  unsigned char v[M][M];
-  constexpr GramTable() : v{} {
-    for (int r = 0; r < M; ++r)
-      for (int c = 0; c < M; ++c) v[r][c] = (unsigned char)gram_moment<M>(r, c);
-  }
-};
-__constant__ GramTable<10> kGram3 = GramTable<10>();
-__constant__ GramTable<6> kGram2 = GramTable<6>();
-
-// lanes of a team that take part in the moment transpose-reduction (the
-// team's partial sums are first folded down to this many lanes)
-__host__ __device__ constexpr int red_lanes(int T) { return T < 4 ? T : 4; }
-
-__host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
-
 // Per-team LDS (doubles): one area that holds in turn the reduction buffer,
 // the moments, the Gauss-Jordan pivot row and the scaled target solutions
 // (an even count, so that every team area starts on a 16-byte boundary);
@@ -221,13 +204,6 @@ __host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 template <int M>
 constexpr int team_lds_doubles(int T, int KC) {
   return ((cmax(cmax(nmom<M>(), 4 * M), cmax(red_lanes(T) * red_lanes(T), M + 1)) + 1) & ~1) + KC * T;
-}
-
-// orders the LDS traffic of the lanes of one wave around a hand-off
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Unnormalised support weight of a neighbour at offset d with support h_j.
@@ -435,35 +411,8 @@ __device__ void weights_row_team(const WArgs &a, const RowPre<T, Q> &pre, int la
   } else {
     for_neighbours<T>(fetch, b, n, lane, acc1);
   }
-  // ---- team sum of the moments: butterflies down to R8 lanes, then a
-  // transpose through LDS in chunks of R8 moments (lane m of the chunk adds
-  // the R8 partials of moment c R8 + m in lane order)
-#pragma unroll
-  for (int o = T / 2; o >= R8; o >>= 1)
-#pragma unroll
-    for (int p = 0; p < NM; ++p) mom[p] += __shfl_xor(mom[p], o, T);
-  {
-    constexpr int NC = (NM + R8 - 1) / R8;
-    const int l8 = lane % R8;
-    double res[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-#pragma unroll
-      for (int m = 0; m < R8; ++m)
-        if (c * R8 + m < NM) s_red[m * R8 + l8] = mom[c * R8 + m];
-      wave_sync();
-      double t = s_red[l8 * R8];
-#pragma unroll
-      for (int q = 1; q < R8; ++q) t += s_red[l8 * R8 + q];
-      res[c] = t;
-      wave_sync();
-    }
-    // the buffer is free again: the moments take its place
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-      if (c * R8 + l8 < NM) s_mom[c * R8 + l8] = res[c];
-    wave_sync();
-  }
+  // ---- team sum of the moments (left in s_mom)
+  team_moment_sum<M, T>(mom, lane, s_red);
   // ---- Gauss-Jordan inversion of G; lane owns rows lane + q T (q < NR).
   // G is the Gram matrix of the unscaled monomials.  With D = diag(h_i^-deg a),
   // the matrix of the scaled coordinates d / h_i is D G D: its inverse gives the
@@ -494,41 +443,7 @@ __device__ void weights_row_team(const WArgs &a, const RowPre<T, Q> &pre, int la
     gsum = fmax(gsum, sacc * (dg == 0 ? 1.0 : (dg == 1 ? ih : ih2)));
   }
   wave_sync();  // the pivot rows overwrite the moments
-  bool okp = true;
-#pragma unroll
-  for (int k = 0; k < M; ++k) {
-    const int kq = k / T;
-    if (lane == k % T) {
-      const double piv = row[kq][k];
-      // 1 / piv from the hardware estimate and two Newton steps
-      double ip = __builtin_amdgcn_rcp(piv);
-      ip = fma(ip, fma(-piv, ip, 1.0), ip);
-      ip = fma(ip, fma(-piv, ip, 1.0), ip);
-      row[kq][k] = 1.0;
-#pragma unroll
-      for (int c = 0; c < M; ++c) row[kq][c] *= ip;
-#pragma unroll
-      for (int c = 0; c < M; ++c) s_prow[c] = row[kq][c];
-      s_prow[M] = piv;
-    }
-    wave_sync();
-    double pr[M];
-#pragma unroll
-    for (int c = 0; c < M; ++c) pr[c] = s_prow[c];
-    const double piv = s_prow[M];
-    okp = okp && (piv > 0.0) && isfinite(piv);
-#pragma unroll
-    for (int q = 0; q < NR; ++q) {
-      const int r = lane + q * T;
-      if (r < M && r != k) {
-        const double f = row[q][k];
-        row[q][k] = 0.0;
-#pragma unroll
-        for (int c = 0; c < M; ++c) row[q][c] -= f * pr[c];
-      }
-    }
-    wave_sync();
-  }
+  const bool okp = team_gauss_jordan<M, T>(row, lane, s_prow);
   double isum = 0.0;
   {
     const double h = g.hi, h2 = h * h;
