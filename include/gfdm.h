@@ -228,8 +228,9 @@ gf_status gf_apply_stencil(gf_ctx *ctx, const gf_nbr *nbr, gf_dtype wtype, const
  * model: the tiled rows with at most 128 neighbours, and the rows with more),
  * times the stencil kernel (weights of type wtype) with teams of 4, 8 and 16
  * lanes per particle and the application kernel with 4..64 lanes (median of
- * three runs each) and keeps the fastest team size in ctx; later calls on ctx
- * use it.  The fused kernel of gf_gfdm_weights_apply (stencils stored and
+ * three runs each) and keeps the fastest team size in ctx (for the stencil
+ * kernels 8 lanes unless 4 or 16 is more than 3% faster; 3D rows do not try
+ * 4); later calls on ctx use it.  The fused kernel of gf_gfdm_weights_apply (stencils stored and
  * applied to a field) is tuned on its own.  Allocates temporary buffers and
  * synchronises.  team_out (host, may be NULL) receives 24 ints indexed by
  * (model, band): the stencil team sizes (bulk bands 0-3, film bands 0-3; the

@@ -28,6 +28,7 @@ constexpr int kT = 8;
 
 struct AArgs {
   const double *x, *y, *z, *h, *nx, *ny, *nz;
+  const double4 *pos;  // (x, y, z, h) packed per particle
   const int64_t *row_ptr;
   const int32_t *col;
   const int32_t *sched;
@@ -82,10 +83,19 @@ __device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane, dou
     return;
   }
   // unnormalised weight e^{-a q^2} - e^{-a}, q^2 = |d|^2 / r^2, r = (h_i + h_j) / 2;
-  // e = e^{-a q^2} and ir2 = 1 / r^2 give dw/dd = -2 a e ir2 d
+  // e = e^{-a q^2} and ir2 = 1 / r^2 give dw/dd = -2 a e ir2 d.  Equal
+  // supports take the row's 1 / h_i^2; others 1 / r^2 from the reciprocal
+  // estimate and two Newton steps
+  const double ir2_row = 1.0 / (g.hi * g.hi);
   auto weight = [&](double hj, double d2, double &e, double &ir2) {
-    const double r = 0.5 * (g.hi + hj);
-    ir2 = 1.0 / (r * r);
+    if (hj == g.hi) {
+      ir2 = ir2_row;
+    } else {
+      const double r = 0.5 * (g.hi + hj), rr = r * r;
+      double q = __builtin_amdgcn_rcp(rr);
+      q = fma(q, fma(-rr, q, 1.0), q);
+      ir2 = fma(q, fma(-rr, q, 1.0), q);
+    }
     e = exp(-a.wf.alpha * (d2 * ir2));
     return e - a.wf.ea;
   };
@@ -95,9 +105,10 @@ __device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane, dou
   for (int p = 0; p < NM; ++p) mom[p] = 0.0;
   for (int k = lane; k < n; k += T) {
     const int32_t j = a.col[b + k];
-    const double dx = a.x[j] - g.xi, dy = a.y[j] - g.yi, dz = a.z[j] - g.zi;
+    const double4 pj = a.pos[j];
+    const double dx = pj.x - g.xi, dy = pj.y - g.yi, dz = pj.z - g.zi;
     double e, ir2;
-    const double w = weight(a.h[j], fma(dz, dz, fma(dy, dy, dx * dx)), e, ir2);
+    const double w = weight(pj.w, fma(dz, dz, fma(dy, dy, dx * dx)), e, ir2);
     double X, Y, Z;
     local_raw<M>(g, dx, dy, dz, X, Y, Z);
     moments_add_raw<M>(mom, w, X, Y, Z);
@@ -170,9 +181,10 @@ __device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane, dou
     for (int r = 0; r < M; ++r) v[s][r] = 0.0;  // (entries outside SEL are never read)
   for (int k = lane; k < n; k += T) {
     const int32_t j = a.col[b + k];
-    const double dx = a.x[j] - g.xi, dy = a.y[j] - g.yi, dz = a.z[j] - g.zi;
+    const double4 pj = a.pos[j];
+    const double dx = pj.x - g.xi, dy = pj.y - g.yi, dz = pj.z - g.zi;
     double e, ir2;
-    const double w = weight(a.h[j], fma(dz, dz, fma(dy, dy, dx * dx)), e, ir2);
+    const double w = weight(pj.w, fma(dz, dz, fma(dy, dy, dx * dx)), e, ir2);
     double phi[M], cb[4];
     monomials<M>(g, dx, dy, dz, phi);
     chatbar(j, cb);
@@ -222,9 +234,10 @@ __device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane, dou
     const int32_t j = a.col[b + k];
     double *out = a.dbar + 3 * (ob + k);
     if (j == i) { out[0] = 0.0; out[1] = 0.0; out[2] = 0.0; continue; }
-    const double dx = a.x[j] - g.xi, dy = a.y[j] - g.yi, dz = a.z[j] - g.zi;
+    const double4 pj = a.pos[j];
+    const double dx = pj.x - g.xi, dy = pj.y - g.yi, dz = pj.z - g.zi;
     double e, ir2;
-    const double w = weight(a.h[j], fma(dz, dz, fma(dy, dy, dx * dx)), e, ir2);
+    const double w = weight(pj.w, fma(dz, dz, fma(dy, dy, dx * dx)), e, ir2);
     double phi[M], cb[4];
     monomials<M>(g, dx, dy, dz, phi);
     chatbar(j, cb);
@@ -261,7 +274,7 @@ __device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane, dou
 }
 
 template <int M, unsigned SEL>
-__global__ void __launch_bounds__(kBlock) k_adjoint_x(AArgs a) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(M == 6 && SEL == 8u ? 4 : 1))) k_adjoint_x(AArgs a) {
   __shared__ double smem[(kBlock / kT) * adj_lds_doubles<M>()];
   const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t team = gt / kT;
@@ -332,7 +345,8 @@ extern "C" gf_status gf_gfdm_weights_adjoint(gf_ctx *ctx, const gf_particles *p,
   if (params) prm = *params;
   if ((st = ensure_grouped_rows(ctx, const_cast<gf_nbr *>(nbr)))) return st;
   Arena ar;
-  if ((st = ensure_scratch(ctx, arena_bytes({sizeof(double) * 3 * (size_t)std::max<int64_t>(nbr->nnz, 1)}), &ar)))
+  if ((st = ensure_scratch(ctx, arena_bytes({sizeof(double) * 3 * (size_t)std::max<int64_t>(nbr->nnz, 1),
+                                             sizeof(double4) * (size_t)p->n}), &ar)))
     return st;
   AArgs a;
   a.x = p->x; a.y = p->y; a.z = p->z; a.h = p->h; a.nx = p->nx; a.ny = p->ny; a.nz = p->nz;
@@ -340,6 +354,14 @@ extern "C" gf_status gf_gfdm_weights_adjoint(gf_ctx *ctx, const gf_particles *p,
   a.wf = make_weight_fn(prm.alpha_w);
   a.mask = op_mask; a.u = u; a.ybar = ybar; a.status = status_n;
   a.dbar = ar.take<double>(3 * (size_t)std::max<int64_t>(nbr->nnz, 1));
+  double4 *pos = ar.take<double4>(p->n);
+  {
+    ProfScope prof(ctx, "pack_positions");
+    hipLaunchKernelGGL(k_pack_pos, dim3(grid_for(p->n, 256)), dim3(256), 0, ctx->stream, p->x, p->y, p->z, p->h, p->n,
+                       pos);
+    GF_LAUNCH_CHECK(ctx);
+  }
+  a.pos = pos;
   a.xbar = xbar_3n;
   for (int m = 0; m < 2; ++m) {
     const int64_t s0 = nbr->group_start[m * GF_NBAND], s1 = nbr->group_start[(m + 1) * GF_NBAND];

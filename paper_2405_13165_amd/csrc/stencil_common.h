@@ -438,6 +438,16 @@ __device__ inline bool team_gauss_jordan(double (&row)[(M + T - 1) / T][M], int 
   return okp;
 }
 
+// (x, y, z, h) of every particle packed into one 32-byte record: kernels that
+// gather neighbour positions through the column lists read one record per
+// neighbour instead of four scattered values
+static __global__ void __launch_bounds__(256) k_pack_pos(const double *__restrict__ x, const double *__restrict__ y,
+                                                         const double *__restrict__ z, const double *__restrict__ h,
+                                                         int64_t n, double4 *__restrict__ pos) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) pos[i] = make_double4(x[i], y[i], z[i], h[i]);
+}
+
 // Consecutive workgroups are dispatched round-robin over the 8 XCDs of the
 // chip, each with its own L2.  Remap so that XCD k processes the k-th
 // contiguous slice of the (Morton-ordered) work: neighbouring particles then

@@ -784,13 +784,6 @@ __global__ void __launch_bounds__(kQrBlock) k_weights_qr(WArgs a, double *panels
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_pack_pos(const double *__restrict__ x, const double *__restrict__ y,
-                                                     const double *__restrict__ z, const double *__restrict__ h,
-                                                     int64_t n, double4 *__restrict__ pos) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) pos[i] = make_double4(x[i], y[i], z[i], h[i]);
-}
-
 __global__ void k_zero_i32(int32_t *p, int n) {
   if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
@@ -1151,11 +1144,16 @@ extern "C" gf_status gf_autotune(gf_ctx *ctx, const gf_particles *p, const gf_nb
   LaunchUnit units[2 * GF_NBAND];
   const int nu = launch_units(nbr, units);
   const bool f32 = wtype == GF_F32;
+  // the team size of each unit: 8 lanes unless 4 or 16 is faster by more than
+  // 3%.  The trials run back to back, where caches are warm; 3D rows do not
+  // try 4 lanes (the kernel then holds one wave per SIMD and cannot hide the
+  // memory latency of a cold cache, however it fares warm), and close calls
+  // go to 8.
   auto tune = [&](int (*team)[4], bool fused) {
     for (int q = 0; q < nu && !st; ++q) {
-      float best = INFINITY;
-      int bestT = team[units[q].model][units[q].band];
+      float med[3] = {INFINITY, INFINITY, INFINITY};
       for (int t = 0; t < 3 && !st; ++t) {
+        if (units[q].model == 0 && sizes[t] == 4) continue;
         float times[3];
         for (int rep = -1; rep < 3 && !st; ++rep) {
           hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, a.qcount, 16);
@@ -1174,9 +1172,13 @@ extern "C" gf_status gf_autotune(gf_ctx *ctx, const gf_particles *p, const gf_nb
         }
         if (st) break;
         std::sort(times, times + 3);
-        if (times[1] < best) { best = times[1]; bestT = sizes[t]; }
+        med[t] = times[1];
       }
-      team[units[q].model][units[q].band] = bestT;
+      int bestT = 8;
+      float best = med[1];
+      for (int t = 0; t < 3; ++t)
+        if (t != 1 && med[t] < 0.97f * med[1] && med[t] < best) { best = med[t]; bestT = sizes[t]; }
+      if (!st) team[units[q].model][units[q].band] = bestT;
     }
   };
   tune(ctx->wteam, false);
