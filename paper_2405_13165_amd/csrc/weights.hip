@@ -246,15 +246,23 @@ struct FetchGlobal {  // packed positions, gathered through col[]
   __device__ double4 get(int32_t j) const { return pos[j]; }
   __device__ double field(int32_t j) const { return u[j]; }
 };
-struct FetchTile {    // the tile's positions (and field) staged in LDS, addressed by slot[]
+// The tile's positions (and field) staged in LDS, addressed by slot[]: (x, y)
+// and (z, h) in two arrays of 16-byte records, so that the two reads of a
+// neighbour each start at one of 8 offsets in a 128-byte bank row (32-byte
+// records start at one of 4, and the lanes of a read collide in the banks
+// twice as often).
+struct FetchTile {
   static constexpr bool kDeep = true;
   static constexpr bool kQuads = true;  // slots may be read in aligned groups of four
-  const double4 *sp;
+  const double2 *sxy, *szh;
   const uint16_t *slot;
   const double *su;
   int32_t dummy;
   __device__ int32_t idx(int64_t e) const { return slot[e]; }
-  __device__ double4 get(int32_t s) const { return sp[s]; }
+  __device__ double4 get(int32_t s) const {
+    const double2 p = sxy[s], q = szh[s];
+    return make_double4(p.x, p.y, q.x, q.y);
+  }
   __device__ double field(int32_t s) const { return su[s]; }
 };
 
@@ -583,6 +591,7 @@ k_weights_tile(WArgs a, TileArgs ta, const uint16_t *__restrict__ slot) {
   const int64_t u0 = ta.off[ta.tile0 + tl];
   const int cnt = (int)(ta.off[ta.tile0 + tl + 1] - u0);
   const bool staged = cnt <= ta.cap;
+  double2 *s_xy = reinterpret_cast<double2 *>(s_dyn), *s_zh = s_xy + ta.cap;   // positions (cap of them)
   double *s_u = reinterpret_cast<double *>(s_dyn + ta.cap);  // fused field values (cap of them)
   const int team = threadIdx.x / T, lane = threadIdx.x % T;
   const int64_t r = tl * kTileRows + team;
@@ -598,7 +607,8 @@ k_weights_tile(WArgs a, TileArgs ta, const uint16_t *__restrict__ slot) {
     for (int s = threadIdx.x; s < cnt; s += blockDim.x) {
       const int32_t j = ta.u[u0 + s];
       const double hj = a.h[j];
-      s_dyn[s] = make_double4(a.x[j], a.y[j], a.z[j], hj);
+      s_xy[s] = make_double2(a.x[j], a.y[j]);
+      s_zh[s] = make_double2(a.z[j], hj);
       same &= hj == h0;
       if constexpr (FUSED) s_u[s] = a.u[j];
     }
@@ -608,9 +618,9 @@ k_weights_tile(WArgs a, TileArgs ta, const uint16_t *__restrict__ slot) {
   double *sm = s_u + (FUSED ? ((ta.cap + 1) & ~1) : 0) + team * team_lds_doubles<M>(T, 0);
   if (staged)
     if (uni)
-      weights_row_team<M, T, OUT, FUSED, FASTW, 0, true>(a, pre, lane, sm, FetchTile{s_dyn, slot, s_u, 0});
+      weights_row_team<M, T, OUT, FUSED, FASTW, 0, true>(a, pre, lane, sm, FetchTile{s_xy, s_zh, slot, s_u, 0});
     else
-      weights_row_team<M, T, OUT, FUSED, FASTW, 0, false>(a, pre, lane, sm, FetchTile{s_dyn, slot, s_u, 0});
+      weights_row_team<M, T, OUT, FUSED, FASTW, 0, false>(a, pre, lane, sm, FetchTile{s_xy, s_zh, slot, s_u, 0});
   else
     weights_row_team<M, T, OUT, FUSED, FASTW, 0, false>(a, pre, lane, sm, FetchGlobal{a.pos, a.col, a.u, pre.i});
 }
