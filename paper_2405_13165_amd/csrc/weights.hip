@@ -18,6 +18,7 @@
 // Plain path: one work-item per particle in the caller's order, an FP64 Gram
 // matrix with LDL^T solves, FP64 output.
 #include <algorithm>
+#include <type_traits>
 #include <mutex>
 
 #include "stencil_common.h"
@@ -237,7 +238,7 @@ __device__ inline double nbr_weight_raw(const WArgs &a, const RowGeom &g, double
 // itself is also loaded one neighbour ahead (global gathers and LDS reads).
 struct FetchGlobal {  // packed positions, gathered through col[]
   static constexpr bool kDeep = true;
-  static constexpr bool kQuads = false;
+  static constexpr bool kPairs = false;
   const double4 *pos;
   const int32_t *col;
   const double *u;     // field of the fused application
@@ -253,7 +254,7 @@ struct FetchGlobal {  // packed positions, gathered through col[]
 // twice as often).
 struct FetchTile {
   static constexpr bool kDeep = true;
-  static constexpr bool kQuads = true;  // slots may be read in aligned groups of four
+  static constexpr bool kPairs = true;  // slots may be read in aligned pairs
   const double2 *sxy, *szh;
   const uint16_t *slot;
   const double *su;
@@ -268,7 +269,9 @@ struct FetchTile {
 
 // Visit the neighbours k = k0, k0 + T, ... (k0 in (-T, T); negative k are
 // skipped) of the row starting at CSR entry b, calling body(k, position,
-// handle) with the loads software-pipelined.
+// handle) with the loads software-pipelined (the handle two steps ahead is
+// read on every step, past the row's end from its last entry: a valid handle,
+// never used).
 template <int T, class F, class Body>
 __device__ inline void for_neighbours(const F &fetch, int64_t b, int n, int k0, Body &&body) {
   auto in = [n](int k) { return k >= 0 && k < n; };
@@ -282,7 +285,7 @@ __device__ inline void for_neighbours(const F &fetch, int64_t b, int n, int k0, 
       const int32_t h = hc;
       hc = hn;
       pc = fetch.get(hn);
-      hn = (k + 2 * T < n) ? fetch.idx(b + k + 2 * T) : fetch.dummy;
+      hn = fetch.idx(b + min(k + 2 * T, n - 1));
       if (k >= 0) body(k, pj, h);
     }
   } else {
@@ -303,6 +306,16 @@ __device__ inline void for_neighbours(const F &fetch, int64_t b, int n, int k0, 
 // frame and field value, and (tiled rows) the slot quads of pass 1.  The tile
 // kernel loads these before it stages the tile, so that their latency (three
 // dependent reads: schedule, row extent, slots) overlaps the staging.
+// Pass 1 of the tiled kernels reads its slots in aligned groups of G: pairs
+// for teams of 8 or more lanes (a row of n entries takes ceil(n / 2T) steps of
+// two slots instead of ceil(n / 4T) steps of four: fewer masked lanes at its
+// end), quads for 4-lane teams (fewer registers, which hold that kernel at four
+// waves per SIMD).
+template <int T>
+constexpr int slot_group() { return T >= 8 ? 2 : 4; }
+template <int G>
+using SlotVec = typename std::conditional<G == 2, ushort2, ushort4>::type;
+
 template <int T, bool QUADS>
 struct RowPre {
   int32_t i;
@@ -310,7 +323,7 @@ struct RowPre {
   int n;
   RowGeom g;
   double ui;
-  ushort4 ss[QUADS ? kTileBandRow / (4 * T) + 1 : 1];
+  SlotVec<slot_group<T>()> ss[QUADS ? kTileBandRow / (slot_group<T>() * T) + 1 : 1];
 };
 
 template <int M, int T, bool FUSED, bool QUADS>
@@ -321,13 +334,14 @@ __device__ inline void row_pre(const WArgs &a, const uint16_t *slot, int32_t i, 
   row_geom<M>(a, i, p.g);
   p.ui = FUSED ? a.u[i] : 0.0;
   if constexpr (QUADS) {
-    // lane l takes the aligned quads of slots q0 + l, q0 + l + T, ...
-    constexpr int kQ1 = kTileBandRow / (4 * T) + 1;
-    const int64_t q0 = (p.b >> 2) + lane, e = p.b + p.n;
+    // lane l takes the aligned groups of slots q0 + l, q0 + l + T, ...
+    constexpr int G = slot_group<T>();
+    constexpr int kQ1 = kTileBandRow / (G * T) + 1;
+    const int64_t q0 = p.b / G + lane, e = p.b + p.n;
 #pragma unroll
     for (int j = 0; j < kQ1; ++j) {
-      const int64_t k = 4 * (q0 + j * T);
-      if (k < e) p.ss[j] = *reinterpret_cast<const ushort4 *>(slot + k);
+      const int64_t k = G * (q0 + j * T);
+      if (k < e) p.ss[j] = *reinterpret_cast<const SlotVec<G> *>(slot + k);
     }
   }
 }
@@ -389,31 +403,38 @@ __device__ void weights_row_team(const WArgs &a, const RowPre<T, Q> &pre, int la
     local_raw<M>(g, dx, dy, dz, X, Y, Z);
     moments_add_raw<M>(mom, w, X, Y, Z);
   };
-  if constexpr (F::kQuads && KC == 0) {
-    // tiled rows (at most kTileBandRow entries): lane l takes the aligned quads of
-    // slots q0 + l, q0 + l + T, ..., all loaded before the first is used (with the
-    // row, by row_pre, where the team is at least 8 wide); a quad may reach up to
-    // three entries into the neighbouring rows (the slot array is padded): those
-    // are skipped
-    constexpr int kQ1 = kTileBandRow / (4 * T) + 1;
-    const int64_t q0 = (b >> 2) + lane, e = b + n;
-    ushort4 ssl[Q ? 1 : kQ1];
+  if constexpr (F::kPairs && KC == 0) {
+    // tiled rows (at most kTileBandRow entries): lane l takes the aligned groups
+    // of G slots q0 + l, q0 + l + T, ..., all loaded before the first is used
+    // (with the row, by row_pre, where the team is at least 8 wide); a group may
+    // reach up to G - 1 entries into the neighbouring rows (the slot array is
+    // padded): those are skipped
+    constexpr int G = slot_group<T>();
+    constexpr int kQ1 = kTileBandRow / (G * T) + 1;
+    const int64_t q0 = b / G + lane, e = b + n;
+    SlotVec<G> ssl[Q ? 1 : kQ1];
     if constexpr (!Q) {
 #pragma unroll
       for (int j = 0; j < kQ1; ++j) {
-        const int64_t k = 4 * (q0 + j * T);
-        if (k < e) ssl[j] = *reinterpret_cast<const ushort4 *>(fetch.slot + k);
+        const int64_t k = G * (q0 + j * T);
+        if (k < e) ssl[j] = *reinterpret_cast<const SlotVec<G> *>(fetch.slot + k);
       }
     }
-    const ushort4 *ss = Q ? pre.ss : ssl;
+    const SlotVec<G> *ss = Q ? pre.ss : ssl;
 #pragma unroll
     for (int j = 0; j < kQ1; ++j) {
-      const int64_t k = 4 * (q0 + j * T);
+      const int64_t k = G * (q0 + j * T);
       if (k < e) {
-        if (k >= b) acc1(0, fetch.get(ss[j].x), 0);
-        if (k + 1 >= b && k + 1 < e) acc1(0, fetch.get(ss[j].y), 0);
-        if (k + 2 >= b && k + 2 < e) acc1(0, fetch.get(ss[j].z), 0);
-        if (k + 3 < e) acc1(0, fetch.get(ss[j].w), 0);
+        // (k < e holds; k + G - 1 >= b, as groups are aligned)
+        if constexpr (G == 4) {
+          if (k >= b) acc1(0, fetch.get(ss[j].x), 0);
+          if (k + 1 >= b && k + 1 < e) acc1(0, fetch.get(ss[j].y), 0);
+          if (k + 2 >= b && k + 2 < e) acc1(0, fetch.get(ss[j].z), 0);
+          if (k + 3 < e) acc1(0, fetch.get(ss[j].w), 0);
+        } else {
+          if (k >= b) acc1(0, fetch.get(ss[j].x), 0);
+          if (k + 1 < e) acc1(0, fetch.get(ss[j].y), 0);
+        }
       }
     }
   } else {
@@ -511,7 +532,15 @@ __device__ void weights_row_team(const WArgs &a, const RowPre<T, Q> &pre, int la
   const double ui = pre.ui;
   // the team's stores of one step cover whole aligned T-entry blocks
   const int k0 = a.w_out ? lane - (int)(b & (T - 1)) : lane;
-  for_neighbours<T>(fetch, b, n, k0, [&](int k, const double4 &pj, int32_t h) {
+  // Stores are issued one step late, at the start of the next step: a load
+  // and a store in flight count against one counter, and the wait for the
+  // next handle (right after the step) would otherwise wait for the store it
+  // just issued.  (Two copies of the loop, with and without stores.)
+  f32x4 vprev = {0.0f, 0.0f, 0.0f, 0.0f};
+  int kprev = -1;
+  auto body2 = [&](int k, const double4 &pj, int32_t h, auto store) {
+    if constexpr (OUT == GF_F32 && decltype(store)::value)
+      if (kprev >= 0) __builtin_nontemporal_store(vprev, reinterpret_cast<f32x4 *>(a.w_out) + (b + kprev));
     const double dx = pj.x - g.xi, dy = pj.y - g.yi, dz = pj.z - g.zi;
     double w;
     if constexpr (KC > 0)
@@ -533,11 +562,14 @@ __device__ void weights_row_team(const WArgs &a, const RowPre<T, Q> &pre, int la
     if constexpr (OUT == GF_F32) {
       // rounded once: the stored stencils are also the ones applied
       const f32x4 v = {(float)c[0], (float)c[1], (float)c[2], (float)c[3]};
-      if (a.w_out) __builtin_nontemporal_store(v, reinterpret_cast<f32x4 *>(a.w_out) + (b + k));
+      if constexpr (decltype(store)::value) {
+        vprev = v;
+        kprev = k;
+      }
 #pragma unroll
       for (int s = 0; s < 4; ++s) c[s] = (double)v[s];
     } else {
-      if (a.w_out) store_w<OUT, true>(a.w_out, b + k, c[0], c[1], c[2], c[3]);
+      if constexpr (decltype(store)::value) store_w<OUT, true>(a.w_out, b + k, c[0], c[1], c[2], c[3]);
     }
     if constexpr (FUSED) {
       // the diagonal entry contributes u_i - u_i = 0
@@ -545,7 +577,17 @@ __device__ void weights_row_team(const WArgs &a, const RowPre<T, Q> &pre, int la
 #pragma unroll
       for (int s = 0; s < 4; ++s) acc[s] = fma(c[s], du, acc[s]);
     }
-  });
+  };
+  if (a.w_out) {
+    for_neighbours<T>(fetch, b, n, k0, [&](int k, const double4 &pj, int32_t h) {
+      body2(k, pj, h, std::true_type{});
+    });
+    if constexpr (OUT == GF_F32)
+      if (kprev >= 0) __builtin_nontemporal_store(vprev, reinterpret_cast<f32x4 *>(a.w_out) + (b + kprev));
+  } else
+    for_neighbours<T>(fetch, b, n, k0, [&](int k, const double4 &pj, int32_t h) {
+      body2(k, pj, h, std::false_type{});
+    });
   if constexpr (FUSED) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) acc[s] = team_sum(acc[s], T);
@@ -583,16 +625,40 @@ struct TileArgs {
   int cap;             // LDS capacity in positions
 };
 
+// LDS positions a tile block may stage (larger tiles read global memory)
+constexpr int kTileCap = 1024;
+
+// LDS of a tile block, in order: (x, y) records, (z, h) records, field values
+// (fused), the team areas, one flag per wave.  The 3D kernels of 8 or more
+// lanes (at most 3 blocks per CU, bound by registers) lay the arrays out for
+// kTileCap positions whatever the tile holds: every offset is then a
+// compile-time constant, and a neighbour's three reads share one address
+// register.  The other kernels size them by the launch's largest tile, which
+// keeps their LDS small enough for more blocks per CU.
+template <int M, int T>
+constexpr int tile_stride() { return (M == 10 && T >= 8) ? kTileCap : 0; }
+
+template <int M, bool FUSED>
+size_t tile_lds_bytes(int T, int cap) {
+  const int st = (M == 10 && T >= 8) ? kTileCap : cap;  // = tile_stride<M, T>() or cap
+  return sizeof(double4) * st + (FUSED ? sizeof(double) * ((st + 1) & ~1) : 0) +
+         sizeof(double) * kTileRows * team_lds_doubles<M>(T, 0) + sizeof(int) * (kTileRows * T / 64);
+}
+
 template <int M, int T, int OUT, bool FUSED, bool FASTW>
 __global__ void __launch_bounds__(kTileRows * T) __attribute__((amdgpu_waves_per_eu(T >= 8 ? 3 : 1)))
 k_weights_tile(WArgs a, TileArgs ta, const uint16_t *__restrict__ slot) {
-  extern __shared__ double4 s_dyn[];
+  extern __shared__ double4 s_dyn[];  // the kernel's only LDS: it starts at address 0
+  constexpr int ZS = tile_stride<M, T>();
+  const int st = ZS ? ZS : ta.cap;
   const int64_t tl = xcd_block(blockIdx.x, gridDim.x);
   const int64_t u0 = ta.off[ta.tile0 + tl];
   const int cnt = (int)(ta.off[ta.tile0 + tl + 1] - u0);
   const bool staged = cnt <= ta.cap;
-  double2 *s_xy = reinterpret_cast<double2 *>(s_dyn), *s_zh = s_xy + ta.cap;   // positions (cap of them)
-  double *s_u = reinterpret_cast<double *>(s_dyn + ta.cap);  // fused field values (cap of them)
+  double2 *s_xy = reinterpret_cast<double2 *>(s_dyn), *s_zh = s_xy + st;   // positions
+  double *s_u = reinterpret_cast<double *>(s_dyn + st);                    // fused field values
+  double *s_team = s_u + (FUSED ? ((st + 1) & ~1) : 0);
+  int *s_flag = reinterpret_cast<int *>(s_team + kTileRows * team_lds_doubles<M>(T, 0));
   const int team = threadIdx.x / T, lane = threadIdx.x % T;
   const int64_t r = tl * kTileRows + team;
   const bool live = r < a.nrows;
@@ -613,9 +679,17 @@ k_weights_tile(WArgs a, TileArgs ta, const uint16_t *__restrict__ slot) {
       if constexpr (FUSED) s_u[s] = a.u[j];
     }
   }
-  const bool uni = __syncthreads_and(same) != 0;
+  // block-wide AND of `same`: a ballot per wave, one flag per wave, one barrier
+  // (which also publishes the staged tile)
+  constexpr int NW = kTileRows * T / 64;
+  const bool wave_same = __ballot(!same) == 0;
+  if ((threadIdx.x & 63) == 0) s_flag[threadIdx.x >> 6] = wave_same;
+  __syncthreads();
+  bool uni = true;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) uni = uni && s_flag[w] != 0;
   if (!live) return;
-  double *sm = s_u + (FUSED ? ((ta.cap + 1) & ~1) : 0) + team * team_lds_doubles<M>(T, 0);
+  double *sm = s_team + team * team_lds_doubles<M>(T, 0);
   if (staged)
     if (uni)
       weights_row_team<M, T, OUT, FUSED, FASTW, 0, true>(a, pre, lane, sm, FetchTile{s_xy, s_zh, slot, s_u, 0});
@@ -849,9 +923,6 @@ gf_status launch_team(gf_ctx *ctx, hipStream_t st, const WArgs &a, int T, const 
   return GF_OK;
 }
 
-// LDS positions a tile block may stage (larger tiles read global memory)
-constexpr int kTileCap = 1024;
-
 template <int M, int OUT, bool FUSED, bool FASTW>
 gf_status launch_tile(gf_ctx *ctx, hipStream_t st, const WArgs &a, const gf_nbr *nbr, const LaunchUnit &u, int T,
                       const char *name) {
@@ -861,8 +932,7 @@ gf_status launch_tile(gf_ctx *ctx, hipStream_t st, const WArgs &a, const gf_nbr 
   ta.u = nbr->tile_u;
   ta.tile0 = u.tile0;
   ta.cap = std::min(u.tile_max, tile_capacity(ctx, kTileCap));
-  const size_t lds = sizeof(double4) * ta.cap + (FUSED ? sizeof(double) * ((ta.cap + 1) & ~1) : 0) +
-                     sizeof(double) * kTileRows * team_lds_doubles<M>(T, 0);
+  const size_t lds = tile_lds_bytes<M, FUSED>(T, ta.cap);
   const dim3 grid(grid_for(u.ntiles, 1)), block(kTileRows * T);
   switch (T) {
     case 4: hipLaunchKernelGGL((k_weights_tile<M, 4, OUT, FUSED, FASTW>), grid, block, lds, st, a, ta, nbr->slot); break;
