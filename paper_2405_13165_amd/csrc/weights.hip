@@ -199,12 +199,14 @@ __device__ void weights_row(const WArgs &a, int32_t i, int lane) {
 
 // ------------------------------------------------------------------ batched
 // Per-team LDS (doubles): one area that holds in turn the reduction buffer,
-// the moments, the Gauss-Jordan pivot row and the scaled target solutions
-// (an even count, so that every team area starts on a 16-byte boundary);
-// then KC cached support weights per lane.
+// the moments, the Gauss-Jordan pivot row, the target solutions and (tiled
+// rows, teams of 8 or more lanes) the row's slots during pass 2 (an even
+// count, so that every team area starts on a 16-byte boundary); then KC
+// cached support weights per lane.
 template <int M>
 constexpr int team_lds_doubles(int T, int KC) {
-  return ((cmax(cmax(nmom<M>(), 4 * M), cmax(red_lanes(T) * red_lanes(T), M + 1)) + 1) & ~1) + KC * T;
+  const int slots = T >= 8 ? (kTileBandRow / (2 * T) + 1) * T / 2 : 0;  // slot pairs, 4 bytes each
+  return ((cmax(cmax(cmax(nmom<M>(), 4 * M), cmax(red_lanes(T) * red_lanes(T), M + 1)), slots) + 1) & ~1) + KC * T;
 }
 
 // Unnormalised support weight of a neighbour at offset d with support h_j.
@@ -260,6 +262,26 @@ struct FetchTile {
   const double *su;
   int32_t dummy;
   __device__ int32_t idx(int64_t e) const { return slot[e]; }
+  __device__ double4 get(int32_t s) const {
+    const double2 p = sxy[s], q = szh[s];
+    return make_double4(p.x, p.y, q.x, q.y);
+  }
+  __device__ double field(int32_t s) const { return su[s]; }
+};
+
+// Pass 2 of the tiled rows of 8- or 16-lane teams: as FetchTile, with the
+// row's slots copied into the team's LDS (entry e at sl[e - b2], b2 the even
+// entry at or below the row's first), so that the loop issues no global loads
+// (whose waits would also wait for the stencil stores in flight).
+struct FetchTileL {
+  static constexpr bool kDeep = true;
+  static constexpr bool kPairs = false;
+  const double2 *sxy, *szh;
+  const uint16_t *sl;
+  int64_t b2;
+  const double *su;
+  int32_t dummy;
+  __device__ int32_t idx(int64_t e) const { return sl[e - b2]; }
   __device__ double4 get(int32_t s) const {
     const double2 p = sxy[s], q = szh[s];
     return make_double4(p.x, p.y, q.x, q.y);
@@ -528,6 +550,19 @@ __device__ void weights_row_team(const WArgs &a, const RowPre<T, Q> &pre, int la
   double lam[4 * M];
 #pragma unroll
   for (int q = 0; q < 4 * M; ++q) lam[q] = s_lam[q];
+  constexpr bool kSlotsLds = F::kPairs && Q && KC == 0;
+  if constexpr (kSlotsLds) {
+    // the target solutions are in registers: the team's area takes the row's
+    // slot pairs (lane l's pair j is word l + j T)
+    wave_sync();
+    constexpr int kQ1 = kTileBandRow / (2 * T) + 1;
+    const int64_t q0 = (b >> 1) + lane, e = b + n;
+    uint32_t *s_sl = reinterpret_cast<uint32_t *>(sm);
+#pragma unroll
+    for (int j = 0; j < kQ1; ++j)
+      if (2 * (q0 + j * T) < e) s_sl[lane + j * T] = __builtin_bit_cast(uint32_t, pre.ss[j]);
+    wave_sync();
+  }
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   const double ui = pre.ui;
   // the team's stores of one step cover whole aligned T-entry blocks
@@ -578,16 +613,23 @@ __device__ void weights_row_team(const WArgs &a, const RowPre<T, Q> &pre, int la
       for (int s = 0; s < 4; ++s) acc[s] = fma(c[s], du, acc[s]);
     }
   };
-  if (a.w_out) {
-    for_neighbours<T>(fetch, b, n, k0, [&](int k, const double4 &pj, int32_t h) {
-      body2(k, pj, h, std::true_type{});
-    });
-    if constexpr (OUT == GF_F32)
-      if (kprev >= 0) __builtin_nontemporal_store(vprev, reinterpret_cast<f32x4 *>(a.w_out) + (b + kprev));
-  } else
-    for_neighbours<T>(fetch, b, n, k0, [&](int k, const double4 &pj, int32_t h) {
-      body2(k, pj, h, std::false_type{});
-    });
+  auto pass2 = [&](const auto &f2) {
+    if (a.w_out) {
+      for_neighbours<T>(f2, b, n, k0, [&](int k, const double4 &pj, int32_t h) {
+        body2(k, pj, h, std::true_type{});
+      });
+      if constexpr (OUT == GF_F32)
+        if (kprev >= 0) __builtin_nontemporal_store(vprev, reinterpret_cast<f32x4 *>(a.w_out) + (b + kprev));
+    } else {
+      for_neighbours<T>(f2, b, n, k0, [&](int k, const double4 &pj, int32_t h) {
+        body2(k, pj, h, std::false_type{});
+      });
+    }
+  };
+  if constexpr (kSlotsLds)
+    pass2(FetchTileL{fetch.sxy, fetch.szh, reinterpret_cast<const uint16_t *>(sm), b & ~int64_t(1), fetch.su, 0});
+  else
+    pass2(fetch);
   if constexpr (FUSED) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) acc[s] = team_sum(acc[s], T);
