@@ -10,8 +10,11 @@
 // to the particle itself keep an exactly planar neighbourhood exactly planar
 // (its third eigenvalue is exactly zero), and with |d| <= h the subtraction
 // loses no more than a few ulp of the largest eigenvalue.  The neighbour
-// kinds are counted in 16-bit fields of one integer.  One lane of the team
-// then runs the eigen solve and the classification.
+// kinds are counted in 16-bit fields of one integer.  The team writes the
+// covariance and the counts of its row (one 64-byte record), and a second
+// kernel runs the eigen solve and the classification with one particle per
+// lane: inside the team kernel only one lane of each team would do that
+// work while the other three idle.
 #include "stencil_common.h"
 
 using namespace gfdm_dev;
@@ -80,6 +83,7 @@ struct PcaArgs {
   int literal;
   double *lam, *w3, *eps;
   uint8_t *raw;
+  double2 *cov;  // [n][4]: c00 c01 | c02 c11 | c12 c22 | counts, 0
 };
 
 // eigen decomposition of the covariance, outputs and the flags of particle i
@@ -205,7 +209,21 @@ __device__ void pca_row(const PcaArgs &a, int32_t i, int lane, const F &fetch) {
   const double cx = mx * inv, cy = my * inv, cz = mz * inv;
   c[0] = sxx - mx * cx; c[1] = sxy - mx * cy; c[2] = sxz - mx * cz;
   c[3] = syy - my * cy; c[4] = syz - my * cz; c[5] = szz - mz * cz;
-  if (lane == 0) pca_finish(a, i, n_int, n_fs, c[0], c[1], c[2], c[3], c[4], c[5]);
+  // every lane holds the sums: lane l writes 16 bytes of the row's record
+  const double cnt = __builtin_bit_cast(double, (uint64_t)(uint32_t)n_int | ((uint64_t)(uint32_t)n_fs << 32));
+  const double2 v = lane == 0 ? make_double2(c[0], c[1])
+                  : lane == 1 ? make_double2(c[2], c[3])
+                  : lane == 2 ? make_double2(c[4], c[5]) : make_double2(cnt, 0.0);
+  a.cov[4 * (int64_t)i + lane] = v;
+}
+
+// eigen solve and classification, one particle per lane
+__global__ void __launch_bounds__(kBlock) k_pca_finish(PcaArgs a, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 r0 = a.cov[4 * i], r1 = a.cov[4 * i + 1], r2 = a.cov[4 * i + 2], r3 = a.cov[4 * i + 3];
+  const uint64_t cnt = __builtin_bit_cast(uint64_t, r3.x);
+  pca_finish(a, (int32_t)i, (int)(uint32_t)cnt, (int)(uint32_t)(cnt >> 32), r0.x, r0.y, r1.x, r1.y, r2.x, r2.y);
 }
 
 // tiled rows: one neighbour tile per block, kTileRows teams
@@ -289,16 +307,18 @@ extern "C" gf_status gf_classify_pca(gf_ctx *ctx, const gf_particles *p, const g
   if (params) prm = *params;
   const int64_t n = p->n;
   Arena ar;
-  if ((st = ensure_scratch(ctx, arena_bytes({(size_t)n}), &ar))) return st;
+  if ((st = ensure_scratch(ctx, arena_bytes({(size_t)n, 64 * (size_t)n}), &ar))) return st;
   uint8_t *raw = flag_n ? ar.take<uint8_t>(n) : nullptr;
+  double2 *cov = ar.take<double2>(4 * (size_t)n);
   PcaArgs a;
   a.x = p->x; a.y = p->y; a.z = p->z; a.model = p->model; a.kind = p->kind;
   a.nx = p->nx; a.ny = p->ny; a.nz = p->nz;
   a.row_ptr = same->row_ptr; a.col = same->col;
   a.film_height = film_height; a.h3d = h3d; a.prev = prev_transitioned; a.user = user_flag;
   a.eps_max = prm.eps_lambda_max; a.cos_theta = std::cos(prm.theta_star); a.literal = prm.literal_rule;
-  a.lam = lam_3n; a.w3 = w3_3n; a.eps = eps_n; a.raw = raw;
-  ProfScope prof(ctx, "pca_flags");
+  a.lam = lam_3n; a.w3 = w3_3n; a.eps = eps_n; a.raw = raw; a.cov = cov;
+  {
+  ProfScope prof(ctx, "pca_cov");
   LaunchUnit units[2 * GF_NBAND];
   const int nu = launch_units(same, units);
   for (int q = 0; q < nu; ++q) {
@@ -312,6 +332,12 @@ extern "C" gf_status gf_classify_pca(gf_ctx *ctx, const gf_particles *p, const g
     } else {
       hipLaunchKernelGGL(k_pca_flags, dim3(grid_for(u.nrows * kTeam, kBlock)), dim3(kBlock), 0, ctx->stream, a);
     }
+    GF_LAUNCH_CHECK(ctx);
+  }
+  }
+  {
+    ProfScope prof(ctx, "pca_finish");
+    hipLaunchKernelGGL(k_pca_finish, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, ctx->stream, a, n);
     GF_LAUNCH_CHECK(ctx);
   }
   if (flag_n) {
