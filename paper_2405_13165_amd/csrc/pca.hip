@@ -137,9 +137,20 @@ __device__ inline double pca_code(const PcaArgs &a, int32_t j) {
   const int k = a.kind ? (int)a.kind[j] : 0;
   return (double)(16 * ((k >= 0 && k <= 2) ? k : 3));
 }
+// The tile's neighbours in LDS as two arrays of 16-byte records, (x, y) and
+// (z, code): the two reads of a neighbour each start at one of 8 offsets in a
+// 128-byte bank row (32-byte records start at one of 4, and the lanes of a
+// read collide in the banks twice as often).
+struct PcaRec {
+  const double2 *xy, *zc;
+  __device__ double4 operator[](int s) const {
+    const double2 p = xy[s], q = zc[s];
+    return make_double4(p.x, p.y, q.x, q.y);
+  }
+};
 struct PcaTile {   // staged in LDS, addressed by slot[]
   static constexpr bool kQuads = true;
-  const double4 *sp;
+  PcaRec sp;
   const uint16_t *slot;
   __device__ double4 operator()(const PcaArgs &, int64_t k) const { return sp[slot[k]]; }
 };
@@ -231,7 +242,7 @@ __global__ void __launch_bounds__(kTileRows * kTeam) k_pca_tile(PcaArgs a, const
                                                                 const int32_t *__restrict__ tu,
                                                                 const uint16_t *__restrict__ slot, int64_t tile0,
                                                                 int cap) {
-  extern __shared__ double4 s_pos[];
+  extern __shared__ double2 s_rec[];  // (x, y)[cap], then (z, code)[cap]
   const int64_t tl = xcd_block(blockIdx.x, gridDim.x);
   const int64_t u0 = toff[tile0 + tl];
   const int cnt = (int)(toff[tile0 + tl + 1] - u0);
@@ -239,7 +250,8 @@ __global__ void __launch_bounds__(kTileRows * kTeam) k_pca_tile(PcaArgs a, const
   if (staged) {
     for (int s = threadIdx.x; s < cnt; s += blockDim.x) {
       const int32_t j = tu[u0 + s];
-      s_pos[s] = make_double4(a.x[j], a.y[j], a.z[j], pca_code(a, j));
+      s_rec[s] = make_double2(a.x[j], a.y[j]);
+      s_rec[cap + s] = make_double2(a.z[j], pca_code(a, j));
     }
   }
   __syncthreads();
@@ -247,7 +259,7 @@ __global__ void __launch_bounds__(kTileRows * kTeam) k_pca_tile(PcaArgs a, const
   const int64_t r = tl * kTileRows + team;
   if (r >= a.nrows) return;
   const int32_t i = a.sched[r];
-  if (staged) pca_row(a, i, lane, PcaTile{s_pos, slot});
+  if (staged) pca_row(a, i, lane, PcaTile{PcaRec{s_rec, s_rec + cap}, slot});
   else pca_row(a, i, lane, PcaGlobal{});
 }
 
