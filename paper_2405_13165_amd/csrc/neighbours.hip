@@ -800,18 +800,23 @@ __global__ void __launch_bounds__(kBlock) k_tile_entries(TileGroups tg, const in
   ent[t] = (int32_t)e;
 }
 
-// One block per tile: collect the distinct indices of the tile's entries in
-// an LDS hash set, sort only those (each one's rank is the number of smaller
-// ones), write them to uniq[ent_off[t] ...], then slot[] = rank of col[] in
-// the sorted list (binary search) for every entry;
-// cnt[t] = number of distinct indices.  The result does not depend on the
-// order of the hash insertions.
-constexpr int kHashSize = 2 * kTileEntries;  // load factor <= 1/2: probes end
-static_assert((kHashSize & (kHashSize - 1)) == 0, "hash size must be a power of two");
+// One block per tile.  The tile's distinct indices go into an LDS hash set
+// (open addressing, linear probing); a new key also takes the next place in
+// ulist (one counter update per wave) and records where it sits in the
+// table.  The distinct indices are ranked by counting (rank = number of
+// smaller distinct indices), each rank is kept beside its key, the sorted list
+// is written to uniq[ent_off[t] ...], and each entry's slot is the rank of its
+// index, read at the table position its insertion found; cnt[t] = number of
+// distinct indices.  Each wave takes whole rows (w, w + 8, ...), a lane at
+// most two entries of each (rows hold at most kTileBandRow = 128 entries):
+// its column indices are all requested at once and stay in registers, with
+// their table positions, until the slots are written.  The result does not
+// depend on the order of the insertions.
+constexpr int kHashBits = 12;
+constexpr int kHashSize = 1 << kHashBits;  // >= kTileEntries >= distinct keys: every probe ends
+static_assert(kHashSize >= kTileEntries, "the hash set must hold every entry of a tile");
 
-__device__ inline int hash_slot(int32_t j) {
-  return (int)(((uint32_t)j * 2654435761u) >> (32 - 13)) & (kHashSize - 1);
-}
+__device__ inline int hash_slot(int32_t j) { return (int)(((uint32_t)j * 2654435761u) >> (32 - kHashBits)); }
 
 __global__ void __launch_bounds__(kTileThreads) k_tile_unique(TileGroups tg, const int64_t *__restrict__ row_ptr,
                                                               const int32_t *__restrict__ col,
@@ -820,101 +825,116 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_unique(TileGroups tg, con
                                                               uint16_t *__restrict__ slot,
                                                               int32_t *__restrict__ uniq, int32_t *__restrict__ cnt,
                                                               int32_t *__restrict__ grp_max) {
-  static_assert(kHashSize == 1 << 13, "hash_slot takes 13 bits");
+  constexpr int NW = kTileThreads / 64;
   __shared__ int32_t hkey[kHashSize];
-  __shared__ __attribute__((aligned(16))) int32_t ulist[kTileEntries];
+  __shared__ uint16_t hrank[kHashSize];
+  __shared__ __attribute__((aligned(16))) int32_t ulist[kTileEntries];  // distinct indices, then sorted
+  __shared__ uint16_t upos[kTileEntries];                                // table position of ulist[s]
   __shared__ int64_t rbase[kTileRows];
-  __shared__ int32_t rloc[kTileRows + 1];
+  __shared__ int32_t rlen[kTileRows];
   __shared__ int32_t ucount;
   const int64_t t = blockIdx.x;
   const int q = tile_group(tg, t);
   const int64_t r0 = (t - tg.tile_start[q]) * kTileRows;
   const int R = (int)min((int64_t)kTileRows, tg.nrows[q] - r0);
-  const int tid = threadIdx.x;
-  if (tid < 64) {
-    int len = 0;
-    if (tid < R) {
-      const int32_t i = grouped[tg.row_start[q] + r0 + tid];
-      rbase[tid] = row_ptr[i];
-      len = (int)(row_ptr[i + 1] - row_ptr[i]);
-    }
-    int inc = len;  // inclusive wave scan
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int v = __shfl_up(inc, o, 64);
-      if (tid >= o) inc += v;
-    }
-    if (tid < kTileRows) rloc[tid + 1] = inc;
-    if (tid == 0) rloc[0] = 0;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  if (tid < R) {
+    const int32_t i = grouped[tg.row_start[q] + r0 + tid];
+    rbase[tid] = row_ptr[i];
+    rlen[tid] = (int)(row_ptr[i + 1] - row_ptr[i]);  // <= kTileBandRow: tiled rows
   }
   for (int h = tid; h < kHashSize; h += kTileThreads) hkey[h] = -1;
   if (tid == 0) ucount = 0;
   __syncthreads();
-  const int E = rloc[R];  // <= kTileEntries: tiled rows hold at most kTileBandRow entries
-  auto row_of = [&](int e) {  // row r with rloc[r] <= e < rloc[r+1]
-    int lo = 0, hi = R - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (rloc[mid] <= e) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-  };
-  // 1. distinct indices
-  for (int e = tid; e < E; e += kTileThreads) {
-    const int r = row_of(e);
-    const int32_t j = col[rbase[r] + (e - rloc[r])];
-    int h = hash_slot(j);
-    while (true) {
-      const int32_t prev = atomicCAS(&hkey[h], -1, j);
-      if (prev == -1) {
-        ulist[atomicAdd(&ucount, 1)] = j;
-        break;
+  // 1. distinct indices; entry c of a lane: row wave + NW (c / 2), entry lane + 64 (c % 2)
+  static_assert(kTileRows == 4 * NW && kTileBandRow == 128, "four rows per wave, two entries per lane and row");
+  constexpr int kC = 8;
+  int32_t jj[kC];
+  int hh[kC];
+#pragma unroll
+  for (int c = 0; c < kC; ++c) {
+    const int r = wave + NW * (c >> 1), e = lane + 64 * (c & 1);
+    jj[c] = (r < R && e < rlen[r]) ? col[rbase[r] + e] : -1;
+  }
+#pragma unroll
+  for (int c = 0; c < kC; ++c) {
+    {
+      const int32_t j = jj[c];
+      bool fresh = false;
+      int h = 0;
+      if (j >= 0) {
+        h = hash_slot(j);
+        while (true) {
+          const int32_t prev = atomicCAS(&hkey[h], -1, j);
+          if (prev == -1) {
+            fresh = true;
+            break;
+          }
+          if (prev == j) break;
+          h = (h + 1) & (kHashSize - 1);
+        }
       }
-      if (prev == j) break;
-      h = (h + 1) & (kHashSize - 1);
+      hh[c] = h;
+      const uint64_t m = __ballot(fresh);
+      int ub = 0;
+      if (lane == 0 && m) ub = atomicAdd(&ucount, __popcll(m));
+      ub = __shfl(ub, 0, 64);
+      if (fresh) {
+        const int s = ub + __popcll(m & ((1ull << lane) - 1));
+        ulist[s] = j;
+        upos[s] = (uint16_t)h;
+      }
     }
   }
   __syncthreads();
   const int U = ucount;
   // 2. rank of each distinct index = number of smaller distinct indices; the
   // list is read four at a time (padded to a multiple of four), every lane
-  // of a wave reading the same address (an LDS broadcast), no barrier per
-  // step.  The sorted list goes to the hash table's storage, free now.
+  // of a wave reading the same address (an LDS broadcast).  The ranks go
+  // beside the keys, and (after a barrier) the list is sorted in place.
   const int U4 = (U + 3) & ~3;
   for (int s = U + tid; s < U4; s += kTileThreads) ulist[s] = 0x7fffffff;
   __syncthreads();
-  int32_t *sorted = hkey;
-  for (int s = tid; s < U; s += kTileThreads) {
-    const int32_t v = ulist[s];
-    int r = 0;
-    const int4 *l4 = reinterpret_cast<const int4 *>(ulist);
-    for (int c = 0; c < U4 / 4; ++c) {
-      const int4 w4 = l4[c];
-      r += (w4.x < v) + (w4.y < v) + (w4.z < v) + (w4.w < v);
+  constexpr int kPer = kTileEntries / kTileThreads;
+  int32_t vv[kPer];
+  int rr[kPer];
+#pragma unroll
+  for (int c = 0; c < kPer; ++c) {
+    const int s = tid + c * kTileThreads;
+    rr[c] = -1;
+    vv[c] = 0;
+    if (s < U) {
+      const int32_t v = ulist[s];
+      int r = 0;
+      const int4 *l4 = reinterpret_cast<const int4 *>(ulist);
+      for (int c4 = 0; c4 < U4 / 4; ++c4) {
+        const int4 w4 = l4[c4];
+        r += (w4.x < v) + (w4.y < v) + (w4.z < v) + (w4.w < v);
+      }
+      vv[c] = v;
+      rr[c] = r;
+      hrank[upos[s]] = (uint16_t)r;
     }
-    sorted[r] = v;
   }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < kPer; ++c)
+    if (rr[c] >= 0) ulist[rr[c]] = vv[c];
   __syncthreads();
   // 3. the sorted distinct indices
   const int64_t ubase = ent_off[t];
-  for (int s = tid; s < U; s += kTileThreads) uniq[ubase + s] = sorted[s];
+  for (int s = tid; s < U; s += kTileThreads) uniq[ubase + s] = ulist[s];
   if (tid == 0) {
     cnt[t] = U;
     atomicMax(&grp_max[q], U);
   }
-  // 4. slots: rank of each entry in the sorted list (present, so the lower
-  // bound is an exact match)
-  for (int e = tid; e < E; e += kTileThreads) {
-    const int r = row_of(e);
-    const int64_t k = rbase[r] + (e - rloc[r]);
-    const int32_t j = col[k];
-    int lo = 0, hi = U - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (sorted[mid] < j) lo = mid + 1; else hi = mid;
+  // 4. slots: the rank kept beside each entry's index
+#pragma unroll
+  for (int c = 0; c < kC; ++c)
+    if (jj[c] >= 0) {
+      const int r = wave + NW * (c >> 1), e = lane + 64 * (c & 1);
+      slot[rbase[r] + e] = hrank[hh[c]];
     }
-    slot[k] = (uint16_t)lo;
-  }
 }
 
 // uniq (at the entry offsets) -> tile_u (at the list offsets)
