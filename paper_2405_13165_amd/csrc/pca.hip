@@ -22,6 +22,7 @@ using namespace gfdm_dev;
 namespace {
 constexpr int kBlock = 256;
 constexpr int kTeam = 4;
+static_assert(kTeam == 4, "a team writes its row's 64-byte record as 16 bytes per lane");
 
 // Symmetric 3x3 eigen-decomposition by Jacobi rotations (each rotation
 // annihilates one off-diagonal entry; sweeps until the off-diagonal mass is
