@@ -28,6 +28,7 @@ using namespace gfdm_dev;
 namespace {
 constexpr int kBlock = 256;
 constexpr int kQrBlock = 64;
+constexpr size_t kQrLdsMax = 48 * 1024;  // the QR panel goes to LDS up to this size
 constexpr int kQrStride = 15;  // per neighbour: 10 columns, 4 targets, sqrt(w)
 
 struct WArgs {
@@ -757,11 +758,14 @@ __device__ inline double wave_sum(double v) {
 }
 
 // Householder QR of A = sqrt(W) M for the queued particles: one wave each.
-// Columns live in a per-block slice of global scratch (column-major, n rows).
-template <int OUT, bool FUSED, bool FASTW>
+// Columns (column-major, n rows) live in LDS where the longest row fits
+// (LDSP: the reflections' dependent reads and updates stay on chip), else in
+// a per-block slice of global scratch.
+template <int OUT, bool FUSED, bool FASTW, bool LDSP>
 __global__ void __launch_bounds__(kQrBlock) k_weights_qr(WArgs a, double *panels, int64_t slice) {
+  extern __shared__ double s_panel[];
   const int lane = threadIdx.x;
-  double *A = panels + (int64_t)blockIdx.x * slice;
+  double *A = LDSP ? s_panel : panels + (int64_t)blockIdx.x * slice;
   __shared__ double R[10][10];
   __shared__ double vtv[10];
   __shared__ double zt[4][10];
@@ -1131,12 +1135,28 @@ gf_status weights_common(gf_ctx *ctx, const gf_particles *p, const gf_nbr *nbr, 
   }
   // fallback queue (sized on the device; the grid loops over it)
   ProfScope prof_qr(ctx, "weights_qr_fallback");
-  if (!fused) {
-    if (f32) hipLaunchKernelGGL((k_weights_qr<GF_F32, false, true>), dim3(qr_blocks), dim3(kQrBlock), 0, ctx->stream, a, ws.qr, slice);
-    else hipLaunchKernelGGL((k_weights_qr<GF_F64, false, false>), dim3(qr_blocks), dim3(kQrBlock), 0, ctx->stream, a, ws.qr, slice);
-  } else {
-    if (f32) hipLaunchKernelGGL((k_weights_qr<GF_F32, true, true>), dim3(qr_blocks), dim3(kQrBlock), 0, ctx->stream, a, ws.qr, slice);
-    else hipLaunchKernelGGL((k_weights_qr<GF_F64, true, false>), dim3(qr_blocks), dim3(kQrBlock), 0, ctx->stream, a, ws.qr, slice);
+  {
+    const size_t lds = sizeof(double) * (size_t)slice;
+    const bool ldsp = lds <= kQrLdsMax;
+    const dim3 qg(qr_blocks), qb(kQrBlock);
+    const size_t ql = ldsp ? lds : 0;
+    if (!fused) {
+      if (f32) {
+        if (ldsp) hipLaunchKernelGGL((k_weights_qr<GF_F32, false, true, true>), qg, qb, ql, ctx->stream, a, ws.qr, slice);
+        else hipLaunchKernelGGL((k_weights_qr<GF_F32, false, true, false>), qg, qb, ql, ctx->stream, a, ws.qr, slice);
+      } else {
+        if (ldsp) hipLaunchKernelGGL((k_weights_qr<GF_F64, false, false, true>), qg, qb, ql, ctx->stream, a, ws.qr, slice);
+        else hipLaunchKernelGGL((k_weights_qr<GF_F64, false, false, false>), qg, qb, ql, ctx->stream, a, ws.qr, slice);
+      }
+    } else {
+      if (f32) {
+        if (ldsp) hipLaunchKernelGGL((k_weights_qr<GF_F32, true, true, true>), qg, qb, ql, ctx->stream, a, ws.qr, slice);
+        else hipLaunchKernelGGL((k_weights_qr<GF_F32, true, true, false>), qg, qb, ql, ctx->stream, a, ws.qr, slice);
+      } else {
+        if (ldsp) hipLaunchKernelGGL((k_weights_qr<GF_F64, true, false, true>), qg, qb, ql, ctx->stream, a, ws.qr, slice);
+        else hipLaunchKernelGGL((k_weights_qr<GF_F64, true, false, false>), qg, qb, ql, ctx->stream, a, ws.qr, slice);
+      }
+    }
   }
   GF_LAUNCH_CHECK(ctx);
   if (stats && !fixed) {
