@@ -236,6 +236,26 @@ def test_weights_qr_fallback_matches(ctx, g):
     assert oracle.operator_error(_np(w), w_o, rp).max() <= 1e-11
 
 
+def test_weights_qr_fallback_long_rows(ctx, g):
+    # rows of up to ~580 neighbours (h = 5.2 spacings): the QR panel of the
+    # longest row exceeds the fallback's LDS limit, so the queued rows take the
+    # panel in global scratch; the rows with more than 128 neighbours also run
+    # the untiled stencil launch before they are queued
+    d = W.plain_cube(n_axis=12)
+    d["h"] = np.full_like(d["h"], 5.2 * 0.01)
+    p, nb, rp, col = _nbr_equal(ctx, g, d)
+    lens = np.diff(rp)
+    assert lens.max() * 15 * 8 > 48 * 1024 and (lens > 128).sum() > 100
+    w_o, st_o, _ = oracle.gfdm_weights(d, rp, col)
+    for wt, tol in ((g.GF_F64, 1e-11), (g.GF_F32, 1e-6)):
+        status = torch.empty(p.n, dtype=torch.int8, device=ctx.device)
+        w = g.gfdm_weights(ctx, p, nb, g.GF_BATCHED, wt, params=g.ls_params(kappa_max=1e-30), status=status)
+        st = _np(status)
+        assert np.all((st == 1) | (st == 3))
+        assert _status_match(st, st_o)
+        assert oracle.operator_error(_np(w).astype(np.float64), w_o, rp).max() <= tol
+
+
 def test_weights_degenerate_rows(ctx, g):
     # coplanar 3D neighbourhoods are rank deficient (status 2); isolated
     # particles have too few neighbours (status 3); both get zero stencils
