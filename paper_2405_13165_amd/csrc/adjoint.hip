@@ -61,6 +61,31 @@ constexpr int adj_lds_doubles() {  // per team: reduction / moments / pivot row,
   return ((cmax(cmax(nmom<M>(), red_lanes(kT) * red_lanes(kT)), cmax(M + 1, 8 * M)) + 1) & ~1);
 }
 
+// Visit the entries k = lane, lane + T, ... of a row of n >= 1 entries at CSR
+// entry b, calling body(k, j, position of j, field value of j (FIELD)); the
+// column two steps ahead and the position (and field value) one step ahead
+// are in flight during the arithmetic.  Loads past the row's end read its
+// last entry (valid, never used), so every load is unconditional.
+template <int T, bool FIELD, class Body>
+__device__ inline void adj_walk(const AArgs &a, int64_t b, int n, int lane, Body &&body) {
+  const int kmax = n - 1;
+  int32_t jc = a.col[b + min(lane, kmax)];
+  int32_t jn = a.col[b + min(lane + T, kmax)];
+  double4 pc = a.pos[jc];
+  double uc = FIELD ? a.u[jc] : 0.0;
+#pragma unroll 1
+  for (int k = lane; k < n; k += T) {
+    const int32_t j = jc;
+    const double4 pj = pc;
+    const double uj = uc;
+    jc = jn;
+    pc = a.pos[jn];
+    if constexpr (FIELD) uc = a.u[jn];
+    jn = a.col[b + min(k + 2 * T, kmax)];
+    body(k, j, pj, uj);
+  }
+}
+
 template <int M, unsigned SEL>
 __device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane, double *sm) {
   constexpr int T = kT;
@@ -103,16 +128,14 @@ __device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane, dou
   double mom[NM];
 #pragma unroll
   for (int p = 0; p < NM; ++p) mom[p] = 0.0;
-  for (int k = lane; k < n; k += T) {
-    const int32_t j = a.col[b + k];
-    const double4 pj = a.pos[j];
+  adj_walk<T, false>(a, b, n, lane, [&](int, int32_t, const double4 &pj, double) {
     const double dx = pj.x - g.xi, dy = pj.y - g.yi, dz = pj.z - g.zi;
     double e, ir2;
     const double w = weight(pj.w, fma(dz, dz, fma(dy, dy, dx * dx)), e, ir2);
     double X, Y, Z;
     local_raw<M>(g, dx, dy, dz, X, Y, Z);
     moments_add_raw<M>(mom, w, X, Y, Z);
-  }
+  });
   team_moment_sum<M, T>(mom, lane, sm);
   // ---- G^{-1}
   double row[NR][M];
@@ -161,8 +184,8 @@ __device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane, dou
   // chatbar_js = dL / dc_js for the stencils the kernel forms (on a film the
   // tangential ones, s = 0, 1, of which the stored x, y, z stencils are the
   // combinations t1 c_0 + t2 c_1)
-  auto chatbar = [&](int32_t j, double cb[4]) {
-    const double du = (j != i) ? (a.u[j] - ui) : 0.0;
+  auto chatbar = [&](int32_t j, double uj, double cb[4]) {
+    const double du = (j != i) ? (uj - ui) : 0.0;
     if constexpr (M == 10) {
       cb[0] = yb[0] * du; cb[1] = yb[1] * du; cb[2] = yb[2] * du;
     } else {
@@ -179,15 +202,13 @@ __device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane, dou
   for (int s = 0; s < 4; ++s)
 #pragma unroll
     for (int r = 0; r < M; ++r) v[s][r] = 0.0;  // (entries outside SEL are never read)
-  for (int k = lane; k < n; k += T) {
-    const int32_t j = a.col[b + k];
-    const double4 pj = a.pos[j];
+  adj_walk<T, true>(a, b, n, lane, [&](int, int32_t j, const double4 &pj, double uj) {
     const double dx = pj.x - g.xi, dy = pj.y - g.yi, dz = pj.z - g.zi;
     double e, ir2;
     const double w = weight(pj.w, fma(dz, dz, fma(dy, dy, dx * dx)), e, ir2);
     double phi[M], cb[4];
     monomials<M>(g, dx, dy, dz, phi);
-    chatbar(j, cb);
+    chatbar(j, uj, cb);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       if (!((SEL >> s) & 1u)) continue;
@@ -195,7 +216,7 @@ __device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane, dou
 #pragma unroll
       for (int r = 0; r < M; ++r) v[s][r] = fma(cw, phi[r], v[s][r]);
     }
-  }
+  });
   // ---- mu_s = G^{-1} v_s, row r on the lane that owns it
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
@@ -230,17 +251,30 @@ __device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane, dou
   }
   // ---- pass 3: dbar_j per entry
   double own[3] = {0.0, 0.0, 0.0};  // this lane's share of sum_j dbar(i, j)
-  for (int k = lane; k < n; k += T) {
-    const int32_t j = a.col[b + k];
-    double *out = a.dbar + 3 * (ob + k);
-    if (j == i) { out[0] = 0.0; out[1] = 0.0; out[2] = 0.0; continue; }
-    const double4 pj = a.pos[j];
+  // each entry's dbar is stored one step late, at the start of the next
+  // step: a load and a store in flight count against one counter, and the
+  // wait for the next entry's column would otherwise wait for the store
+  double po[3] = {0.0, 0.0, 0.0};
+  int kp = -1;
+  auto flush_prev = [&]() {
+    if (kp >= 0) {
+      double *out = a.dbar + 3 * (ob + kp);
+      out[0] = po[0]; out[1] = po[1]; out[2] = po[2];
+    }
+  };
+  adj_walk<T, true>(a, b, n, lane, [&](int k, int32_t j, const double4 &pj, double uj) {
+    flush_prev();
+    kp = k;
+    if (j == i) {
+      po[0] = 0.0; po[1] = 0.0; po[2] = 0.0;
+      return;
+    }
     const double dx = pj.x - g.xi, dy = pj.y - g.yi, dz = pj.z - g.zi;
     double e, ir2;
     const double w = weight(pj.w, fma(dz, dz, fma(dy, dy, dx * dx)), e, ir2);
     double phi[M], cb[4];
     monomials<M>(g, dx, dy, dz, phi);
-    chatbar(j, cb);
+    chatbar(j, uj, cb);
     double wb = 0.0, pb[M];
 #pragma unroll
     for (int q = 0; q < M; ++q) pb[q] = 0.0;
@@ -257,13 +291,14 @@ __device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane, dou
     double dd[3];
     monomials_grad_dot<M>(g, dx, dy, dz, pb, dd);
     const double f = wb * (-2.0 * a.wf.alpha * e * ir2);
-    out[0] = dd[0] + f * dx;
-    out[1] = dd[1] + f * dy;
-    out[2] = dd[2] + f * dz;
-    own[0] += out[0];
-    own[1] += out[1];
-    own[2] += out[2];
-  }
+    po[0] = dd[0] + f * dx;
+    po[1] = dd[1] + f * dy;
+    po[2] = dd[2] + f * dz;
+    own[0] += po[0];
+    own[1] += po[1];
+    own[2] += po[2];
+  });
+  flush_prev();
   // x_i loses every dbar(i, j), whether or not (j, i) is listed
 #pragma unroll
   for (int c = 0; c < 3; ++c) own[c] = team_sum(own[c], T);
@@ -274,7 +309,7 @@ __device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane, dou
 }
 
 template <int M, unsigned SEL>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(M == 6 && SEL == 8u ? 4 : 1))) k_adjoint_x(AArgs a) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SEL == 8u ? (M == 6 ? 4 : 3) : 1))) k_adjoint_x(AArgs a) {
   __shared__ double smem[(kBlock / kT) * adj_lds_doubles<M>()];
   const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t team = gt / kT;
