@@ -132,7 +132,11 @@ constexpr int kApplyCap = 2048;
 // the first sum gathered through the reverse-edge map (entry (i,j) sits at
 // rev[k] for the entry k = (j,i) of row j); an entry of row j without a twin
 // (towards a ghost particle, which has no row) adds only its own term.
-// One team of kAdjTeam lanes per row j (the lanes stride over the row).
+// One team of kAdjTeam lanes per row j (the lanes stride over the row).  The
+// walk is software-pipelined: an entry's column and twin position are read
+// two steps ahead, its two stencils and the seeds ybar_i one step ahead; the
+// loads past the row's end read its last entry and an entry without a twin
+// reads the stencil record 0 (valid, weighted zero), so no load is skipped.
 constexpr int kAdjTeam = 8;
 template <typename WT>
 __global__ void __launch_bounds__(kBlock) k_apply_adjoint(const int64_t *__restrict__ row_ptr,
@@ -150,16 +154,35 @@ __global__ void __launch_bounds__(kBlock) k_apply_adjoint(const int64_t *__restr
   double yj[4];
   for (int q = 0; q < K; ++q) yj[q] = ybar[(int64_t)q * n + j];
   double acc = 0.0;
-#pragma unroll 4
-  for (int64_t k = row_ptr[j] + lane; k < row_ptr[j + 1]; k += kAdjTeam) {
-    const int32_t i = col[k];
-    const int32_t kr = rev[k];  // < 0: (i, j) is not listed (i a ghost particle without a row)
-    if (i == j) continue;
-    double cin[4] = {0.0, 0.0, 0.0, 0.0}, cout_[4];
-    if (kr >= 0) W4<WT>::load(w, kr, cin);  // c_ij (row i, column j)
-    W4<WT>::load(w, k, cout_);              // c_ji (row j, column i)
-    for (int q = 0; q < K; ++q)
-      acc += (kr >= 0 ? cin[sel[q]] * ybar[(int64_t)q * n + i] : 0.0) - cout_[sel[q]] * yj[q];
+  const int64_t b = row_ptr[j], e = row_ptr[j + 1], kl = e - 1;
+  // stage 2 (two ahead): column and twin; stage 1 (one ahead): stencils and seeds
+  auto twin = [&](int64_t k, int32_t &i, int32_t &kr) {
+    const int64_t kk = min(k, kl);
+    i = col[kk];
+    kr = rev[kk];  // < 0: (i, j) is not listed (i a ghost particle without a row)
+  };
+  double cin[4], cout_[4], yi[4];
+  auto fetch = [&](int64_t k, int32_t i, int32_t kr) {
+    W4<WT>::load(w, kr >= 0 ? kr : 0, cin);  // c_ij (row i, column j)
+    W4<WT>::load(w, min(k, kl), cout_);      // c_ji (row j, column i)
+    for (int q = 0; q < K; ++q) yi[q] = ybar[(int64_t)q * n + i];
+  };
+  int32_t i1, kr1, i2, kr2;
+  twin(b + lane, i1, kr1);
+  twin(b + lane + kAdjTeam, i2, kr2);
+  fetch(b + lane, i1, kr1);
+#pragma unroll 1
+  for (int64_t k = b + lane; k < e; k += kAdjTeam) {
+    const int32_t i = i1, kr = kr1;
+    double ci[4], co[4], yv[4];
+    for (int s = 0; s < 4; ++s) { ci[s] = cin[s]; co[s] = cout_[s]; }
+    for (int q = 0; q < K; ++q) yv[q] = yi[q];
+    i1 = i2;
+    kr1 = kr2;
+    fetch(k + kAdjTeam, i1, kr1);
+    twin(k + 2 * kAdjTeam, i2, kr2);
+    if (i != j)
+      for (int q = 0; q < K; ++q) acc += (kr >= 0 ? ci[sel[q]] * yv[q] : 0.0) - co[sel[q]] * yj[q];
   }
   acc = team_sum(acc, kAdjTeam);
   if (lane == 0) ubar[j] = acc;
