@@ -344,13 +344,34 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_gather(const int32_t *__rest
   const int32_t j = grouped[t];
   const int64_t g0 = grow_ptr[t], g1 = grow_ptr[t + 1];
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-#pragma unroll 4
-  for (int64_t gk = g0 + lane; gk < g1; gk += kT) {
-    const int32_t tw = grev[gk];
-    if (tw < 0) continue;
-    s0 += dbar[3 * (int64_t)tw];
-    s1 += dbar[3 * (int64_t)tw + 1];
-    s2 += dbar[3 * (int64_t)tw + 2];
+  if (g1 > g0) {
+    // software-pipelined: the twin position two steps ahead, its dbar one step
+    // ahead; reads past the row's end take its last entry, an entry without a
+    // twin reads record 0 (both valid, neither added)
+    const int64_t gl = g1 - 1;
+    auto twin = [&](int64_t gk) { return grev[min(gk, gl)]; };
+    auto load = [&](int32_t tw, double &a, double &b, double &c) {
+      const int64_t q = 3 * (int64_t)(tw >= 0 ? tw : 0);
+      a = dbar[q];
+      b = dbar[q + 1];
+      c = dbar[q + 2];
+    };
+    int32_t t1 = twin(g0 + lane), t2 = twin(g0 + lane + kT);
+    double d0, d1, d2;
+    load(t1, d0, d1, d2);
+#pragma unroll 1
+    for (int64_t gk = g0 + lane; gk < g1; gk += kT) {
+      const int32_t tw = t1;
+      const double e0 = d0, e1 = d1, e2 = d2;
+      t1 = t2;
+      load(t1, d0, d1, d2);
+      t2 = twin(gk + 2 * kT);
+      if (tw >= 0) {
+        s0 += e0;
+        s1 += e1;
+        s2 += e2;
+      }
+    }
   }
   s0 = team_sum(s0, kT);
   s1 = team_sum(s1, kT);
