@@ -524,19 +524,32 @@ __global__ void __launch_bounds__(kSearchBlock) __attribute__((amdgpu_waves_per_
           if (lane == 0) s_pref[w][0] = 0;
           wave_fence();
           const int C = __shfl(inc, 63, 64);
+          // candidate c's sorted position (c < C): its cell is the largest k
+          // with s_pref[k] <= c
+          auto cand = [&](int c) {
+            int k = 0;
+#pragma unroll
+            for (int step = 32; step > 0; step >>= 1)
+              if (k + step < 64 && s_pref[w][k + step] <= c) k += step;
+            return s_rb[w][k] + (c - s_pref[w][k]);
+          };
+          // the next batch's candidates are requested while this batch is tested
+          double4 qn = make_double4(0.0, 0.0, 0.0, 0.0);
+          int32_t qjn = 0;
+          if (lane < C) {
+            const int32_t t = cand(lane);
+            qn = sp[t];
+            if (MODE == 1 || stage) qjn = order[t];
+          }
           for (int cb = 0; cb < C; cb += 64) {
             const int c = cb + lane;
             const bool cv = c < C;
-            double4 q = make_double4(0.0, 0.0, 0.0, 0.0);
-            int32_t qj = 0;
-            if (cv) {
-              int k = 0;  // cell of candidate c: largest k with s_pref[k] <= c
-#pragma unroll
-              for (int step = 32; step > 0; step >>= 1)
-                if (k + step < 64 && s_pref[w][k + step] <= c) k += step;
-              const int32_t t = s_rb[w][k] + (c - s_pref[w][k]);
-              q = sp[t];
-              if (MODE == 1 || stage) qj = order[t];
+            const double4 q = qn;
+            const int32_t qj = qjn;
+            if (c + 64 < C) {
+              const int32_t t = cand(c + 64);
+              qn = sp[t];
+              if (MODE == 1 || stage) qjn = order[t];
             }
             // two rows per step: independent chains for the FP64 pipeline
             for (int r = 0; r < nr; r += 2) {
