@@ -308,6 +308,8 @@ __device__ void adjoint_row(const AArgs &a, int32_t i, int64_t ob, int lane, dou
   }
 }
 
+// The Laplacian-only kernels (the common case) are held at 4 (film) and 3
+// (3D) waves per SIMD, a few registers spilled; the others take what they need.
 template <int M, unsigned SEL>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SEL == 8u ? (M == 6 ? 4 : 3) : 1))) k_adjoint_x(AArgs a) {
   __shared__ double smem[(kBlock / kT) * adj_lds_doubles<M>()];

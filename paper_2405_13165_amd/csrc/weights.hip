@@ -326,7 +326,7 @@ __device__ inline void for_neighbours(const F &fetch, int64_t b, int n, int k0, 
 }
 
 // What a row reads before its neighbours: its extent, position, support,
-// frame and field value, and (tiled rows) the slot quads of pass 1.  The tile
+// frame and field value, and (tiled rows) the slot groups of pass 1.  The tile
 // kernel loads these before it stages the tile, so that their latency (three
 // dependent reads: schedule, row extent, slots) overlaps the staging.
 // Pass 1 of the tiled kernels reads its slots in aligned groups of G: pairs
@@ -339,24 +339,24 @@ constexpr int slot_group() { return T >= 8 ? 2 : 4; }
 template <int G>
 using SlotVec = typename std::conditional<G == 2, ushort2, ushort4>::type;
 
-template <int T, bool QUADS>
+template <int T, bool SLOTS>
 struct RowPre {
   int32_t i;
   int64_t b;
   int n;
   RowGeom g;
   double ui;
-  SlotVec<slot_group<T>()> ss[QUADS ? kTileBandRow / (slot_group<T>() * T) + 1 : 1];
+  SlotVec<slot_group<T>()> ss[SLOTS ? kTileBandRow / (slot_group<T>() * T) + 1 : 1];
 };
 
-template <int M, int T, bool FUSED, bool QUADS>
-__device__ inline void row_pre(const WArgs &a, const uint16_t *slot, int32_t i, int lane, RowPre<T, QUADS> &p) {
+template <int M, int T, bool FUSED, bool SLOTS>
+__device__ inline void row_pre(const WArgs &a, const uint16_t *slot, int32_t i, int lane, RowPre<T, SLOTS> &p) {
   p.i = i;
   p.b = a.row_ptr[i];
   p.n = (int)(a.row_ptr[i + 1] - p.b);
   row_geom<M>(a, i, p.g);
   p.ui = FUSED ? a.u[i] : 0.0;
-  if constexpr (QUADS) {
+  if constexpr (SLOTS) {
     // lane l takes the aligned groups of slots q0 + l, q0 + l + T, ...
     constexpr int G = slot_group<T>();
     constexpr int kQ1 = kTileBandRow / (G * T) + 1;
@@ -705,7 +705,8 @@ k_weights_tile(WArgs a, TileArgs ta, const uint16_t *__restrict__ slot) {
   const int team = threadIdx.x / T, lane = threadIdx.x % T;
   const int64_t r = tl * kTileRows + team;
   const bool live = r < a.nrows;
-  // (narrower teams hold more quads per lane: they load them in pass 1)
+  // (4-lane teams would hold more slot groups per lane than their registers
+  // allow: they load them in pass 1)
   RowPre<T, (T >= 8)> pre;
   if (live) row_pre<M, T, FUSED, (T >= 8)>(a, slot, a.sched[r], lane, pre);
   // uni: every staged support equals the first (then also each row's own, as
