@@ -138,15 +138,18 @@ __device__ inline double pca_code(const PcaArgs &a, int32_t j) {
   const int k = a.kind ? (int)a.kind[j] : 0;
   return (double)(16 * ((k >= 0 && k <= 2) ? k : 3));
 }
-// The tile's neighbours in LDS as two arrays of 16-byte records, (x, y) and
-// (z, code): the two reads of a neighbour each start at one of 8 offsets in a
-// 128-byte bank row (32-byte records start at one of 4, and the lanes of a
-// read collide in the banks twice as often).
+// The tile's neighbours in LDS as (x, y) 16-byte records, z and the kind
+// code in arrays of their own: 25 bytes per neighbour instead of a 32-byte
+// record, so that more blocks fit a CU (the kernel is bound by latency and
+// LDS-limited in occupancy), and the (x, y) reads start at one of 8 offsets
+// in a 128-byte bank row.
 struct PcaRec {
-  const double2 *xy, *zc;
+  const double2 *xy;
+  const double *zz;
+  const uint8_t *cc;
   __device__ double4 operator[](int s) const {
-    const double2 p = xy[s], q = zc[s];
-    return make_double4(p.x, p.y, q.x, q.y);
+    const double2 p = xy[s];
+    return make_double4(p.x, p.y, zz[s], (double)cc[s]);
   }
 };
 struct PcaTile {   // staged in LDS, addressed by slot[]
@@ -243,7 +246,9 @@ __global__ void __launch_bounds__(kTileRows * kTeam) k_pca_tile(PcaArgs a, const
                                                                 const int32_t *__restrict__ tu,
                                                                 const uint16_t *__restrict__ slot, int64_t tile0,
                                                                 int cap) {
-  extern __shared__ double2 s_rec[];  // (x, y)[cap], then (z, code)[cap]
+  extern __shared__ double2 s_rec[];  // (x, y)[cap], then z[cap], then code[cap]
+  double *s_z = reinterpret_cast<double *>(s_rec + cap);
+  uint8_t *s_c = reinterpret_cast<uint8_t *>(s_z + cap);
   const int64_t tl = xcd_block(blockIdx.x, gridDim.x);
   const int64_t u0 = toff[tile0 + tl];
   const int cnt = (int)(toff[tile0 + tl + 1] - u0);
@@ -252,7 +257,8 @@ __global__ void __launch_bounds__(kTileRows * kTeam) k_pca_tile(PcaArgs a, const
     for (int s = threadIdx.x; s < cnt; s += blockDim.x) {
       const int32_t j = tu[u0 + s];
       s_rec[s] = make_double2(a.x[j], a.y[j]);
-      s_rec[cap + s] = make_double2(a.z[j], pca_code(a, j));
+      s_z[s] = a.z[j];
+      s_c[s] = (uint8_t)pca_code(a, j);
     }
   }
   __syncthreads();
@@ -260,7 +266,7 @@ __global__ void __launch_bounds__(kTileRows * kTeam) k_pca_tile(PcaArgs a, const
   const int64_t r = tl * kTileRows + team;
   if (r >= a.nrows) return;
   const int32_t i = a.sched[r];
-  if (staged) pca_row(a, i, lane, PcaTile{PcaRec{s_rec, s_rec + cap}, slot});
+  if (staged) pca_row(a, i, lane, PcaTile{PcaRec{s_rec, s_z, s_c}, slot});
   else pca_row(a, i, lane, PcaGlobal{});
 }
 
@@ -340,7 +346,7 @@ extern "C" gf_status gf_classify_pca(gf_ctx *ctx, const gf_particles *p, const g
     a.nrows = u.nrows;
     if (u.tiled) {
       const int cap = std::min(u.tile_max, tile_capacity(ctx, kPcaCap));
-      hipLaunchKernelGGL(k_pca_tile, dim3(grid_for(u.ntiles, 1)), dim3(kTileRows * kTeam), sizeof(double4) * cap,
+      hipLaunchKernelGGL(k_pca_tile, dim3(grid_for(u.ntiles, 1)), dim3(kTileRows * kTeam), (sizeof(double2) + sizeof(double) + 1) * (size_t)cap,
                          ctx->stream, a, same->tile_off, same->tile_u, same->slot, u.tile0, cap);
     } else {
       hipLaunchKernelGGL(k_pca_flags, dim3(grid_for(u.nrows * kTeam, kBlock)), dim3(kBlock), 0, ctx->stream, a);
