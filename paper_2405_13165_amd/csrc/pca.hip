@@ -1,10 +1,11 @@
 // Local PCA of every neighbourhood and the transition flags of Sec. 4.
 //
-// A team of kTeam lanes per particle.  Rows with at most 128 neighbours run
+// Rows with at most 128 neighbours get a team of kTeam lanes each and run
 // one neighbour tile per block: the tile's distinct neighbours (position and
 // kind) are staged in LDS and read through the tile slots, which each lane
 // loads in aligned quads, all before the first is used; rows with more
-// neighbours gather from global memory.  One pass accumulates the sums of
+// neighbours gather from global memory, with teams of kTeamWide lanes that
+// keep four entries each in flight.  One pass accumulates the sums of
 // the offsets d = x_j - x_i and of their products, and the covariance about
 // the centroid follows as sum d d^T - (sum d)(sum d)^T / n: offsets relative
 // to the particle itself keep an exactly planar neighbourhood exactly planar
@@ -24,50 +25,63 @@ constexpr int kBlock = 256;
 constexpr int kTeam = 4;
 static_assert(kTeam == 4, "a team writes its row's 64-byte record as 16 bytes per lane");
 
-// Symmetric 3x3 eigen-decomposition by Jacobi rotations (each rotation
-// annihilates one off-diagonal entry; sweeps until the off-diagonal mass is
-// negligible).  a: packed symmetric [a00 a01 a02 a11 a12 a22].
+// One Jacobi rotation in the (p, q) plane of a symmetric 3x3 matrix, r being
+// the third index: annihilates a_pq.  tan(phi) is the root of smaller
+// magnitude of t^2 + 2 t cot(2 phi) - 1 = 0, cot(2 phi) = (a_qq - a_pp) / (2 a_pq),
+// written as 2 a_pq sign(a_qq - a_pp) / (|a_qq - a_pp| + sqrt((a_qq - a_pp)^2 + 4 a_pq^2))
+// so that it takes one division and one square root; cos(phi) = 1 / sqrt(1 + t^2).
+// Only the entries the rotation changes are updated, a_pp and a_qq in the
+// form a_pp - t a_pq, a_qq + t a_pq; vp and vq are columns p and q of the
+// accumulated rotation.
+__device__ __forceinline__ void jacobi_rotate(double &app, double &aqq, double &apq, double &arp, double &arq,
+                                              double vp[3], double vq[3]) {
+  if (apq == 0.0) return;
+  const double d = aqq - app, two = 2.0 * apq;
+  const double r = sqrt(d * d + two * two);
+  const double den = fabs(d) + r;
+  if (!(den > 0.0)) return;  // both squares underflowed with d == 0: leave a_pq for the next sweep
+  const double t = copysign(1.0, d) * two / den;
+  const double c = rsqrt(1.0 + t * t);
+  const double s = t * c;
+  const double ta = t * apq;
+  app -= ta;
+  aqq += ta;
+  apq = 0.0;
+  const double xp = arp, xq = arq;
+  arp = c * xp - s * xq;
+  arq = s * xp + c * xq;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double up = vp[k], uq = vq[k];
+    vp[k] = c * up - s * uq;
+    vq[k] = s * up + c * uq;
+  }
+}
+
+// Symmetric 3x3 eigen-decomposition by cyclic Jacobi rotations over the
+// planes (0, 1), (0, 2), (1, 2), sweeping until the off-diagonal mass is
+// negligible.  lam: the diagonal at the end; V[k][c]: component k of the
+// eigenvector of lam[c].
 __device__ void sym3_eigen(double a00, double a01, double a02, double a11, double a12, double a22,
                            double lam[3], double V[3][3]) {
-  double A[3][3] = {{a00, a01, a02}, {a01, a11, a12}, {a02, a12, a22}};
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c) V[r][c] = (r == c) ? 1.0 : 0.0;
+  double v0[3] = {1.0, 0.0, 0.0}, v1[3] = {0.0, 1.0, 0.0}, v2[3] = {0.0, 0.0, 1.0};
   const double scale = sqrt(a00 * a00 + a11 * a11 + a22 * a22 + 2.0 * (a01 * a01 + a02 * a02 + a12 * a12));
   for (int sweep = 0; sweep < 32; ++sweep) {
-    double off = fabs(A[0][1]) + fabs(A[0][2]) + fabs(A[1][2]);
+    const double off = fabs(a01) + fabs(a02) + fabs(a12);
     if (off == 0.0 || off <= 1e-17 * scale) break;
-    for (int t = 0; t < 3; ++t) {
-      const int p = (t == 2) ? 1 : 0;
-      const int q = (t == 0) ? 1 : 2;
-      const double apq = A[p][q];
-      if (apq == 0.0) continue;
-      // tan of the rotation angle, smaller root of t^2 + 2 t cot(2phi) - 1 = 0
-      const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
-      const double tn = copysign(1.0, tau) / (fabs(tau) + sqrt(1.0 + tau * tau));
-      const double c = 1.0 / sqrt(1.0 + tn * tn);
-      const double s = tn * c;
-      for (int k = 0; k < 3; ++k) {
-        const double akp = A[k][p], akq = A[k][q];
-        A[k][p] = c * akp - s * akq;
-        A[k][q] = s * akp + c * akq;
-      }
-      for (int k = 0; k < 3; ++k) {
-        const double apk = A[p][k], aqk = A[q][k];
-        A[p][k] = c * apk - s * aqk;
-        A[q][k] = s * apk + c * aqk;
-      }
-      A[p][q] = 0.0;
-      A[q][p] = 0.0;
-      for (int k = 0; k < 3; ++k) {
-        const double vkp = V[k][p], vkq = V[k][q];
-        V[k][p] = c * vkp - s * vkq;
-        V[k][q] = s * vkp + c * vkq;
-      }
-    }
+    jacobi_rotate(a00, a11, a01, a02, a12, v0, v1);  // p, q, r = 0, 1, 2
+    jacobi_rotate(a00, a22, a02, a01, a12, v0, v2);  // p, q, r = 0, 2, 1
+    jacobi_rotate(a11, a22, a12, a01, a02, v1, v2);  // p, q, r = 1, 2, 0
   }
-  lam[0] = A[0][0];
-  lam[1] = A[1][1];
-  lam[2] = A[2][2];
+  lam[0] = a00;
+  lam[1] = a11;
+  lam[2] = a22;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    V[k][0] = v0[k];
+    V[k][1] = v1[k];
+    V[k][2] = v2[k];
+  }
 }
 
 struct PcaArgs {
@@ -134,10 +148,7 @@ __device__ void pca_finish(const PcaArgs &a, int32_t i, int n_int, int n_fs, dou
 
 // A neighbour as (x, y, z, 16 * kind code), the code being the kind 0..2 or 3
 // for anything else: the shift that counts it in its 16-bit field.
-__device__ inline double pca_code(const PcaArgs &a, int32_t j) {
-  const int k = a.kind ? (int)a.kind[j] : 0;
-  return (double)(16 * ((k >= 0 && k <= 2) ? k : 3));
-}
+__device__ inline double pca_code_of(int k) { return (double)(16 * ((k >= 0 && k <= 2) ? k : 3)); }
 // The tile's neighbours in LDS as (x, y) 16-byte records, z and the kind
 // code in arrays of their own: 25 bytes per neighbour instead of a 32-byte
 // record, so that more blocks fit a CU (the kernel is bound by latency and
@@ -156,18 +167,16 @@ struct PcaTile {   // staged in LDS, addressed by slot[]
   static constexpr bool kQuads = true;
   PcaRec sp;
   const uint16_t *slot;
-  __device__ double4 operator()(const PcaArgs &, int64_t k) const { return sp[slot[k]]; }
 };
-struct PcaGlobal {
+struct PcaGlobal {  // gathered from global memory
   static constexpr bool kQuads = false;
-  __device__ double4 operator()(const PcaArgs &a, int64_t k) const {
-    const int32_t j = a.col[k];
-    return make_double4(a.x[j], a.y[j], a.z[j], pca_code(a, j));
-  }
 };
 
-constexpr int kPq = 128 / (4 * kTeam) + 1;  // quads per lane for rows of at most 128 entries
-template <class F>
+// lanes per row for rows that gather from global memory (rows of more than
+// 128 neighbours): each lane keeps four entries in flight
+constexpr int kTeamWide = 16;
+
+template <int T, class F>
 __device__ void pca_row(const PcaArgs &a, int32_t i, int lane, const F &fetch) {
   const int64_t b = a.row_ptr[i], e = a.row_ptr[i + 1];
   const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
@@ -185,18 +194,19 @@ __device__ void pca_row(const PcaArgs &a, int32_t i, int lane, const F &fetch) {
     if (need_kinds) kinds += (uint64_t)1 << (int)pj.w;
   };
   if constexpr (F::kQuads) {
-    // entries 4q .. 4q+3 of the aligned quads q0 + lane, q0 + lane + kTeam, ...; a quad may reach
+    // entries 4q .. 4q+3 of the aligned quads q0 + lane, q0 + lane + T, ...; a quad may reach
     // up to three entries into the neighbouring rows (padded slot array): those are skipped
+    constexpr int kPq = 128 / (4 * T) + 1;  // quads per lane for rows of at most 128 entries
     const int64_t q0 = (b >> 2) + lane;
     ushort4 ss[kPq];
 #pragma unroll
     for (int j = 0; j < kPq; ++j) {
-      const int64_t k = 4 * (q0 + j * kTeam);
+      const int64_t k = 4 * (q0 + j * T);
       if (k < e) ss[j] = *reinterpret_cast<const ushort4 *>(fetch.slot + k);
     }
 #pragma unroll
     for (int j = 0; j < kPq; ++j) {
-      const int64_t k = 4 * (q0 + j * kTeam);
+      const int64_t k = 4 * (q0 + j * T);
       if (k < e) {
         if (k >= b) visit(fetch.sp[ss[j].x]);
         if (k + 1 >= b && k + 1 < e) visit(fetch.sp[ss[j].y]);
@@ -205,26 +215,51 @@ __device__ void pca_row(const PcaArgs &a, int32_t i, int lane, const F &fetch) {
       }
     }
   } else {
-    for (int64_t k = b + lane; k < e; k += kTeam) visit(fetch(a, k));
+    // entries k0, k0 + T, k0 + 2T, k0 + 3T per step, every load of a step issued before the first
+    // is used; an entry past the row's end reads particle i itself, whose offset d = 0 adds
+    // nothing to the sums, and is left out of the kind counts.  The kind byte is read without a
+    // branch (from the model array when there are no kinds, whose codes then go unused), so that
+    // no load waits for the one before it.
+    const int8_t *kp = a.kind ? a.kind : a.model;
+    for (int64_t k0 = b + lane; k0 < e; k0 += 4 * T) {
+      int32_t jj[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int32_t c = a.col[min(k0 + u * T, e - 1)];
+        jj[u] = k0 + u * T < e ? c : i;
+      }
+      double4 pj[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) pj[u] = make_double4(a.x[jj[u]], a.y[jj[u]], a.z[jj[u]], pca_code_of(kp[jj[u]]));
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double dx = pj[u].x - xi, dy = pj[u].y - yi, dz = pj[u].z - zi;
+        mx += dx; my += dy; mz += dz;
+        sxx += dx * dx; sxy += dx * dy; sxz += dx * dz;
+        syy += dy * dy; syz += dy * dz; szz += dz * dz;
+        if (need_kinds && k0 + u * T < e) kinds += (uint64_t)1 << (int)pj[u].w;
+      }
+    }
   }
-  mx = team_sum(mx, kTeam);
-  my = team_sum(my, kTeam);
-  mz = team_sum(mz, kTeam);
+  mx = team_sum(mx, T);
+  my = team_sum(my, T);
+  mz = team_sum(mz, T);
   if (need_kinds) {
-    kinds = team_sum(kinds, kTeam);
+    kinds = team_sum(kinds, T);
     // i is in S_i once: remove its own kind
     const int ko = (int)a.kind[i];
     kinds -= (uint64_t)1 << (16 * ((ko >= 0 && ko <= 2) ? ko : 3));
     n_int = (int)(kinds & 0xFFFF);
     n_fs = (int)((kinds >> 16) & 0xFFFF);
   }
-  sxx = team_sum(sxx, kTeam); sxy = team_sum(sxy, kTeam); sxz = team_sum(sxz, kTeam);
-  syy = team_sum(syy, kTeam); syz = team_sum(syz, kTeam); szz = team_sum(szz, kTeam);
+  sxx = team_sum(sxx, T); sxy = team_sum(sxy, T); sxz = team_sum(sxz, T);
+  syy = team_sum(syy, T); syz = team_sum(syz, T); szz = team_sum(szz, T);
   const double inv = 1.0 / (double)(e - b);
   const double cx = mx * inv, cy = my * inv, cz = mz * inv;
   c[0] = sxx - mx * cx; c[1] = sxy - mx * cy; c[2] = sxz - mx * cz;
   c[3] = syy - my * cy; c[4] = syz - my * cz; c[5] = szz - mz * cz;
-  // every lane holds the sums: lane l writes 16 bytes of the row's record
+  // every lane holds the sums: lane l < 4 writes 16 bytes of the row's record
+  if (lane >= 4) return;
   const double cnt = __builtin_bit_cast(double, (uint64_t)(uint32_t)n_int | ((uint64_t)(uint32_t)n_fs << 32));
   const double2 v = lane == 0 ? make_double2(c[0], c[1])
                   : lane == 1 ? make_double2(c[2], c[3])
@@ -254,11 +289,12 @@ __global__ void __launch_bounds__(kTileRows * kTeam) k_pca_tile(PcaArgs a, const
   const int cnt = (int)(toff[tile0 + tl + 1] - u0);
   const bool staged = cnt <= cap;
   if (staged) {
+    const int8_t *kp = a.kind ? a.kind : a.model;  // codes unused without kinds; no branch per load
     for (int s = threadIdx.x; s < cnt; s += blockDim.x) {
       const int32_t j = tu[u0 + s];
       s_rec[s] = make_double2(a.x[j], a.y[j]);
       s_z[s] = a.z[j];
-      s_c[s] = (uint8_t)pca_code(a, j);
+      s_c[s] = (uint8_t)pca_code_of(kp[j]);
     }
   }
   __syncthreads();
@@ -266,16 +302,16 @@ __global__ void __launch_bounds__(kTileRows * kTeam) k_pca_tile(PcaArgs a, const
   const int64_t r = tl * kTileRows + team;
   if (r >= a.nrows) return;
   const int32_t i = a.sched[r];
-  if (staged) pca_row(a, i, lane, PcaTile{PcaRec{s_rec, s_z, s_c}, slot});
-  else pca_row(a, i, lane, PcaGlobal{});
+  if (staged) pca_row<kTeam>(a, i, lane, PcaTile{PcaRec{s_rec, s_z, s_c}, slot});
+  else pca_row<kTeam>(a, i, lane, PcaGlobal{});
 }
 
-// untiled rows: teams over the rows of the launch, gathers from global memory
+// untiled rows: teams of kTeamWide lanes over the rows of the launch, gathers from global memory
 __global__ void __launch_bounds__(kBlock) k_pca_flags(PcaArgs a) {
   const int64_t gt = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  const int64_t r = gt / kTeam;
+  const int64_t r = gt / kTeamWide;
   if (r >= a.nrows) return;
-  pca_row(a, a.sched[r], (int)(gt % kTeam), PcaGlobal{});
+  pca_row<kTeamWide>(a, a.sched[r], (int)(gt % kTeamWide), PcaGlobal{});
 }
 
 // smoothing rule 1 over the cross-model neighbourhood
@@ -349,7 +385,7 @@ extern "C" gf_status gf_classify_pca(gf_ctx *ctx, const gf_particles *p, const g
       hipLaunchKernelGGL(k_pca_tile, dim3(grid_for(u.ntiles, 1)), dim3(kTileRows * kTeam), (sizeof(double2) + sizeof(double) + 1) * (size_t)cap,
                          ctx->stream, a, same->tile_off, same->tile_u, same->slot, u.tile0, cap);
     } else {
-      hipLaunchKernelGGL(k_pca_flags, dim3(grid_for(u.nrows * kTeam, kBlock)), dim3(kBlock), 0, ctx->stream, a);
+      hipLaunchKernelGGL(k_pca_flags, dim3(grid_for(u.nrows * kTeamWide, kBlock)), dim3(kBlock), 0, ctx->stream, a);
     }
     GF_LAUNCH_CHECK(ctx);
   }
