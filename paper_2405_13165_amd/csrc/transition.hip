@@ -13,7 +13,9 @@
 //
 // Each scan runs on a team of kTT lanes per particle (lane l takes the
 // entries k0 + l, k0 + l + kTT, ...), so a particle waits for about
-// |S|/kTT dependent loads instead of |S|.  The nearest wall particle is the
+// |S|/kTT dependent loads instead of |S|; the owner search takes its
+// entries four at a time per lane, every load of a step issued before the
+// first is used.  The nearest wall particle is the
 // team minimum of (distance, index), which keeps the smallest index among
 // equal distances as an ascending scan does; the lumped sums walk each chunk
 // of kTT entries lane by lane, i.e. in ascending entry order.
@@ -23,6 +25,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kTT = 8;  // lanes per particle in the neighbourhood scans
 static_assert(64 % kTT == 0, "a team lies within a wave");
+constexpr int kTU = 4;  // entries per lane and step of the owner search
 
 __global__ void __launch_bounds__(kBlock) k_owner(const double *__restrict__ x, const double *__restrict__ y,
                                                   const double *__restrict__ z, const int8_t *__restrict__ model,
@@ -37,19 +40,36 @@ __global__ void __launch_bounds__(kBlock) k_owner(const double *__restrict__ x, 
   int32_t own = -1;
   if (model[b] == GF_MODEL_BULK && kind[b] != GF_KIND_WALL) {
     const int64_t k0 = row_ptr[b], k1 = row_ptr[b + 1];
+    // entries past the row's end re-read its last entry (a step starts only at kb < k1), which
+    // the OR sees twice and the nearest-wall search skips
     int cand = 0;
-    for (int64_t k = k0 + lane; k < k1; k += kTT) cand |= flag[col[k]] == 1;
+    for (int64_t kb = k0 + lane; kb < k1; kb += kTU * kTT) {
+      int32_t j[kTU];
+#pragma unroll
+      for (int u = 0; u < kTU; ++u) j[u] = col[min(kb + u * kTT, k1 - 1)];
+#pragma unroll
+      for (int u = 0; u < kTU; ++u) cand |= flag[j[u]] == 1;
+    }
     for (int o = kTT >> 1; o > 0; o >>= 1) cand |= __shfl_xor(cand, o, kTT);
     if (cand) {
       int32_t best = -1;
       double bestd = INFINITY;
       const double xb = x[b], yb = y[b], zb = z[b];
-      for (int64_t k = k0 + lane; k < k1; k += kTT) {
-        const int32_t j = col[k];
-        if (kind[j] != GF_KIND_WALL || model[j] != GF_MODEL_BULK) continue;
-        const double dx = x[j] - xb, dy = y[j] - yb, dz = z[j] - zb;
-        const double d2 = (dx * dx + dy * dy) + dz * dz;
-        if (d2 < bestd) { bestd = d2; best = j; }  // ascending j: ties keep the smaller index
+      for (int64_t kb = k0 + lane; kb < k1; kb += kTU * kTT) {
+        int32_t j[kTU];
+#pragma unroll
+        for (int u = 0; u < kTU; ++u) j[u] = col[min(kb + u * kTT, k1 - 1)];
+        bool wall[kTU];
+        double d2[kTU];
+#pragma unroll
+        for (int u = 0; u < kTU; ++u) {
+          wall[u] = kb + u * kTT < k1 && kind[j[u]] == GF_KIND_WALL && model[j[u]] == GF_MODEL_BULK;
+          const double dx = x[j[u]] - xb, dy = y[j[u]] - yb, dz = z[j[u]] - zb;
+          d2[u] = (dx * dx + dy * dy) + dz * dz;
+        }
+#pragma unroll
+        for (int u = 0; u < kTU; ++u)  // ascending j: ties keep the smaller index
+          if (wall[u] && d2[u] < bestd) { bestd = d2[u]; best = j[u]; }
       }
       for (int o = kTT >> 1; o > 0; o >>= 1) {
         const double od = __shfl_xor(bestd, o, kTT);
