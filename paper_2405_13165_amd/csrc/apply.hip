@@ -128,17 +128,51 @@ __global__ void __launch_bounds__(kTileRows * T) k_apply_tile(const int32_t *__r
 // field values a tiled apply block may stage
 constexpr int kApplyCap = 2048;
 
+// A stencil record (four operators of one entry) as loaded, converted to
+// FP64 only where it is used, so that a record still in flight is not waited
+// for when it is handed on.
+template <typename WT>
+struct WRec;
+template <>
+struct WRec<float> {
+  float4 v;
+  __device__ inline void load(const void *w, int64_t k) { v = reinterpret_cast<const float4 *>(w)[k]; }
+  __device__ inline double get(int s) const { return s == 0 ? v.x : s == 1 ? v.y : s == 2 ? v.z : v.w; }
+};
+template <>
+struct WRec<double> {
+  double2 a, b;
+  __device__ inline void load(const void *w, int64_t k) {
+    const double2 *p = reinterpret_cast<const double2 *>(w) + 2 * k;
+    a = p[0];
+    b = p[1];
+  }
+  __device__ inline double get(int s) const { return s == 0 ? a.x : s == 1 ? a.y : s == 2 ? b.x : b.y; }
+};
+
 // ubar_j = sum_{i : j in S_i, i != j} c_ij ybar_i - ybar_j sum_{k in S_j, k != j} c_jk,
 // the first sum gathered through the reverse-edge map (entry (i,j) sits at
 // rev[k] for the entry k = (j,i) of row j); an entry of row j without a twin
 // (towards a ghost particle, which has no row) adds only its own term.
-// One team of kAdjTeam lanes per row j (the lanes stride over the row).  The
-// walk is software-pipelined: an entry's column and twin position are read
-// two steps ahead, its two stencils and the seeds ybar_i one step ahead; the
-// loads past the row's end read its last entry and an entry without a twin
-// reads the stencil record 0 (valid, weighted zero), so no load is skipped.
+// One team of kAdjTeam lanes per row j (the lanes stride over the row), K the
+// number of selected operators.  The walk is software-pipelined: an entry's
+// column and twin position are read two steps ahead, its two stencils and the
+// seeds ybar_i one step ahead, into two sets of registers used in turn (the
+// loop body is unrolled by two), so that no value still in flight is copied;
+// the loads past the row's end read its last entry and an entry without a
+// twin reads the stencil record 0 (valid, weighted zero), so no load is
+// skipped.
 constexpr int kAdjTeam = 8;
-template <typename WT>
+struct AdjTwin {
+  int32_t i, kr;  // column, position of the twin entry (i, j) (< 0: none)
+};
+template <typename WT, int K>
+struct AdjData {
+  WRec<WT> cin, cout;  // c_ij (row i, column j), c_ji (row j, column i)
+  double y[K];         // ybar_i of the selected operators
+  bool other, twin;    // i != j, the twin exists
+};
+template <typename WT, int K>
 __global__ void __launch_bounds__(kBlock) k_apply_adjoint(const int64_t *__restrict__ row_ptr,
                                                           const int32_t *__restrict__ col,
                                                           const int32_t *__restrict__ rev, const void *__restrict__ w,
@@ -148,41 +182,54 @@ __global__ void __launch_bounds__(kBlock) k_apply_adjoint(const int64_t *__restr
   const int64_t j = gt / kAdjTeam;
   const int lane = (int)(gt % kAdjTeam);
   if (j >= n) return;
-  int sel[4], K = 0;
-  for (int s = 0; s < 4; ++s)
-    if (mask & (1u << s)) sel[K++] = s;
-  double yj[4];
+  int sel[K];  // the selected operators in ascending order
+  unsigned m = mask;
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    sel[q] = K == 4 ? q : __builtin_ctz(m);
+    m &= m - 1;
+  }
+  double yj[K];
+#pragma unroll
   for (int q = 0; q < K; ++q) yj[q] = ybar[(int64_t)q * n + j];
   double acc = 0.0;
   const int64_t b = row_ptr[j], e = row_ptr[j + 1], kl = e - 1;
-  // stage 2 (two ahead): column and twin; stage 1 (one ahead): stencils and seeds
-  auto twin = [&](int64_t k, int32_t &i, int32_t &kr) {
+  auto twin = [&](int64_t k) {
     const int64_t kk = min(k, kl);
-    i = col[kk];
-    kr = rev[kk];  // < 0: (i, j) is not listed (i a ghost particle without a row)
+    return AdjTwin{col[kk], rev[kk]};
   };
-  double cin[4], cout_[4], yi[4];
-  auto fetch = [&](int64_t k, int32_t i, int32_t kr) {
-    W4<WT>::load(w, kr >= 0 ? kr : 0, cin);  // c_ij (row i, column j)
-    W4<WT>::load(w, min(k, kl), cout_);      // c_ji (row j, column i)
-    for (int q = 0; q < K; ++q) yi[q] = ybar[(int64_t)q * n + i];
+  auto fetch = [&](int64_t k, const AdjTwin &t, AdjData<WT, K> &d) {
+    d.cin.load(w, t.kr >= 0 ? t.kr : 0);
+    d.cout.load(w, min(k, kl));
+#pragma unroll
+    for (int q = 0; q < K; ++q) d.y[q] = ybar[(int64_t)q * n + t.i];
+    d.other = t.i != j;
+    d.twin = t.kr >= 0;
   };
-  int32_t i1, kr1, i2, kr2;
-  twin(b + lane, i1, kr1);
-  twin(b + lane + kAdjTeam, i2, kr2);
-  fetch(b + lane, i1, kr1);
+  auto use = [&](const AdjData<WT, K> &d) {
+    if (d.other)
+#pragma unroll
+      for (int q = 0; q < K; ++q)
+        acc += (d.twin ? d.cin.get(sel[q]) * d.y[q] : 0.0) - d.cout.get(sel[q]) * yj[q];
+  };
+  int64_t k = b + lane;
+  if (k < e) {
+    AdjTwin t0 = twin(k), t1 = twin(k + kAdjTeam);
+    AdjData<WT, K> d0, d1;
+    fetch(k, t0, d0);
 #pragma unroll 1
-  for (int64_t k = b + lane; k < e; k += kAdjTeam) {
-    const int32_t i = i1, kr = kr1;
-    double ci[4], co[4], yv[4];
-    for (int s = 0; s < 4; ++s) { ci[s] = cin[s]; co[s] = cout_[s]; }
-    for (int q = 0; q < K; ++q) yv[q] = yi[q];
-    i1 = i2;
-    kr1 = kr2;
-    fetch(k + kAdjTeam, i1, kr1);
-    twin(k + 2 * kAdjTeam, i2, kr2);
-    if (i != j)
-      for (int q = 0; q < K; ++q) acc += (kr >= 0 ? ci[sel[q]] * yv[q] : 0.0) - co[sel[q]] * yj[q];
+    for (;;) {
+      t0 = twin(k + 2 * kAdjTeam);
+      fetch(k + kAdjTeam, t1, d1);
+      use(d0);
+      k += kAdjTeam;
+      if (k >= e) break;
+      t1 = twin(k + 2 * kAdjTeam);
+      fetch(k + kAdjTeam, t0, d0);
+      use(d1);
+      k += kAdjTeam;
+      if (k >= e) break;
+    }
   }
   acc = team_sum(acc, kAdjTeam);
   if (lane == 0) ubar[j] = acc;
@@ -316,10 +363,23 @@ extern "C" gf_status gf_apply_stencil_adjoint(gf_ctx *ctx, const gf_nbr *nbr, gf
   if ((st = ensure_rev(ctx, const_cast<gf_nbr *>(nbr)))) return st;
   const dim3 grid(grid_for(nbr->n * kAdjTeam, kBlock)), block(kBlock);
   ProfScope prof(ctx, "apply_adjoint");
-  if (wtype == GF_F32)
-    hipLaunchKernelGGL(k_apply_adjoint<float>, grid, block, 0, ctx->stream, nbr->row_ptr, nbr->col, nbr->rev, w, op_mask, ybar, nbr->n, ubar);
-  else
-    hipLaunchKernelGGL(k_apply_adjoint<double>, grid, block, 0, ctx->stream, nbr->row_ptr, nbr->col, nbr->rev, w, op_mask, ybar, nbr->n, ubar);
+#define GF_ADJ(WT, K)                                                                                      \
+  hipLaunchKernelGGL((k_apply_adjoint<WT, K>), grid, block, 0, ctx->stream, nbr->row_ptr, nbr->col, nbr->rev, w, \
+                     op_mask, ybar, nbr->n, ubar)
+#define GF_ADJ_K(WT)                       \
+  switch (__builtin_popcount(op_mask)) {   \
+    case 1: GF_ADJ(WT, 1); break;          \
+    case 2: GF_ADJ(WT, 2); break;          \
+    case 3: GF_ADJ(WT, 3); break;          \
+    default: GF_ADJ(WT, 4); break;         \
+  }
+  if (wtype == GF_F32) {
+    GF_ADJ_K(float)
+  } else {
+    GF_ADJ_K(double)
+  }
+#undef GF_ADJ_K
+#undef GF_ADJ
   GF_LAUNCH_CHECK(ctx);
   return GF_OK;
 }

@@ -594,6 +594,21 @@ def test_apply_adjoint_matches_oracle(ctx, g):
     assert abs(lhs - rhs) <= 1e-10 * abs(lhs)
 
 
+@pytest.mark.parametrize("wdt", ["f64", "f32"])
+@pytest.mark.parametrize("mask", [0x1, 0x8, 0xA, 0x7, 0xF])
+def test_apply_adjoint_operator_subsets(ctx, g, mask, wdt):
+    # one kernel per number of selected operators (1..4) and stencil type; ybar holds the
+    # selected operators' seeds in ascending operator order
+    d = CASES["mixed_small"]()
+    p, nb, rp, col = _nbr_equal(ctx, g, d)
+    w = g.gfdm_weights(ctx, p, nb, g.GF_BATCHED, g.GF_F64 if wdt == "f64" else g.GF_F32)
+    K = bin(mask).count("1")
+    yb = np.random.default_rng(mask).standard_normal((K, p.n))
+    ub = _np(g.apply_stencil_adjoint(ctx, nb, w, torch.as_tensor(yb, device=ctx.device), op_mask=mask))
+    ub_o = oracle.apply_adjoint(rp, col, _np(w).astype(np.float64), yb, op_mask=mask)
+    assert np.abs(ub - ub_o).max() <= 1e-12 * np.abs(ub_o).max()
+
+
 @pytest.mark.parametrize("name", ["diff_small", "mixed_small"])
 def test_weights_adjoint_matches_oracle(ctx, g, name):
     d = W.diff_cube(n_axis=16) if name == "diff_small" else CASES["mixed_small"]()
