@@ -70,7 +70,8 @@ def parse():
     return ap.parse_args()
 
 
-KERNEL_SOURCES = ("weights.hip", "stencil_common.h", "internal.h", "apply.hip")
+# the translation unit of the fused stencil kernel (sources relative to csrc/)
+KERNEL_SOURCES = ("weights.hip", "stencil_common.h", "internal.h", "../../include/gfdm.h")
 
 
 def log(msg):
