@@ -334,6 +334,7 @@ void launch_adjoint_x(hipStream_t sm, dim3 grid, dim3 block, const AArgs &a) {
 // per row; the twin dbar(i, j) sits at grev[g] (a Morton-near row).  An entry
 // (j, i) without a twin (i a ghost particle whose row holds only itself)
 // adds nothing.
+constexpr int kGU = 4;  // entries per lane and step of the gather
 __global__ void __launch_bounds__(kBlock) k_adjoint_gather(const int32_t *__restrict__ grouped,
                                                            const int64_t *__restrict__ grow_ptr,
                                                            const int32_t *__restrict__ grev,
@@ -346,33 +347,31 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_gather(const int32_t *__rest
   const int32_t j = grouped[t];
   const int64_t g0 = grow_ptr[t], g1 = grow_ptr[t + 1];
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  if (g1 > g0) {
-    // software-pipelined: the twin position two steps ahead, its dbar one step
-    // ahead; reads past the row's end take its last entry, an entry without a
-    // twin reads record 0 (both valid, neither added)
-    const int64_t gl = g1 - 1;
-    auto twin = [&](int64_t gk) { return grev[min(gk, gl)]; };
-    auto load = [&](int32_t tw, double &a, double &b, double &c) {
-      const int64_t q = 3 * (int64_t)(tw >= 0 ? tw : 0);
-      a = dbar[q];
-      b = dbar[q + 1];
-      c = dbar[q + 2];
-    };
-    int32_t t1 = twin(g0 + lane), t2 = twin(g0 + lane + kT);
-    double d0, d1, d2;
-    load(t1, d0, d1, d2);
+  // kGU entries per lane and step: every twin position of the step, then
+  // every dbar record, is requested before the first is used (a straight
+  // block, so none of the loads is moved down to its use); reads past the
+  // row's end take its last entry, an entry without a twin reads record 0
+  // (both valid, neither added)
+  const int64_t gl = g1 - 1;  // a step starts only at gk < g1: gl is in the row
 #pragma unroll 1
-    for (int64_t gk = g0 + lane; gk < g1; gk += kT) {
-      const int32_t tw = t1;
-      const double e0 = d0, e1 = d1, e2 = d2;
-      t1 = t2;
-      load(t1, d0, d1, d2);
-      t2 = twin(gk + 2 * kT);
-      if (tw >= 0) {
-        s0 += e0;
-        s1 += e1;
-        s2 += e2;
-      }
+  for (int64_t gk = g0 + lane; gk < g1; gk += kGU * kT) {
+    int32_t tw[kGU];
+#pragma unroll
+    for (int u = 0; u < kGU; ++u) tw[u] = grev[min(gk + u * kT, gl)];
+    double da[kGU], db[kGU], dc[kGU];
+#pragma unroll
+    for (int u = 0; u < kGU; ++u) {
+      const int64_t q = 3 * (int64_t)(tw[u] >= 0 ? tw[u] : 0);
+      da[u] = dbar[q];
+      db[u] = dbar[q + 1];
+      dc[u] = dbar[q + 2];
+    }
+#pragma unroll
+    for (int u = 0; u < kGU; ++u) {  // in entry order
+      const bool on = tw[u] >= 0 && gk + u * kT < g1;
+      s0 += on ? da[u] : 0.0;
+      s1 += on ? db[u] : 0.0;
+      s2 += on ? dc[u] : 0.0;
     }
   }
   s0 = team_sum(s0, kT);
