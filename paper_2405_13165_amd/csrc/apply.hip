@@ -155,23 +155,14 @@ struct WRec<double> {
 // rev[k] for the entry k = (j,i) of row j); an entry of row j without a twin
 // (towards a ghost particle, which has no row) adds only its own term.
 // One team of kAdjTeam lanes per row j (the lanes stride over the row), K the
-// number of selected operators.  The walk is software-pipelined: an entry's
-// column and twin position are read two steps ahead, its two stencils and the
-// seeds ybar_i one step ahead, into two sets of registers used in turn (the
-// loop body is unrolled by two), so that no value still in flight is copied;
-// the loads past the row's end read its last entry and an entry without a
-// twin reads the stencil record 0 (valid, weighted zero), so no load is
-// skipped.
+// number of selected operators.  Each lane takes kAU entries per step: their
+// columns and twin positions, then their two stencil records (c_ij of row i,
+// c_ji of row j) and seeds ybar_i are all requested before the first is used,
+// in one straight block (so that no load is moved down to its use); entries
+// past the row's end read its last entry and an entry without a twin reads
+// the stencil record 0 (both valid, added as zero), so no load is skipped.
 constexpr int kAdjTeam = 8;
-struct AdjTwin {
-  int32_t i, kr;  // column, position of the twin entry (i, j) (< 0: none)
-};
-template <typename WT, int K>
-struct AdjData {
-  WRec<WT> cin, cout;  // c_ij (row i, column j), c_ji (row j, column i)
-  double y[K];         // ybar_i of the selected operators
-  bool other, twin;    // i != j, the twin exists
-};
+constexpr int kAU = 4;
 template <typename WT, int K>
 __global__ void __launch_bounds__(kBlock) k_apply_adjoint(const int64_t *__restrict__ row_ptr,
                                                           const int32_t *__restrict__ col,
@@ -194,41 +185,32 @@ __global__ void __launch_bounds__(kBlock) k_apply_adjoint(const int64_t *__restr
   for (int q = 0; q < K; ++q) yj[q] = ybar[(int64_t)q * n + j];
   double acc = 0.0;
   const int64_t b = row_ptr[j], e = row_ptr[j + 1], kl = e - 1;
-  auto twin = [&](int64_t k) {
-    const int64_t kk = min(k, kl);
-    return AdjTwin{col[kk], rev[kk]};
-  };
-  auto fetch = [&](int64_t k, const AdjTwin &t, AdjData<WT, K> &d) {
-    d.cin.load(w, t.kr >= 0 ? t.kr : 0);
-    d.cout.load(w, min(k, kl));
-#pragma unroll
-    for (int q = 0; q < K; ++q) d.y[q] = ybar[(int64_t)q * n + t.i];
-    d.other = t.i != j;
-    d.twin = t.kr >= 0;
-  };
-  auto use = [&](const AdjData<WT, K> &d) {
-    if (d.other)
-#pragma unroll
-      for (int q = 0; q < K; ++q)
-        acc += (d.twin ? d.cin.get(sel[q]) * d.y[q] : 0.0) - d.cout.get(sel[q]) * yj[q];
-  };
-  int64_t k = b + lane;
-  if (k < e) {
-    AdjTwin t0 = twin(k), t1 = twin(k + kAdjTeam);
-    AdjData<WT, K> d0, d1;
-    fetch(k, t0, d0);
 #pragma unroll 1
-    for (;;) {
-      t0 = twin(k + 2 * kAdjTeam);
-      fetch(k + kAdjTeam, t1, d1);
-      use(d0);
-      k += kAdjTeam;
-      if (k >= e) break;
-      t1 = twin(k + 2 * kAdjTeam);
-      fetch(k + kAdjTeam, t0, d0);
-      use(d1);
-      k += kAdjTeam;
-      if (k >= e) break;
+  for (int64_t kb = b + lane; kb < e; kb += kAU * kAdjTeam) {
+    int32_t ci[kAU], kr[kAU];
+#pragma unroll
+    for (int u = 0; u < kAU; ++u) {
+      const int64_t kk = min(kb + u * kAdjTeam, kl);
+      ci[u] = col[kk];
+      kr[u] = rev[kk];
+    }
+    WRec<WT> win[kAU], wout[kAU];
+    double y[kAU][K];
+#pragma unroll
+    for (int u = 0; u < kAU; ++u) {
+      win[u].load(w, kr[u] >= 0 ? kr[u] : 0);
+      wout[u].load(w, min(kb + u * kAdjTeam, kl));
+#pragma unroll
+      for (int q = 0; q < K; ++q) y[u][q] = ybar[(int64_t)q * n + ci[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < kAU; ++u) {
+      const bool on = kb + u * kAdjTeam < e && ci[u] != j;
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        const double t = (kr[u] >= 0 ? win[u].get(sel[q]) * y[u][q] : 0.0) - wout[u].get(sel[q]) * yj[q];
+        acc += on ? t : 0.0;
+      }
     }
   }
   acc = team_sum(acc, kAdjTeam);
