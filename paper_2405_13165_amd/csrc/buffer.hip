@@ -135,6 +135,15 @@ __global__ void __launch_bounds__(kBlock) k_write_2d3d(Src s, const int64_t *__r
 // ---------------------------------------------------------------- buffer zone
 // owner[b]: for a flagged interior / free-surface 3D particle, the nearest
 // flagged wall particle of S_b (the wall ghost its ghost maps onto), else -1
+// The nearest flagged wall particle of each flagged interior bulk particle b,
+// over S_b: a team of kOwnTeam lanes per particle, each lane taking kOwnU
+// entries per step with every load of the step issued before the first is
+// used (entries past the row's end re-read its last entry and are skipped);
+// the team minimum of (distance, index) keeps the smallest index among equal
+// distances, as an ascending scan does.
+constexpr int kOwnTeam = 8;
+constexpr int kOwnU = 4;
+static_assert(64 % kOwnTeam == 0, "a team lies within a wave");
 __global__ void __launch_bounds__(kBlock) k_ghost_owner(const double *__restrict__ x, const double *__restrict__ y,
                                                         const double *__restrict__ z,
                                                         const int8_t *__restrict__ model,
@@ -144,21 +153,41 @@ __global__ void __launch_bounds__(kBlock) k_ghost_owner(const double *__restrict
                                                         const int32_t *__restrict__ col, int64_t n,
                                                         int32_t *__restrict__ owner) {
 #pragma clang fp contract(off)
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= n) return;
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t b = gt / kOwnTeam;
+  const int lane = (int)(gt % kOwnTeam);
+  if (b >= n) return;  // (the whole team)
   int32_t best = -1;
   if (flag[b] && model[b] == GF_MODEL_BULK && kind[b] != GF_KIND_WALL) {
     double bestd = INFINITY;
     const double xb = x[b], yb = y[b], zb = z[b];
-    for (int64_t k = row_ptr[b]; k < row_ptr[b + 1]; ++k) {
-      const int32_t j = col[k];
-      if (!flag[j] || kind[j] != GF_KIND_WALL) continue;
-      const double dx = x[j] - xb, dy = y[j] - yb, dz = z[j] - zb;
-      const double d2 = (dx * dx + dy * dy) + dz * dz;
-      if (d2 < bestd) { bestd = d2; best = j; }  // ascending j: ties keep the smaller index
+    const int64_t k1 = row_ptr[b + 1];  // a step starts only at kb < k1: k1 - 1 is in the row
+    for (int64_t kb = row_ptr[b] + lane; kb < k1; kb += kOwnU * kOwnTeam) {
+      int32_t j[kOwnU];
+#pragma unroll
+      for (int u = 0; u < kOwnU; ++u) j[u] = col[min(kb + u * kOwnTeam, k1 - 1)];
+      bool wall[kOwnU];
+      double d2[kOwnU];
+#pragma unroll
+      for (int u = 0; u < kOwnU; ++u) {
+        wall[u] = kb + u * kOwnTeam < k1 && flag[j[u]] && kind[j[u]] == GF_KIND_WALL;
+        const double dx = x[j[u]] - xb, dy = y[j[u]] - yb, dz = z[j[u]] - zb;
+        d2[u] = (dx * dx + dy * dy) + dz * dz;
+      }
+#pragma unroll
+      for (int u = 0; u < kOwnU; ++u)  // ascending j: ties keep the smaller index
+        if (wall[u] && d2[u] < bestd) { bestd = d2[u]; best = j[u]; }
+    }
+    for (int o = kOwnTeam >> 1; o > 0; o >>= 1) {
+      const double od = __shfl_xor(bestd, o, kOwnTeam);
+      const int32_t oj = __shfl_xor(best, o, kOwnTeam);
+      if (oj >= 0 && (best < 0 || od < bestd || (od == bestd && oj < best))) {
+        bestd = od;
+        best = oj;
+      }
     }
   }
-  owner[b] = best;
+  if (lane == 0) owner[b] = best;
 }
 
 __global__ void __launch_bounds__(kBlock) k_count_ghosts(const int8_t *__restrict__ model,
@@ -382,8 +411,8 @@ extern "C" gf_status gf_buffer_zone(gf_ctx *ctx, const gf_particles *p, const gf
     ProfScope prof(ctx, "buffer_flags_owner");
     hipLaunchKernelGGL(k_zero_bad, dim3(1), dim3(64), 0, ctx->stream, bad);
     hipLaunchKernelGGL(k_flag_rows, grid, block, 0, ctx->stream, same->row_ptr, cross->row_ptr, n, flag);
-    hipLaunchKernelGGL(k_ghost_owner, grid, block, 0, ctx->stream, p->x, p->y, p->z, p->model, p->kind, flag,
-                       same->row_ptr, same->col, n, owner);
+    hipLaunchKernelGGL(k_ghost_owner, dim3(grid_for(n * kOwnTeam, kBlock)), block, 0, ctx->stream, p->x, p->y, p->z,
+                       p->model, p->kind, flag, same->row_ptr, same->col, n, owner);
     hipLaunchKernelGGL(k_count_ghosts, grid, block, 0, ctx->stream, p->model, p->kind, flag, film_height, h_other,
                        r_min, r_max, n, cnt, bad);
     GF_LAUNCH_CHECK(ctx);

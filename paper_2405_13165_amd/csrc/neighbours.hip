@@ -961,21 +961,55 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_compact(const int64_t *__
 }
 
 // reverse-edge map: rev[k] = position of (j, i) in row j for entry k = (i, j)
-// (binary search in the sorted row j); a team of kRevTeam lanes per row i
+// (binary search in the sorted row j, -1 if i is not listed there); a team of
+// kRevTeam lanes per row i, each lane running the searches of kRevU entries
+// side by side, so that every step requests kRevU independent loads (a lone
+// search waits for each of its ~log2 |S_j| steps in turn)
 constexpr int kRevTeam = 8;
+constexpr int kRevU = 4;
 __global__ void __launch_bounds__(kBlock) k_rev(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
                                                 int64_t n, int32_t *__restrict__ rev) {
   const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t i = gt / kRevTeam;
   if (i >= n) return;
-  for (int64_t k = row_ptr[i] + gt % kRevTeam; k < row_ptr[i + 1]; k += kRevTeam) {
-    const int32_t j = col[k];
-    int64_t lo = row_ptr[j], hi = row_ptr[j + 1];
-    while (lo < hi) {
-      const int64_t mid = (lo + hi) >> 1;
-      if (col[mid] < i) lo = mid + 1; else hi = mid;
+  const int64_t b = row_ptr[i], e = row_ptr[i + 1];
+  for (int64_t kb = b + gt % kRevTeam; kb < e; kb += kRevU * kRevTeam) {
+    // entries past the row's end search for its last entry's twin and store nothing; a finished
+    // search reads entry kb (in the row) so that no load is skipped
+    int32_t jj[kRevU];
+#pragma unroll
+    for (int u = 0; u < kRevU; ++u) jj[u] = col[min(kb + u * kRevTeam, e - 1)];
+    int64_t lo[kRevU], hi[kRevU], end[kRevU];
+#pragma unroll
+    for (int u = 0; u < kRevU; ++u) {
+      lo[u] = row_ptr[jj[u]];
+      hi[u] = end[u] = row_ptr[jj[u] + 1];
     }
-    rev[k] = (lo < row_ptr[j + 1] && col[lo] == i) ? (int32_t)lo : -1;
+    bool act = true;
+    while (act) {
+      int64_t mid[kRevU];
+      int32_t v[kRevU];
+#pragma unroll
+      for (int u = 0; u < kRevU; ++u) {
+        mid[u] = (lo[u] + hi[u]) >> 1;
+        v[u] = col[lo[u] < hi[u] ? mid[u] : kb];
+      }
+      act = false;
+#pragma unroll
+      for (int u = 0; u < kRevU; ++u) {
+        if (lo[u] < hi[u]) {
+          if (v[u] < i) lo[u] = mid[u] + 1;
+          else hi[u] = mid[u];
+        }
+        act |= lo[u] < hi[u];
+      }
+    }
+    int32_t c[kRevU];
+#pragma unroll
+    for (int u = 0; u < kRevU; ++u) c[u] = col[lo[u] < end[u] ? lo[u] : kb];
+#pragma unroll
+    for (int u = 0; u < kRevU; ++u)
+      if (kb + u * kRevTeam < e) rev[kb + u * kRevTeam] = (lo[u] < end[u] && c[u] == i) ? (int32_t)lo[u] : -1;
   }
 }
 
