@@ -615,6 +615,31 @@ __global__ void __launch_bounds__(kSearchBlock) __attribute__((amdgpu_waves_per_
 constexpr int kSortBlock = 256;
 constexpr int kSortWaves = kSortBlock / 64;
 
+// v of lane `lane ^ j` (j a power of two up to 32, a constant once the
+// networks are unrolled), without the LDS crossbar where a lane move does it:
+// j = 1, 2 by a DPP quad permutation, j = 4, 8 by the two DPP row shifts and a
+// select (a lane with bit j clear reads lane + j, one with it set lane - j,
+// both in its row of 16), j = 16 by a swizzle within 32 lanes (bitmask mode,
+// xor 16), j = 32 by a permute.  Every lane of the wave is active here.
+__device__ __forceinline__ int32_t xor_lane(int32_t v, int j, int lane) {
+  switch (j) {
+    case 1: return __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false);  // quad_perm [1, 0, 3, 2]
+    case 2: return __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false);  // quad_perm [2, 3, 0, 1]
+    case 4: {
+      const int32_t up = __builtin_amdgcn_update_dpp(v, v, 0x104, 0xF, 0xF, false);  // row_shl:4
+      const int32_t dn = __builtin_amdgcn_update_dpp(v, v, 0x114, 0xF, 0xF, false);  // row_shr:4
+      return (lane & 4) ? dn : up;
+    }
+    case 8: {
+      const int32_t up = __builtin_amdgcn_update_dpp(v, v, 0x108, 0xF, 0xF, false);  // row_shl:8
+      const int32_t dn = __builtin_amdgcn_update_dpp(v, v, 0x118, 0xF, 0xF, false);  // row_shr:8
+      return (lane & 8) ? dn : up;
+    }
+    case 16: return __builtin_amdgcn_ds_swizzle(v, (16 << 10) | 0x1F);
+    default: return __shfl_xor(v, j, 64);
+  }
+}
+
 __device__ inline int32_t bitonic_pick(int32_t v, int32_t partner, int t, int j, int k) {
   const bool up = (t & k) == 0;     // direction of this k-sequence
   const bool lower = (t & j) == 0;  // t is the smaller position of its pair
@@ -633,8 +658,8 @@ __device__ inline void sort_net(int32_t &v0, int32_t &v1, int lane) {
         v0 = lo;
         v1 = hi;
       } else {
-        v0 = bitonic_pick(v0, __shfl_xor(v0, j, 64), lane, j, k);
-        if (P > 64) v1 = bitonic_pick(v1, __shfl_xor(v1, j, 64), lane + 64, j, k);
+        v0 = bitonic_pick(v0, xor_lane(v0, j, lane), lane, j, k);
+        if (P > 64) v1 = bitonic_pick(v1, xor_lane(v1, j, lane), lane + 64, j, k);
       }
     }
   }
@@ -662,7 +687,7 @@ __device__ inline void sort_net256(int32_t v[4], int lane) {
         cx(v[2], v[3], lane + 128, k);
       } else {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[r] = bitonic_pick(v[r], __shfl_xor(v[r], j, 64), lane + 64 * r, j, k);
+        for (int r = 0; r < 4; ++r) v[r] = bitonic_pick(v[r], xor_lane(v[r], j, lane), lane + 64 * r, j, k);
       }
     }
   }
