@@ -25,8 +25,10 @@ __global__ void __launch_bounds__(kBlock) k_flag_rows(const int64_t *__restrict_
   flag[i] = (cross_rp[i + 1] - cross_rp[i]) != (same_rp[i + 1] - same_rp[i]) ? 1 : 0;
 }
 
-// Eq. (Height): one team of kHeightTeam lanes per particle, rows in grouped
-// (Morton) order so that neighbouring teams share their neighbours' data.
+// Eq. (Height): one team of kHeightTeam lanes per film particle, rows in
+// grouped (Morton) order so that neighbouring teams share their neighbours'
+// data; the launch covers the film rows of the grouped order only (a team per
+// bulk row would find nothing to sum, and half the waves would do no work).
 __global__ void __launch_bounds__(kBlock) k_film_height(const int32_t *__restrict__ grouped, int64_t n,
                                                         const double *__restrict__ x, const double *__restrict__ y,
                                                         const double *__restrict__ z, const double *__restrict__ h,
@@ -55,6 +57,13 @@ __global__ void __launch_bounds__(kBlock) k_film_height(const int32_t *__restric
     for (int o = kHeightTeam / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kHeightTeam);
   }
   if (lane == 0) height[i] = acc;
+}
+
+// the bulk rows' film height: zero
+__global__ void __launch_bounds__(kBlock) k_zero_rows(const int32_t *__restrict__ grouped, int64_t n,
+                                                      double *__restrict__ height) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) height[grouped[r]] = 0.0;
 }
 
 // gamma of Eq. (gamma) with psi~ of Eq. (psi~); false if it is not a valid
@@ -136,14 +145,13 @@ __global__ void __launch_bounds__(kBlock) k_write_2d3d(Src s, const int64_t *__r
 // owner[b]: for a flagged interior / free-surface 3D particle, the nearest
 // flagged wall particle of S_b (the wall ghost its ghost maps onto), else -1
 // The nearest flagged wall particle of each flagged interior bulk particle b,
-// over S_b: a team of kOwnTeam lanes per particle, each lane taking kOwnU
-// entries per step with every load of the step issued before the first is
-// used (entries past the row's end re-read its last entry and are skipped);
-// the team minimum of (distance, index) keeps the smallest index among equal
-// distances, as an ascending scan does.
-constexpr int kOwnTeam = 8;
+// over S_b.  Few particles are flagged, so a wave takes 64 particles, finds
+// its flagged ones by a ballot and scans each of their rows with all 64
+// lanes, each lane taking kOwnU entries per step with every load of the step
+// issued before the first is used (entries past the row's end re-read its
+// last entry and are skipped); the wave minimum of (distance, index) keeps
+// the smallest index among equal distances, as an ascending scan does.
 constexpr int kOwnU = 4;
-static_assert(64 % kOwnTeam == 0, "a team lies within a wave");
 __global__ void __launch_bounds__(kBlock) k_ghost_owner(const double *__restrict__ x, const double *__restrict__ y,
                                                         const double *__restrict__ z,
                                                         const int8_t *__restrict__ model,
@@ -153,24 +161,29 @@ __global__ void __launch_bounds__(kBlock) k_ghost_owner(const double *__restrict
                                                         const int32_t *__restrict__ col, int64_t n,
                                                         int32_t *__restrict__ owner) {
 #pragma clang fp contract(off)
-  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t b = gt / kOwnTeam;
-  const int lane = (int)(gt % kOwnTeam);
-  if (b >= n) return;  // (the whole team)
-  int32_t best = -1;
-  if (flag[b] && model[b] == GF_MODEL_BULK && kind[b] != GF_KIND_WALL) {
-    double bestd = INFINITY;
+  const int lane = threadIdx.x & 63;
+  const int64_t b0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63);  // the wave's first particle
+  const int64_t bl = b0 + lane;
+  const bool mine = bl < n && flag[bl] && model[bl] == GF_MODEL_BULK && kind[bl] != GF_KIND_WALL;
+  if (bl < n && !mine) owner[bl] = -1;
+  uint64_t todo = __ballot(mine);  // the same in every lane: the loop below is uniform
+  while (todo) {
+    const int src = __builtin_ctzll(todo);
+    todo &= todo - 1;
+    const int64_t b = b0 + src;
     const double xb = x[b], yb = y[b], zb = z[b];
     const int64_t k1 = row_ptr[b + 1];  // a step starts only at kb < k1: k1 - 1 is in the row
-    for (int64_t kb = row_ptr[b] + lane; kb < k1; kb += kOwnU * kOwnTeam) {
+    int32_t best = -1;
+    double bestd = INFINITY;
+    for (int64_t kb = row_ptr[b] + lane; kb < k1; kb += kOwnU * 64) {
       int32_t j[kOwnU];
 #pragma unroll
-      for (int u = 0; u < kOwnU; ++u) j[u] = col[min(kb + u * kOwnTeam, k1 - 1)];
+      for (int u = 0; u < kOwnU; ++u) j[u] = col[min(kb + u * 64, k1 - 1)];
       bool wall[kOwnU];
       double d2[kOwnU];
 #pragma unroll
       for (int u = 0; u < kOwnU; ++u) {
-        wall[u] = kb + u * kOwnTeam < k1 && flag[j[u]] && kind[j[u]] == GF_KIND_WALL;
+        wall[u] = kb + u * 64 < k1 && flag[j[u]] && kind[j[u]] == GF_KIND_WALL;
         const double dx = x[j[u]] - xb, dy = y[j[u]] - yb, dz = z[j[u]] - zb;
         d2[u] = (dx * dx + dy * dy) + dz * dz;
       }
@@ -178,16 +191,16 @@ __global__ void __launch_bounds__(kBlock) k_ghost_owner(const double *__restrict
       for (int u = 0; u < kOwnU; ++u)  // ascending j: ties keep the smaller index
         if (wall[u] && d2[u] < bestd) { bestd = d2[u]; best = j[u]; }
     }
-    for (int o = kOwnTeam >> 1; o > 0; o >>= 1) {
-      const double od = __shfl_xor(bestd, o, kOwnTeam);
-      const int32_t oj = __shfl_xor(best, o, kOwnTeam);
+    for (int o = 32; o > 0; o >>= 1) {
+      const double od = __shfl_xor(bestd, o, 64);
+      const int32_t oj = __shfl_xor(best, o, 64);
       if (oj >= 0 && (best < 0 || od < bestd || (od == bestd && oj < best))) {
         bestd = od;
         best = oj;
       }
     }
+    if (lane == 0) owner[b] = best;
   }
-  if (lane == 0) owner[b] = best;
 }
 
 __global__ void __launch_bounds__(kBlock) k_count_ghosts(const int8_t *__restrict__ model,
@@ -308,10 +321,16 @@ extern "C" gf_status gf_film_height(gf_ctx *ctx, const gf_particles *p, const gf
   if (!diam || !height_out) return set_error(ctx, GF_EINVAL, "diam and height_out are required");
   if (!(alpha > 0.0) || !std::isfinite(alpha)) return set_error(ctx, GF_EINVAL, "alpha must be positive and finite");
   const int64_t rows_per_block = kBlock / kHeightTeam;
+  // the grouped order holds the bulk rows, then the film rows
+  const int64_t r0 = same->group_start[GF_NBAND], r1 = same->group_start[2 * GF_NBAND];
   ProfScope prof(ctx, "film_height");
-  hipLaunchKernelGGL(k_film_height, dim3(grid_for((p->n + rows_per_block - 1) / rows_per_block, 1)), dim3(kBlock), 0,
-                     ctx->stream, same->grouped, p->n, p->x, p->y, p->z, p->h, p->model, diam, same->row_ptr,
-                     same->col, alpha, height_out);
+  if (r0 > 0)
+    hipLaunchKernelGGL(k_zero_rows, dim3(grid_for(r0, kBlock)), dim3(kBlock), 0, ctx->stream, same->grouped, r0,
+                       height_out);
+  if (r1 > r0)
+    hipLaunchKernelGGL(k_film_height, dim3(grid_for((r1 - r0 + rows_per_block - 1) / rows_per_block, 1)), dim3(kBlock),
+                       0, ctx->stream, same->grouped + r0, r1 - r0, p->x, p->y, p->z, p->h, p->model, diam,
+                       same->row_ptr, same->col, alpha, height_out);
   GF_LAUNCH_CHECK(ctx);
   return GF_OK;
 }
@@ -411,8 +430,8 @@ extern "C" gf_status gf_buffer_zone(gf_ctx *ctx, const gf_particles *p, const gf
     ProfScope prof(ctx, "buffer_flags_owner");
     hipLaunchKernelGGL(k_zero_bad, dim3(1), dim3(64), 0, ctx->stream, bad);
     hipLaunchKernelGGL(k_flag_rows, grid, block, 0, ctx->stream, same->row_ptr, cross->row_ptr, n, flag);
-    hipLaunchKernelGGL(k_ghost_owner, dim3(grid_for(n * kOwnTeam, kBlock)), block, 0, ctx->stream, p->x, p->y, p->z,
-                       p->model, p->kind, flag, same->row_ptr, same->col, n, owner);
+    hipLaunchKernelGGL(k_ghost_owner, grid, block, 0, ctx->stream, p->x, p->y, p->z, p->model, p->kind, flag,
+                       same->row_ptr, same->col, n, owner);
     hipLaunchKernelGGL(k_count_ghosts, grid, block, 0, ctx->stream, p->model, p->kind, flag, film_height, h_other,
                        r_min, r_max, n, cnt, bad);
     GF_LAUNCH_CHECK(ctx);
