@@ -393,14 +393,16 @@ __device__ inline bool in_support(double4 a, double4 b) {
 // MODE 1: fill col (each row in candidate order; rows are sorted afterwards).
 // Both passes visit candidates in the same order, so the fill ends exactly at
 // the counted length.  With `stage`, the count pass also writes each row's
-// first kStage hits to stage[i * kStage ...], which saves the fill pass when
-// no row is longer.  Particles i >= n_rows (ghost particles) appear in the
+// first sw hits to stage[i * sw ...] (sw, the stage width, 512 or 256 hits
+// by the memory it takes), which saves the fill pass when no row is longer;
+// with `stage` the fill pass writes only the longer rows (and skips the groups
+// of rows without one).  Particles i >= n_rows (ghost particles) appear in the
 // rows of others but their own row holds only i.
 constexpr int kSearchBlock = 256;
 constexpr int kSearchWaves = kSearchBlock / 64;
 constexpr int kSearchWavesPerSimd = 6;  // occupancy the search kernels are compiled for
 constexpr int kQueueGrab = 4;           // cells a wave takes from the queue at once
-constexpr int kStage = 256;             // hits per row the count pass can stage
+constexpr int kStageWidths[2] = {512, 256};  // hits per row the count pass may stage, widest first
 
 // the value of v in lane r (r the same in every lane)
 __device__ inline int64_t readlane64(int64_t v, int r) {
@@ -429,7 +431,8 @@ __global__ void __launch_bounds__(kSearchBlock) __attribute__((amdgpu_waves_per_
                                                          int32_t *__restrict__ cnt, int32_t *__restrict__ hist,
                                                          int32_t *__restrict__ maxrow,
                                                          const int64_t *__restrict__ row_ptr,
-                                                         int32_t *__restrict__ col, int32_t *__restrict__ stage) {
+                                                         int32_t *__restrict__ col, int32_t *__restrict__ stage,
+                                                         int sw) {
   __shared__ int32_t s_rb[kSearchWaves][64];    // first sorted position of each cell of the batch
   __shared__ int32_t s_pref[kSearchWaves][65];  // candidates before each cell of the batch
   __shared__ double4 s_row[kSearchWaves][64];   // positions of the current row group
@@ -467,13 +470,15 @@ __global__ void __launch_bounds__(kSearchBlock) __attribute__((amdgpu_waves_per_
         if (MODE == 1) {
           myoff = row_ptr[myi];
           mylen = (int)(row_ptr[myi + 1] - myoff);
+          if (stage && mylen <= sw) mylen = 0;  // staged by the count pass: not written here
           if (ghost && mylen > 0) col[myoff] = myi;
         } else if (stage) {
-          myoff = (int64_t)myi * kStage;
-          mylen = kStage;
+          myoff = (int64_t)myi * sw;
+          mylen = sw;
           if (ghost) stage[myoff] = myi;
         }
       }
+      if (MODE == 1 && stage && __ballot(mylen > 0) == 0) continue;  // no row of the group to fill
       const bool act = lane < nr && !ghost;
       const double bx0 = uniform_f64(wave_min(act ? me.x : INFINITY));
       const double bx1 = uniform_f64(wave_max(act ? me.x : -INFINITY));
@@ -693,11 +698,12 @@ __device__ inline void sort_net256(int32_t v[4], int lane) {
   }
 }
 
-// STAGED: row i is read from stage[i * kStage ...] (the count pass's copy)
-// and written, sorted, to its CSR place; otherwise it is sorted in place.
+// STAGED: a row of at most sw entries is read from stage[i * sw ...]
+// (the count pass's copy) and written, sorted, to its CSR place; a longer row
+// (filled by the fill pass), or every row without STAGED, is sorted in place.
 template <bool LONG, bool STAGED>
 __global__ void __launch_bounds__(kSortBlock) k_row_sort(const int64_t *__restrict__ row_ptr, int32_t *__restrict__ col,
-                                                         const int32_t *__restrict__ stage, int64_t n) {
+                                                         const int32_t *__restrict__ stage, int sw, int64_t n) {
   extern __shared__ int32_t sort_buf[];  // LONG: kSortWaves x kMaxRow
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t nchunks = (n + 63) / 64;
@@ -711,7 +717,8 @@ __global__ void __launch_bounds__(kSortBlock) k_row_sort(const int64_t *__restri
       rl = (int)(row_ptr[i0 + lane + 1] - rb);
     }
     auto src = [&](int r) -> const int32_t * {
-      return STAGED ? stage + (i0 + r) * (int64_t)kStage : col + readlane64(rb, r);
+      if (STAGED && __builtin_amdgcn_readlane(rl, r) <= sw) return stage + (i0 + r) * (int64_t)sw;
+      return col + readlane64(rb, r);
     };
     // rows of up to kRegRow entries are held in registers (NV per lane)
     constexpr int NV = LONG ? 4 : 2;
@@ -1360,10 +1367,13 @@ extern "C" gf_status gf_build_neighbours_rows(gf_ctx *ctx, const gf_particles *p
         sizeof(double4) * n, sizeof(int32_t) * n, sizeof(int64_t) * scan_tmp_elems(n + 1), sizeof(int32_t) * 32,
         sizeof(int32_t) * n, sizeof(int32_t) * (n + 1), sizeof(int32_t) * scan_tmp_elems(n + 1),
         sizeof(int32_t) * n, sizeof(int32_t) * n};
-  // rows staged by the count pass (kStage entries each) while that stays
-  // under 8 GB; rows found longer fall back to a fill pass
-  const bool use_stage = (double)n * kStage * sizeof(int32_t) <= 8e9;
-  if (use_stage) sz.push_back(sizeof(int32_t) * (size_t)n * kStage);
+  // rows staged by the count pass (sw entries each, the widest that stays
+  // under 8 GB); rows found longer are filled by a second search pass
+  int sw = 0;
+  for (int w : kStageWidths)
+    if (sw == 0 && (double)n * w * sizeof(int32_t) <= 8e9) sw = w;
+  const bool use_stage = sw > 0;
+  if (use_stage) sz.push_back(sizeof(int32_t) * (size_t)n * sw);
   if ((st = ensure_scratch(ctx, arena_bytes(sz), &ar))) return st;
   int32_t *key = ar.take<int32_t>(n);
   int32_t *slot = ar.take<int32_t>(n);
@@ -1384,7 +1394,7 @@ extern "C" gf_status gf_build_neighbours_rows(gf_ctx *ctx, const gf_particles *p
   // pass has finished
   int32_t *cells = ar.take<int32_t>(n);
   int32_t *order1 = ar.take<int32_t>(n);  // model-wide cell order for the grouping (several levels)
-  int32_t *stage = use_stage ? ar.take<int32_t>((size_t)n * kStage) : nullptr;
+  int32_t *stage = use_stage ? ar.take<int32_t>((size_t)n * sw) : nullptr;
   int32_t *head = gflag, *cpos = gpos;
   const int32_t *ncells = cpos + n;
 
@@ -1427,7 +1437,7 @@ extern "C" gf_status gf_build_neighbours_rows(gf_ctx *ctx, const gf_particles *p
   ProfScope prof_count(ctx, "nbr_count");
   hipLaunchKernelGGL(k_search<0>, search_grid, dim3(kSearchBlock), 0, sm, nb->order, sp, p->model, cell_start, cells,
                      ncells, slot_count, small + 10, n, n_rows, g, cross_model ? 1 : 0, cnt, small, small + 8,
-                     (const int64_t *)nullptr, (int32_t *)nullptr, stage);
+                     (const int64_t *)nullptr, (int32_t *)nullptr, stage, sw);
   }
   if (hipGetLastError() != hipSuccess) return fail(set_error(ctx, GF_EHIP, "count kernel launch failed"));
   if ((st = scan_i32_to_i64(ctx, cnt, nb->row_ptr, n, tmp64))) return fail(st);
@@ -1453,12 +1463,15 @@ extern "C" gf_status gf_build_neighbours_rows(gf_ctx *ctx, const gf_particles *p
   if (nb->nnz >= (int64_t)1 << 40) return fail(set_error(ctx, GF_ECAPACITY, "too many neighbour pairs"));
   if (hipMalloc(&nb->col, sizeof(int32_t) * std::max<int64_t>(nb->nnz, 1)) != hipSuccess)
     return fail(set_error(ctx, GF_ENOMEM, "neighbour list allocation (%lld entries) failed", (long long)nb->nnz));
-  const bool staged = use_stage && nb->max_row <= kStage;
-  if (!staged) {
+  // staged rows need no fill pass; rows longer than sw (if any) are filled by one that
+  // writes only those
+  const bool staged = use_stage;
+  if (!staged || nb->max_row > sw) {
     ProfScope prof_fill(ctx, "nbr_fill");
     hipLaunchKernelGGL(k_search<1>, search_grid, dim3(kSearchBlock), 0, sm, nb->order, sp, p->model, cell_start,
                        cells, ncells, slot_count, small + 11, n, n_rows, g, cross_model ? 1 : 0, (int32_t *)nullptr,
-                       (int32_t *)nullptr, (int32_t *)nullptr, nb->row_ptr, nb->col, (int32_t *)nullptr);
+                       (int32_t *)nullptr, (int32_t *)nullptr, nb->row_ptr, nb->col, staged ? stage : (int32_t *)nullptr,
+                       sw);
   }
   {
     // staged rows: sorted on their way into the CSR; else sorted in place
@@ -1467,15 +1480,17 @@ extern "C" gf_status gf_build_neighbours_rows(gf_ctx *ctx, const gf_particles *p
     const dim3 sgrid((unsigned)std::max<int64_t>(1, std::min<int64_t>((nchunks + kSortWaves - 1) / kSortWaves, 4096)));
     const size_t lds = nb->max_row > 128 ? sizeof(int32_t) * kSortWaves * kMaxRow : 0;
     if (staged && nb->max_row > 128)
-      hipLaunchKernelGGL((k_row_sort<true, true>), sgrid, dim3(kSortBlock), lds, sm, nb->row_ptr, nb->col, stage, n);
+      hipLaunchKernelGGL((k_row_sort<true, true>), sgrid, dim3(kSortBlock), lds, sm, nb->row_ptr, nb->col, stage, sw,
+                         n);
     else if (staged)
-      hipLaunchKernelGGL((k_row_sort<false, true>), sgrid, dim3(kSortBlock), 0, sm, nb->row_ptr, nb->col, stage, n);
+      hipLaunchKernelGGL((k_row_sort<false, true>), sgrid, dim3(kSortBlock), 0, sm, nb->row_ptr, nb->col, stage, sw,
+                         n);
     else if (nb->max_row > 128)
       hipLaunchKernelGGL((k_row_sort<true, false>), sgrid, dim3(kSortBlock), lds, sm, nb->row_ptr, nb->col,
-                         (const int32_t *)nullptr, n);
+                         (const int32_t *)nullptr, 0, n);
     else
       hipLaunchKernelGGL((k_row_sort<false, false>), sgrid, dim3(kSortBlock), 0, sm, nb->row_ptr, nb->col,
-                         (const int32_t *)nullptr, n);
+                         (const int32_t *)nullptr, 0, n);
   }
   if (hipGetLastError() != hipSuccess) return fail(set_error(ctx, GF_EHIP, "fill/sort kernel launch failed"));
 
