@@ -125,9 +125,9 @@ gf_status gf_set_tile_capacity(gf_ctx *ctx, int entries);
  * particle (GF_ECAPACITY).  Synchronises (the size of the result is read back).
  * The handle holds the CSR lists, the Morton processing order and the
  * grouping of particles used by the batched kernels.  Scratch: the context's
- * arena grows to about n x 1.1 KB while the rows are staged (256 entries per
- * particle, used while that stays under 8 GB) and keeps that size for later
- * calls on the context. */
+ * arena grows to about n x 2.1 KB while the rows are staged (512 entries per
+ * particle while that stays under 8 GB, else 256, else none) and keeps that
+ * size for later calls on the context. */
 gf_status gf_build_neighbours(gf_ctx *ctx, const gf_particles *p, int cross_model, gf_nbr **out);
 /* Extended neighbourhoods of a cloud whose particles [n_rows, n) are ghost
  * particles (Sec. 6.2): the rows of particles [0, n_rows) hold S_i of

@@ -81,9 +81,10 @@ def test_neighbours_edge_cases(ctx, g):
 
 
 def test_neighbours_long_rows(ctx, g):
-    # rows of 129-256 entries (staged by the count pass, sorted in LDS), rows
-    # above 256 (fill pass, in-place sort), a few rows above 500 entries, and
-    # a row beyond the 2,048-entry limit
+    # rows of 129-256 entries (staged by the count pass, sorted in registers),
+    # rows of 257-512 (staged, sorted in LDS), a few rows above 512 (the fill
+    # pass writes only those, sorted in place), and a row beyond the
+    # 2,048-entry limit
     base = W.plain_cube(20)
     s = 0.01
     for hf in (3.6, 4.5):
