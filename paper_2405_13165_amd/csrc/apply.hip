@@ -129,8 +129,8 @@ __global__ void __launch_bounds__(kTileRows * T) k_apply_tile(const int32_t *__r
 constexpr int kApplyCap = 2048;
 
 // A stencil record (four operators of one entry) as loaded, converted to
-// FP64 only where it is used, so that a record still in flight is not waited
-// for when it is handed on.
+// FP64 only where it is used: a conversion right after the load would wait
+// for it there.
 template <typename WT>
 struct WRec;
 template <>
