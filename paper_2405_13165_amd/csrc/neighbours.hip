@@ -400,7 +400,10 @@ __device__ inline bool in_support(double4 a, double4 b) {
 // rows of others but their own row holds only i.
 constexpr int kSearchBlock = 256;
 constexpr int kSearchWaves = kSearchBlock / 64;
-constexpr int kSearchWavesPerSimd = 6;  // occupancy the search kernels are compiled for
+// occupancy the search kernels are compiled for: five waves per SIMD leave
+// them the registers they use unconstrained (88); asking for six squeezes
+// them into 80 and runs them 15% slower
+constexpr int kSearchWavesPerSimd = 5;
 constexpr int kQueueGrab = 4;           // cells a wave takes from the queue at once
 constexpr int kStageWidths[2] = {512, 256};  // hits per row the count pass may stage, widest first
 
