@@ -154,21 +154,27 @@ struct WRec<double> {
 // the first sum gathered through the reverse-edge map (entry (i,j) sits at
 // rev[k] for the entry k = (j,i) of row j); an entry of row j without a twin
 // (towards a ghost particle, which has no row) adds only its own term.
-// One team of kAdjTeam lanes per row j (the lanes stride over the row), K the
-// number of selected operators.  Each lane takes kAU entries per step: their
+// One team of adj_team lanes per row j (the lanes stride over the row), K the
+// number of selected operators.  Each lane takes adj_unroll entries per step: their
 // columns and twin positions, then their two stencil records (c_ij of row i,
 // c_ji of row j) and seeds ybar_i are all requested before the first is used,
 // in one straight block (so that no load is moved down to its use); entries
 // past the row's end read its last entry and an entry without a twin reads
 // the stencil record 0 (both valid, added as zero), so no load is skipped.
-constexpr int kAdjTeam = 8;
-constexpr int kAU = 4;
+// Team width and entries per step, as measured on the mixed cloud (FP32
+// stencils: 8 x 4 took 572 / 631 us for one / four operators, 8 x 8 461 / 626,
+// 16 x 4 495 / 569); FP64 records are twice as large and keep 8 x 4.
+template <typename WT>
+__host__ __device__ constexpr int adj_team(int K) { return (sizeof(WT) == 4 && K >= 3) ? 16 : 8; }
+template <typename WT>
+__host__ __device__ constexpr int adj_unroll(int K) { return (sizeof(WT) == 4 && K <= 2) ? 8 : 4; }
 template <typename WT, int K>
 __global__ void __launch_bounds__(kBlock) k_apply_adjoint(const int64_t *__restrict__ row_ptr,
                                                           const int32_t *__restrict__ col,
                                                           const int32_t *__restrict__ rev, const void *__restrict__ w,
                                                           unsigned mask, const double *__restrict__ ybar, int64_t n,
                                                           double *__restrict__ ubar) {
+  constexpr int kAdjTeam = adj_team<WT>(K), kAU = adj_unroll<WT>(K);
   const int64_t gt = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int64_t j = gt / kAdjTeam;
   const int lane = (int)(gt % kAdjTeam);
@@ -343,11 +349,11 @@ extern "C" gf_status gf_apply_stencil_adjoint(gf_ctx *ctx, const gf_nbr *nbr, gf
   if (wtype != GF_F32 && wtype != GF_F64) return set_error(ctx, GF_EINVAL, "unknown dtype");
   GF_HIP(ctx, hipSetDevice(ctx->device));
   if ((st = ensure_rev(ctx, const_cast<gf_nbr *>(nbr)))) return st;
-  const dim3 grid(grid_for(nbr->n * kAdjTeam, kBlock)), block(kBlock);
+  const dim3 block(kBlock);
   ProfScope prof(ctx, "apply_adjoint");
-#define GF_ADJ(WT, K)                                                                                      \
-  hipLaunchKernelGGL((k_apply_adjoint<WT, K>), grid, block, 0, ctx->stream, nbr->row_ptr, nbr->col, nbr->rev, w, \
-                     op_mask, ybar, nbr->n, ubar)
+#define GF_ADJ(WT, K)                                                                                            \
+  hipLaunchKernelGGL((k_apply_adjoint<WT, K>), dim3(grid_for(nbr->n * adj_team<WT>(K), kBlock)), block, 0,         \
+                     ctx->stream, nbr->row_ptr, nbr->col, nbr->rev, w, op_mask, ybar, nbr->n, ubar)
 #define GF_ADJ_K(WT)                       \
   switch (__builtin_popcount(op_mask)) {   \
     case 1: GF_ADJ(WT, 1); break;          \
