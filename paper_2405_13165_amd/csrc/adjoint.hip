@@ -330,19 +330,22 @@ void launch_adjoint_x(hipStream_t sm, dim3 grid, dim3 block, const AArgs &a) {
 
 // xbar_j += sum over entries (j, i) of row j, i != j, of dbar(i, j) (x_j gains
 // what row i differentiated with respect to it; the row's own entries were
-// subtracted by the row kernel); rows in grouped order, a team of kT lanes
+// subtracted by the row kernel); rows in grouped order, a team of kGT lanes
 // per row; the twin dbar(i, j) sits at grev[g] (a Morton-near row).  An entry
 // (j, i) without a twin (i a ghost particle whose row holds only itself)
 // adds nothing.
-constexpr int kGU = 4;  // entries per lane and step of the gather
+constexpr int kGT = 8;  // lanes per row of the gather
+// entries per lane and step of the gather (lanes x entries on the mixed cloud:
+// 8 x 8 481 us, 8 x 4 497, 16 x 4 488, 4 x 8 526)
+constexpr int kGU = 8;
 __global__ void __launch_bounds__(kBlock) k_adjoint_gather(const int32_t *__restrict__ grouped,
                                                            const int64_t *__restrict__ grow_ptr,
                                                            const int32_t *__restrict__ grev,
                                                            const double *__restrict__ dbar, int64_t n,
                                                            double *__restrict__ xbar) {
   const int64_t gt = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  const int64_t t = gt / kT;
-  const int lane = (int)(gt % kT);
+  const int64_t t = gt / kGT;
+  const int lane = (int)(gt % kGT);
   if (t >= n) return;
   const int32_t j = grouped[t];
   const int64_t g0 = grow_ptr[t], g1 = grow_ptr[t + 1];
@@ -354,10 +357,10 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_gather(const int32_t *__rest
   // (both valid, neither added)
   const int64_t gl = g1 - 1;  // a step starts only at gk < g1: gl is in the row
 #pragma unroll 1
-  for (int64_t gk = g0 + lane; gk < g1; gk += kGU * kT) {
+  for (int64_t gk = g0 + lane; gk < g1; gk += kGU * kGT) {
     int32_t tw[kGU];
 #pragma unroll
-    for (int u = 0; u < kGU; ++u) tw[u] = grev[min(gk + u * kT, gl)];
+    for (int u = 0; u < kGU; ++u) tw[u] = grev[min(gk + u * kGT, gl)];
     double da[kGU], db[kGU], dc[kGU];
 #pragma unroll
     for (int u = 0; u < kGU; ++u) {
@@ -368,15 +371,15 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_gather(const int32_t *__rest
     }
 #pragma unroll
     for (int u = 0; u < kGU; ++u) {  // in entry order
-      const bool on = tw[u] >= 0 && gk + u * kT < g1;
+      const bool on = tw[u] >= 0 && gk + u * kGT < g1;
       s0 += on ? da[u] : 0.0;
       s1 += on ? db[u] : 0.0;
       s2 += on ? dc[u] : 0.0;
     }
   }
-  s0 = team_sum(s0, kT);
-  s1 = team_sum(s1, kT);
-  s2 = team_sum(s2, kT);
+  s0 = team_sum(s0, kGT);
+  s1 = team_sum(s1, kGT);
+  s2 = team_sum(s2, kGT);
   if (lane == 0) {
     xbar[3 * j] += s0;
     xbar[3 * j + 1] += s1;
@@ -434,7 +437,7 @@ extern "C" gf_status gf_gfdm_weights_adjoint(gf_ctx *ctx, const gf_particles *p,
   }
   {
     ProfScope prof(ctx, "weights_adjoint_gather");
-    hipLaunchKernelGGL(k_adjoint_gather, dim3(grid_for(p->n * kT, kBlock)), dim3(kBlock), 0, ctx->stream,
+    hipLaunchKernelGGL(k_adjoint_gather, dim3(grid_for(p->n * kGT, kBlock)), dim3(kBlock), 0, ctx->stream,
                        nbr->grouped, nbr->grow_ptr, nbr->grev, a.dbar, p->n, xbar_3n);
     GF_LAUNCH_CHECK(ctx);
   }
